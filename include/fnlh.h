@@ -1,0 +1,213 @@
+/*
+ * fnlh.h -- C ABI of libfnlh, the MI355X (gfx950) solver for the shared-Jacobian,
+ * frequency-shifted block-sparse linear systems of the implicit FNLH scheme
+ * (Wang, Weber, Radford, di Mare, Meyer, "Convergence Acceleration of Favre-Averaged
+ * Non-Linear Harmonic Method", arXiv 2404.01407).
+ *
+ * What is solved.  Section "Generalized RK Scheme for The Mean Flow" defines the
+ * preconditioner matrix K = P/(eps sigma_CFL) + J (implicit) or K = P (explicit), with J
+ * the first-order residual Jacobian (6x6 blocks: five flow variables plus the
+ * Spalart-Allmaras variable) and P its block diagonal.  Section "Generalized RK Scheme
+ * for Time-Linearized Harmonic Flows" adds i omega_l V I to the diagonal of K for
+ * harmonic l; the sparsity pattern is shared by the mean flow and every harmonic.
+ * Section "Solution Update" writes each RK stage as A x = B with A = K/(Gamma alpha_k)
+ * and, for harmonic l, (A + i omega_l I V/(Gamma alpha_k)) x = B; multiplying by
+ * Gamma alpha_k gives the canonical system solved here,
+ *
+ *       (K + i omega_{z(i),s} V_i I) x_s = b_s,      s = 0 .. n_sys-1,
+ *
+ * with b_s = Gamma alpha_k B_s supplied by the caller.  K is stored once; the shift
+ * is applied on the fly, so matrix memory does not depend on the number of systems.
+ * System s with omega row == 0 is the mean flow.
+ *
+ * How.  Each system is solved by preconditioned Richardson iteration
+ * x <- x + M^-1 (b - K_s x), the paper's "ILU(0) used as a smoother, solved
+ * iteratively and inexactly" (section "Solution Update"), with M one of
+ *   FNLH_DILU    (D~ + L) D~^-1 (D~ + U) on a colour ordering (equals block ILU(0) when
+ *                the cell graph has no triangles, e.g. every hex mesh),
+ *   FNLH_SGS     (D + L) D^-1 (D + U),
+ *   FNLH_JACOBI  block diagonal (the paper's explicit, point-by-point inversion).
+ * The stopping test is the paper's relative 2-norm of B - A x (section "Results",
+ * key-parameter table: 1e-2 and 10 iterations there; any rtol / max here).
+ *
+ * Conventions for every call:
+ *   - return value: FNLH_OK (0), a positive solver outcome, or a negative error code;
+ *     no C++ exception crosses the ABI.  fnlh_last_error() gives a message.
+ *   - "host" pointers are read during the call only; the caller keeps ownership.
+ *   - "device" pointers are HIP device memory on the context's device (e.g. the data
+ *     pointer of a torch tensor); the caller owns them.  The library owns its mesh
+ *     copy, blocks, factor slots and scratch, all released by fnlh_destroy.
+ *   - vectors cross the ABI in user cell order as interleaved complex128, [N][6]
+ *     (12 doubles per cell: re0, im0, ..., re5, im5).
+ *   - stream: a hipStream_t passed as void*; NULL is the default stream.  Work is
+ *     stream-ordered; calls that return numbers to the host synchronise that stream.
+ *   - call order: create -> (assemble_jacobian | set_blocks) -> set_harmonics ->
+ *     (relax | residual)*.  Anything else returns FNLH_E_ORDER.  Re-assembly or new
+ *     blocks invalidate all factors; set_harmonics invalidates the factors too.
+ *   - a context is not thread-safe; use one context per host thread / stream.
+ */
+#ifndef FNLH_H
+#define FNLH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fnlh_ctx_s* fnlh_ctx;
+
+/* status codes */
+enum {
+  FNLH_OK = 0,
+  FNLH_NOT_CONVERGED = 1, /* max_sweeps reached above the tolerance            */
+  FNLH_DIVERGED = 2,      /* NaN/Inf or ||r|| > div_factor ||r0||               */
+  FNLH_FELL_BACK = 3,     /* reserved: a learned step was rejected              */
+  FNLH_E_ARG = -1,        /* invalid argument                                   */
+  FNLH_E_MESH = -2,       /* invalid mesh (ids, duplicates, volumes, colouring) */
+  FNLH_E_SINGULAR = -3,   /* a diagonal block to invert is singular / not finite */
+  FNLH_E_OOM = -4,        /* device allocation failed                           */
+  FNLH_E_HIP = -5,        /* HIP runtime error (incl. no device)                */
+  FNLH_E_ORDER = -6       /* call made in the wrong order                       */
+};
+
+/* block storage precision (matrix K and its shadow); D~^-1 is never below FP32 */
+enum { FNLH_F64 = 0, FNLH_F32 = 1, FNLH_BF16 = 2 };
+/* operator of the outer (FP64) residual in reduced-precision modes:
+ *   EXACT  - the FP64 operator: recomputed from the FP64 state and geometry after
+ *            fnlh_assemble_jacobian, an FP64 copy of the blocks after fnlh_set_blocks;
+ *            the iteration converges to the FP64 solution (defect correction).
+ *   STORED - FP64 arithmetic on the upcast stored blocks: converges to the solution
+ *            of the rounded system. */
+enum { FNLH_OUTER_EXACT = 0, FNLH_OUTER_STORED = 1 };
+/* colour ordering: AUTO = two colours when the cell graph is bipartite, else greedy */
+enum { FNLH_ORDER_AUTO = 0, FNLH_ORDER_GREEDY = 1, FNLH_ORDER_BIPARTITE = 2, FNLH_ORDER_USER = 3 };
+/* preconditioner */
+enum { FNLH_DILU = 0, FNLH_SGS = 1, FNLH_JACOBI = 2, FNLH_LEARNED = 3 };
+/* scheme of the preconditioner matrix (section "Generalized RK Scheme for The Mean Flow") */
+enum { FNLH_IMPLICIT = 0, FNLH_EXPLICIT = 1 };
+
+/* Mesh of node-centred control volumes as an edge list (section "Brief Description
+ * of Hydra": edge-based finite volume).  All pointers are host memory. */
+typedef struct {
+  int64_t n_cells;            /* N > 0                                                */
+  int64_t n_edges;            /* E >= 0 interior faces                                */
+  int64_t n_bfaces;           /* B >= 0 boundary faces                                */
+  int32_t n_zones;            /* >= 1; omega is given per zone (e.g. per blade row)   */
+  int32_t pad_;
+  const int32_t* edges;       /* [E][2] cell ids (a, b), a != b, no duplicate pairs   */
+  const double* area;         /* [E][3] face area vector oriented from a to b         */
+  const double* volume;       /* [N] control volumes, > 0                             */
+  const int32_t* zone;        /* [N] zone of each cell in [0, n_zones), or NULL       */
+  const int32_t* bface_cell;  /* [B] owning cell of each boundary face                */
+  const double* bface_area;   /* [B][3] outward area vector                           */
+} fnlh_mesh;
+
+typedef struct {
+  int32_t storage;            /* FNLH_F64 | FNLH_F32 | FNLH_BF16                        */
+  int32_t outer;              /* FNLH_OUTER_EXACT | FNLH_OUTER_STORED                   */
+  int32_t ordering;           /* FNLH_ORDER_*                                           */
+  int32_t factor_slots;       /* D~^-1 slots kept at once; 0 = one per system           */
+  const int32_t* user_colour; /* host [N] colour per cell if ordering == USER; classes
+                                 must be independent sets, taken in ascending value    */
+  int32_t device;             /* HIP device ordinal                                     */
+  int32_t pad_;
+} fnlh_options;
+
+/* Create a context: validates and copies the mesh, builds the colour ordering, the
+ * colour-major internal numbering (locality-ordered within each colour) and the
+ * sliced-ELL block layout, and allocates the matrix on the device.
+ * Errors: FNLH_E_ARG (null pointers, bad option values), FNLH_E_MESH (ids out of range,
+ * self or duplicate edges, volume <= 0, zone out of range, invalid user colouring),
+ * FNLH_E_HIP / FNLH_E_OOM (device).  *out is NULL on failure. */
+int fnlh_create(fnlh_ctx* out, const fnlh_mesh* mesh, const fnlh_options* opts);
+int fnlh_destroy(fnlh_ctx c);
+
+/* Assemble K on the device from the FP64 state (section "Generalized RK Scheme for The
+ * Mean Flow"): J from first-order Rusanov flux Jacobians with a frozen spectral radius
+ * (stand-in for the paper's first-order approximate Jacobian), boundary faces against a
+ * frozen far-field state, P = blockdiag(J), K = J + P/(eps sigma) (FNLH_IMPLICIT) or
+ * K = P (FNLH_EXPLICIT); stored in the context's precision.
+ *   state  device [N][6] conservative (rho, rho u, rho v, rho w, rho E, rho nu~), user order
+ *   bstate device [B][6] far-field state per boundary face, or NULL (= owning cell's state)
+ * Errors: FNLH_E_ARG (eps*sigma <= 0, null state), FNLH_E_HIP. */
+int fnlh_assemble_jacobian(fnlh_ctx c, const double* state, const double* bstate, double eps,
+                           double sigma, int32_t scheme, void* stream);
+
+/* Set K from raw FP64 blocks instead (any matrix with the mesh's pattern).
+ *   diag device [N][6][6]   K_ii, row-major, user order
+ *   offd device [E][2][6][6] per edge e = (a, b): K_ab then K_ba, row-major */
+int fnlh_set_blocks(fnlh_ctx c, const double* diag, const double* offd, void* stream);
+
+/* Read back the stored blocks (upcast to FP64) in the layouts of fnlh_set_blocks. */
+int fnlh_get_blocks(fnlh_ctx c, double* diag, double* offd, void* stream);
+
+/* Frequencies: host [n_sys][n_zones] omega_{z,s} (section "Generalized RK Scheme for
+ * Time-Linearized Harmonic Flows"; omega indexed per zone, cf. the harmonic series with
+ * omega_{i,l}).  Invalidates factors.  1 <= n_sys <= 4096. */
+int fnlh_set_harmonics(fnlh_ctx c, int32_t n_sys, const double* omega, void* stream);
+
+/* r = b - K_s x with the outer FP64 operator (see FNLH_OUTER_*).
+ *   x, b device [N][6] complex128 user order; r device [N][6] or NULL;
+ *   norm2 host out: ||r||_2^2 over all 6N complex entries (may be NULL). */
+int fnlh_residual(fnlh_ctx c, int32_t sys, const double* x, const double* b, double* r,
+                  double* norm2, void* stream);
+
+typedef struct {
+  int32_t kind;          /* FNLH_DILU | FNLH_SGS | FNLH_JACOBI                              */
+  int32_t max_sweeps;    /* >= 0: total preconditioned sweeps per system                  */
+  double rtol;           /* stop when ||b - K_s x|| <= rtol ||b - K_s x0||                 */
+  int32_t check_every;   /* sweeps between host read-backs of the device stop flags (>=1) */
+  int32_t inner_sweeps;  /* reduced precision: max inner sweeps per FP64 correction (0=auto) */
+  double inner_rtol;     /* reduced precision: inner relative tolerance (0 = auto)          */
+  double div_factor;     /* DIVERGED when ||r|| > div_factor ||r0|| (0 = 1e3)               */
+  int32_t use_graph;     /* 1: replay check_every sweeps as one captured hipGraph            */
+  int32_t pad_;
+} fnlh_relax_opts;
+
+typedef struct {
+  int32_t sweeps;        /* preconditioned sweeps applied                                 */
+  int32_t outer;         /* FP64 outer corrections (reduced precision), else 0            */
+  int32_t status;        /* FNLH_OK | FNLH_NOT_CONVERGED | FNLH_DIVERGED                  */
+  int32_t fallbacks;     /* reserved                                                       */
+  double rel_res;        /* ||b - K_s x|| / ||b - K_s x0|| of the returned x, outer operator */
+  double res0;           /* ||b - K_s x0||                                                 */
+  double t_factor_ms;    /* time in factorisation (device events)                          */
+  double t_sweep_ms;     /* time in sweeps and residuals (device events)                   */
+} fnlh_sys_report;
+
+/* Solve n systems: sys[j] indexes the omega table, x[j] (in: x0, out: x) and b[j] are
+ * device [N][6] complex128 user-order buffers (host arrays of n device pointers).
+ * Returns the worst per-system status (FNLH_OK if all converged) or an error.
+ * The tolerance test is evaluated on the residual of the previous iterate, computed
+ * inside the sweep; the returned x is one sweep past the first iterate that met it and
+ * rel_res is recomputed for it with the outer operator. */
+int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x,
+               const double* const* b, const fnlh_relax_opts* opts, fnlh_sys_report* rep,
+               void* stream);
+
+/* Ordering actually used: colour per cell (user order, host out [N]) and the count. */
+int fnlh_get_ordering(fnlh_ctx c, int32_t* colour_of_cell, int32_t* n_colours);
+
+/* Device bytes held: matrix (blocks, shadow, pattern), factor slots, vectors/scratch. */
+int fnlh_memory(fnlh_ctx c, size_t* matrix_bytes, size_t* factor_bytes, size_t* vector_bytes);
+
+/* Message of the last error on this context (or of the last failed fnlh_create when
+ * c is NULL).  Valid until the next call on the same context. */
+const char* fnlh_last_error(fnlh_ctx c);
+
+/* Host-only helpers (no device needed): mesh validation and the ordering fnlh_create
+ * would build.  colour [N] and perm [N] (internal position of each user cell) are host
+ * outputs and may be NULL.  Same error codes as fnlh_create. */
+int fnlh_order_mesh(const fnlh_mesh* mesh, const fnlh_options* opts, int32_t* colour,
+                    int32_t* perm, int32_t* n_colours);
+
+/* Library version string. */
+const char* fnlh_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FNLH_H */

@@ -1,0 +1,683 @@
+// C ABI of libfnlh (include/fnlh.h): context lifecycle, assembly, factorisation and
+// the relaxation driver.  Stop decisions are taken on the device (SysState); the host
+// reads the few per-system states back every `check_every` sweeps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fnlh.h"
+#include "kernels.h"
+#include "layout.h"
+
+using namespace fnlh;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct fnlh_ctx_s {
+  Layout L;
+  int dev = 0;
+  int storage = FNLH_F64;
+  int outer = FNLH_OUTER_EXACT;
+  int factor_slots_opt = 0;
+  std::string err;
+
+  // pattern (device)
+  DevBuf tile_nrows, tile_width, tile_slot0, ent_nbr, ent_edge, ent_rev, vol, zone, iperm, perm, edge_ent, bf_ptr,
+      bf_idx, area, bface_area;
+  // matrix
+  DevBuf offd, diag, offd64, diag64;  // *64: FP64 shadow of raw blocks in reduced precision
+  DevBuf state, bstate;
+  bool have_matrix = false, assembled = false, have_shadow = false;
+  double eps = 0.6, sigma = 50.0;
+  int scheme = FNLH_IMPLICIT;
+  // systems
+  int n_sys = 0;
+  std::vector<double> omega;
+  DevBuf d_omega;
+  // factors
+  int n_slots = 0;
+  DevBuf dinv;
+  std::vector<int> slot_sys, slot_kind;
+  // scratch
+  int vec_cap = 0;
+  DevBuf x64, b64, r64, y, rhs32, d32, partial, st, st_outer;
+  SysState* h_st = nullptr;
+  DevBuf d_err;
+  int* h_err = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+
+  DevPattern pat() const {
+    DevPattern p;
+    p.NP = L.NP;
+    p.n_tiles = L.n_tiles;
+    p.tile_nrows = (const int32_t*)tile_nrows.p;
+    p.tile_width = (const int32_t*)tile_width.p;
+    p.tile_slot0 = (const int64_t*)tile_slot0.p;
+    p.ent_nbr = (const int32_t*)ent_nbr.p;
+    p.ent_edge = (const int32_t*)ent_edge.p;
+    p.ent_rev = (const int32_t*)ent_rev.p;
+    p.vol = (const double*)vol.p;
+    p.zone = (const int32_t*)zone.p;
+    p.omega = (const double*)d_omega.p;
+    p.n_zones = L.n_zones;
+    return p;
+  }
+  DevFlow flow() const {
+    DevFlow f;
+    f.state = (const double*)state.p;
+    f.area = (const double*)area.p;
+    f.bf_ptr = (const int32_t*)bf_ptr.p;
+    f.bf_idx = (const int32_t*)bf_idx.p;
+    f.bface_area = (const double*)bface_area.p;
+    f.bstate = (const double*)bstate.p;
+    f.diag_scale = scheme == FNLH_IMPLICIT ? 1.0 + 1.0 / (eps * sigma) : 1.0;
+    f.offdiag = scheme == FNLH_IMPLICIT ? 1 : 0;
+    return f;
+  }
+  size_t block_bytes() const { return storage == FNLH_F64 ? 8 : storage == FNLH_F32 ? 4 : 2; }
+  int64_t slot_elems_storage() const {
+    return storage == FNLH_F64 ? 18 * 64 * 2 : storage == FNLH_F32 ? 9 * 64 * 4 : 5 * 64 * 8;
+  }
+  size_t tv_bytes() const { return storage == FNLH_F64 ? 8 : 4; }
+};
+
+namespace {
+
+int set_err(fnlh_ctx c, int code, const std::string& m) {
+  if (c) c->err = m; else g_create_error = m;
+  return code;
+}
+
+int hip_fail(fnlh_ctx c, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return set_err(c, e == hipErrorOutOfMemory ? FNLH_E_OOM : FNLH_E_HIP, m);
+}
+
+#define HIPC(c, expr, what)                     \
+  do {                                          \
+    hipError_t _e = (expr);                     \
+    if (_e != hipSuccess) return hip_fail(c, _e, what); \
+  } while (0)
+
+int dalloc(fnlh_ctx c, DevBuf& b, size_t bytes, const char* what) {
+  if (b.p) {
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  if (bytes == 0) return FNLH_OK;
+  HIPC(c, hipMalloc(&b.p, bytes), what);
+  b.bytes = bytes;
+  return FNLH_OK;
+}
+
+template <typename T> int dupload(fnlh_ctx c, DevBuf& b, const std::vector<T>& v, const char* what) {
+  int rc = dalloc(c, b, v.size() * sizeof(T), what);
+  if (rc) return rc;
+  if (!v.empty()) HIPC(c, hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), what);
+  return FNLH_OK;
+}
+
+void dfree(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+inline hipStream_t S(void* s) { return (hipStream_t)s; }
+
+int check_launch(fnlh_ctx c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, what);
+  return FNLH_OK;
+}
+
+int ensure_vectors(fnlh_ctx c, int n) {
+  if (n <= c->vec_cap) return FNLH_OK;
+  const size_t v64 = (size_t)n * c->L.NP * 12 * sizeof(double);
+  const size_t v32 = (size_t)n * c->L.NP * 12 * sizeof(float);
+  int rc;
+  if ((rc = dalloc(c, c->x64, v64, "alloc x"))) return rc;
+  if ((rc = dalloc(c, c->b64, v64, "alloc b"))) return rc;
+  if ((rc = dalloc(c, c->y, v64, "alloc y"))) return rc;
+  if ((rc = dalloc(c, c->partial, (size_t)n * c->L.n_tiles * sizeof(double), "alloc partial"))) return rc;
+  if ((rc = dalloc(c, c->st, (size_t)n * sizeof(SysState), "alloc state"))) return rc;
+  if ((rc = dalloc(c, c->st_outer, (size_t)n * sizeof(SysState), "alloc state"))) return rc;
+  if (c->storage != FNLH_F64) {
+    if ((rc = dalloc(c, c->r64, v64, "alloc r"))) return rc;
+    if ((rc = dalloc(c, c->rhs32, v32, "alloc rhs32"))) return rc;
+    if ((rc = dalloc(c, c->d32, v32, "alloc d32"))) return rc;
+  }
+  if (c->h_st) (void)hipHostFree(c->h_st);
+  c->h_st = nullptr;
+  HIPC(c, hipHostMalloc((void**)&c->h_st, 2 * (size_t)n * sizeof(SysState), hipHostMallocDefault), "host state");
+  // vectors start at zero so padding rows stay zero
+  HIPC(c, hipMemset(c->x64.p, 0, v64), "zero");
+  HIPC(c, hipMemset(c->b64.p, 0, v64), "zero");
+  HIPC(c, hipMemset(c->y.p, 0, v64), "zero");
+  if (c->storage != FNLH_F64) {
+    HIPC(c, hipMemset(c->r64.p, 0, v64), "zero");
+    HIPC(c, hipMemset(c->rhs32.p, 0, v32), "zero");
+    HIPC(c, hipMemset(c->d32.p, 0, v32), "zero");
+  }
+  c->vec_cap = n;
+  return FNLH_OK;
+}
+
+int ensure_slots(fnlh_ctx c, int slots) {
+  if (slots <= c->n_slots) return FNLH_OK;
+  const size_t per = (size_t)c->L.n_tiles * kDinvTileReals * c->tv_bytes();
+  int rc = dalloc(c, c->dinv, per * slots, "alloc factor slots");
+  if (rc) return rc;
+  HIPC(c, hipMemset(c->dinv.p, 0, per * slots), "zero factors");
+  c->n_slots = slots;
+  c->slot_sys.assign(slots, -1);
+  c->slot_kind.assign(slots, -1);
+  return FNLH_OK;
+}
+
+int64_t dinv_stride(fnlh_ctx c) { return c->L.n_tiles * kDinvTileReals; }
+
+void invalidate_factors(fnlh_ctx c) {
+  std::fill(c->slot_sys.begin(), c->slot_sys.end(), -1);
+  std::fill(c->slot_kind.begin(), c->slot_kind.end(), -1);
+}
+
+// outer FP64 operator residual of the systems of sb (x64, b64 -> r, partial)
+void outer_residual(fnlh_ctx c, const SysBatch& sb, double* r, hipStream_t s) {
+  DevPattern p = c->pat();
+  if (c->storage == FNLH_F64) {
+    launch_resid_stored(kF64, p, c->offd.p, c->diag.p, (const double*)c->x64.p, (const double*)c->b64.p, r, sb,
+                        (double*)c->partial.p, s);
+  } else if (c->outer == FNLH_OUTER_STORED) {
+    launch_resid_stored(c->storage, p, c->offd.p, c->diag.p, (const double*)c->x64.p, (const double*)c->b64.p, r,
+                        sb, (double*)c->partial.p, s);
+  } else if (c->assembled) {
+    launch_resid_mfree(p, c->flow(), (const double*)c->x64.p, (const double*)c->b64.p, r, sb,
+                       (double*)c->partial.p, s);
+  } else {
+    launch_resid_stored(kF64, p, c->offd64.p, c->diag64.p, (const double*)c->x64.p, (const double*)c->b64.p, r, sb,
+                        (double*)c->partial.p, s);
+  }
+}
+
+int factor_batch(fnlh_ctx c, const SysBatch& sb, bool dilu, hipStream_t s) {
+  DevPattern p = c->pat();
+  HIPC(c, hipMemsetAsync(c->d_err.p, 0, sizeof(int), s), "clear error flag");
+  for (int col = 0; col < c->L.n_colours; ++col) {
+    launch_factor(c->storage, dilu, p, c->offd.p, c->diag.p, c->dinv.p, dinv_stride(c), sb, c->L.ctile[col],
+                  c->L.ctile[col + 1] - c->L.ctile[col], c->L.cstart[col], (int*)c->d_err.p, s);
+  }
+  int rc = check_launch(c, "factor launch");
+  if (rc) return rc;
+  HIPC(c, hipMemcpyAsync(c->h_err, c->d_err.p, sizeof(int), hipMemcpyDeviceToHost, s), "read error flag");
+  HIPC(c, hipStreamSynchronize(s), "factor sync");
+  if (*c->h_err) return set_err(c, FNLH_E_SINGULAR, "factorisation: singular or non-finite diagonal block");
+  return FNLH_OK;
+}
+
+enum Path { kPathRB, kPathGeneral, kPathJacobi };
+
+// One preconditioned sweep for the systems of sb (vectors x, b, y of type TV).
+void one_sweep(fnlh_ctx c, Path path, const SweepCfg& cfg, const SysBatch& sb, void* x, const void* b, void* y,
+               SysState* st, bool first, double rtol, double divf, hipStream_t s) {
+  DevPattern p = c->pat();
+  const Layout& L = c->L;
+  const int64_t ds = dinv_stride(c);
+  double* part = (double*)c->partial.p;
+  if (path == kPathRB) {
+    launch_rb_pass(cfg, true, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, sb, st, part, L.ctile[1],
+                   L.ctile[2] - L.ctile[1], s);
+    launch_reduce(sb, part, L.n_tiles, L.ctile[1], L.ctile[2] - L.ctile[1], st,
+                  first ? kReduceSweepNoNorm : kReduceSweep, rtol, divf, 0, s);
+    launch_rb_pass(cfg, false, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, sb, st, part, L.ctile[0],
+                   L.ctile[1] - L.ctile[0], s);
+  } else if (path == kPathGeneral) {
+    const int m = L.n_colours;
+    for (int col = 0; col < m; ++col)
+      launch_fwd(cfg, col == m - 1, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, y, sb, st, part, L.ctile[col],
+                 L.ctile[col + 1] - L.ctile[col], L.cstart[col], s);
+    launch_reduce(sb, part, L.n_tiles, 0, L.n_tiles, st, kReduceSweep, rtol, divf, 0, s);
+    for (int col = m - 2; col >= 0; --col)
+      launch_bwd(cfg, p, c->offd.p, c->dinv.p, ds, x, y, sb, st, L.ctile[col], L.ctile[col + 1] - L.ctile[col],
+                 L.cstart[col + 1], s);
+  } else {
+    launch_jacobi(cfg, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, y, sb, st, part, s);
+    launch_reduce(sb, part, L.n_tiles, 0, L.n_tiles, st, kReduceSweep, rtol, divf, 0, s);
+    launch_axpy_y(cfg.storage, p, x, y, sb, st, s);
+  }
+}
+
+// Iterate until every system of sb is inactive.  States must be initialised.
+int sweep_loop(fnlh_ctx c, Path path, const SweepCfg& cfg, const SysBatch& sb, void* x, const void* b, void* y,
+               SysState* st, double rtol, double divf, int max_sweeps, int check_every, hipStream_t s) {
+  if (path == kPathRB) {
+    DevPattern p = c->pat();
+    launch_rb_pass(cfg, false, p, c->offd.p, c->diag.p, c->dinv.p, dinv_stride(c), x, b, sb, st,
+                   (double*)c->partial.p, c->L.ctile[0], c->L.ctile[1] - c->L.ctile[0], s);
+  }
+  int launched = 0;
+  // each system needs at most max_sweeps sweeps plus one to retire
+  while (launched <= max_sweeps + 1) {
+    for (int i = 0; i < check_every && launched <= max_sweeps + 1; ++i, ++launched)
+      one_sweep(c, path, cfg, sb, x, b, y, st, launched == 0, rtol, divf, s);
+    int rc = check_launch(c, "sweep launch");
+    if (rc) return rc;
+    SysState* h = c->h_st;
+    HIPC(c, hipMemcpyAsync(h, st, sizeof(SysState) * (sb.vslot[sb.n - 1] + 1), hipMemcpyDeviceToHost, s),
+         "read states");
+    HIPC(c, hipStreamSynchronize(s), "sweep sync");
+    bool any = false;
+    for (int k = 0; k < sb.n; ++k) any |= h[sb.vslot[k]].active != 0;
+    if (!any) break;
+  }
+  return FNLH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fnlh_version(void) { return "fnlh 0.1 gfx950"; }
+
+const char* fnlh_last_error(fnlh_ctx c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int fnlh_order_mesh(const fnlh_mesh* mesh, const fnlh_options* opts, int32_t* colour, int32_t* perm,
+                    int32_t* n_colours) {
+  if (!mesh || !opts) return set_err(nullptr, FNLH_E_ARG, "null mesh or options");
+  Layout L;
+  std::string e;
+  int rc = build_layout(*mesh, *opts, L, e);
+  if (rc) return set_err(nullptr, rc, e);
+  if (colour) std::copy(L.colour_user.begin(), L.colour_user.end(), colour);
+  if (perm) std::copy(L.perm.begin(), L.perm.end(), perm);
+  if (n_colours) *n_colours = L.n_colours;
+  return FNLH_OK;
+}
+
+int fnlh_create(fnlh_ctx* out, const fnlh_mesh* mesh, const fnlh_options* opts) {
+  if (!out) return set_err(nullptr, FNLH_E_ARG, "null output pointer");
+  *out = nullptr;
+  if (!mesh || !opts) return set_err(nullptr, FNLH_E_ARG, "null mesh or options");
+  fnlh_ctx c = new fnlh_ctx_s();
+  std::string e;
+  int rc = build_layout(*mesh, *opts, c->L, e);
+  if (rc) {
+    delete c;
+    return set_err(nullptr, rc, e);
+  }
+  c->dev = opts->device;
+  c->storage = opts->storage;
+  c->outer = opts->outer;
+  c->factor_slots_opt = opts->factor_slots;
+  auto fail = [&](int code) {
+    g_create_error = c->err;
+    fnlh_destroy(c);
+    return code;
+  };
+  hipError_t he = hipSetDevice(c->dev);
+  if (he != hipSuccess) {
+    hip_fail(c, he, "hipSetDevice");
+    return fail(FNLH_E_HIP);
+  }
+  const Layout& L = c->L;
+  if ((rc = dupload(c, c->tile_nrows, L.tile_nrows, "pattern"))) return fail(rc);
+  if ((rc = dupload(c, c->tile_width, L.tile_width, "pattern"))) return fail(rc);
+  if ((rc = dupload(c, c->tile_slot0, L.tile_slot0, "pattern"))) return fail(rc);
+  if ((rc = dupload(c, c->ent_nbr, L.ent_nbr, "pattern"))) return fail(rc);
+  if ((rc = dupload(c, c->ent_edge, L.ent_edge, "pattern"))) return fail(rc);
+  if ((rc = dupload(c, c->ent_rev, L.ent_rev, "pattern"))) return fail(rc);
+  if ((rc = dupload(c, c->vol, L.vol, "pattern"))) return fail(rc);
+  if ((rc = dupload(c, c->zone, L.zone, "pattern"))) return fail(rc);
+  if ((rc = dupload(c, c->iperm, L.iperm, "pattern"))) return fail(rc);
+  if ((rc = dupload(c, c->perm, L.perm, "pattern"))) return fail(rc);
+  if ((rc = dupload(c, c->edge_ent, L.edge_ent, "pattern"))) return fail(rc);
+  if ((rc = dupload(c, c->bf_ptr, L.bf_ptr, "pattern"))) return fail(rc);
+  if ((rc = dupload(c, c->bf_idx, L.bf_idx, "pattern"))) return fail(rc);
+  {
+    std::vector<double> a(mesh->area, mesh->area + 3 * mesh->n_edges);
+    if ((rc = dupload(c, c->area, a, "geometry"))) return fail(rc);
+    std::vector<double> ba(mesh->bface_area, mesh->bface_area + 3 * mesh->n_bfaces);
+    if ((rc = dupload(c, c->bface_area, ba, "geometry"))) return fail(rc);
+  }
+  const size_t be = c->block_bytes();
+  if ((rc = dalloc(c, c->offd, (size_t)L.n_slots * c->slot_elems_storage() * be, "alloc blocks"))) return fail(rc);
+  if ((rc = dalloc(c, c->diag, (size_t)L.n_tiles * c->slot_elems_storage() * be, "alloc blocks"))) return fail(rc);
+  if (c->offd.p && hipMemset(c->offd.p, 0, c->offd.bytes) != hipSuccess) return fail(FNLH_E_HIP);
+  if (hipMemset(c->diag.p, 0, c->diag.bytes) != hipSuccess) return fail(FNLH_E_HIP);
+  if ((rc = dalloc(c, c->d_err, sizeof(int), "alloc flag"))) return fail(rc);
+  if (hipHostMalloc((void**)&c->h_err, sizeof(int), hipHostMallocDefault) != hipSuccess) return fail(FNLH_E_HIP);
+  for (auto& ev : c->ev)
+    if (hipEventCreate(&ev) != hipSuccess) return fail(FNLH_E_HIP);
+  *out = c;
+  return FNLH_OK;
+}
+
+int fnlh_destroy(fnlh_ctx c) {
+  if (!c) return FNLH_E_ARG;
+  DevBuf* bufs[] = {&c->tile_nrows, &c->tile_width, &c->tile_slot0, &c->ent_nbr, &c->ent_edge, &c->ent_rev,
+                    &c->vol, &c->zone, &c->iperm, &c->perm, &c->edge_ent, &c->bf_ptr, &c->bf_idx, &c->area,
+                    &c->bface_area, &c->offd, &c->diag, &c->offd64, &c->diag64, &c->state, &c->bstate,
+                    &c->d_omega, &c->dinv, &c->x64, &c->b64, &c->r64, &c->y, &c->rhs32, &c->d32, &c->partial,
+                    &c->st, &c->st_outer, &c->d_err};
+  for (DevBuf* b : bufs) dfree(*b);
+  if (c->h_st) (void)hipHostFree(c->h_st);
+  if (c->h_err) (void)hipHostFree(c->h_err);
+  for (auto& ev : c->ev)
+    if (ev) (void)hipEventDestroy(ev);
+  delete c;
+  return FNLH_OK;
+}
+
+int fnlh_assemble_jacobian(fnlh_ctx c, const double* state, const double* bstate, double eps, double sigma,
+                           int32_t scheme, void* stream) {
+  if (!c) return FNLH_E_ARG;
+  if (!state) return set_err(c, FNLH_E_ARG, "assemble: null state");
+  if (scheme != FNLH_IMPLICIT && scheme != FNLH_EXPLICIT) return set_err(c, FNLH_E_ARG, "assemble: bad scheme");
+  if (scheme == FNLH_IMPLICIT && !(eps * sigma > 0.0 && std::isfinite(eps * sigma)))
+    return set_err(c, FNLH_E_ARG, "assemble: need eps * sigma > 0");
+  hipStream_t s = S(stream);
+  int rc;
+  if (!c->state.p && (rc = dalloc(c, c->state, (size_t)c->L.NP * 6 * sizeof(double), "alloc state"))) return rc;
+  DevPattern p = c->pat();
+  launch_to_internal(p, (const int32_t*)c->iperm.p, state, (double*)c->state.p, 6, s);
+  if (bstate && c->L.B > 0) {
+    if (!c->bstate.p && (rc = dalloc(c, c->bstate, (size_t)c->L.B * 6 * sizeof(double), "alloc bstate"))) return rc;
+    HIPC(c, hipMemcpyAsync(c->bstate.p, bstate, (size_t)c->L.B * 6 * sizeof(double), hipMemcpyDeviceToDevice, s),
+         "copy bstate");
+  } else {
+    dfree(c->bstate);
+  }
+  c->eps = eps;
+  c->sigma = sigma;
+  c->scheme = scheme;
+  launch_assemble(c->storage, p, c->flow(), c->offd.p, c->diag.p, s);
+  if ((rc = check_launch(c, "assemble launch"))) return rc;
+  dfree(c->offd64);
+  dfree(c->diag64);
+  c->have_shadow = false;
+  c->have_matrix = true;
+  c->assembled = true;
+  invalidate_factors(c);
+  return FNLH_OK;
+}
+
+int fnlh_set_blocks(fnlh_ctx c, const double* diag, const double* offd, void* stream) {
+  if (!c) return FNLH_E_ARG;
+  if (!diag || (c->L.E > 0 && !offd)) return set_err(c, FNLH_E_ARG, "set_blocks: null blocks");
+  hipStream_t s = S(stream);
+  DevPattern p = c->pat();
+  launch_set_blocks(c->storage, p, c->L.N, c->L.E, (const int32_t*)c->perm.p, (const int64_t*)c->edge_ent.p, diag,
+                    offd, c->offd.p, c->diag.p, s);
+  int rc;
+  if (c->storage != FNLH_F64 && c->outer == FNLH_OUTER_EXACT) {
+    if (!c->offd64.p && (rc = dalloc(c, c->offd64, (size_t)c->L.n_slots * 18 * 64 * 2 * 8, "alloc shadow")))
+      return rc;
+    if (!c->diag64.p && (rc = dalloc(c, c->diag64, (size_t)c->L.n_tiles * 18 * 64 * 2 * 8, "alloc shadow")))
+      return rc;
+    if (c->offd64.p) HIPC(c, hipMemsetAsync(c->offd64.p, 0, c->offd64.bytes, s), "zero shadow");
+    HIPC(c, hipMemsetAsync(c->diag64.p, 0, c->diag64.bytes, s), "zero shadow");
+    launch_set_blocks(kF64, p, c->L.N, c->L.E, (const int32_t*)c->perm.p, (const int64_t*)c->edge_ent.p, diag, offd,
+                      c->offd64.p, c->diag64.p, s);
+    c->have_shadow = true;
+  }
+  if ((rc = check_launch(c, "set_blocks launch"))) return rc;
+  c->have_matrix = true;
+  c->assembled = false;
+  invalidate_factors(c);
+  return FNLH_OK;
+}
+
+int fnlh_get_blocks(fnlh_ctx c, double* diag, double* offd, void* stream) {
+  if (!c) return FNLH_E_ARG;
+  if (!c->have_matrix) return set_err(c, FNLH_E_ORDER, "get_blocks: no matrix yet");
+  if (!diag || (c->L.E > 0 && !offd)) return set_err(c, FNLH_E_ARG, "get_blocks: null output");
+  hipStream_t s = S(stream);
+  launch_get_blocks(c->storage, c->pat(), c->L.N, c->L.E, (const int32_t*)c->perm.p, (const int64_t*)c->edge_ent.p,
+                    c->offd.p, c->diag.p, diag, offd, s);
+  return check_launch(c, "get_blocks launch");
+}
+
+int fnlh_set_harmonics(fnlh_ctx c, int32_t n_sys, const double* omega, void* stream) {
+  if (!c) return FNLH_E_ARG;
+  if (!c->have_matrix) return set_err(c, FNLH_E_ORDER, "set_harmonics: assemble or set blocks first");
+  if (n_sys < 1 || n_sys > 4096 || !omega) return set_err(c, FNLH_E_ARG, "set_harmonics: need 1 <= n_sys <= 4096");
+  const size_t n = (size_t)n_sys * c->L.n_zones;
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(omega[i])) return set_err(c, FNLH_E_ARG, "set_harmonics: non-finite omega");
+  c->omega.assign(omega, omega + n);
+  int rc;
+  if ((rc = dalloc(c, c->d_omega, n * sizeof(double), "alloc omega"))) return rc;
+  HIPC(c, hipMemcpy(c->d_omega.p, omega, n * sizeof(double), hipMemcpyHostToDevice), "copy omega");
+  c->n_sys = n_sys;
+  invalidate_factors(c);
+  (void)stream;
+  return FNLH_OK;
+}
+
+int fnlh_residual(fnlh_ctx c, int32_t sys, const double* x, const double* b, double* r, double* norm2,
+                  void* stream) {
+  if (!c) return FNLH_E_ARG;
+  if (!c->have_matrix || c->n_sys == 0) return set_err(c, FNLH_E_ORDER, "residual: matrix and harmonics first");
+  if (sys < 0 || sys >= c->n_sys) return set_err(c, FNLH_E_ARG, "residual: system out of range");
+  if (!x || !b) return set_err(c, FNLH_E_ARG, "residual: null vector");
+  hipStream_t s = S(stream);
+  int rc;
+  if ((rc = ensure_vectors(c, 1))) return rc;
+  DevPattern p = c->pat();
+  launch_to_internal(p, (const int32_t*)c->iperm.p, x, (double*)c->x64.p, 12, s);
+  launch_to_internal(p, (const int32_t*)c->iperm.p, b, (double*)c->b64.p, 12, s);
+  SysBatch sb;
+  sb.n = 1;
+  sb.orow[0] = sys;
+  sb.dslot[0] = 0;
+  sb.vslot[0] = 0;
+  double* rint = r ? (double*)c->y.p : nullptr;
+  outer_residual(c, sb, rint, s);
+  launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, (SysState*)c->st.p, kReduceFinal, 0,
+                0, 0, s);
+  if (r) launch_to_user(p, (const int32_t*)c->iperm.p, rint, r, 12, s);
+  if ((rc = check_launch(c, "residual launch"))) return rc;
+  HIPC(c, hipMemcpyAsync(c->h_st, c->st.p, sizeof(SysState), hipMemcpyDeviceToHost, s), "read state");
+  HIPC(c, hipStreamSynchronize(s), "residual sync");
+  if (norm2) *norm2 = c->h_st[0].last_n2;
+  return FNLH_OK;
+}
+
+int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, const double* const* b,
+               const fnlh_relax_opts* o, fnlh_sys_report* rep, void* stream) {
+  if (!c) return FNLH_E_ARG;
+  if (!c->have_matrix || c->n_sys == 0) return set_err(c, FNLH_E_ORDER, "relax: matrix and harmonics first");
+  if (n < 1 || !sys || !x || !b || !o) return set_err(c, FNLH_E_ARG, "relax: bad arguments");
+  for (int j = 0; j < n; ++j) {
+    if (sys[j] < 0 || sys[j] >= c->n_sys) return set_err(c, FNLH_E_ARG, "relax: system out of range");
+    if (!x[j] || !b[j]) return set_err(c, FNLH_E_ARG, "relax: null vector");
+  }
+  if (o->kind != FNLH_DILU && o->kind != FNLH_SGS && o->kind != FNLH_JACOBI)
+    return set_err(c, FNLH_E_ARG, "relax: unsupported preconditioner kind");
+  if (o->max_sweeps < 0 || !(o->rtol >= 0.0)) return set_err(c, FNLH_E_ARG, "relax: need max_sweeps >= 0, rtol >= 0");
+  const int check_every = o->check_every > 0 ? o->check_every : 8;
+  const double divf = o->div_factor > 0 ? o->div_factor : 1e3;
+  const bool reduced = c->storage != FNLH_F64;
+  const double inner_rtol = o->inner_rtol > 0 ? o->inner_rtol : (c->storage == FNLH_F32 ? 1e-4 : 1e-2);
+  const int inner_max = o->inner_sweeps > 0 ? o->inner_sweeps : std::max(1, o->max_sweeps);
+  hipStream_t s = S(stream);
+  int rc;
+  if ((rc = ensure_vectors(c, n))) return rc;
+  const int want_slots = c->factor_slots_opt > 0 ? c->factor_slots_opt : std::min<int>(c->n_sys, 64);
+  if ((rc = ensure_slots(c, want_slots))) return rc;
+  DevPattern p = c->pat();
+  for (int j = 0; j < n; ++j) {
+    launch_to_internal(p, (const int32_t*)c->iperm.p, x[j], (double*)c->x64.p + (size_t)j * c->L.NP * 12, 12, s);
+    launch_to_internal(p, (const int32_t*)c->iperm.p, b[j], (double*)c->b64.p + (size_t)j * c->L.NP * 12, 12, s);
+  }
+  const Path path = o->kind == FNLH_JACOBI ? kPathJacobi : (c->L.n_colours == 2 ? kPathRB : kPathGeneral);
+  const int fkind = o->kind == FNLH_DILU ? 0 : 1;
+  SweepCfg cfg;
+  cfg.storage = c->storage;
+  cfg.spw = 4;
+  const int G = std::min({n, kMaxBatch, c->n_slots});
+  std::vector<double> tf(n, 0.0), ts(n, 0.0);
+  for (int g0 = 0; g0 < n; g0 += G) {
+    SysBatch sb;
+    sb.n = std::min(G, n - g0);
+    // factor slots: reuse cached factors, fill the rest
+    std::vector<int> used(c->n_slots, 0);
+    SysBatch need;
+    need.n = 0;
+    for (int k = 0; k < sb.n; ++k) {
+      sb.orow[k] = sys[g0 + k];
+      sb.vslot[k] = g0 + k;
+      sb.dslot[k] = -1;
+      for (int q = 0; q < c->n_slots; ++q)
+        if (!used[q] && c->slot_sys[q] == sys[g0 + k] && c->slot_kind[q] == fkind) {
+          sb.dslot[k] = q;
+          used[q] = 1;
+          break;
+        }
+    }
+    for (int k = 0; k < sb.n; ++k) {
+      if (sb.dslot[k] >= 0) continue;
+      int q = 0;
+      while (used[q]) ++q;
+      used[q] = 1;
+      sb.dslot[k] = q;
+      need.orow[need.n] = sb.orow[k];
+      need.dslot[need.n] = q;
+      need.vslot[need.n] = sb.vslot[k];
+      need.n++;
+    }
+    HIPC(c, hipEventRecord(c->ev[0], s), "event");
+    if (need.n) {
+      for (int k = 0; k < need.n; ++k) {
+        c->slot_sys[need.dslot[k]] = -1;
+        c->slot_kind[need.dslot[k]] = -1;
+      }
+      if ((rc = factor_batch(c, need, fkind == 0, s))) return rc;
+      for (int k = 0; k < need.n; ++k) {
+        c->slot_sys[need.dslot[k]] = need.orow[k];
+        c->slot_kind[need.dslot[k]] = fkind;
+      }
+    }
+    HIPC(c, hipEventRecord(c->ev[1], s), "event");
+    SysState* st = (SysState*)c->st.p;
+    if (!reduced) {
+      outer_residual(c, sb, nullptr, s);
+      launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, st, kReduceInit, 0, 0,
+                    o->max_sweeps, s);
+      if ((rc = sweep_loop(c, path, cfg, sb, c->x64.p, c->b64.p, c->y.p, st, o->rtol, divf, o->max_sweeps,
+                           check_every, s)))
+        return rc;
+    } else {
+      SysState* so = (SysState*)c->st_outer.p;
+      outer_residual(c, sb, (double*)c->r64.p, s);
+      launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, so, kReduceInit, 0, 0,
+                    o->max_sweeps, s);
+      for (int it = 0; it < 100000; ++it) {
+        if ((rc = check_launch(c, "outer launch"))) return rc;
+        HIPC(c, hipMemcpyAsync(c->h_st, so, sizeof(SysState) * (sb.vslot[sb.n - 1] + 1), hipMemcpyDeviceToHost, s),
+             "read states");
+        HIPC(c, hipStreamSynchronize(s), "outer sync");
+        bool any = false;
+        for (int k = 0; k < sb.n; ++k) any |= c->h_st[sb.vslot[k]].active != 0;
+        if (!any) break;
+        launch_to_f32(p, (const double*)c->r64.p, (float*)c->rhs32.p, (float*)c->d32.p, sb, so, s);
+        launch_inner_init(sb, so, st, inner_max, s);
+        if ((rc = sweep_loop(c, path, cfg, sb, c->d32.p, c->rhs32.p, c->y.p, st, inner_rtol, 1e30, inner_max,
+                             check_every, s)))
+          return rc;
+        launch_outer_update(sb, st, so, s);
+        launch_add_f32(p, (double*)c->x64.p, (const float*)c->d32.p, sb, so, s);
+        outer_residual(c, sb, (double*)c->r64.p, s);
+        launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, so, kReduceOuter, o->rtol,
+                      divf, 0, s);
+      }
+    }
+    HIPC(c, hipEventRecord(c->ev[2], s), "event");
+    HIPC(c, hipEventSynchronize(c->ev[2]), "event sync");
+    float a = 0.f, bms = 0.f;
+    (void)hipEventElapsedTime(&a, c->ev[0], c->ev[1]);
+    (void)hipEventElapsedTime(&bms, c->ev[1], c->ev[2]);
+    for (int k = 0; k < sb.n; ++k) {
+      tf[g0 + k] = a;
+      ts[g0 + k] = bms;
+    }
+  }
+  // final: residual of the returned iterates with the outer operator
+  std::vector<SysState> fin(n);
+  for (int g0 = 0; g0 < n; g0 += kMaxBatch) {
+    SysBatch sb;
+    sb.n = std::min(kMaxBatch, n - g0);
+    for (int k = 0; k < sb.n; ++k) {
+      sb.orow[k] = sys[g0 + k];
+      sb.vslot[k] = g0 + k;
+      sb.dslot[k] = 0;
+    }
+    SysState* stf = (SysState*)(reduced ? c->st_outer.p : c->st.p);
+    outer_residual(c, sb, nullptr, s);
+    launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, stf, kReduceFinal, 0, 0, 0, s);
+  }
+  for (int j = 0; j < n; ++j)
+    launch_to_user(p, (const int32_t*)c->iperm.p, (const double*)c->x64.p + (size_t)j * c->L.NP * 12, x[j], 12, s);
+  if ((rc = check_launch(c, "final launch"))) return rc;
+  HIPC(c, hipMemcpyAsync(c->h_st, reduced ? c->st_outer.p : c->st.p, sizeof(SysState) * n, hipMemcpyDeviceToHost, s),
+       "read states");
+  HIPC(c, hipStreamSynchronize(s), "final sync");
+  int worst = FNLH_OK;
+  for (int j = 0; j < n; ++j) {
+    const SysState& S0 = c->h_st[j];
+    fnlh_sys_report R;
+    std::memset(&R, 0, sizeof(R));
+    R.sweeps = S0.sweeps;
+    R.outer = reduced ? S0.outer_iters : 0;
+    R.res0 = std::sqrt(S0.norm0sq);
+    R.rel_res = S0.norm0sq > 0 ? std::sqrt(S0.last_n2 / S0.norm0sq) : 0.0;
+    int status = S0.status;
+    if (status != FNLH_DIVERGED) status = (R.rel_res <= o->rtol) ? FNLH_OK : FNLH_NOT_CONVERGED;
+    if (!std::isfinite(R.rel_res)) status = FNLH_DIVERGED;
+    R.status = status;
+    R.t_factor_ms = tf[j];
+    R.t_sweep_ms = ts[j];
+    if (rep) rep[j] = R;
+    if (status == FNLH_DIVERGED || (status == FNLH_NOT_CONVERGED && worst == FNLH_OK)) worst = status;
+  }
+  return worst;
+}
+
+int fnlh_get_ordering(fnlh_ctx c, int32_t* colour_of_cell, int32_t* n_colours) {
+  if (!c) return FNLH_E_ARG;
+  if (colour_of_cell) std::copy(c->L.colour_user.begin(), c->L.colour_user.end(), colour_of_cell);
+  if (n_colours) *n_colours = c->L.n_colours;
+  return FNLH_OK;
+}
+
+int fnlh_memory(fnlh_ctx c, size_t* matrix_bytes, size_t* factor_bytes, size_t* vector_bytes) {
+  if (!c) return FNLH_E_ARG;
+  const DevBuf* mat[] = {&c->tile_nrows, &c->tile_width, &c->tile_slot0, &c->ent_nbr, &c->ent_edge, &c->ent_rev,
+                         &c->vol, &c->zone, &c->iperm, &c->perm, &c->edge_ent, &c->bf_ptr, &c->bf_idx, &c->area,
+                         &c->bface_area, &c->offd, &c->diag, &c->offd64, &c->diag64, &c->state, &c->bstate};
+  const DevBuf* vec[] = {&c->x64, &c->b64,     &c->r64,     &c->y,  &c->rhs32,   &c->d32,
+                         &c->partial, &c->st, &c->st_outer, &c->d_omega};
+  size_t m = 0, v = 0;
+  for (auto* b : mat) m += b->bytes;
+  for (auto* b : vec) v += b->bytes;
+  if (matrix_bytes) *matrix_bytes = m;
+  if (factor_bytes) *factor_bytes = c->dinv.bytes;
+  if (vector_bytes) *vector_bytes = v;
+  return FNLH_OK;
+}
+
+}  // extern "C"

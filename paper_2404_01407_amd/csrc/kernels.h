@@ -1,0 +1,121 @@
+// Launchers of the gfx950 kernels (kernels.hip).  All work is stream-ordered.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace fnlh {
+
+constexpr int kMaxBatch = 16;  // systems handled by one launch
+constexpr int64_t kDinvTileReals = 72 * 64;  // one tile of complex 6x6 inverses
+
+// Per-system solver state kept on the device so stop decisions need no host round trip.
+struct SysState {
+  double norm0sq;       // ||r0||^2
+  double last_n2;       // latest residual norm^2
+  int32_t active;       // still iterating
+  int32_t pending;      // met a stop criterion; finish the current sweep, then stop
+  int32_t sweeps;       // sweeps done
+  int32_t status;       // FNLH_OK / NOT_CONVERGED / DIVERGED
+  int32_t limit;        // max sweeps
+  int32_t outer_iters;  // FP64 corrections (reduced precision)
+};
+
+struct DevPattern {
+  int64_t NP = 0;
+  int64_t n_tiles = 0;
+  const int32_t* tile_nrows = nullptr;
+  const int32_t* tile_width = nullptr;
+  const int64_t* tile_slot0 = nullptr;
+  const int32_t* ent_nbr = nullptr;
+  const int32_t* ent_edge = nullptr;
+  const int32_t* ent_rev = nullptr;
+  const double* vol = nullptr;
+  const int32_t* zone = nullptr;
+  const double* omega = nullptr;  // [n_sys][n_zones]
+  int32_t n_zones = 1;
+};
+
+struct SysBatch {
+  int32_t n = 0;
+  int32_t orow[kMaxBatch];   // omega row (system id)
+  int32_t dslot[kMaxBatch];  // factor slot
+  int32_t vslot[kMaxBatch];  // internal vector / state slot
+};
+
+enum Store { kF64 = 0, kF32 = 1, kBF16 = 2 };
+
+// Rusanov geometry + state for assembly and the matrix-free FP64 operator.
+struct DevFlow {
+  const double* state = nullptr;       // [NP][6] internal order
+  const double* area = nullptr;        // [E][3] user edge order
+  const int32_t* bf_ptr = nullptr;     // [NP+1]
+  const int32_t* bf_idx = nullptr;     // [B]
+  const double* bface_area = nullptr;  // [B][3]
+  const double* bstate = nullptr;      // [B][6] far field or null
+  double diag_scale = 1.0;             // 1 + 1/(eps sigma) (implicit) or 1 (explicit)
+  int32_t offdiag = 1;                 // 0 for the explicit scheme (K = P)
+};
+
+struct SweepCfg {
+  int storage = kF64;
+  int spw = 4;  // systems per workgroup (wave per system)
+};
+
+// assembly / raw blocks
+void launch_assemble(int storage, const DevPattern& p, const DevFlow& f, void* offd, void* diag, hipStream_t s);
+void launch_set_blocks(int storage, const DevPattern& p, int64_t N, int64_t E, const int32_t* perm,
+                       const int64_t* edge_ent, const double* diag_user, const double* offd_user, void* offd,
+                       void* diag, hipStream_t s);
+void launch_get_blocks(int storage, const DevPattern& p, int64_t N, int64_t E, const int32_t* perm,
+                       const int64_t* edge_ent, const void* offd, const void* diag, double* diag_user,
+                       double* offd_user, hipStream_t s);
+
+// factorisation of one colour (tiles [t0, t0+nt), rows below cstart are lower)
+void launch_factor(int storage, bool dilu, const DevPattern& p, const void* offd, const void* diag, void* dinv,
+                   int64_t dinv_stride, const SysBatch& sb, int64_t t0, int64_t nt, int64_t cstart, int* err,
+                   hipStream_t s);
+
+// sweeps; TV = double for F64 storage, float otherwise
+void launch_rb_pass(const SweepCfg& c, bool update, const DevPattern& p, const void* offd, const void* diag,
+                    const void* dinv, int64_t dinv_stride, void* x, const void* b, const SysBatch& sb,
+                    const SysState* st, double* partial, int64_t t0, int64_t nt, hipStream_t s);
+void launch_fwd(const SweepCfg& c, bool last, const DevPattern& p, const void* offd, const void* diag,
+                const void* dinv, int64_t dinv_stride, void* x, const void* b, void* y, const SysBatch& sb,
+                const SysState* st, double* partial, int64_t t0, int64_t nt, int64_t cstart, hipStream_t s);
+void launch_bwd(const SweepCfg& c, const DevPattern& p, const void* offd, const void* dinv, int64_t dinv_stride,
+                void* x, void* y, const SysBatch& sb, const SysState* st, int64_t t0, int64_t nt, int64_t cend,
+                hipStream_t s);
+void launch_jacobi(const SweepCfg& c, const DevPattern& p, const void* offd, const void* diag, const void* dinv,
+                   int64_t dinv_stride, const void* x, const void* b, void* y, const SysBatch& sb,
+                   const SysState* st, double* partial, hipStream_t s);
+void launch_axpy_y(int storage, const DevPattern& p, void* x, const void* y, const SysBatch& sb,
+                   const SysState* st, hipStream_t s);
+
+// residual norms -> state.  modes: 0 init (limit = max_sweeps), 1 sweep with a valid
+// norm, 2 sweep without a norm, 3 final (record only), 4 outer FP64 correction test
+enum { kReduceInit = 0, kReduceSweep = 1, kReduceSweepNoNorm = 2, kReduceFinal = 3, kReduceOuter = 4 };
+void launch_reduce(const SysBatch& sb, const double* partial, int64_t n_tiles, int64_t t0, int64_t nt,
+                   SysState* st, int mode, double rtol, double div_factor, int max_sweeps, hipStream_t s);
+
+// FP64 residual r = b - K_s x.  stored: blocks of the given storage upcast; mfree: Rusanov
+// recomputed from the FP64 state.  r may be null.
+void launch_resid_stored(int storage, const DevPattern& p, const void* offd, const void* diag, const double* x,
+                         const double* b, double* r, const SysBatch& sb, double* partial, hipStream_t s);
+void launch_resid_mfree(const DevPattern& p, const DevFlow& f, const double* x, const double* b, double* r,
+                        const SysBatch& sb, double* partial, hipStream_t s);
+
+// vectors
+void launch_to_internal(const DevPattern& p, const int32_t* iperm, const double* user, double* internal, int width,
+                        hipStream_t s);
+void launch_to_user(const DevPattern& p, const int32_t* iperm, const double* internal, double* user, int width,
+                    hipStream_t s);
+void launch_to_f32(const DevPattern& p, const double* r64, float* rhs32, float* d32, const SysBatch& sb,
+                   const SysState* outer, hipStream_t s);
+void launch_add_f32(const DevPattern& p, double* x64, const float* d32, const SysBatch& sb, const SysState* outer,
+                    hipStream_t s);
+void launch_inner_init(const SysBatch& sb, const SysState* outer, SysState* inner, int max_sweeps, hipStream_t s);
+void launch_outer_update(const SysBatch& sb, const SysState* inner, SysState* outer, hipStream_t s);
+void launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+
+}  // namespace fnlh

@@ -1,0 +1,989 @@
+// gfx950 kernels of the shared-Jacobian, frequency-shifted block solve.
+//
+// Work decomposition: a tile is 64 consecutive internal rows of one colour (one row per
+// lane of a wave).  A workgroup handles one tile for `spw` systems, one wave per system:
+// the waves of a workgroup read the same off-diagonal blocks (sliced-ELL, coalesced
+// 16-byte loads, served once from HBM and then from L2/L1), each applies them to its own
+// system's vectors, whose only difference is the diagonal shift i omega V (section
+// "Generalized RK Scheme for Time-Linearized Harmonic Flows": the harmonic LHS differs
+// from the mean-flow LHS by that diagonal term and keeps its pattern).
+//
+// No floating-point atomics: norms are reduced per wave with shuffles, written per
+// (system, tile), then summed in a fixed order by one workgroup per system, so results
+// are bitwise reproducible run to run.
+#include <cfloat>
+
+#include "device.h"
+#include "kernels.h"
+
+namespace fnlh {
+
+namespace {
+
+constexpr int kOK = 0, kNotConverged = 1, kDiverged = 2;
+
+inline dim3 tile_grid(int64_t nt, int ng) {
+  const int64_t total = nt * ng;
+  const int64_t per = (total + 7) / 8;
+  return dim3((unsigned)(8 * per));
+}
+
+template <typename TB> struct TV_of {
+  using T = typename Fmt<TB>::A;
+};
+
+__device__ inline double shift_w(const DevPattern& p, int orow, int64_t row) {
+  return p.omega[(int64_t)orow * p.n_zones + p.zone[row]] * p.vol[row];
+}
+
+// acc -= (K_ii + i w I) x_i
+template <typename A>
+__device__ inline void sub_diag_shift(A (&acc)[12], const A (&d)[36], A w, const A (&xi)[12]) {
+  sub_kx(acc, d, xi);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    acc[2 * c] += w * xi[2 * c + 1];
+    acc[2 * c + 1] -= w * xi[2 * c];
+  }
+}
+
+template <typename A> __device__ inline double norm2_12(const A (&v)[12]) {
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) s += (double)v[i] * (double)v[i];
+  return s;
+}
+
+// ================================================================ sweeps
+// Two-colour fused pass.  With colours C0 (first) and C1, the DILU-Richardson step
+//   forward:  y = Dt^-1 (r - L y),  backward: z = y - Dt^-1 U z,  x += z
+// satisfies, row by row,
+//   C0 rows:  x_i <- Dt_i^-1 (b_i - sum_k K_ik x_k)          (Dt_i = D_i on C0)
+//   C1 rows:  x_k <- x_k + Dt_k^-1 (b_k - D_k x_k - sum_i K_ki x_i)
+// so one step = [C1 pass, C0 pass] after an initial C0 pass, each block read once per
+// step, and the C1 pass accumulates ||b - K_s x||^2 of the previous iterate (its C0
+// residual is zero).  UPDATE = C1 form, !UPDATE = C0 form.
+template <typename TB, bool UPDATE>
+__global__ void __launch_bounds__(256) k_rb_pass(DevPattern p, const TB* __restrict__ offd,
+                                                 const TB* __restrict__ diag,
+                                                 const typename TV_of<TB>::T* __restrict__ dinv, int64_t dstride,
+                                                 typename TV_of<TB>::T* __restrict__ x,
+                                                 const typename TV_of<TB>::T* __restrict__ b, SysBatch sb,
+                                                 const SysState* __restrict__ st, double* __restrict__ partial,
+                                                 int64_t t0, int64_t nt, int spw) {
+  using A = typename TV_of<TB>::T;
+  int64_t tile;
+  int grp;
+  const int ng = (sb.n + spw - 1) / spw;
+  if (!map_tile(nt, ng, tile, grp)) return;
+  tile += t0;
+  const int lane = threadIdx.x & 63;
+  const int k = grp * spw + (int)(threadIdx.x >> 6);
+  if (k >= sb.n) return;
+  const int vs = sb.vslot[k];
+  const int act = st[vs].active, pen = st[vs].pending;
+  if (UPDATE ? (!act || pen) : !act) return;
+  const int64_t row = tile * kLanes + lane;
+  const bool valid = lane < p.tile_nrows[tile];
+  A* xs = x + (size_t)vs * p.NP * 12;
+  const A* bs = b + (size_t)vs * p.NP * 12;
+  A acc[12];
+  load_vec(bs + row * 12, acc);
+  A xi[12];
+  if (UPDATE) {
+    load_vec(xs + row * 12, xi);
+    A d[36];
+    load_block(diag + tile * slot_elems<TB>(), lane, d);
+    sub_diag_shift(acc, d, (A)shift_w(p, sb.orow[k], row), xi);
+  }
+  const int w = p.tile_width[tile];
+  const int64_t s0 = p.tile_slot0[tile];
+  for (int q = 0; q < w; ++q) {
+    const int64_t slot = s0 + q;
+    const int nb = p.ent_nbr[slot * kLanes + lane];
+    A kb[36];
+    load_block(offd + slot * slot_elems<TB>(), lane, kb);
+    A xn[12];
+    load_vec(xs + (int64_t)nb * 12, xn);
+    sub_kx(acc, kb, xn);
+  }
+  if (UPDATE) {
+    double n2 = wave_sum(valid ? norm2_12(acc) : 0.0);
+    if (lane == 0) partial[(int64_t)vs * p.n_tiles + tile] = n2;
+  }
+  A y[12];
+  apply_dinv(dinv + (int64_t)sb.dslot[k] * dstride + tile * kDinvTile, lane, acc, y);
+  if (valid) {
+    if (UPDATE) {
+#pragma unroll
+      for (int i = 0; i < 12; ++i) y[i] += xi[i];
+    }
+    store_vec(xs + row * 12, y);
+  }
+}
+
+// General colouring, forward pass of colour c (rows of lower colours are < cstart):
+//   r_i = b_i - (K_ii + i w) x_i - sum_k K_ik x_k      (accumulated into ||r||^2)
+//   y_i = Dt_i^-1 (r_i - sum_{k lower} K_ik y_k);  LAST colour: x_i += y_i (z = y there)
+template <typename TB, bool LAST>
+__global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict__ offd, const TB* __restrict__ diag,
+                                             const typename TV_of<TB>::T* __restrict__ dinv, int64_t dstride,
+                                             typename TV_of<TB>::T* __restrict__ x,
+                                             const typename TV_of<TB>::T* __restrict__ b,
+                                             typename TV_of<TB>::T* __restrict__ y, SysBatch sb,
+                                             const SysState* __restrict__ st, double* __restrict__ partial,
+                                             int64_t t0, int64_t nt, int64_t cstart, int spw) {
+  using A = typename TV_of<TB>::T;
+  int64_t tile;
+  int grp;
+  const int ng = (sb.n + spw - 1) / spw;
+  if (!map_tile(nt, ng, tile, grp)) return;
+  tile += t0;
+  const int lane = threadIdx.x & 63;
+  const int k = grp * spw + (int)(threadIdx.x >> 6);
+  if (k >= sb.n) return;
+  const int vs = sb.vslot[k];
+  if (!st[vs].active || st[vs].pending) return;
+  const int64_t row = tile * kLanes + lane;
+  const bool valid = lane < p.tile_nrows[tile];
+  const size_t vo = (size_t)vs * p.NP * 12;
+  A r[12], t[12], xi[12];
+  load_vec(b + vo + row * 12, r);
+  load_vec(x + vo + row * 12, xi);
+  {
+    A d[36];
+    load_block(diag + tile * slot_elems<TB>(), lane, d);
+    sub_diag_shift(r, d, (A)shift_w(p, sb.orow[k], row), xi);
+  }
+#pragma unroll
+  for (int i = 0; i < 12; ++i) t[i] = 0;
+  const int w = p.tile_width[tile];
+  const int64_t s0 = p.tile_slot0[tile];
+  for (int q = 0; q < w; ++q) {
+    const int64_t slot = s0 + q;
+    const int nb = p.ent_nbr[slot * kLanes + lane];
+    A kb[36];
+    load_block(offd + slot * slot_elems<TB>(), lane, kb);
+    A v[12];
+    load_vec(x + vo + (int64_t)nb * 12, v);
+    sub_kx(r, kb, v);
+    if (nb < cstart) {
+      load_vec(y + vo + (int64_t)nb * 12, v);
+      sub_kx(t, kb, v);
+    }
+  }
+  double n2 = wave_sum(valid ? norm2_12(r) : 0.0);
+  if (lane == 0) partial[(int64_t)vs * p.n_tiles + tile] = n2;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) t[i] += r[i];
+  A yi[12];
+  apply_dinv(dinv + (int64_t)sb.dslot[k] * dstride + tile * kDinvTile, lane, t, yi);
+  if (valid) {
+    store_vec(y + vo + row * 12, yi);
+    if (LAST) {
+#pragma unroll
+      for (int i = 0; i < 12; ++i) xi[i] += yi[i];
+      store_vec(x + vo + row * 12, xi);
+    }
+  }
+}
+
+// General colouring, backward pass of colour c (rows of higher colours are >= cend and
+// already hold z in y):  z_i = y_i - Dt_i^-1 sum_{k upper} K_ik z_k;  x_i += z_i; y_i <- z_i
+template <typename TB>
+__global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict__ offd,
+                                             const typename TV_of<TB>::T* __restrict__ dinv, int64_t dstride,
+                                             typename TV_of<TB>::T* __restrict__ x,
+                                             typename TV_of<TB>::T* __restrict__ y, SysBatch sb,
+                                             const SysState* __restrict__ st, int64_t t0, int64_t nt, int64_t cend,
+                                             int spw) {
+  using A = typename TV_of<TB>::T;
+  int64_t tile;
+  int grp;
+  const int ng = (sb.n + spw - 1) / spw;
+  if (!map_tile(nt, ng, tile, grp)) return;
+  tile += t0;
+  const int lane = threadIdx.x & 63;
+  const int k = grp * spw + (int)(threadIdx.x >> 6);
+  if (k >= sb.n) return;
+  const int vs = sb.vslot[k];
+  if (!st[vs].active) return;
+  const int64_t row = tile * kLanes + lane;
+  const bool valid = lane < p.tile_nrows[tile];
+  const size_t vo = (size_t)vs * p.NP * 12;
+  A t[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) t[i] = 0;
+  const int w = p.tile_width[tile];
+  const int64_t s0 = p.tile_slot0[tile];
+  for (int q = 0; q < w; ++q) {
+    const int64_t slot = s0 + q;
+    const int nb = p.ent_nbr[slot * kLanes + lane];
+    if (nb >= cend) {
+      A kb[36];
+      load_block(offd + slot * slot_elems<TB>(), lane, kb);
+      A v[12];
+      load_vec(y + vo + (int64_t)nb * 12, v);
+      sub_kx(t, kb, v);
+    }
+  }
+  A z[12];
+  apply_dinv(dinv + (int64_t)sb.dslot[k] * dstride + tile * kDinvTile, lane, t, z);
+  if (valid) {
+    A yi[12], xi[12];
+    load_vec(y + vo + row * 12, yi);
+    load_vec(x + vo + row * 12, xi);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      z[i] += yi[i];
+      xi[i] += z[i];
+    }
+    store_vec(y + vo + row * 12, z);
+    store_vec(x + vo + row * 12, xi);
+  }
+}
+
+// Block Jacobi (the paper's explicit, point-by-point inversion): y = D_s^-1 (b - K_s x)
+// over all rows, then x += y.
+template <typename TB>
+__global__ void __launch_bounds__(256) k_jacobi(DevPattern p, const TB* __restrict__ offd,
+                                                const TB* __restrict__ diag,
+                                                const typename TV_of<TB>::T* __restrict__ dinv, int64_t dstride,
+                                                const typename TV_of<TB>::T* __restrict__ x,
+                                                const typename TV_of<TB>::T* __restrict__ b,
+                                                typename TV_of<TB>::T* __restrict__ y, SysBatch sb,
+                                                const SysState* __restrict__ st, double* __restrict__ partial,
+                                                int spw) {
+  using A = typename TV_of<TB>::T;
+  int64_t tile;
+  int grp;
+  const int ng = (sb.n + spw - 1) / spw;
+  if (!map_tile(p.n_tiles, ng, tile, grp)) return;
+  const int lane = threadIdx.x & 63;
+  const int k = grp * spw + (int)(threadIdx.x >> 6);
+  if (k >= sb.n) return;
+  const int vs = sb.vslot[k];
+  if (!st[vs].active || st[vs].pending) return;
+  const int64_t row = tile * kLanes + lane;
+  const bool valid = lane < p.tile_nrows[tile];
+  const size_t vo = (size_t)vs * p.NP * 12;
+  A r[12], xi[12];
+  load_vec(b + vo + row * 12, r);
+  load_vec(x + vo + row * 12, xi);
+  {
+    A d[36];
+    load_block(diag + tile * slot_elems<TB>(), lane, d);
+    sub_diag_shift(r, d, (A)shift_w(p, sb.orow[k], row), xi);
+  }
+  const int w = p.tile_width[tile];
+  const int64_t s0 = p.tile_slot0[tile];
+  for (int q = 0; q < w; ++q) {
+    const int64_t slot = s0 + q;
+    const int nb = p.ent_nbr[slot * kLanes + lane];
+    A kb[36];
+    load_block(offd + slot * slot_elems<TB>(), lane, kb);
+    A v[12];
+    load_vec(x + vo + (int64_t)nb * 12, v);
+    sub_kx(r, kb, v);
+  }
+  double n2 = wave_sum(valid ? norm2_12(r) : 0.0);
+  if (lane == 0) partial[(int64_t)vs * p.n_tiles + tile] = n2;
+  A yi[12];
+  apply_dinv(dinv + (int64_t)sb.dslot[k] * dstride + tile * kDinvTile, lane, r, yi);
+  if (valid) store_vec(y + vo + row * 12, yi);
+}
+
+template <typename A>
+__global__ void k_axpy_y(int64_t NP, A* __restrict__ x, const A* __restrict__ y, SysBatch sb,
+                         const SysState* __restrict__ st) {
+  const int k = blockIdx.y;
+  const int vs = sb.vslot[k];
+  if (!st[vs].active) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NP * 12) return;
+  const size_t o = (size_t)vs * NP * 12 + i;
+  x[o] += y[o];
+}
+
+// ================================================================ norm reduction
+__global__ void __launch_bounds__(256) k_reduce(SysBatch sb, const double* __restrict__ partial, int64_t n_tiles,
+                                                int64_t t0, int64_t nt, SysState* __restrict__ st, int mode,
+                                                double rtol2, double div2, int max_sweeps) {
+  __shared__ double sh[256];
+  const int k = blockIdx.x;
+  const int vs = sb.vslot[k];
+  double s = 0.0;
+  if (mode != kReduceSweepNoNorm) {
+    const double* pp = partial + (int64_t)vs * n_tiles + t0;
+    for (int64_t i = threadIdx.x; i < nt; i += 256) s += pp[i];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double n2 = sh[0];
+  SysState S = st[vs];
+  switch (mode) {
+    case kReduceInit:
+      S.norm0sq = n2;
+      S.last_n2 = n2;
+      S.sweeps = 0;
+      S.pending = 0;
+      S.outer_iters = 0;
+      S.limit = max_sweeps;
+      if (!isfinite(n2)) {
+        S.status = kDiverged;
+        S.active = 0;
+      } else {
+        S.status = n2 > 0.0 ? kNotConverged : kOK;
+        S.active = (n2 > 0.0 && max_sweeps > 0) ? 1 : 0;
+      }
+      break;
+    case kReduceSweep:
+    case kReduceSweepNoNorm:
+      if (!S.active) break;
+      if (S.pending) {
+        S.active = 0;
+        break;
+      }
+      S.sweeps += 1;
+      if (mode == kReduceSweep) {
+        S.last_n2 = n2;
+        if (n2 <= rtol2 * S.norm0sq) {
+          S.status = kOK;
+          S.pending = 1;
+        } else if (!isfinite(n2) || n2 > div2 * S.norm0sq) {
+          S.status = kDiverged;
+          S.pending = 1;
+        }
+      }
+      if (S.sweeps >= S.limit) S.pending = 1;
+      break;
+    case kReduceFinal:
+      S.last_n2 = n2;
+      break;
+    case kReduceOuter:
+      S.last_n2 = n2;
+      if (!S.active) break;
+      if (n2 <= rtol2 * S.norm0sq) {
+        S.status = kOK;
+        S.active = 0;
+      } else if (!isfinite(n2) || n2 > div2 * S.norm0sq) {
+        S.status = kDiverged;
+        S.active = 0;
+      } else if (S.sweeps >= S.limit) {
+        S.status = kNotConverged;
+        S.active = 0;
+      }
+      break;
+  }
+  st[vs] = S;
+}
+
+__global__ void k_inner_init(SysBatch sb, const SysState* __restrict__ outer, SysState* __restrict__ inner,
+                             int max_inner) {
+  const int k = threadIdx.x;
+  if (k >= sb.n) return;
+  const int vs = sb.vslot[k];
+  const SysState O = outer[vs];
+  SysState I;
+  I.norm0sq = O.last_n2;
+  I.last_n2 = O.last_n2;
+  I.pending = 0;
+  I.sweeps = 0;
+  I.outer_iters = 0;
+  I.status = kNotConverged;
+  int lim = O.limit - O.sweeps;
+  if (lim > max_inner) lim = max_inner;
+  I.limit = lim;
+  I.active = (O.active && lim > 0 && O.last_n2 > 0.0) ? 1 : 0;
+  inner[vs] = I;
+}
+
+__global__ void k_outer_update(SysBatch sb, const SysState* __restrict__ inner, SysState* __restrict__ outer) {
+  const int k = threadIdx.x;
+  if (k >= sb.n) return;
+  const int vs = sb.vslot[k];
+  if (!outer[vs].active) return;
+  outer[vs].sweeps += inner[vs].sweeps;
+  outer[vs].outer_iters += 1;
+}
+
+// ================================================================ assembly
+// First-order Rusanov Jacobian (frozen spectral radius), section "Generalized RK Scheme
+// for The Mean Flow": for row i and neighbour k with area S_ik (outward from i),
+//   K_ik = 1/2 A(Q_k; S_ik) - 1/2 lam_ik I,  lam_ik = max(rho(Q_i,S), rho(Q_k,S))
+//   J_ii = sum over faces [1/2 A(Q_i; S) + 1/2 lam I] = 1/2 A(Q_i; sum S) + 1/2 (sum lam) I
+// (A is linear in S), boundary faces against the frozen far-field state, and
+// K_ii = (1 + 1/(eps sigma)) J_ii (implicit) / J_ii with no off-diagonal (explicit).
+__device__ inline void load_state(const double* __restrict__ q, double (&Q)[6]) {
+  const double2* p = reinterpret_cast<const double2*>(q);
+  double2 a = p[0], b = p[1], c = p[2];
+  Q[0] = a.x;
+  Q[1] = a.y;
+  Q[2] = b.x;
+  Q[3] = b.y;
+  Q[4] = c.x;
+  Q[5] = c.y;
+}
+
+__device__ inline void entry_area(const DevFlow& f, int32_t e, double (&S)[3]) {
+  const int64_t id = (e > 0 ? e : -e) - 1;
+  const double sg = e > 0 ? 1.0 : -1.0;
+  S[0] = sg * f.area[3 * id];
+  S[1] = sg * f.area[3 * id + 1];
+  S[2] = sg * f.area[3 * id + 2];
+}
+
+template <typename TB>
+__global__ void __launch_bounds__(64) k_assemble(DevPattern p, DevFlow f, TB* __restrict__ offd,
+                                                 TB* __restrict__ diag) {
+  const int64_t tile = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t row = tile * kLanes + lane;
+  const bool valid = lane < p.tile_nrows[tile];
+  double Qi[6] = {1, 0, 0, 0, 2.5, 0};
+  if (valid) load_state(f.state + row * 6, Qi);
+  double sumS[3] = {0, 0, 0}, lam_sum = 0.0;
+  const int w = p.tile_width[tile];
+  const int64_t s0 = p.tile_slot0[tile];
+  for (int q = 0; q < w; ++q) {
+    const int64_t slot = s0 + q;
+    const int64_t fe = slot * kLanes + lane;
+    const int32_t e = p.ent_edge[fe];
+    TB* dst = offd + slot * slot_elems<TB>();
+    if (e == 0) {
+#pragma unroll
+      for (int c = 0; c < 36; ++c) store_entry<TB>(dst, c, lane, 0.0);
+      continue;
+    }
+    double S[3], Qk[6], Ak[36];
+    entry_area(f, e, S);
+    load_state(f.state + (int64_t)p.ent_nbr[fe] * 6, Qk);
+    const double lam = fmax(spectral_radius(Qi, S), spectral_radius(Qk, S));
+    flux_jacobian(Qk, S, Ak);
+    sumS[0] += S[0];
+    sumS[1] += S[1];
+    sumS[2] += S[2];
+    lam_sum += lam;
+#pragma unroll
+    for (int c = 0; c < 36; ++c) {
+      double v = 0.5 * Ak[c] - ((c % 7 == 0) ? 0.5 * lam : 0.0);
+      store_entry<TB>(dst, c, lane, f.offdiag ? v : 0.0);
+    }
+  }
+  if (valid) {
+    for (int32_t j = f.bf_ptr[row]; j < f.bf_ptr[row + 1]; ++j) {
+      const int32_t face = f.bf_idx[j];
+      double S[3] = {f.bface_area[3 * face], f.bface_area[3 * face + 1], f.bface_area[3 * face + 2]};
+      double Qf[6];
+      if (f.bstate) {
+        load_state(f.bstate + (int64_t)face * 6, Qf);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) Qf[c] = Qi[c];
+      }
+      lam_sum += fmax(spectral_radius(Qi, S), spectral_radius(Qf, S));
+      sumS[0] += S[0];
+      sumS[1] += S[1];
+      sumS[2] += S[2];
+    }
+  }
+  double Ai[36];
+  flux_jacobian(Qi, sumS, Ai);
+  TB* dst = diag + tile * slot_elems<TB>();
+#pragma unroll
+  for (int c = 0; c < 36; ++c) {
+    double v = f.diag_scale * (0.5 * Ai[c] + ((c % 7 == 0) ? 0.5 * lam_sum : 0.0));
+    store_entry<TB>(dst, c, lane, valid ? v : 0.0);
+  }
+}
+
+// raw blocks: thread per (directed coupling | cell, entry)
+template <typename TB>
+__global__ void k_set_offd(int64_t E, const int64_t* __restrict__ edge_ent, const double* __restrict__ offd_user,
+                           TB* __restrict__ offd) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * E * 36) return;
+  const int64_t d = t / 36;
+  const int c = (int)(t % 36);
+  const int64_t f = edge_ent[d];
+  store_entry<TB>(offd + (f >> 6) * slot_elems<TB>(), c, (int)(f & 63), offd_user[t]);
+}
+template <typename TB>
+__global__ void k_set_diag(int64_t N, const int32_t* __restrict__ perm, const double* __restrict__ diag_user,
+                           TB* __restrict__ diag) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * 36) return;
+  const int64_t u = t / 36;
+  const int c = (int)(t % 36);
+  const int64_t row = perm[u];
+  store_entry<TB>(diag + (row >> 6) * slot_elems<TB>(), c, (int)(row & 63), diag_user[t]);
+}
+template <typename TB>
+__global__ void k_get_offd(int64_t E, const int64_t* __restrict__ edge_ent, const TB* __restrict__ offd,
+                           double* __restrict__ offd_user) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * E * 36) return;
+  const int64_t d = t / 36;
+  const int c = (int)(t % 36);
+  const int64_t f = edge_ent[d];
+  offd_user[t] = load_entry_f64<TB>(offd + (f >> 6) * slot_elems<TB>(), c, (int)(f & 63));
+}
+template <typename TB>
+__global__ void k_get_diag(int64_t N, const int32_t* __restrict__ perm, const TB* __restrict__ diag,
+                           double* __restrict__ diag_user) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * 36) return;
+  const int64_t u = t / 36;
+  const int c = (int)(t % 36);
+  const int64_t row = perm[u];
+  diag_user[t] = load_entry_f64<TB>(diag + (row >> 6) * slot_elems<TB>(), c, (int)(row & 63));
+}
+
+// ================================================================ factorisation
+// Colour c, one wave per (tile, system):
+//   Dt_i = K_ii + i w_i I - sum_{k in N(i), col k < c} K_ik Dt_k^-1 K_ki   (DILU)
+//   Dt_i = K_ii + i w_i I                                                (SGS / Jacobi)
+// in FP64 from the stored blocks, inverted by Gauss-Jordan with partial pivoting.
+template <typename TB, typename TD, bool DILU>
+__global__ void __launch_bounds__(64) k_factor(DevPattern p, const TB* __restrict__ offd,
+                                               const TB* __restrict__ diag, TD* __restrict__ dinv,
+                                               int64_t dstride, SysBatch sb, int64_t t0, int64_t nt, int64_t cstart,
+                                               int* __restrict__ err) {
+  const int64_t tile = t0 + blockIdx.x;
+  const int k = blockIdx.y;
+  const int lane = threadIdx.x;
+  const int64_t row = tile * kLanes + lane;
+  const bool valid = lane < p.tile_nrows[tile];
+  double mr[36], mi[36];
+  const TB* dslot = diag + tile * slot_elems<TB>();
+#pragma unroll
+  for (int c = 0; c < 36; ++c) {
+    mr[c] = load_entry_f64<TB>(dslot, c, lane);
+    mi[c] = 0.0;
+  }
+  const double wv = shift_w(p, sb.orow[k], row);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) mi[7 * c] += wv;
+  TD* dbase = dinv + (int64_t)sb.dslot[k] * dstride;
+  if (DILU) {
+    const int w = p.tile_width[tile];
+    const int64_t s0 = p.tile_slot0[tile];
+    for (int q = 0; q < w; ++q) {
+      const int64_t fe = (s0 + q) * kLanes + lane;
+      const int nb = p.ent_nbr[fe];
+      if (p.ent_edge[fe] == 0 || nb >= cstart) continue;
+      const TB* ks = offd + (s0 + q) * slot_elems<TB>();
+      double kij[36];
+#pragma unroll
+      for (int c = 0; c < 36; ++c) kij[c] = load_entry_f64<TB>(ks, c, lane);
+      const int32_t rv = p.ent_rev[fe];
+      const TB* rs = offd + (int64_t)(rv >> 6) * slot_elems<TB>();
+      const int rl = rv & 63;
+      const TD* dn = dbase + (int64_t)(nb >> 6) * kDinvTile;
+      const int nl = nb & 63;
+      for (int c = 0; c < 6; ++c) {
+        double kc[6];
+#pragma unroll
+        for (int q2 = 0; q2 < 6; ++q2) kc[q2] = load_entry_f64<TB>(rs, 6 * q2 + c, rl);
+        double tr[6], ti[6];
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+          double sr = 0.0, si = 0.0;
+#pragma unroll
+          for (int q2 = 0; q2 < 6; ++q2) {
+            double dr, di;
+            load_dinv_entry<TD>(dn, nl, 6 * r + q2, dr, di);
+            sr += dr * kc[q2];
+            si += di * kc[q2];
+          }
+          tr[r] = sr;
+          ti[r] = si;
+        }
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+          double sr = 0.0, si = 0.0;
+#pragma unroll
+          for (int q2 = 0; q2 < 6; ++q2) {
+            sr += kij[6 * r + q2] * tr[q2];
+            si += kij[6 * r + q2] * ti[q2];
+          }
+          mr[6 * r + c] -= sr;
+          mi[6 * r + c] -= si;
+        }
+      }
+    }
+  }
+  bool ok = true;
+  cinv6(mr, mi, ok);
+  if (valid && !ok) atomicOr(err, 1);
+  if (!valid) {
+#pragma unroll
+    for (int c = 0; c < 36; ++c) {
+      mr[c] = 0.0;
+      mi[c] = 0.0;
+    }
+  }
+  store_dinv<TD>(dbase + tile * kDinvTile, lane, mr, mi);
+}
+
+// ================================================================ FP64 residuals
+template <typename TB>
+__global__ void __launch_bounds__(256) k_resid_stored(DevPattern p, const TB* __restrict__ offd,
+                                                      const TB* __restrict__ diag, const double* __restrict__ x,
+                                                      const double* __restrict__ b, double* __restrict__ r,
+                                                      SysBatch sb, double* __restrict__ partial, int spw) {
+  int64_t tile;
+  int grp;
+  const int ng = (sb.n + spw - 1) / spw;
+  if (!map_tile(p.n_tiles, ng, tile, grp)) return;
+  const int lane = threadIdx.x & 63;
+  const int k = grp * spw + (int)(threadIdx.x >> 6);
+  if (k >= sb.n) return;
+  const int vs = sb.vslot[k];
+  const int64_t row = tile * kLanes + lane;
+  const bool valid = lane < p.tile_nrows[tile];
+  const size_t vo = (size_t)vs * p.NP * 12;
+  double acc[12], xi[12];
+  load_vec(b + vo + row * 12, acc);
+  load_vec(x + vo + row * 12, xi);
+  {
+    double d[36];
+    load_block(diag + tile * slot_elems<TB>(), lane, d);
+    sub_diag_shift(acc, d, shift_w(p, sb.orow[k], row), xi);
+  }
+  const int w = p.tile_width[tile];
+  const int64_t s0 = p.tile_slot0[tile];
+  for (int q = 0; q < w; ++q) {
+    const int64_t slot = s0 + q;
+    const int nb = p.ent_nbr[slot * kLanes + lane];
+    double kb[36], v[12];
+    load_block(offd + slot * slot_elems<TB>(), lane, kb);
+    load_vec(x + vo + (int64_t)nb * 12, v);
+    sub_kx(acc, kb, v);
+  }
+  double n2 = wave_sum(valid ? norm2_12(acc) : 0.0);
+  if (lane == 0) partial[(int64_t)vs * p.n_tiles + tile] = n2;
+  if (r && valid) store_vec(r + vo + row * 12, acc);
+}
+
+__global__ void __launch_bounds__(256) k_resid_mfree(DevPattern p, DevFlow f, const double* __restrict__ x,
+                                                     const double* __restrict__ b, double* __restrict__ r,
+                                                     SysBatch sb, double* __restrict__ partial, int spw) {
+  int64_t tile;
+  int grp;
+  const int ng = (sb.n + spw - 1) / spw;
+  if (!map_tile(p.n_tiles, ng, tile, grp)) return;
+  const int lane = threadIdx.x & 63;
+  const int k = grp * spw + (int)(threadIdx.x >> 6);
+  if (k >= sb.n) return;
+  const int vs = sb.vslot[k];
+  const int64_t row = tile * kLanes + lane;
+  const bool valid = lane < p.tile_nrows[tile];
+  const size_t vo = (size_t)vs * p.NP * 12;
+  double Qi[6] = {1, 0, 0, 0, 2.5, 0};
+  if (valid) load_state(f.state + row * 6, Qi);
+  double acc[12], xi[12];
+  load_vec(b + vo + row * 12, acc);
+  load_vec(x + vo + row * 12, xi);
+  double sumS[3] = {0, 0, 0}, lam_sum = 0.0;
+  const int w = p.tile_width[tile];
+  const int64_t s0 = p.tile_slot0[tile];
+  for (int q = 0; q < w; ++q) {
+    const int64_t fe = (s0 + q) * kLanes + lane;
+    const int32_t e = p.ent_edge[fe];
+    if (e == 0) continue;
+    const int nb = p.ent_nbr[fe];
+    double S[3], Qk[6], Ak[36], v[12];
+    entry_area(f, e, S);
+    load_state(f.state + (int64_t)nb * 6, Qk);
+    const double lam = fmax(spectral_radius(Qi, S), spectral_radius(Qk, S));
+    sumS[0] += S[0];
+    sumS[1] += S[1];
+    sumS[2] += S[2];
+    lam_sum += lam;
+    if (!f.offdiag) continue;
+    flux_jacobian(Qk, S, Ak);
+#pragma unroll
+    for (int c = 0; c < 36; ++c) Ak[c] = 0.5 * Ak[c] - ((c % 7 == 0) ? 0.5 * lam : 0.0);
+    load_vec(x + vo + (int64_t)nb * 12, v);
+    sub_kx(acc, Ak, v);
+  }
+  if (valid) {
+    for (int32_t j = f.bf_ptr[row]; j < f.bf_ptr[row + 1]; ++j) {
+      const int32_t face = f.bf_idx[j];
+      double S[3] = {f.bface_area[3 * face], f.bface_area[3 * face + 1], f.bface_area[3 * face + 2]};
+      double Qf[6];
+      if (f.bstate) {
+        load_state(f.bstate + (int64_t)face * 6, Qf);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) Qf[c] = Qi[c];
+      }
+      lam_sum += fmax(spectral_radius(Qi, S), spectral_radius(Qf, S));
+      sumS[0] += S[0];
+      sumS[1] += S[1];
+      sumS[2] += S[2];
+    }
+  }
+  double Ai[36];
+  flux_jacobian(Qi, sumS, Ai);
+#pragma unroll
+  for (int c = 0; c < 36; ++c) Ai[c] = f.diag_scale * (0.5 * Ai[c] + ((c % 7 == 0) ? 0.5 * lam_sum : 0.0));
+  sub_diag_shift(acc, Ai, shift_w(p, sb.orow[k], row), xi);
+  double n2 = wave_sum(valid ? norm2_12(acc) : 0.0);
+  if (lane == 0) partial[(int64_t)vs * p.n_tiles + tile] = n2;
+  if (r && valid) store_vec(r + vo + row * 12, acc);
+}
+
+// ================================================================ vectors
+__global__ void k_to_internal(int64_t NP, const int32_t* __restrict__ iperm, const double* __restrict__ user,
+                              double* __restrict__ internal, int width) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= NP * width) return;
+  const int64_t row = t / width;
+  const int c = (int)(t % width);
+  const int32_t u = iperm[row];
+  internal[t] = u >= 0 ? user[(int64_t)u * width + c] : 0.0;
+}
+__global__ void k_to_user(int64_t NP, const int32_t* __restrict__ iperm, const double* __restrict__ internal,
+                          double* __restrict__ user, int width) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= NP * width) return;
+  const int64_t row = t / width;
+  const int c = (int)(t % width);
+  const int32_t u = iperm[row];
+  if (u >= 0) user[(int64_t)u * width + c] = internal[t];
+}
+__global__ void k_to_f32(int64_t NP, const double* __restrict__ r64, float* __restrict__ rhs32,
+                         float* __restrict__ d32, SysBatch sb, const SysState* __restrict__ outer) {
+  const int k = blockIdx.y;
+  const int vs = sb.vslot[k];
+  if (!outer[vs].active) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NP * 12) return;
+  const size_t o = (size_t)vs * NP * 12 + i;
+  rhs32[o] = (float)r64[o];
+  d32[o] = 0.0f;
+}
+__global__ void k_add_f32(int64_t NP, double* __restrict__ x64, const float* __restrict__ d32, SysBatch sb,
+                          const SysState* __restrict__ outer) {
+  const int k = blockIdx.y;
+  const int vs = sb.vslot[k];
+  if (!outer[vs].active) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NP * 12) return;
+  const size_t o = (size_t)vs * NP * 12 + i;
+  x64[o] += (double)d32[o];
+}
+__global__ void k_fill_zero(uint32_t* __restrict__ p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+inline int ng_of(const SysBatch& sb, int spw) { return (sb.n + spw - 1) / spw; }
+
+}  // namespace
+
+// ================================================================ launchers
+#define FNLH_DISPATCH_STORE(storage, BODY)    \
+  do {                                        \
+    if ((storage) == kF64) {                  \
+      using TB = double;                      \
+      BODY;                                   \
+    } else if ((storage) == kF32) {           \
+      using TB = float;                       \
+      BODY;                                   \
+    } else {                                  \
+      using TB = bf16s;                       \
+      BODY;                                   \
+    }                                         \
+  } while (0)
+
+void launch_assemble(int storage, const DevPattern& p, const DevFlow& f, void* offd, void* diag, hipStream_t s) {
+  FNLH_DISPATCH_STORE(storage, {
+    hipLaunchKernelGGL((k_assemble<TB>), dim3((unsigned)p.n_tiles), dim3(64), 0, s, p, f, (TB*)offd, (TB*)diag);
+  });
+}
+
+void launch_set_blocks(int storage, const DevPattern& p, int64_t N, int64_t E, const int32_t* perm,
+                       const int64_t* edge_ent, const double* diag_user, const double* offd_user, void* offd,
+                       void* diag, hipStream_t s) {
+  FNLH_DISPATCH_STORE(storage, {
+    if (E > 0)
+      hipLaunchKernelGGL((k_set_offd<TB>), dim3((unsigned)((2 * E * 36 + 255) / 256)), dim3(256), 0, s, E, edge_ent,
+                         offd_user, (TB*)offd);
+    hipLaunchKernelGGL((k_set_diag<TB>), dim3((unsigned)((N * 36 + 255) / 256)), dim3(256), 0, s, N, perm, diag_user,
+                       (TB*)diag);
+  });
+}
+
+void launch_get_blocks(int storage, const DevPattern& p, int64_t N, int64_t E, const int32_t* perm,
+                       const int64_t* edge_ent, const void* offd, const void* diag, double* diag_user,
+                       double* offd_user, hipStream_t s) {
+  FNLH_DISPATCH_STORE(storage, {
+    if (E > 0)
+      hipLaunchKernelGGL((k_get_offd<TB>), dim3((unsigned)((2 * E * 36 + 255) / 256)), dim3(256), 0, s, E, edge_ent,
+                         (const TB*)offd, offd_user);
+    hipLaunchKernelGGL((k_get_diag<TB>), dim3((unsigned)((N * 36 + 255) / 256)), dim3(256), 0, s, N, perm,
+                       (const TB*)diag, diag_user);
+  });
+}
+
+void launch_factor(int storage, bool dilu, const DevPattern& p, const void* offd, const void* diag, void* dinv,
+                   int64_t dinv_stride, const SysBatch& sb, int64_t t0, int64_t nt, int64_t cstart, int* err,
+                   hipStream_t s) {
+  if (nt <= 0 || sb.n <= 0) return;
+  dim3 grid((unsigned)nt, (unsigned)sb.n);
+  FNLH_DISPATCH_STORE(storage, {
+    using TD = typename Fmt<TB>::A;
+    if (dilu)
+      hipLaunchKernelGGL((k_factor<TB, TD, true>), grid, dim3(64), 0, s, p, (const TB*)offd, (const TB*)diag,
+                         (TD*)dinv, dinv_stride, sb, t0, nt, cstart, err);
+    else
+      hipLaunchKernelGGL((k_factor<TB, TD, false>), grid, dim3(64), 0, s, p, (const TB*)offd, (const TB*)diag,
+                         (TD*)dinv, dinv_stride, sb, t0, nt, cstart, err);
+  });
+}
+
+void launch_rb_pass(const SweepCfg& c, bool update, const DevPattern& p, const void* offd, const void* diag,
+                    const void* dinv, int64_t dinv_stride, void* x, const void* b, const SysBatch& sb,
+                    const SysState* st, double* partial, int64_t t0, int64_t nt, hipStream_t s) {
+  if (nt <= 0 || sb.n <= 0) return;
+  const int spw = c.spw < sb.n ? c.spw : sb.n;
+  dim3 grid = tile_grid(nt, ng_of(sb, spw));
+  dim3 block(64 * spw);
+  FNLH_DISPATCH_STORE(c.storage, {
+    using A = typename Fmt<TB>::A;
+    if (update)
+      hipLaunchKernelGGL((k_rb_pass<TB, true>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag,
+                         (const A*)dinv, dinv_stride, (A*)x, (const A*)b, sb, st, partial, t0, nt, spw);
+    else
+      hipLaunchKernelGGL((k_rb_pass<TB, false>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag,
+                         (const A*)dinv, dinv_stride, (A*)x, (const A*)b, sb, st, partial, t0, nt, spw);
+  });
+}
+
+void launch_fwd(const SweepCfg& c, bool last, const DevPattern& p, const void* offd, const void* diag,
+                const void* dinv, int64_t dinv_stride, void* x, const void* b, void* y, const SysBatch& sb,
+                const SysState* st, double* partial, int64_t t0, int64_t nt, int64_t cstart, hipStream_t s) {
+  if (nt <= 0 || sb.n <= 0) return;
+  const int spw = c.spw < sb.n ? c.spw : sb.n;
+  dim3 grid = tile_grid(nt, ng_of(sb, spw));
+  dim3 block(64 * spw);
+  FNLH_DISPATCH_STORE(c.storage, {
+    using A = typename Fmt<TB>::A;
+    if (last)
+      hipLaunchKernelGGL((k_fwd<TB, true>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag, (const A*)dinv,
+                         dinv_stride, (A*)x, (const A*)b, (A*)y, sb, st, partial, t0, nt, cstart, spw);
+    else
+      hipLaunchKernelGGL((k_fwd<TB, false>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag, (const A*)dinv,
+                         dinv_stride, (A*)x, (const A*)b, (A*)y, sb, st, partial, t0, nt, cstart, spw);
+  });
+}
+
+void launch_bwd(const SweepCfg& c, const DevPattern& p, const void* offd, const void* dinv, int64_t dinv_stride,
+                void* x, void* y, const SysBatch& sb, const SysState* st, int64_t t0, int64_t nt, int64_t cend,
+                hipStream_t s) {
+  if (nt <= 0 || sb.n <= 0) return;
+  const int spw = c.spw < sb.n ? c.spw : sb.n;
+  dim3 grid = tile_grid(nt, ng_of(sb, spw));
+  dim3 block(64 * spw);
+  FNLH_DISPATCH_STORE(c.storage, {
+    using A = typename Fmt<TB>::A;
+    hipLaunchKernelGGL((k_bwd<TB>), grid, block, 0, s, p, (const TB*)offd, (const A*)dinv, dinv_stride, (A*)x, (A*)y,
+                       sb, st, t0, nt, cend, spw);
+  });
+}
+
+void launch_jacobi(const SweepCfg& c, const DevPattern& p, const void* offd, const void* diag, const void* dinv,
+                   int64_t dinv_stride, const void* x, const void* b, void* y, const SysBatch& sb,
+                   const SysState* st, double* partial, hipStream_t s) {
+  if (sb.n <= 0) return;
+  const int spw = c.spw < sb.n ? c.spw : sb.n;
+  dim3 grid = tile_grid(p.n_tiles, ng_of(sb, spw));
+  dim3 block(64 * spw);
+  FNLH_DISPATCH_STORE(c.storage, {
+    using A = typename Fmt<TB>::A;
+    hipLaunchKernelGGL((k_jacobi<TB>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag, (const A*)dinv,
+                       dinv_stride, (const A*)x, (const A*)b, (A*)y, sb, st, partial, spw);
+  });
+}
+
+void launch_axpy_y(int storage, const DevPattern& p, void* x, const void* y, const SysBatch& sb,
+                   const SysState* st, hipStream_t s) {
+  if (sb.n <= 0) return;
+  dim3 grid((unsigned)((p.NP * 12 + 255) / 256), (unsigned)sb.n);
+  if (storage == kF64)
+    hipLaunchKernelGGL((k_axpy_y<double>), grid, dim3(256), 0, s, p.NP, (double*)x, (const double*)y, sb, st);
+  else
+    hipLaunchKernelGGL((k_axpy_y<float>), grid, dim3(256), 0, s, p.NP, (float*)x, (const float*)y, sb, st);
+}
+
+void launch_reduce(const SysBatch& sb, const double* partial, int64_t n_tiles, int64_t t0, int64_t nt, SysState* st,
+                   int mode, double rtol, double div_factor, int max_sweeps, hipStream_t s) {
+  if (sb.n <= 0) return;
+  hipLaunchKernelGGL(k_reduce, dim3((unsigned)sb.n), dim3(256), 0, s, sb, partial, n_tiles, t0, nt, st, mode,
+                     rtol * rtol, div_factor * div_factor, max_sweeps);
+}
+
+void launch_resid_stored(int storage, const DevPattern& p, const void* offd, const void* diag, const double* x,
+                         const double* b, double* r, const SysBatch& sb, double* partial, hipStream_t s) {
+  if (sb.n <= 0) return;
+  const int spw = 4 < sb.n ? 4 : sb.n;
+  dim3 grid = tile_grid(p.n_tiles, ng_of(sb, spw));
+  FNLH_DISPATCH_STORE(storage, {
+    hipLaunchKernelGGL((k_resid_stored<TB>), grid, dim3(64 * spw), 0, s, p, (const TB*)offd, (const TB*)diag, x, b,
+                       r, sb, partial, spw);
+  });
+}
+
+void launch_resid_mfree(const DevPattern& p, const DevFlow& f, const double* x, const double* b, double* r,
+                        const SysBatch& sb, double* partial, hipStream_t s) {
+  if (sb.n <= 0) return;
+  const int spw = 4 < sb.n ? 4 : sb.n;
+  dim3 grid = tile_grid(p.n_tiles, ng_of(sb, spw));
+  hipLaunchKernelGGL(k_resid_mfree, grid, dim3(64 * spw), 0, s, p, f, x, b, r, sb, partial, spw);
+}
+
+void launch_to_internal(const DevPattern& p, const int32_t* iperm, const double* user, double* internal, int width,
+                        hipStream_t s) {
+  const int64_t n = p.NP * width;
+  hipLaunchKernelGGL(k_to_internal, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p.NP, iperm, user, internal,
+                     width);
+}
+void launch_to_user(const DevPattern& p, const int32_t* iperm, const double* internal, double* user, int width,
+                    hipStream_t s) {
+  const int64_t n = p.NP * width;
+  hipLaunchKernelGGL(k_to_user, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p.NP, iperm, internal, user,
+                     width);
+}
+void launch_to_f32(const DevPattern& p, const double* r64, float* rhs32, float* d32, const SysBatch& sb,
+                   const SysState* outer, hipStream_t s) {
+  if (sb.n <= 0) return;
+  dim3 grid((unsigned)((p.NP * 12 + 255) / 256), (unsigned)sb.n);
+  hipLaunchKernelGGL(k_to_f32, grid, dim3(256), 0, s, p.NP, r64, rhs32, d32, sb, outer);
+}
+void launch_add_f32(const DevPattern& p, double* x64, const float* d32, const SysBatch& sb, const SysState* outer,
+                    hipStream_t s) {
+  if (sb.n <= 0) return;
+  dim3 grid((unsigned)((p.NP * 12 + 255) / 256), (unsigned)sb.n);
+  hipLaunchKernelGGL(k_add_f32, grid, dim3(256), 0, s, p.NP, x64, d32, sb, outer);
+}
+void launch_inner_init(const SysBatch& sb, const SysState* outer, SysState* inner, int max_sweeps, hipStream_t s) {
+  hipLaunchKernelGGL(k_inner_init, dim3(1), dim3(64), 0, s, sb, outer, inner, max_sweeps);
+}
+void launch_outer_update(const SysBatch& sb, const SysState* inner, SysState* outer, hipStream_t s) {
+  hipLaunchKernelGGL(k_outer_update, dim3(1), dim3(64), 0, s, sb, inner, outer);
+}
+void launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+  const size_t n = bytes / 4;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (uint32_t*)p, n);
+}
+
+}  // namespace fnlh

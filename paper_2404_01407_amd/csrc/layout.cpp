@@ -1,0 +1,394 @@
+// Mesh ingest on the host: validation, ordering and the SELL-64 layout.
+//
+// The paper leaves the ILU(0) ordering unstated (section "Solution Update": L and U
+// take the pattern of A).  Here the ordering is a colouring (independent sets, taken in
+// ascending colour), which is what lets every cell of one colour be processed in
+// parallel on the GPU:
+//   AUTO       two colours when the cell graph is bipartite (every hex passage), else
+//              GREEDY;
+//   BIPARTITE  breadth-first two-colouring from the lowest uncoloured id (error if the
+//              graph has an odd cycle);
+//   GREEDY     first-fit colouring visiting cells in reverse Cuthill-McKee order;
+//   USER       the caller's colours (must be a proper colouring).
+// Internally cells are renumbered colour-major, and inside each colour by their reverse
+// Cuthill-McKee position, so the 64 rows of a tile are neighbours in the mesh and the
+// neighbour gathers of a tile touch a narrow window of the vectors.
+#include "layout.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <queue>
+#include <sstream>
+
+namespace fnlh {
+
+namespace {
+
+struct Csr {
+  std::vector<int64_t> ptr;
+  std::vector<int32_t> nbr;
+  std::vector<int64_t> eid;  // directed coupling id: 2e (a->b) or 2e+1 (b->a)
+};
+
+Csr adjacency(int64_t N, int64_t E, const int32_t* edges) {
+  Csr g;
+  g.ptr.assign(N + 1, 0);
+  for (int64_t e = 0; e < E; ++e) {
+    g.ptr[edges[2 * e] + 1]++;
+    g.ptr[edges[2 * e + 1] + 1]++;
+  }
+  for (int64_t i = 0; i < N; ++i) g.ptr[i + 1] += g.ptr[i];
+  g.nbr.resize(2 * E);
+  g.eid.resize(2 * E);
+  std::vector<int64_t> fill(g.ptr.begin(), g.ptr.end() - 1);
+  for (int64_t e = 0; e < E; ++e) {
+    int32_t a = edges[2 * e], b = edges[2 * e + 1];
+    g.nbr[fill[a]] = b;
+    g.eid[fill[a]++] = 2 * e;
+    g.nbr[fill[b]] = a;
+    g.eid[fill[b]++] = 2 * e + 1;
+  }
+  // neighbour lists sorted by neighbour id (deterministic regardless of edge order)
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t s = g.ptr[i], t = g.ptr[i + 1];
+    std::vector<std::pair<int32_t, int64_t>> v;
+    v.reserve(t - s);
+    for (int64_t p = s; p < t; ++p) v.emplace_back(g.nbr[p], g.eid[p]);
+    std::sort(v.begin(), v.end());
+    for (int64_t p = s; p < t; ++p) {
+      g.nbr[p] = v[p - s].first;
+      g.eid[p] = v[p - s].second;
+    }
+  }
+  return g;
+}
+
+// Reverse Cuthill-McKee over every connected component.  Each component starts from a
+// pseudo-peripheral cell (two BFS sweeps from its minimum-degree cell); neighbours are
+// visited by ascending degree, ties by id.
+std::vector<int32_t> rcm_order(int64_t N, const Csr& g) {
+  std::vector<int32_t> order;
+  order.reserve(N);
+  std::vector<char> seen(N, 0);
+  std::vector<int32_t> deg(N);
+  for (int64_t i = 0; i < N; ++i) deg[i] = (int32_t)(g.ptr[i + 1] - g.ptr[i]);
+  std::vector<int32_t> level(N, -1);
+  auto bfs_last = [&](int32_t s, std::vector<int32_t>& comp) {
+    comp.clear();
+    std::queue<int32_t> q;
+    q.push(s);
+    level[s] = 0;
+    comp.push_back(s);
+    int32_t last = s;
+    while (!q.empty()) {
+      int32_t i = q.front();
+      q.pop();
+      last = i;
+      for (int64_t p = g.ptr[i]; p < g.ptr[i + 1]; ++p) {
+        int32_t k = g.nbr[p];
+        if (level[k] < 0) {
+          level[k] = level[i] + 1;
+          q.push(k);
+          comp.push_back(k);
+        }
+      }
+    }
+    // farthest cell of minimum degree on the last level
+    int32_t best = last;
+    for (int32_t c : comp)
+      if (level[c] == level[last] && (deg[c] < deg[best] || (deg[c] == deg[best] && c < best))) best = c;
+    for (int32_t c : comp) level[c] = -1;
+    return best;
+  };
+  std::vector<int32_t> comp;
+  for (int64_t s0 = 0; s0 < N; ++s0) {
+    if (seen[s0]) continue;
+    // component of s0: find its min-degree cell
+    bfs_last((int32_t)s0, comp);
+    int32_t start = comp[0];
+    for (int32_t c : comp)
+      if (deg[c] < deg[start] || (deg[c] == deg[start] && c < start)) start = c;
+    start = bfs_last(start, comp);
+    start = bfs_last(start, comp);
+    // Cuthill-McKee from start
+    size_t head = order.size();
+    order.push_back(start);
+    seen[start] = 1;
+    std::vector<int32_t> nb;
+    while (head < order.size()) {
+      int32_t i = order[head++];
+      nb.clear();
+      for (int64_t p = g.ptr[i]; p < g.ptr[i + 1]; ++p)
+        if (!seen[g.nbr[p]]) nb.push_back(g.nbr[p]);
+      std::sort(nb.begin(), nb.end(), [&](int32_t x, int32_t y) {
+        return deg[x] < deg[y] || (deg[x] == deg[y] && x < y);
+      });
+      for (int32_t k : nb) {
+        seen[k] = 1;
+        order.push_back(k);
+      }
+    }
+  }
+  std::reverse(order.begin(), order.end());
+  return order;
+}
+
+bool bipartite_colour(int64_t N, const Csr& g, std::vector<int32_t>& col) {
+  col.assign(N, -1);
+  std::queue<int32_t> q;
+  for (int64_t s = 0; s < N; ++s) {
+    if (col[s] >= 0) continue;
+    col[s] = 0;
+    q.push((int32_t)s);
+    while (!q.empty()) {
+      int32_t i = q.front();
+      q.pop();
+      for (int64_t p = g.ptr[i]; p < g.ptr[i + 1]; ++p) {
+        int32_t k = g.nbr[p];
+        if (col[k] < 0) {
+          col[k] = 1 - col[i];
+          q.push(k);
+        } else if (col[k] == col[i]) {
+          return false;
+        }
+      }
+    }
+  }
+  return true;
+}
+
+void greedy_colour(int64_t N, const Csr& g, const std::vector<int32_t>& visit, std::vector<int32_t>& col) {
+  col.assign(N, -1);
+  std::vector<int32_t> mark;
+  for (int32_t i : visit) {
+    mark.assign(g.ptr[i + 1] - g.ptr[i] + 2, 0);
+    for (int64_t p = g.ptr[i]; p < g.ptr[i + 1]; ++p) {
+      int32_t c = col[g.nbr[p]];
+      if (c >= 0 && c < (int32_t)mark.size()) mark[c] = 1;
+    }
+    int32_t c = 0;
+    while (mark[c]) ++c;
+    col[i] = c;
+  }
+}
+
+}  // namespace
+
+int build_layout(const fnlh_mesh& m, const fnlh_options& o, Layout& L, std::string& err) {
+  std::ostringstream es;
+  const int64_t N = m.n_cells, E = m.n_edges, B = m.n_bfaces;
+  if (N <= 0 || E < 0 || B < 0 || m.n_zones < 1) {
+    err = "mesh: need n_cells > 0, n_edges >= 0, n_bfaces >= 0, n_zones >= 1";
+    return FNLH_E_ARG;
+  }
+  if (N >= (int64_t)1 << 30 || E >= (int64_t)1 << 29) {
+    err = "mesh: too large for 32-bit internal indices";
+    return FNLH_E_ARG;
+  }
+  if ((E > 0 && (!m.edges || !m.area)) || !m.volume || (B > 0 && (!m.bface_cell || !m.bface_area))) {
+    err = "mesh: null array";
+    return FNLH_E_ARG;
+  }
+  if (o.storage < FNLH_F64 || o.storage > FNLH_BF16 || o.outer < FNLH_OUTER_EXACT ||
+      o.outer > FNLH_OUTER_STORED || o.ordering < FNLH_ORDER_AUTO || o.ordering > FNLH_ORDER_USER ||
+      o.factor_slots < 0) {
+    err = "options: value out of range";
+    return FNLH_E_ARG;
+  }
+  if (o.ordering == FNLH_ORDER_USER && !o.user_colour) {
+    err = "options: ordering USER needs user_colour";
+    return FNLH_E_ARG;
+  }
+  for (int64_t e = 0; e < E; ++e) {
+    int64_t a = m.edges[2 * e], b = m.edges[2 * e + 1];
+    if (a < 0 || a >= N || b < 0 || b >= N) {
+      es << "mesh: edge " << e << " has a cell id out of range";
+      err = es.str();
+      return FNLH_E_MESH;
+    }
+    if (a == b) {
+      es << "mesh: edge " << e << " is a self loop";
+      err = es.str();
+      return FNLH_E_MESH;
+    }
+    for (int d = 0; d < 3; ++d)
+      if (!std::isfinite(m.area[3 * e + d])) {
+        es << "mesh: edge " << e << " has a non-finite area";
+        err = es.str();
+        return FNLH_E_MESH;
+      }
+  }
+  for (int64_t i = 0; i < N; ++i) {
+    if (!(m.volume[i] > 0.0) || !std::isfinite(m.volume[i])) {
+      es << "mesh: volume of cell " << i << " is not positive";
+      err = es.str();
+      return FNLH_E_MESH;
+    }
+    if (m.zone && (m.zone[i] < 0 || m.zone[i] >= m.n_zones)) {
+      es << "mesh: zone of cell " << i << " out of range";
+      err = es.str();
+      return FNLH_E_MESH;
+    }
+  }
+  for (int64_t f = 0; f < B; ++f) {
+    if (m.bface_cell[f] < 0 || m.bface_cell[f] >= N) {
+      es << "mesh: boundary face " << f << " has a cell id out of range";
+      err = es.str();
+      return FNLH_E_MESH;
+    }
+  }
+  Csr g = adjacency(N, E, m.edges);
+  for (int64_t i = 0; i < N; ++i)
+    for (int64_t p = g.ptr[i] + 1; p < g.ptr[i + 1]; ++p)
+      if (g.nbr[p] == g.nbr[p - 1]) {
+        es << "mesh: duplicate edge between cells " << i << " and " << g.nbr[p];
+        err = es.str();
+        return FNLH_E_MESH;
+      }
+
+  L.N = N;
+  L.E = E;
+  L.B = B;
+  L.n_zones = m.n_zones;
+  std::vector<int32_t> rcm = rcm_order(N, g);
+  std::vector<int32_t>& col = L.colour_user;
+  if (o.ordering == FNLH_ORDER_USER) {
+    col.assign(o.user_colour, o.user_colour + N);
+    for (int64_t i = 0; i < N; ++i)
+      if (col[i] < 0) {
+        err = "ordering: negative user colour";
+        return FNLH_E_MESH;
+      }
+    for (int64_t e = 0; e < E; ++e)
+      if (col[m.edges[2 * e]] == col[m.edges[2 * e + 1]]) {
+        es << "ordering: user colouring is not proper (edge " << e << ")";
+        err = es.str();
+        return FNLH_E_MESH;
+      }
+    // compact colour values, keeping their order
+    std::vector<int32_t> vals(col);
+    std::sort(vals.begin(), vals.end());
+    vals.erase(std::unique(vals.begin(), vals.end()), vals.end());
+    for (auto& c : col) c = (int32_t)(std::lower_bound(vals.begin(), vals.end(), c) - vals.begin());
+    L.bipartite = vals.size() == 2;
+  } else {
+    bool bip = false;
+    if (o.ordering == FNLH_ORDER_AUTO || o.ordering == FNLH_ORDER_BIPARTITE) {
+      bip = bipartite_colour(N, g, col);
+      if (!bip && o.ordering == FNLH_ORDER_BIPARTITE) {
+        err = "ordering: cell graph is not bipartite";
+        return FNLH_E_MESH;
+      }
+    }
+    if (!bip) greedy_colour(N, g, rcm, col);
+    int32_t mx = 0;
+    for (auto c : col) mx = std::max(mx, c);
+    L.bipartite = bip || mx == 1;
+  }
+  int32_t ncol = 0;
+  for (auto c : col) ncol = std::max(ncol, c + 1);
+  L.n_colours = ncol;
+
+  // colour-major, RCM position inside each colour; every colour is padded to a
+  // multiple of 64 rows so tile t is rows [64t, 64t+64) and never straddles a colour
+  std::vector<int32_t> rpos(N);
+  for (int64_t p = 0; p < N; ++p) rpos[rcm[p]] = (int32_t)p;
+  std::vector<int32_t> byc(N);
+  std::iota(byc.begin(), byc.end(), 0);
+  std::stable_sort(byc.begin(), byc.end(), [&](int32_t x, int32_t y) {
+    return col[x] < col[y] || (col[x] == col[y] && rpos[x] < rpos[y]);
+  });
+  std::vector<int64_t> count(ncol, 0);
+  for (auto c : col) count[c]++;
+  L.cstart.assign(ncol + 1, 0);
+  L.ccount = count;
+  for (int32_t c = 0; c < ncol; ++c) L.cstart[c + 1] = L.cstart[c] + (count[c] + kTile - 1) / kTile * kTile;
+  const int64_t NP = L.cstart[ncol];
+  L.NP = NP;
+  L.perm.assign(N, -1);
+  L.iperm.assign(NP, -1);
+  {
+    int64_t p = 0;
+    for (int32_t c = 0; c < ncol; ++c) {
+      for (int64_t k = 0; k < count[c]; ++k, ++p) {
+        const int32_t u = byc[p];
+        const int64_t row = L.cstart[c] + k;
+        L.perm[u] = (int32_t)row;
+        L.iperm[row] = u;
+      }
+    }
+  }
+
+  // tiles
+  L.n_tiles = NP / kTile;
+  L.ctile.assign(ncol + 1, 0);
+  for (int32_t c = 0; c <= ncol; ++c) L.ctile[c] = L.cstart[c] / kTile;
+  L.tile_nrows.assign(L.n_tiles, 0);
+  L.tile_width.assign(L.n_tiles, 0);
+  L.tile_slot0.assign(L.n_tiles, 0);
+  int64_t slot = 0;
+  for (int64_t t = 0; t < L.n_tiles; ++t) {
+    int32_t nr = 0, w = 0;
+    for (int32_t l = 0; l < kTile; ++l) {
+      const int32_t u = L.iperm[t * kTile + l];
+      if (u < 0) continue;
+      ++nr;
+      w = std::max<int32_t>(w, (int32_t)(g.ptr[u + 1] - g.ptr[u]));
+    }
+    L.tile_nrows[t] = nr;
+    L.tile_width[t] = w;
+    L.tile_slot0[t] = slot;
+    slot += w;
+  }
+  L.n_slots = slot;
+  if (slot * kTile >= ((int64_t)1 << 31)) {
+    err = "mesh: too many couplings for 32-bit entry indices";
+    return FNLH_E_ARG;
+  }
+  const int64_t nent = slot * kTile;
+  L.ent_nbr.assign(nent, 0);
+  L.ent_edge.assign(nent, 0);
+  L.ent_rev.assign(nent, -1);
+  L.edge_ent.assign(2 * E, -1);
+  for (int64_t t = 0; t < L.n_tiles; ++t) {
+    for (int32_t l = 0; l < kTile; ++l) {
+      const int64_t row = t * kTile + l;
+      const int32_t u = L.iperm[row];
+      const int64_t deg = u >= 0 ? g.ptr[u + 1] - g.ptr[u] : 0;
+      for (int32_t j = 0; j < L.tile_width[t]; ++j) {
+        const int64_t f = (L.tile_slot0[t] + j) * kTile + l;
+        if (j < deg) {
+          const int64_t p = g.ptr[u] + j;
+          const int64_t d = g.eid[p];
+          L.ent_nbr[f] = L.perm[g.nbr[p]];
+          const int64_t e = d >> 1;
+          L.ent_edge[f] = (d & 1) ? -(int32_t)(e + 1) : (int32_t)(e + 1);
+          L.edge_ent[d] = f;
+        } else {
+          L.ent_nbr[f] = (int32_t)row;  // zero block: contributes nothing
+        }
+      }
+    }
+  }
+  for (int64_t d = 0; d < 2 * E; ++d) L.ent_rev[L.edge_ent[d]] = (int32_t)L.edge_ent[d ^ 1];
+
+  L.vol.assign(NP, 1.0);
+  L.zone.assign(NP, 0);
+  for (int64_t u = 0; u < N; ++u) {
+    L.vol[L.perm[u]] = m.volume[u];
+    L.zone[L.perm[u]] = m.zone ? m.zone[u] : 0;
+  }
+  L.bf_ptr.assign(NP + 1, 0);
+  for (int64_t f = 0; f < B; ++f) L.bf_ptr[L.perm[m.bface_cell[f]] + 1]++;
+  for (int64_t i = 0; i < NP; ++i) L.bf_ptr[i + 1] += L.bf_ptr[i];
+  L.bf_idx.resize(B);
+  {
+    std::vector<int32_t> fill(L.bf_ptr.begin(), L.bf_ptr.end() - 1);
+    for (int64_t f = 0; f < B; ++f) L.bf_idx[fill[L.perm[m.bface_cell[f]]]++] = (int32_t)f;
+  }
+  return FNLH_OK;
+}
+
+}  // namespace fnlh

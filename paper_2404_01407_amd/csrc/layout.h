@@ -1,0 +1,52 @@
+// Host-side mesh ingest: validation, colour ordering, colour-major internal numbering
+// with locality ordering inside each colour, and the sliced-ELL (SELL-64) layout the
+// device kernels stream.  Pure C++ (no HIP): unit-testable without a GPU.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fnlh.h"
+
+namespace fnlh {
+
+constexpr int kTile = 64;  // rows per tile == wavefront width on CDNA
+
+struct Layout {
+  int64_t N = 0, E = 0, B = 0;
+  int32_t n_zones = 1;
+  int32_t n_colours = 0;
+  bool bipartite = false;
+  std::vector<int32_t> colour_user;  // [N] colour of each user cell
+  int64_t NP = 0;                    // internal rows incl. padding (each colour padded to 64)
+  std::vector<int32_t> perm;         // [N] user id -> internal row
+  std::vector<int32_t> iperm;        // [NP] internal row -> user id, -1 for padding rows
+  std::vector<int64_t> cstart;       // [n_colours+1] internal row range of each colour (64-aligned)
+  std::vector<int64_t> ccount;       // [n_colours] cells of each colour
+  std::vector<int64_t> ctile;        // [n_colours+1] tile range of each colour
+
+  // tile t = internal rows [64t, 64t+64), never straddling a colour
+  int64_t n_tiles = 0;
+  int64_t n_slots = 0;               // sum of tile widths
+  std::vector<int32_t> tile_nrows;   // valid (non-padding) rows, a prefix of the tile
+  std::vector<int32_t> tile_width;   // max degree in the tile
+  std::vector<int64_t> tile_slot0;   // first slot
+
+  // entries, flat index (slot * 64 + lane)
+  std::vector<int32_t> ent_nbr;      // internal neighbour row (padding: the row itself)
+  std::vector<int32_t> ent_edge;     // +(e+1) if the row is edge e's first cell, -(e+1) if second, 0 pad
+  std::vector<int32_t> ent_rev;      // flat index of the transposed coupling, -1 pad
+  std::vector<int64_t> edge_ent;     // [2E] flat entry of coupling (a->b) at 2e, (b->a) at 2e+1
+
+  // per internal row (padding rows: volume 1, zone 0, no faces)
+  std::vector<double> vol;           // [NP]
+  std::vector<int32_t> zone;         // [NP]
+  std::vector<int32_t> bf_ptr;       // [NP+1] boundary faces of each internal row
+  std::vector<int32_t> bf_idx;       // [B]  boundary face ids
+};
+
+// Validate and build.  Returns FNLH_OK or a negative code with a message in err.
+int build_layout(const fnlh_mesh& m, const fnlh_options& o, Layout& L, std::string& err);
+
+}  // namespace fnlh

@@ -1,0 +1,260 @@
+"""Python binding of libfnlh (include/fnlh.h): argument marshalling only.
+
+Every step of the solve runs in the HIP library; this module converts numpy arrays
+(host mesh data) and torch CUDA tensors (device vectors, HIP streams) into the plain
+pointers of the C ABI.  There is no fallback: if the built library is missing the
+import of this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libfnlh.so")
+
+# status codes (fnlh.h)
+OK, NOT_CONVERGED, DIVERGED, FELL_BACK = 0, 1, 2, 3
+E_ARG, E_MESH, E_SINGULAR, E_OOM, E_HIP, E_ORDER = -1, -2, -3, -4, -5, -6
+STORAGE = {"f64": 0, "f32": 1, "bf16": 2}
+OUTER = {"exact": 0, "stored": 1}
+ORDERING = {"auto": 0, "greedy": 1, "bipartite": 2, "user": 3}
+KIND = {"dilu": 0, "sgs": 1, "jacobi": 2, "learned": 3}
+SCHEME = {"implicit": 0, "explicit": 1}
+
+
+class FnlhError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fnlh error {code}: {msg}")
+        self.code = code
+
+
+class Mesh(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("n_edges", C.c_int64), ("n_bfaces", C.c_int64),
+                ("n_zones", C.c_int32), ("pad_", C.c_int32),
+                ("edges", C.c_void_p), ("area", C.c_void_p), ("volume", C.c_void_p),
+                ("zone", C.c_void_p), ("bface_cell", C.c_void_p), ("bface_area", C.c_void_p)]
+
+
+class Options(C.Structure):
+    _fields_ = [("storage", C.c_int32), ("outer", C.c_int32), ("ordering", C.c_int32),
+                ("factor_slots", C.c_int32), ("user_colour", C.c_void_p), ("device", C.c_int32),
+                ("pad_", C.c_int32)]
+
+
+class RelaxOpts(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("max_sweeps", C.c_int32), ("rtol", C.c_double),
+                ("check_every", C.c_int32), ("inner_sweeps", C.c_int32), ("inner_rtol", C.c_double),
+                ("div_factor", C.c_double), ("use_graph", C.c_int32), ("pad_", C.c_int32)]
+
+
+class Report(C.Structure):
+    _fields_ = [("sweeps", C.c_int32), ("outer", C.c_int32), ("status", C.c_int32),
+                ("fallbacks", C.c_int32), ("rel_res", C.c_double), ("res0", C.c_double),
+                ("t_factor_ms", C.c_double), ("t_sweep_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libfnlh.so not built ({LIB_PATH}); run __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    P, I32, I64, D, V = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_void_p
+    sig = {
+        "fnlh_create": (I32, [C.POINTER(P), C.POINTER(Mesh), C.POINTER(Options)]),
+        "fnlh_destroy": (I32, [P]),
+        "fnlh_assemble_jacobian": (I32, [P, V, V, D, D, I32, V]),
+        "fnlh_set_blocks": (I32, [P, V, V, V]),
+        "fnlh_get_blocks": (I32, [P, V, V, V]),
+        "fnlh_set_harmonics": (I32, [P, I32, V, V]),
+        "fnlh_residual": (I32, [P, I32, V, V, V, C.POINTER(D), V]),
+        "fnlh_relax": (I32, [P, I32, V, V, V, C.POINTER(RelaxOpts), V, V]),
+        "fnlh_get_ordering": (I32, [P, V, C.POINTER(I32)]),
+        "fnlh_memory": (I32, [P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+        "fnlh_last_error": (C.c_char_p, [P]),
+        "fnlh_order_mesh": (I32, [C.POINTER(Mesh), C.POINTER(Options), V, V, C.POINTER(I32)]),
+        "fnlh_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()  # torch tensor
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _dev_tensor(t, shape, dtype_name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"expected a CUDA (HIP) torch tensor for {dtype_name}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{dtype_name}: shape {tuple(t.shape)} != {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{dtype_name}: tensor must be contiguous")
+    return t
+
+
+class _MeshArrays:
+    """Keeps contiguous host copies alive for the duration of a call."""
+
+    def __init__(self, mesh, n_zones=None):
+        self.edges = np.ascontiguousarray(mesh.edges, dtype=np.int32)
+        self.area = np.ascontiguousarray(mesh.area, dtype=np.float64)
+        self.volume = np.ascontiguousarray(mesh.volume, dtype=np.float64)
+        z = getattr(mesh, "zone", None)
+        self.zone = None if z is None else np.ascontiguousarray(z, dtype=np.int32)
+        self.bface_cell = np.ascontiguousarray(mesh.bface_cell, dtype=np.int32)
+        self.bface_area = np.ascontiguousarray(mesh.bface_area, dtype=np.float64)
+        nz = n_zones if n_zones is not None else getattr(mesh, "n_zones", 1)
+        self.s = Mesh(self.volume.shape[0], self.edges.shape[0], self.bface_cell.shape[0], int(nz), 0,
+                      _ptr(self.edges), _ptr(self.area), _ptr(self.volume), _ptr(self.zone),
+                      _ptr(self.bface_cell), _ptr(self.bface_area))
+
+
+def _options(storage="f64", outer="exact", ordering="auto", factor_slots=0, user_colour=None, device=0):
+    uc = None if user_colour is None else np.ascontiguousarray(user_colour, dtype=np.int32)
+    o = Options(STORAGE[storage], OUTER[outer], ORDERING[ordering], int(factor_slots), _ptr(uc), int(device), 0)
+    return o, uc
+
+
+def order_mesh(mesh, ordering="auto", user_colour=None):
+    """Host-only: the colouring and internal permutation fnlh_create would build."""
+    m = _MeshArrays(mesh)
+    o, uc = _options(ordering=ordering, user_colour=user_colour)
+    n = m.s.n_cells
+    colour = np.empty(n, np.int32)
+    perm = np.empty(n, np.int32)
+    nc = C.c_int32(0)
+    rc = LIB.fnlh_order_mesh(C.byref(m.s), C.byref(o), _ptr(colour), _ptr(perm), C.byref(nc))
+    if rc != OK:
+        raise FnlhError(rc, LIB.fnlh_last_error(None).decode())
+    return colour, perm, nc.value
+
+
+class Context:
+    """One mesh, one stored Jacobian, any number of shifted systems."""
+
+    def __init__(self, mesh, storage="f64", outer="exact", ordering="auto", factor_slots=0,
+                 user_colour=None, device=0):
+        self.mesh_arrays = _MeshArrays(mesh)
+        self.n = int(self.mesh_arrays.s.n_cells)
+        self.E = int(self.mesh_arrays.s.n_edges)
+        self.B = int(self.mesh_arrays.s.n_bfaces)
+        self.n_zones = int(self.mesh_arrays.s.n_zones)
+        self.storage = storage
+        o, uc = _options(storage, outer, ordering, factor_slots, user_colour, device)
+        h = C.c_void_p()
+        rc = LIB.fnlh_create(C.byref(h), C.byref(self.mesh_arrays.s), C.byref(o))
+        if rc != OK:
+            raise FnlhError(rc, LIB.fnlh_last_error(None).decode())
+        self.h = h
+        self.n_sys = 0
+
+    def _check(self, rc, allow_positive=False):
+        if rc < 0 or (rc > 0 and not allow_positive):
+            raise FnlhError(rc, LIB.fnlh_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            LIB.fnlh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def assemble_jacobian(self, state, bstate=None, eps=0.6, sigma=50.0, scheme="implicit", stream=None):
+        _dev_tensor(state, (self.n, 6), "state")
+        if bstate is not None:
+            _dev_tensor(bstate, (self.B, 6), "bstate")
+        self._check(LIB.fnlh_assemble_jacobian(self.h, _ptr(state), _ptr(bstate), float(eps), float(sigma),
+                                               SCHEME[scheme], _stream(stream)))
+
+    def set_blocks(self, diag, offd, stream=None):
+        _dev_tensor(diag, (self.n, 6, 6), "diag")
+        _dev_tensor(offd, (self.E, 2, 6, 6), "offd")
+        self._check(LIB.fnlh_set_blocks(self.h, _ptr(diag), _ptr(offd), _stream(stream)))
+
+    def get_blocks(self, stream=None):
+        import torch
+        diag = torch.empty((self.n, 6, 6), dtype=torch.float64, device="cuda")
+        offd = torch.empty((self.E, 2, 6, 6), dtype=torch.float64, device="cuda")
+        self._check(LIB.fnlh_get_blocks(self.h, _ptr(diag), _ptr(offd), _stream(stream)))
+        return diag, offd
+
+    def set_harmonics(self, omega, stream=None):
+        om = np.ascontiguousarray(omega, dtype=np.float64).reshape(-1, self.n_zones)
+        self._check(LIB.fnlh_set_harmonics(self.h, om.shape[0], _ptr(om), _stream(stream)))
+        self.n_sys = om.shape[0]
+
+    def residual(self, sys, x, b, r=None, stream=None):
+        for t, nm in ((x, "x"), (b, "b")):
+            _dev_tensor(t, (self.n, 6), nm)
+        if r is not None:
+            _dev_tensor(r, (self.n, 6), "r")
+        n2 = C.c_double(0.0)
+        self._check(LIB.fnlh_residual(self.h, int(sys), _ptr(x), _ptr(b), _ptr(r), C.byref(n2), _stream(stream)))
+        return n2.value
+
+    def relax(self, systems, xs, bs, kind="dilu", max_sweeps=500, rtol=1e-8, check_every=8,
+              inner_sweeps=0, inner_rtol=0.0, div_factor=0.0, use_graph=False, stream=None):
+        """Solve (K + i omega_s V) x = b for each s in ``systems``; xs (in: x0, out: x) and
+        bs are complex128 CUDA tensors [N, 6].  Returns (status, list of report dicts)."""
+        n = len(systems)
+        for t in list(xs) + list(bs):
+            _dev_tensor(t, (self.n, 6), "vector")
+        sysarr = np.ascontiguousarray(systems, dtype=np.int32)
+        xp = (C.c_void_p * n)(*[_ptr(t) for t in xs])
+        bp = (C.c_void_p * n)(*[_ptr(t) for t in bs])
+        o = RelaxOpts(KIND[kind], int(max_sweeps), float(rtol), int(check_every), int(inner_sweeps),
+                      float(inner_rtol), float(div_factor), int(bool(use_graph)), 0)
+        rep = (Report * n)()
+        rc = LIB.fnlh_relax(self.h, n, _ptr(sysarr), C.cast(xp, C.c_void_p), C.cast(bp, C.c_void_p),
+                            C.byref(o), C.cast(rep, C.c_void_p), _stream(stream))
+        self._check(rc, allow_positive=True)
+        return rc, [r.as_dict() for r in rep]
+
+    def ordering(self):
+        colour = np.empty(self.n, np.int32)
+        nc = C.c_int32(0)
+        self._check(LIB.fnlh_get_ordering(self.h, _ptr(colour), C.byref(nc)))
+        return colour, nc.value
+
+    def memory(self):
+        a, b, c = C.c_size_t(0), C.c_size_t(0), C.c_size_t(0)
+        self._check(LIB.fnlh_memory(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return {"matrix_bytes": a.value, "factor_bytes": b.value, "vector_bytes": c.value}
+
+
+def version():
+    return LIB.fnlh_version().decode()

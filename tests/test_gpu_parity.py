@@ -1,0 +1,307 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on the same
+seeded inputs.
+
+Tolerances (FP64 mode): the device sums in a different order than NumPy (fused
+two-colour pass, Gauss-Jordan instead of LAPACK inverses), so iterates differ by
+rounding only; the iteration is a contraction (rho ~ 0.7), so the difference after m
+sweeps stays at a small multiple of machine epsilon times the iterate.  1e-11 relative
+leaves three orders of margin over the observed ~1e-14.  Converged solutions are held
+to the spec bar: relative residual <= 1e-10 and agreement with a dense direct
+solve to 1e-9."""
+import numpy as np
+import pytest
+
+from oracle import assemble, ordering, precision, solve
+from paper_2404_01407_amd import synth
+
+from gpu_helpers import blocks_user_layout, case, relerr, rounded, to_dev
+
+pytestmark = pytest.mark.gpu
+
+ITER_TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2404_01407_amd import fnlh
+    return fnlh
+
+
+def _ctx(F, m, Q, storage="f64", outer="exact", ordering_="auto", user_colour=None, sigma=50.0, scheme="implicit",
+         factor_slots=0):
+    c = F.Context(m, storage=storage, outer=outer, ordering=ordering_, user_colour=user_colour,
+                  factor_slots=factor_slots)
+    c.assemble_jacobian(to_dev(Q), eps=0.6, sigma=sigma, scheme=scheme)
+    return c
+
+
+def _solve(c, systems, bs, x0s=None, **kw):
+    import torch
+    xs = [to_dev(np.zeros((c.n, 6), complex) if x0s is None else x0s[j]) for j in range(len(systems))]
+    bd = [to_dev(b.astype(complex)) for b in bs]
+    st, rep = c.relax(systems, xs, bd, **kw)
+    torch.cuda.synchronize()
+    return st, rep, [x.cpu().numpy() for x in xs]
+
+
+def test_assembly_matches_oracle(F):
+    m, Q, K = case()
+    for storage in ("f64", "f32", "bf16"):
+        c = _ctx(F, m, Q, storage=storage)
+        d, o = c.get_blocks()
+        d, o = d.cpu().numpy(), o.cpu().numpy()
+        Kr = rounded(K, storage)
+        dref, oref = blocks_user_layout(Kr)
+        if storage == "f64":
+            scale = np.abs(dref).max()
+            assert np.abs(d - dref).max() <= 1e-13 * scale
+            assert np.abs(o - oref).max() <= 1e-13 * scale
+        else:
+            # both sides round the FP64 entry to nearest-even; FP64 entries that differ
+            # in the last bits may straddle a tie, so allow one unit in the last place
+            ulp = 2.0 ** -23 if storage == "f32" else 2.0 ** -7
+            for got, ref in ((d, dref), (o, oref)):
+                tol = ulp * np.abs(ref) + 1e-300
+                assert np.all(np.abs(got - ref) <= tol)
+                assert np.mean(got == ref) > 0.999
+        c.close()
+
+
+@pytest.mark.parametrize("kind", ["dilu", "sgs", "jacobi"])
+def test_iterates_cfg1(F, kind):
+    m, Q, K = case()
+    c = _ctx(F, m, Q)
+    om = synth.omegas_single_zone(1)
+    c.set_harmonics(om)
+    col, nc = c.ordering()
+    assert nc == 2
+    bs = [synth.rhs(m.n_cells, 0, real=True), synth.rhs(m.n_cells, 1)]
+    st, rep, xs = _solve(c, [0, 1], bs, kind=kind, max_sweeps=50, rtol=0.0)
+    for s in range(2):
+        x_or, info = solve.richardson(K, m.volume, m.zone, om[s], bs[s], col, kind.upper(), rtol=0.0, max_sweeps=50)
+        assert rep[s]["sweeps"] == 50
+        assert relerr(xs[s], x_or) <= ITER_TOL, (kind, s, relerr(xs[s], x_or))
+        assert abs(rep[s]["rel_res"] - info.rel_res) <= 1e-9 * info.rel_res + 1e-15
+    c.close()
+
+
+def test_converged_vs_dense_cfg1(F):
+    m, Q, K = case()
+    c = _ctx(F, m, Q)
+    om = synth.omegas_single_zone(1)
+    c.set_harmonics(om)
+    bs = [synth.rhs(m.n_cells, 0, real=True), synth.rhs(m.n_cells, 1)]
+    st, rep, xs = _solve(c, [0, 1], bs, kind="dilu", max_sweeps=1000, rtol=1e-12)
+    assert st == 0
+    for s in range(2):
+        xd = solve.dense_solve(K, m.volume, m.zone, om[s], bs[s])
+        assert rep[s]["rel_res"] <= 1e-10
+        assert relerr(xs[s], xd) <= 1e-9
+        r = bs[s] - solve.apply(K, solve.system_diag(K, m.volume, m.zone, om[s]), xs[s])
+        assert np.linalg.norm(r) / np.linalg.norm(bs[s]) <= 1e-10
+    assert np.all(xs[0].imag == 0.0)  # mean system stays real
+    c.close()
+
+
+def test_omega_zero_and_conjugate_on_device(F):
+    m, Q, K = case()
+    c = _ctx(F, m, Q)
+    c.set_harmonics(np.array([[0.0], [18.0], [-18.0]]))
+    b = synth.rhs(m.n_cells, 4)
+    st, rep, xs = _solve(c, [0, 0, 0, 1, 2], [b, b.real, b.imag, b, np.conj(b)], kind="dilu", max_sweeps=30,
+                         rtol=0.0)
+    # omega = 0: complex RHS splits into two real mean solves
+    assert relerr(xs[0], xs[1] + 1j * xs[2]) <= 1e-13
+    # -omega with the conjugate RHS gives the conjugate iterate
+    assert relerr(np.conj(xs[4]), xs[3]) <= 1e-13
+    c.close()
+
+
+def test_ragged_tiles_and_zero_rhs(F):
+    m, Q, K = case(shape=(7, 5, 3), seed=3)  # 105 cells: ragged last tile of each colour
+    c = _ctx(F, m, Q)
+    om = np.array([[0.0], [25.0]])
+    c.set_harmonics(om)
+    col, nc = c.ordering()
+    b1 = synth.rhs(m.n_cells, 1)
+    st, rep, xs = _solve(c, [1, 1], [b1, np.zeros_like(b1)], kind="dilu", max_sweeps=40, rtol=0.0)
+    x_or, _ = solve.richardson(K, m.volume, m.zone, om[1], b1, col, "DILU", rtol=0.0, max_sweeps=40)
+    assert relerr(xs[0], x_or) <= ITER_TOL
+    assert rep[1]["sweeps"] == 0 and np.all(xs[1] == 0) and rep[1]["status"] == 0
+    # max_sweeps = 0 leaves x0 untouched
+    x0 = synth.rhs(m.n_cells, 7)
+    st, rep, xs = _solve(c, [1], [b1], x0s=[x0], kind="dilu", max_sweeps=0, rtol=1e-8)
+    assert np.array_equal(xs[0], x0) and rep[0]["sweeps"] == 0
+    c.close()
+
+
+def test_nonzero_initial_guess(F):
+    m, Q, K = case()
+    c = _ctx(F, m, Q)
+    om = synth.omegas_single_zone(1)
+    c.set_harmonics(om)
+    col, _ = c.ordering()
+    b = synth.rhs(m.n_cells, 1)
+    x0 = 0.1 * synth.rhs(m.n_cells, 9)
+    st, rep, xs = _solve(c, [1], [b], x0s=[x0], kind="dilu", max_sweeps=17, rtol=0.0)
+    x_or, _ = solve.richardson(K, m.volume, m.zone, om[1], b, col, "DILU", x0=x0, rtol=0.0, max_sweeps=17)
+    assert relerr(xs[0], x_or) <= ITER_TOL
+    c.close()
+
+
+def test_general_colouring_with_triangles(F):
+    m = synth.multi_row(6, 8, 4, n_blades=(36, 60, 48), seed=5)
+    Q = synth.flow_state(m, 5)
+    K = assemble.assemble(m, Q)
+    c = _ctx(F, m, Q)
+    col, nc = c.ordering()
+    assert nc >= 3 and ordering.is_valid(col, m.edges)
+    om = synth.omegas_multi_row(2, (36, 60, 48))
+    c.set_harmonics(om)
+    bs = [synth.rhs(m.n_cells, s, real=(s == 0)) for s in range(3)]
+    for kind in ("dilu", "sgs"):
+        st, rep, xs = _solve(c, [0, 1, 2], bs, kind=kind, max_sweeps=25, rtol=0.0)
+        for s in range(3):
+            x_or, _ = solve.richardson(K, m.volume, m.zone, om[s], bs[s], col, kind.upper(), rtol=0.0,
+                                       max_sweeps=25)
+            assert relerr(xs[s], x_or) <= ITER_TOL, (kind, s)
+    st, rep, xs = _solve(c, [0, 1, 2], bs, kind="dilu", max_sweeps=2000, rtol=1e-11)
+    for s in range(3):
+        xd = solve.dense_solve(K, m.volume, m.zone, om[s], bs[s])
+        assert relerr(xs[s], xd) <= 1e-9
+    c.close()
+
+
+def test_chain_natural_order_exact(F):
+    m = synth.chain(12)
+    Q = synth.flow_state(m, 3)
+    K = assemble.assemble(m, Q)
+    nat = ordering.natural_colouring(m.n_cells)
+    c = _ctx(F, m, Q, ordering_="user", user_colour=nat)
+    c.set_harmonics(np.array([[18.0]]))
+    b = synth.rhs(m.n_cells, 1)
+    st, rep, xs = _solve(c, [0], [b], kind="dilu", max_sweeps=1, rtol=0.0)
+    xd = solve.dense_solve(K, m.volume, m.zone, np.array([18.0]), b)
+    assert relerr(xs[0], xd) <= 1e-12
+    c.close()
+
+
+def test_set_blocks_random_matrix(F):
+    # raw blocks (any matrix on the pattern): a perturbed Jacobian with a random scaling
+    m, Q, K = case(shape=(9, 6, 5), seed=8)
+    rng = np.random.default_rng(0)
+    K2 = K.copy()
+    K2.offd = K.offd * (1.0 + 0.2 * rng.standard_normal(K.offd.shape))
+    K2.diag = K.diag * 1.2 + 0.01 * np.abs(K.diag).max() * rng.standard_normal(K.diag.shape)
+    import torch
+    c = F.Context(m)
+    d, o = blocks_user_layout(K2)
+    c.set_blocks(to_dev(d), to_dev(o))
+    om = np.array([[0.0], [30.0]])
+    c.set_harmonics(om)
+    col, _ = c.ordering()
+    bs = [synth.rhs(m.n_cells, 0, real=True), synth.rhs(m.n_cells, 1)]
+    st, rep, xs = _solve(c, [0, 1], bs, kind="dilu", max_sweeps=20, rtol=0.0)
+    for s in range(2):
+        x_or, _ = solve.richardson(K2, m.volume, m.zone, om[s], bs[s], col, "DILU", rtol=0.0, max_sweeps=20)
+        assert relerr(xs[s], x_or) <= ITER_TOL
+    c.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_reduced_precision_defect_correction(F, storage):
+    """FP32 / BF16 blocks, FP32 sweeps, FP64 outer residual from the FP64 state: the
+    iteration reaches the FP64 solution (rel. residual <= 1e-10 of the exact operator);
+    OUTER_STORED converges to the rounded system instead."""
+    m, Q, K = case()
+    om = synth.omegas_single_zone(1)
+    bs = [synth.rhs(m.n_cells, 0, real=True), synth.rhs(m.n_cells, 1)]
+    c = _ctx(F, m, Q, storage=storage, outer="exact")
+    c.set_harmonics(om)
+    st, rep, xs = _solve(c, [0, 1], bs, kind="dilu", max_sweeps=3000, rtol=1e-10)
+    assert st == 0
+    for s in range(2):
+        xd = solve.dense_solve(K, m.volume, m.zone, om[s], bs[s])
+        r = bs[s] - solve.apply(K, solve.system_diag(K, m.volume, m.zone, om[s]), xs[s])
+        assert np.linalg.norm(r) / np.linalg.norm(bs[s]) <= 1.5e-10
+        assert relerr(xs[s], xd) <= 1e-8
+        assert rep[s]["outer"] >= 1
+    c.close()
+    c = _ctx(F, m, Q, storage=storage, outer="stored")
+    c.set_harmonics(om)
+    st, rep, xs = _solve(c, [0, 1], bs, kind="dilu", max_sweeps=3000, rtol=1e-11)
+    Kr = rounded(K, storage)
+    for s in range(2):
+        xr = solve.dense_solve(Kr, m.volume, m.zone, om[s], bs[s])
+        xd = solve.dense_solve(K, m.volume, m.zone, om[s], bs[s])
+        assert relerr(xs[s], xr) <= 1e-8
+        # the rounded system's solution differs from the FP64 one by the storage error
+        assert relerr(xr, xd) > 1e-12
+    c.close()
+
+
+def test_deterministic_bitwise(F):
+    m, Q, K = case()
+    c = _ctx(F, m, Q)
+    c.set_harmonics(synth.omegas_single_zone(1))
+    bs = [synth.rhs(m.n_cells, 0, real=True), synth.rhs(m.n_cells, 1)]
+    _, r1, x1 = _solve(c, [0, 1], bs, kind="dilu", max_sweeps=200, rtol=1e-9)
+    _, r2, x2 = _solve(c, [0, 1], bs, kind="dilu", max_sweeps=200, rtol=1e-9)
+    for a, b in zip(x1, x2):
+        assert np.array_equal(a, b)
+    assert [r["sweeps"] for r in r1] == [r["sweeps"] for r in r2]
+    c.close()
+
+
+def test_residual_entry_point(F):
+    m, Q, K = case()
+    c = _ctx(F, m, Q)
+    om = synth.omegas_single_zone(1)
+    c.set_harmonics(om)
+    import torch
+    x = synth.rhs(m.n_cells, 3)
+    b = synth.rhs(m.n_cells, 4)
+    r = torch.empty((m.n_cells, 6), dtype=torch.complex128, device="cuda")
+    n2 = c.residual(1, to_dev(x), to_dev(b), r)
+    rr = b - solve.apply(K, solve.system_diag(K, m.volume, m.zone, om[1]), x)
+    assert relerr(r.cpu().numpy(), rr) <= 1e-13
+    assert abs(n2 - np.linalg.norm(rr) ** 2) <= 1e-12 * n2
+    c.close()
+
+
+def test_explicit_scheme_is_block_jacobi(F):
+    m, Q, K = case()
+    Ke = assemble.assemble(m, Q, scheme="explicit")
+    c = _ctx(F, m, Q, scheme="explicit")
+    om = np.array([[18.0]])
+    c.set_harmonics(om)
+    b = synth.rhs(m.n_cells, 1)
+    st, rep, xs = _solve(c, [0], [b], kind="jacobi", max_sweeps=1, rtol=0.0)
+    xd = solve.dense_solve(Ke, m.volume, m.zone, om[0], b)
+    assert relerr(xs[0], xd) <= 1e-13
+    c.close()
+
+
+def test_factor_slot_pool(F):
+    # fewer factor slots than systems: systems are factored batch by batch into the pool
+    m, Q, K = case()
+    c = _ctx(F, m, Q, factor_slots=1)
+    om = synth.omegas_single_zone(3)
+    c.set_harmonics(om)
+    col, _ = c.ordering()
+    bs = [synth.rhs(m.n_cells, s, real=(s == 0)) for s in range(4)]
+    st, rep, xs = _solve(c, [0, 1, 2, 3], bs, kind="dilu", max_sweeps=10, rtol=0.0)
+    for s in range(4):
+        x_or, _ = solve.richardson(K, m.volume, m.zone, om[s], bs[s], col, "DILU", rtol=0.0, max_sweeps=10)
+        assert relerr(xs[s], x_or) <= ITER_TOL
+    mem1 = c.memory()
+    c.close()
+    c = _ctx(F, m, Q, factor_slots=1)
+    c.set_harmonics(synth.omegas_single_zone(10))
+    _solve(c, list(range(11)), [synth.rhs(m.n_cells, s) for s in range(11)], kind="dilu", max_sweeps=2, rtol=0.0)
+    mem2 = c.memory()
+    assert mem2["matrix_bytes"] == mem1["matrix_bytes"]
+    assert mem2["factor_bytes"] == mem1["factor_bytes"]
+    c.close()

@@ -59,13 +59,18 @@ def test_assembly_matches_oracle(F):
             assert np.abs(d - dref).max() <= 1e-13 * scale
             assert np.abs(o - oref).max() <= 1e-13 * scale
         else:
-            # both sides round the FP64 entry to nearest-even; FP64 entries that differ
-            # in the last bits may straddle a tie, so allow one unit in the last place
+            # both sides round their FP64 entry to nearest-even.  The FP64 entries
+            # differ by summation-order rounding (~1e-16 of the block scale; entries that
+            # cancel to zero, such as the off-identity part of a closed cell's diagonal,
+            # are pure rounding noise), so allow one storage ulp plus that FP64 noise
             ulp = 2.0 ** -23 if storage == "f32" else 2.0 ** -7
             for got, ref in ((d, dref), (o, oref)):
-                tol = ulp * np.abs(ref) + 1e-300
+                scale = np.abs(ref).reshape(ref.shape[0], -1).max(axis=1)
+                scale = scale.reshape((-1,) + (1,) * (ref.ndim - 1))
+                tol = ulp * np.abs(ref) + 1e-13 * scale
                 assert np.all(np.abs(got - ref) <= tol)
-                assert np.mean(got == ref) > 0.999
+                big = np.abs(ref) > 1e-10 * scale
+                assert np.mean(got[big] == ref[big]) > 0.999
         c.close()
 
 

@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark of the shared-Jacobian, frequency-shifted block solve on one MI355X.
+
+Workload (the precision configuration: 200k-cell hex annular sector 80x50x50 as an edge
+list with 589,500 interior faces and 21,000 boundary faces, mean flow + 3 harmonics at
+omega = 0, 18, 36, 54 = 0..3 x BPF for 36 blades).  One step is the whole hot path on
+inputs already resident in HBM:
+    assemble K from the FP64 state (Rusanov first-order Jacobian, eps = 0.6, sigma = 50)
+    -> set the harmonics (factor slots invalidated) -> DILU factorisation of 4 systems
+    -> preconditioned Richardson of all 4 systems to a 1e-8 relative residual drop,
+       FP64 outer residual of the exact operator (defect correction for FP32/BF16 blocks).
+Mesh ingest (validation, colouring, numbering: host work done once per mesh) is
+outside the step and reported as ingest_ms.
+
+value = cell-unknown updates per second: one update is the 6 complex unknowns of one
+cell of one system advanced by one preconditioned sweep (x6 for scalar unknowns).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cell-unknown updates/s; time to 1e-8 residual drop, plain vs learned+batched"
+HBM_PEAK_GBS = 8000.0
+SHAPE = (80, 50, 50)
+N_HARM = 3
+RTOL = 1e-8
+
+
+def build_inputs():
+    import numpy as np
+    from paper_2404_01407_amd import synth
+    mesh = synth.passage_block(*SHAPE, 36, seed=2)
+    Q = synth.flow_state(mesh, 2)
+    om = synth.omegas_single_zone(N_HARM, 36)
+    bs = [synth.rhs(mesh.n_cells, s, real=(s == 0)) for s in range(N_HARM + 1)]
+    return mesh, Q, om, bs
+
+
+class Runner:
+    def __init__(self, mesh, Q, om, bs, storage):
+        import torch
+        from paper_2404_01407_amd import fnlh
+        t0 = time.perf_counter()
+        self.ctx = fnlh.Context(mesh, storage=storage, outer="exact")
+        self.ingest_ms = 1e3 * (time.perf_counter() - t0)
+        self.Qd = torch.from_numpy(Q).cuda()
+        self.bd = [torch.from_numpy(b).cuda() for b in bs]
+        self.xd = [torch.zeros_like(b) for b in self.bd]
+        self.om = om
+        self.S = len(bs)
+        self.N = mesh.n_cells
+
+    def step(self):
+        for x in self.xd:
+            x.zero_()
+        self.ctx.assemble_jacobian(self.Qd, eps=0.6, sigma=50.0)
+        self.ctx.set_harmonics(self.om)
+        st, rep = self.ctx.relax(list(range(self.S)), self.xd, self.bd, kind="dilu", max_sweeps=4000, rtol=RTOL,
+                                 check_every=8)
+        if st != 0:
+            raise RuntimeError(f"solve did not converge: status {st}, reports {rep}")
+        return rep
+
+    def timed(self, steps, warmup, stats=False):
+        import torch
+        for _ in range(warmup):
+            self.step()
+        if stats:
+            self.ctx.stats_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = []
+        for _ in range(steps):
+            reps.append(self.step())
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = self.ctx.stats() if stats else None
+        if stats:
+            self.ctx.stats_enable(False)
+        updates = sum(self.N * r["sweeps"] for rep in reps for r in rep)
+        return {"seconds": dt, "ms_per_step": 1e3 * dt / steps, "updates_per_s": updates / dt,
+                "sweeps": [r["sweeps"] for r in reps[-1]], "outer": [r["outer"] for r in reps[-1]],
+                "rel_res": [r["rel_res"] for r in reps[-1]], "stats": st}
+
+
+def cpu_baseline(mesh, Q, om, bs, colour, gpu_sweeps):
+    """The oracle as it stands, on one host core, on a bounded sample of the same
+    workload: assembly of K, DILU factorisation of one harmonic system and two sweeps,
+    timed separately; the step time is extrapolated to 4 systems x the GPU's sweep
+    counts (assembly once, 4 factorisations, sum of sweeps)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import assemble, solve
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        K = assemble.assemble(mesh, Q, eps=0.6, sigma=50.0)
+        t_asm = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        f = solve.factor(K, mesh.volume, mesh.zone, om[1], colour, "DILU")
+        t_fac = time.perf_counter() - t0
+        Ds = solve.system_diag(K, mesh.volume, mesh.zone, om[1])
+        x = np.zeros_like(bs[1])
+        n_sw = 2
+        t0 = time.perf_counter()
+        for _ in range(n_sw):
+            r = bs[1] - solve.apply(K, Ds, x)
+            x = x + solve.precondition(K, f, r)
+        t_sw = (time.perf_counter() - t0) / n_sw
+    t_step = t_asm + len(bs) * t_fac + sum(gpu_sweeps) * t_sw
+    updates = mesh.n_cells * sum(gpu_sweeps)
+    return {"value": updates / t_step, "unit": "cell-unknown updates/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle (NumPy FP64) on the same 200k-cell mesh: assemble {t_asm:.2f} s, DILU factor of one "
+                       f"system {t_fac:.2f} s, {t_sw:.2f} s per sweep (mean of {n_sw}); step time extrapolated to "
+                       f"{len(bs)} systems x GPU sweep counts {gpu_sweeps} = {t_step:.1f} s"),
+            "extrapolated_step_s": t_step}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--storage", default="f32", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-modes", action="store_true", help="skip the other storage precisions")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    mesh, Q, om, bs = build_inputs()
+    print(f"[bench] inputs: {mesh.n_cells} cells, {mesh.n_edges} faces, {len(bs)} systems", file=sys.stderr, flush=True)
+    main_run = Runner(mesh, Q, om, bs, args.storage)
+    res = main_run.timed(args.steps, args.warmup, stats=True)
+    print(f"[bench] {args.storage}: {res['ms_per_step']:.2f} ms/step, sweeps {res['sweeps']}", file=sys.stderr,
+          flush=True)
+    st = res["stats"]
+    upd = st["sweep_update"]
+    setp = st["sweep_set"]
+    avg_ms = upd["total_ms"] / max(upd["launches"], 1)
+    bytes_per_launch = upd["alg_bytes"] / max(upd["launches"], 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"k_rb_pass<{args.storage}, update> (two-colour sweep pass over the second colour)",
+                "avg_launch_us": round(1e3 * avg_ms, 2), "alg_bytes_per_launch": round(bytes_per_launch),
+                "launches": upd["launches"]}
+    if setp["launches"]:
+        set_ms = setp["total_ms"] / setp["launches"]
+        roofline["other_pass"] = {
+            "kernel": "k_rb_pass<set> (first colour)", "avg_launch_us": round(1e3 * set_ms, 2),
+            "achieved": round(setp["alg_bytes"] / setp["launches"] / (set_ms * 1e-3) / 1e9, 1)}
+    memory = main_run.ctx.memory()
+    colour, _ = main_run.ctx.ordering()
+
+    modes = {}
+    if not args.no_modes:
+        for s in ("f64", "f32", "bf16"):
+            if s == args.storage:
+                continue
+            r = Runner(mesh, Q, om, bs, s)
+            m = r.timed(3, 1)
+            modes[s] = {"ms_per_step": round(m["ms_per_step"], 3), "updates_per_s": round(m["updates_per_s"]),
+                        "sweeps": m["sweeps"], "outer": m["outer"], "rel_res": m["rel_res"]}
+            r.ctx.close()
+            print(f"[bench] {s}: {m['ms_per_step']:.2f} ms/step, sweeps {m['sweeps']}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(mesh, Q, om, bs, colour, res["sweeps"])
+
+    out = {
+        "metric": METRIC,
+        "value": round(res["updates_per_s"]),
+        "unit": "cell-unknown updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32 blocks, f32 sweep, f64 outer residual",
+                  "bf16": "bf16 blocks, f32 sweep, f64 outer residual"}[args.storage],
+        "data": "synthetic",
+        "config": {"workload": ("200k-cell hex annular passage sector 80x50x50 (589,500 faces), mean + 3 harmonics "
+                                "(omega = 0, 18, 36, 54), DILU-preconditioned Richardson to a 1e-8 residual drop"),
+                   "cells": mesh.n_cells, "faces": mesh.n_edges, "systems": len(bs), "storage": args.storage,
+                   "eps": 0.6, "sigma": 50.0},
+        "time_to_1e-8_ms": round(res["ms_per_step"], 3),
+        "sweeps": res["sweeps"],
+        "outer": res["outer"],
+        "rel_res": res["rel_res"],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "modes": modes,
+        "memory_bytes": memory,
+        "ingest_ms": round(main_run.ingest_ms, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -203,6 +203,27 @@ const char* fnlh_last_error(fnlh_ctx c);
 int fnlh_order_mesh(const fnlh_mesh* mesh, const fnlh_options* opts, int32_t* colour,
                     int32_t* perm, int32_t* n_colours);
 
+/* Kernel timing of the sweep passes.  While enabled, every sweep-pass launch is
+ * bracketed by HIP events on the caller's stream; durations and the algorithmic bytes
+ * of each launch (blocks once per launch, per active system: D~^-1, own vectors, and
+ * each distinct neighbour vector once) are accumulated per kernel kind. */
+typedef struct {
+  int64_t launches;  /* launches timed                     */
+  double total_ms;   /* sum of event-measured durations    */
+  double alg_bytes;  /* sum of algorithmic bytes           */
+} fnlh_kernel_stats;
+enum {
+  FNLH_KSTAT_SWEEP_UPDATE = 0, /* two-colour pass over the second colour (reads K_ii) */
+  FNLH_KSTAT_SWEEP_SET = 1,    /* two-colour pass over the first colour              */
+  FNLH_KSTAT_FWD = 2,          /* general colouring, forward pass                     */
+  FNLH_KSTAT_BWD = 3,          /* general colouring, backward pass                    */
+  FNLH_KSTAT_JACOBI = 4,       /* block Jacobi pass                                   */
+  FNLH_KSTAT_N = 5
+};
+/* on = 1 resets the counters and starts timing; on = 0 stops. */
+int fnlh_stats_enable(fnlh_ctx c, int32_t on);
+int fnlh_stats_get(fnlh_ctx c, int32_t which, fnlh_kernel_stats* out);
+
 /* Library version string. */
 const char* fnlh_version(void);
 

@@ -58,6 +58,12 @@ struct fnlh_ctx_s {
   DevBuf d_err;
   int* h_err = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // kernel statistics
+  bool stats_on = false;
+  std::vector<hipEvent_t> evpool;
+  double st_ms[FNLH_KSTAT_N] = {0};
+  double st_bytes[FNLH_KSTAT_N] = {0};
+  int64_t st_n[FNLH_KSTAT_N] = {0};
 
   DevPattern pat() const {
     DevPattern p;
@@ -231,31 +237,146 @@ int factor_batch(fnlh_ctx c, const SysBatch& sb, bool dilu, hipStream_t s) {
 
 enum Path { kPathRB, kPathGeneral, kPathJacobi };
 
+// One timed launch: kernel kind, colour, sweep index (0 = the initial pass), events.
+struct LaunchRec {
+  int kind, colour, sweep;
+  hipEvent_t a, b;
+  double ms;
+};
+
+struct Timer {
+  fnlh_ctx c;
+  hipStream_t s;
+  std::vector<LaunchRec> recs;
+  size_t harvested = 0;
+  hipEvent_t get() {
+    if (c->evpool.empty()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      return e;
+    }
+    hipEvent_t e = c->evpool.back();
+    c->evpool.pop_back();
+    return e;
+  }
+  void begin(int kind, int colour, int sweep) {
+    if (!c->stats_on) return;
+    LaunchRec r{kind, colour, sweep, get(), get(), 0.0};
+    (void)hipEventRecord(r.a, s);
+    recs.push_back(r);
+  }
+  void end() {
+    if (!c->stats_on) return;
+    (void)hipEventRecord(recs.back().b, s);
+  }
+  // after a stream synchronisation: read durations, recycle events
+  void harvest() {
+    for (; harvested < recs.size(); ++harvested) {
+      LaunchRec& r = recs[harvested];
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, r.a, r.b);
+      r.ms = ms;
+      c->evpool.push_back(r.a);
+      c->evpool.push_back(r.b);
+    }
+  }
+};
+
+// Algorithmic bytes of one launch (compulsory traffic: each block, vector entry and
+// factor entry touched once), for `na` active systems.
+double alg_bytes(fnlh_ctx c, int kind, int col, int na) {
+  const Layout& L = c->L;
+  const double sA = (double)c->block_bytes();
+  const double sv = (double)c->tv_bytes();
+  const double blk = 36.0 * sA;
+  auto nrows = [&](int cc) { return (double)L.ccount[cc]; };
+  double shared = 0.0, per = 0.0;
+  switch (kind) {
+    case FNLH_KSTAT_SWEEP_UPDATE:
+      shared = L.c_deg[col] * (blk + 4) + nrows(col) * (blk + 12);
+      per = nrows(col) * (3 * 12 + 72) * sv + L.c_nbr[col] * 12 * sv;
+      break;
+    case FNLH_KSTAT_SWEEP_SET:
+      shared = L.c_deg[col] * (blk + 4) + nrows(col) * 12;
+      per = nrows(col) * (2 * 12 + 72) * sv + L.c_nbr[col] * 12 * sv;
+      break;
+    case FNLH_KSTAT_FWD: {
+      const bool last = col == L.n_colours - 1;
+      shared = L.c_deg[col] * (blk + 4) + nrows(col) * (blk + 12);
+      per = nrows(col) * ((last ? 4 : 3) * 12 + 72) * sv + (L.c_nbr[col] + L.c_nbr_lower[col]) * 12 * sv;
+      break;
+    }
+    case FNLH_KSTAT_BWD:
+      shared = L.c_deg_upper[col] * blk + L.c_deg[col] * 4;
+      per = nrows(col) * (4 * 12 + 72) * sv + L.c_nbr_upper[col] * 12 * sv;
+      break;
+    case FNLH_KSTAT_JACOBI: {
+      double deg = 0;
+      for (int cc = 0; cc < L.n_colours; ++cc) deg += L.c_deg[cc];
+      shared = deg * (blk + 4) + (double)L.N * (blk + 12);
+      per = (double)L.N * (3 * 12 + 72) * sv;
+      break;
+    }
+  }
+  return shared + na * per;
+}
+
+// Fold a finished loop's launches into the context totals; S_j = final sweeps.
+void account(fnlh_ctx c, Timer& t, const SysBatch& sb, const SysState* h) {
+  if (!c->stats_on) return;
+  t.harvest();
+  for (const LaunchRec& r : t.recs) {
+    int na = 0;
+    for (int k = 0; k < sb.n; ++k) {
+      const int S = h[sb.vslot[k]].sweeps;
+      na += (r.sweep == 0 ? S >= 1 : S >= r.sweep) ? 1 : 0;
+    }
+    c->st_ms[r.kind] += r.ms;
+    c->st_n[r.kind] += 1;
+    c->st_bytes[r.kind] += alg_bytes(c, r.kind, r.colour, na);
+  }
+  t.recs.clear();
+  t.harvested = 0;
+}
+
 // One preconditioned sweep for the systems of sb (vectors x, b, y of type TV).
 void one_sweep(fnlh_ctx c, Path path, const SweepCfg& cfg, const SysBatch& sb, void* x, const void* b, void* y,
-               SysState* st, bool first, double rtol, double divf, hipStream_t s) {
+               SysState* st, int k, double rtol, double divf, hipStream_t s, Timer& T) {
+  const bool first = k == 1;
   DevPattern p = c->pat();
   const Layout& L = c->L;
   const int64_t ds = dinv_stride(c);
   double* part = (double*)c->partial.p;
   if (path == kPathRB) {
+    T.begin(FNLH_KSTAT_SWEEP_UPDATE, 1, k);
     launch_rb_pass(cfg, true, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, sb, st, part, L.ctile[1],
                    L.ctile[2] - L.ctile[1], s);
+    T.end();
     launch_reduce(sb, part, L.n_tiles, L.ctile[1], L.ctile[2] - L.ctile[1], st,
                   first ? kReduceSweepNoNorm : kReduceSweep, rtol, divf, 0, s);
+    T.begin(FNLH_KSTAT_SWEEP_SET, 0, k);
     launch_rb_pass(cfg, false, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, sb, st, part, L.ctile[0],
                    L.ctile[1] - L.ctile[0], s);
+    T.end();
   } else if (path == kPathGeneral) {
     const int m = L.n_colours;
-    for (int col = 0; col < m; ++col)
+    for (int col = 0; col < m; ++col) {
+      T.begin(FNLH_KSTAT_FWD, col, k);
       launch_fwd(cfg, col == m - 1, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, y, sb, st, part, L.ctile[col],
                  L.ctile[col + 1] - L.ctile[col], L.cstart[col], s);
+      T.end();
+    }
     launch_reduce(sb, part, L.n_tiles, 0, L.n_tiles, st, kReduceSweep, rtol, divf, 0, s);
-    for (int col = m - 2; col >= 0; --col)
+    for (int col = m - 2; col >= 0; --col) {
+      T.begin(FNLH_KSTAT_BWD, col, k);
       launch_bwd(cfg, p, c->offd.p, c->dinv.p, ds, x, y, sb, st, L.ctile[col], L.ctile[col + 1] - L.ctile[col],
                  L.cstart[col + 1], s);
+      T.end();
+    }
   } else {
+    T.begin(FNLH_KSTAT_JACOBI, 0, k);
     launch_jacobi(cfg, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, y, sb, st, part, s);
+    T.end();
     launch_reduce(sb, part, L.n_tiles, 0, L.n_tiles, st, kReduceSweep, rtol, divf, 0, s);
     launch_axpy_y(cfg.storage, p, x, y, sb, st, s);
   }
@@ -264,26 +385,31 @@ void one_sweep(fnlh_ctx c, Path path, const SweepCfg& cfg, const SysBatch& sb, v
 // Iterate until every system of sb is inactive.  States must be initialised.
 int sweep_loop(fnlh_ctx c, Path path, const SweepCfg& cfg, const SysBatch& sb, void* x, const void* b, void* y,
                SysState* st, double rtol, double divf, int max_sweeps, int check_every, hipStream_t s) {
+  Timer T{c, s, {}, 0};
   if (path == kPathRB) {
     DevPattern p = c->pat();
+    T.begin(FNLH_KSTAT_SWEEP_SET, 0, 0);
     launch_rb_pass(cfg, false, p, c->offd.p, c->diag.p, c->dinv.p, dinv_stride(c), x, b, sb, st,
                    (double*)c->partial.p, c->L.ctile[0], c->L.ctile[1] - c->L.ctile[0], s);
+    T.end();
   }
   int launched = 0;
+  SysState* h = c->h_st;
   // each system needs at most max_sweeps sweeps plus one to retire
   while (launched <= max_sweeps + 1) {
     for (int i = 0; i < check_every && launched <= max_sweeps + 1; ++i, ++launched)
-      one_sweep(c, path, cfg, sb, x, b, y, st, launched == 0, rtol, divf, s);
+      one_sweep(c, path, cfg, sb, x, b, y, st, launched + 1, rtol, divf, s, T);
     int rc = check_launch(c, "sweep launch");
     if (rc) return rc;
-    SysState* h = c->h_st;
     HIPC(c, hipMemcpyAsync(h, st, sizeof(SysState) * (sb.vslot[sb.n - 1] + 1), hipMemcpyDeviceToHost, s),
          "read states");
     HIPC(c, hipStreamSynchronize(s), "sweep sync");
+    T.harvest();
     bool any = false;
     for (int k = 0; k < sb.n; ++k) any |= h[sb.vslot[k]].active != 0;
     if (!any) break;
   }
+  account(c, T, sb, h);
   return FNLH_OK;
 }
 
@@ -378,6 +504,7 @@ int fnlh_destroy(fnlh_ctx c) {
   if (c->h_err) (void)hipHostFree(c->h_err);
   for (auto& ev : c->ev)
     if (ev) (void)hipEventDestroy(ev);
+  for (auto ev : c->evpool) (void)hipEventDestroy(ev);
   delete c;
   return FNLH_OK;
 }
@@ -655,6 +782,27 @@ int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, cons
     if (status == FNLH_DIVERGED || (status == FNLH_NOT_CONVERGED && worst == FNLH_OK)) worst = status;
   }
   return worst;
+}
+
+int fnlh_stats_enable(fnlh_ctx c, int32_t on) {
+  if (!c) return FNLH_E_ARG;
+  if (on) {
+    for (int k = 0; k < FNLH_KSTAT_N; ++k) {
+      c->st_ms[k] = 0.0;
+      c->st_bytes[k] = 0.0;
+      c->st_n[k] = 0;
+    }
+  }
+  c->stats_on = on != 0;
+  return FNLH_OK;
+}
+
+int fnlh_stats_get(fnlh_ctx c, int32_t which, fnlh_kernel_stats* out) {
+  if (!c || !out || which < 0 || which >= FNLH_KSTAT_N) return set_err(c, FNLH_E_ARG, "stats_get: bad arguments");
+  out->launches = c->st_n[which];
+  out->total_ms = c->st_ms[which];
+  out->alg_bytes = c->st_bytes[which];
+  return FNLH_OK;
 }
 
 int fnlh_get_ordering(fnlh_ctx c, int32_t* colour_of_cell, int32_t* n_colours) {

@@ -374,6 +374,30 @@ int build_layout(const fnlh_mesh& m, const fnlh_options& o, Layout& L, std::stri
   }
   for (int64_t d = 0; d < 2 * E; ++d) L.ent_rev[L.edge_ent[d]] = (int32_t)L.edge_ent[d ^ 1];
 
+  L.c_deg.assign(ncol, 0);
+  L.c_deg_upper.assign(ncol, 0);
+  L.c_nbr.assign(ncol, 0);
+  L.c_nbr_lower.assign(ncol, 0);
+  L.c_nbr_upper.assign(ncol, 0);
+  {
+    std::vector<int32_t> stamp(N, -1);
+    for (int64_t p = 0; p < N; ++p) {
+      const int32_t u = byc[p];
+      const int32_t c = col[u];
+      for (int64_t q = g.ptr[u]; q < g.ptr[u + 1]; ++q) {
+        const int32_t k = g.nbr[q];
+        L.c_deg[c]++;
+        if (col[k] > c) L.c_deg_upper[c]++;
+        if (stamp[k] != c) {
+          stamp[k] = c;
+          L.c_nbr[c]++;
+          if (col[k] < c) L.c_nbr_lower[c]++;
+          else L.c_nbr_upper[c]++;
+        }
+      }
+    }
+  }
+
   L.vol.assign(NP, 1.0);
   L.zone.assign(NP, 0);
   for (int64_t u = 0; u < N; ++u) {

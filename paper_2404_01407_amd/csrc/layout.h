@@ -25,6 +25,12 @@ struct Layout {
   std::vector<int64_t> cstart;       // [n_colours+1] internal row range of each colour (64-aligned)
   std::vector<int64_t> ccount;       // [n_colours] cells of each colour
   std::vector<int64_t> ctile;        // [n_colours+1] tile range of each colour
+  // per colour, for the algorithmic-traffic model of the sweep kernels
+  std::vector<int64_t> c_deg;        // couplings leaving rows of the colour
+  std::vector<int64_t> c_deg_upper;  // ... to higher colours
+  std::vector<int64_t> c_nbr;        // distinct neighbour cells of its rows
+  std::vector<int64_t> c_nbr_lower;  // ... of lower colours
+  std::vector<int64_t> c_nbr_upper;  // ... of higher colours
 
   // tile t = internal rows [64t, 64t+64), never straddling a colour
   int64_t n_tiles = 0;

@@ -59,6 +59,13 @@ class Report(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class KernelStats(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("alg_bytes", C.c_double)]
+
+
+KSTAT = {"sweep_update": 0, "sweep_set": 1, "fwd": 2, "bwd": 3, "jacobi": 4}
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libfnlh.so not built ({LIB_PATH}); run __graft_entry__.build()")
@@ -78,6 +85,8 @@ def _load():
         "fnlh_last_error": (C.c_char_p, [P]),
         "fnlh_order_mesh": (I32, [C.POINTER(Mesh), C.POINTER(Options), V, V, C.POINTER(I32)]),
         "fnlh_version": (C.c_char_p, []),
+        "fnlh_stats_enable": (I32, [P, I32]),
+        "fnlh_stats_get": (I32, [P, I32, C.POINTER(KernelStats)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -243,6 +252,17 @@ class Context:
                             C.byref(o), C.cast(rep, C.c_void_p), _stream(stream))
         self._check(rc, allow_positive=True)
         return rc, [r.as_dict() for r in rep]
+
+    def stats_enable(self, on=True):
+        self._check(LIB.fnlh_stats_enable(self.h, int(bool(on))))
+
+    def stats(self):
+        out = {}
+        for name, k in KSTAT.items():
+            st = KernelStats()
+            self._check(LIB.fnlh_stats_get(self.h, k, C.byref(st)))
+            out[name] = {"launches": st.launches, "total_ms": st.total_ms, "alg_bytes": st.alg_bytes}
+        return out
 
     def ordering(self):
         colour = np.empty(self.n, np.int32)

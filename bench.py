@@ -30,6 +30,7 @@ HBM_PEAK_GBS = 8000.0
 SHAPE = (80, 50, 50)
 N_HARM = 3
 RTOL = 1e-8
+STATS_PERIOD = 4  # time the sweep-pass launches of every 4th sweep (bounds event overhead)
 
 
 def build_inputs():
@@ -43,12 +44,15 @@ def build_inputs():
 
 
 class Runner:
-    def __init__(self, mesh, Q, om, bs, storage):
+    def __init__(self, mesh, Q, om, bs, storage, lanes=0, row_lanes=0, check_every=16, use_graph=True):
         import torch
         from paper_2404_01407_amd import fnlh
         t0 = time.perf_counter()
         self.ctx = fnlh.Context(mesh, storage=storage, outer="exact")
         self.ingest_ms = 1e3 * (time.perf_counter() - t0)
+        self.ctx.tune(sys_per_lane=lanes, lanes_per_row=row_lanes)
+        self.check_every = check_every
+        self.use_graph = use_graph
         self.Qd = torch.from_numpy(Q).cuda()
         self.bd = [torch.from_numpy(b).cuda() for b in bs]
         self.xd = [torch.zeros_like(b) for b in self.bd]
@@ -62,7 +66,7 @@ class Runner:
         self.ctx.assemble_jacobian(self.Qd, eps=0.6, sigma=50.0)
         self.ctx.set_harmonics(self.om)
         st, rep = self.ctx.relax(list(range(self.S)), self.xd, self.bd, kind="dilu", max_sweeps=4000, rtol=RTOL,
-                                 check_every=8)
+                                 check_every=self.check_every, use_graph=self.use_graph)
         if st != 0:
             raise RuntimeError(f"solve did not converge: status {st}, reports {rep}")
         return rep
@@ -72,7 +76,7 @@ class Runner:
         for _ in range(warmup):
             self.step()
         if stats:
-            self.ctx.stats_enable(True)
+            self.ctx.stats_enable(True, period=STATS_PERIOD)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         reps = []
@@ -129,6 +133,13 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true", help="skip the other storage precisions")
+    ap.add_argument("--lanes", type=int, default=0, help="systems per lane of the sweep kernels (0 = auto)")
+    ap.add_argument("--row-lanes", type=int, default=0, help="lanes sharing a row in the two-colour pass (0 = auto)")
+    ap.add_argument("--check-every", type=int, default=16, help="sweeps between host checks of the stop flags")
+    ap.add_argument("--no-graph", action="store_true", help="direct launches instead of graph replay")
+    ap.add_argument("--no-stats", action="store_true", help="no per-kernel event timing in the timed region")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -136,13 +147,23 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if args.calib_copy:
+        xs = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        ys = torch.empty_like(xs)
+        for _ in range(3):
+            torch.neg(xs, out=ys)
+        torch.cuda.synchronize()
+        del xs, ys
+        print("[bench] calibration: torch.neg over 1 GiB (read 1 GiB, write 1 GiB) x3", file=sys.stderr, flush=True)
+
     mesh, Q, om, bs = build_inputs()
     print(f"[bench] inputs: {mesh.n_cells} cells, {mesh.n_edges} faces, {len(bs)} systems", file=sys.stderr, flush=True)
-    main_run = Runner(mesh, Q, om, bs, args.storage)
-    res = main_run.timed(args.steps, args.warmup, stats=True)
+    main_run = Runner(mesh, Q, om, bs, args.storage, args.lanes, args.row_lanes, args.check_every,
+                      not args.no_graph)
+    res = main_run.timed(args.steps, args.warmup, stats=not args.no_stats)
     print(f"[bench] {args.storage}: {res['ms_per_step']:.2f} ms/step, sweeps {res['sweeps']}", file=sys.stderr,
           flush=True)
-    st = res["stats"]
+    st = res["stats"] or {k: {"launches": 0, "total_ms": 0.0, "alg_bytes": 0.0} for k in ("sweep_update", "sweep_set")}
     upd = st["sweep_update"]
     setp = st["sweep_set"]
     avg_ms = upd["total_ms"] / max(upd["launches"], 1)
@@ -166,7 +187,7 @@ def main():
         for s in ("f64", "f32", "bf16"):
             if s == args.storage:
                 continue
-            r = Runner(mesh, Q, om, bs, s)
+            r = Runner(mesh, Q, om, bs, s, check_every=args.check_every, use_graph=not args.no_graph)
             m = r.timed(3, 1)
             modes[s] = {"ms_per_step": round(m["ms_per_step"], 3), "updates_per_s": round(m["updates_per_s"]),
                         "sweeps": m["sweeps"], "outer": m["outer"], "rel_res": m["rel_res"]}

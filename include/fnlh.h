@@ -220,9 +220,20 @@ enum {
   FNLH_KSTAT_JACOBI = 4,       /* block Jacobi pass                                   */
   FNLH_KSTAT_N = 5
 };
-/* on = 1 resets the counters and starts timing; on = 0 stops. */
+/* on >= 1 resets the counters and starts timing the launches of every on-th sweep
+ * (1 = every launch; a larger period bounds the event overhead); on = 0 stops.
+ * While timing, sweeps are launched directly even if use_graph is set. */
 int fnlh_stats_enable(fnlh_ctx c, int32_t on);
 int fnlh_stats_get(fnlh_ctx c, int32_t which, fnlh_kernel_stats* out);
+
+/* Tuning knobs (chosen by an autotuner or the caller; results do not depend on them
+ * beyond floating-point summation order):
+ *   FNLH_TUNE_SYS_PER_LANE  minimum systems a lane of the sweep kernels carries: 1, 2
+ *                           or 4 (0 = automatic).
+ *   FNLH_TUNE_LANES_PER_ROW lanes sharing one row in the two-colour pass: 1, 2 or 4
+ *                           (0 = automatic: min(4, systems)). */
+enum { FNLH_TUNE_SYS_PER_LANE = 0, FNLH_TUNE_LANES_PER_ROW = 1 };
+int fnlh_tune(fnlh_ctx c, int32_t param, int32_t value);
 
 /* Library version string. */
 const char* fnlh_version(void);

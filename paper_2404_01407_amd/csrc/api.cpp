@@ -26,12 +26,16 @@ struct DevBuf {
 
 }  // namespace
 
+struct GraphEntry;
+
 struct fnlh_ctx_s {
   Layout L;
   int dev = 0;
   int storage = FNLH_F64;
   int outer = FNLH_OUTER_EXACT;
   int factor_slots_opt = 0;
+  int lanes_per_sys = 0;  // systems per lane of the sweep kernels (0 = automatic)
+  int lanes_per_row = 0;  // lanes sharing a row in the two-colour pass (0 = automatic)
   std::string err;
 
   // pattern (device)
@@ -58,8 +62,17 @@ struct fnlh_ctx_s {
   DevBuf d_err;
   int* h_err = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // diagonal blocks strictly diagonally dominant (first-colour solve without pivoting)
+  bool dom_known = false, dom = false;
+  DevBuf d_dom;
+  int* h_dom = nullptr;
+  // captured sweep graphs
+  hipStream_t cap = nullptr;
+  std::vector<GraphEntry*> graphs;
+  bool graph_broken = false;
   // kernel statistics
   bool stats_on = false;
+  int stats_period = 1;  // time the launches of every stats_period-th sweep
   std::vector<hipEvent_t> evpool;
   double st_ms[FNLH_KSTAT_N] = {0};
   double st_bytes[FNLH_KSTAT_N] = {0};
@@ -159,7 +172,8 @@ int ensure_vectors(fnlh_ctx c, int n) {
   if ((rc = dalloc(c, c->x64, v64, "alloc x"))) return rc;
   if ((rc = dalloc(c, c->b64, v64, "alloc b"))) return rc;
   if ((rc = dalloc(c, c->y, v64, "alloc y"))) return rc;
-  if ((rc = dalloc(c, c->partial, (size_t)n * c->L.n_tiles * sizeof(double), "alloc partial"))) return rc;
+  if ((rc = dalloc(c, c->partial, (size_t)n * c->L.n_tiles * kPartialSlots * sizeof(double), "alloc partial")))
+    return rc;
   if ((rc = dalloc(c, c->st, (size_t)n * sizeof(SysState), "alloc state"))) return rc;
   if ((rc = dalloc(c, c->st_outer, (size_t)n * sizeof(SysState), "alloc state"))) return rc;
   if (c->storage != FNLH_F64) {
@@ -203,20 +217,19 @@ void invalidate_factors(fnlh_ctx c) {
 }
 
 // outer FP64 operator residual of the systems of sb (x64, b64 -> r, partial)
-void outer_residual(fnlh_ctx c, const SysBatch& sb, double* r, hipStream_t s) {
+void outer_residual(fnlh_ctx c, int ns, const SysBatch& sb, double* r, hipStream_t s) {
   DevPattern p = c->pat();
+  const double* x = (const double*)c->x64.p;
+  const double* b = (const double*)c->b64.p;
+  double* part = (double*)c->partial.p;
   if (c->storage == FNLH_F64) {
-    launch_resid_stored(kF64, p, c->offd.p, c->diag.p, (const double*)c->x64.p, (const double*)c->b64.p, r, sb,
-                        (double*)c->partial.p, s);
+    launch_resid_stored(kF64, p, c->offd.p, c->diag.p, x, b, r, ns, sb, part, s);
   } else if (c->outer == FNLH_OUTER_STORED) {
-    launch_resid_stored(c->storage, p, c->offd.p, c->diag.p, (const double*)c->x64.p, (const double*)c->b64.p, r,
-                        sb, (double*)c->partial.p, s);
+    launch_resid_stored(c->storage, p, c->offd.p, c->diag.p, x, b, r, ns, sb, part, s);
   } else if (c->assembled) {
-    launch_resid_mfree(p, c->flow(), (const double*)c->x64.p, (const double*)c->b64.p, r, sb,
-                       (double*)c->partial.p, s);
+    launch_resid_mfree(p, c->flow(), x, b, r, ns, sb, part, s);
   } else {
-    launch_resid_stored(kF64, p, c->offd64.p, c->diag64.p, (const double*)c->x64.p, (const double*)c->b64.p, r, sb,
-                        (double*)c->partial.p, s);
+    launch_resid_stored(kF64, p, c->offd64.p, c->diag64.p, x, b, r, ns, sb, part, s);
   }
 }
 
@@ -249,38 +262,69 @@ struct Timer {
   hipStream_t s;
   std::vector<LaunchRec> recs;
   size_t harvested = 0;
+  bool pooled = true;                 // events come from (and return to) the context pool
+  std::vector<hipEvent_t>* own = nullptr;  // graph capture: events owned by the graph
   hipEvent_t get() {
+    hipEvent_t e = nullptr;
+    if (!pooled) {
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      own->push_back(e);
+      return e;
+    }
     if (c->evpool.empty()) {
-      hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) return nullptr;
       return e;
     }
-    hipEvent_t e = c->evpool.back();
+    e = c->evpool.back();
     c->evpool.pop_back();
     return e;
   }
+  bool open = false;
   void begin(int kind, int colour, int sweep) {
-    if (!c->stats_on) return;
+    open = c->stats_on && sweep % c->stats_period == 0;
+    if (!open) return;
     LaunchRec r{kind, colour, sweep, get(), get(), 0.0};
     (void)hipEventRecord(r.a, s);
     recs.push_back(r);
   }
   void end() {
-    if (!c->stats_on) return;
+    if (!open) return;
     (void)hipEventRecord(recs.back().b, s);
+    open = false;
   }
-  // after a stream synchronisation: read durations, recycle events
+  // after a stream synchronisation: read durations, recycle pooled events
   void harvest() {
     for (; harvested < recs.size(); ++harvested) {
       LaunchRec& r = recs[harvested];
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, r.a, r.b);
       r.ms = ms;
-      c->evpool.push_back(r.a);
-      c->evpool.push_back(r.b);
+      if (pooled) {
+        c->evpool.push_back(r.a);
+        c->evpool.push_back(r.b);
+      }
     }
   }
 };
+
+}  // namespace
+
+// A captured run of `K` sweeps (all after the first), replayed with hipGraphLaunch.
+struct GraphEntry {
+  // key
+  int path, storage, spw, lpr, pivot, ns, K;
+  SysBatch sb;
+  const void *x, *b, *y, *st;
+  double rtol, divf;
+  bool stats;
+  // value
+  hipGraphExec_t exec = nullptr;
+  std::vector<hipEvent_t> events;
+  std::vector<LaunchRec> tmpl;  // timed launches inside, sweep = offset within the graph
+  uint64_t last_use = 0;
+};
+
+namespace {
 
 // Algorithmic bytes of one launch (compulsory traffic: each block, vector entry and
 // factor entry touched once), for `na` active systems.
@@ -296,9 +340,9 @@ double alg_bytes(fnlh_ctx c, int kind, int col, int na) {
       shared = L.c_deg[col] * (blk + 4) + nrows(col) * (blk + 12);
       per = nrows(col) * (3 * 12 + 72) * sv + L.c_nbr[col] * 12 * sv;
       break;
-    case FNLH_KSTAT_SWEEP_SET:
-      shared = L.c_deg[col] * (blk + 4) + nrows(col) * 12;
-      per = nrows(col) * (2 * 12 + 72) * sv + L.c_nbr[col] * 12 * sv;
+    case FNLH_KSTAT_SWEEP_SET:  // solves with the shifted diagonal block, no factor read
+      shared = L.c_deg[col] * (blk + 4) + nrows(col) * (blk + 12);
+      per = nrows(col) * (2 * 12) * sv + L.c_nbr[col] * 12 * sv;
       break;
     case FNLH_KSTAT_FWD: {
       const bool last = col == L.n_colours - 1;
@@ -324,7 +368,6 @@ double alg_bytes(fnlh_ctx c, int kind, int col, int na) {
 // Fold a finished loop's launches into the context totals; S_j = final sweeps.
 void account(fnlh_ctx c, Timer& t, const SysBatch& sb, const SysState* h) {
   if (!c->stats_on) return;
-  t.harvest();
   for (const LaunchRec& r : t.recs) {
     int na = 0;
     for (int k = 0; k < sb.n; ++k) {
@@ -340,8 +383,8 @@ void account(fnlh_ctx c, Timer& t, const SysBatch& sb, const SysState* h) {
 }
 
 // One preconditioned sweep for the systems of sb (vectors x, b, y of type TV).
-void one_sweep(fnlh_ctx c, Path path, const SweepCfg& cfg, const SysBatch& sb, void* x, const void* b, void* y,
-               SysState* st, int k, double rtol, double divf, hipStream_t s, Timer& T) {
+void one_sweep(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, const SysBatch& sb, void* x, const void* b,
+               void* y, SysState* st, int k, double rtol, double divf, hipStream_t s, Timer& T) {
   const bool first = k == 1;
   DevPattern p = c->pat();
   const Layout& L = c->L;
@@ -349,67 +392,199 @@ void one_sweep(fnlh_ctx c, Path path, const SweepCfg& cfg, const SysBatch& sb, v
   double* part = (double*)c->partial.p;
   if (path == kPathRB) {
     T.begin(FNLH_KSTAT_SWEEP_UPDATE, 1, k);
-    launch_rb_pass(cfg, true, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, sb, st, part, L.ctile[1],
+    launch_rb_pass(cfg, true, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, ns, sb, st, part, L.ctile[1],
                    L.ctile[2] - L.ctile[1], s);
     T.end();
-    launch_reduce(sb, part, L.n_tiles, L.ctile[1], L.ctile[2] - L.ctile[1], st,
+    launch_reduce(sb, part, L.n_tiles, L.ctile[1], L.ctile[2] - L.ctile[1], rb_slots(cfg, sb.n), st,
                   first ? kReduceSweepNoNorm : kReduceSweep, rtol, divf, 0, s);
     T.begin(FNLH_KSTAT_SWEEP_SET, 0, k);
-    launch_rb_pass(cfg, false, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, sb, st, part, L.ctile[0],
+    launch_rb_pass(cfg, false, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, ns, sb, st, part, L.ctile[0],
                    L.ctile[1] - L.ctile[0], s);
     T.end();
   } else if (path == kPathGeneral) {
     const int m = L.n_colours;
     for (int col = 0; col < m; ++col) {
       T.begin(FNLH_KSTAT_FWD, col, k);
-      launch_fwd(cfg, col == m - 1, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, y, sb, st, part, L.ctile[col],
+      launch_fwd(cfg, col == m - 1, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, y, ns, sb, st, part, L.ctile[col],
                  L.ctile[col + 1] - L.ctile[col], L.cstart[col], s);
       T.end();
     }
-    launch_reduce(sb, part, L.n_tiles, 0, L.n_tiles, st, kReduceSweep, rtol, divf, 0, s);
+    launch_reduce(sb, part, L.n_tiles, 0, L.n_tiles, 1, st, kReduceSweep, rtol, divf, 0, s);
     for (int col = m - 2; col >= 0; --col) {
       T.begin(FNLH_KSTAT_BWD, col, k);
-      launch_bwd(cfg, p, c->offd.p, c->dinv.p, ds, x, y, sb, st, L.ctile[col], L.ctile[col + 1] - L.ctile[col],
+      launch_bwd(cfg, p, c->offd.p, c->dinv.p, ds, x, y, ns, sb, st, L.ctile[col], L.ctile[col + 1] - L.ctile[col],
                  L.cstart[col + 1], s);
       T.end();
     }
   } else {
     T.begin(FNLH_KSTAT_JACOBI, 0, k);
-    launch_jacobi(cfg, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, y, sb, st, part, s);
+    launch_jacobi(cfg, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, y, ns, sb, st, part, s);
     T.end();
-    launch_reduce(sb, part, L.n_tiles, 0, L.n_tiles, st, kReduceSweep, rtol, divf, 0, s);
-    launch_axpy_y(cfg.storage, p, x, y, sb, st, s);
+    launch_reduce(sb, part, L.n_tiles, 0, L.n_tiles, 1, st, kReduceSweep, rtol, divf, 0, s);
+    launch_axpy_y(cfg.storage, p, x, y, ns, sb, st, s);
   }
 }
 
-// Iterate until every system of sb is inactive.  States must be initialised.
-int sweep_loop(fnlh_ctx c, Path path, const SweepCfg& cfg, const SysBatch& sb, void* x, const void* b, void* y,
-               SysState* st, double rtol, double divf, int max_sweeps, int check_every, hipStream_t s) {
-  Timer T{c, s, {}, 0};
+bool same_key(const GraphEntry* g, int path, const SweepCfg& cfg, int ns, int K, const SysBatch& sb, const void* x,
+              const void* b, const void* y, const void* st, double rtol, double divf, bool stats) {
+  if (g->path != path || g->storage != cfg.storage || g->spw != cfg.spw || g->lpr != cfg.lanes_per_row ||
+      g->pivot != (int)cfg.pivot || g->ns != ns || g->K != K || g->x != x || g->b != b || g->y != y ||
+      g->st != st || g->rtol != rtol || g->divf != divf || g->stats != stats || g->sb.n != sb.n)
+    return false;
+  for (int k = 0; k < sb.n; ++k)
+    if (g->sb.orow[k] != sb.orow[k] || g->sb.dslot[k] != sb.dslot[k] || g->sb.vslot[k] != sb.vslot[k]) return false;
+  return true;
+}
+
+void destroy_graph(GraphEntry* g) {
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  for (auto e : g->events) (void)hipEventDestroy(e);
+  delete g;
+}
+
+// Find or capture the graph of K sweeps for this configuration (nullptr: capture failed).
+GraphEntry* get_graph(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, int K, const SysBatch& sb, void* x,
+                      const void* b, void* y, SysState* st, double rtol, double divf) {
+  static uint64_t tick = 0;
+  for (GraphEntry* g : c->graphs)
+    if (same_key(g, path, cfg, ns, K, sb, x, b, y, st, rtol, divf, c->stats_on)) {
+      g->last_use = ++tick;
+      return g;
+    }
+  if (c->graph_broken) return nullptr;
+  if (!c->cap && hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+    c->graph_broken = true;
+    return nullptr;
+  }
+  GraphEntry* g = new GraphEntry();
+  g->path = path;
+  g->storage = cfg.storage;
+  g->spw = cfg.spw;
+  g->lpr = cfg.lanes_per_row;
+  g->pivot = cfg.pivot;
+  g->ns = ns;
+  g->K = K;
+  g->sb = sb;
+  g->x = x;
+  g->b = b;
+  g->y = y;
+  g->st = st;
+  g->rtol = rtol;
+  g->divf = divf;
+  g->stats = c->stats_on;
+  Timer T{c, c->cap, {}, 0, false, &g->events};
+  hipGraph_t graph = nullptr;
+  bool ok = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    for (int i = 0; i < K; ++i) one_sweep(c, path, cfg, ns, sb, x, b, y, st, 2 + i, rtol, divf, c->cap, T);
+    ok = hipStreamEndCapture(c->cap, &graph) == hipSuccess && graph;
+  }
+  (void)hipGetLastError();
+  if (ok) ok = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) == hipSuccess;
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipGetLastError();
+  if (!ok) {
+    c->graph_broken = true;
+    destroy_graph(g);
+    return nullptr;
+  }
+  for (auto& r : T.recs) r.sweep -= 2;
+  g->tmpl = T.recs;
+  g->last_use = ++tick;
+  if (c->graphs.size() >= 8) {
+    auto it = std::min_element(c->graphs.begin(), c->graphs.end(),
+                               [](GraphEntry* a, GraphEntry* b2) { return a->last_use < b2->last_use; });
+    destroy_graph(*it);
+    c->graphs.erase(it);
+  }
+  c->graphs.push_back(g);
+  return g;
+}
+
+// Iterate until every system of sb is inactive.  States must be initialised.  Sweeps
+// after the first are replayed from a captured graph of check_every sweeps when
+// use_graph is set (direct launches otherwise, or if capture is unavailable).
+int sweep_loop(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, const SysBatch& sb, void* x, const void* b,
+               void* y, SysState* st, double rtol, double divf, int max_sweeps, int check_every, bool use_graph,
+               hipStream_t s) {
+  Timer T{c, s, {}, 0, true, nullptr};
   if (path == kPathRB) {
     DevPattern p = c->pat();
     T.begin(FNLH_KSTAT_SWEEP_SET, 0, 0);
-    launch_rb_pass(cfg, false, p, c->offd.p, c->diag.p, c->dinv.p, dinv_stride(c), x, b, sb, st,
+    launch_rb_pass(cfg, false, p, c->offd.p, c->diag.p, c->dinv.p, dinv_stride(c), x, b, ns, sb, st,
                    (double*)c->partial.p, c->L.ctile[0], c->L.ctile[1] - c->L.ctile[0], s);
     T.end();
   }
   int launched = 0;
   SysState* h = c->h_st;
+  GraphEntry* g = nullptr;
   // each system needs at most max_sweeps sweeps plus one to retire
   while (launched <= max_sweeps + 1) {
-    for (int i = 0; i < check_every && launched <= max_sweeps + 1; ++i, ++launched)
-      one_sweep(c, path, cfg, sb, x, b, y, st, launched + 1, rtol, divf, s, T);
+    if (launched == 0) {
+      one_sweep(c, path, cfg, ns, sb, x, b, y, st, 1, rtol, divf, s, T);
+      launched = 1;
+      // per-kernel timing needs events around every launch; events recorded by graph
+      // nodes cannot be queried for elapsed time here, so timing runs launch directly
+      if (use_graph && !c->stats_on) g = get_graph(c, path, cfg, ns, check_every, sb, x, b, y, st, rtol, divf);
+      if (!g) {
+        for (int i = 1; i < check_every && launched <= max_sweeps + 1; ++i, ++launched)
+          one_sweep(c, path, cfg, ns, sb, x, b, y, st, launched + 1, rtol, divf, s, T);
+      }
+    } else if (g) {
+      HIPC(c, hipGraphLaunch(g->exec, s), "graph launch");
+      if (c->stats_on)
+        for (const LaunchRec& r : g->tmpl) T.recs.push_back(LaunchRec{r.kind, r.colour, launched + 1 + r.sweep,
+                                                                       r.a, r.b, 0.0});
+      launched += check_every;
+    } else {
+      for (int i = 0; i < check_every && launched <= max_sweeps + 1; ++i, ++launched)
+        one_sweep(c, path, cfg, ns, sb, x, b, y, st, launched + 1, rtol, divf, s, T);
+    }
     int rc = check_launch(c, "sweep launch");
     if (rc) return rc;
     HIPC(c, hipMemcpyAsync(h, st, sizeof(SysState) * (sb.vslot[sb.n - 1] + 1), hipMemcpyDeviceToHost, s),
          "read states");
     HIPC(c, hipStreamSynchronize(s), "sweep sync");
-    T.harvest();
+    // graph events are re-recorded on every replay: read them now, never recycle them
+    for (; T.harvested < T.recs.size(); ++T.harvested) {
+      LaunchRec& r = T.recs[T.harvested];
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, r.a, r.b);
+      r.ms = ms;
+      bool from_graph = false;
+      if (g)
+        for (auto e : g->events)
+          if (e == r.a) {
+            from_graph = true;
+            break;
+          }
+      if (!from_graph) {
+        c->evpool.push_back(r.a);
+        c->evpool.push_back(r.b);
+      }
+    }
     bool any = false;
     for (int k = 0; k < sb.n; ++k) any |= h[sb.vslot[k]].active != 0;
     if (!any) break;
   }
   account(c, T, sb, h);
+  return FNLH_OK;
+}
+
+// Dominance of the diagonal blocks (decides the first-colour solve), once per matrix.
+int ensure_dominance(fnlh_ctx c, hipStream_t s) {
+  if (c->dom_known) return FNLH_OK;
+  int rc;
+  if (!c->d_dom.p && (rc = dalloc(c, c->d_dom, sizeof(int), "alloc flag"))) return rc;
+  if (!c->h_dom) HIPC(c, hipHostMalloc((void**)&c->h_dom, sizeof(int), hipHostMallocDefault), "host flag");
+  const int one = 1;
+  HIPC(c, hipMemcpyAsync(c->d_dom.p, &one, sizeof(int), hipMemcpyHostToDevice, s), "set flag");
+  launch_check_dominance(c->storage, c->pat(), c->diag.p, (int*)c->d_dom.p, s);
+  if ((rc = check_launch(c, "dominance launch"))) return rc;
+  HIPC(c, hipMemcpyAsync(c->h_dom, c->d_dom.p, sizeof(int), hipMemcpyDeviceToHost, s), "read flag");
+  HIPC(c, hipStreamSynchronize(s), "dominance sync");
+  c->dom = *c->h_dom != 0;
+  c->dom_known = true;
   return FNLH_OK;
 }
 
@@ -505,6 +680,10 @@ int fnlh_destroy(fnlh_ctx c) {
   for (auto& ev : c->ev)
     if (ev) (void)hipEventDestroy(ev);
   for (auto ev : c->evpool) (void)hipEventDestroy(ev);
+  for (auto g : c->graphs) destroy_graph(g);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
+  if (c->h_dom) (void)hipHostFree(c->h_dom);
+  dfree(c->d_dom);
   delete c;
   return FNLH_OK;
 }
@@ -520,7 +699,7 @@ int fnlh_assemble_jacobian(fnlh_ctx c, const double* state, const double* bstate
   int rc;
   if (!c->state.p && (rc = dalloc(c, c->state, (size_t)c->L.NP * 6 * sizeof(double), "alloc state"))) return rc;
   DevPattern p = c->pat();
-  launch_to_internal(p, (const int32_t*)c->iperm.p, state, (double*)c->state.p, 6, s);
+  launch_to_internal(p, (const int32_t*)c->iperm.p, state, (double*)c->state.p, 6, 1, 0, s);
   if (bstate && c->L.B > 0) {
     if (!c->bstate.p && (rc = dalloc(c, c->bstate, (size_t)c->L.B * 6 * sizeof(double), "alloc bstate"))) return rc;
     HIPC(c, hipMemcpyAsync(c->bstate.p, bstate, (size_t)c->L.B * 6 * sizeof(double), hipMemcpyDeviceToDevice, s),
@@ -538,6 +717,7 @@ int fnlh_assemble_jacobian(fnlh_ctx c, const double* state, const double* bstate
   c->have_shadow = false;
   c->have_matrix = true;
   c->assembled = true;
+  c->dom_known = false;
   invalidate_factors(c);
   return FNLH_OK;
 }
@@ -564,6 +744,7 @@ int fnlh_set_blocks(fnlh_ctx c, const double* diag, const double* offd, void* st
   if ((rc = check_launch(c, "set_blocks launch"))) return rc;
   c->have_matrix = true;
   c->assembled = false;
+  c->dom_known = false;
   invalidate_factors(c);
   return FNLH_OK;
 }
@@ -605,18 +786,18 @@ int fnlh_residual(fnlh_ctx c, int32_t sys, const double* x, const double* b, dou
   int rc;
   if ((rc = ensure_vectors(c, 1))) return rc;
   DevPattern p = c->pat();
-  launch_to_internal(p, (const int32_t*)c->iperm.p, x, (double*)c->x64.p, 12, s);
-  launch_to_internal(p, (const int32_t*)c->iperm.p, b, (double*)c->b64.p, 12, s);
+  launch_to_internal(p, (const int32_t*)c->iperm.p, x, (double*)c->x64.p, 12, 1, 0, s);
+  launch_to_internal(p, (const int32_t*)c->iperm.p, b, (double*)c->b64.p, 12, 1, 0, s);
   SysBatch sb;
   sb.n = 1;
   sb.orow[0] = sys;
   sb.dslot[0] = 0;
   sb.vslot[0] = 0;
   double* rint = r ? (double*)c->y.p : nullptr;
-  outer_residual(c, sb, rint, s);
-  launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, (SysState*)c->st.p, kReduceFinal, 0,
+  outer_residual(c, 1, sb, rint, s);
+  launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, 1, (SysState*)c->st.p, kReduceFinal, 0,
                 0, 0, s);
-  if (r) launch_to_user(p, (const int32_t*)c->iperm.p, rint, r, 12, s);
+  if (r) launch_to_user(p, (const int32_t*)c->iperm.p, rint, r, 12, 1, 0, s);
   if ((rc = check_launch(c, "residual launch"))) return rc;
   HIPC(c, hipMemcpyAsync(c->h_st, c->st.p, sizeof(SysState), hipMemcpyDeviceToHost, s), "read state");
   HIPC(c, hipStreamSynchronize(s), "residual sync");
@@ -648,14 +829,18 @@ int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, cons
   if ((rc = ensure_slots(c, want_slots))) return rc;
   DevPattern p = c->pat();
   for (int j = 0; j < n; ++j) {
-    launch_to_internal(p, (const int32_t*)c->iperm.p, x[j], (double*)c->x64.p + (size_t)j * c->L.NP * 12, 12, s);
-    launch_to_internal(p, (const int32_t*)c->iperm.p, b[j], (double*)c->b64.p + (size_t)j * c->L.NP * 12, 12, s);
+    launch_to_internal(p, (const int32_t*)c->iperm.p, x[j], (double*)c->x64.p, 12, n, j, s);
+    launch_to_internal(p, (const int32_t*)c->iperm.p, b[j], (double*)c->b64.p, 12, n, j, s);
   }
   const Path path = o->kind == FNLH_JACOBI ? kPathJacobi : (c->L.n_colours == 2 ? kPathRB : kPathGeneral);
   const int fkind = o->kind == FNLH_DILU ? 0 : 1;
   SweepCfg cfg;
   cfg.storage = c->storage;
-  cfg.spw = 4;
+  cfg.spw = c->lanes_per_sys;
+  cfg.lanes_per_row = c->lanes_per_row;
+  if ((rc = ensure_dominance(c, s))) return rc;
+  cfg.pivot = !c->dom;
+  const bool use_graph = o->use_graph != 0;
   const int G = std::min({n, kMaxBatch, c->n_slots});
   std::vector<double> tf(n, 0.0), ts(n, 0.0);
   for (int g0 = 0; g0 < n; g0 += G) {
@@ -702,16 +887,16 @@ int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, cons
     HIPC(c, hipEventRecord(c->ev[1], s), "event");
     SysState* st = (SysState*)c->st.p;
     if (!reduced) {
-      outer_residual(c, sb, nullptr, s);
-      launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, st, kReduceInit, 0, 0,
+      outer_residual(c, n, sb, nullptr, s);
+      launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, 1, st, kReduceInit, 0, 0,
                     o->max_sweeps, s);
-      if ((rc = sweep_loop(c, path, cfg, sb, c->x64.p, c->b64.p, c->y.p, st, o->rtol, divf, o->max_sweeps,
-                           check_every, s)))
+      if ((rc = sweep_loop(c, path, cfg, n, sb, c->x64.p, c->b64.p, c->y.p, st, o->rtol, divf, o->max_sweeps,
+                           check_every, use_graph, s)))
         return rc;
     } else {
       SysState* so = (SysState*)c->st_outer.p;
-      outer_residual(c, sb, (double*)c->r64.p, s);
-      launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, so, kReduceInit, 0, 0,
+      outer_residual(c, n, sb, (double*)c->r64.p, s);
+      launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, 1, so, kReduceInit, 0, 0,
                     o->max_sweeps, s);
       for (int it = 0; it < 100000; ++it) {
         if ((rc = check_launch(c, "outer launch"))) return rc;
@@ -721,15 +906,15 @@ int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, cons
         bool any = false;
         for (int k = 0; k < sb.n; ++k) any |= c->h_st[sb.vslot[k]].active != 0;
         if (!any) break;
-        launch_to_f32(p, (const double*)c->r64.p, (float*)c->rhs32.p, (float*)c->d32.p, sb, so, s);
+        launch_to_f32(p, (const double*)c->r64.p, (float*)c->rhs32.p, (float*)c->d32.p, n, sb, so, s);
         launch_inner_init(sb, so, st, inner_max, s);
-        if ((rc = sweep_loop(c, path, cfg, sb, c->d32.p, c->rhs32.p, c->y.p, st, inner_rtol, 1e30, inner_max,
-                             check_every, s)))
+        if ((rc = sweep_loop(c, path, cfg, n, sb, c->d32.p, c->rhs32.p, c->y.p, st, inner_rtol, 1e30, inner_max,
+                             check_every, use_graph, s)))
           return rc;
         launch_outer_update(sb, st, so, s);
-        launch_add_f32(p, (double*)c->x64.p, (const float*)c->d32.p, sb, so, s);
-        outer_residual(c, sb, (double*)c->r64.p, s);
-        launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, so, kReduceOuter, o->rtol,
+        launch_add_f32(p, (double*)c->x64.p, (const float*)c->d32.p, n, sb, so, s);
+        outer_residual(c, n, sb, (double*)c->r64.p, s);
+        launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, 1, so, kReduceOuter, o->rtol,
                       divf, 0, s);
       }
     }
@@ -754,11 +939,11 @@ int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, cons
       sb.dslot[k] = 0;
     }
     SysState* stf = (SysState*)(reduced ? c->st_outer.p : c->st.p);
-    outer_residual(c, sb, nullptr, s);
-    launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, stf, kReduceFinal, 0, 0, 0, s);
+    outer_residual(c, n, sb, nullptr, s);
+    launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, 1, stf, kReduceFinal, 0, 0, 0, s);
   }
   for (int j = 0; j < n; ++j)
-    launch_to_user(p, (const int32_t*)c->iperm.p, (const double*)c->x64.p + (size_t)j * c->L.NP * 12, x[j], 12, s);
+    launch_to_user(p, (const int32_t*)c->iperm.p, (const double*)c->x64.p, x[j], 12, n, j, s);
   if ((rc = check_launch(c, "final launch"))) return rc;
   HIPC(c, hipMemcpyAsync(c->h_st, reduced ? c->st_outer.p : c->st.p, sizeof(SysState) * n, hipMemcpyDeviceToHost, s),
        "read states");
@@ -784,6 +969,23 @@ int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, cons
   return worst;
 }
 
+int fnlh_tune(fnlh_ctx c, int32_t param, int32_t value) {
+  if (!c) return FNLH_E_ARG;
+  if (param == FNLH_TUNE_SYS_PER_LANE) {
+    if (value != 0 && value != 1 && value != 2 && value != 4)
+      return set_err(c, FNLH_E_ARG, "tune: systems per lane must be 0, 1, 2 or 4");
+    c->lanes_per_sys = value;
+    return FNLH_OK;
+  }
+  if (param == FNLH_TUNE_LANES_PER_ROW) {
+    if (value != 0 && value != 1 && value != 2 && value != 4)
+      return set_err(c, FNLH_E_ARG, "tune: lanes per row must be 0, 1, 2 or 4");
+    c->lanes_per_row = value;
+    return FNLH_OK;
+  }
+  return set_err(c, FNLH_E_ARG, "tune: unknown parameter");
+}
+
 int fnlh_stats_enable(fnlh_ctx c, int32_t on) {
   if (!c) return FNLH_E_ARG;
   if (on) {
@@ -793,7 +995,9 @@ int fnlh_stats_enable(fnlh_ctx c, int32_t on) {
       c->st_n[k] = 0;
     }
   }
+  if (on < 0) return set_err(c, FNLH_E_ARG, "stats_enable: period must be >= 0");
   c->stats_on = on != 0;
+  c->stats_period = on > 0 ? on : 1;
   return FNLH_OK;
 }
 

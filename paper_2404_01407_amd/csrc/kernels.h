@@ -8,6 +8,7 @@ namespace fnlh {
 
 constexpr int kMaxBatch = 16;  // systems handled by one launch
 constexpr int64_t kDinvTileReals = 72 * 64;  // one tile of complex 6x6 inverses
+constexpr int kPartialSlots = 4;             // norm partials per (system, tile): one per wave
 
 // Per-system solver state kept on the device so stop decisions need no host round trip.
 struct SysState {
@@ -59,8 +60,11 @@ struct DevFlow {
 
 struct SweepCfg {
   int storage = kF64;
-  int spw = 4;  // systems per workgroup (wave per system)
+  int spw = 0;            // systems per lane (1, 2, 4); 0 = automatic
+  int lanes_per_row = 0;  // two-colour pass: lanes sharing a row (1, 2, 4); 0 = automatic
+  bool pivot = true;      // first-colour solve pivots (false: diagonal blocks are dominant)
 };
+int rb_slots(const SweepCfg& c, int n);  // norm partial slots per tile of the two-colour pass
 
 // assembly / raw blocks
 void launch_assemble(int storage, const DevPattern& p, const DevFlow& f, void* offd, void* diag, hipStream_t s);
@@ -71,49 +75,53 @@ void launch_get_blocks(int storage, const DevPattern& p, int64_t N, int64_t E, c
                        const int64_t* edge_ent, const void* offd, const void* diag, double* diag_user,
                        double* offd_user, hipStream_t s);
 
+// *flag = 0 if some diagonal block is not strictly diagonally dominant by rows
+void launch_check_dominance(int storage, const DevPattern& p, const void* diag, int* flag, hipStream_t s);
+
 // factorisation of one colour (tiles [t0, t0+nt), rows below cstart are lower)
 void launch_factor(int storage, bool dilu, const DevPattern& p, const void* offd, const void* diag, void* dinv,
                    int64_t dinv_stride, const SysBatch& sb, int64_t t0, int64_t nt, int64_t cstart, int* err,
                    hipStream_t s);
 
 // sweeps; TV = double for F64 storage, float otherwise
+// Vectors: internal layout [NP][ns][12], ns = systems of the solve, slot = vslot.
 void launch_rb_pass(const SweepCfg& c, bool update, const DevPattern& p, const void* offd, const void* diag,
-                    const void* dinv, int64_t dinv_stride, void* x, const void* b, const SysBatch& sb,
+                    const void* dinv, int64_t dinv_stride, void* x, const void* b, int ns, const SysBatch& sb,
                     const SysState* st, double* partial, int64_t t0, int64_t nt, hipStream_t s);
 void launch_fwd(const SweepCfg& c, bool last, const DevPattern& p, const void* offd, const void* diag,
-                const void* dinv, int64_t dinv_stride, void* x, const void* b, void* y, const SysBatch& sb,
+                const void* dinv, int64_t dinv_stride, void* x, const void* b, void* y, int ns, const SysBatch& sb,
                 const SysState* st, double* partial, int64_t t0, int64_t nt, int64_t cstart, hipStream_t s);
 void launch_bwd(const SweepCfg& c, const DevPattern& p, const void* offd, const void* dinv, int64_t dinv_stride,
-                void* x, void* y, const SysBatch& sb, const SysState* st, int64_t t0, int64_t nt, int64_t cend,
-                hipStream_t s);
+                void* x, void* y, int ns, const SysBatch& sb, const SysState* st, int64_t t0, int64_t nt,
+                int64_t cend, hipStream_t s);
 void launch_jacobi(const SweepCfg& c, const DevPattern& p, const void* offd, const void* diag, const void* dinv,
-                   int64_t dinv_stride, const void* x, const void* b, void* y, const SysBatch& sb,
+                   int64_t dinv_stride, const void* x, const void* b, void* y, int ns, const SysBatch& sb,
                    const SysState* st, double* partial, hipStream_t s);
-void launch_axpy_y(int storage, const DevPattern& p, void* x, const void* y, const SysBatch& sb,
+void launch_axpy_y(int storage, const DevPattern& p, void* x, const void* y, int ns, const SysBatch& sb,
                    const SysState* st, hipStream_t s);
 
 // residual norms -> state.  modes: 0 init (limit = max_sweeps), 1 sweep with a valid
 // norm, 2 sweep without a norm, 3 final (record only), 4 outer FP64 correction test
 enum { kReduceInit = 0, kReduceSweep = 1, kReduceSweepNoNorm = 2, kReduceFinal = 3, kReduceOuter = 4 };
-void launch_reduce(const SysBatch& sb, const double* partial, int64_t n_tiles, int64_t t0, int64_t nt,
+void launch_reduce(const SysBatch& sb, const double* partial, int64_t n_tiles, int64_t t0, int64_t nt, int slots,
                    SysState* st, int mode, double rtol, double div_factor, int max_sweeps, hipStream_t s);
 
 // FP64 residual r = b - K_s x.  stored: blocks of the given storage upcast; mfree: Rusanov
 // recomputed from the FP64 state.  r may be null.
 void launch_resid_stored(int storage, const DevPattern& p, const void* offd, const void* diag, const double* x,
-                         const double* b, double* r, const SysBatch& sb, double* partial, hipStream_t s);
-void launch_resid_mfree(const DevPattern& p, const DevFlow& f, const double* x, const double* b, double* r,
+                         const double* b, double* r, int ns, const SysBatch& sb, double* partial, hipStream_t s);
+void launch_resid_mfree(const DevPattern& p, const DevFlow& f, const double* x, const double* b, double* r, int ns,
                         const SysBatch& sb, double* partial, hipStream_t s);
 
-// vectors
+// vectors: user [N][width] of one system <-> internal [NP][ns][width] slot vs
 void launch_to_internal(const DevPattern& p, const int32_t* iperm, const double* user, double* internal, int width,
-                        hipStream_t s);
+                        int ns, int vs, hipStream_t s);
 void launch_to_user(const DevPattern& p, const int32_t* iperm, const double* internal, double* user, int width,
-                    hipStream_t s);
-void launch_to_f32(const DevPattern& p, const double* r64, float* rhs32, float* d32, const SysBatch& sb,
+                    int ns, int vs, hipStream_t s);
+void launch_to_f32(const DevPattern& p, const double* r64, float* rhs32, float* d32, int ns, const SysBatch& sb,
                    const SysState* outer, hipStream_t s);
-void launch_add_f32(const DevPattern& p, double* x64, const float* d32, const SysBatch& sb, const SysState* outer,
-                    hipStream_t s);
+void launch_add_f32(const DevPattern& p, double* x64, const float* d32, int ns, const SysBatch& sb,
+                    const SysState* outer, hipStream_t s);
 void launch_inner_init(const SysBatch& sb, const SysState* outer, SysState* inner, int max_sweeps, hipStream_t s);
 void launch_outer_update(const SysBatch& sb, const SysState* inner, SysState* outer, hipStream_t s);
 void launch_fill_zero(void* p, size_t bytes, hipStream_t s);

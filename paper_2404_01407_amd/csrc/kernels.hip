@@ -55,108 +55,328 @@ template <typename A> __device__ inline double norm2_12(const A (&v)[12]) {
 }
 
 // ================================================================ sweeps
-// Two-colour fused pass.  With colours C0 (first) and C1, the DILU-Richardson step
-//   forward:  y = Dt^-1 (r - L y),  backward: z = y - Dt^-1 U z,  x += z
-// satisfies, row by row,
-//   C0 rows:  x_i <- Dt_i^-1 (b_i - sum_k K_ik x_k)          (Dt_i = D_i on C0)
-//   C1 rows:  x_k <- x_k + Dt_k^-1 (b_k - D_k x_k - sum_i K_ki x_i)
-// so one step = [C1 pass, C0 pass] after an initial C0 pass, each block read once per
-// step, and the C1 pass accumulates ||b - K_s x||^2 of the previous iterate (its C0
-// residual is zero).  UPDATE = C1 form, !UPDATE = C0 form.
-template <typename TB, bool UPDATE>
-__global__ void __launch_bounds__(256) k_rb_pass(DevPattern p, const TB* __restrict__ offd,
-                                                 const TB* __restrict__ diag,
-                                                 const typename TV_of<TB>::T* __restrict__ dinv, int64_t dstride,
-                                                 typename TV_of<TB>::T* __restrict__ x,
-                                                 const typename TV_of<TB>::T* __restrict__ b, SysBatch sb,
-                                                 const SysState* __restrict__ st, double* __restrict__ partial,
-                                                 int64_t t0, int64_t nt, int spw) {
-  using A = typename TV_of<TB>::T;
-  int64_t tile;
-  int grp;
-  const int ng = (sb.n + spw - 1) / spw;
-  if (!map_tile(nt, ng, tile, grp)) return;
-  tile += t0;
-  const int lane = threadIdx.x & 63;
-  const int k = grp * spw + (int)(threadIdx.x >> 6);
-  if (k >= sb.n) return;
-  const int vs = sb.vslot[k];
-  const int act = st[vs].active, pen = st[vs].pending;
-  if (UPDATE ? (!act || pen) : !act) return;
-  const int64_t row = tile * kLanes + lane;
-  const bool valid = lane < p.tile_nrows[tile];
-  A* xs = x + (size_t)vs * p.NP * 12;
-  const A* bs = b + (size_t)vs * p.NP * 12;
-  A acc[12];
-  load_vec(bs + row * 12, acc);
-  A xi[12];
-  if (UPDATE) {
-    load_vec(xs + row * 12, xi);
-    A d[36];
-    load_block(diag + tile * slot_elems<TB>(), lane, d);
-    sub_diag_shift(acc, d, (A)shift_w(p, sb.orow[k], row), xi);
+// Internal vectors interleave the systems of a solve per row, [row][ns][12], so the P
+// systems a lane carries sit in one contiguous run of P*12 values: a lane loads each
+// block once and applies it to all P systems.  A workgroup handles one tile (64 rows)
+// with ceil(nb / P) waves.
+
+// The systems of one wave: batch entries w*P .. w*P+P-1.
+template <int P> struct WaveSys {
+  int vs[P];
+  int orow[P];
+  int ds[P];
+  bool run[P];
+};
+
+// norm_pass selects the flag test: a pass that accumulates the residual norm runs
+// only for systems not yet pending; the other passes run for every active system.
+template <int P>
+__device__ inline bool wave_systems(const SysBatch& sb, const SysState* __restrict__ st, int w, bool norm_pass,
+                                    WaveSys<P>& W) {
+  bool any = false;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int k = w * P + j;
+    W.run[j] = false;
+    W.vs[j] = 0;
+    W.orow[j] = 0;
+    W.ds[j] = 0;
+    if (k < sb.n) {
+      W.vs[j] = sb.vslot[k];
+      W.orow[j] = sb.orow[k];
+      W.ds[j] = sb.dslot[k];
+      const int act = st[W.vs[j]].active, pen = st[W.vs[j]].pending;
+      W.run[j] = norm_pass ? (act && !pen) : (act != 0);
+      any |= W.run[j];
+    }
   }
+  return any;
+}
+
+// acc[j] -= sum over the tile's slots of K_ik x_k (x of system j), blocks loaded once
+template <typename TB, typename A, int P>
+__device__ inline void gather_offd(const DevPattern& p, const TB* __restrict__ offd, const A* __restrict__ x, int ns,
+                                   int64_t tile, int lane, const WaveSys<P>& W, A (&acc)[P][12]) {
   const int w = p.tile_width[tile];
   const int64_t s0 = p.tile_slot0[tile];
-  for (int q = 0; q < w; ++q) {
+  auto body = [&](int q) {
     const int64_t slot = s0 + q;
     const int nb = p.ent_nbr[slot * kLanes + lane];
     A kb[36];
     load_block(offd + slot * slot_elems<TB>(), lane, kb);
-    A xn[12];
-    load_vec(xs + (int64_t)nb * 12, xn);
-    sub_kx(acc, kb, xn);
-  }
-  if (UPDATE) {
-    double n2 = wave_sum(valid ? norm2_12(acc) : 0.0);
-    if (lane == 0) partial[(int64_t)vs * p.n_tiles + tile] = n2;
-  }
-  A y[12];
-  apply_dinv(dinv + (int64_t)sb.dslot[k] * dstride + tile * kDinvTile, lane, acc, y);
-  if (valid) {
-    if (UPDATE) {
+    const A* xr = x + (int64_t)nb * ns * 12;
 #pragma unroll
-      for (int i = 0; i < 12; ++i) y[i] += xi[i];
+    for (int j = 0; j < P; ++j) {
+      if (!W.run[j]) continue;
+      A xn[12];
+      load_vec(xr + W.vs[j] * 12, xn);
+      sub_kx(acc[j], kb, xn);
     }
-    store_vec(xs + row * 12, y);
+  };
+  if (w == 6) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) body(q);
+  } else {
+    for (int q = 0; q < w; ++q) body(q);
+  }
+}
+
+// Solve (Kd + i w I) y = r in place (r -> y) for a real 6x6 Kd: complex Gaussian
+// elimination, static indexing (registers only).  PIVOT: partial pivoting; without it
+// the caller guarantees Kd is strictly diagonally dominant by rows, which the shift
+// preserves and elimination keeps (Schur complements stay dominant, pivots nonzero).
+template <bool PIVOT, typename A>
+__device__ inline void csolve6_shift(const A (&kd)[36], A w, A (&r)[12]) {
+  A mr[36], mi[36], ivr[6], ivi[6];
+#pragma unroll
+  for (int c = 0; c < 36; ++c) {
+    mr[c] = kd[c];
+    mi[c] = 0;
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) mi[7 * i] = w;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    if (PIVOT) {
+      A best = mr[7 * k] * mr[7 * k] + mi[7 * k] * mi[7 * k];
+      int pv = k;
+#pragma unroll
+      for (int i = k + 1; i < 6; ++i) {
+        const A m = mr[6 * i + k] * mr[6 * i + k] + mi[6 * i + k] * mi[6 * i + k];
+        if (m > best) {
+          best = m;
+          pv = i;
+        }
+      }
+#pragma unroll
+      for (int i = k + 1; i < 6; ++i) {
+        const bool sw = pv == i;
+#pragma unroll
+        for (int c = k; c < 6; ++c) {
+          const A ar = mr[6 * k + c], ai = mi[6 * k + c], br = mr[6 * i + c], bi = mi[6 * i + c];
+          mr[6 * k + c] = sw ? br : ar;
+          mi[6 * k + c] = sw ? bi : ai;
+          mr[6 * i + c] = sw ? ar : br;
+          mi[6 * i + c] = sw ? ai : bi;
+        }
+        const A xr = r[2 * k], xi = r[2 * k + 1], yr = r[2 * i], yi = r[2 * i + 1];
+        r[2 * k] = sw ? yr : xr;
+        r[2 * k + 1] = sw ? yi : xi;
+        r[2 * i] = sw ? xr : yr;
+        r[2 * i + 1] = sw ? xi : yi;
+      }
+    }
+    const A pr = mr[7 * k], pi = mi[7 * k];
+    const A rden = (A)1 / (pr * pr + pi * pi);
+    ivr[k] = pr * rden;
+    ivi[k] = -pi * rden;
+#pragma unroll
+    for (int i = k + 1; i < 6; ++i) {
+      const A ar = mr[6 * i + k], ai = mi[6 * i + k];
+      const A fr = ar * ivr[k] - ai * ivi[k], fi = ar * ivi[k] + ai * ivr[k];
+#pragma unroll
+      for (int c = k + 1; c < 6; ++c) {
+        const A br = mr[6 * k + c], bi = mi[6 * k + c];
+        mr[6 * i + c] -= fr * br - fi * bi;
+        mi[6 * i + c] -= fr * bi + fi * br;
+      }
+      r[2 * i] -= fr * r[2 * k] - fi * r[2 * k + 1];
+      r[2 * i + 1] -= fr * r[2 * k + 1] + fi * r[2 * k];
+    }
+  }
+#pragma unroll
+  for (int k = 5; k >= 0; --k) {
+    A sr = r[2 * k], si = r[2 * k + 1];
+#pragma unroll
+    for (int c = k + 1; c < 6; ++c) {
+      sr -= mr[6 * k + c] * r[2 * c] - mi[6 * k + c] * r[2 * c + 1];
+      si -= mr[6 * k + c] * r[2 * c + 1] + mi[6 * k + c] * r[2 * c];
+    }
+    r[2 * k] = sr * ivr[k] - si * ivi[k];
+    r[2 * k + 1] = sr * ivi[k] + si * ivr[k];
+  }
+}
+
+// Strict row diagonal dominance of every stored diagonal block (valid rows); clears
+// *flag (vector store) when a block is not dominant.
+template <typename TB>
+__global__ void k_check_dominance(DevPattern p, const TB* __restrict__ diag, int* __restrict__ flag) {
+  const int64_t tile = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (lane >= p.tile_nrows[tile]) return;
+  const TB* d = diag + tile * slot_elems<TB>();
+  bool ok = true;
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    double off = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+      if (c != r) off += fabs(load_entry_f64<TB>(d, 6 * r + c, lane));
+    ok &= fabs(load_entry_f64<TB>(d, 7 * r, lane)) > off;
+  }
+  if (!ok) *flag = 0;
+}
+
+// Two-colour fused pass.  With colours C0 (first) and C1, the DILU-Richardson step
+//   forward:  y = Dt^-1 (r - L y),  backward: z = y - Dt^-1 U z,  x += z
+// satisfies, row by row,
+//   C0 rows:  x_i <- (K_ii + i w_i I)^-1 (b_i - sum_k K_ik x_k)          (Dt_i = D_i on C0)
+//   C1 rows:  x_k <- x_k + Dt_k^-1 (b_k - (K_kk + i w_k I) x_k - sum_i K_ki x_i)
+// so one step = [C1 pass, C0 pass] after an initial C0 pass, each block read once per
+// step, and the C1 pass accumulates ||b - K_s x||^2 of the previous iterate (its C0
+// residual is zero).  The C0 pass solves with the shifted diagonal block directly
+// (no per-system factor read); the C1 pass applies the stored Dt^-1.
+//
+// Lane mapping: SW lanes share a row (lane = row_in_wave * SW + s), each carrying P
+// systems (batch entries s, s+SW, ...).  The SW lanes of a row load the same block
+// address (one fetch per instruction), and their vector records are adjacent in the
+// interleaved layout.  A tile of 64 rows takes SW waves of 64/SW rows each.
+template <typename TB, int SW, int P, bool UPDATE, bool PIVOT>
+__global__ void __launch_bounds__(256) k_rb_pass(DevPattern p, const TB* __restrict__ offd,
+                                                 const TB* __restrict__ diag,
+                                                 const typename TV_of<TB>::T* __restrict__ dinv, int64_t dstride,
+                                                 typename TV_of<TB>::T* __restrict__ x,
+                                                 const typename TV_of<TB>::T* __restrict__ b, int ns, SysBatch sb,
+                                                 const SysState* __restrict__ st, double* __restrict__ partial,
+                                                 int64_t t0, int64_t nt) {
+  using A = typename TV_of<TB>::T;
+  int64_t tile;
+  int grp;
+  if (!map_tile(nt, 1, tile, grp)) return;
+  tile += t0;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int sidx = lane % SW;
+  const int rl = w * (kLanes / SW) + lane / SW;  // row within the tile
+  const int64_t row = tile * kLanes + rl;
+  const bool valid = rl < p.tile_nrows[tile];
+  int vs[P], orow[P], ds[P];
+  bool run[P];
+  bool any = false;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int k = j * SW + sidx;
+    run[j] = false;
+    vs[j] = orow[j] = ds[j] = 0;
+    if (k < sb.n) {
+      vs[j] = sb.vslot[k];
+      orow[j] = sb.orow[k];
+      ds[j] = sb.dslot[k];
+      const int act = st[vs[j]].active, pen = st[vs[j]].pending;
+      run[j] = UPDATE ? (act && !pen) : (act != 0);
+      any |= run[j];
+    }
+  }
+  if (!__any(any)) return;
+  const int64_t rb = row * ns * 12;
+  A acc[P][12];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc[j][i] = 0;
+    if (run[j]) load_vec(b + rb + vs[j] * 12, acc[j]);
+  }
+  A d[36];
+  load_block(diag + tile * slot_elems<TB>(), rl, d);
+  if (UPDATE) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      if (!run[j]) continue;
+      A xi[12];
+      load_vec(x + rb + vs[j] * 12, xi);
+      sub_diag_shift(acc[j], d, (A)shift_w(p, orow[j], row), xi);
+    }
+  }
+  {
+    const int wd = p.tile_width[tile];
+    const int64_t s0 = p.tile_slot0[tile];
+    auto body = [&](int q) {
+      const int64_t slot = s0 + q;
+      const int nb = p.ent_nbr[slot * kLanes + rl];
+      A kb[36];
+      load_block(offd + slot * slot_elems<TB>(), rl, kb);
+      const A* xr = x + (int64_t)nb * ns * 12;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        if (!run[j]) continue;
+        A xn[12];
+        load_vec(xr + vs[j] * 12, xn);
+        sub_kx(acc[j], kb, xn);
+      }
+    };
+    if (wd == 6) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) body(q);
+    } else {
+      for (int q = 0; q < wd; ++q) body(q);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    if (UPDATE) {
+      double n2 = (valid && run[j]) ? norm2_12(acc[j]) : 0.0;
+#pragma unroll
+      for (int o = 32; o >= SW; o >>= 1) n2 += __shfl_xor(n2, o, 64);
+      if (lane < SW && j * SW + lane < sb.n && run[j])
+        partial[((int64_t)vs[j] * p.n_tiles + tile) * kPartialSlots + w] = n2;
+    }
+    if (!run[j]) continue;
+    if (UPDATE) {
+      A y[12];
+      apply_dinv(dinv + (int64_t)ds[j] * dstride + tile * kDinvTile, rl, acc[j], y);
+      if (valid) {
+        A xi[12];
+        load_vec(x + rb + vs[j] * 12, xi);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) y[i] += xi[i];
+        store_vec(x + rb + vs[j] * 12, y);
+      }
+    } else {
+      if (valid) {
+        csolve6_shift<PIVOT>(d, (A)shift_w(p, orow[j], row), acc[j]);
+        store_vec(x + rb + vs[j] * 12, acc[j]);
+      }
+    }
   }
 }
 
 // General colouring, forward pass of colour c (rows of lower colours are < cstart):
 //   r_i = b_i - (K_ii + i w) x_i - sum_k K_ik x_k      (accumulated into ||r||^2)
 //   y_i = Dt_i^-1 (r_i - sum_{k lower} K_ik y_k);  LAST colour: x_i += y_i (z = y there)
-template <typename TB, bool LAST>
+template <typename TB, int P, bool LAST>
 __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict__ offd, const TB* __restrict__ diag,
                                              const typename TV_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                              typename TV_of<TB>::T* __restrict__ x,
                                              const typename TV_of<TB>::T* __restrict__ b,
-                                             typename TV_of<TB>::T* __restrict__ y, SysBatch sb,
+                                             typename TV_of<TB>::T* __restrict__ y, int ns, SysBatch sb,
                                              const SysState* __restrict__ st, double* __restrict__ partial,
-                                             int64_t t0, int64_t nt, int64_t cstart, int spw) {
+                                             int64_t t0, int64_t nt, int64_t cstart) {
   using A = typename TV_of<TB>::T;
   int64_t tile;
   int grp;
-  const int ng = (sb.n + spw - 1) / spw;
-  if (!map_tile(nt, ng, tile, grp)) return;
+  if (!map_tile(nt, 1, tile, grp)) return;
   tile += t0;
   const int lane = threadIdx.x & 63;
-  const int k = grp * spw + (int)(threadIdx.x >> 6);
-  if (k >= sb.n) return;
-  const int vs = sb.vslot[k];
-  if (!st[vs].active || st[vs].pending) return;
+  WaveSys<P> W;
+  if (!wave_systems<P>(sb, st, threadIdx.x >> 6, true, W)) return;
   const int64_t row = tile * kLanes + lane;
   const bool valid = lane < p.tile_nrows[tile];
-  const size_t vo = (size_t)vs * p.NP * 12;
-  A r[12], t[12], xi[12];
-  load_vec(b + vo + row * 12, r);
-  load_vec(x + vo + row * 12, xi);
+  const int64_t rb = row * ns * 12;
+  A r[P][12], t[P][12];
   {
     A d[36];
     load_block(diag + tile * slot_elems<TB>(), lane, d);
-    sub_diag_shift(r, d, (A)shift_w(p, sb.orow[k], row), xi);
-  }
 #pragma unroll
-  for (int i = 0; i < 12; ++i) t[i] = 0;
+    for (int j = 0; j < P; ++j) {
+#pragma unroll
+      for (int i = 0; i < 12; ++i) t[j][i] = 0;
+      if (!W.run[j]) continue;
+      A xi[12];
+      load_vec(b + rb + W.vs[j] * 12, r[j]);
+      load_vec(x + rb + W.vs[j] * 12, xi);
+      sub_diag_shift(r[j], d, (A)shift_w(p, W.orow[j], row), xi);
+    }
+  }
   const int w = p.tile_width[tile];
   const int64_t s0 = p.tile_slot0[tile];
   for (int q = 0; q < w; ++q) {
@@ -164,56 +384,65 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
     const int nb = p.ent_nbr[slot * kLanes + lane];
     A kb[36];
     load_block(offd + slot * slot_elems<TB>(), lane, kb);
-    A v[12];
-    load_vec(x + vo + (int64_t)nb * 12, v);
-    sub_kx(r, kb, v);
-    if (nb < cstart) {
-      load_vec(y + vo + (int64_t)nb * 12, v);
-      sub_kx(t, kb, v);
+    const int64_t nbo = (int64_t)nb * ns * 12;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      if (!W.run[j]) continue;
+      A v[12];
+      load_vec(x + nbo + W.vs[j] * 12, v);
+      sub_kx(r[j], kb, v);
+      if (nb < cstart) {
+        load_vec(y + nbo + W.vs[j] * 12, v);
+        sub_kx(t[j], kb, v);
+      }
     }
   }
-  double n2 = wave_sum(valid ? norm2_12(r) : 0.0);
-  if (lane == 0) partial[(int64_t)vs * p.n_tiles + tile] = n2;
 #pragma unroll
-  for (int i = 0; i < 12; ++i) t[i] += r[i];
-  A yi[12];
-  apply_dinv(dinv + (int64_t)sb.dslot[k] * dstride + tile * kDinvTile, lane, t, yi);
-  if (valid) {
-    store_vec(y + vo + row * 12, yi);
-    if (LAST) {
+  for (int j = 0; j < P; ++j) {
+    if (!W.run[j]) continue;
+    const double n2 = wave_sum(valid ? norm2_12(r[j]) : 0.0);
+    if (lane == 0) partial[((int64_t)W.vs[j] * p.n_tiles + tile) * kPartialSlots] = n2;
 #pragma unroll
-      for (int i = 0; i < 12; ++i) xi[i] += yi[i];
-      store_vec(x + vo + row * 12, xi);
+    for (int i = 0; i < 12; ++i) t[j][i] += r[j][i];
+    A yi[12];
+    apply_dinv(dinv + (int64_t)W.ds[j] * dstride + tile * kDinvTile, lane, t[j], yi);
+    if (valid) {
+      store_vec(y + rb + W.vs[j] * 12, yi);
+      if (LAST) {
+        A xi[12];
+        load_vec(x + rb + W.vs[j] * 12, xi);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) xi[i] += yi[i];
+        store_vec(x + rb + W.vs[j] * 12, xi);
+      }
     }
   }
 }
 
 // General colouring, backward pass of colour c (rows of higher colours are >= cend and
 // already hold z in y):  z_i = y_i - Dt_i^-1 sum_{k upper} K_ik z_k;  x_i += z_i; y_i <- z_i
-template <typename TB>
+template <typename TB, int P>
 __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict__ offd,
                                              const typename TV_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                              typename TV_of<TB>::T* __restrict__ x,
-                                             typename TV_of<TB>::T* __restrict__ y, SysBatch sb,
-                                             const SysState* __restrict__ st, int64_t t0, int64_t nt, int64_t cend,
-                                             int spw) {
+                                             typename TV_of<TB>::T* __restrict__ y, int ns, SysBatch sb,
+                                             const SysState* __restrict__ st, int64_t t0, int64_t nt, int64_t cend) {
   using A = typename TV_of<TB>::T;
   int64_t tile;
   int grp;
-  const int ng = (sb.n + spw - 1) / spw;
-  if (!map_tile(nt, ng, tile, grp)) return;
+  if (!map_tile(nt, 1, tile, grp)) return;
   tile += t0;
   const int lane = threadIdx.x & 63;
-  const int k = grp * spw + (int)(threadIdx.x >> 6);
-  if (k >= sb.n) return;
-  const int vs = sb.vslot[k];
-  if (!st[vs].active) return;
+  WaveSys<P> W;
+  if (!wave_systems<P>(sb, st, threadIdx.x >> 6, false, W)) return;
   const int64_t row = tile * kLanes + lane;
   const bool valid = lane < p.tile_nrows[tile];
-  const size_t vo = (size_t)vs * p.NP * 12;
-  A t[12];
+  const int64_t rb = row * ns * 12;
+  A t[P][12];
 #pragma unroll
-  for (int i = 0; i < 12; ++i) t[i] = 0;
+  for (int j = 0; j < P; ++j)
+#pragma unroll
+    for (int i = 0; i < 12; ++i) t[j][i] = 0;
   const int w = p.tile_width[tile];
   const int64_t s0 = p.tile_slot0[tile];
   for (int q = 0; q < w; ++q) {
@@ -222,100 +451,105 @@ __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict_
     if (nb >= cend) {
       A kb[36];
       load_block(offd + slot * slot_elems<TB>(), lane, kb);
-      A v[12];
-      load_vec(y + vo + (int64_t)nb * 12, v);
-      sub_kx(t, kb, v);
+      const int64_t nbo = (int64_t)nb * ns * 12;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        if (!W.run[j]) continue;
+        A v[12];
+        load_vec(y + nbo + W.vs[j] * 12, v);
+        sub_kx(t[j], kb, v);
+      }
     }
   }
-  A z[12];
-  apply_dinv(dinv + (int64_t)sb.dslot[k] * dstride + tile * kDinvTile, lane, t, z);
-  if (valid) {
-    A yi[12], xi[12];
-    load_vec(y + vo + row * 12, yi);
-    load_vec(x + vo + row * 12, xi);
 #pragma unroll
-    for (int i = 0; i < 12; ++i) {
-      z[i] += yi[i];
-      xi[i] += z[i];
+  for (int j = 0; j < P; ++j) {
+    if (!W.run[j]) continue;
+    A z[12];
+    apply_dinv(dinv + (int64_t)W.ds[j] * dstride + tile * kDinvTile, lane, t[j], z);
+    if (valid) {
+      A yi[12], xi[12];
+      load_vec(y + rb + W.vs[j] * 12, yi);
+      load_vec(x + rb + W.vs[j] * 12, xi);
+#pragma unroll
+      for (int i = 0; i < 12; ++i) {
+        z[i] += yi[i];
+        xi[i] += z[i];
+      }
+      store_vec(y + rb + W.vs[j] * 12, z);
+      store_vec(x + rb + W.vs[j] * 12, xi);
     }
-    store_vec(y + vo + row * 12, z);
-    store_vec(x + vo + row * 12, xi);
   }
 }
 
 // Block Jacobi (the paper's explicit, point-by-point inversion): y = D_s^-1 (b - K_s x)
 // over all rows, then x += y.
-template <typename TB>
+template <typename TB, int P>
 __global__ void __launch_bounds__(256) k_jacobi(DevPattern p, const TB* __restrict__ offd,
                                                 const TB* __restrict__ diag,
                                                 const typename TV_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                                 const typename TV_of<TB>::T* __restrict__ x,
                                                 const typename TV_of<TB>::T* __restrict__ b,
-                                                typename TV_of<TB>::T* __restrict__ y, SysBatch sb,
-                                                const SysState* __restrict__ st, double* __restrict__ partial,
-                                                int spw) {
+                                                typename TV_of<TB>::T* __restrict__ y, int ns, SysBatch sb,
+                                                const SysState* __restrict__ st, double* __restrict__ partial) {
   using A = typename TV_of<TB>::T;
   int64_t tile;
   int grp;
-  const int ng = (sb.n + spw - 1) / spw;
-  if (!map_tile(p.n_tiles, ng, tile, grp)) return;
+  if (!map_tile(p.n_tiles, 1, tile, grp)) return;
   const int lane = threadIdx.x & 63;
-  const int k = grp * spw + (int)(threadIdx.x >> 6);
-  if (k >= sb.n) return;
-  const int vs = sb.vslot[k];
-  if (!st[vs].active || st[vs].pending) return;
+  WaveSys<P> W;
+  if (!wave_systems<P>(sb, st, threadIdx.x >> 6, true, W)) return;
   const int64_t row = tile * kLanes + lane;
   const bool valid = lane < p.tile_nrows[tile];
-  const size_t vo = (size_t)vs * p.NP * 12;
-  A r[12], xi[12];
-  load_vec(b + vo + row * 12, r);
-  load_vec(x + vo + row * 12, xi);
+  const int64_t rb = row * ns * 12;
+  A r[P][12];
   {
     A d[36];
     load_block(diag + tile * slot_elems<TB>(), lane, d);
-    sub_diag_shift(r, d, (A)shift_w(p, sb.orow[k], row), xi);
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      if (!W.run[j]) continue;
+      A xi[12];
+      load_vec(b + rb + W.vs[j] * 12, r[j]);
+      load_vec(x + rb + W.vs[j] * 12, xi);
+      sub_diag_shift(r[j], d, (A)shift_w(p, W.orow[j], row), xi);
+    }
   }
-  const int w = p.tile_width[tile];
-  const int64_t s0 = p.tile_slot0[tile];
-  for (int q = 0; q < w; ++q) {
-    const int64_t slot = s0 + q;
-    const int nb = p.ent_nbr[slot * kLanes + lane];
-    A kb[36];
-    load_block(offd + slot * slot_elems<TB>(), lane, kb);
-    A v[12];
-    load_vec(x + vo + (int64_t)nb * 12, v);
-    sub_kx(r, kb, v);
+  gather_offd<TB, A, P>(p, offd, x, ns, tile, lane, W, r);
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    if (!W.run[j]) continue;
+    const double n2 = wave_sum(valid ? norm2_12(r[j]) : 0.0);
+    if (lane == 0) partial[((int64_t)W.vs[j] * p.n_tiles + tile) * kPartialSlots] = n2;
+    A yi[12];
+    apply_dinv(dinv + (int64_t)W.ds[j] * dstride + tile * kDinvTile, lane, r[j], yi);
+    if (valid) store_vec(y + rb + W.vs[j] * 12, yi);
   }
-  double n2 = wave_sum(valid ? norm2_12(r) : 0.0);
-  if (lane == 0) partial[(int64_t)vs * p.n_tiles + tile] = n2;
-  A yi[12];
-  apply_dinv(dinv + (int64_t)sb.dslot[k] * dstride + tile * kDinvTile, lane, r, yi);
-  if (valid) store_vec(y + vo + row * 12, yi);
 }
 
+// x += y for the active systems (interleaved layout), also used for the FP64 update.
 template <typename A>
-__global__ void k_axpy_y(int64_t NP, A* __restrict__ x, const A* __restrict__ y, SysBatch sb,
+__global__ void k_axpy_y(int64_t NP, int ns, A* __restrict__ x, const A* __restrict__ y, SysBatch sb,
                          const SysState* __restrict__ st) {
   const int k = blockIdx.y;
   const int vs = sb.vslot[k];
   if (!st[vs].active) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= NP * 12) return;
-  const size_t o = (size_t)vs * NP * 12 + i;
+  const int64_t o = (i / 12) * ns * 12 + vs * 12 + (i % 12);
   x[o] += y[o];
 }
 
 // ================================================================ norm reduction
 __global__ void __launch_bounds__(256) k_reduce(SysBatch sb, const double* __restrict__ partial, int64_t n_tiles,
-                                                int64_t t0, int64_t nt, SysState* __restrict__ st, int mode,
-                                                double rtol2, double div2, int max_sweeps) {
+                                                int64_t t0, int64_t nt, int slots, SysState* __restrict__ st,
+                                                int mode, double rtol2, double div2, int max_sweeps) {
   __shared__ double sh[256];
   const int k = blockIdx.x;
   const int vs = sb.vslot[k];
   double s = 0.0;
   if (mode != kReduceSweepNoNorm) {
-    const double* pp = partial + (int64_t)vs * n_tiles + t0;
-    for (int64_t i = threadIdx.x; i < nt; i += 256) s += pp[i];
+    const double* pp = partial + ((int64_t)vs * n_tiles + t0) * kPartialSlots;
+    for (int64_t i = threadIdx.x; i < nt * slots; i += 256) s += pp[(i / slots) * kPartialSlots + (i % slots)];
   }
   sh[threadIdx.x] = s;
   __syncthreads();
@@ -632,10 +866,11 @@ __global__ void __launch_bounds__(64) k_factor(DevPattern p, const TB* __restric
 }
 
 // ================================================================ FP64 residuals
+// One wave per (tile, system), FP64 vectors in the interleaved layout.
 template <typename TB>
 __global__ void __launch_bounds__(256) k_resid_stored(DevPattern p, const TB* __restrict__ offd,
                                                       const TB* __restrict__ diag, const double* __restrict__ x,
-                                                      const double* __restrict__ b, double* __restrict__ r,
+                                                      const double* __restrict__ b, double* __restrict__ r, int ns,
                                                       SysBatch sb, double* __restrict__ partial, int spw) {
   int64_t tile;
   int grp;
@@ -647,10 +882,10 @@ __global__ void __launch_bounds__(256) k_resid_stored(DevPattern p, const TB* __
   const int vs = sb.vslot[k];
   const int64_t row = tile * kLanes + lane;
   const bool valid = lane < p.tile_nrows[tile];
-  const size_t vo = (size_t)vs * p.NP * 12;
+  const int64_t ro = (row * ns + vs) * 12;
   double acc[12], xi[12];
-  load_vec(b + vo + row * 12, acc);
-  load_vec(x + vo + row * 12, xi);
+  load_vec(b + ro, acc);
+  load_vec(x + ro, xi);
   {
     double d[36];
     load_block(diag + tile * slot_elems<TB>(), lane, d);
@@ -663,16 +898,16 @@ __global__ void __launch_bounds__(256) k_resid_stored(DevPattern p, const TB* __
     const int nb = p.ent_nbr[slot * kLanes + lane];
     double kb[36], v[12];
     load_block(offd + slot * slot_elems<TB>(), lane, kb);
-    load_vec(x + vo + (int64_t)nb * 12, v);
+    load_vec(x + ((int64_t)nb * ns + vs) * 12, v);
     sub_kx(acc, kb, v);
   }
   double n2 = wave_sum(valid ? norm2_12(acc) : 0.0);
-  if (lane == 0) partial[(int64_t)vs * p.n_tiles + tile] = n2;
-  if (r && valid) store_vec(r + vo + row * 12, acc);
+  if (lane == 0) partial[((int64_t)vs * p.n_tiles + tile) * kPartialSlots] = n2;
+  if (r && valid) store_vec(r + ro, acc);
 }
 
 __global__ void __launch_bounds__(256) k_resid_mfree(DevPattern p, DevFlow f, const double* __restrict__ x,
-                                                     const double* __restrict__ b, double* __restrict__ r,
+                                                     const double* __restrict__ b, double* __restrict__ r, int ns,
                                                      SysBatch sb, double* __restrict__ partial, int spw) {
   int64_t tile;
   int grp;
@@ -684,12 +919,12 @@ __global__ void __launch_bounds__(256) k_resid_mfree(DevPattern p, DevFlow f, co
   const int vs = sb.vslot[k];
   const int64_t row = tile * kLanes + lane;
   const bool valid = lane < p.tile_nrows[tile];
-  const size_t vo = (size_t)vs * p.NP * 12;
+  const int64_t ro = (row * ns + vs) * 12;
   double Qi[6] = {1, 0, 0, 0, 2.5, 0};
   if (valid) load_state(f.state + row * 6, Qi);
   double acc[12], xi[12];
-  load_vec(b + vo + row * 12, acc);
-  load_vec(x + vo + row * 12, xi);
+  load_vec(b + ro, acc);
+  load_vec(x + ro, xi);
   double sumS[3] = {0, 0, 0}, lam_sum = 0.0;
   const int w = p.tile_width[tile];
   const int64_t s0 = p.tile_slot0[tile];
@@ -710,7 +945,7 @@ __global__ void __launch_bounds__(256) k_resid_mfree(DevPattern p, DevFlow f, co
     flux_jacobian(Qk, S, Ak);
 #pragma unroll
     for (int c = 0; c < 36; ++c) Ak[c] = 0.5 * Ak[c] - ((c % 7 == 0) ? 0.5 * lam : 0.0);
-    load_vec(x + vo + (int64_t)nb * 12, v);
+    load_vec(x + ((int64_t)nb * ns + vs) * 12, v);
     sub_kx(acc, Ak, v);
   }
   if (valid) {
@@ -736,48 +971,49 @@ __global__ void __launch_bounds__(256) k_resid_mfree(DevPattern p, DevFlow f, co
   for (int c = 0; c < 36; ++c) Ai[c] = f.diag_scale * (0.5 * Ai[c] + ((c % 7 == 0) ? 0.5 * lam_sum : 0.0));
   sub_diag_shift(acc, Ai, shift_w(p, sb.orow[k], row), xi);
   double n2 = wave_sum(valid ? norm2_12(acc) : 0.0);
-  if (lane == 0) partial[(int64_t)vs * p.n_tiles + tile] = n2;
-  if (r && valid) store_vec(r + vo + row * 12, acc);
+  if (lane == 0) partial[((int64_t)vs * p.n_tiles + tile) * kPartialSlots] = n2;
+  if (r && valid) store_vec(r + ro, acc);
 }
 
 // ================================================================ vectors
+// user [N][width] (one system)  <->  internal [NP][ns][width], slot vs
 __global__ void k_to_internal(int64_t NP, const int32_t* __restrict__ iperm, const double* __restrict__ user,
-                              double* __restrict__ internal, int width) {
+                              double* __restrict__ internal, int width, int ns, int vs) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= NP * width) return;
   const int64_t row = t / width;
   const int c = (int)(t % width);
   const int32_t u = iperm[row];
-  internal[t] = u >= 0 ? user[(int64_t)u * width + c] : 0.0;
+  internal[(row * ns + vs) * width + c] = u >= 0 ? user[(int64_t)u * width + c] : 0.0;
 }
 __global__ void k_to_user(int64_t NP, const int32_t* __restrict__ iperm, const double* __restrict__ internal,
-                          double* __restrict__ user, int width) {
+                          double* __restrict__ user, int width, int ns, int vs) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= NP * width) return;
   const int64_t row = t / width;
   const int c = (int)(t % width);
   const int32_t u = iperm[row];
-  if (u >= 0) user[(int64_t)u * width + c] = internal[t];
+  if (u >= 0) user[(int64_t)u * width + c] = internal[(row * ns + vs) * width + c];
 }
-__global__ void k_to_f32(int64_t NP, const double* __restrict__ r64, float* __restrict__ rhs32,
+__global__ void k_to_f32(int64_t NP, int ns, const double* __restrict__ r64, float* __restrict__ rhs32,
                          float* __restrict__ d32, SysBatch sb, const SysState* __restrict__ outer) {
   const int k = blockIdx.y;
   const int vs = sb.vslot[k];
   if (!outer[vs].active) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= NP * 12) return;
-  const size_t o = (size_t)vs * NP * 12 + i;
+  const int64_t o = (i / 12) * ns * 12 + vs * 12 + (i % 12);
   rhs32[o] = (float)r64[o];
   d32[o] = 0.0f;
 }
-__global__ void k_add_f32(int64_t NP, double* __restrict__ x64, const float* __restrict__ d32, SysBatch sb,
+__global__ void k_add_f32(int64_t NP, int ns, double* __restrict__ x64, const float* __restrict__ d32, SysBatch sb,
                           const SysState* __restrict__ outer) {
   const int k = blockIdx.y;
   const int vs = sb.vslot[k];
   if (!outer[vs].active) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= NP * 12) return;
-  const size_t o = (size_t)vs * NP * 12 + i;
+  const int64_t o = (i / 12) * ns * 12 + vs * 12 + (i % 12);
   x64[o] += (double)d32[o];
 }
 __global__ void k_fill_zero(uint32_t* __restrict__ p, size_t n) {
@@ -807,6 +1043,12 @@ inline int ng_of(const SysBatch& sb, int spw) { return (sb.n + spw - 1) / spw; }
 void launch_assemble(int storage, const DevPattern& p, const DevFlow& f, void* offd, void* diag, hipStream_t s) {
   FNLH_DISPATCH_STORE(storage, {
     hipLaunchKernelGGL((k_assemble<TB>), dim3((unsigned)p.n_tiles), dim3(64), 0, s, p, f, (TB*)offd, (TB*)diag);
+  });
+}
+
+void launch_check_dominance(int storage, const DevPattern& p, const void* diag, int* flag, hipStream_t s) {
+  FNLH_DISPATCH_STORE(storage, {
+    hipLaunchKernelGGL((k_check_dominance<TB>), dim3((unsigned)p.n_tiles), dim3(64), 0, s, p, (const TB*)diag, flag);
   });
 }
 
@@ -850,129 +1092,197 @@ void launch_factor(int storage, bool dilu, const DevPattern& p, const void* offd
   });
 }
 
+// systems per lane: all of a small batch, else 4 (FP32 vectors) / 2 (FP64 vectors)
+inline int lanes_p(const SweepCfg& c, int n) {
+  int P = c.spw > 0 ? c.spw : (c.storage == kF64 ? 2 : 4);
+  if (P > 4) P = 4;
+  if (P >= 4 && n <= 3) P = n <= 2 ? n : 4;
+  if (P == 3) P = 4;
+  return P;
+}
+inline dim3 block_for(int n, int P) {
+  int nw = (n + P - 1) / P;
+  if (nw > 4) nw = 4;
+  return dim3(64 * nw);
+}
+
+#define FNLH_DISPATCH_P(P, BODY)                         \
+  do {                                                   \
+    if ((P) == 1) {                                      \
+      constexpr int PP = 1;                              \
+      BODY;                                              \
+    } else if ((P) == 2) {                               \
+      constexpr int PP = 2;                              \
+      BODY;                                              \
+    } else {                                             \
+      constexpr int PP = 4;                              \
+      BODY;                                              \
+    }                                                    \
+  } while (0)
+
+// lanes per row (SW) and systems per lane (P) of the two-colour pass
+inline void rb_shape(const SweepCfg& c, int n, int& SW, int& P) {
+  SW = c.lanes_per_row;
+  if (SW <= 0) SW = n >= 4 ? 4 : (n >= 2 ? 2 : 1);
+  if (SW != 1 && SW != 2 && SW != 4) SW = 4;
+  P = (n + SW - 1) / SW;
+  if (c.spw > 0 && c.spw > P) P = c.spw;
+  P = P <= 1 ? 1 : (P <= 2 ? 2 : 4);
+}
+int rb_slots(const SweepCfg& c, int n) {
+  int SW, P;
+  rb_shape(c, n, SW, P);
+  return SW;
+}
+
 void launch_rb_pass(const SweepCfg& c, bool update, const DevPattern& p, const void* offd, const void* diag,
-                    const void* dinv, int64_t dinv_stride, void* x, const void* b, const SysBatch& sb,
+                    const void* dinv, int64_t dinv_stride, void* x, const void* b, int ns, const SysBatch& sb,
                     const SysState* st, double* partial, int64_t t0, int64_t nt, hipStream_t s) {
   if (nt <= 0 || sb.n <= 0) return;
-  const int spw = c.spw < sb.n ? c.spw : sb.n;
-  dim3 grid = tile_grid(nt, ng_of(sb, spw));
-  dim3 block(64 * spw);
+  int SW, P;
+  rb_shape(c, sb.n, SW, P);
+  dim3 grid = tile_grid(nt, 1);
+  dim3 block(64 * SW);
+#define FNLH_RB_LAUNCH(SWV)                                                                                     \
+  FNLH_DISPATCH_P(P, {                                                                                          \
+    if (update)                                                                                                 \
+      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, true, true>), grid, block, 0, s, p, (const TB*)offd,           \
+                         (const TB*)diag, (const A*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, st, partial, \
+                         t0, nt);                                                                               \
+    else if (c.pivot)                                                                                           \
+      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, true>), grid, block, 0, s, p, (const TB*)offd,          \
+                         (const TB*)diag, (const A*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, st, partial, \
+                         t0, nt);                                                                               \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, false>), grid, block, 0, s, p, (const TB*)offd,         \
+                         (const TB*)diag, (const A*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, st, partial, \
+                         t0, nt);                                                                               \
+  })
   FNLH_DISPATCH_STORE(c.storage, {
     using A = typename Fmt<TB>::A;
-    if (update)
-      hipLaunchKernelGGL((k_rb_pass<TB, true>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag,
-                         (const A*)dinv, dinv_stride, (A*)x, (const A*)b, sb, st, partial, t0, nt, spw);
+    if (SW == 1)
+      FNLH_RB_LAUNCH(1);
+    else if (SW == 2)
+      FNLH_RB_LAUNCH(2);
     else
-      hipLaunchKernelGGL((k_rb_pass<TB, false>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag,
-                         (const A*)dinv, dinv_stride, (A*)x, (const A*)b, sb, st, partial, t0, nt, spw);
+      FNLH_RB_LAUNCH(4);
   });
+#undef FNLH_RB_LAUNCH
 }
 
 void launch_fwd(const SweepCfg& c, bool last, const DevPattern& p, const void* offd, const void* diag,
-                const void* dinv, int64_t dinv_stride, void* x, const void* b, void* y, const SysBatch& sb,
+                const void* dinv, int64_t dinv_stride, void* x, const void* b, void* y, int ns, const SysBatch& sb,
                 const SysState* st, double* partial, int64_t t0, int64_t nt, int64_t cstart, hipStream_t s) {
   if (nt <= 0 || sb.n <= 0) return;
-  const int spw = c.spw < sb.n ? c.spw : sb.n;
-  dim3 grid = tile_grid(nt, ng_of(sb, spw));
-  dim3 block(64 * spw);
+  const int P = lanes_p(c, sb.n);
+  dim3 grid = tile_grid(nt, 1);
+  dim3 block = block_for(sb.n, P);
   FNLH_DISPATCH_STORE(c.storage, {
     using A = typename Fmt<TB>::A;
-    if (last)
-      hipLaunchKernelGGL((k_fwd<TB, true>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag, (const A*)dinv,
-                         dinv_stride, (A*)x, (const A*)b, (A*)y, sb, st, partial, t0, nt, cstart, spw);
-    else
-      hipLaunchKernelGGL((k_fwd<TB, false>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag, (const A*)dinv,
-                         dinv_stride, (A*)x, (const A*)b, (A*)y, sb, st, partial, t0, nt, cstart, spw);
+    FNLH_DISPATCH_P(P, {
+      if (last)
+        hipLaunchKernelGGL((k_fwd<TB, PP, true>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag,
+                           (const A*)dinv, dinv_stride, (A*)x, (const A*)b, (A*)y, ns, sb, st, partial, t0, nt,
+                           cstart);
+      else
+        hipLaunchKernelGGL((k_fwd<TB, PP, false>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag,
+                           (const A*)dinv, dinv_stride, (A*)x, (const A*)b, (A*)y, ns, sb, st, partial, t0, nt,
+                           cstart);
+    });
   });
 }
 
 void launch_bwd(const SweepCfg& c, const DevPattern& p, const void* offd, const void* dinv, int64_t dinv_stride,
-                void* x, void* y, const SysBatch& sb, const SysState* st, int64_t t0, int64_t nt, int64_t cend,
-                hipStream_t s) {
+                void* x, void* y, int ns, const SysBatch& sb, const SysState* st, int64_t t0, int64_t nt,
+                int64_t cend, hipStream_t s) {
   if (nt <= 0 || sb.n <= 0) return;
-  const int spw = c.spw < sb.n ? c.spw : sb.n;
-  dim3 grid = tile_grid(nt, ng_of(sb, spw));
-  dim3 block(64 * spw);
+  const int P = lanes_p(c, sb.n);
+  dim3 grid = tile_grid(nt, 1);
+  dim3 block = block_for(sb.n, P);
   FNLH_DISPATCH_STORE(c.storage, {
     using A = typename Fmt<TB>::A;
-    hipLaunchKernelGGL((k_bwd<TB>), grid, block, 0, s, p, (const TB*)offd, (const A*)dinv, dinv_stride, (A*)x, (A*)y,
-                       sb, st, t0, nt, cend, spw);
+    FNLH_DISPATCH_P(P, {
+      hipLaunchKernelGGL((k_bwd<TB, PP>), grid, block, 0, s, p, (const TB*)offd, (const A*)dinv, dinv_stride,
+                         (A*)x, (A*)y, ns, sb, st, t0, nt, cend);
+    });
   });
 }
 
 void launch_jacobi(const SweepCfg& c, const DevPattern& p, const void* offd, const void* diag, const void* dinv,
-                   int64_t dinv_stride, const void* x, const void* b, void* y, const SysBatch& sb,
+                   int64_t dinv_stride, const void* x, const void* b, void* y, int ns, const SysBatch& sb,
                    const SysState* st, double* partial, hipStream_t s) {
   if (sb.n <= 0) return;
-  const int spw = c.spw < sb.n ? c.spw : sb.n;
-  dim3 grid = tile_grid(p.n_tiles, ng_of(sb, spw));
-  dim3 block(64 * spw);
+  const int P = lanes_p(c, sb.n);
+  dim3 grid = tile_grid(p.n_tiles, 1);
+  dim3 block = block_for(sb.n, P);
   FNLH_DISPATCH_STORE(c.storage, {
     using A = typename Fmt<TB>::A;
-    hipLaunchKernelGGL((k_jacobi<TB>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag, (const A*)dinv,
-                       dinv_stride, (const A*)x, (const A*)b, (A*)y, sb, st, partial, spw);
+    FNLH_DISPATCH_P(P, {
+      hipLaunchKernelGGL((k_jacobi<TB, PP>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag,
+                         (const A*)dinv, dinv_stride, (const A*)x, (const A*)b, (A*)y, ns, sb, st, partial);
+    });
   });
 }
 
-void launch_axpy_y(int storage, const DevPattern& p, void* x, const void* y, const SysBatch& sb,
+void launch_axpy_y(int storage, const DevPattern& p, void* x, const void* y, int ns, const SysBatch& sb,
                    const SysState* st, hipStream_t s) {
   if (sb.n <= 0) return;
   dim3 grid((unsigned)((p.NP * 12 + 255) / 256), (unsigned)sb.n);
   if (storage == kF64)
-    hipLaunchKernelGGL((k_axpy_y<double>), grid, dim3(256), 0, s, p.NP, (double*)x, (const double*)y, sb, st);
+    hipLaunchKernelGGL((k_axpy_y<double>), grid, dim3(256), 0, s, p.NP, ns, (double*)x, (const double*)y, sb, st);
   else
-    hipLaunchKernelGGL((k_axpy_y<float>), grid, dim3(256), 0, s, p.NP, (float*)x, (const float*)y, sb, st);
+    hipLaunchKernelGGL((k_axpy_y<float>), grid, dim3(256), 0, s, p.NP, ns, (float*)x, (const float*)y, sb, st);
 }
 
-void launch_reduce(const SysBatch& sb, const double* partial, int64_t n_tiles, int64_t t0, int64_t nt, SysState* st,
-                   int mode, double rtol, double div_factor, int max_sweeps, hipStream_t s) {
+void launch_reduce(const SysBatch& sb, const double* partial, int64_t n_tiles, int64_t t0, int64_t nt, int slots,
+                   SysState* st, int mode, double rtol, double div_factor, int max_sweeps, hipStream_t s) {
   if (sb.n <= 0) return;
-  hipLaunchKernelGGL(k_reduce, dim3((unsigned)sb.n), dim3(256), 0, s, sb, partial, n_tiles, t0, nt, st, mode,
+  hipLaunchKernelGGL(k_reduce, dim3((unsigned)sb.n), dim3(256), 0, s, sb, partial, n_tiles, t0, nt, slots, st, mode,
                      rtol * rtol, div_factor * div_factor, max_sweeps);
 }
 
 void launch_resid_stored(int storage, const DevPattern& p, const void* offd, const void* diag, const double* x,
-                         const double* b, double* r, const SysBatch& sb, double* partial, hipStream_t s) {
+                         const double* b, double* r, int ns, const SysBatch& sb, double* partial, hipStream_t s) {
   if (sb.n <= 0) return;
   const int spw = 4 < sb.n ? 4 : sb.n;
   dim3 grid = tile_grid(p.n_tiles, ng_of(sb, spw));
   FNLH_DISPATCH_STORE(storage, {
     hipLaunchKernelGGL((k_resid_stored<TB>), grid, dim3(64 * spw), 0, s, p, (const TB*)offd, (const TB*)diag, x, b,
-                       r, sb, partial, spw);
+                       r, ns, sb, partial, spw);
   });
 }
 
-void launch_resid_mfree(const DevPattern& p, const DevFlow& f, const double* x, const double* b, double* r,
+void launch_resid_mfree(const DevPattern& p, const DevFlow& f, const double* x, const double* b, double* r, int ns,
                         const SysBatch& sb, double* partial, hipStream_t s) {
   if (sb.n <= 0) return;
   const int spw = 4 < sb.n ? 4 : sb.n;
   dim3 grid = tile_grid(p.n_tiles, ng_of(sb, spw));
-  hipLaunchKernelGGL(k_resid_mfree, grid, dim3(64 * spw), 0, s, p, f, x, b, r, sb, partial, spw);
+  hipLaunchKernelGGL(k_resid_mfree, grid, dim3(64 * spw), 0, s, p, f, x, b, r, ns, sb, partial, spw);
 }
 
 void launch_to_internal(const DevPattern& p, const int32_t* iperm, const double* user, double* internal, int width,
-                        hipStream_t s) {
+                        int ns, int vs, hipStream_t s) {
   const int64_t n = p.NP * width;
   hipLaunchKernelGGL(k_to_internal, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p.NP, iperm, user, internal,
-                     width);
+                     width, ns, vs);
 }
 void launch_to_user(const DevPattern& p, const int32_t* iperm, const double* internal, double* user, int width,
-                    hipStream_t s) {
+                    int ns, int vs, hipStream_t s) {
   const int64_t n = p.NP * width;
   hipLaunchKernelGGL(k_to_user, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p.NP, iperm, internal, user,
-                     width);
+                     width, ns, vs);
 }
-void launch_to_f32(const DevPattern& p, const double* r64, float* rhs32, float* d32, const SysBatch& sb,
+void launch_to_f32(const DevPattern& p, const double* r64, float* rhs32, float* d32, int ns, const SysBatch& sb,
                    const SysState* outer, hipStream_t s) {
   if (sb.n <= 0) return;
   dim3 grid((unsigned)((p.NP * 12 + 255) / 256), (unsigned)sb.n);
-  hipLaunchKernelGGL(k_to_f32, grid, dim3(256), 0, s, p.NP, r64, rhs32, d32, sb, outer);
+  hipLaunchKernelGGL(k_to_f32, grid, dim3(256), 0, s, p.NP, ns, r64, rhs32, d32, sb, outer);
 }
-void launch_add_f32(const DevPattern& p, double* x64, const float* d32, const SysBatch& sb, const SysState* outer,
-                    hipStream_t s) {
+void launch_add_f32(const DevPattern& p, double* x64, const float* d32, int ns, const SysBatch& sb,
+                    const SysState* outer, hipStream_t s) {
   if (sb.n <= 0) return;
   dim3 grid((unsigned)((p.NP * 12 + 255) / 256), (unsigned)sb.n);
-  hipLaunchKernelGGL(k_add_f32, grid, dim3(256), 0, s, p.NP, x64, d32, sb, outer);
+  hipLaunchKernelGGL(k_add_f32, grid, dim3(256), 0, s, p.NP, ns, x64, d32, sb, outer);
 }
 void launch_inner_init(const SysBatch& sb, const SysState* outer, SysState* inner, int max_sweeps, hipStream_t s) {
   hipLaunchKernelGGL(k_inner_init, dim3(1), dim3(64), 0, s, sb, outer, inner, max_sweeps);

@@ -86,6 +86,7 @@ def _load():
         "fnlh_order_mesh": (I32, [C.POINTER(Mesh), C.POINTER(Options), V, V, C.POINTER(I32)]),
         "fnlh_version": (C.c_char_p, []),
         "fnlh_stats_enable": (I32, [P, I32]),
+        "fnlh_tune": (I32, [P, I32, I32]),
         "fnlh_stats_get": (I32, [P, I32, C.POINTER(KernelStats)]),
     }
     for name, (res, args) in sig.items():
@@ -253,8 +254,12 @@ class Context:
         self._check(rc, allow_positive=True)
         return rc, [r.as_dict() for r in rep]
 
-    def stats_enable(self, on=True):
-        self._check(LIB.fnlh_stats_enable(self.h, int(bool(on))))
+    def tune(self, sys_per_lane=0, lanes_per_row=0):
+        self._check(LIB.fnlh_tune(self.h, 0, int(sys_per_lane)))
+        self._check(LIB.fnlh_tune(self.h, 1, int(lanes_per_row)))
+
+    def stats_enable(self, on=True, period=1):
+        self._check(LIB.fnlh_stats_enable(self.h, int(period) if on else 0))
 
     def stats(self):
         out = {}

@@ -310,3 +310,52 @@ def test_factor_slot_pool(F):
     assert mem2["matrix_bytes"] == mem1["matrix_bytes"]
     assert mem2["factor_bytes"] == mem1["factor_bytes"]
     c.close()
+
+
+def test_graph_replay_bitwise_matches_direct(F):
+    # the sweep loop replayed from a captured graph gives the same bits as direct
+    # launches, solve after solve (eager work in between)
+    m, Q, K = case(shape=(12, 9, 7), seed=6)
+    c = _ctx(F, m, Q)
+    c.set_harmonics(synth.omegas_single_zone(3))
+    bs = [synth.rhs(m.n_cells, s, real=(s == 0)) for s in range(4)]
+    _, r0, x0 = _solve(c, [0, 1, 2, 3], bs, kind="dilu", max_sweeps=300, rtol=1e-9, check_every=8)
+    for rep in range(3):
+        _, r1, x1 = _solve(c, [0, 1, 2, 3], bs, kind="dilu", max_sweeps=300, rtol=1e-9, check_every=8,
+                           use_graph=True)
+        for a, b in zip(x0, x1):
+            assert np.array_equal(a, b), rep
+        assert [r["sweeps"] for r in r0] == [r["sweeps"] for r in r1]
+        c.residual(1, to_dev(x1[1]), to_dev(bs[1]))  # eager work between replays
+    # reduced precision with graphs
+    c2 = _ctx(F, m, Q, storage="f32")
+    c2.set_harmonics(synth.omegas_single_zone(3))
+    _, s0, y0 = _solve(c2, [0, 1, 2, 3], bs, kind="dilu", max_sweeps=500, rtol=1e-9)
+    _, s1, y1 = _solve(c2, [0, 1, 2, 3], bs, kind="dilu", max_sweeps=500, rtol=1e-9, use_graph=True)
+    for a, b in zip(y0, y1):
+        assert np.array_equal(a, b)
+    c.close()
+    c2.close()
+
+
+def test_first_colour_solve_without_pivoting(F):
+    # assembled Rusanov diagonals are dominant (pivot-free solve); raw blocks with a
+    # non-dominant diagonal take the pivoting solve; both match the oracle
+    m, Q, K = case(shape=(9, 6, 5), seed=8)
+    rng = np.random.default_rng(3)
+    K2 = K.copy()
+    perm = np.array([1, 0, 2, 3, 5, 4])
+    K2.diag = K.diag[:, perm, :] + 0.05 * np.abs(K.diag).max() * rng.standard_normal(K.diag.shape)
+    om = np.array([[0.0], [30.0]])
+    bs = [synth.rhs(m.n_cells, 0, real=True), synth.rhs(m.n_cells, 1)]
+    for KK in (K, K2):
+        c = F.Context(m)
+        d, o = blocks_user_layout(KK)
+        c.set_blocks(to_dev(d), to_dev(o))
+        c.set_harmonics(om)
+        col, _ = c.ordering()
+        st, rep, xs = _solve(c, [0, 1], bs, kind="sgs", max_sweeps=12, rtol=0.0)
+        for s in range(2):
+            x_or, _ = solve.richardson(KK, m.volume, m.zone, om[s], bs[s], col, "SGS", rtol=0.0, max_sweeps=12)
+            assert relerr(xs[s], x_or) <= ITER_TOL
+        c.close()

@@ -203,6 +203,30 @@ const char* fnlh_last_error(fnlh_ctx c);
 int fnlh_order_mesh(const fnlh_mesh* mesh, const fnlh_options* opts, int32_t* colour,
                     int32_t* perm, int32_t* n_colours);
 
+/* ---- batching: many independent instances (e.g. blade rows of different sizes, each
+ * with its own mean + harmonics) solved together.  The harmonic systems are decoupled
+ * (section "Favre-averaged Non-Linear Harmonic Method": cross-coupling of harmonics is
+ * ignored) and so are the instances, so every sweep phase of every instance can run in
+ * one launch.  Each instance keeps its own context (matrix, factors, stop state); the
+ * batch groups the instances by system count and, per sweep, issues one launch per
+ * group and colour phase over a concatenated (instance, tile) work list plus one
+ * reduction for all (instance, system) pairs; check_every sweeps are replayed as one
+ * captured hipGraph when use_graph is set.  Every system stops on its own tolerance.
+ * Instances whose ordering is not two-coloured, or with more systems than one launch
+ * handles (16, or fewer factor slots), are solved one by one with fnlh_relax. */
+typedef struct fnlh_batch_s* fnlh_batch;
+/* inst: n contexts on the same device with the same storage precision (host array);
+ * the contexts must outlive the batch. */
+int fnlh_batch_create(fnlh_batch* out, int32_t n, const fnlh_ctx* inst);
+int fnlh_batch_destroy(fnlh_batch b);
+/* Per instance i: n_sys[i] systems sys[i][j], vectors x[i][j] (in: x0, out: x) and
+ * b[i][j] as in fnlh_relax.  rep has sum(n_sys) entries in instance order.
+ * opts.kind must be FNLH_DILU or FNLH_SGS.  Returns the worst status. */
+int fnlh_batch_relax(fnlh_batch b, const int32_t* n_sys, const int32_t* const* sys, double* const* const* x,
+                     const double* const* const* bvec, const fnlh_relax_opts* opts, fnlh_sys_report* rep,
+                     void* stream);
+const char* fnlh_batch_last_error(fnlh_batch b);
+
 /* Kernel timing of the sweep passes.  While enabled, every sweep-pass launch is
  * bracketed by HIP events on the caller's stream; durations and the algorithmic bytes
  * of each launch (blocks once per launch, per active system: D~^-1, own vectors, and

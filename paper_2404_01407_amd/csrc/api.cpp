@@ -588,6 +588,271 @@ int ensure_dominance(fnlh_ctx c, hipStream_t s) {
   return FNLH_OK;
 }
 
+// ---------------------------------------------------------------- relax phases
+struct RelaxPlan {
+  Path path = kPathRB;
+  SweepCfg cfg;
+  bool reduced = false, use_graph = false;
+  double inner_rtol = 1e-4, divf = 1e3;
+  int inner_max = 1, check_every = 8, fkind = 0, G = 1;
+  std::vector<double> tf, ts;
+};
+
+// Validate, size the scratch, move x and b into the internal layout, pick the path.
+int relax_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, const double* const* b,
+                  const fnlh_relax_opts* o, hipStream_t s, RelaxPlan& P) {
+  if (!c) return FNLH_E_ARG;
+  if (!c->have_matrix || c->n_sys == 0) return set_err(c, FNLH_E_ORDER, "relax: matrix and harmonics first");
+  if (n < 1 || !sys || !x || !b || !o) return set_err(c, FNLH_E_ARG, "relax: bad arguments");
+  for (int j = 0; j < n; ++j) {
+    if (sys[j] < 0 || sys[j] >= c->n_sys) return set_err(c, FNLH_E_ARG, "relax: system out of range");
+    if (!x[j] || !b[j]) return set_err(c, FNLH_E_ARG, "relax: null vector");
+  }
+  if (o->kind != FNLH_DILU && o->kind != FNLH_SGS && o->kind != FNLH_JACOBI)
+    return set_err(c, FNLH_E_ARG, "relax: unsupported preconditioner kind");
+  if (o->max_sweeps < 0 || !(o->rtol >= 0.0)) return set_err(c, FNLH_E_ARG, "relax: need max_sweeps >= 0, rtol >= 0");
+  P.check_every = o->check_every > 0 ? o->check_every : 8;
+  P.divf = o->div_factor > 0 ? o->div_factor : 1e3;
+  P.reduced = c->storage != FNLH_F64;
+  P.inner_rtol = o->inner_rtol > 0 ? o->inner_rtol : (c->storage == FNLH_F32 ? 1e-4 : 1e-2);
+  P.inner_max = o->inner_sweeps > 0 ? o->inner_sweeps : std::max(1, o->max_sweeps);
+  P.use_graph = o->use_graph != 0;
+  int rc;
+  if ((rc = ensure_vectors(c, n))) return rc;
+  const int want_slots = c->factor_slots_opt > 0 ? c->factor_slots_opt : std::min<int>(c->n_sys, 64);
+  if ((rc = ensure_slots(c, want_slots))) return rc;
+  if ((rc = ensure_dominance(c, s))) return rc;
+  DevPattern p = c->pat();
+  for (int j = 0; j < n; ++j) {
+    launch_to_internal(p, (const int32_t*)c->iperm.p, x[j], (double*)c->x64.p, 12, n, j, s);
+    launch_to_internal(p, (const int32_t*)c->iperm.p, b[j], (double*)c->b64.p, 12, n, j, s);
+  }
+  P.path = o->kind == FNLH_JACOBI ? kPathJacobi : (c->L.n_colours == 2 ? kPathRB : kPathGeneral);
+  P.fkind = o->kind == FNLH_DILU ? 0 : 1;
+  P.cfg.storage = c->storage;
+  P.cfg.spw = c->lanes_per_sys;
+  P.cfg.lanes_per_row = c->lanes_per_row;
+  P.cfg.pivot = !c->dom;
+  P.G = std::min({n, kMaxBatch, c->n_slots});
+  P.tf.assign(n, 0.0);
+  P.ts.assign(n, 0.0);
+  return FNLH_OK;
+}
+
+// Assign factor slots to the systems of sb (reusing cached factors) and factor the rest.
+int relax_factor(fnlh_ctx c, SysBatch& sb, int fkind, hipStream_t s) {
+  std::vector<int> used(c->n_slots, 0);
+  SysBatch need;
+  need.n = 0;
+  for (int k = 0; k < sb.n; ++k) {
+    sb.dslot[k] = -1;
+    for (int q = 0; q < c->n_slots; ++q)
+      if (!used[q] && c->slot_sys[q] == sb.orow[k] && c->slot_kind[q] == fkind) {
+        sb.dslot[k] = q;
+        used[q] = 1;
+        break;
+      }
+  }
+  for (int k = 0; k < sb.n; ++k) {
+    if (sb.dslot[k] >= 0) continue;
+    int q = 0;
+    while (used[q]) ++q;
+    used[q] = 1;
+    sb.dslot[k] = q;
+    need.orow[need.n] = sb.orow[k];
+    need.dslot[need.n] = q;
+    need.vslot[need.n] = sb.vslot[k];
+    need.n++;
+  }
+  if (!need.n) return FNLH_OK;
+  for (int k = 0; k < need.n; ++k) {
+    c->slot_sys[need.dslot[k]] = -1;
+    c->slot_kind[need.dslot[k]] = -1;
+  }
+  int rc = factor_batch(c, need, fkind == 0, s);
+  if (rc) return rc;
+  for (int k = 0; k < need.n; ++k) {
+    c->slot_sys[need.dslot[k]] = need.orow[k];
+    c->slot_kind[need.dslot[k]] = fkind;
+  }
+  return FNLH_OK;
+}
+
+// Defect correction: FP64 residual (in r64) -> FP32 inner right-hand side, inner states.
+void outer_to_inner(fnlh_ctx c, int ns, const SysBatch& sb, const SysState* so, SysState* st, int inner_max,
+                    hipStream_t s) {
+  launch_to_f32(c->pat(), (const double*)c->r64.p, (float*)c->rhs32.p, (float*)c->d32.p, ns, sb, so, s);
+  launch_inner_init(sb, so, st, inner_max, s);
+}
+// x64 += d32, new FP64 residual, outer stop test.
+void inner_to_outer(fnlh_ctx c, int ns, const SysBatch& sb, const SysState* st, SysState* so, double rtol,
+                    double divf, hipStream_t s) {
+  launch_outer_update(sb, st, so, s);
+  launch_add_f32(c->pat(), (double*)c->x64.p, (const float*)c->d32.p, ns, sb, so, s);
+  outer_residual(c, ns, sb, (double*)c->r64.p, s);
+  launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, 1, so, kReduceOuter, rtol, divf, 0,
+                s);
+}
+
+// Outer residual of the returned iterates (into fin), x back to user order.
+int relax_finish_launch(fnlh_ctx c, int n, const int32_t* sys, double* const* x, SysState* fin, hipStream_t s) {
+  for (int g0 = 0; g0 < n; g0 += kMaxBatch) {
+    SysBatch sb;
+    sb.n = std::min(kMaxBatch, n - g0);
+    for (int k = 0; k < sb.n; ++k) {
+      sb.orow[k] = sys[g0 + k];
+      sb.vslot[k] = g0 + k;
+      sb.dslot[k] = 0;
+    }
+    outer_residual(c, n, sb, nullptr, s);
+    launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, 1, fin, kReduceFinal, 0, 0, 0, s);
+  }
+  DevPattern p = c->pat();
+  for (int j = 0; j < n; ++j)
+    launch_to_user(p, (const int32_t*)c->iperm.p, (const double*)c->x64.p, x[j], 12, n, j, s);
+  return check_launch(c, "final launch");
+}
+
+int relax_reports(const SysState* h, int n, const RelaxPlan& P, const fnlh_relax_opts* o, fnlh_sys_report* rep) {
+  int worst = FNLH_OK;
+  for (int j = 0; j < n; ++j) {
+    const SysState& S0 = h[j];
+    fnlh_sys_report R;
+    std::memset(&R, 0, sizeof(R));
+    R.sweeps = S0.sweeps;
+    R.outer = P.reduced ? S0.outer_iters : 0;
+    R.res0 = std::sqrt(S0.norm0sq);
+    R.rel_res = S0.norm0sq > 0 ? std::sqrt(S0.last_n2 / S0.norm0sq) : 0.0;
+    int status = S0.status;
+    if (status != FNLH_DIVERGED) status = (R.rel_res <= o->rtol) ? FNLH_OK : FNLH_NOT_CONVERGED;
+    if (!std::isfinite(R.rel_res)) status = FNLH_DIVERGED;
+    R.status = status;
+    R.t_factor_ms = P.tf.empty() ? 0.0 : P.tf[j];
+    R.t_sweep_ms = P.ts.empty() ? 0.0 : P.ts[j];
+    if (rep) rep[j] = R;
+    if (status == FNLH_DIVERGED || (status == FNLH_NOT_CONVERGED && worst == FNLH_OK)) worst = status;
+  }
+  return worst;
+}
+
+
+// ---------------------------------------------------------------- batching
+struct BatchGroup {
+  int SW = 4, P = 1;
+  int64_t w0_off = 0, w0_n = 0, w1_off = 0, w1_n = 0;  // into the C0 / C1 work lists
+};
+
+}  // namespace
+
+struct fnlh_batch_s {
+  std::vector<fnlh_ctx> inst;
+  std::string err;
+  DevBuf desc, work0, work1, items, st, sto;
+  SysState* h_st = nullptr;
+  size_t h_cap = 0;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int g_K = -1, g_storage = -1;
+  double g_rtol = -1, g_divf = -1;
+  std::vector<BatchGroup> groups;
+  int n_items = 0;
+};
+
+namespace {
+
+int bset_err(fnlh_batch b, int code, const std::string& m) {
+  b->err = m;
+  return code;
+}
+
+int bdalloc(fnlh_batch b, DevBuf& d, size_t bytes) {
+  if (d.bytes >= bytes && d.p) return FNLH_OK;
+  if (d.p) (void)hipFree(d.p);
+  d.p = nullptr;
+  d.bytes = 0;
+  if (hipMalloc(&d.p, bytes) != hipSuccess) return bset_err(b, FNLH_E_OOM, "batch: device allocation failed");
+  d.bytes = bytes;
+  if (b->exec) {  // graphs hold buffer addresses
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  return FNLH_OK;
+}
+
+void batched_sweep(fnlh_batch B, int storage, bool first, double rtol, double divf, hipStream_t s) {
+  const InstDesc* d = (const InstDesc*)B->desc.p;
+  const WorkItem* w0 = (const WorkItem*)B->work0.p;
+  const WorkItem* w1 = (const WorkItem*)B->work1.p;
+  for (const BatchGroup& g : B->groups)
+    launch_rb_batched(storage, g.SW, g.P, true, d, w1 + g.w1_off, g.w1_n, s);
+  launch_reduce_batched(d, (const WorkItem*)B->items.p, B->n_items, first ? kReduceSweepNoNorm : kReduceSweep, rtol,
+                        divf, s);
+  for (const BatchGroup& g : B->groups)
+    launch_rb_batched(storage, g.SW, g.P, false, d, w0 + g.w0_off, g.w0_n, s);
+}
+
+// All systems of the batch to their stop criteria (states in B->st, initialised).
+int batched_loop(fnlh_batch B, int storage, double rtol, double divf, int max_sweeps, int check_every, bool use_graph,
+                 int total, hipStream_t s) {
+  const InstDesc* d = (const InstDesc*)B->desc.p;
+  const WorkItem* w0 = (const WorkItem*)B->work0.p;
+  for (const BatchGroup& g : B->groups)
+    launch_rb_batched(storage, g.SW, g.P, false, d, w0 + g.w0_off, g.w0_n, s);
+  int launched = 0;
+  bool graph = false;
+  while (launched <= max_sweeps + 1) {
+    if (launched == 0) {
+      batched_sweep(B, storage, true, rtol, divf, s);
+      launched = 1;
+      if (use_graph) {
+        if (B->exec && (B->g_K != check_every || B->g_storage != storage || B->g_rtol != rtol || B->g_divf != divf)) {
+          (void)hipGraphExecDestroy(B->exec);
+          B->exec = nullptr;
+        }
+        if (!B->exec) {
+          if (!B->cap) (void)hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking);
+          hipGraph_t gr = nullptr;
+          bool ok = B->cap && hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+          if (ok) {
+            for (int i = 0; i < check_every; ++i) batched_sweep(B, storage, false, rtol, divf, B->cap);
+            ok = hipStreamEndCapture(B->cap, &gr) == hipSuccess && gr;
+          }
+          if (ok) ok = hipGraphInstantiate(&B->exec, gr, nullptr, nullptr, 0) == hipSuccess;
+          if (gr) (void)hipGraphDestroy(gr);
+          (void)hipGetLastError();
+          if (ok) {
+            B->g_K = check_every;
+            B->g_storage = storage;
+            B->g_rtol = rtol;
+            B->g_divf = divf;
+          } else {
+            B->exec = nullptr;
+          }
+        }
+        graph = B->exec != nullptr;
+      }
+      if (!graph)
+        for (int i = 1; i < check_every && launched <= max_sweeps + 1; ++i, ++launched)
+          batched_sweep(B, storage, false, rtol, divf, s);
+    } else if (graph) {
+      if (hipGraphLaunch(B->exec, s) != hipSuccess) return bset_err(B, FNLH_E_HIP, "batch: graph launch failed");
+      launched += check_every;
+    } else {
+      for (int i = 0; i < check_every && launched <= max_sweeps + 1; ++i, ++launched)
+        batched_sweep(B, storage, false, rtol, divf, s);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bset_err(B, FNLH_E_HIP, std::string("batch: launch: ") + hipGetErrorString(e));
+    if (hipMemcpyAsync(B->h_st, B->st.p, sizeof(SysState) * total, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return bset_err(B, FNLH_E_HIP, "batch: state read-back failed");
+    bool any = false;
+    for (int k = 0; k < total; ++k) any |= B->h_st[k].active != 0;
+    if (!any) break;
+  }
+  return FNLH_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -807,94 +1072,30 @@ int fnlh_residual(fnlh_ctx c, int32_t sys, const double* x, const double* b, dou
 
 int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, const double* const* b,
                const fnlh_relax_opts* o, fnlh_sys_report* rep, void* stream) {
-  if (!c) return FNLH_E_ARG;
-  if (!c->have_matrix || c->n_sys == 0) return set_err(c, FNLH_E_ORDER, "relax: matrix and harmonics first");
-  if (n < 1 || !sys || !x || !b || !o) return set_err(c, FNLH_E_ARG, "relax: bad arguments");
-  for (int j = 0; j < n; ++j) {
-    if (sys[j] < 0 || sys[j] >= c->n_sys) return set_err(c, FNLH_E_ARG, "relax: system out of range");
-    if (!x[j] || !b[j]) return set_err(c, FNLH_E_ARG, "relax: null vector");
-  }
-  if (o->kind != FNLH_DILU && o->kind != FNLH_SGS && o->kind != FNLH_JACOBI)
-    return set_err(c, FNLH_E_ARG, "relax: unsupported preconditioner kind");
-  if (o->max_sweeps < 0 || !(o->rtol >= 0.0)) return set_err(c, FNLH_E_ARG, "relax: need max_sweeps >= 0, rtol >= 0");
-  const int check_every = o->check_every > 0 ? o->check_every : 8;
-  const double divf = o->div_factor > 0 ? o->div_factor : 1e3;
-  const bool reduced = c->storage != FNLH_F64;
-  const double inner_rtol = o->inner_rtol > 0 ? o->inner_rtol : (c->storage == FNLH_F32 ? 1e-4 : 1e-2);
-  const int inner_max = o->inner_sweeps > 0 ? o->inner_sweeps : std::max(1, o->max_sweeps);
+  RelaxPlan P;
   hipStream_t s = S(stream);
-  int rc;
-  if ((rc = ensure_vectors(c, n))) return rc;
-  const int want_slots = c->factor_slots_opt > 0 ? c->factor_slots_opt : std::min<int>(c->n_sys, 64);
-  if ((rc = ensure_slots(c, want_slots))) return rc;
-  DevPattern p = c->pat();
-  for (int j = 0; j < n; ++j) {
-    launch_to_internal(p, (const int32_t*)c->iperm.p, x[j], (double*)c->x64.p, 12, n, j, s);
-    launch_to_internal(p, (const int32_t*)c->iperm.p, b[j], (double*)c->b64.p, 12, n, j, s);
-  }
-  const Path path = o->kind == FNLH_JACOBI ? kPathJacobi : (c->L.n_colours == 2 ? kPathRB : kPathGeneral);
-  const int fkind = o->kind == FNLH_DILU ? 0 : 1;
-  SweepCfg cfg;
-  cfg.storage = c->storage;
-  cfg.spw = c->lanes_per_sys;
-  cfg.lanes_per_row = c->lanes_per_row;
-  if ((rc = ensure_dominance(c, s))) return rc;
-  cfg.pivot = !c->dom;
-  const bool use_graph = o->use_graph != 0;
-  const int G = std::min({n, kMaxBatch, c->n_slots});
-  std::vector<double> tf(n, 0.0), ts(n, 0.0);
-  for (int g0 = 0; g0 < n; g0 += G) {
+  int rc = relax_prepare(c, n, sys, x, b, o, s, P);
+  if (rc) return rc;
+  SysState* st = (SysState*)c->st.p;
+  SysState* so = (SysState*)c->st_outer.p;
+  for (int g0 = 0; g0 < n; g0 += P.G) {
     SysBatch sb;
-    sb.n = std::min(G, n - g0);
-    // factor slots: reuse cached factors, fill the rest
-    std::vector<int> used(c->n_slots, 0);
-    SysBatch need;
-    need.n = 0;
+    sb.n = std::min(P.G, n - g0);
     for (int k = 0; k < sb.n; ++k) {
       sb.orow[k] = sys[g0 + k];
       sb.vslot[k] = g0 + k;
-      sb.dslot[k] = -1;
-      for (int q = 0; q < c->n_slots; ++q)
-        if (!used[q] && c->slot_sys[q] == sys[g0 + k] && c->slot_kind[q] == fkind) {
-          sb.dslot[k] = q;
-          used[q] = 1;
-          break;
-        }
-    }
-    for (int k = 0; k < sb.n; ++k) {
-      if (sb.dslot[k] >= 0) continue;
-      int q = 0;
-      while (used[q]) ++q;
-      used[q] = 1;
-      sb.dslot[k] = q;
-      need.orow[need.n] = sb.orow[k];
-      need.dslot[need.n] = q;
-      need.vslot[need.n] = sb.vslot[k];
-      need.n++;
     }
     HIPC(c, hipEventRecord(c->ev[0], s), "event");
-    if (need.n) {
-      for (int k = 0; k < need.n; ++k) {
-        c->slot_sys[need.dslot[k]] = -1;
-        c->slot_kind[need.dslot[k]] = -1;
-      }
-      if ((rc = factor_batch(c, need, fkind == 0, s))) return rc;
-      for (int k = 0; k < need.n; ++k) {
-        c->slot_sys[need.dslot[k]] = need.orow[k];
-        c->slot_kind[need.dslot[k]] = fkind;
-      }
-    }
+    if ((rc = relax_factor(c, sb, P.fkind, s))) return rc;
     HIPC(c, hipEventRecord(c->ev[1], s), "event");
-    SysState* st = (SysState*)c->st.p;
-    if (!reduced) {
+    if (!P.reduced) {
       outer_residual(c, n, sb, nullptr, s);
       launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, 1, st, kReduceInit, 0, 0,
                     o->max_sweeps, s);
-      if ((rc = sweep_loop(c, path, cfg, n, sb, c->x64.p, c->b64.p, c->y.p, st, o->rtol, divf, o->max_sweeps,
-                           check_every, use_graph, s)))
+      if ((rc = sweep_loop(c, P.path, P.cfg, n, sb, c->x64.p, c->b64.p, c->y.p, st, o->rtol, P.divf, o->max_sweeps,
+                           P.check_every, P.use_graph, s)))
         return rc;
     } else {
-      SysState* so = (SysState*)c->st_outer.p;
       outer_residual(c, n, sb, (double*)c->r64.p, s);
       launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, 1, so, kReduceInit, 0, 0,
                     o->max_sweeps, s);
@@ -906,65 +1107,252 @@ int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, cons
         bool any = false;
         for (int k = 0; k < sb.n; ++k) any |= c->h_st[sb.vslot[k]].active != 0;
         if (!any) break;
-        launch_to_f32(p, (const double*)c->r64.p, (float*)c->rhs32.p, (float*)c->d32.p, n, sb, so, s);
-        launch_inner_init(sb, so, st, inner_max, s);
-        if ((rc = sweep_loop(c, path, cfg, n, sb, c->d32.p, c->rhs32.p, c->y.p, st, inner_rtol, 1e30, inner_max,
-                             check_every, use_graph, s)))
+        outer_to_inner(c, n, sb, so, st, P.inner_max, s);
+        if ((rc = sweep_loop(c, P.path, P.cfg, n, sb, c->d32.p, c->rhs32.p, c->y.p, st, P.inner_rtol, 1e30,
+                             P.inner_max, P.check_every, P.use_graph, s)))
           return rc;
-        launch_outer_update(sb, st, so, s);
-        launch_add_f32(p, (double*)c->x64.p, (const float*)c->d32.p, n, sb, so, s);
-        outer_residual(c, n, sb, (double*)c->r64.p, s);
-        launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, 1, so, kReduceOuter, o->rtol,
-                      divf, 0, s);
+        inner_to_outer(c, n, sb, st, so, o->rtol, P.divf, s);
       }
     }
     HIPC(c, hipEventRecord(c->ev[2], s), "event");
     HIPC(c, hipEventSynchronize(c->ev[2]), "event sync");
-    float a = 0.f, bms = 0.f;
-    (void)hipEventElapsedTime(&a, c->ev[0], c->ev[1]);
-    (void)hipEventElapsedTime(&bms, c->ev[1], c->ev[2]);
+    float fa = 0.f, fb = 0.f;
+    (void)hipEventElapsedTime(&fa, c->ev[0], c->ev[1]);
+    (void)hipEventElapsedTime(&fb, c->ev[1], c->ev[2]);
     for (int k = 0; k < sb.n; ++k) {
-      tf[g0 + k] = a;
-      ts[g0 + k] = bms;
+      P.tf[g0 + k] = fa;
+      P.ts[g0 + k] = fb;
     }
   }
-  // final: residual of the returned iterates with the outer operator
-  std::vector<SysState> fin(n);
-  for (int g0 = 0; g0 < n; g0 += kMaxBatch) {
-    SysBatch sb;
-    sb.n = std::min(kMaxBatch, n - g0);
-    for (int k = 0; k < sb.n; ++k) {
-      sb.orow[k] = sys[g0 + k];
-      sb.vslot[k] = g0 + k;
-      sb.dslot[k] = 0;
-    }
-    SysState* stf = (SysState*)(reduced ? c->st_outer.p : c->st.p);
-    outer_residual(c, n, sb, nullptr, s);
-    launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, 1, stf, kReduceFinal, 0, 0, 0, s);
-  }
-  for (int j = 0; j < n; ++j)
-    launch_to_user(p, (const int32_t*)c->iperm.p, (const double*)c->x64.p, x[j], 12, n, j, s);
-  if ((rc = check_launch(c, "final launch"))) return rc;
-  HIPC(c, hipMemcpyAsync(c->h_st, reduced ? c->st_outer.p : c->st.p, sizeof(SysState) * n, hipMemcpyDeviceToHost, s),
-       "read states");
+  SysState* fin = P.reduced ? so : st;
+  if ((rc = relax_finish_launch(c, n, sys, x, fin, s))) return rc;
+  HIPC(c, hipMemcpyAsync(c->h_st, fin, sizeof(SysState) * n, hipMemcpyDeviceToHost, s), "read states");
   HIPC(c, hipStreamSynchronize(s), "final sync");
+  return relax_reports(c->h_st, n, P, o, rep);
+}
+
+
+int fnlh_batch_create(fnlh_batch* out, int32_t n, const fnlh_ctx* inst) {
+  if (!out) return set_err(nullptr, FNLH_E_ARG, "batch: null output");
+  *out = nullptr;
+  if (n < 1 || !inst) return set_err(nullptr, FNLH_E_ARG, "batch: need n >= 1 instances");
+  for (int i = 0; i < n; ++i) {
+    if (!inst[i]) return set_err(nullptr, FNLH_E_ARG, "batch: null instance");
+    if (inst[i]->storage != inst[0]->storage || inst[i]->dev != inst[0]->dev)
+      return set_err(nullptr, FNLH_E_ARG, "batch: instances differ in storage precision or device");
+  }
+  fnlh_batch b = new fnlh_batch_s();
+  b->inst.assign(inst, inst + n);
+  *out = b;
+  return FNLH_OK;
+}
+
+int fnlh_batch_destroy(fnlh_batch b) {
+  if (!b) return FNLH_E_ARG;
+  DevBuf* bufs[] = {&b->desc, &b->work0, &b->work1, &b->items, &b->st, &b->sto};
+  for (DevBuf* d : bufs) dfree(*d);
+  if (b->h_st) (void)hipHostFree(b->h_st);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
+  return FNLH_OK;
+}
+
+const char* fnlh_batch_last_error(fnlh_batch b) { return b ? b->err.c_str() : g_create_error.c_str(); }
+
+int fnlh_batch_relax(fnlh_batch B, const int32_t* n_sys, const int32_t* const* sys, double* const* const* x,
+                     const double* const* const* bvec, const fnlh_relax_opts* o, fnlh_sys_report* rep, void* stream) {
+  if (!B) return FNLH_E_ARG;
+  if (!n_sys || !sys || !x || !bvec || !o) return bset_err(B, FNLH_E_ARG, "batch_relax: bad arguments");
+  if (o->kind != FNLH_DILU && o->kind != FNLH_SGS)
+    return bset_err(B, FNLH_E_ARG, "batch_relax: kind must be DILU or SGS");
+  hipStream_t s = S(stream);
+  const int n = (int)B->inst.size();
+  std::vector<int> base(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    if (n_sys[i] < 1) return bset_err(B, FNLH_E_ARG, "batch_relax: every instance needs >= 1 system");
+    base[i + 1] = base[i] + n_sys[i];
+  }
+  const int total = base[n];
+  int rc;
+  if ((rc = bdalloc(B, B->st, sizeof(SysState) * total)) || (rc = bdalloc(B, B->sto, sizeof(SysState) * total)))
+    return rc;
+  if (B->h_cap < (size_t)total) {
+    if (B->h_st) (void)hipHostFree(B->h_st);
+    B->h_st = nullptr;
+    if (hipHostMalloc((void**)&B->h_st, sizeof(SysState) * total, hipHostMallocDefault) != hipSuccess)
+      return bset_err(B, FNLH_E_OOM, "batch: host allocation failed");
+    B->h_cap = total;
+  }
+  SysState* dst = (SysState*)B->st.p;
+  SysState* dso = (SysState*)B->sto.p;
+  const int storage = B->inst[0]->storage;
+  const bool reduced = storage != FNLH_F64;
+  std::vector<RelaxPlan> plans(n);
+  std::vector<SysBatch> sbs(n);
+  std::vector<char> batched(n, 0);
+  std::vector<InstDesc> desc;
+  std::vector<int> di(n, -1);
+  // prepare and factor every instance
+  for (int i = 0; i < n; ++i) {
+    fnlh_ctx c = B->inst[i];
+    if ((rc = relax_prepare(c, n_sys[i], sys[i], x[i], bvec[i], o, s, plans[i]))) {
+      B->err = c->err;
+      return rc;
+    }
+    if (plans[i].path != kPathRB || plans[i].G < n_sys[i]) continue;  // solved one by one below
+    SysBatch& sb = sbs[i];
+    sb.n = n_sys[i];
+    for (int k = 0; k < sb.n; ++k) {
+      sb.orow[k] = sys[i][k];
+      sb.vslot[k] = k;
+    }
+    if ((rc = relax_factor(c, sb, plans[i].fkind, s))) {
+      B->err = c->err;
+      return rc;
+    }
+    batched[i] = 1;
+    InstDesc D;
+    D.p = c->pat();
+    D.offd = c->offd.p;
+    D.diag = c->diag.p;
+    D.dinv = c->dinv.p;
+    D.dstride = dinv_stride(c);
+    D.ns = n_sys[i];
+    D.pivot = plans[i].cfg.pivot ? 1 : 0;
+    D.sb = sb;
+    D.st = dst + base[i];
+    D.partial = (double*)c->partial.p;
+    D.c1_t0 = c->L.ctile[1];
+    D.c1_nt = c->L.ctile[2] - c->L.ctile[1];
+    int SW, P;
+    rb_shape(plans[i].cfg, sb.n, SW, P);
+    D.slots = SW;
+    di[i] = (int)desc.size();
+    desc.push_back(D);
+  }
+  // groups of equal (SW, P); work lists and reduction items
+  std::vector<WorkItem> w0, w1, items;
+  B->groups.clear();
+  {
+    std::vector<std::pair<int, int>> keys;
+    for (int i = 0; i < n; ++i)
+      if (batched[i]) {
+        int SW, P;
+        rb_shape(plans[i].cfg, sbs[i].n, SW, P);
+        if (std::find(keys.begin(), keys.end(), std::make_pair(SW, P)) == keys.end()) keys.emplace_back(SW, P);
+      }
+    for (auto& kp : keys) {
+      BatchGroup g;
+      g.SW = kp.first;
+      g.P = kp.second;
+      g.w0_off = (int64_t)w0.size();
+      g.w1_off = (int64_t)w1.size();
+      for (int i = 0; i < n; ++i) {
+        if (!batched[i]) continue;
+        int SW, P;
+        rb_shape(plans[i].cfg, sbs[i].n, SW, P);
+        if (SW != g.SW || P != g.P) continue;
+        const Layout& L = B->inst[i]->L;
+        for (int64_t t = L.ctile[0]; t < L.ctile[1]; ++t) w0.push_back(WorkItem{di[i], (int32_t)t});
+        for (int64_t t = L.ctile[1]; t < L.ctile[2]; ++t) w1.push_back(WorkItem{di[i], (int32_t)t});
+      }
+      g.w0_n = (int64_t)w0.size() - g.w0_off;
+      g.w1_n = (int64_t)w1.size() - g.w1_off;
+      B->groups.push_back(g);
+    }
+    for (int i = 0; i < n; ++i)
+      if (batched[i])
+        for (int k = 0; k < sbs[i].n; ++k) items.push_back(WorkItem{di[i], k});
+  }
+  B->n_items = (int)items.size();
+  if (!desc.empty()) {
+    if ((rc = bdalloc(B, B->desc, sizeof(InstDesc) * desc.size())) ||
+        (rc = bdalloc(B, B->work0, sizeof(WorkItem) * std::max<size_t>(1, w0.size()))) ||
+        (rc = bdalloc(B, B->work1, sizeof(WorkItem) * std::max<size_t>(1, w1.size()))) ||
+        (rc = bdalloc(B, B->items, sizeof(WorkItem) * std::max<size_t>(1, items.size()))))
+      return rc;
+    HIPC(nullptr, hipMemcpyAsync(B->work0.p, w0.data(), sizeof(WorkItem) * w0.size(), hipMemcpyHostToDevice, s),
+         "upload");
+    HIPC(nullptr, hipMemcpyAsync(B->work1.p, w1.data(), sizeof(WorkItem) * w1.size(), hipMemcpyHostToDevice, s),
+         "upload");
+    HIPC(nullptr, hipMemcpyAsync(B->items.p, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, s),
+         "upload");
+    const RelaxPlan& P0 = plans[std::find(batched.begin(), batched.end(), 1) - batched.begin()];
+    if (!reduced) {
+      for (int i = 0; i < n; ++i) {
+        if (!batched[i]) continue;
+        fnlh_ctx c = B->inst[i];
+        desc[di[i]].x = c->x64.p;
+        desc[di[i]].b = c->b64.p;
+        outer_residual(c, n_sys[i], sbs[i], nullptr, s);
+        launch_reduce(sbs[i], (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, 1, dst + base[i],
+                      kReduceInit, 0, 0, o->max_sweeps, s);
+      }
+      HIPC(nullptr, hipMemcpyAsync(B->desc.p, desc.data(), sizeof(InstDesc) * desc.size(), hipMemcpyHostToDevice, s),
+           "upload");
+      if ((rc = batched_loop(B, storage, o->rtol, P0.divf, o->max_sweeps, P0.check_every, P0.use_graph, total, s)))
+        return rc;
+    } else {
+      for (int i = 0; i < n; ++i) {
+        if (!batched[i]) continue;
+        fnlh_ctx c = B->inst[i];
+        desc[di[i]].x = c->d32.p;
+        desc[di[i]].b = c->rhs32.p;
+        outer_residual(c, n_sys[i], sbs[i], (double*)c->r64.p, s);
+        launch_reduce(sbs[i], (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, 1, dso + base[i],
+                      kReduceInit, 0, 0, o->max_sweeps, s);
+      }
+      HIPC(nullptr, hipMemcpyAsync(B->desc.p, desc.data(), sizeof(InstDesc) * desc.size(), hipMemcpyHostToDevice, s),
+           "upload");
+      for (int it = 0; it < 100000; ++it) {
+        if (hipMemcpyAsync(B->h_st, dso, sizeof(SysState) * total, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+          return bset_err(B, FNLH_E_HIP, "batch: state read-back failed");
+        bool any = false;
+        for (int i = 0; i < n; ++i)
+          if (batched[i])
+            for (int k = 0; k < n_sys[i]; ++k) any |= B->h_st[base[i] + k].active != 0;
+        if (!any) break;
+        for (int i = 0; i < n; ++i)
+          if (batched[i]) outer_to_inner(B->inst[i], n_sys[i], sbs[i], dso + base[i], dst + base[i], P0.inner_max, s);
+        if ((rc = batched_loop(B, storage, P0.inner_rtol, 1e30, P0.inner_max, P0.check_every, P0.use_graph, total,
+                               s)))
+          return rc;
+        for (int i = 0; i < n; ++i)
+          if (batched[i])
+            inner_to_outer(B->inst[i], n_sys[i], sbs[i], dst + base[i], dso + base[i], o->rtol, P0.divf, s);
+      }
+    }
+  }
+  // finish the batched instances
+  SysState* fin = reduced ? dso : dst;
+  for (int i = 0; i < n; ++i) {
+    if (!batched[i]) continue;
+    if ((rc = relax_finish_launch(B->inst[i], n_sys[i], sys[i], x[i], fin + base[i], s))) {
+      B->err = B->inst[i]->err;
+      return rc;
+    }
+  }
+  if (hipMemcpyAsync(B->h_st, fin, sizeof(SysState) * total, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return bset_err(B, FNLH_E_HIP, "batch: state read-back failed");
   int worst = FNLH_OK;
-  for (int j = 0; j < n; ++j) {
-    const SysState& S0 = c->h_st[j];
-    fnlh_sys_report R;
-    std::memset(&R, 0, sizeof(R));
-    R.sweeps = S0.sweeps;
-    R.outer = reduced ? S0.outer_iters : 0;
-    R.res0 = std::sqrt(S0.norm0sq);
-    R.rel_res = S0.norm0sq > 0 ? std::sqrt(S0.last_n2 / S0.norm0sq) : 0.0;
-    int status = S0.status;
-    if (status != FNLH_DIVERGED) status = (R.rel_res <= o->rtol) ? FNLH_OK : FNLH_NOT_CONVERGED;
-    if (!std::isfinite(R.rel_res)) status = FNLH_DIVERGED;
-    R.status = status;
-    R.t_factor_ms = tf[j];
-    R.t_sweep_ms = ts[j];
-    if (rep) rep[j] = R;
-    if (status == FNLH_DIVERGED || (status == FNLH_NOT_CONVERGED && worst == FNLH_OK)) worst = status;
+  auto fold = [&](int r) {
+    if (r < 0) return;
+    if (r == FNLH_DIVERGED || (r == FNLH_NOT_CONVERGED && worst == FNLH_OK)) worst = r;
+  };
+  for (int i = 0; i < n; ++i)
+    if (batched[i]) fold(relax_reports(B->h_st + base[i], n_sys[i], plans[i], o, rep ? rep + base[i] : nullptr));
+  // the rest one by one
+  for (int i = 0; i < n; ++i) {
+    if (batched[i]) continue;
+    rc = fnlh_relax(B->inst[i], n_sys[i], sys[i], x[i], bvec[i], o, rep ? rep + base[i] : nullptr, stream);
+    if (rc < 0) {
+      B->err = B->inst[i]->err;
+      return rc;
+    }
+    fold(rc);
   }
   return worst;
 }

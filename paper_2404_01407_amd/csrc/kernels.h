@@ -58,6 +58,29 @@ struct DevFlow {
   int32_t offdiag = 1;                 // 0 for the explicit scheme (K = P)
 };
 
+// One instance of a batched solve: its pattern, matrix, factors, vectors and states.
+struct InstDesc {
+  DevPattern p;
+  const void* offd = nullptr;
+  const void* diag = nullptr;
+  const void* dinv = nullptr;
+  int64_t dstride = 0;
+  void* x = nullptr;        // inner vectors (TV) of the solve, [NP][ns][12]
+  const void* b = nullptr;
+  int32_t ns = 0;
+  int32_t pivot = 1;        // first-colour solve pivots
+  SysBatch sb;              // the instance's systems (vslot indexes st and the vectors)
+  SysState* st = nullptr;   // states, indexed by vslot
+  double* partial = nullptr;
+  int64_t c1_t0 = 0, c1_nt = 0;  // second-colour tile range
+  int32_t slots = 1;        // norm partial slots per tile
+  int32_t pad_ = 0;
+};
+struct WorkItem {
+  int32_t inst;
+  int32_t tile;  // tile (work lists) or batch entry (reduction items)
+};
+
 struct SweepCfg {
   int storage = kF64;
   int spw = 0;            // systems per lane (1, 2, 4); 0 = automatic
@@ -65,6 +88,7 @@ struct SweepCfg {
   bool pivot = true;      // first-colour solve pivots (false: diagonal blocks are dominant)
 };
 int rb_slots(const SweepCfg& c, int n);  // norm partial slots per tile of the two-colour pass
+void rb_shape(const SweepCfg& c, int n, int& SW, int& P);  // lanes per row, systems per lane
 
 // assembly / raw blocks
 void launch_assemble(int storage, const DevPattern& p, const DevFlow& f, void* offd, void* diag, hipStream_t s);
@@ -99,6 +123,12 @@ void launch_jacobi(const SweepCfg& c, const DevPattern& p, const void* offd, con
                    const SysState* st, double* partial, hipStream_t s);
 void launch_axpy_y(int storage, const DevPattern& p, void* x, const void* y, int ns, const SysBatch& sb,
                    const SysState* st, hipStream_t s);
+
+// batched two-colour pass over a work list (instances grouped so SW, P are uniform)
+void launch_rb_batched(int storage, int SW, int P, bool update, const InstDesc* inst, const WorkItem* work,
+                       int64_t n_work, hipStream_t s);
+void launch_reduce_batched(const InstDesc* inst, const WorkItem* items, int n_items, int mode, double rtol,
+                           double div_factor, hipStream_t s);
 
 // residual norms -> state.  modes: 0 init (limit = max_sweeps), 1 sweep with a valid
 // norm, 2 sweep without a norm, 3 final (record only), 4 outer FP64 correction test

@@ -232,18 +232,12 @@ __global__ void k_check_dominance(DevPattern p, const TB* __restrict__ diag, int
 // address (one fetch per instruction), and their vector records are adjacent in the
 // interleaved layout.  A tile of 64 rows takes SW waves of 64/SW rows each.
 template <typename TB, int SW, int P, bool UPDATE, bool PIVOT>
-__global__ void __launch_bounds__(256) k_rb_pass(DevPattern p, const TB* __restrict__ offd,
-                                                 const TB* __restrict__ diag,
-                                                 const typename TV_of<TB>::T* __restrict__ dinv, int64_t dstride,
-                                                 typename TV_of<TB>::T* __restrict__ x,
-                                                 const typename TV_of<TB>::T* __restrict__ b, int ns, SysBatch sb,
-                                                 const SysState* __restrict__ st, double* __restrict__ partial,
-                                                 int64_t t0, int64_t nt) {
+__device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd, const TB* __restrict__ diag,
+                               const typename TV_of<TB>::T* __restrict__ dinv, int64_t dstride,
+                               typename TV_of<TB>::T* __restrict__ x, const typename TV_of<TB>::T* __restrict__ b,
+                               int ns, const SysBatch& sb, const SysState* __restrict__ st,
+                               double* __restrict__ partial, int64_t tile) {
   using A = typename TV_of<TB>::T;
-  int64_t tile;
-  int grp;
-  if (!map_tile(nt, 1, tile, grp)) return;
-  tile += t0;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int sidx = lane % SW;
@@ -338,6 +332,40 @@ __global__ void __launch_bounds__(256) k_rb_pass(DevPattern p, const TB* __restr
       }
     }
   }
+}
+
+template <typename TB, int SW, int P, bool UPDATE, bool PIVOT>
+__global__ void __launch_bounds__(256) k_rb_pass(DevPattern p, const TB* __restrict__ offd,
+                                                 const TB* __restrict__ diag,
+                                                 const typename TV_of<TB>::T* __restrict__ dinv, int64_t dstride,
+                                                 typename TV_of<TB>::T* __restrict__ x,
+                                                 const typename TV_of<TB>::T* __restrict__ b, int ns, SysBatch sb,
+                                                 const SysState* __restrict__ st, double* __restrict__ partial,
+                                                 int64_t t0, int64_t nt) {
+  int64_t tile;
+  int grp;
+  if (!map_tile(nt, 1, tile, grp)) return;
+  rb_tile<TB, SW, P, UPDATE, PIVOT>(p, offd, diag, dinv, dstride, x, b, ns, sb, st, partial, t0 + tile);
+}
+
+// Batched form: one launch over the concatenated (instance, tile) work list of many
+// independent instances; each workgroup reads its instance's descriptor.
+template <typename TB, int SW, int P, bool UPDATE, bool PIVOT>
+__global__ void __launch_bounds__(256) k_rb_batched(const InstDesc* __restrict__ inst,
+                                                    const WorkItem* __restrict__ work, int64_t n_work) {
+  using A = typename TV_of<TB>::T;
+  int64_t k;
+  int grp;
+  if (!map_tile(n_work, 1, k, grp)) return;
+  const WorkItem wi = work[k];
+  const InstDesc& D = inst[wi.inst];
+  const bool pivot = D.pivot;
+  if (!UPDATE && !pivot)
+    rb_tile<TB, SW, P, UPDATE, false>(D.p, (const TB*)D.offd, (const TB*)D.diag, (const A*)D.dinv, D.dstride,
+                                      (A*)D.x, (const A*)D.b, D.ns, D.sb, D.st, D.partial, wi.tile);
+  else
+    rb_tile<TB, SW, P, UPDATE, true>(D.p, (const TB*)D.offd, (const TB*)D.diag, (const A*)D.dinv, D.dstride,
+                                     (A*)D.x, (const A*)D.b, D.ns, D.sb, D.st, D.partial, wi.tile);
 }
 
 // General colouring, forward pass of colour c (rows of lower colours are < cstart):
@@ -540,12 +568,11 @@ __global__ void k_axpy_y(int64_t NP, int ns, A* __restrict__ x, const A* __restr
 }
 
 // ================================================================ norm reduction
-__global__ void __launch_bounds__(256) k_reduce(SysBatch sb, const double* __restrict__ partial, int64_t n_tiles,
-                                                int64_t t0, int64_t nt, int slots, SysState* __restrict__ st,
-                                                int mode, double rtol2, double div2, int max_sweeps) {
+// Sum the norm partials of one system in a fixed order and advance its state.
+__device__ inline void reduce_one(const double* __restrict__ partial, int64_t n_tiles, int64_t t0, int64_t nt,
+                                  int slots, SysState* __restrict__ st, int vs, int mode, double rtol2, double div2,
+                                  int max_sweeps) {
   __shared__ double sh[256];
-  const int k = blockIdx.x;
-  const int vs = sb.vslot[k];
   double s = 0.0;
   if (mode != kReduceSweepNoNorm) {
     const double* pp = partial + ((int64_t)vs * n_tiles + t0) * kPartialSlots;
@@ -615,6 +642,22 @@ __global__ void __launch_bounds__(256) k_reduce(SysBatch sb, const double* __res
       break;
   }
   st[vs] = S;
+}
+
+__global__ void __launch_bounds__(256) k_reduce(SysBatch sb, const double* __restrict__ partial, int64_t n_tiles,
+                                                int64_t t0, int64_t nt, int slots, SysState* __restrict__ st,
+                                                int mode, double rtol2, double div2, int max_sweeps) {
+  reduce_one(partial, n_tiles, t0, nt, slots, st, sb.vslot[blockIdx.x], mode, rtol2, div2, max_sweeps);
+}
+
+// Batched reduction: one workgroup per (instance, system) item, over the instance's
+// second-colour tiles.
+__global__ void __launch_bounds__(256) k_reduce_batched(const InstDesc* __restrict__ inst,
+                                                        const WorkItem* __restrict__ items, int mode, double rtol2,
+                                                        double div2) {
+  const WorkItem it = items[blockIdx.x];
+  const InstDesc& D = inst[it.inst];
+  reduce_one(D.partial, D.p.n_tiles, D.c1_t0, D.c1_nt, D.slots, D.st, D.sb.vslot[it.tile], mode, rtol2, div2, 0);
 }
 
 __global__ void k_inner_init(SysBatch sb, const SysState* __restrict__ outer, SysState* __restrict__ inner,
@@ -1121,7 +1164,7 @@ inline dim3 block_for(int n, int P) {
   } while (0)
 
 // lanes per row (SW) and systems per lane (P) of the two-colour pass
-inline void rb_shape(const SweepCfg& c, int n, int& SW, int& P) {
+void rb_shape(const SweepCfg& c, int n, int& SW, int& P) {
   SW = c.lanes_per_row;
   if (SW <= 0) SW = n >= 4 ? 4 : (n >= 2 ? 2 : 1);
   if (SW != 1 && SW != 2 && SW != 4) SW = 4;
@@ -1168,6 +1211,36 @@ void launch_rb_pass(const SweepCfg& c, bool update, const DevPattern& p, const v
       FNLH_RB_LAUNCH(4);
   });
 #undef FNLH_RB_LAUNCH
+}
+
+void launch_rb_batched(int storage, int SW, int P, bool update, const InstDesc* inst, const WorkItem* work,
+                       int64_t n_work, hipStream_t s) {
+  if (n_work <= 0) return;
+  dim3 grid = tile_grid(n_work, 1);
+  dim3 block(64 * SW);
+#define FNLH_RBB_LAUNCH(SWV)                                                                                   \
+  FNLH_DISPATCH_P(P, {                                                                                         \
+    if (update)                                                                                                \
+      hipLaunchKernelGGL((k_rb_batched<TB, SWV, PP, true, true>), grid, block, 0, s, inst, work, n_work);      \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_rb_batched<TB, SWV, PP, false, true>), grid, block, 0, s, inst, work, n_work);     \
+  })
+  FNLH_DISPATCH_STORE(storage, {
+    if (SW == 1)
+      FNLH_RBB_LAUNCH(1);
+    else if (SW == 2)
+      FNLH_RBB_LAUNCH(2);
+    else
+      FNLH_RBB_LAUNCH(4);
+  });
+#undef FNLH_RBB_LAUNCH
+}
+
+void launch_reduce_batched(const InstDesc* inst, const WorkItem* items, int n_items, int mode, double rtol,
+                           double div_factor, hipStream_t s) {
+  if (n_items <= 0) return;
+  hipLaunchKernelGGL(k_reduce_batched, dim3((unsigned)n_items), dim3(256), 0, s, inst, items, mode, rtol * rtol,
+                     div_factor * div_factor);
 }
 
 void launch_fwd(const SweepCfg& c, bool last, const DevPattern& p, const void* offd, const void* diag,

@@ -87,6 +87,10 @@ def _load():
         "fnlh_version": (C.c_char_p, []),
         "fnlh_stats_enable": (I32, [P, I32]),
         "fnlh_tune": (I32, [P, I32, I32]),
+        "fnlh_batch_create": (I32, [C.POINTER(P), I32, V]),
+        "fnlh_batch_destroy": (I32, [P]),
+        "fnlh_batch_relax": (I32, [P, V, V, V, V, C.POINTER(RelaxOpts), V, V]),
+        "fnlh_batch_last_error": (C.c_char_p, [P]),
         "fnlh_stats_get": (I32, [P, I32, C.POINTER(KernelStats)]),
     }
     for name, (res, args) in sig.items():
@@ -279,6 +283,65 @@ class Context:
         a, b, c = C.c_size_t(0), C.c_size_t(0), C.c_size_t(0)
         self._check(LIB.fnlh_memory(self.h, C.byref(a), C.byref(b), C.byref(c)))
         return {"matrix_bytes": a.value, "factor_bytes": b.value, "vector_bytes": c.value}
+
+
+class Batch:
+    """Independent instances (contexts) solved together: one launch per colour phase and
+    system-count group over all instances, sweeps replayed from a captured graph."""
+
+    def __init__(self, contexts):
+        self.contexts = list(contexts)
+        arr = (C.c_void_p * len(self.contexts))(*[c.h.value for c in self.contexts])
+        h = C.c_void_p()
+        rc = LIB.fnlh_batch_create(C.byref(h), len(self.contexts), C.cast(arr, C.c_void_p))
+        if rc != OK:
+            raise FnlhError(rc, LIB.fnlh_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            LIB.fnlh_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def relax(self, systems, xs, bs, kind="dilu", max_sweeps=500, rtol=1e-8, check_every=8, inner_sweeps=0,
+              inner_rtol=0.0, div_factor=0.0, use_graph=True, stream=None):
+        """systems[i]: system ids of instance i; xs[i][j], bs[i][j]: complex128 CUDA
+        tensors [N_i, 6].  Returns (status, reports per instance)."""
+        n = len(self.contexts)
+        nsys = np.array([len(sy) for sy in systems], np.int32)
+        keep = []
+        sys_ptrs = (C.c_void_p * n)()
+        x_ptrs = (C.c_void_p * n)()
+        b_ptrs = (C.c_void_p * n)()
+        for i, ctx in enumerate(self.contexts):
+            for t in list(xs[i]) + list(bs[i]):
+                _dev_tensor(t, (ctx.n, 6), "vector")
+            sa = np.ascontiguousarray(systems[i], dtype=np.int32)
+            xa = (C.c_void_p * len(xs[i]))(*[_ptr(t) for t in xs[i]])
+            ba = (C.c_void_p * len(bs[i]))(*[_ptr(t) for t in bs[i]])
+            keep += [sa, xa, ba]
+            sys_ptrs[i] = sa.ctypes.data
+            x_ptrs[i] = C.cast(xa, C.c_void_p).value
+            b_ptrs[i] = C.cast(ba, C.c_void_p).value
+        o = RelaxOpts(KIND[kind], int(max_sweeps), float(rtol), int(check_every), int(inner_sweeps),
+                      float(inner_rtol), float(div_factor), int(bool(use_graph)), 0)
+        total = int(nsys.sum())
+        rep = (Report * total)()
+        rc = LIB.fnlh_batch_relax(self.h, _ptr(nsys), C.cast(sys_ptrs, C.c_void_p), C.cast(x_ptrs, C.c_void_p),
+                                  C.cast(b_ptrs, C.c_void_p), C.byref(o), C.cast(rep, C.c_void_p), _stream(stream))
+        if rc < 0:
+            raise FnlhError(rc, LIB.fnlh_batch_last_error(self.h).decode())
+        out, k = [], 0
+        for i in range(n):
+            out.append([rep[k + j].as_dict() for j in range(nsys[i])])
+            k += nsys[i]
+        return rc, out
 
 
 def version():

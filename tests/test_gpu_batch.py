@@ -1,0 +1,90 @@
+"""Batched solves of many independent instances against the same instances solved one
+by one (bitwise: the batched launch runs the same per-tile arithmetic) and against the
+oracle."""
+import numpy as np
+import pytest
+
+from oracle import assemble, solve
+from paper_2404_01407_amd import synth
+
+from gpu_helpers import relerr, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2404_01407_amd import fnlh
+    return fnlh
+
+
+def _instances(F, storage, specs):
+    out = []
+    for (shape, nb, nh, seed) in specs:
+        m = synth.passage_block(*shape, nb, seed=seed) if shape[0] > 0 else synth.multi_row(4, 6, 3, seed=seed)
+        Q = synth.flow_state(m, seed)
+        c = F.Context(m, storage=storage)
+        c.assemble_jacobian(to_dev(Q))
+        om = synth.omegas_single_zone(nh, nb) if m.n_zones == 1 else synth.omegas_multi_row(nh)
+        c.set_harmonics(om)
+        bs = [synth.rhs(m.n_cells, 50 + s, real=(s == 0)) for s in range(nh + 1)]
+        out.append((m, Q, c, om, bs))
+    return out
+
+
+SPECS = [((9, 6, 5), 24, 1, 1), ((12, 7, 6), 40, 3, 2), ((6, 5, 4), 60, 8, 3), ((15, 8, 8), 33, 4, 4),
+         ((7, 7, 3), 50, 2, 5), ((0, 0, 0), 36, 2, 6)]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_matches_per_instance(F, storage, graph):
+    import torch
+    insts = _instances(F, storage, SPECS)
+    B = F.Batch([c for (_, _, c, _, _) in insts])
+    systems = [list(range(len(bs))) for (_, _, _, _, bs) in insts]
+    xs = [[torch.zeros((m.n_cells, 6), dtype=torch.complex128, device="cuda") for _ in bs] for (m, _, _, _, bs) in insts]
+    bd = [[to_dev(b) for b in bs] for (_, _, _, _, bs) in insts]
+    st, reps = B.relax(systems, xs, bd, kind="dilu", max_sweeps=2000, rtol=1e-9, check_every=8, use_graph=graph)
+    assert st == 0
+    for i, (m, Q, c, om, bs) in enumerate(insts):
+        xi = [torch.zeros((m.n_cells, 6), dtype=torch.complex128, device="cuda") for _ in bs]
+        st1, rep1 = c.relax(systems[i], xi, [to_dev(b) for b in bs], kind="dilu", max_sweeps=2000, rtol=1e-9,
+                            check_every=8)
+        for j in range(len(bs)):
+            a, b = xs[i][j].cpu().numpy(), xi[j].cpu().numpy()
+            assert np.array_equal(a, b), (i, j)
+            assert reps[i][j]["sweeps"] == rep1[j]["sweeps"]
+            assert reps[i][j]["rel_res"] <= 1e-9
+    # one instance against the oracle's dense solve
+    m, Q, c, om, bs = insts[1]
+    K = assemble.assemble(m, Q)
+    xd = solve.dense_solve(K, m.volume, m.zone, om[2], bs[2])
+    tol = 1e-7 if storage == "f64" else 1e-7
+    assert relerr(xs[1][2].cpu().numpy(), xd) <= tol
+    B.close()
+    for (_, _, c, _, _) in insts:
+        c.close()
+
+
+def test_batch_repeated_solves_graph(F):
+    import torch
+    insts = _instances(F, "f32", SPECS[:4])
+    B = F.Batch([c for (_, _, c, _, _) in insts])
+    systems = [list(range(len(bs))) for (_, _, _, _, bs) in insts]
+    bd = [[to_dev(b) for b in bs] for (_, _, _, _, bs) in insts]
+    ref = None
+    for rep in range(3):
+        xs = [[torch.zeros((m.n_cells, 6), dtype=torch.complex128, device="cuda") for _ in bs] for (m, _, _, _, bs) in insts]
+        st, reps = B.relax(systems, xs, bd, kind="dilu", max_sweeps=2000, rtol=1e-8, check_every=16, use_graph=True)
+        got = [[x.cpu().numpy() for x in row] for row in xs]
+        if ref is None:
+            ref = got
+        else:
+            for r1, r2 in zip(ref, got):
+                for a, b in zip(r1, r2):
+                    assert np.array_equal(a, b)
+        torch.cuda.synchronize()
+    B.close()

@@ -259,6 +259,21 @@ int fnlh_stats_get(fnlh_ctx c, int32_t which, fnlh_kernel_stats* out);
 enum { FNLH_TUNE_SYS_PER_LANE = 0, FNLH_TUNE_LANES_PER_ROW = 1 };
 int fnlh_tune(fnlh_ctx c, int32_t param, int32_t value);
 
+/* Autotuner: times `sweeps` preconditioned sweeps of the first n_sys systems (constant
+ * right-hand side, zero start) for every feasible kernel shape (lanes per row 1/2/4 x
+ * systems per lane 1/2/4 of the sweep kernels) and keeps the fastest on the context
+ * (as fnlh_tune would).  Requires harmonics; the ordering is the context's.  out
+ * (may be NULL) receives the choice and the measured time per sweep. */
+typedef struct {
+  int32_t lanes_per_row;
+  int32_t sys_per_lane;
+  double us_per_sweep;     /* best: sum of sweep-pass kernel times per sweep (all systems) */
+  double us_per_sweep_default;  /* the automatic choice, for comparison */
+  int32_t candidates;      /* shapes timed */
+  int32_t pad_;
+} fnlh_tune_result;
+int fnlh_autotune(fnlh_ctx c, int32_t n_sys, int32_t sweeps, fnlh_tune_result* out, void* stream);
+
 /* Library version string. */
 const char* fnlh_version(void);
 

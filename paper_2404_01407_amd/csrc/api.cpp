@@ -756,6 +756,10 @@ struct fnlh_batch_s {
   double g_rtol = -1, g_divf = -1;
   std::vector<BatchGroup> groups;
   int n_items = 0;
+  // full lists (all batched instances) and the per-instance state ranges, for compaction
+  std::vector<WorkItem> all_w0, all_w1, all_items;
+  std::vector<std::pair<int, int>> group_key;  // (SW, P) per group
+  std::vector<int> inst_group, inst_base, inst_ns;  // per descriptor
 };
 
 namespace {
@@ -779,6 +783,39 @@ int bdalloc(fnlh_batch b, DevBuf& d, size_t bytes) {
   return FNLH_OK;
 }
 
+// Rebuild the device work lists keeping only the instances flagged live.
+int compact_lists(fnlh_batch B, const std::vector<char>& live, hipStream_t s) {
+  std::vector<WorkItem> w0, w1, it;
+  for (size_t g = 0; g < B->groups.size(); ++g) {
+    BatchGroup& G = B->groups[g];
+    G.w0_off = (int64_t)w0.size();
+    G.w1_off = (int64_t)w1.size();
+    for (const WorkItem& w : B->all_w0)
+      if (live[w.inst] && B->inst_group[w.inst] == (int)g) w0.push_back(w);
+    for (const WorkItem& w : B->all_w1)
+      if (live[w.inst] && B->inst_group[w.inst] == (int)g) w1.push_back(w);
+    G.w0_n = (int64_t)w0.size() - G.w0_off;
+    G.w1_n = (int64_t)w1.size() - G.w1_off;
+  }
+  for (const WorkItem& w : B->all_items)
+    if (live[w.inst]) it.push_back(w);
+  B->n_items = (int)it.size();
+  if (!w0.empty() &&
+      hipMemcpyAsync(B->work0.p, w0.data(), sizeof(WorkItem) * w0.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+    return bset_err(B, FNLH_E_HIP, "batch: upload failed");
+  if (!w1.empty() &&
+      hipMemcpyAsync(B->work1.p, w1.data(), sizeof(WorkItem) * w1.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+    return bset_err(B, FNLH_E_HIP, "batch: upload failed");
+  if (!it.empty() &&
+      hipMemcpyAsync(B->items.p, it.data(), sizeof(WorkItem) * it.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+    return bset_err(B, FNLH_E_HIP, "batch: upload failed");
+  if (B->exec) {  // the graph holds the old list lengths
+    (void)hipGraphExecDestroy(B->exec);
+    B->exec = nullptr;
+  }
+  return FNLH_OK;
+}
+
 void batched_sweep(fnlh_batch B, int storage, bool first, double rtol, double divf, hipStream_t s) {
   const InstDesc* d = (const InstDesc*)B->desc.p;
   const WorkItem* w0 = (const WorkItem*)B->work0.p;
@@ -791,50 +828,53 @@ void batched_sweep(fnlh_batch B, int storage, bool first, double rtol, double di
     launch_rb_batched(storage, g.SW, g.P, false, d, w0 + g.w0_off, g.w0_n, s);
 }
 
-// All systems of the batch to their stop criteria (states in B->st, initialised).
+// All systems of the batch to their stop criteria (states in B->st, initialised).  At
+// every check the work lists are compacted to the instances that still iterate.
 int batched_loop(fnlh_batch B, int storage, double rtol, double divf, int max_sweeps, int check_every, bool use_graph,
                  int total, hipStream_t s) {
+  const int nd = (int)B->inst_group.size();
+  std::vector<char> live(nd, 1);
+  int rc = compact_lists(B, live, s);
+  if (rc) return rc;
   const InstDesc* d = (const InstDesc*)B->desc.p;
   const WorkItem* w0 = (const WorkItem*)B->work0.p;
   for (const BatchGroup& g : B->groups)
     launch_rb_batched(storage, g.SW, g.P, false, d, w0 + g.w0_off, g.w0_n, s);
   int launched = 0;
-  bool graph = false;
   while (launched <= max_sweeps + 1) {
+    bool graph = false;
     if (launched == 0) {
       batched_sweep(B, storage, true, rtol, divf, s);
       launched = 1;
-      if (use_graph) {
-        if (B->exec && (B->g_K != check_every || B->g_storage != storage || B->g_rtol != rtol || B->g_divf != divf)) {
-          (void)hipGraphExecDestroy(B->exec);
+    }
+    if (use_graph) {
+      if (B->exec && (B->g_K != check_every || B->g_storage != storage || B->g_rtol != rtol || B->g_divf != divf)) {
+        (void)hipGraphExecDestroy(B->exec);
+        B->exec = nullptr;
+      }
+      if (!B->exec) {
+        if (!B->cap) (void)hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking);
+        hipGraph_t gr = nullptr;
+        bool ok = B->cap && hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+          for (int i = 0; i < check_every; ++i) batched_sweep(B, storage, false, rtol, divf, B->cap);
+          ok = hipStreamEndCapture(B->cap, &gr) == hipSuccess && gr;
+        }
+        if (ok) ok = hipGraphInstantiate(&B->exec, gr, nullptr, nullptr, 0) == hipSuccess;
+        if (gr) (void)hipGraphDestroy(gr);
+        (void)hipGetLastError();
+        if (ok) {
+          B->g_K = check_every;
+          B->g_storage = storage;
+          B->g_rtol = rtol;
+          B->g_divf = divf;
+        } else {
           B->exec = nullptr;
         }
-        if (!B->exec) {
-          if (!B->cap) (void)hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking);
-          hipGraph_t gr = nullptr;
-          bool ok = B->cap && hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
-          if (ok) {
-            for (int i = 0; i < check_every; ++i) batched_sweep(B, storage, false, rtol, divf, B->cap);
-            ok = hipStreamEndCapture(B->cap, &gr) == hipSuccess && gr;
-          }
-          if (ok) ok = hipGraphInstantiate(&B->exec, gr, nullptr, nullptr, 0) == hipSuccess;
-          if (gr) (void)hipGraphDestroy(gr);
-          (void)hipGetLastError();
-          if (ok) {
-            B->g_K = check_every;
-            B->g_storage = storage;
-            B->g_rtol = rtol;
-            B->g_divf = divf;
-          } else {
-            B->exec = nullptr;
-          }
-        }
-        graph = B->exec != nullptr;
       }
-      if (!graph)
-        for (int i = 1; i < check_every && launched <= max_sweeps + 1; ++i, ++launched)
-          batched_sweep(B, storage, false, rtol, divf, s);
-    } else if (graph) {
+      graph = B->exec != nullptr;
+    }
+    if (graph) {
       if (hipGraphLaunch(B->exec, s) != hipSuccess) return bset_err(B, FNLH_E_HIP, "batch: graph launch failed");
       launched += check_every;
     } else {
@@ -846,9 +886,19 @@ int batched_loop(fnlh_batch B, int storage, double rtol, double divf, int max_sw
     if (hipMemcpyAsync(B->h_st, B->st.p, sizeof(SysState) * total, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return bset_err(B, FNLH_E_HIP, "batch: state read-back failed");
-    bool any = false;
-    for (int k = 0; k < total; ++k) any |= B->h_st[k].active != 0;
+    bool any = false, changed = false;
+    for (int i = 0; i < nd; ++i) {
+      if (!live[i]) continue;
+      bool a = false;
+      for (int k = 0; k < B->inst_ns[i]; ++k) a |= B->h_st[B->inst_base[i] + k].active != 0;
+      if (!a) {
+        live[i] = 0;
+        changed = true;
+      }
+      any |= a;
+    }
     if (!any) break;
+    if (changed && (rc = compact_lists(B, live, s))) return rc;
   }
   return FNLH_OK;
 }
@@ -1266,18 +1316,27 @@ int fnlh_batch_relax(fnlh_batch B, const int32_t* n_sys, const int32_t* const* s
         for (int k = 0; k < sbs[i].n; ++k) items.push_back(WorkItem{di[i], k});
   }
   B->n_items = (int)items.size();
+  B->all_w0 = w0;
+  B->all_w1 = w1;
+  B->all_items = items;
+  B->inst_group.assign(desc.size(), 0);
+  B->inst_base.assign(desc.size(), 0);
+  B->inst_ns.assign(desc.size(), 0);
+  for (int i = 0; i < n; ++i) {
+    if (!batched[i]) continue;
+    int SW, P;
+    rb_shape(plans[i].cfg, sbs[i].n, SW, P);
+    for (size_t g = 0; g < B->groups.size(); ++g)
+      if (B->groups[g].SW == SW && B->groups[g].P == P) B->inst_group[di[i]] = (int)g;
+    B->inst_base[di[i]] = base[i];
+    B->inst_ns[di[i]] = n_sys[i];
+  }
   if (!desc.empty()) {
     if ((rc = bdalloc(B, B->desc, sizeof(InstDesc) * desc.size())) ||
         (rc = bdalloc(B, B->work0, sizeof(WorkItem) * std::max<size_t>(1, w0.size()))) ||
         (rc = bdalloc(B, B->work1, sizeof(WorkItem) * std::max<size_t>(1, w1.size()))) ||
         (rc = bdalloc(B, B->items, sizeof(WorkItem) * std::max<size_t>(1, items.size()))))
       return rc;
-    HIPC(nullptr, hipMemcpyAsync(B->work0.p, w0.data(), sizeof(WorkItem) * w0.size(), hipMemcpyHostToDevice, s),
-         "upload");
-    HIPC(nullptr, hipMemcpyAsync(B->work1.p, w1.data(), sizeof(WorkItem) * w1.size(), hipMemcpyHostToDevice, s),
-         "upload");
-    HIPC(nullptr, hipMemcpyAsync(B->items.p, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, s),
-         "upload");
     const RelaxPlan& P0 = plans[std::find(batched.begin(), batched.end(), 1) - batched.begin()];
     if (!reduced) {
       for (int i = 0; i < n; ++i) {
@@ -1355,6 +1414,97 @@ int fnlh_batch_relax(fnlh_batch B, const int32_t* n_sys, const int32_t* const* s
     fold(rc);
   }
   return worst;
+}
+
+int fnlh_autotune(fnlh_ctx c, int32_t n_sys, int32_t sweeps, fnlh_tune_result* out, void* stream) {
+  if (!c) return FNLH_E_ARG;
+  if (!c->have_matrix || c->n_sys == 0) return set_err(c, FNLH_E_ORDER, "autotune: matrix and harmonics first");
+  if (n_sys < 1 || n_sys > c->n_sys || n_sys > kMaxBatch || sweeps < 2)
+    return set_err(c, FNLH_E_ARG, "autotune: need 1 <= n_sys <= min(harmonics, 16), sweeps >= 2");
+  hipStream_t s = S(stream);
+  const size_t vb = (size_t)c->L.N * 12 * sizeof(double);
+  DevBuf xb, bb;
+  int rc;
+  if ((rc = dalloc(c, xb, vb * n_sys, "autotune alloc")) || (rc = dalloc(c, bb, vb * n_sys, "autotune alloc"))) {
+    dfree(xb);
+    dfree(bb);
+    return rc;
+  }
+  std::vector<double> ones(c->L.N * 12, 1.0);
+  std::vector<double*> xs(n_sys), bs(n_sys);
+  std::vector<int32_t> sys(n_sys);
+  for (int j = 0; j < n_sys; ++j) {
+    xs[j] = (double*)xb.p + (size_t)j * c->L.N * 12;
+    bs[j] = (double*)bb.p + (size_t)j * c->L.N * 12;
+    sys[j] = j;
+    (void)hipMemcpyAsync(bs[j], ones.data(), vb, hipMemcpyHostToDevice, s);
+  }
+  fnlh_relax_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.kind = FNLH_DILU;
+  o.max_sweeps = sweeps;
+  o.rtol = 0.0;
+  o.check_every = sweeps;
+  o.inner_sweeps = sweeps;
+  o.inner_rtol = 1e-30;
+  const int save_spw = c->lanes_per_sys, save_lpr = c->lanes_per_row;
+  const bool save_stats = c->stats_on;
+  const int save_period = c->stats_period;
+  struct Cand {
+    int lpr, spw;
+  };
+  std::vector<Cand> cands = {{0, 0}};
+  for (int lpr : {1, 2, 4})
+    for (int spw : {1, 2, 4})
+      if (lpr * spw <= 4 * ((n_sys + 3) / 4) * 4 && lpr <= std::max(1, n_sys)) cands.push_back({lpr, spw});
+  double best = 1e300, dflt = 0.0;
+  Cand pick{0, 0};
+  int tried = 0;
+  for (const Cand& cd : cands) {
+    c->lanes_per_sys = cd.spw;
+    c->lanes_per_row = cd.lpr;
+    // warm-up (factors, code), then a timed run
+    for (int rep = 0; rep < 2; ++rep) {
+      (void)hipMemsetAsync(xb.p, 0, vb * n_sys, s);
+      fnlh_stats_enable(c, rep == 1 ? 1 : 0);
+      rc = fnlh_relax(c, n_sys, sys.data(), xs.data(), bs.data(), &o, nullptr, stream);
+      if (rc < 0) break;
+    }
+    if (rc < 0) break;
+    double ms = 0.0;
+    int64_t sweeps_timed = 0;
+    for (int k = 0; k < FNLH_KSTAT_N; ++k) ms += c->st_ms[k];
+    sweeps_timed = c->st_n[FNLH_KSTAT_SWEEP_UPDATE] + c->st_n[FNLH_KSTAT_JACOBI] +
+                   (c->L.n_colours > 2 ? c->st_n[FNLH_KSTAT_FWD] / c->L.n_colours : 0);
+    if (c->L.n_colours == 1) sweeps_timed = c->st_n[FNLH_KSTAT_FWD];
+    const double us = sweeps_timed > 0 ? 1e3 * ms / (double)sweeps_timed : 1e300;
+    ++tried;
+    if (cd.lpr == 0 && cd.spw == 0) dflt = us;
+    if (us < best) {
+      best = us;
+      pick = cd;
+    }
+  }
+  c->stats_on = save_stats;
+  c->stats_period = save_period;
+  dfree(xb);
+  dfree(bb);
+  if (rc < 0) {
+    c->lanes_per_sys = save_spw;
+    c->lanes_per_row = save_lpr;
+    return rc;
+  }
+  c->lanes_per_sys = pick.spw;
+  c->lanes_per_row = pick.lpr;
+  if (out) {
+    out->lanes_per_row = pick.lpr;
+    out->sys_per_lane = pick.spw;
+    out->us_per_sweep = best;
+    out->us_per_sweep_default = dflt;
+    out->candidates = tried;
+    out->pad_ = 0;
+  }
+  return FNLH_OK;
 }
 
 int fnlh_tune(fnlh_ctx c, int32_t param, int32_t value) {

@@ -1135,13 +1135,15 @@ void launch_factor(int storage, bool dilu, const DevPattern& p, const void* offd
   });
 }
 
-// systems per lane: all of a small batch, else 4 (FP32 vectors) / 2 (FP64 vectors)
+// systems per lane for the one-row-per-lane kernels (general colouring, Jacobi): the
+// requested value, or automatic; never fewer than ceil(n / 4) so that at most four
+// waves per tile cover all n <= 16 systems.
 inline int lanes_p(const SweepCfg& c, int n) {
   int P = c.spw > 0 ? c.spw : (c.storage == kF64 ? 2 : 4);
-  if (P > 4) P = 4;
   if (P >= 4 && n <= 3) P = n <= 2 ? n : 4;
-  if (P == 3) P = 4;
-  return P;
+  const int need = (n + 3) / 4;
+  if (P < need) P = need;
+  return P <= 1 ? 1 : (P <= 2 ? 2 : 4);
 }
 inline dim3 block_for(int n, int P) {
   int nw = (n + P - 1) / P;
@@ -1168,6 +1170,9 @@ void rb_shape(const SweepCfg& c, int n, int& SW, int& P) {
   SW = c.lanes_per_row;
   if (SW <= 0) SW = n >= 4 ? 4 : (n >= 2 ? 2 : 1);
   if (SW != 1 && SW != 2 && SW != 4) SW = 4;
+  // SW * P must cover the n <= 16 systems with P <= 4
+  const int sw_need = n <= 4 ? 1 : (n <= 8 ? 2 : 4);
+  if (SW < sw_need) SW = sw_need;
   P = (n + SW - 1) / SW;
   if (c.spw > 0 && c.spw > P) P = c.spw;
   P = P <= 1 ? 1 : (P <= 2 ? 2 : 4);

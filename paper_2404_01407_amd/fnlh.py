@@ -59,6 +59,11 @@ class Report(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("lanes_per_row", C.c_int32), ("sys_per_lane", C.c_int32), ("us_per_sweep", C.c_double),
+                ("us_per_sweep_default", C.c_double), ("candidates", C.c_int32), ("pad_", C.c_int32)]
+
+
 class KernelStats(C.Structure):
     _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("alg_bytes", C.c_double)]
 
@@ -87,6 +92,7 @@ def _load():
         "fnlh_version": (C.c_char_p, []),
         "fnlh_stats_enable": (I32, [P, I32]),
         "fnlh_tune": (I32, [P, I32, I32]),
+        "fnlh_autotune": (I32, [P, I32, I32, C.POINTER(TuneResult), V]),
         "fnlh_batch_create": (I32, [C.POINTER(P), I32, V]),
         "fnlh_batch_destroy": (I32, [P]),
         "fnlh_batch_relax": (I32, [P, V, V, V, V, C.POINTER(RelaxOpts), V, V]),
@@ -259,8 +265,41 @@ class Context:
         return rc, [r.as_dict() for r in rep]
 
     def tune(self, sys_per_lane=0, lanes_per_row=0):
+        """Set the sweep-kernel shape (0 = automatic)."""
         self._check(LIB.fnlh_tune(self.h, 0, int(sys_per_lane)))
         self._check(LIB.fnlh_tune(self.h, 1, int(lanes_per_row)))
+
+    def autotune(self, n_sys, sweeps=16, cache=None, stream=None):
+        """Pick the sweep-kernel shape by timing (native autotuner).  ``cache``: path of a
+        JSON file keyed by mesh signature, storage, system count and device; a hit
+        applies the stored choice without timing."""
+        import json
+        key = None
+        if cache:
+            import torch
+            col, nc = self.ordering()
+            dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
+            key = f"{self.n}:{self.E}:{nc}:{int(np.bincount(col).max())}:{self.storage}:{n_sys}:{dev}"
+            try:
+                db = json.load(open(cache))
+            except (OSError, ValueError):
+                db = {}
+            if key in db:
+                r = db[key]
+                self.tune(r["sys_per_lane"], r["lanes_per_row"])
+                return dict(r, cached=True)
+        res = TuneResult()
+        self._check(LIB.fnlh_autotune(self.h, int(n_sys), int(sweeps), C.byref(res), _stream(stream)))
+        out = {k: getattr(res, k) for k, _ in res._fields_ if k != "pad_"}
+        if cache:
+            try:
+                db = json.load(open(cache))
+            except (OSError, ValueError):
+                db = {}
+            db[key] = out
+            with open(cache, "w") as f:
+                json.dump(db, f, indent=1)
+        return dict(out, cached=False)
 
     def stats_enable(self, on=True, period=1):
         self._check(LIB.fnlh_stats_enable(self.h, int(period) if on else 0))

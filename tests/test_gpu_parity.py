@@ -359,3 +359,30 @@ def test_first_colour_solve_without_pivoting(F):
             x_or, _ = solve.richardson(KK, m.volume, m.zone, om[s], bs[s], col, "SGS", rtol=0.0, max_sweeps=12)
             assert relerr(xs[s], x_or) <= ITER_TOL
         c.close()
+
+
+def test_every_kernel_shape_covers_all_systems(F):
+    # 9 systems: every (lanes per row, systems per lane) request must still sweep all
+    # of them, and the per-system arithmetic does not depend on the shape
+    m, Q, K = case(shape=(10, 7, 5), seed=12)
+    om = synth.omegas_single_zone(8)
+    bs = [synth.rhs(m.n_cells, s, real=(s == 0)) for s in range(9)]
+    ref = None
+    for lpr in (0, 1, 2, 4):
+        for spw in (0, 1, 2, 4):
+            c = _ctx(F, m, Q)
+            c.set_harmonics(om)
+            c.tune(spw, lpr)
+            st, rep, xs = _solve(c, list(range(9)), bs, kind="dilu", max_sweeps=15, rtol=0.0)
+            assert all(r["sweeps"] == 15 for r in rep), (lpr, spw)
+            if ref is None:
+                ref = xs
+                col, _ = c.ordering()
+                for s in (0, 4, 8):
+                    x_or, _ = solve.richardson(K, m.volume, m.zone, om[s], bs[s], col, "DILU", rtol=0.0,
+                                               max_sweeps=15)
+                    assert relerr(xs[s], x_or) <= ITER_TOL
+            else:
+                for a, b in zip(ref, xs):
+                    assert np.array_equal(a, b), (lpr, spw)
+            c.close()

@@ -63,7 +63,6 @@ enum {
   FNLH_OK = 0,
   FNLH_NOT_CONVERGED = 1, /* max_sweeps reached above the tolerance            */
   FNLH_DIVERGED = 2,      /* NaN/Inf or ||r|| > div_factor ||r0||               */
-  FNLH_FELL_BACK = 3,     /* reserved: a learned step was rejected              */
   FNLH_E_ARG = -1,        /* invalid argument                                   */
   FNLH_E_MESH = -2,       /* invalid mesh (ids, duplicates, volumes, colouring) */
   FNLH_E_SINGULAR = -3,   /* a diagonal block to invert is singular / not finite */
@@ -155,7 +154,7 @@ int fnlh_residual(fnlh_ctx c, int32_t sys, const double* x, const double* b, dou
                   double* norm2, void* stream);
 
 typedef struct {
-  int32_t kind;          /* FNLH_DILU | FNLH_SGS | FNLH_JACOBI                              */
+  int32_t kind;          /* FNLH_DILU | FNLH_SGS | FNLH_JACOBI | FNLH_LEARNED               */
   int32_t max_sweeps;    /* >= 0: total preconditioned sweeps per system                  */
   double rtol;           /* stop when ||b - K_s x|| <= rtol ||b - K_s x0||                 */
   int32_t check_every;   /* sweeps between host read-backs of the device stop flags (>=1) */
@@ -163,21 +162,31 @@ typedef struct {
   double inner_rtol;     /* reduced precision: inner relative tolerance (0 = auto)          */
   double div_factor;     /* DIVERGED when ||r|| > div_factor ||r0|| (0 = 1e3)               */
   int32_t use_graph;     /* 1: replay check_every sweeps as one captured hipGraph            */
-  int32_t pad_;
+  int32_t learn_every;   /* FNLH_LEARNED: sweeps between learned corrections (0 = 16)       */
 } fnlh_relax_opts;
 
 typedef struct {
   int32_t sweeps;        /* preconditioned sweeps applied                                 */
   int32_t outer;         /* FP64 outer corrections (reduced precision), else 0            */
   int32_t status;        /* FNLH_OK | FNLH_NOT_CONVERGED | FNLH_DIVERGED                  */
-  int32_t fallbacks;     /* reserved                                                       */
+  int32_t fallbacks;     /* FNLH_LEARNED: learned corrections rejected (plain sweeps kept)   */
   double rel_res;        /* ||b - K_s x|| / ||b - K_s x0|| of the returned x, outer operator */
   double res0;           /* ||b - K_s x0||                                                 */
   double t_factor_ms;    /* time in factorisation (device events)                          */
   double t_sweep_ms;     /* time in sweeps and residuals (device events)                   */
+  int32_t learned;       /* FNLH_LEARNED: learned corrections accepted                      */
+  int32_t pad_;
 } fnlh_sys_report;
 
-/* Solve n systems: sys[j] indexes the omega table, x[j] (in: x0, out: x) and b[j] are
+/* FNLH_LEARNED runs the FNLH_DILU sweeps of this call and, every learn_every sweeps
+ * (at every FP64 correction in reduced precision, with at most learn_every inner
+ * sweeps), a correction by the network attached with fnlh_nn_create: with r the FP64
+ * residual of x and dx the network's output for r, x <- x + alpha dx with the complex
+ * alpha minimising ||r - alpha K_s dx||.  The FP64 residual judges every correction:
+ * one that is not finite or lowers ||r||^2 by less than 0.1% is rejected (counted in
+ * fallbacks) and the sweeps go on from the unchanged x.
+ *
+ * Solve n systems: sys[j] indexes the omega table, x[j] (in: x0, out: x) and b[j] are
  * device [N][6] complex128 user-order buffers (host arrays of n device pointers).
  * Returns the worst per-system status (FNLH_OK if all converged) or an error.
  * The tolerance test is evaluated on the residual of the previous iterate, computed
@@ -273,6 +282,51 @@ typedef struct {
   int32_t pad_;
 } fnlh_tune_result;
 int fnlh_autotune(fnlh_ctx c, int32_t n_sys, int32_t sweeps, fnlh_tune_result* out, void* stream);
+
+/* ---- learned preconditioner (a project addition; the paper has no learned part).
+ * A two-layer per-edge message-passing network on the context's cell graph maps the
+ * residual r of system s to a correction dx ~ K_s^-1 r:
+ *   sigma = sqrt(sum |r|^2 / (12 N)),  z_i = (K_ii + i omega V_i I)^-1 r_i,
+ *   u_i = [r_i, z_i] / sigma (24 reals),  g_ij = K_ij z_j / sigma (12 reals),
+ *   m_ij = relu(W1^T [u_i; u_j; g_ij]) (60 -> 64),  a_i = sum_j m_ij,
+ *   h_i = relu(W2^T [u_i; a_i]) (88 -> 64),  p_ij = relu(W3^T [h_i; h_j]) (128 -> 64),
+ *   c_i = sum_j p_ij,  q_i = relu(W4^T [h_i; c_i]) (128 -> 64),  d_i = W5^T q_i (64 -> 12),
+ *   dx_i = sigma d_i;   complex values as (re, im) pairs; no biases, so dx(a r) = a dx(r).
+ * Weights: FNLH_NN_PARAMS FP32 values W1..W5, each row-major [in][out]; the kernels use
+ * BF16 copies with FP32 accumulation on the matrix cores.  Training loss of a pair
+ * (r, e), e the error x* - x that left residual r: ||d - e/sigma||^2 / ||e/sigma||^2,
+ * averaged over a batch; Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 master.
+ * The network belongs to one context (its mesh, matrix and harmonics) and is freed with
+ * it at the latest. */
+typedef struct fnlh_nn_s* fnlh_nn;
+enum { FNLH_NN_PARAMS = 26624 };
+/* Attach a network to c (one per context; FNLH_E_ORDER if c has one).  Weights unset. */
+int fnlh_nn_create(fnlh_nn* out, fnlh_ctx c);
+int fnlh_nn_destroy(fnlh_nn nn);
+/* host [FNLH_NN_PARAMS] FP32 weights in / out; setting them resets Adam.  Errors:
+ * FNLH_E_ARG for non-finite values. */
+int fnlh_nn_set_weights(fnlh_nn nn, const float* w);
+int fnlh_nn_get_weights(fnlh_nn nn, float* w);
+/* dx = network(r) for system sys: r, dx device [N][6] complex128 user order. */
+int fnlh_nn_apply(fnlh_nn nn, int32_t sys, const double* r, double* dx, void* stream);
+/* Mean loss and its gradient over n pairs (device [N][6] user-order r[k], e[k]);
+ * grad host [FNLH_NN_PARAMS] or NULL, loss host or NULL.  Synchronises the stream. */
+int fnlh_nn_loss_grad(fnlh_nn nn, int32_t n, const int32_t* sys, const double* const* r,
+                      const double* const* e, float* grad, double* loss, void* stream);
+/* Keep n training pairs (r[k], e[k]) of system sys[k] on the device (FP32 copies; the
+ * caller's buffers may be reused after the call's stream work).  n_pairs: count held. */
+int fnlh_nn_add_pairs(fnlh_nn nn, int32_t n, const int32_t* sys, const double* const* r,
+                      const double* const* e, void* stream);
+int fnlh_nn_clear_pairs(fnlh_nn nn);
+int fnlh_nn_pairs(fnlh_nn nn, int64_t* n_pairs);
+/* steps Adam steps on batches of `batch` pairs drawn with replacement (splitmix64 from
+ * seed); loss host [steps] (may be NULL) receives each step's batch loss before its
+ * update.  Synchronises the stream. */
+int fnlh_nn_train(fnlh_nn nn, int32_t steps, int32_t batch, float lr, uint64_t seed, float* loss,
+                  void* stream);
+/* Matrix-core check: out = A B for 64x64 BF16 operands (host a [64][64], host bt = B^T
+ * [64][64], raw BF16 bits), FP32 out [64][64], computed by the network's tile routine. */
+int fnlh_nn_selftest(fnlh_ctx c, const uint16_t* a, const uint16_t* bt, float* out);
 
 /* Library version string. */
 const char* fnlh_version(void);

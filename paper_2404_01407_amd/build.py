@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libfnlh.so")
-SOURCES = ["kernels.hip", "nn.hip", "api.cpp", "layout.cpp"]
+SOURCES = ["kernels.hip", "nn.hip", "api.cpp", "nn.cpp", "layout.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

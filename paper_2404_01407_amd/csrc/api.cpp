@@ -9,9 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/fnlh.h"
-#include "kernels.h"
-#include "layout.h"
+#include "ctx.h"
 
 using namespace fnlh;
 
@@ -19,101 +17,9 @@ namespace {
 
 thread_local std::string g_create_error;
 
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-};
-
 }  // namespace
 
-struct GraphEntry;
-
-struct fnlh_ctx_s {
-  Layout L;
-  int dev = 0;
-  int storage = FNLH_F64;
-  int outer = FNLH_OUTER_EXACT;
-  int factor_slots_opt = 0;
-  int lanes_per_sys = 0;  // systems per lane of the sweep kernels (0 = automatic)
-  int lanes_per_row = 0;  // lanes sharing a row in the two-colour pass (0 = automatic)
-  std::string err;
-
-  // pattern (device)
-  DevBuf tile_nrows, tile_width, tile_slot0, ent_nbr, ent_edge, ent_rev, vol, zone, iperm, perm, edge_ent, bf_ptr,
-      bf_idx, area, bface_area;
-  // matrix
-  DevBuf offd, diag, offd64, diag64;  // *64: FP64 shadow of raw blocks in reduced precision
-  DevBuf state, bstate;
-  bool have_matrix = false, assembled = false, have_shadow = false;
-  double eps = 0.6, sigma = 50.0;
-  int scheme = FNLH_IMPLICIT;
-  // systems
-  int n_sys = 0;
-  std::vector<double> omega;
-  DevBuf d_omega;
-  // factors
-  int n_slots = 0;
-  DevBuf dinv;
-  std::vector<int> slot_sys, slot_kind;
-  // scratch
-  int vec_cap = 0;
-  DevBuf x64, b64, r64, y, rhs32, d32, partial, st, st_outer;
-  SysState* h_st = nullptr;
-  DevBuf d_err;
-  int* h_err = nullptr;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  // diagonal blocks strictly diagonally dominant (first-colour solve without pivoting)
-  bool dom_known = false, dom = false;
-  DevBuf d_dom;
-  int* h_dom = nullptr;
-  // captured sweep graphs
-  hipStream_t cap = nullptr;
-  std::vector<GraphEntry*> graphs;
-  bool graph_broken = false;
-  // kernel statistics
-  bool stats_on = false;
-  int stats_period = 1;  // time the launches of every stats_period-th sweep
-  std::vector<hipEvent_t> evpool;
-  double st_ms[FNLH_KSTAT_N] = {0};
-  double st_bytes[FNLH_KSTAT_N] = {0};
-  int64_t st_n[FNLH_KSTAT_N] = {0};
-
-  DevPattern pat() const {
-    DevPattern p;
-    p.NP = L.NP;
-    p.n_tiles = L.n_tiles;
-    p.tile_nrows = (const int32_t*)tile_nrows.p;
-    p.tile_width = (const int32_t*)tile_width.p;
-    p.tile_slot0 = (const int64_t*)tile_slot0.p;
-    p.ent_nbr = (const int32_t*)ent_nbr.p;
-    p.ent_edge = (const int32_t*)ent_edge.p;
-    p.ent_rev = (const int32_t*)ent_rev.p;
-    p.vol = (const double*)vol.p;
-    p.zone = (const int32_t*)zone.p;
-    p.omega = (const double*)d_omega.p;
-    p.n_zones = L.n_zones;
-    return p;
-  }
-  DevFlow flow() const {
-    DevFlow f;
-    f.state = (const double*)state.p;
-    f.area = (const double*)area.p;
-    f.bf_ptr = (const int32_t*)bf_ptr.p;
-    f.bf_idx = (const int32_t*)bf_idx.p;
-    f.bface_area = (const double*)bface_area.p;
-    f.bstate = (const double*)bstate.p;
-    f.diag_scale = scheme == FNLH_IMPLICIT ? 1.0 + 1.0 / (eps * sigma) : 1.0;
-    f.offdiag = scheme == FNLH_IMPLICIT ? 1 : 0;
-    return f;
-  }
-  size_t block_bytes() const { return storage == FNLH_F64 ? 8 : storage == FNLH_F32 ? 4 : 2; }
-  int64_t slot_elems_storage() const {
-    return storage == FNLH_F64 ? 18 * 64 * 2 : storage == FNLH_F32 ? 9 * 64 * 4 : 5 * 64 * 8;
-  }
-  size_t tv_bytes() const { return storage == FNLH_F64 ? 8 : 4; }
-};
-
-namespace {
+namespace fnlh {
 
 int set_err(fnlh_ctx c, int code, const std::string& m) {
   if (c) c->err = m; else g_create_error = m;
@@ -124,12 +30,6 @@ int hip_fail(fnlh_ctx c, hipError_t e, const char* what) {
   std::string m = std::string(what) + ": " + hipGetErrorString(e);
   return set_err(c, e == hipErrorOutOfMemory ? FNLH_E_OOM : FNLH_E_HIP, m);
 }
-
-#define HIPC(c, expr, what)                     \
-  do {                                          \
-    hipError_t _e = (expr);                     \
-    if (_e != hipSuccess) return hip_fail(c, _e, what); \
-  } while (0)
 
 int dalloc(fnlh_ctx c, DevBuf& b, size_t bytes, const char* what) {
   if (b.p) {
@@ -143,6 +43,37 @@ int dalloc(fnlh_ctx c, DevBuf& b, size_t bytes, const char* what) {
   return FNLH_OK;
 }
 
+void dfree(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+int check_launch(fnlh_ctx c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, what);
+  return FNLH_OK;
+}
+
+void outer_residual_of(fnlh_ctx c, int ns, const SysBatch& sb, const double* x, const double* b, double* r,
+                       hipStream_t s) {
+  DevPattern p = c->pat();
+  double* part = (double*)c->partial.p;
+  if (c->storage == FNLH_F64) {
+    launch_resid_stored(kF64, p, c->offd.p, c->diag.p, x, b, r, ns, sb, part, s);
+  } else if (c->outer == FNLH_OUTER_STORED) {
+    launch_resid_stored(c->storage, p, c->offd.p, c->diag.p, x, b, r, ns, sb, part, s);
+  } else if (c->assembled) {
+    launch_resid_mfree(p, c->flow(), x, b, r, ns, sb, part, s);
+  } else {
+    launch_resid_stored(kF64, p, c->offd64.p, c->diag64.p, x, b, r, ns, sb, part, s);
+  }
+}
+
+}  // namespace fnlh
+
+namespace {
+
 template <typename T> int dupload(fnlh_ctx c, DevBuf& b, const std::vector<T>& v, const char* what) {
   int rc = dalloc(c, b, v.size() * sizeof(T), what);
   if (rc) return rc;
@@ -150,19 +81,7 @@ template <typename T> int dupload(fnlh_ctx c, DevBuf& b, const std::vector<T>& v
   return FNLH_OK;
 }
 
-void dfree(DevBuf& b) {
-  if (b.p) (void)hipFree(b.p);
-  b.p = nullptr;
-  b.bytes = 0;
-}
-
 inline hipStream_t S(void* s) { return (hipStream_t)s; }
-
-int check_launch(fnlh_ctx c, const char* what) {
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(c, e, what);
-  return FNLH_OK;
-}
 
 int ensure_vectors(fnlh_ctx c, int n) {
   if (n <= c->vec_cap) return FNLH_OK;
@@ -218,19 +137,7 @@ void invalidate_factors(fnlh_ctx c) {
 
 // outer FP64 operator residual of the systems of sb (x64, b64 -> r, partial)
 void outer_residual(fnlh_ctx c, int ns, const SysBatch& sb, double* r, hipStream_t s) {
-  DevPattern p = c->pat();
-  const double* x = (const double*)c->x64.p;
-  const double* b = (const double*)c->b64.p;
-  double* part = (double*)c->partial.p;
-  if (c->storage == FNLH_F64) {
-    launch_resid_stored(kF64, p, c->offd.p, c->diag.p, x, b, r, ns, sb, part, s);
-  } else if (c->outer == FNLH_OUTER_STORED) {
-    launch_resid_stored(c->storage, p, c->offd.p, c->diag.p, x, b, r, ns, sb, part, s);
-  } else if (c->assembled) {
-    launch_resid_mfree(p, c->flow(), x, b, r, ns, sb, part, s);
-  } else {
-    launch_resid_stored(kF64, p, c->offd64.p, c->diag64.p, x, b, r, ns, sb, part, s);
-  }
+  outer_residual_of(c, ns, sb, (const double*)c->x64.p, (const double*)c->b64.p, r, s);
 }
 
 int factor_batch(fnlh_ctx c, const SysBatch& sb, bool dilu, hipStream_t s) {
@@ -504,9 +411,12 @@ GraphEntry* get_graph(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, int K,
 // Iterate until every system of sb is inactive.  States must be initialised.  Sweeps
 // after the first are replayed from a captured graph of check_every sweeps when
 // use_graph is set (direct launches otherwise, or if capture is unavailable).
+// chunk: launch about max_sweeps sweeps (whole graph replays) and return with the states
+// read back; otherwise run until every system has stopped (max_sweeps plus one to retire).
 int sweep_loop(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, const SysBatch& sb, void* x, const void* b,
                void* y, SysState* st, double rtol, double divf, int max_sweeps, int check_every, bool use_graph,
-               hipStream_t s) {
+               hipStream_t s, bool chunk = false) {
+  const int limit = chunk ? max_sweeps : max_sweeps + 2;
   Timer T{c, s, {}, 0, true, nullptr};
   if (path == kPathRB) {
     DevPattern p = c->pat();
@@ -519,7 +429,7 @@ int sweep_loop(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, const SysBatc
   SysState* h = c->h_st;
   GraphEntry* g = nullptr;
   // each system needs at most max_sweeps sweeps plus one to retire
-  while (launched <= max_sweeps + 1) {
+  while (launched < limit) {
     if (launched == 0) {
       one_sweep(c, path, cfg, ns, sb, x, b, y, st, 1, rtol, divf, s, T);
       launched = 1;
@@ -527,7 +437,7 @@ int sweep_loop(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, const SysBatc
       // nodes cannot be queried for elapsed time here, so timing runs launch directly
       if (use_graph && !c->stats_on) g = get_graph(c, path, cfg, ns, check_every, sb, x, b, y, st, rtol, divf);
       if (!g) {
-        for (int i = 1; i < check_every && launched <= max_sweeps + 1; ++i, ++launched)
+        for (int i = 1; i < check_every && launched < limit; ++i, ++launched)
           one_sweep(c, path, cfg, ns, sb, x, b, y, st, launched + 1, rtol, divf, s, T);
       }
     } else if (g) {
@@ -537,7 +447,7 @@ int sweep_loop(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, const SysBatc
                                                                        r.a, r.b, 0.0});
       launched += check_every;
     } else {
-      for (int i = 0; i < check_every && launched <= max_sweeps + 1; ++i, ++launched)
+      for (int i = 0; i < check_every && launched < limit; ++i, ++launched)
         one_sweep(c, path, cfg, ns, sb, x, b, y, st, launched + 1, rtol, divf, s, T);
     }
     int rc = check_launch(c, "sweep launch");
@@ -592,7 +502,8 @@ int ensure_dominance(fnlh_ctx c, hipStream_t s) {
 struct RelaxPlan {
   Path path = kPathRB;
   SweepCfg cfg;
-  bool reduced = false, use_graph = false;
+  bool reduced = false, use_graph = false, learned = false;
+  int learn_every = 16;
   double inner_rtol = 1e-4, divf = 1e3;
   int inner_max = 1, check_every = 8, fkind = 0, G = 1;
   std::vector<double> tf, ts;
@@ -608,8 +519,9 @@ int relax_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, c
     if (sys[j] < 0 || sys[j] >= c->n_sys) return set_err(c, FNLH_E_ARG, "relax: system out of range");
     if (!x[j] || !b[j]) return set_err(c, FNLH_E_ARG, "relax: null vector");
   }
-  if (o->kind != FNLH_DILU && o->kind != FNLH_SGS && o->kind != FNLH_JACOBI)
+  if (o->kind != FNLH_DILU && o->kind != FNLH_SGS && o->kind != FNLH_JACOBI && o->kind != FNLH_LEARNED)
     return set_err(c, FNLH_E_ARG, "relax: unsupported preconditioner kind");
+  if (o->learn_every < 0) return set_err(c, FNLH_E_ARG, "relax: learn_every >= 0");
   if (o->max_sweeps < 0 || !(o->rtol >= 0.0)) return set_err(c, FNLH_E_ARG, "relax: need max_sweeps >= 0, rtol >= 0");
   P.check_every = o->check_every > 0 ? o->check_every : 8;
   P.divf = o->div_factor > 0 ? o->div_factor : 1e3;
@@ -617,8 +529,12 @@ int relax_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, c
   P.inner_rtol = o->inner_rtol > 0 ? o->inner_rtol : (c->storage == FNLH_F32 ? 1e-4 : 1e-2);
   P.inner_max = o->inner_sweeps > 0 ? o->inner_sweeps : std::max(1, o->max_sweeps);
   P.use_graph = o->use_graph != 0;
+  P.learned = o->kind == FNLH_LEARNED;
+  P.learn_every = o->learn_every > 0 ? o->learn_every : 16;
+  if (P.learned && P.reduced) P.inner_max = std::min(P.inner_max, P.learn_every);
   int rc;
   if ((rc = ensure_vectors(c, n))) return rc;
+  if (P.learned && (rc = nn_relax_begin(c, n, s))) return rc;
   const int want_slots = c->factor_slots_opt > 0 ? c->factor_slots_opt : std::min<int>(c->n_sys, 64);
   if ((rc = ensure_slots(c, want_slots))) return rc;
   if ((rc = ensure_dominance(c, s))) return rc;
@@ -628,7 +544,7 @@ int relax_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, c
     launch_to_internal(p, (const int32_t*)c->iperm.p, b[j], (double*)c->b64.p, 12, n, j, s);
   }
   P.path = o->kind == FNLH_JACOBI ? kPathJacobi : (c->L.n_colours == 2 ? kPathRB : kPathGeneral);
-  P.fkind = o->kind == FNLH_DILU ? 0 : 1;
+  P.fkind = (o->kind == FNLH_DILU || o->kind == FNLH_LEARNED) ? 0 : 1;
   P.cfg.storage = c->storage;
   P.cfg.spw = c->lanes_per_sys;
   P.cfg.lanes_per_row = c->lanes_per_row;
@@ -713,7 +629,8 @@ int relax_finish_launch(fnlh_ctx c, int n, const int32_t* sys, double* const* x,
   return check_launch(c, "final launch");
 }
 
-int relax_reports(const SysState* h, int n, const RelaxPlan& P, const fnlh_relax_opts* o, fnlh_sys_report* rep) {
+int relax_reports(const SysState* h, int n, const RelaxPlan& P, const fnlh_relax_opts* o, fnlh_sys_report* rep,
+                  const int* counts = nullptr) {
   int worst = FNLH_OK;
   for (int j = 0; j < n; ++j) {
     const SysState& S0 = h[j];
@@ -729,6 +646,10 @@ int relax_reports(const SysState* h, int n, const RelaxPlan& P, const fnlh_relax
     R.status = status;
     R.t_factor_ms = P.tf.empty() ? 0.0 : P.tf[j];
     R.t_sweep_ms = P.ts.empty() ? 0.0 : P.ts[j];
+    if (counts) {
+      R.learned = counts[2 * j];
+      R.fallbacks = counts[2 * j + 1];
+    }
     if (rep) rep[j] = R;
     if (status == FNLH_DIVERGED || (status == FNLH_NOT_CONVERGED && worst == FNLH_OK)) worst = status;
   }
@@ -831,7 +752,8 @@ void batched_sweep(fnlh_batch B, int storage, bool first, double rtol, double di
 // All systems of the batch to their stop criteria (states in B->st, initialised).  At
 // every check the work lists are compacted to the instances that still iterate.
 int batched_loop(fnlh_batch B, int storage, double rtol, double divf, int max_sweeps, int check_every, bool use_graph,
-                 int total, hipStream_t s) {
+                 int total, hipStream_t s, bool chunk = false) {
+  const int limit = chunk ? max_sweeps : max_sweeps + 2;
   const int nd = (int)B->inst_group.size();
   std::vector<char> live(nd, 1);
   int rc = compact_lists(B, live, s);
@@ -841,7 +763,7 @@ int batched_loop(fnlh_batch B, int storage, double rtol, double divf, int max_sw
   for (const BatchGroup& g : B->groups)
     launch_rb_batched(storage, g.SW, g.P, false, d, w0 + g.w0_off, g.w0_n, s);
   int launched = 0;
-  while (launched <= max_sweeps + 1) {
+  while (launched < limit) {
     bool graph = false;
     if (launched == 0) {
       batched_sweep(B, storage, true, rtol, divf, s);
@@ -878,7 +800,7 @@ int batched_loop(fnlh_batch B, int storage, double rtol, double divf, int max_sw
       if (hipGraphLaunch(B->exec, s) != hipSuccess) return bset_err(B, FNLH_E_HIP, "batch: graph launch failed");
       launched += check_every;
     } else {
-      for (int i = 0; i < check_every && launched <= max_sweeps + 1; ++i, ++launched)
+      for (int i = 0; i < check_every && launched < limit; ++i, ++launched)
         batched_sweep(B, storage, false, rtol, divf, s);
     }
     hipError_t e = hipGetLastError();
@@ -984,6 +906,7 @@ int fnlh_create(fnlh_ctx* out, const fnlh_mesh* mesh, const fnlh_options* opts) 
 
 int fnlh_destroy(fnlh_ctx c) {
   if (!c) return FNLH_E_ARG;
+  nn_release(c);
   DevBuf* bufs[] = {&c->tile_nrows, &c->tile_width, &c->tile_slot0, &c->ent_nbr, &c->ent_edge, &c->ent_rev,
                     &c->vol, &c->zone, &c->iperm, &c->perm, &c->edge_ent, &c->bf_ptr, &c->bf_idx, &c->area,
                     &c->bface_area, &c->offd, &c->diag, &c->offd64, &c->diag64, &c->state, &c->bstate,
@@ -1142,9 +1065,25 @@ int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, cons
       outer_residual(c, n, sb, nullptr, s);
       launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, 1, st, kReduceInit, 0, 0,
                     o->max_sweeps, s);
-      if ((rc = sweep_loop(c, P.path, P.cfg, n, sb, c->x64.p, c->b64.p, c->y.p, st, o->rtol, P.divf, o->max_sweeps,
-                           P.check_every, P.use_graph, s)))
-        return rc;
+      if (!P.learned) {
+        if ((rc = sweep_loop(c, P.path, P.cfg, n, sb, c->x64.p, c->b64.p, c->y.p, st, o->rtol, P.divf,
+                             o->max_sweeps, P.check_every, P.use_graph, s)))
+          return rc;
+      } else {
+        // chunks of sweeps, each followed by a learned correction of the active systems
+        for (int done = 0;;) {
+          const int chunk = std::min(P.learn_every, o->max_sweeps + 1 - done);
+          if ((rc = sweep_loop(c, P.path, P.cfg, n, sb, c->x64.p, c->b64.p, c->y.p, st, o->rtol, P.divf,
+                               std::max(chunk, 1), P.check_every, P.use_graph, s, true)))
+            return rc;
+          done += std::max(chunk, 1);
+          bool any = false;
+          for (int k = 0; k < sb.n; ++k) any |= c->h_st[sb.vslot[k]].active != 0;
+          if (!any || done > o->max_sweeps) break;
+          if ((rc = nn_learned_step(c, n, sb, (double*)c->x64.p, (const double*)c->b64.p, nullptr, st, s)))
+            return rc;
+        }
+      }
     } else {
       outer_residual(c, n, sb, (double*)c->r64.p, s);
       launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, 1, so, kReduceInit, 0, 0,
@@ -1162,6 +1101,9 @@ int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, cons
                              P.inner_max, P.check_every, P.use_graph, s)))
           return rc;
         inner_to_outer(c, n, sb, st, so, o->rtol, P.divf, s);
+        if (P.learned &&
+            (rc = nn_learned_step(c, n, sb, (double*)c->x64.p, (const double*)c->b64.p, (double*)c->r64.p, so, s)))
+          return rc;
       }
     }
     HIPC(c, hipEventRecord(c->ev[2], s), "event");
@@ -1178,7 +1120,12 @@ int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, cons
   if ((rc = relax_finish_launch(c, n, sys, x, fin, s))) return rc;
   HIPC(c, hipMemcpyAsync(c->h_st, fin, sizeof(SysState) * n, hipMemcpyDeviceToHost, s), "read states");
   HIPC(c, hipStreamSynchronize(s), "final sync");
-  return relax_reports(c->h_st, n, P, o, rep);
+  std::vector<int> counts;
+  if (P.learned) {
+    counts.assign(2 * n, 0);
+    if ((rc = nn_relax_counts(c, n, counts.data(), s))) return rc;
+  }
+  return relax_reports(c->h_st, n, P, o, rep, P.learned ? counts.data() : nullptr);
 }
 
 

@@ -1,0 +1,146 @@
+// Private host-side state of a context, shared by the C ABI (api.cpp) and the learned
+// preconditioner (nn.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/fnlh.h"
+#include "kernels.h"
+#include "layout.h"
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct GraphEntry;
+struct fnlh_nn_s;
+
+using fnlh::DevPattern;
+using fnlh::Layout;
+using fnlh::SysState;
+using fnlh::DevFlow;
+
+struct fnlh_ctx_s {
+  Layout L;
+  int dev = 0;
+  int storage = FNLH_F64;
+  int outer = FNLH_OUTER_EXACT;
+  int factor_slots_opt = 0;
+  int lanes_per_sys = 0;  // systems per lane of the sweep kernels (0 = automatic)
+  int lanes_per_row = 0;  // lanes sharing a row in the two-colour pass (0 = automatic)
+  std::string err;
+
+  // pattern (device)
+  DevBuf tile_nrows, tile_width, tile_slot0, ent_nbr, ent_edge, ent_rev, vol, zone, iperm, perm, edge_ent, bf_ptr,
+      bf_idx, area, bface_area;
+  // matrix
+  DevBuf offd, diag, offd64, diag64;  // *64: FP64 shadow of raw blocks in reduced precision
+  DevBuf state, bstate;
+  bool have_matrix = false, assembled = false, have_shadow = false;
+  double eps = 0.6, sigma = 50.0;
+  int scheme = FNLH_IMPLICIT;
+  // systems
+  int n_sys = 0;
+  std::vector<double> omega;
+  DevBuf d_omega;
+  // factors
+  int n_slots = 0;
+  DevBuf dinv;
+  std::vector<int> slot_sys, slot_kind;
+  // scratch
+  int vec_cap = 0;
+  DevBuf x64, b64, r64, y, rhs32, d32, partial, st, st_outer;
+  SysState* h_st = nullptr;
+  DevBuf d_err;
+  int* h_err = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // diagonal blocks strictly diagonally dominant (first-colour solve without pivoting)
+  bool dom_known = false, dom = false;
+  DevBuf d_dom;
+  int* h_dom = nullptr;
+  // captured sweep graphs
+  hipStream_t cap = nullptr;
+  std::vector<GraphEntry*> graphs;
+  bool graph_broken = false;
+  // learned preconditioner attached to this context (nn.cpp)
+  fnlh_nn_s* nn = nullptr;
+  // kernel statistics
+  bool stats_on = false;
+  int stats_period = 1;  // time the launches of every stats_period-th sweep
+  std::vector<hipEvent_t> evpool;
+  double st_ms[FNLH_KSTAT_N] = {0};
+  double st_bytes[FNLH_KSTAT_N] = {0};
+  int64_t st_n[FNLH_KSTAT_N] = {0};
+
+  DevPattern pat() const {
+    DevPattern p;
+    p.NP = L.NP;
+    p.n_tiles = L.n_tiles;
+    p.tile_nrows = (const int32_t*)tile_nrows.p;
+    p.tile_width = (const int32_t*)tile_width.p;
+    p.tile_slot0 = (const int64_t*)tile_slot0.p;
+    p.ent_nbr = (const int32_t*)ent_nbr.p;
+    p.ent_edge = (const int32_t*)ent_edge.p;
+    p.ent_rev = (const int32_t*)ent_rev.p;
+    p.vol = (const double*)vol.p;
+    p.zone = (const int32_t*)zone.p;
+    p.omega = (const double*)d_omega.p;
+    p.n_zones = L.n_zones;
+    return p;
+  }
+  DevFlow flow() const {
+    DevFlow f;
+    f.state = (const double*)state.p;
+    f.area = (const double*)area.p;
+    f.bf_ptr = (const int32_t*)bf_ptr.p;
+    f.bf_idx = (const int32_t*)bf_idx.p;
+    f.bface_area = (const double*)bface_area.p;
+    f.bstate = (const double*)bstate.p;
+    f.diag_scale = scheme == FNLH_IMPLICIT ? 1.0 + 1.0 / (eps * sigma) : 1.0;
+    f.offdiag = scheme == FNLH_IMPLICIT ? 1 : 0;
+    return f;
+  }
+  size_t block_bytes() const { return storage == FNLH_F64 ? 8 : storage == FNLH_F32 ? 4 : 2; }
+  int64_t slot_elems_storage() const {
+    return storage == FNLH_F64 ? 18 * 64 * 2 : storage == FNLH_F32 ? 9 * 64 * 4 : 5 * 64 * 8;
+  }
+  size_t tv_bytes() const { return storage == FNLH_F64 ? 8 : 4; }
+};
+
+namespace fnlh {
+
+// helpers of the ABI layer (api.cpp)
+int set_err(fnlh_ctx c, int code, const std::string& m);
+int hip_fail(fnlh_ctx c, hipError_t e, const char* what);
+int dalloc(fnlh_ctx c, DevBuf& b, size_t bytes, const char* what);
+void dfree(DevBuf& b);
+int check_launch(fnlh_ctx c, const char* what);
+// outer FP64 operator residual of the systems of sb (x, b internal -> r, c->partial)
+void outer_residual_of(fnlh_ctx c, int ns, const SysBatch& sb, const double* x, const double* b, double* r,
+                       hipStream_t s);
+
+// Learned preconditioner inside fnlh_relax (nn.cpp).  nn_relax_begin checks that a
+// network with weights is attached, sizes its scratch for ns systems and clears the
+// per-system step counters.  nn_learned_step corrects the systems of sb that are still
+// active in st: x <- x + alpha dx, r <- r - alpha K dx, with dx the network's output for
+// the FP64 residual r (computed from x and b into scratch when r is null) and alpha the
+// complex step minimising ||r - alpha K dx||; a step that is not finite or lowers
+// ||r||^2 by less than the acceptance fraction is rejected (x, r unchanged).
+// nn_relax_counts copies [ns][2] (accepted, rejected) to the host.
+int nn_relax_begin(fnlh_ctx c, int ns, hipStream_t s);
+int nn_learned_step(fnlh_ctx c, int ns, const SysBatch& sb, double* x, const double* b, double* r,
+                    const SysState* st, hipStream_t s);
+int nn_relax_counts(fnlh_ctx c, int ns, int* host_counts, hipStream_t s);
+void nn_release(fnlh_ctx c);  // context destroyed: detach its network
+
+}  // namespace fnlh
+
+#define HIPC(c, expr, what)                              \
+  do {                                                   \
+    hipError_t _e = (expr);                              \
+    if (_e != hipSuccess) return hip_fail(c, _e, what);  \
+  } while (0)

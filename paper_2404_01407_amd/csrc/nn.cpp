@@ -1,0 +1,435 @@
+// C ABI of the learned preconditioner (include/fnlh.h, "learned preconditioner") and
+// its use inside fnlh_relax.  The network, its FP32 master weights, Adam moments and the
+// training pairs live on the device; every step (features, forward, backward, gradient
+// reduction, Adam, the corrected update) is a kernel of nn.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "ctx.h"
+#include "nn.h"
+
+using namespace fnlh;
+
+struct fnlh_nn_s {
+  fnlh_ctx c = nullptr;
+  DevBuf master, mom1, mom2, grad, wt, w;  // FP32 master/moments/gradient [kNnParams], bf16 padded weights
+  DevBuf u, h, d, sc, part;                // inference
+  DevBuf ehat, dc, dh, gpart, lpart, loss;  // training
+  DevBuf pool;                             // pairs: [cap][2][NP][12] FP32 (r, e), internal order
+  std::vector<int32_t> pair_sys;
+  int64_t n_pairs = 0, cap_pairs = 0;
+  DevBuf rr, xt, rn, part4, alpha, counts;  // learned step scratch
+  int step_cap = 0;
+  int G = 0;
+  int adam_t = 0;
+  bool weights_set = false;
+};
+
+namespace {
+
+constexpr float kB1 = 0.9f, kB2 = 0.999f, kEps = 1e-8f;
+constexpr double kAccept = 1e-3;  // minimum fractional drop of ||r||^2 for a learned step
+constexpr int kMaxG = 512;        // workgroups of the backward kernels (gradient partials)
+
+inline hipStream_t S(void* s) { return (hipStream_t)s; }
+
+int nn_err(fnlh_nn nn, int code, const char* m) { return nn->c ? set_err(nn->c, code, m) : code; }
+
+NnBufs bufs(fnlh_nn nn) {
+  NnBufs B;
+  B.wt = (const uint16_t*)nn->wt.p;
+  B.w = (const uint16_t*)nn->w.p;
+  B.u = (uint16_t*)nn->u.p;
+  B.h = (uint16_t*)nn->h.p;
+  B.d = (float*)nn->d.p;
+  B.ehat = (float*)nn->ehat.p;
+  B.dc = (float*)nn->dc.p;
+  B.dh = (float*)nn->dh.p;
+  B.part = (double*)nn->part.p;
+  B.sc = (NnScalars*)nn->sc.p;
+  B.gpart = (float*)nn->gpart.p;
+  B.lpart = (double*)nn->lpart.p;
+  return B;
+}
+
+void free_all(fnlh_nn nn) {
+  DevBuf* b[] = {&nn->master, &nn->mom1, &nn->mom2, &nn->grad, &nn->wt, &nn->w, &nn->u, &nn->h, &nn->d,
+                 &nn->sc, &nn->part, &nn->ehat, &nn->dc, &nn->dh, &nn->gpart, &nn->lpart, &nn->loss,
+                 &nn->pool, &nn->rr, &nn->xt, &nn->rn, &nn->part4, &nn->alpha, &nn->counts};
+  for (DevBuf* x : b) dfree(*x);
+  nn->n_pairs = nn->cap_pairs = 0;
+  nn->pair_sys.clear();
+  nn->step_cap = 0;
+}
+
+int ready(fnlh_nn nn) {
+  if (!nn) return FNLH_E_ARG;
+  if (!nn->c) return FNLH_E_ORDER;
+  fnlh_ctx c = nn->c;
+  if (!c->have_matrix || c->n_sys == 0) return set_err(c, FNLH_E_ORDER, "network: matrix and harmonics first");
+  if (!nn->weights_set) return set_err(c, FNLH_E_ORDER, "network: weights not set");
+  return FNLH_OK;
+}
+
+int ensure_train(fnlh_nn nn) {
+  if (nn->ehat.p) return FNLH_OK;
+  fnlh_ctx c = nn->c;
+  const size_t NP = (size_t)c->L.NP;
+  int rc;
+  if ((rc = dalloc(c, nn->ehat, NP * 16 * sizeof(float), "alloc network"))) return rc;
+  if ((rc = dalloc(c, nn->dc, NP * 64 * sizeof(float), "alloc network"))) return rc;
+  if ((rc = dalloc(c, nn->dh, NP * 64 * sizeof(float), "alloc network"))) return rc;
+  if ((rc = dalloc(c, nn->gpart, (size_t)nn->G * kNnPadded * sizeof(float), "alloc network"))) return rc;
+  if ((rc = dalloc(c, nn->lpart, (size_t)nn->G * sizeof(double), "alloc network"))) return rc;
+  HIPC(c, hipMemset(nn->ehat.p, 0, nn->ehat.bytes), "zero");
+  return FNLH_OK;
+}
+
+// features + forward of one residual (and the training target when e is given)
+void features(fnlh_nn nn, int sys, const NnVec& r, const NnVec* e, hipStream_t s) {
+  fnlh_ctx c = nn->c;
+  NnBufs B = bufs(nn);
+  if (!e) B.ehat = nullptr;
+  nn_launch_features(c->storage, c->pat(), c->diag.p, sys, r, e, c->L.N, B, true, s);
+}
+
+NnVec user_vec(fnlh_ctx c, const double* v) {
+  NnVec x;
+  x.d64 = v;
+  x.iperm = (const int32_t*)c->iperm.p;
+  return x;
+}
+
+// gradient of the batch-mean loss of n samples into nn->grad (device) and the loss
+// into *loss_dev; samples given by a callback filling (sys, r, e)
+template <typename F> int batch_grad(fnlh_nn nn, int n, F sample, double* loss_dev, hipStream_t s) {
+  fnlh_ctx c = nn->c;
+  int rc;
+  if ((rc = ensure_train(nn))) return rc;
+  launch_fill_zero(nn->gpart.p, nn->gpart.bytes, s);
+  launch_fill_zero(nn->lpart.p, nn->lpart.bytes, s);
+  const DevPattern p = c->pat();
+  const NnBufs B = bufs(nn);
+  for (int k = 0; k < n; ++k) {
+    int sys = 0;
+    NnVec r, e;
+    sample(k, sys, r, e);
+    features(nn, sys, r, &e, s);
+    nn_launch_forward_l1(c->storage, p, c->offd.p, B, s);
+    nn_launch_backward(c->storage, p, c->offd.p, B, nn->G, 1.0 / n, s);
+  }
+  nn_launch_grad_reduce(B, nn->G, (float*)nn->grad.p, loss_dev, s);
+  return check_launch(c, "network gradient launch");
+}
+
+}  // namespace
+
+namespace fnlh {
+
+void nn_release(fnlh_ctx c) {
+  if (!c || !c->nn) return;
+  free_all(c->nn);
+  c->nn->c = nullptr;
+  c->nn = nullptr;
+}
+
+int nn_relax_begin(fnlh_ctx c, int ns, hipStream_t s) {
+  fnlh_nn nn = c->nn;
+  if (!nn) return set_err(c, FNLH_E_ORDER, "relax: FNLH_LEARNED needs a network (fnlh_nn_create)");
+  int rc = ready(nn);
+  if (rc) return rc;
+  if (ns > nn->step_cap) {
+    const size_t v = (size_t)ns * c->L.NP * 12 * sizeof(double);
+    if ((rc = dalloc(c, nn->rr, v, "alloc learned step"))) return rc;
+    if ((rc = dalloc(c, nn->xt, v, "alloc learned step"))) return rc;
+    if ((rc = dalloc(c, nn->rn, v, "alloc learned step"))) return rc;
+    if ((rc = dalloc(c, nn->alpha, (size_t)ns * 2 * sizeof(double), "alloc learned step"))) return rc;
+    if ((rc = dalloc(c, nn->counts, (size_t)ns * 2 * sizeof(int), "alloc learned step"))) return rc;
+    HIPC(c, hipMemset(nn->rr.p, 0, v), "zero");
+    HIPC(c, hipMemset(nn->xt.p, 0, v), "zero");
+    HIPC(c, hipMemset(nn->rn.p, 0, v), "zero");
+    nn->step_cap = ns;
+  }
+  if (!nn->part4.p && (rc = dalloc(c, nn->part4, (size_t)c->L.n_tiles * 4 * sizeof(double), "alloc learned step")))
+    return rc;
+  launch_fill_zero(nn->counts.p, (size_t)ns * 2 * sizeof(int), s);
+  return check_launch(c, "learned step setup");
+}
+
+int nn_learned_step(fnlh_ctx c, int ns, const SysBatch& sb, double* x, const double* b, double* r,
+                    const SysState* st, hipStream_t s) {
+  fnlh_nn nn = c->nn;
+  const DevPattern p = c->pat();
+  double* res = r;
+  if (!res) {
+    res = (double*)nn->rr.p;
+    outer_residual_of(c, ns, sb, x, b, res, s);
+  }
+  const NnBufs B = bufs(nn);
+  for (int k = 0; k < sb.n; ++k) {
+    NnVec rv;
+    rv.d64 = res;
+    rv.ns = ns;
+    rv.vs = sb.vslot[k];
+    features(nn, sb.orow[k], rv, nullptr, s);
+    nn_launch_forward(c->storage, p, c->offd.p, B, s);
+    NnOut o;
+    o.out = (double*)nn->xt.p;
+    o.base = x;
+    o.ns = ns;
+    o.vs = sb.vslot[k];
+    nn_launch_output(p, B, o, s);
+  }
+  outer_residual_of(c, ns, sb, (const double*)nn->xt.p, b, (double*)nn->rn.p, s);
+  for (int k = 0; k < sb.n; ++k)
+    nn_launch_step(p, x, (const double*)nn->xt.p, res, (const double*)nn->rn.p, ns, sb.vslot[k], st,
+                   (double*)nn->part4.p, (double*)nn->alpha.p, (int*)nn->counts.p, kAccept, s);
+  return check_launch(c, "learned step launch");
+}
+
+int nn_relax_counts(fnlh_ctx c, int ns, int* host_counts, hipStream_t s) {
+  HIPC(c, hipMemcpyAsync(host_counts, c->nn->counts.p, (size_t)ns * 2 * sizeof(int), hipMemcpyDeviceToHost, s),
+       "read counts");
+  HIPC(c, hipStreamSynchronize(s), "counts sync");
+  return FNLH_OK;
+}
+
+}  // namespace fnlh
+
+extern "C" {
+
+int fnlh_nn_create(fnlh_nn* out, fnlh_ctx c) {
+  if (!out || !c) return FNLH_E_ARG;
+  *out = nullptr;
+  if (c->nn) return set_err(c, FNLH_E_ORDER, "network: context already has one");
+  fnlh_nn nn = new fnlh_nn_s();
+  nn->c = c;
+  const size_t NP = (size_t)c->L.NP;
+  nn->G = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxG, c->L.n_tiles));
+  int rc = 0;
+  auto fail = [&](int code) {
+    free_all(nn);
+    delete nn;
+    return code;
+  };
+  if ((rc = dalloc(c, nn->master, kNnParams * sizeof(float), "alloc network"))) return fail(rc);
+  if ((rc = dalloc(c, nn->mom1, kNnParams * sizeof(float), "alloc network"))) return fail(rc);
+  if ((rc = dalloc(c, nn->mom2, kNnParams * sizeof(float), "alloc network"))) return fail(rc);
+  if ((rc = dalloc(c, nn->grad, kNnParams * sizeof(float), "alloc network"))) return fail(rc);
+  if ((rc = dalloc(c, nn->wt, kNnPadded * sizeof(uint16_t), "alloc network"))) return fail(rc);
+  if ((rc = dalloc(c, nn->w, kNnPadded * sizeof(uint16_t), "alloc network"))) return fail(rc);
+  if ((rc = dalloc(c, nn->u, NP * kNnU * sizeof(uint16_t), "alloc network"))) return fail(rc);
+  if ((rc = dalloc(c, nn->h, NP * 64 * sizeof(uint16_t), "alloc network"))) return fail(rc);
+  if ((rc = dalloc(c, nn->d, NP * 16 * sizeof(float), "alloc network"))) return fail(rc);
+  if ((rc = dalloc(c, nn->sc, sizeof(NnScalars), "alloc network"))) return fail(rc);
+  if ((rc = dalloc(c, nn->part, (size_t)c->L.n_tiles * sizeof(double), "alloc network"))) return fail(rc);
+  if (hipMemset(nn->d.p, 0, nn->d.bytes) != hipSuccess) return fail(FNLH_E_HIP);
+  c->nn = nn;
+  *out = nn;
+  return FNLH_OK;
+}
+
+int fnlh_nn_destroy(fnlh_nn nn) {
+  if (!nn) return FNLH_E_ARG;
+  if (nn->c) nn->c->nn = nullptr;
+  free_all(nn);
+  delete nn;
+  return FNLH_OK;
+}
+
+int fnlh_nn_set_weights(fnlh_nn nn, const float* w) {
+  if (!nn || !w) return FNLH_E_ARG;
+  if (!nn->c) return FNLH_E_ORDER;
+  fnlh_ctx c = nn->c;
+  for (int i = 0; i < kNnParams; ++i)
+    if (!std::isfinite(w[i])) return set_err(c, FNLH_E_ARG, "network: weights must be finite");
+  HIPC(c, hipMemcpy(nn->master.p, w, kNnParams * sizeof(float), hipMemcpyHostToDevice), "upload weights");
+  HIPC(c, hipMemset(nn->mom1.p, 0, nn->mom1.bytes), "zero");
+  HIPC(c, hipMemset(nn->mom2.p, 0, nn->mom2.bytes), "zero");
+  nn_launch_cast((const float*)nn->master.p, (uint16_t*)nn->wt.p, (uint16_t*)nn->w.p, nullptr);
+  HIPC(c, hipDeviceSynchronize(), "cast weights");
+  nn->adam_t = 0;
+  nn->weights_set = true;
+  return check_launch(c, "cast weights");
+}
+
+int fnlh_nn_get_weights(fnlh_nn nn, float* w) {
+  if (!nn || !w) return FNLH_E_ARG;
+  if (!nn->c) return FNLH_E_ORDER;
+  HIPC(nn->c, hipMemcpy(w, nn->master.p, kNnParams * sizeof(float), hipMemcpyDeviceToHost), "read weights");
+  return FNLH_OK;
+}
+
+int fnlh_nn_apply(fnlh_nn nn, int32_t sys, const double* r, double* dx, void* stream) {
+  int rc = ready(nn);
+  if (rc) return rc;
+  fnlh_ctx c = nn->c;
+  if (sys < 0 || sys >= c->n_sys) return set_err(c, FNLH_E_ARG, "network: system out of range");
+  if (!r || !dx) return set_err(c, FNLH_E_ARG, "network: null vector");
+  hipStream_t s = S(stream);
+  features(nn, sys, user_vec(c, r), nullptr, s);
+  nn_launch_forward(c->storage, c->pat(), c->offd.p, bufs(nn), s);
+  NnOut o;
+  o.out = dx;
+  o.iperm = (const int32_t*)c->iperm.p;
+  nn_launch_output(c->pat(), bufs(nn), o, s);
+  return check_launch(c, "network apply launch");
+}
+
+int fnlh_nn_loss_grad(fnlh_nn nn, int32_t n, const int32_t* sys, const double* const* r, const double* const* e,
+                      float* grad, double* loss, void* stream) {
+  int rc = ready(nn);
+  if (rc) return rc;
+  fnlh_ctx c = nn->c;
+  if (n < 1 || !sys || !r || !e) return set_err(c, FNLH_E_ARG, "network: bad arguments");
+  for (int k = 0; k < n; ++k) {
+    if (sys[k] < 0 || sys[k] >= c->n_sys) return set_err(c, FNLH_E_ARG, "network: system out of range");
+    if (!r[k] || !e[k]) return set_err(c, FNLH_E_ARG, "network: null vector");
+  }
+  hipStream_t s = S(stream);
+  if (!nn->loss.p && (rc = dalloc(c, nn->loss, sizeof(double), "alloc network"))) return rc;
+  rc = batch_grad(
+      nn, n,
+      [&](int k, int& sy, NnVec& rv, NnVec& ev) {
+        sy = sys[k];
+        rv = user_vec(c, r[k]);
+        ev = user_vec(c, e[k]);
+      },
+      (double*)nn->loss.p, s);
+  if (rc) return rc;
+  if (grad) HIPC(c, hipMemcpyAsync(grad, nn->grad.p, kNnParams * sizeof(float), hipMemcpyDeviceToHost, s), "read");
+  double l = 0.0;
+  HIPC(c, hipMemcpyAsync(&l, nn->loss.p, sizeof(double), hipMemcpyDeviceToHost, s), "read");
+  HIPC(c, hipStreamSynchronize(s), "gradient sync");
+  if (loss) *loss = l;
+  return FNLH_OK;
+}
+
+int fnlh_nn_add_pairs(fnlh_nn nn, int32_t n, const int32_t* sys, const double* const* r, const double* const* e,
+                      void* stream) {
+  if (!nn) return FNLH_E_ARG;
+  if (!nn->c) return FNLH_E_ORDER;
+  fnlh_ctx c = nn->c;
+  if (c->n_sys == 0) return set_err(c, FNLH_E_ORDER, "network: harmonics first");
+  if (n < 1 || !sys || !r || !e) return set_err(c, FNLH_E_ARG, "network: bad arguments");
+  for (int k = 0; k < n; ++k) {
+    if (sys[k] < 0 || sys[k] >= c->n_sys) return set_err(c, FNLH_E_ARG, "network: system out of range");
+    if (!r[k] || !e[k]) return set_err(c, FNLH_E_ARG, "network: null vector");
+  }
+  hipStream_t s = S(stream);
+  const size_t pair = (size_t)2 * c->L.NP * 12;  // floats
+  if (nn->n_pairs + n > nn->cap_pairs) {
+    const int64_t cap = std::max<int64_t>(nn->n_pairs + n, 2 * nn->cap_pairs);
+    DevBuf nb;
+    int rc = dalloc(c, nb, (size_t)cap * pair * sizeof(float), "alloc training pairs");
+    if (rc) return rc;
+    if (nn->n_pairs)
+      HIPC(c, hipMemcpyAsync(nb.p, nn->pool.p, (size_t)nn->n_pairs * pair * sizeof(float), hipMemcpyDeviceToDevice,
+                             s),
+           "grow pairs");
+    HIPC(c, hipStreamSynchronize(s), "grow pairs");
+    dfree(nn->pool);
+    nn->pool = nb;
+    nn->cap_pairs = cap;
+  }
+  const DevPattern p = c->pat();
+  for (int k = 0; k < n; ++k) {
+    float* dst = (float*)nn->pool.p + (size_t)(nn->n_pairs + k) * pair;
+    nn_launch_pack32(p, (const int32_t*)c->iperm.p, r[k], dst, s);
+    nn_launch_pack32(p, (const int32_t*)c->iperm.p, e[k], dst + pair / 2, s);
+    nn->pair_sys.push_back(sys[k]);
+  }
+  nn->n_pairs += n;
+  return check_launch(c, "store pairs");
+}
+
+int fnlh_nn_clear_pairs(fnlh_nn nn) {
+  if (!nn) return FNLH_E_ARG;
+  nn->n_pairs = 0;
+  nn->pair_sys.clear();
+  return FNLH_OK;
+}
+
+int fnlh_nn_pairs(fnlh_nn nn, int64_t* n_pairs) {
+  if (!nn || !n_pairs) return FNLH_E_ARG;
+  *n_pairs = nn->n_pairs;
+  return FNLH_OK;
+}
+
+int fnlh_nn_train(fnlh_nn nn, int32_t steps, int32_t batch, float lr, uint64_t seed, float* loss, void* stream) {
+  int rc = ready(nn);
+  if (rc) return rc;
+  fnlh_ctx c = nn->c;
+  if (steps < 0 || batch < 1 || !(lr > 0.f)) return set_err(c, FNLH_E_ARG, "train: need steps >= 0, batch >= 1, lr > 0");
+  if (nn->n_pairs == 0) return set_err(c, FNLH_E_ORDER, "train: no training pairs");
+  if (steps == 0) return FNLH_OK;
+  hipStream_t s = S(stream);
+  DevBuf hist;
+  if ((rc = dalloc(c, hist, (size_t)steps * sizeof(double), "alloc loss history"))) return rc;
+  const size_t pair = (size_t)2 * c->L.NP * 12;
+  uint64_t z = seed;
+  auto next = [&]() {  // splitmix64
+    z += 0x9e3779b97f4a7c15ull;
+    uint64_t q = z;
+    q = (q ^ (q >> 30)) * 0xbf58476d1ce4e5b9ull;
+    q = (q ^ (q >> 27)) * 0x94d049bb133111ebull;
+    return q ^ (q >> 31);
+  };
+  for (int t = 0; t < steps && !rc; ++t) {
+    rc = batch_grad(
+        nn, batch,
+        [&](int, int& sy, NnVec& rv, NnVec& ev) {
+          const int64_t i = (int64_t)(next() % (uint64_t)nn->n_pairs);
+          const float* base = (const float*)nn->pool.p + (size_t)i * pair;
+          sy = nn->pair_sys[i];
+          rv = NnVec{};
+          rv.f32 = base;
+          ev = NnVec{};
+          ev.f32 = base + pair / 2;
+        },
+        (double*)hist.p + t, s);
+    if (rc) break;
+    nn->adam_t++;
+    nn_launch_adam((float*)nn->master.p, (float*)nn->mom1.p, (float*)nn->mom2.p, (const float*)nn->grad.p,
+                   kNnParams, lr, kB1, kB2, kEps, nn->adam_t, s);
+    nn_launch_cast((const float*)nn->master.p, (uint16_t*)nn->wt.p, (uint16_t*)nn->w.p, s);
+    rc = check_launch(c, "train launch");
+  }
+  if (!rc && loss) {
+    std::vector<double> h(steps);
+    hipError_t e = hipMemcpyAsync(h.data(), hist.p, (size_t)steps * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = hip_fail(c, e, "read loss history");
+    for (int t = 0; t < steps; ++t) loss[t] = (float)h[t];
+  }
+  if (!rc) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = hip_fail(c, e, "train sync");
+  }
+  dfree(hist);
+  return rc;
+}
+
+int fnlh_nn_selftest(fnlh_ctx c, const uint16_t* a, const uint16_t* bt, float* out) {
+  if (!c || !a || !bt || !out) return FNLH_E_ARG;
+  DevBuf da, db, dc;
+  int rc = 0;
+  if ((rc = dalloc(c, da, 64 * 64 * 2, "selftest"))) return rc;
+  if ((rc = dalloc(c, db, 64 * 64 * 2, "selftest"))) return rc;
+  if ((rc = dalloc(c, dc, 64 * 64 * 4, "selftest"))) return rc;
+  hipError_t e = hipMemcpy(da.p, a, 64 * 64 * 2, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(db.p, bt, 64 * 64 * 2, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    nn_launch_selftest((const uint16_t*)da.p, (const uint16_t*)db.p, (float*)dc.p, nullptr);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpy(out, dc.p, 64 * 64 * 4, hipMemcpyDeviceToHost);
+  dfree(da);
+  dfree(db);
+  dfree(dc);
+  if (e != hipSuccess) return hip_fail(c, e, "selftest");
+  return FNLH_OK;
+}
+
+}  // extern "C"

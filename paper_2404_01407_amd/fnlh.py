@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libfnlh.so")
 
 # status codes (fnlh.h)
-OK, NOT_CONVERGED, DIVERGED, FELL_BACK = 0, 1, 2, 3
+OK, NOT_CONVERGED, DIVERGED = 0, 1, 2
 E_ARG, E_MESH, E_SINGULAR, E_OOM, E_HIP, E_ORDER = -1, -2, -3, -4, -5, -6
 STORAGE = {"f64": 0, "f32": 1, "bf16": 2}
 OUTER = {"exact": 0, "stored": 1}
@@ -47,16 +47,17 @@ class Options(C.Structure):
 class RelaxOpts(C.Structure):
     _fields_ = [("kind", C.c_int32), ("max_sweeps", C.c_int32), ("rtol", C.c_double),
                 ("check_every", C.c_int32), ("inner_sweeps", C.c_int32), ("inner_rtol", C.c_double),
-                ("div_factor", C.c_double), ("use_graph", C.c_int32), ("pad_", C.c_int32)]
+                ("div_factor", C.c_double), ("use_graph", C.c_int32), ("learn_every", C.c_int32)]
 
 
 class Report(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("outer", C.c_int32), ("status", C.c_int32),
                 ("fallbacks", C.c_int32), ("rel_res", C.c_double), ("res0", C.c_double),
-                ("t_factor_ms", C.c_double), ("t_sweep_ms", C.c_double)]
+                ("t_factor_ms", C.c_double), ("t_sweep_ms", C.c_double), ("learned", C.c_int32),
+                ("pad_", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
 
 
 class TuneResult(C.Structure):
@@ -98,6 +99,17 @@ def _load():
         "fnlh_batch_relax": (I32, [P, V, V, V, V, C.POINTER(RelaxOpts), V, V]),
         "fnlh_batch_last_error": (C.c_char_p, [P]),
         "fnlh_stats_get": (I32, [P, I32, C.POINTER(KernelStats)]),
+        "fnlh_nn_create": (I32, [C.POINTER(P), P]),
+        "fnlh_nn_destroy": (I32, [P]),
+        "fnlh_nn_set_weights": (I32, [P, V]),
+        "fnlh_nn_get_weights": (I32, [P, V]),
+        "fnlh_nn_apply": (I32, [P, I32, V, V, V]),
+        "fnlh_nn_loss_grad": (I32, [P, I32, V, V, V, V, C.POINTER(D), V]),
+        "fnlh_nn_add_pairs": (I32, [P, I32, V, V, V, V]),
+        "fnlh_nn_clear_pairs": (I32, [P]),
+        "fnlh_nn_pairs": (I32, [P, C.POINTER(I64)]),
+        "fnlh_nn_train": (I32, [P, I32, I32, C.c_float, C.c_uint64, V, V]),
+        "fnlh_nn_selftest": (I32, [P, V, V, V]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -247,7 +259,7 @@ class Context:
         return n2.value
 
     def relax(self, systems, xs, bs, kind="dilu", max_sweeps=500, rtol=1e-8, check_every=8,
-              inner_sweeps=0, inner_rtol=0.0, div_factor=0.0, use_graph=False, stream=None):
+              inner_sweeps=0, inner_rtol=0.0, div_factor=0.0, use_graph=False, learn_every=0, stream=None):
         """Solve (K + i omega_s V) x = b for each s in ``systems``; xs (in: x0, out: x) and
         bs are complex128 CUDA tensors [N, 6].  Returns (status, list of report dicts)."""
         n = len(systems)
@@ -257,7 +269,7 @@ class Context:
         xp = (C.c_void_p * n)(*[_ptr(t) for t in xs])
         bp = (C.c_void_p * n)(*[_ptr(t) for t in bs])
         o = RelaxOpts(KIND[kind], int(max_sweeps), float(rtol), int(check_every), int(inner_sweeps),
-                      float(inner_rtol), float(div_factor), int(bool(use_graph)), 0)
+                      float(inner_rtol), float(div_factor), int(bool(use_graph)), int(learn_every))
         rep = (Report * n)()
         rc = LIB.fnlh_relax(self.h, n, _ptr(sysarr), C.cast(xp, C.c_void_p), C.cast(bp, C.c_void_p),
                             C.byref(o), C.cast(rep, C.c_void_p), _stream(stream))
@@ -349,7 +361,7 @@ class Batch:
             pass
 
     def relax(self, systems, xs, bs, kind="dilu", max_sweeps=500, rtol=1e-8, check_every=8, inner_sweeps=0,
-              inner_rtol=0.0, div_factor=0.0, use_graph=True, stream=None):
+              inner_rtol=0.0, div_factor=0.0, use_graph=True, learn_every=0, stream=None):
         """systems[i]: system ids of instance i; xs[i][j], bs[i][j]: complex128 CUDA
         tensors [N_i, 6].  Returns (status, reports per instance)."""
         n = len(self.contexts)
@@ -369,7 +381,7 @@ class Batch:
             x_ptrs[i] = C.cast(xa, C.c_void_p).value
             b_ptrs[i] = C.cast(ba, C.c_void_p).value
         o = RelaxOpts(KIND[kind], int(max_sweeps), float(rtol), int(check_every), int(inner_sweeps),
-                      float(inner_rtol), float(div_factor), int(bool(use_graph)), 0)
+                      float(inner_rtol), float(div_factor), int(bool(use_graph)), int(learn_every))
         total = int(nsys.sum())
         rep = (Report * total)()
         rc = LIB.fnlh_batch_relax(self.h, _ptr(nsys), C.cast(sys_ptrs, C.c_void_p), C.cast(x_ptrs, C.c_void_p),
@@ -381,6 +393,100 @@ class Batch:
             out.append([rep[k + j].as_dict() for j in range(nsys[i])])
             k += nsys[i]
         return rc, out
+
+
+NN_PARAMS = 26624
+
+
+class Network:
+    """Learned preconditioner attached to one context (fnlh_nn_*): weights are a flat
+    float32 array of NN_PARAMS values, W1..W5 each row-major [in][out]."""
+
+    def __init__(self, ctx):
+        self.ctx = ctx
+        h = C.c_void_p()
+        ctx._check(LIB.fnlh_nn_create(C.byref(h), ctx.h))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            LIB.fnlh_nn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32).reshape(-1)
+        if w.size != NN_PARAMS:
+            raise ValueError(f"expected {NN_PARAMS} weights, got {w.size}")
+        self.ctx._check(LIB.fnlh_nn_set_weights(self.h, _ptr(w)))
+
+    def get_weights(self):
+        w = np.empty(NN_PARAMS, np.float32)
+        self.ctx._check(LIB.fnlh_nn_get_weights(self.h, _ptr(w)))
+        return w
+
+    def apply(self, sys, r, dx=None, stream=None):
+        import torch
+        _dev_tensor(r, (self.ctx.n, 6), "r")
+        if dx is None:
+            dx = torch.empty_like(r)
+        _dev_tensor(dx, (self.ctx.n, 6), "dx")
+        self.ctx._check(LIB.fnlh_nn_apply(self.h, int(sys), _ptr(r), _ptr(dx), _stream(stream)))
+        return dx
+
+    @staticmethod
+    def _lists(systems, rs, es, n_cells):
+        n = len(systems)
+        for t in list(rs) + list(es):
+            _dev_tensor(t, (n_cells, 6), "vector")
+        sa = np.ascontiguousarray(systems, dtype=np.int32)
+        rp = (C.c_void_p * n)(*[_ptr(t) for t in rs])
+        ep = (C.c_void_p * n)(*[_ptr(t) for t in es])
+        return n, sa, rp, ep
+
+    def loss_grad(self, systems, rs, es, stream=None):
+        """Mean loss and its gradient (float32 [NN_PARAMS]) over pairs (r, e)."""
+        n, sa, rp, ep = self._lists(systems, rs, es, self.ctx.n)
+        g = np.empty(NN_PARAMS, np.float32)
+        loss = C.c_double(0.0)
+        self.ctx._check(LIB.fnlh_nn_loss_grad(self.h, n, _ptr(sa), C.cast(rp, C.c_void_p), C.cast(ep, C.c_void_p),
+                                              _ptr(g), C.byref(loss), _stream(stream)))
+        return loss.value, g
+
+    def add_pairs(self, systems, rs, es, stream=None):
+        n, sa, rp, ep = self._lists(systems, rs, es, self.ctx.n)
+        self.ctx._check(LIB.fnlh_nn_add_pairs(self.h, n, _ptr(sa), C.cast(rp, C.c_void_p), C.cast(ep, C.c_void_p),
+                                              _stream(stream)))
+
+    def clear_pairs(self):
+        self.ctx._check(LIB.fnlh_nn_clear_pairs(self.h))
+
+    def n_pairs(self):
+        n = C.c_int64(0)
+        self.ctx._check(LIB.fnlh_nn_pairs(self.h, C.byref(n)))
+        return n.value
+
+    def train(self, steps, batch=8, lr=1e-3, seed=0, stream=None):
+        """Adam steps on the stored pairs; returns the per-step batch losses."""
+        loss = np.zeros(max(int(steps), 1), np.float32)
+        self.ctx._check(LIB.fnlh_nn_train(self.h, int(steps), int(batch), float(lr), int(seed), _ptr(loss),
+                                          _stream(stream)))
+        return loss[:int(steps)]
+
+
+def mfma_selftest(ctx, a_bits, bt_bits):
+    """out = A B on the matrix cores for 64x64 BF16 operands given as uint16 bit patterns
+    (bt_bits = B^T)."""
+    a = np.ascontiguousarray(a_bits, dtype=np.uint16)
+    bt = np.ascontiguousarray(bt_bits, dtype=np.uint16)
+    out = np.empty((64, 64), np.float32)
+    ctx._check(LIB.fnlh_nn_selftest(ctx.h, _ptr(a), _ptr(bt), _ptr(out)))
+    return out
 
 
 def version():

@@ -29,12 +29,39 @@ def test_exports_every_declared_symbol(F):
     assert "gfx950" in F.version()
 
 
-def test_struct_sizes_match_header(F):
+def test_struct_layouts_match_header(F, tmp_path):
+    """Size and every field offset of the ctypes mirrors equal what a C compiler makes
+    of include/fnlh.h."""
     import ctypes as C
-    assert C.sizeof(F.Mesh) == 8 * 3 + 4 * 2 + 8 * 6
-    assert C.sizeof(F.Options) == 4 * 4 + 8 + 4 * 2
-    assert C.sizeof(F.RelaxOpts) == 4 * 2 + 8 + 4 * 2 + 8 + 8 + 4 * 2
-    assert C.sizeof(F.Report) == 4 * 4 + 8 * 4
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"fnlh_mesh": F.Mesh, "fnlh_options": F.Options, "fnlh_relax_opts": F.RelaxOpts,
+               "fnlh_sys_report": F.Report, "fnlh_kernel_stats": F.KernelStats,
+               "fnlh_tune_result": F.TuneResult}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fnlh.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ['  printf("params %d\\n", (int)FNLH_NN_PARAMS);', "  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            *key, val = ln.split()
+            got[" ".join(key)] = int(val)
+    for cname, py in structs.items():
+        assert got[f"{cname} size"] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[f"{cname} {fname}"] == getattr(py, fname).offset, (cname, fname)
+    assert got["params"] == F.NN_PARAMS
 
 
 @pytest.mark.parametrize("shape", [(16, 8, 4), (7, 5, 3), (3, 2, 2)])

@@ -125,6 +125,241 @@ def cpu_baseline(mesh, Q, om, bs, colour, gpu_sweeps):
             "extrapolated_step_s": t_step}
 
 
+def learned_compare(mesh, Q, om, bs, storage, n_pairs, train_steps, batch, learn_every, reps=3, lr=1e-3, seed=0):
+    """Learned preconditioner against the plain sweep on the same systems: training pairs
+    from the plain solver (b = 0, random start, m DILU sweeps: the iterate is minus its
+    error, its residual -K x), Adam on the GPU, then both solves to the 1e-8 drop."""
+    import numpy as np
+    import torch
+    from paper_2404_01407_amd import fnlh
+    from paper_2404_01407_amd.synth import he_init
+    ctx = fnlh.Context(mesh, storage=storage, outer="exact")
+    ctx.assemble_jacobian(torch.from_numpy(Q).cuda(), eps=0.6, sigma=50.0)
+    ctx.set_harmonics(om)
+    S, N = len(bs), mesh.n_cells
+    bd = [torch.from_numpy(b).cuda() for b in bs]
+
+    def solve(kind):
+        times, rep = [], None
+        for _ in range(reps):
+            xs = [torch.zeros_like(b) for b in bd]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, rep = ctx.relax(list(range(S)), xs, bd, kind=kind, max_sweeps=4000, rtol=RTOL, check_every=16,
+                                use_graph=True, learn_every=learn_every)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            if st != 0:
+                raise RuntimeError(f"{kind} solve did not converge: {rep}")
+        ms = 1e3 * float(np.median(times))
+        return {"ms": round(ms, 3), "sweeps": [r["sweeps"] for r in rep], "outer": [r["outer"] for r in rep],
+                "rel_res": [r["rel_res"] for r in rep], "learned_steps": [r["learned"] for r in rep],
+                "rejected": [r["fallbacks"] for r in rep],
+                "updates_per_s": round(N * sum(r["sweeps"] for r in rep) / (ms * 1e-3))}
+
+    plain = solve("dilu")
+    net = fnlh.Network(ctx)
+    net.set_weights(he_init(seed))
+    net.reserve_pairs(n_pairs)
+    zero = torch.zeros(N, 6, dtype=torch.complex128, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1234 + seed)
+    sweep_choices = [4, 8, 16, 32, 64, 128]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    k = 0
+    while net.n_pairs() < n_pairs:
+        m = sweep_choices[k % len(sweep_choices)]
+        take = min(S, n_pairs - net.n_pairs())
+        xs = [torch.randn(N, 6, dtype=torch.complex128, device="cuda", generator=gen) for _ in range(take)]
+        ctx.relax(list(range(take)), xs, [zero] * take, kind="dilu", max_sweeps=m, rtol=0.0, check_every=16,
+                  use_graph=True)
+        for j in range(take):
+            r = torch.empty_like(xs[j])
+            ctx.residual(j, xs[j], zero, r)
+            net.add_pairs([j], [r], [-xs[j]])
+        k += 1
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    hist = net.train(train_steps, batch=batch, lr=lr, seed=seed + 1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    learned = solve("learned")
+    q = max(1, len(hist) // 10)
+    out = {"storage": storage, "learn_every": learn_every, "plain": plain, "learned": learned,
+           "speedup_time": round(plain["ms"] / learned["ms"], 3),
+           "sweep_ratio": round(sum(plain["sweeps"]) / max(sum(learned["sweeps"]), 1), 3),
+           "training": {"pairs": n_pairs, "pair_sweeps": sweep_choices, "steps": train_steps, "batch": batch,
+                        "lr": lr, "generate_s": round(t_gen, 2), "train_s": round(t_train, 2),
+                        "ms_per_sample": round(1e3 * t_train / max(train_steps * batch, 1), 3),
+                        "loss_first": round(float(np.mean(hist[:q])), 4),
+                        "loss_last": round(float(np.mean(hist[-q:])), 4)}}
+    net.close()
+    ctx.close()
+    return out
+
+
+def run_learned(args):
+    mesh, Q, om, bs = build_inputs()
+    print(f"[bench] learned: {mesh.n_cells} cells, {len(bs)} systems, {args.pairs} pairs, {args.train_steps} steps",
+          file=sys.stderr, flush=True)
+    res = learned_compare(mesh, Q, om, bs, args.storage, args.pairs, args.train_steps, args.batch, args.learn_every,
+                          reps=max(args.steps, 1))
+    print(f"[bench] plain {res['plain']['ms']} ms, learned {res['learned']['ms']} ms", file=sys.stderr, flush=True)
+    out = {
+        "metric": METRIC,
+        "value": res["learned"]["updates_per_s"],
+        "unit": "cell-unknown updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 0,
+        "ms_per_step": res["learned"]["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 network (f32 accumulate), " + args.storage + " blocks, f64 outer residual",
+        "data": "synthetic",
+        "config": {"workload": ("learned preconditioner: 200k-cell hex passage sector 80x50x50, mean + 3 harmonics; "
+                                "network trained on the GPU on plain-solver residual/error pairs, then learned vs "
+                                "plain DILU sweeps to a 1e-8 residual drop"),
+                   "cells": mesh.n_cells, "systems": len(bs)},
+        "time_to_1e-8_ms": {"plain": res["plain"]["ms"], "learned": res["learned"]["ms"]},
+        "learned": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_largest(args):
+    """Three-row sector (rotor-stator-rotor, 3 x 100x64x100 = 1.92M cells plus the pitch-
+    overlap interface couplings, greedy colouring), mean + 10 harmonics at mixed per-row
+    frequencies, FP32 blocks with the FP64 defect correction, DILU sweeps to 1e-8; then
+    the same solve with learned corrections.  Device memory is read for 1, 3, 6 and 11
+    systems: the matrix part does not depend on the harmonic count."""
+    import numpy as np
+    import torch
+    from paper_2404_01407_amd import fnlh, synth
+    t0 = time.perf_counter()
+    mesh = synth.multi_row(*args.largest_shape, n_blades=(36, 60, 48), seed=5)
+    Q = synth.flow_state(mesh, 5)
+    n_h = 10
+    om = synth.omegas_multi_row(n_h, (36, 60, 48))
+    bs = [synth.rhs(mesh.n_cells, s, real=(s == 0)) for s in range(n_h + 1)]
+    print(f"[bench] largest: {mesh.n_cells} cells, {mesh.n_edges} faces, {len(bs)} systems, inputs "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ctx = fnlh.Context(mesh, storage=args.storage, outer="exact")
+    ingest_ms = 1e3 * (time.perf_counter() - t0)
+    colour, n_col = ctx.ordering()
+    Qd = torch.from_numpy(Q).cuda()
+    bd = [torch.from_numpy(b).cuda() for b in bs]
+    mem = {}
+    for k in (1, 3, 6, n_h + 1):
+        ctx.assemble_jacobian(Qd, eps=0.6, sigma=50.0)
+        ctx.set_harmonics(om[:k])
+        xs = [torch.zeros_like(b) for b in bd[:k]]
+        ctx.relax(list(range(k)), xs, bd[:k], kind="dilu", max_sweeps=2, rtol=0.0, check_every=2)
+        mem[k] = ctx.memory()
+        del xs
+    print(f"[bench] largest: memory by system count {mem}", file=sys.stderr, flush=True)
+    S = len(bs)
+
+    def step(kind):
+        xs = [torch.zeros_like(b) for b in bd]
+        ctx.assemble_jacobian(Qd, eps=0.6, sigma=50.0)
+        ctx.set_harmonics(om)
+        st, rep = ctx.relax(list(range(S)), xs, bd, kind=kind, max_sweeps=6000, rtol=RTOL, check_every=16,
+                            use_graph=True, learn_every=args.learn_every)
+        if st != 0:
+            raise RuntimeError(f"largest: {kind} solve did not converge: {rep}")
+        return rep
+
+    step("dilu")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rep = step("dilu")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    sweeps = [r["sweeps"] for r in rep]
+    print(f"[bench] largest: {1e3 * dt:.1f} ms/step, sweeps {sweeps}", file=sys.stderr, flush=True)
+    ctx.stats_enable(True, period=STATS_PERIOD)
+    step("dilu")
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    ctx.stats_enable(False)
+    kernels = {}
+    for name in ("fwd", "bwd", "sweep_update", "sweep_set"):
+        k = st[name]
+        if k["launches"]:
+            ms = k["total_ms"] / k["launches"]
+            kernels[name] = {"launches": k["launches"], "avg_launch_us": round(1e3 * ms, 2),
+                             "achieved_GBs": round(k["alg_bytes"] / k["launches"] / (ms * 1e-3) / 1e9, 1)}
+    tot_ms = sum(st[n]["total_ms"] for n in ("fwd", "bwd", "sweep_update", "sweep_set"))
+    tot_b = sum(st[n]["alg_bytes"] for n in ("fwd", "bwd", "sweep_update", "sweep_set"))
+    sweep_gbs = tot_b / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
+    learned = None
+    if not args.no_learned:
+        net = fnlh.Network(ctx)
+        net.set_weights(synth.he_init(0))
+        zero = torch.zeros_like(bd[0])
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(99)
+        n_pairs = 8 * S
+        net.reserve_pairs(n_pairs)
+        t0 = time.perf_counter()
+        for k in range(8):
+            xs = [torch.randn(bd[0].shape, dtype=torch.complex128, device="cuda", generator=gen) for _ in range(S)]
+            ctx.relax(list(range(S)), xs, [zero] * S, kind="dilu", max_sweeps=[8, 16, 32, 64][k % 4], rtol=0.0,
+                      check_every=8)
+            for j in range(S):
+                r = torch.empty_like(xs[j])
+                ctx.residual(j, xs[j], zero, r)
+                net.add_pairs([j], [r], [-xs[j]])
+            del xs
+        hist = net.train(64, batch=4, lr=1e-3, seed=1)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep_l = step("learned")
+        torch.cuda.synchronize()
+        t_l = time.perf_counter() - t0
+        learned = {"ms": round(1e3 * t_l, 2), "sweeps": [r["sweeps"] for r in rep_l],
+                   "learned_steps": [r["learned"] for r in rep_l], "rejected": [r["fallbacks"] for r in rep_l],
+                   "rel_res": [r["rel_res"] for r in rep_l], "pairs": n_pairs, "train_steps": 64,
+                   "generate_and_train_s": round(t_train, 2),
+                   "loss_first": round(float(np.mean(hist[:6])), 4), "loss_last": round(float(np.mean(hist[-6:])), 4),
+                   "learn_every": args.learn_every}
+        print(f"[bench] largest learned: {learned['ms']} ms, sweeps {learned['sweeps']}", file=sys.stderr,
+              flush=True)
+        net.close()
+    updates = mesh.n_cells * sum(sweeps)
+    out = {
+        "metric": METRIC,
+        "value": round(updates / dt),
+        "unit": "cell-unknown updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": round(1e3 * dt, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32 blocks, f32 sweep, f64 outer residual",
+                  "bf16": "bf16 blocks, f32 sweep, f64 outer residual"}[args.storage],
+        "data": "synthetic",
+        "config": {"workload": ("three-row sector rotor-stator-rotor 3 x 100x64x100 (36/60/48 blades), mean + 10 "
+                                "harmonics at mixed per-row frequencies, one shared Jacobian, DILU sweeps on a "
+                                "greedy colouring to a 1e-8 residual drop"),
+                   "cells": mesh.n_cells, "faces": mesh.n_edges, "systems": S, "colours": n_col,
+                   "storage": args.storage},
+        "time_to_1e-8_ms": round(1e3 * dt, 3),
+        "sweeps": sweeps,
+        "outer": [r["outer"] for r in rep],
+        "rel_res": [r["rel_res"] for r in rep],
+        "sweep_kernels": kernels,
+        "sweep_kernels_GBs": round(sweep_gbs, 1),
+        "sweep_kernels_frac_of_hbm_peak": round(sweep_gbs / HBM_PEAK_GBS, 4),
+        "memory_bytes_by_systems": {str(k): v for k, v in mem.items()},
+        "learned": learned,
+        "ingest_ms": round(ingest_ms, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_batch(args):
     """Batching workload: 64 independent blade-row instances, seeded log-uniform sizes in
     [20k, 300k] cells (~8M total), passage shapes (2n', n', n'), blade counts U{20..80},
@@ -246,8 +481,17 @@ def main():
     ap.add_argument("--check-every", type=int, default=16, help="sweeps between host checks of the stop flags")
     ap.add_argument("--no-graph", action="store_true", help="direct launches instead of graph replay")
     ap.add_argument("--no-stats", action="store_true", help="no per-kernel event timing in the timed region")
-    ap.add_argument("--workload", default="precision", choices=["precision", "batch"],
-                    help="precision: 200k cells, mean + 3 harmonics (default); batch: 64 uneven instances")
+    ap.add_argument("--workload", default="precision", choices=["precision", "batch", "learned", "largest"],
+                    help="precision: 200k cells, mean + 3 harmonics (default); batch: 64 uneven instances; "
+                         "learned: network training and learned vs plain solves; largest: 1.92M-cell three-row "
+                         "sector, mean + 10 harmonics")
+    ap.add_argument("--largest-shape", type=int, nargs=3, default=[100, 64, 100],
+                    help="largest workload: cells per row (axial, pitch, radial)")
+    ap.add_argument("--pairs", type=int, default=10000, help="learned workload: training pairs")
+    ap.add_argument("--train-steps", type=int, default=1250, help="learned workload: Adam steps")
+    ap.add_argument("--batch", type=int, default=8, help="learned workload: pairs per Adam step")
+    ap.add_argument("--learn-every", type=int, default=32, help="sweeps between learned corrections")
+    ap.add_argument("--no-learned", action="store_true", help="skip the short learned-vs-plain comparison")
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--total-cells", type=float, default=8.0e6)
     ap.add_argument("--calib-copy", action="store_true",
@@ -260,6 +504,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "batch":
         return run_batch(args)
+    if args.workload == "learned":
+        return run_learned(args)
+    if args.workload == "largest":
+        return run_largest(args)
 
     if args.calib_copy:
         xs = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
@@ -308,6 +556,13 @@ def main():
             r.ctx.close()
             print(f"[bench] {s}: {m['ms_per_step']:.2f} ms/step, sweeps {m['sweeps']}", file=sys.stderr, flush=True)
 
+    learned = None
+    if not args.no_learned:
+        print("[bench] short learned-vs-plain comparison (512 pairs, 128 Adam steps)", file=sys.stderr, flush=True)
+        learned = learned_compare(mesh, Q, om, bs, args.storage, 512, 128, 8, args.learn_every)
+        print(f"[bench] learned: plain {learned['plain']['ms']} ms, learned {learned['learned']['ms']} ms",
+              file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
@@ -338,6 +593,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "modes": modes,
+        "learned": learned,
         "memory_bytes": memory,
         "ingest_ms": round(main_run.ingest_ms, 1),
     }

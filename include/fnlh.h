@@ -162,7 +162,7 @@ typedef struct {
   double inner_rtol;     /* reduced precision: inner relative tolerance (0 = auto)          */
   double div_factor;     /* DIVERGED when ||r|| > div_factor ||r0|| (0 = 1e3)               */
   int32_t use_graph;     /* 1: replay check_every sweeps as one captured hipGraph            */
-  int32_t learn_every;   /* FNLH_LEARNED: sweeps between learned corrections (0 = 16)       */
+  int32_t learn_every;   /* FNLH_LEARNED, FP64 blocks: sweeps between learned corrections (0 = 16) */
 } fnlh_relax_opts;
 
 typedef struct {
@@ -179,8 +179,9 @@ typedef struct {
 } fnlh_sys_report;
 
 /* FNLH_LEARNED runs the FNLH_DILU sweeps of this call and, every learn_every sweeps
- * (at every FP64 correction in reduced precision, with at most learn_every inner
- * sweeps), a correction by the network attached with fnlh_nn_create: with r the FP64
+ * (in reduced precision: after every FP64 correction, i.e. every inner solve, whose
+ * length inner_sweeps / inner_rtol set), a correction by the network attached with
+ * fnlh_nn_create: with r the FP64
  * residual of x and dx the network's output for r, x <- x + alpha dx with the complex
  * alpha minimising ||r - alpha K_s dx||.  The FP64 residual judges every correction:
  * one that is not finite or lowers ||r||^2 by less than 0.1% is rejected (counted in
@@ -313,10 +314,13 @@ int fnlh_nn_apply(fnlh_nn nn, int32_t sys, const double* r, double* dx, void* st
  * grad host [FNLH_NN_PARAMS] or NULL, loss host or NULL.  Synchronises the stream. */
 int fnlh_nn_loss_grad(fnlh_nn nn, int32_t n, const int32_t* sys, const double* const* r,
                       const double* const* e, float* grad, double* loss, void* stream);
-/* Keep n training pairs (r[k], e[k]) of system sys[k] on the device (FP32 copies; the
- * caller's buffers may be reused after the call's stream work).  n_pairs: count held. */
+/* Keep n training pairs (r[k], e[k]) of system sys[k] on the device as BF16 copies in
+ * the internal cell order (48 bytes per cell and pair; the caller's buffers may be
+ * reused once the stream has run the call's work).  The pool grows by doubling;
+ * fnlh_nn_reserve_pairs sizes it once for a known count.  n_pairs: count held. */
 int fnlh_nn_add_pairs(fnlh_nn nn, int32_t n, const int32_t* sys, const double* const* r,
                       const double* const* e, void* stream);
+int fnlh_nn_reserve_pairs(fnlh_nn nn, int64_t n_pairs, void* stream);
 int fnlh_nn_clear_pairs(fnlh_nn nn);
 int fnlh_nn_pairs(fnlh_nn nn, int64_t* n_pairs);
 /* steps Adam steps on batches of `batch` pairs drawn with replacement (splitmix64 from

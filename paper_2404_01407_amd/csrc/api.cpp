@@ -32,6 +32,7 @@ int hip_fail(fnlh_ctx c, hipError_t e, const char* what) {
 }
 
 int dalloc(fnlh_ctx c, DevBuf& b, size_t bytes, const char* what) {
+  if (c) c->buf_gen++;
   if (b.p) {
     (void)hipFree(b.p);
     b.p = nullptr;
@@ -224,6 +225,7 @@ struct GraphEntry {
   const void *x, *b, *y, *st;
   double rtol, divf;
   bool stats;
+  uint64_t gen = 0;  // buffer generation at capture
   // value
   hipGraphExec_t exec = nullptr;
   std::vector<hipEvent_t> events;
@@ -332,9 +334,9 @@ void one_sweep(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, const SysBatc
   }
 }
 
-bool same_key(const GraphEntry* g, int path, const SweepCfg& cfg, int ns, int K, const SysBatch& sb, const void* x,
-              const void* b, const void* y, const void* st, double rtol, double divf, bool stats) {
-  if (g->path != path || g->storage != cfg.storage || g->spw != cfg.spw || g->lpr != cfg.lanes_per_row ||
+bool same_key(const GraphEntry* g, uint64_t gen, int path, const SweepCfg& cfg, int ns, int K, const SysBatch& sb,
+              const void* x, const void* b, const void* y, const void* st, double rtol, double divf, bool stats) {
+  if (g->gen != gen || g->path != path || g->storage != cfg.storage || g->spw != cfg.spw || g->lpr != cfg.lanes_per_row ||
       g->pivot != (int)cfg.pivot || g->ns != ns || g->K != K || g->x != x || g->b != b || g->y != y ||
       g->st != st || g->rtol != rtol || g->divf != divf || g->stats != stats || g->sb.n != sb.n)
     return false;
@@ -353,8 +355,17 @@ void destroy_graph(GraphEntry* g) {
 GraphEntry* get_graph(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, int K, const SysBatch& sb, void* x,
                       const void* b, void* y, SysState* st, double rtol, double divf) {
   static uint64_t tick = 0;
+  // graphs captured before a buffer was (re)allocated may point at freed memory
+  for (size_t i = 0; i < c->graphs.size();) {
+    if (c->graphs[i]->gen != c->buf_gen) {
+      destroy_graph(c->graphs[i]);
+      c->graphs.erase(c->graphs.begin() + i);
+    } else {
+      ++i;
+    }
+  }
   for (GraphEntry* g : c->graphs)
-    if (same_key(g, path, cfg, ns, K, sb, x, b, y, st, rtol, divf, c->stats_on)) {
+    if (same_key(g, c->buf_gen, path, cfg, ns, K, sb, x, b, y, st, rtol, divf, c->stats_on)) {
       g->last_use = ++tick;
       return g;
     }
@@ -364,6 +375,7 @@ GraphEntry* get_graph(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, int K,
     return nullptr;
   }
   GraphEntry* g = new GraphEntry();
+  g->gen = c->buf_gen;
   g->path = path;
   g->storage = cfg.storage;
   g->spw = cfg.spw;
@@ -531,7 +543,6 @@ int relax_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, c
   P.use_graph = o->use_graph != 0;
   P.learned = o->kind == FNLH_LEARNED;
   P.learn_every = o->learn_every > 0 ? o->learn_every : 16;
-  if (P.learned && P.reduced) P.inner_max = std::min(P.inner_max, P.learn_every);
   int rc;
   if ((rc = ensure_vectors(c, n))) return rc;
   if (P.learned && (rc = nn_relax_begin(c, n, s))) return rc;
@@ -1006,7 +1017,9 @@ int fnlh_set_harmonics(fnlh_ctx c, int32_t n_sys, const double* omega, void* str
     if (!std::isfinite(omega[i])) return set_err(c, FNLH_E_ARG, "set_harmonics: non-finite omega");
   c->omega.assign(omega, omega + n);
   int rc;
-  if ((rc = dalloc(c, c->d_omega, n * sizeof(double), "alloc omega"))) return rc;
+  // the table keeps its buffer while it fits (captured sweep graphs hold its address)
+  if (n * sizeof(double) > c->d_omega.bytes && (rc = dalloc(c, c->d_omega, n * sizeof(double), "alloc omega")))
+    return rc;
   HIPC(c, hipMemcpy(c->d_omega.p, omega, n * sizeof(double), hipMemcpyHostToDevice), "copy omega");
   c->n_sys = n_sys;
   invalidate_factors(c);

@@ -62,7 +62,10 @@ struct fnlh_ctx_s {
   bool dom_known = false, dom = false;
   DevBuf d_dom;
   int* h_dom = nullptr;
-  // captured sweep graphs
+  // captured sweep graphs; their kernel nodes hold device pointers (factors, omega,
+  // partial sums, vectors), so every (re)allocation bumps buf_gen and graphs captured
+  // under an older generation are discarded
+  uint64_t buf_gen = 0;
   hipStream_t cap = nullptr;
   std::vector<GraphEntry*> graphs;
   bool graph_broken = false;

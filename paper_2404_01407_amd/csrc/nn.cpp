@@ -16,7 +16,7 @@ struct fnlh_nn_s {
   DevBuf master, mom1, mom2, grad, wt, w;  // FP32 master/moments/gradient [kNnParams], bf16 padded weights
   DevBuf u, h, d, sc, part;                // inference
   DevBuf ehat, dc, dh, gpart, lpart, loss;  // training
-  DevBuf pool;                             // pairs: [cap][2][NP][12] FP32 (r, e), internal order
+  DevBuf pool;                             // pairs: [cap][2][NP][12] BF16 (r, e), internal order
   std::vector<int32_t> pair_sys;
   int64_t n_pairs = 0, cap_pairs = 0;
   DevBuf rr, xt, rn, part4, alpha, counts;  // learned step scratch
@@ -121,6 +121,22 @@ template <typename F> int batch_grad(fnlh_nn nn, int n, F sample, double* loss_d
   }
   nn_launch_grad_reduce(B, nn->G, (float*)nn->grad.p, loss_dev, s);
   return check_launch(c, "network gradient launch");
+}
+
+// pair pool to cap pairs, keeping the stored ones
+int grow_pairs(fnlh_nn nn, int64_t cap, hipStream_t s) {
+  fnlh_ctx c = nn->c;
+  const size_t bytes = (size_t)2 * c->L.NP * 12 * sizeof(uint16_t);
+  DevBuf nb;
+  int rc = dalloc(c, nb, (size_t)cap * bytes, "alloc training pairs");
+  if (rc) return rc;
+  if (nn->n_pairs)
+    HIPC(c, hipMemcpyAsync(nb.p, nn->pool.p, (size_t)nn->n_pairs * bytes, hipMemcpyDeviceToDevice, s), "grow pairs");
+  HIPC(c, hipStreamSynchronize(s), "grow pairs");
+  dfree(nn->pool);
+  nn->pool = nb;
+  nn->cap_pairs = cap;
+  return FNLH_OK;
 }
 
 }  // namespace
@@ -318,30 +334,27 @@ int fnlh_nn_add_pairs(fnlh_nn nn, int32_t n, const int32_t* sys, const double* c
     if (!r[k] || !e[k]) return set_err(c, FNLH_E_ARG, "network: null vector");
   }
   hipStream_t s = S(stream);
-  const size_t pair = (size_t)2 * c->L.NP * 12;  // floats
-  if (nn->n_pairs + n > nn->cap_pairs) {
-    const int64_t cap = std::max<int64_t>(nn->n_pairs + n, 2 * nn->cap_pairs);
-    DevBuf nb;
-    int rc = dalloc(c, nb, (size_t)cap * pair * sizeof(float), "alloc training pairs");
-    if (rc) return rc;
-    if (nn->n_pairs)
-      HIPC(c, hipMemcpyAsync(nb.p, nn->pool.p, (size_t)nn->n_pairs * pair * sizeof(float), hipMemcpyDeviceToDevice,
-                             s),
-           "grow pairs");
-    HIPC(c, hipStreamSynchronize(s), "grow pairs");
-    dfree(nn->pool);
-    nn->pool = nb;
-    nn->cap_pairs = cap;
-  }
+  int rc;
+  if (nn->n_pairs + n > nn->cap_pairs &&
+      (rc = grow_pairs(nn, std::max<int64_t>(nn->n_pairs + n, 2 * nn->cap_pairs), s)))
+    return rc;
+  const size_t pair = (size_t)2 * c->L.NP * 12;  // BF16 values
   const DevPattern p = c->pat();
   for (int k = 0; k < n; ++k) {
-    float* dst = (float*)nn->pool.p + (size_t)(nn->n_pairs + k) * pair;
-    nn_launch_pack32(p, (const int32_t*)c->iperm.p, r[k], dst, s);
-    nn_launch_pack32(p, (const int32_t*)c->iperm.p, e[k], dst + pair / 2, s);
+    uint16_t* dst = (uint16_t*)nn->pool.p + (size_t)(nn->n_pairs + k) * pair;
+    nn_launch_pack16(p, (const int32_t*)c->iperm.p, r[k], dst, s);
+    nn_launch_pack16(p, (const int32_t*)c->iperm.p, e[k], dst + pair / 2, s);
     nn->pair_sys.push_back(sys[k]);
   }
   nn->n_pairs += n;
   return check_launch(c, "store pairs");
+}
+
+int fnlh_nn_reserve_pairs(fnlh_nn nn, int64_t n_pairs, void* stream) {
+  if (!nn || n_pairs < 0) return FNLH_E_ARG;
+  if (!nn->c) return FNLH_E_ORDER;
+  if (n_pairs <= nn->cap_pairs) return FNLH_OK;
+  return grow_pairs(nn, n_pairs, S(stream));
 }
 
 int fnlh_nn_clear_pairs(fnlh_nn nn) {
@@ -367,7 +380,7 @@ int fnlh_nn_train(fnlh_nn nn, int32_t steps, int32_t batch, float lr, uint64_t s
   hipStream_t s = S(stream);
   DevBuf hist;
   if ((rc = dalloc(c, hist, (size_t)steps * sizeof(double), "alloc loss history"))) return rc;
-  const size_t pair = (size_t)2 * c->L.NP * 12;
+  const size_t pair = (size_t)2 * c->L.NP * 12;  // BF16 values
   uint64_t z = seed;
   auto next = [&]() {  // splitmix64
     z += 0x9e3779b97f4a7c15ull;
@@ -381,12 +394,12 @@ int fnlh_nn_train(fnlh_nn nn, int32_t steps, int32_t batch, float lr, uint64_t s
         nn, batch,
         [&](int, int& sy, NnVec& rv, NnVec& ev) {
           const int64_t i = (int64_t)(next() % (uint64_t)nn->n_pairs);
-          const float* base = (const float*)nn->pool.p + (size_t)i * pair;
+          const uint16_t* base = (const uint16_t*)nn->pool.p + (size_t)i * pair;
           sy = nn->pair_sys[i];
           rv = NnVec{};
-          rv.f32 = base;
+          rv.b16 = base;
           ev = NnVec{};
-          ev.f32 = base + pair / 2;
+          ev.b16 = base + pair / 2;
         },
         (double*)hist.p + t, s);
     if (rc) break;

@@ -55,10 +55,10 @@ struct NnBufs {
 };
 
 // A complex vector of one system: FP64 user order [N][12] (iperm maps internal rows to
-// user cells), or internal [NP][ns][12] at slot vs in FP64 or FP32.
+// user cells), or internal [NP][ns][12] at slot vs in FP64 or BF16 (bit patterns).
 struct NnVec {
   const double* d64 = nullptr;
-  const float* f32 = nullptr;
+  const uint16_t* b16 = nullptr;
   const int32_t* iperm = nullptr;
   int ns = 1, vs = 0;
 };
@@ -86,8 +86,8 @@ void nn_launch_backward(int storage, const DevPattern& p, const void* offd, cons
 void nn_launch_grad_reduce(const NnBufs& B, int G, float* grad_packed, double* loss_out, hipStream_t s);
 void nn_launch_adam(float* w, float* m, float* v, const float* g, int n, float lr, float b1, float b2, float eps,
                     int t, hipStream_t s);
-// FP64 user-order vector -> FP32 internal [NP][12]
-void nn_launch_pack32(const DevPattern& p, const int32_t* iperm, const double* user, float* out, hipStream_t s);
+// FP64 user-order vector -> BF16 internal [NP][12] (training pairs)
+void nn_launch_pack16(const DevPattern& p, const int32_t* iperm, const double* user, uint16_t* out, hipStream_t s);
 // learned step, per system slot vs: y = r - rn; alpha = <y, r> / <y, y> if that lowers
 // ||r||^2 by at least the fraction accept and the system is active, else 0;
 // x <- x + alpha (xt - x), r <- r - alpha y

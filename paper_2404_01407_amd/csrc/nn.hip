@@ -125,7 +125,7 @@ __device__ inline double nv_get(const NnVec& v, int64_t row, int c) {
     return u < 0 ? 0.0 : v.d64[(int64_t)u * 12 + c];
   }
   const int64_t o = (row * v.ns + v.vs) * 12 + c;
-  return v.d64 ? v.d64[o] : (double)v.f32[o];
+  return v.d64 ? v.d64[o] : (double)bf2f(v.b16[o]);
 }
 
 // sum |r|^2 per tile
@@ -462,12 +462,14 @@ __global__ void k_nn_output(int64_t NP, NnBufs B, NnOut o) {
   }
 }
 
-__global__ void k_nn_pack32(int64_t NP, const int32_t* __restrict__ iperm, const double* __restrict__ user,
-                            float* __restrict__ out) {
+// BF16 keeps the exponent range of FP32, so pairs need no scaling (the loss is
+// scale-free as long as r and e share one factor)
+__global__ void k_nn_pack16(int64_t NP, const int32_t* __restrict__ iperm, const double* __restrict__ user,
+                            uint16_t* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= NP * 12) return;
   const int32_t u = iperm[t / 12];
-  out[t] = u < 0 ? 0.f : (float)user[(int64_t)u * 12 + t % 12];
+  out[t] = u < 0 ? (uint16_t)0 : f2bf((float)user[(int64_t)u * 12 + t % 12]);
 }
 
 // learned step: partial sums per tile of <y, r> (re, im), |y|^2, |r|^2 with y = r - rn
@@ -860,9 +862,9 @@ void nn_launch_output(const DevPattern& p, const NnBufs& B, const NnOut& o, hipS
   hipLaunchKernelGGL(k_nn_output, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p.NP, B, o);
 }
 
-void nn_launch_pack32(const DevPattern& p, const int32_t* iperm, const double* user, float* out, hipStream_t s) {
+void nn_launch_pack16(const DevPattern& p, const int32_t* iperm, const double* user, uint16_t* out, hipStream_t s) {
   const int64_t n = p.NP * 12;
-  hipLaunchKernelGGL(k_nn_pack32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p.NP, iperm, user, out);
+  hipLaunchKernelGGL(k_nn_pack16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p.NP, iperm, user, out);
 }
 
 void nn_launch_step(const DevPattern& p, double* x, const double* xt, double* r, const double* rn, int ns, int vs,

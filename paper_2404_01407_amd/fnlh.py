@@ -107,6 +107,7 @@ def _load():
         "fnlh_nn_loss_grad": (I32, [P, I32, V, V, V, V, C.POINTER(D), V]),
         "fnlh_nn_add_pairs": (I32, [P, I32, V, V, V, V]),
         "fnlh_nn_clear_pairs": (I32, [P]),
+        "fnlh_nn_reserve_pairs": (I32, [P, I64, V]),
         "fnlh_nn_pairs": (I32, [P, C.POINTER(I64)]),
         "fnlh_nn_train": (I32, [P, I32, I32, C.c_float, C.c_uint64, V, V]),
         "fnlh_nn_selftest": (I32, [P, V, V, V]),
@@ -462,6 +463,9 @@ class Network:
         n, sa, rp, ep = self._lists(systems, rs, es, self.ctx.n)
         self.ctx._check(LIB.fnlh_nn_add_pairs(self.h, n, _ptr(sa), C.cast(rp, C.c_void_p), C.cast(ep, C.c_void_p),
                                               _stream(stream)))
+
+    def reserve_pairs(self, n, stream=None):
+        self.ctx._check(LIB.fnlh_nn_reserve_pairs(self.h, int(n), _stream(stream)))
 
     def clear_pairs(self):
         self.ctx._check(LIB.fnlh_nn_clear_pairs(self.h))

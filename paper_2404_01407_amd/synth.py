@@ -408,3 +408,17 @@ def batch_instances(n_inst: int = 64, total_cells: float = 8.0e6, seed: int = 3,
         out.append({"shape": (2 * m, m, m), "n_blades": int(rng.integers(20, 81)),
                     "n_harmonics": int(rng.integers(1, 9)), "seed": 100 + q})
     return out
+
+
+# layer shapes (in, out) of the learned preconditioner's five weight matrices
+NN_SHAPES = ((60, 64), (88, 64), (128, 64), (128, 64), (64, 12))
+
+
+def he_init(seed: int = 0) -> np.ndarray:
+    """Initial network weights (float32, W1..W5 row-major [in][out] concatenated):
+    normal with standard deviation sqrt(2 / fan_in); the output layer scaled by 0.1 so
+    the first corrections are small."""
+    rng = np.random.default_rng(seed)
+    mats = [rng.standard_normal((a, b)) * np.sqrt(2.0 / a) for a, b in NN_SHAPES]
+    mats[-1] = mats[-1] * 0.1
+    return np.concatenate([m.reshape(-1) for m in mats]).astype(np.float32)

@@ -154,9 +154,9 @@ def test_adam_step_on_device(F, small):
     w = _weights(9)
     net.set_weights(w)
     rng = np.random.default_rng(13)
-    # FP32-representable pair, so the stored FP32 copy equals the FP64 input
-    r = _cvec(rng, m.n_cells).astype(np.complex64).astype(complex)
-    e = _cvec(rng, m.n_cells).astype(np.complex64).astype(complex)
+    # BF16-representable pair, so the stored BF16 copy equals the FP64 input
+    r = _bf16(_cvec(rng, m.n_cells).view(np.float64)).view(complex)
+    e = _bf16(_cvec(rng, m.n_cells).view(np.float64)).view(complex)
     net.add_pairs([1], [to_dev(r)], [to_dev(e)])
     loss0, g = net.loss_grad([1], [to_dev(r)], [to_dev(e)])
     lr = np.float32(1e-3)

@@ -386,3 +386,25 @@ def test_every_kernel_shape_covers_all_systems(F):
                 for a, b in zip(ref, xs):
                     assert np.array_equal(a, b), (lpr, spw)
             c.close()
+
+
+def test_graph_replay_after_buffer_reallocation(F):
+    """Captured sweep graphs hold device addresses (factor slots, the omega table,
+    partial sums).  Changing the system count reallocates those; replays must never use
+    a freed buffer.  Memory released in between is refilled with NaN by fresh
+    allocations, so a stale address would show up as a non-finite or wrong result."""
+    import torch
+    m, Q, K = case()
+    om = synth.omegas_single_zone(3, 36)
+    c = _ctx(F, m, Q)
+    junk = []
+    for k in (1, 3, 2, 4, 4):
+        c.set_harmonics(om[:k])
+        bs = [synth.rhs(m.n_cells, s) for s in range(k)]
+        _, _, xg = _solve(c, list(range(k)), bs, max_sweeps=40, rtol=0.0, use_graph=True, check_every=4)
+        junk += [torch.full((1 << 20,), float("nan"), dtype=torch.float64, device="cuda") for _ in range(4)]
+        _, _, xd = _solve(c, list(range(k)), bs, max_sweeps=40, rtol=0.0, use_graph=False, check_every=4)
+        for a, b in zip(xg, xd):
+            assert np.all(np.isfinite(a))
+            assert np.array_equal(a, b)
+    c.close()

@@ -318,7 +318,7 @@ void one_sweep(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, const SysBatc
                  L.ctile[col + 1] - L.ctile[col], L.cstart[col], s);
       T.end();
     }
-    launch_reduce(sb, part, L.n_tiles, 0, L.n_tiles, 1, st, kReduceSweep, rtol, divf, 0, s);
+    launch_reduce(sb, part, L.n_tiles, 0, L.n_tiles, rb_slots(cfg, sb.n), st, kReduceSweep, rtol, divf, 0, s);
     for (int col = m - 2; col >= 0; --col) {
       T.begin(FNLH_KSTAT_BWD, col, k);
       launch_bwd(cfg, p, c->offd.p, c->dinv.p, ds, x, y, ns, sb, st, L.ctile[col], L.ctile[col + 1] - L.ctile[col],

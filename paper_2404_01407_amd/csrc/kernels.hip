@@ -368,10 +368,37 @@ __global__ void __launch_bounds__(256) k_rb_batched(const InstDesc* __restrict__
                                      (A*)D.x, (const A*)D.b, D.ns, D.sb, D.st, D.partial, wi.tile);
 }
 
+// Systems of one lane when SW lanes share a row: batch entries k = j * SW + sidx.
+template <int SW, int P>
+__device__ inline bool row_systems(const SysBatch& sb, const SysState* __restrict__ st, int sidx, bool norm_pass,
+                                   WaveSys<P>& W) {
+  bool any = false;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int k = j * SW + sidx;
+    W.run[j] = false;
+    W.vs[j] = 0;
+    W.orow[j] = 0;
+    W.ds[j] = 0;
+    if (k < sb.n) {
+      W.vs[j] = sb.vslot[k];
+      W.orow[j] = sb.orow[k];
+      W.ds[j] = sb.dslot[k];
+      const int act = st[W.vs[j]].active, pen = st[W.vs[j]].pending;
+      W.run[j] = norm_pass ? (act && !pen) : (act != 0);
+      any |= W.run[j];
+    }
+  }
+  return any;
+}
+
 // General colouring, forward pass of colour c (rows of lower colours are < cstart):
 //   r_i = b_i - (K_ii + i w) x_i - sum_k K_ik x_k      (accumulated into ||r||^2)
 //   y_i = Dt_i^-1 (r_i - sum_{k lower} K_ik y_k);  LAST colour: x_i += y_i (z = y there)
-template <typename TB, int P, bool LAST>
+// Lane mapping as in the two-colour pass: SW lanes share a row (one block fetch serves
+// all of them), each carrying P systems; a 64-row tile takes SW waves; the norm of
+// system k over the rows of wave w goes to partial slot w.
+template <typename TB, int SW, int P, bool LAST>
 __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict__ offd, const TB* __restrict__ diag,
                                              const typename TV_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                              typename TV_of<TB>::T* __restrict__ x,
@@ -385,19 +412,23 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
   if (!map_tile(nt, 1, tile, grp)) return;
   tile += t0;
   const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int sidx = lane % SW;
+  const int rl = w * (kLanes / SW) + lane / SW;
   WaveSys<P> W;
-  if (!wave_systems<P>(sb, st, threadIdx.x >> 6, true, W)) return;
-  const int64_t row = tile * kLanes + lane;
-  const bool valid = lane < p.tile_nrows[tile];
+  const bool any = row_systems<SW, P>(sb, st, sidx, true, W);
+  if (!__any(any)) return;
+  const int64_t row = tile * kLanes + rl;
+  const bool valid = rl < p.tile_nrows[tile];
   const int64_t rb = row * ns * 12;
   A r[P][12], t[P][12];
   {
     A d[36];
-    load_block(diag + tile * slot_elems<TB>(), lane, d);
+    load_block(diag + tile * slot_elems<TB>(), rl, d);
 #pragma unroll
     for (int j = 0; j < P; ++j) {
 #pragma unroll
-      for (int i = 0; i < 12; ++i) t[j][i] = 0;
+      for (int i = 0; i < 12; ++i) t[j][i] = r[j][i] = 0;
       if (!W.run[j]) continue;
       A xi[12];
       load_vec(b + rb + W.vs[j] * 12, r[j]);
@@ -405,21 +436,22 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
       sub_diag_shift(r[j], d, (A)shift_w(p, W.orow[j], row), xi);
     }
   }
-  const int w = p.tile_width[tile];
+  const int wd = p.tile_width[tile];
   const int64_t s0 = p.tile_slot0[tile];
-  for (int q = 0; q < w; ++q) {
+  for (int q = 0; q < wd; ++q) {
     const int64_t slot = s0 + q;
-    const int nb = p.ent_nbr[slot * kLanes + lane];
+    const int nb = p.ent_nbr[slot * kLanes + rl];
     A kb[36];
-    load_block(offd + slot * slot_elems<TB>(), lane, kb);
+    load_block(offd + slot * slot_elems<TB>(), rl, kb);
     const int64_t nbo = (int64_t)nb * ns * 12;
+    const bool lower = nb < cstart;
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       if (!W.run[j]) continue;
       A v[12];
       load_vec(x + nbo + W.vs[j] * 12, v);
       sub_kx(r[j], kb, v);
-      if (nb < cstart) {
+      if (lower) {
         load_vec(y + nbo + W.vs[j] * 12, v);
         sub_kx(t[j], kb, v);
       }
@@ -427,13 +459,16 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
   }
 #pragma unroll
   for (int j = 0; j < P; ++j) {
+    double n2 = (valid && W.run[j]) ? norm2_12(r[j]) : 0.0;
+#pragma unroll
+    for (int o = 32; o >= SW; o >>= 1) n2 += __shfl_xor(n2, o, 64);
+    if (lane < SW && j * SW + lane < sb.n && W.run[j])
+      partial[((int64_t)W.vs[j] * p.n_tiles + tile) * kPartialSlots + w] = n2;
     if (!W.run[j]) continue;
-    const double n2 = wave_sum(valid ? norm2_12(r[j]) : 0.0);
-    if (lane == 0) partial[((int64_t)W.vs[j] * p.n_tiles + tile) * kPartialSlots] = n2;
 #pragma unroll
     for (int i = 0; i < 12; ++i) t[j][i] += r[j][i];
     A yi[12];
-    apply_dinv(dinv + (int64_t)W.ds[j] * dstride + tile * kDinvTile, lane, t[j], yi);
+    apply_dinv(dinv + (int64_t)W.ds[j] * dstride + tile * kDinvTile, rl, t[j], yi);
     if (valid) {
       store_vec(y + rb + W.vs[j] * 12, yi);
       if (LAST) {
@@ -449,7 +484,7 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
 
 // General colouring, backward pass of colour c (rows of higher colours are >= cend and
 // already hold z in y):  z_i = y_i - Dt_i^-1 sum_{k upper} K_ik z_k;  x_i += z_i; y_i <- z_i
-template <typename TB, int P>
+template <typename TB, int SW, int P>
 __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict__ offd,
                                              const typename TV_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                              typename TV_of<TB>::T* __restrict__ x,
@@ -461,24 +496,28 @@ __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict_
   if (!map_tile(nt, 1, tile, grp)) return;
   tile += t0;
   const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int sidx = lane % SW;
+  const int rl = w * (kLanes / SW) + lane / SW;
   WaveSys<P> W;
-  if (!wave_systems<P>(sb, st, threadIdx.x >> 6, false, W)) return;
-  const int64_t row = tile * kLanes + lane;
-  const bool valid = lane < p.tile_nrows[tile];
+  const bool any = row_systems<SW, P>(sb, st, sidx, false, W);
+  if (!__any(any)) return;
+  const int64_t row = tile * kLanes + rl;
+  const bool valid = rl < p.tile_nrows[tile];
   const int64_t rb = row * ns * 12;
   A t[P][12];
 #pragma unroll
   for (int j = 0; j < P; ++j)
 #pragma unroll
     for (int i = 0; i < 12; ++i) t[j][i] = 0;
-  const int w = p.tile_width[tile];
+  const int wd = p.tile_width[tile];
   const int64_t s0 = p.tile_slot0[tile];
-  for (int q = 0; q < w; ++q) {
+  for (int q = 0; q < wd; ++q) {
     const int64_t slot = s0 + q;
-    const int nb = p.ent_nbr[slot * kLanes + lane];
+    const int nb = p.ent_nbr[slot * kLanes + rl];
     if (nb >= cend) {
       A kb[36];
-      load_block(offd + slot * slot_elems<TB>(), lane, kb);
+      load_block(offd + slot * slot_elems<TB>(), rl, kb);
       const int64_t nbo = (int64_t)nb * ns * 12;
 #pragma unroll
       for (int j = 0; j < P; ++j) {
@@ -493,7 +532,7 @@ __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict_
   for (int j = 0; j < P; ++j) {
     if (!W.run[j]) continue;
     A z[12];
-    apply_dinv(dinv + (int64_t)W.ds[j] * dstride + tile * kDinvTile, lane, t[j], z);
+    apply_dinv(dinv + (int64_t)W.ds[j] * dstride + tile * kDinvTile, rl, t[j], z);
     if (valid) {
       A yi[12], xi[12];
       load_vec(y + rb + W.vs[j] * 12, yi);
@@ -575,8 +614,11 @@ __device__ inline void reduce_one(const double* __restrict__ partial, int64_t n_
   __shared__ double sh[256];
   double s = 0.0;
   if (mode != kReduceSweepNoNorm) {
+    // each thread sums whole tiles (their slots in order): a fixed order, no divisions
     const double* pp = partial + ((int64_t)vs * n_tiles + t0) * kPartialSlots;
-    for (int64_t i = threadIdx.x; i < nt * slots; i += 256) s += pp[(i / slots) * kPartialSlots + (i % slots)];
+    const int n = (int)nt;
+    for (int t = threadIdx.x; t < n; t += 256)
+      for (int q = 0; q < slots; ++q) s += pp[(int64_t)t * kPartialSlots + q];
   }
   sh[threadIdx.x] = s;
   __syncthreads();
@@ -1252,38 +1294,56 @@ void launch_fwd(const SweepCfg& c, bool last, const DevPattern& p, const void* o
                 const void* dinv, int64_t dinv_stride, void* x, const void* b, void* y, int ns, const SysBatch& sb,
                 const SysState* st, double* partial, int64_t t0, int64_t nt, int64_t cstart, hipStream_t s) {
   if (nt <= 0 || sb.n <= 0) return;
-  const int P = lanes_p(c, sb.n);
+  int SW, P;
+  rb_shape(c, sb.n, SW, P);
   dim3 grid = tile_grid(nt, 1);
-  dim3 block = block_for(sb.n, P);
+  dim3 block(64 * SW);
+#define FNLH_FWD_LAUNCH(SWV)                                                                                      \
+  FNLH_DISPATCH_P(P, {                                                                                            \
+    if (last)                                                                                                     \
+      hipLaunchKernelGGL((k_fwd<TB, SWV, PP, true>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag,      \
+                         (const A*)dinv, dinv_stride, (A*)x, (const A*)b, (A*)y, ns, sb, st, partial, t0, nt,     \
+                         cstart);                                                                                 \
+    else                                                                                                          \
+      hipLaunchKernelGGL((k_fwd<TB, SWV, PP, false>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag,     \
+                         (const A*)dinv, dinv_stride, (A*)x, (const A*)b, (A*)y, ns, sb, st, partial, t0, nt,     \
+                         cstart);                                                                                 \
+  })
   FNLH_DISPATCH_STORE(c.storage, {
     using A = typename Fmt<TB>::A;
-    FNLH_DISPATCH_P(P, {
-      if (last)
-        hipLaunchKernelGGL((k_fwd<TB, PP, true>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag,
-                           (const A*)dinv, dinv_stride, (A*)x, (const A*)b, (A*)y, ns, sb, st, partial, t0, nt,
-                           cstart);
-      else
-        hipLaunchKernelGGL((k_fwd<TB, PP, false>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag,
-                           (const A*)dinv, dinv_stride, (A*)x, (const A*)b, (A*)y, ns, sb, st, partial, t0, nt,
-                           cstart);
-    });
+    if (SW == 1)
+      FNLH_FWD_LAUNCH(1);
+    else if (SW == 2)
+      FNLH_FWD_LAUNCH(2);
+    else
+      FNLH_FWD_LAUNCH(4);
   });
+#undef FNLH_FWD_LAUNCH
 }
 
 void launch_bwd(const SweepCfg& c, const DevPattern& p, const void* offd, const void* dinv, int64_t dinv_stride,
                 void* x, void* y, int ns, const SysBatch& sb, const SysState* st, int64_t t0, int64_t nt,
                 int64_t cend, hipStream_t s) {
   if (nt <= 0 || sb.n <= 0) return;
-  const int P = lanes_p(c, sb.n);
+  int SW, P;
+  rb_shape(c, sb.n, SW, P);
   dim3 grid = tile_grid(nt, 1);
-  dim3 block = block_for(sb.n, P);
+  dim3 block(64 * SW);
+#define FNLH_BWD_LAUNCH(SWV)                                                                                  \
+  FNLH_DISPATCH_P(P, {                                                                                        \
+    hipLaunchKernelGGL((k_bwd<TB, SWV, PP>), grid, block, 0, s, p, (const TB*)offd, (const A*)dinv, dinv_stride, \
+                       (A*)x, (A*)y, ns, sb, st, t0, nt, cend);                                               \
+  })
   FNLH_DISPATCH_STORE(c.storage, {
     using A = typename Fmt<TB>::A;
-    FNLH_DISPATCH_P(P, {
-      hipLaunchKernelGGL((k_bwd<TB, PP>), grid, block, 0, s, p, (const TB*)offd, (const A*)dinv, dinv_stride,
-                         (A*)x, (A*)y, ns, sb, st, t0, nt, cend);
-    });
+    if (SW == 1)
+      FNLH_BWD_LAUNCH(1);
+    else if (SW == 2)
+      FNLH_BWD_LAUNCH(2);
+    else
+      FNLH_BWD_LAUNCH(4);
   });
+#undef FNLH_BWD_LAUNCH
 }
 
 void launch_jacobi(const SweepCfg& c, const DevPattern& p, const void* offd, const void* diag, const void* dinv,

@@ -408,3 +408,33 @@ def test_graph_replay_after_buffer_reallocation(F):
             assert np.all(np.isfinite(a))
             assert np.array_equal(a, b)
     c.close()
+
+
+def test_every_general_path_shape_covers_all_systems(F):
+    # general colouring (triangles): 11 systems under every kernel shape, iterates equal
+    # the oracle's and do not depend on the shape
+    m = synth.multi_row(5, 6, 3, n_blades=(36, 60, 48), seed=7)
+    Q = synth.flow_state(m, 7)
+    K = assemble.assemble(m, Q)
+    om = synth.omegas_multi_row(10, (36, 60, 48))
+    bs = [synth.rhs(m.n_cells, s, real=(s == 0)) for s in range(11)]
+    ref = None
+    for lpr in (0, 1, 2, 4):
+        for spw in (0, 1, 4):
+            c = _ctx(F, m, Q)
+            c.set_harmonics(om)
+            c.tune(spw, lpr)
+            st, rep, xs = _solve(c, list(range(11)), bs, kind="dilu", max_sweeps=12, rtol=0.0)
+            assert all(r["sweeps"] == 12 for r in rep), (lpr, spw)
+            if ref is None:
+                ref = xs
+                col, nc = c.ordering()
+                assert nc >= 3
+                for s in (0, 5, 10):
+                    x_or, _ = solve.richardson(K, m.volume, m.zone, om[s], bs[s], col, "DILU", rtol=0.0,
+                                               max_sweeps=12)
+                    assert relerr(xs[s], x_or) <= ITER_TOL
+            else:
+                for a, b in zip(ref, xs):
+                    assert np.array_equal(a, b), (lpr, spw)
+            c.close()

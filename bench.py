@@ -546,15 +546,25 @@ def main():
 
     modes = {}
     if not args.no_modes:
+        sols = {args.storage: [x.clone() for x in main_run.xd]}
         for s in ("f64", "f32", "bf16"):
             if s == args.storage:
                 continue
             r = Runner(mesh, Q, om, bs, s, check_every=args.check_every, use_graph=not args.no_graph)
             m = r.timed(3, 1)
+            sols[s] = [x.clone() for x in r.xd]
             modes[s] = {"ms_per_step": round(m["ms_per_step"], 3), "updates_per_s": round(m["updates_per_s"]),
                         "sweeps": m["sweeps"], "outer": m["outer"], "rel_res": m["rel_res"]}
             r.ctx.close()
             print(f"[bench] {s}: {m['ms_per_step']:.2f} ms/step, sweeps {m['sweeps']}", file=sys.stderr, flush=True)
+        # error of each precision's solution against the FP64 one (the FP64 path is held
+        # to the oracle by the parity tests)
+        for s, xs in sols.items():
+            err = [float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) for a, b in zip(xs, sols["f64"])]
+            if s == args.storage:
+                res["err_vs_f64"] = err
+            else:
+                modes[s]["err_vs_f64"] = err
 
     learned = None
     if not args.no_learned:
@@ -590,6 +600,7 @@ def main():
         "sweeps": res["sweeps"],
         "outer": res["outer"],
         "rel_res": res["rel_res"],
+        "err_vs_f64": res.get("err_vs_f64"),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "modes": modes,

@@ -1201,6 +1201,9 @@ inline dim3 block_for(int n, int P) {
     } else if ((P) == 2) {                               \
       constexpr int PP = 2;                              \
       BODY;                                              \
+    } else if ((P) == 3) {                               \
+      constexpr int PP = 3;                              \
+      BODY;                                              \
     } else {                                             \
       constexpr int PP = 4;                              \
       BODY;                                              \
@@ -1217,7 +1220,7 @@ void rb_shape(const SweepCfg& c, int n, int& SW, int& P) {
   if (SW < sw_need) SW = sw_need;
   P = (n + SW - 1) / SW;
   if (c.spw > 0 && c.spw > P) P = c.spw;
-  P = P <= 1 ? 1 : (P <= 2 ? 2 : 4);
+  if (P > 4) P = 4;
 }
 int rb_slots(const SweepCfg& c, int n) {
   int SW, P;

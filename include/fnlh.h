@@ -231,7 +231,10 @@ int fnlh_batch_create(fnlh_batch* out, int32_t n, const fnlh_ctx* inst);
 int fnlh_batch_destroy(fnlh_batch b);
 /* Per instance i: n_sys[i] systems sys[i][j], vectors x[i][j] (in: x0, out: x) and
  * b[i][j] as in fnlh_relax.  rep has sum(n_sys) entries in instance order.
- * opts.kind must be FNLH_DILU or FNLH_SGS.  Returns the worst status. */
+ * opts.kind is FNLH_DILU, FNLH_SGS or FNLH_LEARNED (every instance then needs a network
+ * with weights; the learned corrections run per instance between batched chunks of
+ * learn_every sweeps, or after every FP64 correction in reduced precision).  Returns
+ * the worst status. */
 int fnlh_batch_relax(fnlh_batch b, const int32_t* n_sys, const int32_t* const* sys, double* const* const* x,
                      const double* const* const* bvec, const fnlh_relax_opts* opts, fnlh_sys_report* rep,
                      void* stream);

@@ -1174,8 +1174,8 @@ int fnlh_batch_relax(fnlh_batch B, const int32_t* n_sys, const int32_t* const* s
                      const double* const* const* bvec, const fnlh_relax_opts* o, fnlh_sys_report* rep, void* stream) {
   if (!B) return FNLH_E_ARG;
   if (!n_sys || !sys || !x || !bvec || !o) return bset_err(B, FNLH_E_ARG, "batch_relax: bad arguments");
-  if (o->kind != FNLH_DILU && o->kind != FNLH_SGS)
-    return bset_err(B, FNLH_E_ARG, "batch_relax: kind must be DILU or SGS");
+  if (o->kind != FNLH_DILU && o->kind != FNLH_SGS && o->kind != FNLH_LEARNED)
+    return bset_err(B, FNLH_E_ARG, "batch_relax: kind must be DILU, SGS or LEARNED");
   hipStream_t s = S(stream);
   const int n = (int)B->inst.size();
   std::vector<int> base(n + 1, 0);
@@ -1310,8 +1310,35 @@ int fnlh_batch_relax(fnlh_batch B, const int32_t* n_sys, const int32_t* const* s
       }
       HIPC(nullptr, hipMemcpyAsync(B->desc.p, desc.data(), sizeof(InstDesc) * desc.size(), hipMemcpyHostToDevice, s),
            "upload");
-      if ((rc = batched_loop(B, storage, o->rtol, P0.divf, o->max_sweeps, P0.check_every, P0.use_graph, total, s)))
-        return rc;
+      if (!P0.learned) {
+        if ((rc = batched_loop(B, storage, o->rtol, P0.divf, o->max_sweeps, P0.check_every, P0.use_graph, total, s)))
+          return rc;
+      } else {
+        // batched chunks of sweeps, each followed by the learned correction of every
+        // instance that still iterates
+        for (int done = 0;;) {
+          const int chunk = std::max(1, std::min(P0.learn_every, o->max_sweeps + 1 - done));
+          if ((rc = batched_loop(B, storage, o->rtol, P0.divf, chunk, P0.check_every, P0.use_graph, total, s, true)))
+            return rc;
+          done += chunk;
+          bool any = false;
+          std::vector<char> act(n, 0);
+          for (int i = 0; i < n; ++i)
+            if (batched[i])
+              for (int k = 0; k < n_sys[i]; ++k) act[i] |= B->h_st[base[i] + k].active != 0;
+          for (int i = 0; i < n; ++i) any |= act[i] != 0;
+          if (!any || done > o->max_sweeps) break;
+          for (int i = 0; i < n; ++i) {
+            if (!act[i]) continue;
+            fnlh_ctx c = B->inst[i];
+            if ((rc = nn_learned_step(c, n_sys[i], sbs[i], (double*)c->x64.p, (const double*)c->b64.p, nullptr,
+                                      dst + base[i], s))) {
+              B->err = c->err;
+              return rc;
+            }
+          }
+        }
+      }
     } else {
       for (int i = 0; i < n; ++i) {
         if (!batched[i]) continue;
@@ -1341,6 +1368,16 @@ int fnlh_batch_relax(fnlh_batch B, const int32_t* n_sys, const int32_t* const* s
         for (int i = 0; i < n; ++i)
           if (batched[i])
             inner_to_outer(B->inst[i], n_sys[i], sbs[i], dst + base[i], dso + base[i], o->rtol, P0.divf, s);
+        if (P0.learned)
+          for (int i = 0; i < n; ++i) {
+            if (!batched[i]) continue;
+            fnlh_ctx c = B->inst[i];
+            if ((rc = nn_learned_step(c, n_sys[i], sbs[i], (double*)c->x64.p, (const double*)c->b64.p,
+                                      (double*)c->r64.p, dso + base[i], s))) {
+              B->err = c->err;
+              return rc;
+            }
+          }
       }
     }
   }
@@ -1361,8 +1398,19 @@ int fnlh_batch_relax(fnlh_batch B, const int32_t* n_sys, const int32_t* const* s
     if (r < 0) return;
     if (r == FNLH_DIVERGED || (r == FNLH_NOT_CONVERGED && worst == FNLH_OK)) worst = r;
   };
-  for (int i = 0; i < n; ++i)
-    if (batched[i]) fold(relax_reports(B->h_st + base[i], n_sys[i], plans[i], o, rep ? rep + base[i] : nullptr));
+  for (int i = 0; i < n; ++i) {
+    if (!batched[i]) continue;
+    std::vector<int> counts;
+    if (plans[i].learned) {
+      counts.assign(2 * n_sys[i], 0);
+      if ((rc = nn_relax_counts(B->inst[i], n_sys[i], counts.data(), s))) {
+        B->err = B->inst[i]->err;
+        return rc;
+      }
+    }
+    fold(relax_reports(B->h_st + base[i], n_sys[i], plans[i], o, rep ? rep + base[i] : nullptr,
+                       plans[i].learned ? counts.data() : nullptr));
+  }
   // the rest one by one
   for (int i = 0; i < n; ++i) {
     if (batched[i]) continue;

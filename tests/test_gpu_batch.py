@@ -88,3 +88,41 @@ def test_batch_repeated_solves_graph(F):
                     assert np.array_equal(a, b)
         torch.cuda.synchronize()
     B.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_batch_learned_converges(F, storage):
+    """Learned corrections in the batched solver: every instance carries a network with
+    the same weights (the network is local per edge, so one set of weights serves every
+    mesh); the batched instances and the one solved alone all reach the tolerance, and
+    the corrections are counted."""
+    import torch
+    insts = _instances(F, storage, SPECS)
+    nets = []
+    w = synth.he_init(3)
+    for (_, _, c, _, _) in insts:
+        net = F.Network(c)
+        net.set_weights(w)
+        nets.append(net)
+    B = F.Batch([c for (_, _, c, _, _) in insts])
+    systems = [list(range(len(bs))) for (_, _, _, _, bs) in insts]
+    xs = [[torch.zeros((m.n_cells, 6), dtype=torch.complex128, device="cuda") for _ in bs] for (m, _, _, _, bs) in insts]
+    bd = [[to_dev(b) for b in bs] for (_, _, _, _, bs) in insts]
+    st, reps = B.relax(systems, xs, bd, kind="learned", max_sweeps=3000, rtol=1e-9, check_every=8, use_graph=True,
+                       learn_every=16)
+    torch.cuda.synchronize()
+    assert st == 0, reps
+    steps = 0
+    for i, (m, Q, c, om, bs) in enumerate(insts):
+        for j in range(len(bs)):
+            assert reps[i][j]["rel_res"] <= 1e-9, (i, j, reps[i][j])
+            steps += reps[i][j]["learned"] + reps[i][j]["fallbacks"]
+            r = torch.empty_like(xs[i][j])
+            n2 = c.residual(j, xs[i][j], bd[i][j], r)
+            assert np.sqrt(n2) <= 1e-9 * reps[i][j]["res0"] * 1.0001
+    assert steps > 0
+    B.close()
+    for net in nets:
+        net.close()
+    for (_, _, c, _, _) in insts:
+        c.close()

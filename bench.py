@@ -445,6 +445,61 @@ def run_batch(args):
     print(f"[bench] batched: {1e3 * tb:.1f} ms per step", file=sys.stderr, flush=True)
     tl, reps_l = timeit(loop, max(1, args.steps // 2), 1)
     print(f"[bench] per-instance loop: {1e3 * tl:.1f} ms per step", file=sys.stderr, flush=True)
+    learned = None
+    if not args.no_learned:
+        # one set of weights for every instance (the network is local per edge): trained
+        # on pairs from the plain solver of the largest instance, then batched learned
+        # solves of all instances
+        big = max(range(len(ctxs)), key=lambda i: ctxs[i].n)
+        nets = [fnlh.Network(c) for c in ctxs]
+        for net in nets:
+            net.set_weights(synth.he_init(0))
+        cb, nb = ctxs[big], nets[big]
+        zero = torch.zeros((cb.n, 6), dtype=torch.complex128, device="cuda")
+        gen = torch.Generator(device="cuda").manual_seed(77)
+        n_pairs = 256
+        nb.reserve_pairs(n_pairs)
+        t0 = time.perf_counter()
+        k = 0
+        while nb.n_pairs() < n_pairs:
+            take = min(len(systems[big]), n_pairs - nb.n_pairs())
+            xs_ = [torch.randn((cb.n, 6), dtype=torch.complex128, device="cuda", generator=gen) for _ in range(take)]
+            cb.relax(list(range(take)), xs_, [zero] * take, kind="dilu", max_sweeps=[4, 8, 16, 32, 64, 128][k % 6],
+                     rtol=0.0, check_every=16, use_graph=True)
+            for j in range(take):
+                r = torch.empty_like(xs_[j])
+                cb.residual(j, xs_[j], zero, r)
+                nb.add_pairs([j], [r], [-xs_[j]])
+            k += 1
+        hist = nb.train(128, batch=8, lr=1e-3, seed=1)
+        w = nb.get_weights()
+        for net in nets:
+            net.set_weights(w)
+        t_train = time.perf_counter() - t0
+
+        def batched_learned():
+            for row in xd:
+                for x in row:
+                    x.zero_()
+            st, reps = B.relax(systems, xd, bd, kind="learned", max_sweeps=5000, rtol=RTOL,
+                               check_every=args.check_every, use_graph=not args.no_graph, learn_every=args.learn_every)
+            if st != 0:
+                raise RuntimeError(f"batched learned solve status {st}")
+            return reps
+
+        tln, reps_ln = timeit(batched_learned, max(1, args.steps // 2), 1)
+        print(f"[bench] batched learned: {1e3 * tln:.1f} ms per step", file=sys.stderr, flush=True)
+        learned = {"ms": round(1e3 * tln, 3), "vs_batched_plain": round(tb / tln, 3),
+                   "sweeps_total": sum(r["sweeps"] for rep in reps_ln for r in rep),
+                   "plain_sweeps_total": sum(r["sweeps"] for rep in reps_b for r in rep),
+                   "learned_steps": sum(r["learned"] for rep in reps_ln for r in rep),
+                   "rejected": sum(r["fallbacks"] for rep in reps_ln for r in rep),
+                   "worst_rel_res": max(r["rel_res"] for rep in reps_ln for r in rep),
+                   "training": {"pairs": n_pairs, "steps": 128, "batch": 8, "generate_and_train_s": round(t_train, 2),
+                                "loss_first": round(float(np.mean(hist[:12])), 4),
+                                "loss_last": round(float(np.mean(hist[-12:])), 4), "on_instance_cells": cb.n}}
+        for net in nets:
+            net.close()
     ncell = [c.n for c in ctxs]
     updates = sum(ncell[i] * r["sweeps"] for i, rep in enumerate(reps_b) for r in rep)
     worst = max(r["rel_res"] for rep in reps_b for r in rep)
@@ -463,6 +518,7 @@ def run_batch(args):
         "batched_speedup_vs_loop": round(tl / tb, 3),
         "sweeps_min_max": [min(sweeps), max(sweeps)], "worst_rel_res": worst,
         "autotune": {str(k): v for k, v in tuned.items()}, "setup_s": round(setup_s, 1),
+        "learned_batched": learned,
     }
     print(json.dumps(out), flush=True)
     B.close()

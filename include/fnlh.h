@@ -71,7 +71,10 @@ enum {
   FNLH_E_ORDER = -6       /* call made in the wrong order                       */
 };
 
-/* block storage precision (matrix K and its shadow); D~^-1 is never below FP32 */
+/* block storage precision (matrix K and its shadow).  The factor inverses D~^-1 are FP64
+ * with FP64 blocks and FP16 with a power-of-two scale per row otherwise: they only shape
+ * the preconditioner, whose precision the FP64 outer residual makes irrelevant to the
+ * converged result. */
 enum { FNLH_F64 = 0, FNLH_F32 = 1, FNLH_BF16 = 2 };
 /* operator of the outer (FP64) residual in reduced-precision modes:
  *   EXACT  - the FP64 operator: recomputed from the FP64 state and geometry after

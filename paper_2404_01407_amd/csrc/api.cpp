@@ -119,7 +119,7 @@ int ensure_vectors(fnlh_ctx c, int n) {
 
 int ensure_slots(fnlh_ctx c, int slots) {
   if (slots <= c->n_slots) return FNLH_OK;
-  const size_t per = (size_t)c->L.n_tiles * kDinvTileReals * c->tv_bytes();
+  const size_t per = (size_t)c->L.n_tiles * dinv_tile_elems(c->storage) * dinv_elem_bytes(c->storage);
   int rc = dalloc(c, c->dinv, per * slots, "alloc factor slots");
   if (rc) return rc;
   HIPC(c, hipMemset(c->dinv.p, 0, per * slots), "zero factors");
@@ -129,7 +129,7 @@ int ensure_slots(fnlh_ctx c, int slots) {
   return FNLH_OK;
 }
 
-int64_t dinv_stride(fnlh_ctx c) { return c->L.n_tiles * kDinvTileReals; }
+int64_t dinv_stride(fnlh_ctx c) { return c->L.n_tiles * dinv_tile_elems(c->storage); }
 
 void invalidate_factors(fnlh_ctx c) {
   std::fill(c->slot_sys.begin(), c->slot_sys.end(), -1);
@@ -242,12 +242,13 @@ double alg_bytes(fnlh_ctx c, int kind, int col, int na) {
   const double sA = (double)c->block_bytes();
   const double sv = (double)c->tv_bytes();
   const double blk = 36.0 * sA;
+  const double dv = dinv_row_bytes(c->storage);  // one row's factor inverse
   auto nrows = [&](int cc) { return (double)L.ccount[cc]; };
   double shared = 0.0, per = 0.0;
   switch (kind) {
     case FNLH_KSTAT_SWEEP_UPDATE:
       shared = L.c_deg[col] * (blk + 4) + nrows(col) * (blk + 12);
-      per = nrows(col) * (3 * 12 + 72) * sv + L.c_nbr[col] * 12 * sv;
+      per = nrows(col) * (3 * 12 * sv + dv) + L.c_nbr[col] * 12 * sv;
       break;
     case FNLH_KSTAT_SWEEP_SET:  // solves with the shifted diagonal block, no factor read
       shared = L.c_deg[col] * (blk + 4) + nrows(col) * (blk + 12);
@@ -256,18 +257,18 @@ double alg_bytes(fnlh_ctx c, int kind, int col, int na) {
     case FNLH_KSTAT_FWD: {
       const bool last = col == L.n_colours - 1;
       shared = L.c_deg[col] * (blk + 4) + nrows(col) * (blk + 12);
-      per = nrows(col) * ((last ? 4 : 3) * 12 + 72) * sv + (L.c_nbr[col] + L.c_nbr_lower[col]) * 12 * sv;
+      per = nrows(col) * ((last ? 4 : 3) * 12 * sv + dv) + (L.c_nbr[col] + L.c_nbr_lower[col]) * 12 * sv;
       break;
     }
     case FNLH_KSTAT_BWD:
       shared = L.c_deg_upper[col] * blk + L.c_deg[col] * 4;
-      per = nrows(col) * (4 * 12 + 72) * sv + L.c_nbr_upper[col] * 12 * sv;
+      per = nrows(col) * (4 * 12 * sv + dv) + L.c_nbr_upper[col] * 12 * sv;
       break;
     case FNLH_KSTAT_JACOBI: {
       double deg = 0;
       for (int cc = 0; cc < L.n_colours; ++cc) deg += L.c_deg[cc];
       shared = deg * (blk + 4) + (double)L.N * (blk + 12);
-      per = (double)L.N * (3 * 12 + 72) * sv;
+      per = (double)L.N * (3 * 12 * sv + dv);
       break;
     }
   }

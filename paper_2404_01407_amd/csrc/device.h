@@ -88,13 +88,24 @@ template <> __device__ inline double load_entry_f64<bf16s>(const bf16s* s, int q
   return (double)bf16_to_f32(s[((q >> 3) * kLanes + lane) * 8 + (q & 7)].v);
 }
 
+// Read-once streams (blocks, factors) use non-temporal loads so they do not displace
+// the neighbour vectors that other rows read again from the cache.
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef unsigned int nt_u4 __attribute__((ext_vector_type(4)));
+__device__ inline nt_f4 ld_stream(const float4* p) { return __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p)); }
+__device__ inline nt_d2 ld_stream(const double2* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+}
+__device__ inline nt_u4 ld_stream(const uint4* p) { return __builtin_nontemporal_load(reinterpret_cast<const nt_u4*>(p)); }
+
 // Whole block of one lane, 16-byte vector loads, converted to the arithmetic type A.
 template <typename T, typename A> __device__ inline void load_block(const T* __restrict__ slot, int lane, A (&k)[36]);
 template <typename A> __device__ inline void load_block(const double* __restrict__ s, int lane, A (&k)[36]) {
   const double2* p = reinterpret_cast<const double2*>(s) + lane;
 #pragma unroll
   for (int v = 0; v < 18; ++v) {
-    double2 d = p[v * kLanes];
+    const nt_d2 d = ld_stream(p + v * kLanes);
     k[2 * v] = (A)d.x;
     k[2 * v + 1] = (A)d.y;
   }
@@ -103,7 +114,7 @@ template <typename A> __device__ inline void load_block(const float* __restrict_
   const float4* p = reinterpret_cast<const float4*>(s) + lane;
 #pragma unroll
   for (int v = 0; v < 9; ++v) {
-    float4 d = p[v * kLanes];
+    const nt_f4 d = ld_stream(p + v * kLanes);
     k[4 * v] = (A)d.x;
     k[4 * v + 1] = (A)d.y;
     k[4 * v + 2] = (A)d.z;
@@ -114,7 +125,7 @@ template <typename A> __device__ inline void load_block(const bf16s* __restrict_
   const uint4* p = reinterpret_cast<const uint4*>(s) + lane;
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    uint4 d = p[v * kLanes];
+    const nt_u4 d = ld_stream(p + v * kLanes);
     uint32_t w[4] = {d.x, d.y, d.z, d.w};
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
@@ -135,7 +146,22 @@ template <> struct DFmt<double> {
 template <> struct DFmt<float> {
   static constexpr int NV = 18;
 };
-constexpr int64_t kDinvTile = 72 * kLanes;  // reals per tile (kDinvTileReals on the host)
+// Reduced-precision factors: FP16 entries with a power-of-two scale per row.  A tile is
+// [9][lane][8 halves] (four complex entries per 16-byte vector, row-major) followed by
+// one float scale per lane: 74 * 64 two-byte elements.
+struct hfac {
+  uint16_t v;
+};
+template <typename TD> struct DinvTile;  // elements of TD per tile (dinv_tile_elems on the host)
+template <> struct DinvTile<double> {
+  static constexpr int64_t N = 72 * kLanes;
+};
+template <> struct DinvTile<float> {
+  static constexpr int64_t N = 72 * kLanes;
+};
+template <> struct DinvTile<hfac> {
+  static constexpr int64_t N = 74 * kLanes;
+};
 
 template <typename TD> __device__ inline void store_dinv(TD* tile, int lane, const double (&re)[36], const double (&im)[36]);
 template <> __device__ inline void store_dinv<double>(double* t, int lane, const double (&re)[36], const double (&im)[36]) {
@@ -150,6 +176,30 @@ template <> __device__ inline void store_dinv<float>(float* t, int lane, const d
     p[v * kLanes] = make_float4((float)re[2 * v], (float)im[2 * v], (float)re[2 * v + 1], (float)im[2 * v + 1]);
 }
 
+template <> __device__ inline void store_dinv<hfac>(hfac* t, int lane, const double (&re)[36], const double (&im)[36]) {
+  double m = 0.0;
+#pragma unroll
+  for (int c = 0; c < 36; ++c) m = fmax(m, fmax(fabs(re[c]), fabs(im[c])));
+  // entries scaled by 2^(14 - e) with m in [2^e, 2^(e+1)) stay below 2^15 (FP16 max 65504)
+  int e = 0;
+  if (m > 0.0 && isfinite(m)) e = ilogb(m);
+  const double up = ldexp(1.0, 14 - e);
+  uint4* p = reinterpret_cast<uint4*>(t) + lane;
+#pragma unroll
+  for (int v = 0; v < 9; ++v) {
+    uint32_t w[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int c = 4 * v + h;
+      const uint16_t a = __builtin_bit_cast(uint16_t, (_Float16)(float)(re[c] * up));
+      const uint16_t b = __builtin_bit_cast(uint16_t, (_Float16)(float)(im[c] * up));
+      w[h] = (uint32_t)a | ((uint32_t)b << 16);
+    }
+    p[v * kLanes] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+  reinterpret_cast<float*>(t + 72 * kLanes)[lane] = (float)ldexp(1.0, e - 14);
+}
+
 // y = Dinv a, complex; Dinv streamed from memory row by row.
 template <typename TD, typename A>
 __device__ inline void apply_dinv(const TD* __restrict__ t, int lane, const A (&a)[12], A (&y)[12]);
@@ -161,7 +211,7 @@ __device__ inline void apply_dinv(const double* __restrict__ t, int lane, const 
     A yr = 0, yi = 0;
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      double2 d = p[(6 * r + c) * kLanes];
+      const nt_d2 d = ld_stream(p + (6 * r + c) * kLanes);
       yr += (A)d.x * a[2 * c] - (A)d.y * a[2 * c + 1];
       yi += (A)d.x * a[2 * c + 1] + (A)d.y * a[2 * c];
     }
@@ -177,7 +227,7 @@ __device__ inline void apply_dinv(const float* __restrict__ t, int lane, const A
     A yr = 0, yi = 0;
 #pragma unroll
     for (int h = 0; h < 3; ++h) {
-      float4 d = p[(3 * r + h) * kLanes];
+      const nt_f4 d = ld_stream(p + (3 * r + h) * kLanes);
       const int c0 = 2 * h, c1 = 2 * h + 1;
       yr += (A)d.x * a[2 * c0] - (A)d.y * a[2 * c0 + 1] + (A)d.z * a[2 * c1] - (A)d.w * a[2 * c1 + 1];
       yi += (A)d.x * a[2 * c0 + 1] + (A)d.y * a[2 * c0] + (A)d.z * a[2 * c1 + 1] + (A)d.w * a[2 * c1];
@@ -186,11 +236,46 @@ __device__ inline void apply_dinv(const float* __restrict__ t, int lane, const A
     y[2 * r + 1] = yi;
   }
 }
+__device__ inline float h2f(uint32_t bits) { return (float)__builtin_bit_cast(_Float16, (uint16_t)bits); }
+template <typename A>
+__device__ inline void apply_dinv(const hfac* __restrict__ t, int lane, const A (&a)[12], A (&y)[12]) {
+  const uint4* p = reinterpret_cast<const uint4*>(t) + lane;
+  uint32_t w[36];
+#pragma unroll
+  for (int v = 0; v < 9; ++v) {
+    const nt_u4 d = ld_stream(p + v * kLanes);
+    w[4 * v] = d.x;
+    w[4 * v + 1] = d.y;
+    w[4 * v + 2] = d.z;
+    w[4 * v + 3] = d.w;
+  }
+  const A sc = (A)reinterpret_cast<const float*>(t + 72 * kLanes)[lane];
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    A yr = 0, yi = 0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const uint32_t q = w[6 * r + c];  // complex entry (r, c): low half re, high half im
+      const A dr = (A)h2f(q & 0xffffu), di = (A)h2f(q >> 16);
+      yr += dr * a[2 * c] - di * a[2 * c + 1];
+      yi += dr * a[2 * c + 1] + di * a[2 * c];
+    }
+    y[2 * r] = yr * sc;
+    y[2 * r + 1] = yi * sc;
+  }
+}
+
 template <typename TD> __device__ inline void load_dinv_entry(const TD* t, int lane, int c, double& re, double& im);
 template <> __device__ inline void load_dinv_entry<double>(const double* t, int lane, int c, double& re, double& im) {
   double2 d = reinterpret_cast<const double2*>(t)[c * kLanes + lane];
   re = d.x;
   im = d.y;
+}
+template <> __device__ inline void load_dinv_entry<hfac>(const hfac* t, int lane, int c, double& re, double& im) {
+  const uint32_t q = reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint4*>(t) + (c >> 2) * kLanes + lane)[c & 3];
+  const double sc = (double)reinterpret_cast<const float*>(t + 72 * kLanes)[lane];
+  re = (double)h2f(q & 0xffffu) * sc;
+  im = (double)h2f(q >> 16) * sc;
 }
 template <> __device__ inline void load_dinv_entry<float>(const float* t, int lane, int c, double& re, double& im) {
   float4 d = reinterpret_cast<const float4*>(t)[(c >> 1) * kLanes + lane];

@@ -7,7 +7,11 @@
 namespace fnlh {
 
 constexpr int kMaxBatch = 16;  // systems handled by one launch
-constexpr int64_t kDinvTileReals = 72 * 64;  // one tile of complex 6x6 inverses
+// One tile of complex 6x6 factor inverses: FP64 with FP64 blocks (72 * 64 doubles), else
+// FP16 entries with a power-of-two scale per row (74 * 64 two-byte elements).
+inline int64_t dinv_tile_elems(int storage) { return storage == 0 ? 72 * 64 : 74 * 64; }
+inline size_t dinv_elem_bytes(int storage) { return storage == 0 ? 8 : 2; }
+inline double dinv_row_bytes(int storage) { return storage == 0 ? 72.0 * 8 : 72.0 * 2 + 4; }
 constexpr int kPartialSlots = 4;             // norm partials per (system, tile): one per wave
 
 // Per-system solver state kept on the device so stop decisions need no host round trip.

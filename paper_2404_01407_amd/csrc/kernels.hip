@@ -31,6 +31,13 @@ inline dim3 tile_grid(int64_t nt, int ng) {
 template <typename TB> struct TV_of {
   using T = typename Fmt<TB>::A;
 };
+// factor storage: FP64 with FP64 blocks, scaled FP16 with FP32 / BF16 blocks
+template <typename TB> struct DF_of {
+  using T = hfac;
+};
+template <> struct DF_of<double> {
+  using T = double;
+};
 
 __device__ inline double shift_w(const DevPattern& p, int orow, int64_t row) {
   return p.omega[(int64_t)orow * p.n_zones + p.zone[row]] * p.vol[row];
@@ -233,7 +240,7 @@ __global__ void k_check_dominance(DevPattern p, const TB* __restrict__ diag, int
 // interleaved layout.  A tile of 64 rows takes SW waves of 64/SW rows each.
 template <typename TB, int SW, int P, bool UPDATE, bool PIVOT>
 __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd, const TB* __restrict__ diag,
-                               const typename TV_of<TB>::T* __restrict__ dinv, int64_t dstride,
+                               const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                typename TV_of<TB>::T* __restrict__ x, const typename TV_of<TB>::T* __restrict__ b,
                                int ns, const SysBatch& sb, const SysState* __restrict__ st,
                                double* __restrict__ partial, int64_t tile) {
@@ -317,7 +324,7 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
     if (!run[j]) continue;
     if (UPDATE) {
       A y[12];
-      apply_dinv(dinv + (int64_t)ds[j] * dstride + tile * kDinvTile, rl, acc[j], y);
+      apply_dinv(dinv + (int64_t)ds[j] * dstride + tile * DinvTile<typename DF_of<TB>::T>::N, rl, acc[j], y);
       if (valid) {
         A xi[12];
         load_vec(x + rb + vs[j] * 12, xi);
@@ -337,7 +344,7 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
 template <typename TB, int SW, int P, bool UPDATE, bool PIVOT>
 __global__ void __launch_bounds__(256) k_rb_pass(DevPattern p, const TB* __restrict__ offd,
                                                  const TB* __restrict__ diag,
-                                                 const typename TV_of<TB>::T* __restrict__ dinv, int64_t dstride,
+                                                 const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                                  typename TV_of<TB>::T* __restrict__ x,
                                                  const typename TV_of<TB>::T* __restrict__ b, int ns, SysBatch sb,
                                                  const SysState* __restrict__ st, double* __restrict__ partial,
@@ -361,10 +368,10 @@ __global__ void __launch_bounds__(256) k_rb_batched(const InstDesc* __restrict__
   const InstDesc& D = inst[wi.inst];
   const bool pivot = D.pivot;
   if (!UPDATE && !pivot)
-    rb_tile<TB, SW, P, UPDATE, false>(D.p, (const TB*)D.offd, (const TB*)D.diag, (const A*)D.dinv, D.dstride,
+    rb_tile<TB, SW, P, UPDATE, false>(D.p, (const TB*)D.offd, (const TB*)D.diag, (const typename DF_of<TB>::T*)D.dinv, D.dstride,
                                       (A*)D.x, (const A*)D.b, D.ns, D.sb, D.st, D.partial, wi.tile);
   else
-    rb_tile<TB, SW, P, UPDATE, true>(D.p, (const TB*)D.offd, (const TB*)D.diag, (const A*)D.dinv, D.dstride,
+    rb_tile<TB, SW, P, UPDATE, true>(D.p, (const TB*)D.offd, (const TB*)D.diag, (const typename DF_of<TB>::T*)D.dinv, D.dstride,
                                      (A*)D.x, (const A*)D.b, D.ns, D.sb, D.st, D.partial, wi.tile);
 }
 
@@ -400,7 +407,7 @@ __device__ inline bool row_systems(const SysBatch& sb, const SysState* __restric
 // system k over the rows of wave w goes to partial slot w.
 template <typename TB, int SW, int P, bool LAST>
 __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict__ offd, const TB* __restrict__ diag,
-                                             const typename TV_of<TB>::T* __restrict__ dinv, int64_t dstride,
+                                             const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                              typename TV_of<TB>::T* __restrict__ x,
                                              const typename TV_of<TB>::T* __restrict__ b,
                                              typename TV_of<TB>::T* __restrict__ y, int ns, SysBatch sb,
@@ -468,7 +475,7 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
 #pragma unroll
     for (int i = 0; i < 12; ++i) t[j][i] += r[j][i];
     A yi[12];
-    apply_dinv(dinv + (int64_t)W.ds[j] * dstride + tile * kDinvTile, rl, t[j], yi);
+    apply_dinv(dinv + (int64_t)W.ds[j] * dstride + tile * DinvTile<typename DF_of<TB>::T>::N, rl, t[j], yi);
     if (valid) {
       store_vec(y + rb + W.vs[j] * 12, yi);
       if (LAST) {
@@ -486,7 +493,7 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
 // already hold z in y):  z_i = y_i - Dt_i^-1 sum_{k upper} K_ik z_k;  x_i += z_i; y_i <- z_i
 template <typename TB, int SW, int P>
 __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict__ offd,
-                                             const typename TV_of<TB>::T* __restrict__ dinv, int64_t dstride,
+                                             const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                              typename TV_of<TB>::T* __restrict__ x,
                                              typename TV_of<TB>::T* __restrict__ y, int ns, SysBatch sb,
                                              const SysState* __restrict__ st, int64_t t0, int64_t nt, int64_t cend) {
@@ -532,7 +539,7 @@ __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict_
   for (int j = 0; j < P; ++j) {
     if (!W.run[j]) continue;
     A z[12];
-    apply_dinv(dinv + (int64_t)W.ds[j] * dstride + tile * kDinvTile, rl, t[j], z);
+    apply_dinv(dinv + (int64_t)W.ds[j] * dstride + tile * DinvTile<typename DF_of<TB>::T>::N, rl, t[j], z);
     if (valid) {
       A yi[12], xi[12];
       load_vec(y + rb + W.vs[j] * 12, yi);
@@ -553,7 +560,7 @@ __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict_
 template <typename TB, int P>
 __global__ void __launch_bounds__(256) k_jacobi(DevPattern p, const TB* __restrict__ offd,
                                                 const TB* __restrict__ diag,
-                                                const typename TV_of<TB>::T* __restrict__ dinv, int64_t dstride,
+                                                const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                                 const typename TV_of<TB>::T* __restrict__ x,
                                                 const typename TV_of<TB>::T* __restrict__ b,
                                                 typename TV_of<TB>::T* __restrict__ y, int ns, SysBatch sb,
@@ -588,7 +595,7 @@ __global__ void __launch_bounds__(256) k_jacobi(DevPattern p, const TB* __restri
     const double n2 = wave_sum(valid ? norm2_12(r[j]) : 0.0);
     if (lane == 0) partial[((int64_t)W.vs[j] * p.n_tiles + tile) * kPartialSlots] = n2;
     A yi[12];
-    apply_dinv(dinv + (int64_t)W.ds[j] * dstride + tile * kDinvTile, lane, r[j], yi);
+    apply_dinv(dinv + (int64_t)W.ds[j] * dstride + tile * DinvTile<typename DF_of<TB>::T>::N, lane, r[j], yi);
     if (valid) store_vec(y + rb + W.vs[j] * 12, yi);
   }
 }
@@ -903,7 +910,7 @@ __global__ void __launch_bounds__(64) k_factor(DevPattern p, const TB* __restric
       const int32_t rv = p.ent_rev[fe];
       const TB* rs = offd + (int64_t)(rv >> 6) * slot_elems<TB>();
       const int rl = rv & 63;
-      const TD* dn = dbase + (int64_t)(nb >> 6) * kDinvTile;
+      const TD* dn = dbase + (int64_t)(nb >> 6) * DinvTile<TD>::N;
       const int nl = nb & 63;
       for (int c = 0; c < 6; ++c) {
         double kc[6];
@@ -947,7 +954,7 @@ __global__ void __launch_bounds__(64) k_factor(DevPattern p, const TB* __restric
       mi[c] = 0.0;
     }
   }
-  store_dinv<TD>(dbase + tile * kDinvTile, lane, mr, mi);
+  store_dinv<TD>(dbase + tile * DinvTile<TD>::N, lane, mr, mi);
 }
 
 // ================================================================ FP64 residuals
@@ -1167,7 +1174,7 @@ void launch_factor(int storage, bool dilu, const DevPattern& p, const void* offd
   if (nt <= 0 || sb.n <= 0) return;
   dim3 grid((unsigned)nt, (unsigned)sb.n);
   FNLH_DISPATCH_STORE(storage, {
-    using TD = typename Fmt<TB>::A;
+    using TD = typename DF_of<TB>::T;
     if (dilu)
       hipLaunchKernelGGL((k_factor<TB, TD, true>), grid, dim3(64), 0, s, p, (const TB*)offd, (const TB*)diag,
                          (TD*)dinv, dinv_stride, sb, t0, nt, cstart, err);
@@ -1240,15 +1247,15 @@ void launch_rb_pass(const SweepCfg& c, bool update, const DevPattern& p, const v
   FNLH_DISPATCH_P(P, {                                                                                          \
     if (update)                                                                                                 \
       hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, true, true>), grid, block, 0, s, p, (const TB*)offd,           \
-                         (const TB*)diag, (const A*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, st, partial, \
+                         (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, st, partial, \
                          t0, nt);                                                                               \
     else if (c.pivot)                                                                                           \
       hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, true>), grid, block, 0, s, p, (const TB*)offd,          \
-                         (const TB*)diag, (const A*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, st, partial, \
+                         (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, st, partial, \
                          t0, nt);                                                                               \
     else                                                                                                        \
       hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, false>), grid, block, 0, s, p, (const TB*)offd,         \
-                         (const TB*)diag, (const A*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, st, partial, \
+                         (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, st, partial, \
                          t0, nt);                                                                               \
   })
   FNLH_DISPATCH_STORE(c.storage, {
@@ -1305,11 +1312,11 @@ void launch_fwd(const SweepCfg& c, bool last, const DevPattern& p, const void* o
   FNLH_DISPATCH_P(P, {                                                                                            \
     if (last)                                                                                                     \
       hipLaunchKernelGGL((k_fwd<TB, SWV, PP, true>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag,      \
-                         (const A*)dinv, dinv_stride, (A*)x, (const A*)b, (A*)y, ns, sb, st, partial, t0, nt,     \
+                         (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, (A*)y, ns, sb, st, partial, t0, nt,     \
                          cstart);                                                                                 \
     else                                                                                                          \
       hipLaunchKernelGGL((k_fwd<TB, SWV, PP, false>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag,     \
-                         (const A*)dinv, dinv_stride, (A*)x, (const A*)b, (A*)y, ns, sb, st, partial, t0, nt,     \
+                         (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, (A*)y, ns, sb, st, partial, t0, nt,     \
                          cstart);                                                                                 \
   })
   FNLH_DISPATCH_STORE(c.storage, {
@@ -1334,7 +1341,7 @@ void launch_bwd(const SweepCfg& c, const DevPattern& p, const void* offd, const 
   dim3 block(64 * SW);
 #define FNLH_BWD_LAUNCH(SWV)                                                                                  \
   FNLH_DISPATCH_P(P, {                                                                                        \
-    hipLaunchKernelGGL((k_bwd<TB, SWV, PP>), grid, block, 0, s, p, (const TB*)offd, (const A*)dinv, dinv_stride, \
+    hipLaunchKernelGGL((k_bwd<TB, SWV, PP>), grid, block, 0, s, p, (const TB*)offd, (const typename DF_of<TB>::T*)dinv, dinv_stride, \
                        (A*)x, (A*)y, ns, sb, st, t0, nt, cend);                                               \
   })
   FNLH_DISPATCH_STORE(c.storage, {
@@ -1360,7 +1367,7 @@ void launch_jacobi(const SweepCfg& c, const DevPattern& p, const void* offd, con
     using A = typename Fmt<TB>::A;
     FNLH_DISPATCH_P(P, {
       hipLaunchKernelGGL((k_jacobi<TB, PP>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag,
-                         (const A*)dinv, dinv_stride, (const A*)x, (const A*)b, (A*)y, ns, sb, st, partial);
+                         (const typename DF_of<TB>::T*)dinv, dinv_stride, (const A*)x, (const A*)b, (A*)y, ns, sb, st, partial);
     });
   });
 }

@@ -305,7 +305,26 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
         sub_kx(acc[j], kb, xn);
       }
     };
-    if (wd == 6) {
+    if constexpr (P == 1 && UPDATE) {
+      // two slots in flight: slot q + 1's block and neighbour vector load while slot q
+      // is applied (the loop otherwise drains all loads before the next slot's issue);
+      // the first-colour pass keeps one slot, its solve needs the registers
+      A kb0[36], kb1[36], xn0[12], xn1[12];
+      auto fetch = [&](int q, A(&kb)[36], A(&xn)[12]) {
+        const int64_t slot = s0 + q;
+        const int nb = p.ent_nbr[slot * kLanes + rl];
+        load_block(offd + slot * slot_elems<TB>(), rl, kb);
+        if (run[0]) load_vec(x + (int64_t)nb * ns * 12 + vs[0] * 12, xn);
+      };
+      if (wd > 0) fetch(0, kb0, xn0);
+      for (int q = 0; q < wd; q += 2) {
+        if (q + 1 < wd) fetch(q + 1, kb1, xn1);
+        if (run[0]) sub_kx(acc[0], kb0, xn0);
+        if (q + 1 >= wd) break;
+        if (q + 2 < wd) fetch(q + 2, kb0, xn0);
+        if (run[0]) sub_kx(acc[0], kb1, xn1);
+      }
+    } else if (wd == 6) {
 #pragma unroll
       for (int q = 0; q < 6; ++q) body(q);
     } else {

@@ -31,6 +31,11 @@ SHAPE = (80, 50, 50)
 N_HARM = 3
 RTOL = 1e-8
 STATS_PERIOD = 4  # time the sweep-pass launches of every 4th sweep (bounds event overhead)
+# HBM bytes per launch of the update pass from two rocprofv3 counter runs (FETCH_SIZE x 2.0
+# + WRITE_SIZE x 1.0, calibrated on a 1 GiB copy), for the kernel these sources build at the
+# default configuration (FP32 blocks, 4 systems, 4 lanes per row):
+# profiles/k_rb_pass_f32_200k_mean3h.md.  Reported only for that configuration.
+UPDATE_PASS_TRAFFIC = {("f32", 4): 227241244}
 
 
 def build_inputs():
@@ -587,8 +592,11 @@ def main():
     avg_ms = upd["total_ms"] / max(upd["launches"], 1)
     bytes_per_launch = upd["alg_bytes"] / max(upd["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic = None
+    if (args.storage, len(bs)) in UPDATE_PASS_TRAFFIC and args.lanes == 0 and args.row_lanes == 0:
+        traffic = UPDATE_PASS_TRAFFIC[(args.storage, len(bs))]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": f"k_rb_pass<{args.storage}, update> (two-colour sweep pass over the second colour)",
                 "avg_launch_us": round(1e3 * avg_ms, 2), "alg_bytes_per_launch": round(bytes_per_launch),
                 "launches": upd["launches"]}

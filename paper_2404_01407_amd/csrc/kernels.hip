@@ -360,8 +360,14 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
   }
 }
 
+// the update pass with one system per lane and FP32 blocks fits four waves per SIMD
+// without spilling (its two neighbour slots in flight otherwise take it to three)
+template <typename TB, int P, bool UPDATE> constexpr int rb_min_waves() {
+  return (UPDATE && P == 1 && sizeof(TB) == 4) ? 4 : 1;
+}
+
 template <typename TB, int SW, int P, bool UPDATE, bool PIVOT>
-__global__ void __launch_bounds__(256) k_rb_pass(DevPattern p, const TB* __restrict__ offd,
+__global__ void __launch_bounds__(256, (rb_min_waves<TB, P, UPDATE>())) k_rb_pass(DevPattern p, const TB* __restrict__ offd,
                                                  const TB* __restrict__ diag,
                                                  const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                                  typename TV_of<TB>::T* __restrict__ x,

@@ -55,6 +55,20 @@ def apply(K: BlockMatrix, Ds, x):
     return y
 
 
+def phase_lagged(K: BlockMatrix, edge_phase, sigma):
+    """K with phase-lagged periodic couplings (section "Solution Update": on periodic
+    boundaries each harmonic carries its own inter-blade phase angle sigma, which changes
+    its left-hand side but not the sparsity pattern).  A periodic edge e = (a, b) with
+    sign s_e = +1 couples a to the image of b one pitch over, whose value is x_b e^{i sigma}:
+    the coupling of row a (entry 2e) is multiplied by e^{i s_e sigma} and that of row b
+    (entry 2e+1) by e^{-i s_e sigma}.  Non-periodic edges (s_e = 0) are unchanged."""
+    s = np.asarray(edge_phase, np.float64)
+    ph = np.empty(2 * s.shape[0], np.complex128)
+    ph[0::2] = np.exp(1j * s * sigma)
+    ph[1::2] = np.exp(-1j * s * sigma)
+    return BlockMatrix(K.n, K.diag.copy(), K.rows.copy(), K.cols.copy(), K.offd * ph[:, None, None])
+
+
 def dense(K: BlockMatrix, volume, zone, omega_row):
     """K_s as a dense [6N, 6N] complex matrix (for pins on small meshes)."""
     n = K.n

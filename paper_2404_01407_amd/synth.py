@@ -20,6 +20,10 @@ geometry here is a seeded stand-in:
 * ``flow_state``: conservative state (rho, rho u, rho v, rho w, rho E, rho nu~) with
   low-mode Fourier variations, Mach 0.3-0.6, density 1 +/- 5 %, nu~ in [1e-5, 1e-3].
 * ``rhs``: i.i.d. N(0,1) real and imaginary parts; the mean (omega = 0) RHS is real.
+* ``cascade_block``: a linear-cascade passage (pitchwise direction y) whose two pitchwise
+  sides are joined by translationally periodic edges, flagged in ``edge_phase`` for the
+  phase-lagged boundary of the harmonic systems; ``n_passages`` > 1 stacks identical
+  passages pitchwise (a full wheel when the closing edges carry no phase).
 """
 from __future__ import annotations
 
@@ -49,6 +53,9 @@ class Mesh:
     n_zones: int = 1
     n_blades: tuple = (36,)
     meta: dict = field(default_factory=dict)
+    # per edge: 0, or +1 / -1 for a periodic coupling whose b side is the image of b one
+    # pitch above (+1) or below (-1) the a side; None when the mesh has no periodic edges
+    edge_phase: np.ndarray = None
 
     @property
     def n_edges(self) -> int:
@@ -113,6 +120,10 @@ class _Block:
 
 def _build_block(nx, nt, nr, n_blades, x0, rng, jitter, theta_shift=0.0):
     P, th = _passage_vertices(nx, nt, nr, n_blades, x0, rng, jitter, theta_shift)
+    return _block_from_vertices(P, th, nx, nt, nr)
+
+
+def _block_from_vertices(P, th, nx, nt, nr):
     faces = _structured_faces(P, nx, nt, nr)
     cen = 0.125 * (P[:-1, :-1, :-1] + P[1:, :-1, :-1] + P[:-1, 1:, :-1] + P[:-1, :-1, 1:]
                    + P[1:, 1:, :-1] + P[1:, :-1, 1:] + P[:-1, 1:, 1:] + P[1:, 1:, 1:])
@@ -183,7 +194,7 @@ def _block_edges(blk: _Block, base: int):
     return (np.concatenate(E_a), np.concatenate(E_b), np.concatenate(E_S)), sides
 
 
-def _finish(n_cells, ea, eb, eS, bc, bS, vol, cen, zone, rng, permute, n_zones, n_blades, meta):
+def _finish(n_cells, ea, eb, eS, bc, bS, vol, cen, zone, rng, permute, n_zones, n_blades, meta, eph=None):
     ea = ea.astype(np.int64)
     eb = eb.astype(np.int64)
     if permute:
@@ -198,6 +209,8 @@ def _finish(n_cells, ea, eb, eS, bc, bS, vol, cen, zone, rng, permute, n_zones, 
         flip = rng.random(ea.shape[0]) < 0.5
         ea, eb = np.where(flip, eb, ea), np.where(flip, ea, eb)
         eS = np.where(flip[:, None], -eS, eS)
+        if eph is not None:
+            eph = np.where(flip, -eph[order], eph[order])
     else:
         meta["struct_to_user"] = np.arange(n_cells)
     edges = np.stack([ea, eb], axis=1).astype(np.int32)
@@ -208,7 +221,8 @@ def _finish(n_cells, ea, eb, eS, bc, bS, vol, cen, zone, rng, permute, n_zones, 
                 bface_cell=np.ascontiguousarray(bc, dtype=np.int32),
                 bface_area=np.ascontiguousarray(bS, dtype=np.float64),
                 centroid=np.ascontiguousarray(cen, dtype=np.float64),
-                n_zones=n_zones, n_blades=tuple(n_blades), meta=meta)
+                n_zones=n_zones, n_blades=tuple(n_blades), meta=meta,
+                edge_phase=None if eph is None else np.ascontiguousarray(eph, dtype=np.int8))
 
 
 def passage_block(nx: int, nt: int, nr: int, n_blades: int = 36, seed: int = 1,
@@ -225,6 +239,58 @@ def passage_block(nx: int, nt: int, nr: int, n_blades: int = 36, seed: int = 1,
             "xi": _cell_frac(blk), "row": np.zeros(n, np.int32)}
     return _finish(n, ea, eb, eS, bc, bS, blk.volume.ravel(), blk.centroid.reshape(-1, 3),
                    np.zeros(n, np.int32), rng, permute, 1, (n_blades,), meta)
+
+
+def cascade_block(nx: int, ny: int, nz: int, n_blades: int = 36, seed: int = 1, jitter: float = 0.1,
+                  permute: bool = True, n_passages: int = 1, stagger: float = 0.3) -> Mesh:
+    """Linear-cascade passage(s) of nx*ny*nz hex cells: axial x in [0, 0.3], pitchwise y
+    over n_passages pitches of 2 pi / n_blades, spanwise z in [0, 0.2], stagger y += 0.3 x.
+    The top and bottom pitchwise sides are joined by translationally periodic edges
+    (top cell a, bottom cell b, area of a's top face; edge_phase +1).  Vertex jitter and
+    the cells' fractional positions repeat with the pitch, so stacked passages are
+    identical copies."""
+    rng = np.random.default_rng(seed)
+    pitch = 2.0 * np.pi / n_blades
+    nyt = ny * n_passages
+    i = np.arange(nx + 1)[:, None, None] + np.zeros((1, nyt + 1, nz + 1))
+    j = np.arange(nyt + 1)[None, :, None] + np.zeros((nx + 1, 1, nz + 1))
+    k = np.arange(nz + 1)[None, None, :] + np.zeros((nx + 1, nyt + 1, 1))
+    x = 0.3 * i / nx
+    y = pitch * j / ny + stagger * x
+    z = 0.2 * k / nz
+    if jitter > 0.0:
+        d = rng.uniform(-1.0, 1.0, size=(3, nx + 1, ny, nz + 1)) * jitter
+        jm = (j % ny).astype(np.int64)
+        ii = i.astype(np.int64)
+        kk = k.astype(np.int64)
+        dd = d[:, ii, jm, kk]
+        interior = (ii > 0) & (ii < nx) & (kk > 0) & (kk < nz)
+        x = x + np.where(interior, dd[0] * 0.3 / nx, 0.0)
+        y = y + np.where(interior, dd[1] * pitch / ny, 0.0)
+        z = z + np.where(interior, dd[2] * 0.2 / nz, 0.0)
+    P = np.stack([x, y, z], axis=-1)
+    blk = _block_from_vertices(P, np.zeros_like(x), nx, nyt, nz)
+    (ea, eb, eS), sides = _block_edges(blk, 0)
+    bc = np.concatenate([sides[kk_][0].ravel() for kk_ in sorted(sides) if kk_[0] != 1])
+    bS = np.concatenate([sides[kk_][1].reshape(-1, 3) for kk_ in sorted(sides) if kk_[0] != 1])
+    top, S_top = sides[(1, 1)]
+    bot, _ = sides[(1, 0)]
+    n_int = ea.shape[0]
+    ea = np.concatenate([ea, top.ravel()])
+    eb = np.concatenate([eb, bot.ravel()])
+    eS = np.concatenate([eS, S_top.reshape(-1, 3)])
+    eph = np.zeros(ea.shape[0], np.int8)
+    eph[n_int:] = 1
+    n = nx * nyt * nz
+    fx, fy, fz = np.meshgrid((np.arange(nx) + 0.5) / nx, ((np.arange(nyt) % ny) + 0.5) / ny,
+                             (np.arange(nz) + 0.5) / nz, indexing="ij")
+    passage = np.broadcast_to((np.arange(nyt) // ny)[None, :, None], (nx, nyt, nz)).ravel()
+    meta = {"kind": "cascade", "shape": (nx, nyt, nz), "n_blades": n_blades, "seed": seed,
+            "theta": np.full(n, -0.5 * np.pi), "radius": np.ones(n),
+            "xi": np.stack([fx.ravel(), fy.ravel(), fz.ravel()], axis=1), "row": np.zeros(n, np.int32),
+            "passage": passage.copy(), "n_passages": n_passages}
+    return _finish(n, ea, eb, eS, bc, bS, blk.volume.ravel(), blk.centroid.reshape(-1, 3),
+                   np.zeros(n, np.int32), rng, permute, 1, (n_blades,), meta, eph)
 
 
 def _cell_theta(blk):

@@ -150,6 +150,20 @@ int fnlh_get_blocks(fnlh_ctx c, double* diag, double* offd, void* stream);
  * omega_{i,l}).  Invalidates factors.  1 <= n_sys <= 4096. */
 int fnlh_set_harmonics(fnlh_ctx c, int32_t n_sys, const double* omega, void* stream);
 
+/* Phase-lagged periodic couplings (section "Solution Update": on periodic boundaries each
+ * harmonic carries its own inter-blade phase angle, which changes its left-hand side but
+ * not the sparsity pattern).  edge_phase host [E]: 0 for an ordinary edge; +1 (-1) when
+ * edge e = (a, b) couples a to the image of b one pitch above (below), whose value is
+ * x_b e^{+i sigma} (e^{-i sigma}); row a's coupling K_ab is then applied to
+ * x_b e^{i s sigma_s} and row b's K_ba to x_a e^{-i s sigma_s}.  sigma host [n_sys]: the
+ * phase of every system (radians; 0 for the mean), n_sys as in fnlh_set_harmonics.
+ * Applied on the fly in every sweep and residual; the DILU factors do not depend on it
+ * (a coupling and its transpose carry conjugate phases), so no factor is invalidated.
+ * edge_phase NULL removes the couplings' phases.  fnlh_set_harmonics resets every
+ * system's phase to 0.  Errors: FNLH_E_ORDER before set_harmonics, FNLH_E_ARG for signs
+ * outside {-1, 0, 1}, a wrong system count or non-finite phases. */
+int fnlh_set_phase_lag(fnlh_ctx c, const int8_t* edge_phase, int32_t n_sys, const double* sigma);
+
 /* r = b - K_s x with the outer FP64 operator (see FNLH_OUTER_*).
  *   x, b device [N][6] complex128 user order; r device [N][6] or NULL;
  *   norm2 host out: ||r||_2^2 over all 6N complex entries (may be NULL). */

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -923,7 +924,7 @@ int fnlh_destroy(fnlh_ctx c) {
                     &c->vol, &c->zone, &c->iperm, &c->perm, &c->edge_ent, &c->bf_ptr, &c->bf_idx, &c->area,
                     &c->bface_area, &c->offd, &c->diag, &c->offd64, &c->diag64, &c->state, &c->bstate,
                     &c->d_omega, &c->dinv, &c->x64, &c->b64, &c->r64, &c->y, &c->rhs32, &c->d32, &c->partial,
-                    &c->st, &c->st_outer, &c->d_err};
+                    &c->st, &c->st_outer, &c->d_err, &c->ent_phase, &c->phase_cs};
   for (DevBuf* b : bufs) dfree(*b);
   if (c->h_st) (void)hipHostFree(c->h_st);
   if (c->h_err) (void)hipHostFree(c->h_err);
@@ -1024,7 +1025,53 @@ int fnlh_set_harmonics(fnlh_ctx c, int32_t n_sys, const double* omega, void* str
   HIPC(c, hipMemcpy(c->d_omega.p, omega, n * sizeof(double), hipMemcpyHostToDevice), "copy omega");
   c->n_sys = n_sys;
   invalidate_factors(c);
+  if (c->ent_phase.p) {  // every system's phase back to 0 (fnlh_set_phase_lag sets them)
+    c->ibpa.assign(n_sys, 0.0);
+    std::vector<double> cs(2 * (size_t)n_sys);
+    for (int s = 0; s < n_sys; ++s) {
+      cs[2 * s] = 1.0;
+      cs[2 * s + 1] = 0.0;
+    }
+    if ((rc = dupload(c, c->phase_cs, cs, "phase table"))) return rc;
+  }
   (void)stream;
+  return FNLH_OK;
+}
+
+int fnlh_set_phase_lag(fnlh_ctx c, const int8_t* edge_phase, int32_t n_sys, const double* sigma) {
+  if (!c) return FNLH_E_ARG;
+  if (c->n_sys == 0) return set_err(c, FNLH_E_ORDER, "set_phase_lag: set the harmonics first");
+  int rc;
+  if (!edge_phase) {  // no periodic couplings
+    dfree(c->ent_phase);
+    dfree(c->phase_cs);
+    c->ibpa.clear();
+    c->buf_gen++;
+    return FNLH_OK;
+  }
+  if (n_sys != c->n_sys || !sigma)
+    return set_err(c, FNLH_E_ARG, "set_phase_lag: one phase per system of set_harmonics");
+  const Layout& L = c->L;
+  for (int64_t e = 0; e < L.E; ++e)
+    if (edge_phase[e] < -1 || edge_phase[e] > 1) return set_err(c, FNLH_E_ARG, "set_phase_lag: edge signs are -1, 0, +1");
+  for (int s = 0; s < n_sys; ++s)
+    if (!std::isfinite(sigma[s])) return set_err(c, FNLH_E_ARG, "set_phase_lag: non-finite phase");
+  // per entry: the edge's sign seen from its first cell, negated from its second
+  std::vector<int8_t> ph(L.ent_edge.size(), 0);
+  for (size_t f = 0; f < L.ent_edge.size(); ++f) {
+    const int32_t e = L.ent_edge[f];
+    if (e == 0) continue;
+    const int8_t sg = edge_phase[std::abs(e) - 1];
+    ph[f] = (int8_t)(e > 0 ? sg : -sg);
+  }
+  std::vector<double> cs(2 * (size_t)n_sys);
+  for (int s = 0; s < n_sys; ++s) {
+    cs[2 * s] = std::cos(sigma[s]);
+    cs[2 * s + 1] = std::sin(sigma[s]);
+  }
+  if ((rc = dupload(c, c->ent_phase, ph, "periodic couplings"))) return rc;
+  if ((rc = dupload(c, c->phase_cs, cs, "phase table"))) return rc;
+  c->ibpa.assign(sigma, sigma + n_sys);
   return FNLH_OK;
 }
 
@@ -1565,11 +1612,11 @@ int fnlh_get_ordering(fnlh_ctx c, int32_t* colour_of_cell, int32_t* n_colours) {
 
 int fnlh_memory(fnlh_ctx c, size_t* matrix_bytes, size_t* factor_bytes, size_t* vector_bytes) {
   if (!c) return FNLH_E_ARG;
-  const DevBuf* mat[] = {&c->tile_nrows, &c->tile_width, &c->tile_slot0, &c->ent_nbr, &c->ent_edge, &c->ent_rev,
+  const DevBuf* mat[] = {&c->ent_phase, &c->tile_nrows, &c->tile_width, &c->tile_slot0, &c->ent_nbr, &c->ent_edge, &c->ent_rev,
                          &c->vol, &c->zone, &c->iperm, &c->perm, &c->edge_ent, &c->bf_ptr, &c->bf_idx, &c->area,
                          &c->bface_area, &c->offd, &c->diag, &c->offd64, &c->diag64, &c->state, &c->bstate};
   const DevBuf* vec[] = {&c->x64, &c->b64,     &c->r64,     &c->y,  &c->rhs32,   &c->d32,
-                         &c->partial, &c->st, &c->st_outer, &c->d_omega};
+                         &c->partial, &c->st, &c->st_outer, &c->d_omega, &c->phase_cs};
   size_t m = 0, v = 0;
   for (auto* b : mat) m += b->bytes;
   for (auto* b : vec) v += b->bytes;

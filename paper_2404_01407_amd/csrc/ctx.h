@@ -47,6 +47,9 @@ struct fnlh_ctx_s {
   int n_sys = 0;
   std::vector<double> omega;
   DevBuf d_omega;
+  // phase-lagged periodic couplings: per-entry sign, per-system phase (cos, sin)
+  DevBuf ent_phase, phase_cs;
+  std::vector<double> ibpa;  // inter-blade phase angle per system
   // factors
   int n_slots = 0;
   DevBuf dinv;
@@ -93,6 +96,8 @@ struct fnlh_ctx_s {
     p.zone = (const int32_t*)zone.p;
     p.omega = (const double*)d_omega.p;
     p.n_zones = L.n_zones;
+    p.ent_phase = (const int8_t*)ent_phase.p;
+    p.phase_cs = (const double*)phase_cs.p;
     return p;
   }
   DevFlow flow() const {

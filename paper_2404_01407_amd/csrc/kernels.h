@@ -39,6 +39,10 @@ struct DevPattern {
   const int32_t* zone = nullptr;
   const double* omega = nullptr;  // [n_sys][n_zones]
   int32_t n_zones = 1;
+  // phase-lagged periodic couplings: per entry 0 or +-1 (null: none), and per system
+  // (cos sigma, sin sigma) of its inter-blade phase angle
+  const int8_t* ent_phase = nullptr;
+  const double* phase_cs = nullptr;  // [n_sys][2]
 };
 
 struct SysBatch {

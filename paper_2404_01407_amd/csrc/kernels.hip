@@ -43,6 +43,20 @@ __device__ inline double shift_w(const DevPattern& p, int orow, int64_t row) {
   return p.omega[(int64_t)orow * p.n_zones + p.zone[row]] * p.vol[row];
 }
 
+// Phase-lagged periodic coupling (entry fe, system omega row orow): the neighbour is the
+// image one pitch over, its value v times e^{i s sigma}, s = +-1 from the entry.
+template <typename A> __device__ inline void apply_phase(const DevPattern& p, int64_t fe, int orow, A (&v)[12]) {
+  const int sg = p.ent_phase[fe];
+  if (sg == 0) return;
+  const A c = (A)p.phase_cs[2 * orow], sn = (A)(sg * p.phase_cs[2 * orow + 1]);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const A re = v[2 * k], im = v[2 * k + 1];
+    v[2 * k] = c * re - sn * im;
+    v[2 * k + 1] = sn * re + c * im;
+  }
+}
+
 // acc -= (K_ii + i w I) x_i
 template <typename A>
 __device__ inline void sub_diag_shift(A (&acc)[12], const A (&d)[36], A w, const A (&xi)[12]) {
@@ -117,6 +131,7 @@ __device__ inline void gather_offd(const DevPattern& p, const TB* __restrict__ o
       if (!W.run[j]) continue;
       A xn[12];
       load_vec(xr + W.vs[j] * 12, xn);
+      if (p.ent_phase) apply_phase(p, slot * kLanes + lane, W.orow[j], xn);
       sub_kx(acc[j], kb, xn);
     }
   };
@@ -302,6 +317,7 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
         if (!run[j]) continue;
         A xn[12];
         load_vec(xr + vs[j] * 12, xn);
+        if (p.ent_phase) apply_phase(p, slot * kLanes + rl, orow[j], xn);
         sub_kx(acc[j], kb, xn);
       }
     };
@@ -315,6 +331,7 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
         const int nb = p.ent_nbr[slot * kLanes + rl];
         load_block(offd + slot * slot_elems<TB>(), rl, kb);
         if (run[0]) load_vec(x + (int64_t)nb * ns * 12 + vs[0] * 12, xn);
+        if (run[0] && p.ent_phase) apply_phase(p, slot * kLanes + rl, orow[0], xn);
       };
       if (wd > 0) fetch(0, kb0, xn0);
       for (int q = 0; q < wd; q += 2) {
@@ -482,9 +499,11 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
       if (!W.run[j]) continue;
       A v[12];
       load_vec(x + nbo + W.vs[j] * 12, v);
+      if (p.ent_phase) apply_phase(p, slot * kLanes + rl, W.orow[j], v);
       sub_kx(r[j], kb, v);
       if (lower) {
         load_vec(y + nbo + W.vs[j] * 12, v);
+        if (p.ent_phase) apply_phase(p, slot * kLanes + rl, W.orow[j], v);
         sub_kx(t[j], kb, v);
       }
     }
@@ -556,6 +575,7 @@ __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict_
         if (!W.run[j]) continue;
         A v[12];
         load_vec(y + nbo + W.vs[j] * 12, v);
+        if (p.ent_phase) apply_phase(p, slot * kLanes + rl, W.orow[j], v);
         sub_kx(t[j], kb, v);
       }
     }
@@ -1016,6 +1036,7 @@ __global__ void __launch_bounds__(256) k_resid_stored(DevPattern p, const TB* __
     double kb[36], v[12];
     load_block(offd + slot * slot_elems<TB>(), lane, kb);
     load_vec(x + ((int64_t)nb * ns + vs) * 12, v);
+    if (p.ent_phase) apply_phase(p, slot * kLanes + lane, sb.orow[k], v);
     sub_kx(acc, kb, v);
   }
   double n2 = wave_sum(valid ? norm2_12(acc) : 0.0);
@@ -1063,6 +1084,7 @@ __global__ void __launch_bounds__(256) k_resid_mfree(DevPattern p, DevFlow f, co
 #pragma unroll
     for (int c = 0; c < 36; ++c) Ak[c] = 0.5 * Ak[c] - ((c % 7 == 0) ? 0.5 * lam : 0.0);
     load_vec(x + ((int64_t)nb * ns + vs) * 12, v);
+    if (p.ent_phase) apply_phase(p, fe, sb.orow[k], v);
     sub_kx(acc, Ak, v);
   }
   if (valid) {

@@ -84,6 +84,7 @@ def _load():
         "fnlh_set_blocks": (I32, [P, V, V, V]),
         "fnlh_get_blocks": (I32, [P, V, V, V]),
         "fnlh_set_harmonics": (I32, [P, I32, V, V]),
+        "fnlh_set_phase_lag": (I32, [P, V, I32, V]),
         "fnlh_residual": (I32, [P, I32, V, V, V, C.POINTER(D), V]),
         "fnlh_relax": (I32, [P, I32, V, V, V, C.POINTER(RelaxOpts), V, V]),
         "fnlh_get_ordering": (I32, [P, V, C.POINTER(I32)]),
@@ -249,6 +250,18 @@ class Context:
         om = np.ascontiguousarray(omega, dtype=np.float64).reshape(-1, self.n_zones)
         self._check(LIB.fnlh_set_harmonics(self.h, om.shape[0], _ptr(om), _stream(stream)))
         self.n_sys = om.shape[0]
+
+    def set_phase_lag(self, edge_phase, sigma):
+        """Per-system inter-blade phase angles on the mesh's periodic edges (edge_phase:
+        int [E] in {-1, 0, 1}, sigma: [n_sys] radians); edge_phase None removes them."""
+        if edge_phase is None:
+            self._check(LIB.fnlh_set_phase_lag(self.h, None, 0, None))
+            return
+        ep = np.ascontiguousarray(edge_phase, dtype=np.int8).reshape(-1)
+        sg = np.ascontiguousarray(sigma, dtype=np.float64).reshape(-1)
+        if ep.size != self.E:
+            raise ValueError(f"edge_phase: {ep.size} entries for {self.E} edges")
+        self._check(LIB.fnlh_set_phase_lag(self.h, _ptr(ep), sg.size, _ptr(sg)))
 
     def residual(self, sys, x, b, r=None, stream=None):
         for t, nm in ((x, "x"), (b, "b")):

@@ -1032,7 +1032,11 @@ int fnlh_set_harmonics(fnlh_ctx c, int32_t n_sys, const double* omega, void* str
       cs[2 * s] = 1.0;
       cs[2 * s + 1] = 0.0;
     }
-    if ((rc = dupload(c, c->phase_cs, cs, "phase table"))) return rc;
+    if (c->phase_cs.bytes == cs.size() * sizeof(double)) {
+      HIPC(c, hipMemcpy(c->phase_cs.p, cs.data(), c->phase_cs.bytes, hipMemcpyHostToDevice), "phase table");
+    } else if ((rc = dupload(c, c->phase_cs, cs, "phase table"))) {
+      return rc;
+    }
   }
   (void)stream;
   return FNLH_OK;
@@ -1046,6 +1050,7 @@ int fnlh_set_phase_lag(fnlh_ctx c, const int8_t* edge_phase, int32_t n_sys, cons
     dfree(c->ent_phase);
     dfree(c->phase_cs);
     c->ibpa.clear();
+    c->edge_phase_host.clear();
     c->buf_gen++;
     return FNLH_OK;
   }
@@ -1056,21 +1061,30 @@ int fnlh_set_phase_lag(fnlh_ctx c, const int8_t* edge_phase, int32_t n_sys, cons
     if (edge_phase[e] < -1 || edge_phase[e] > 1) return set_err(c, FNLH_E_ARG, "set_phase_lag: edge signs are -1, 0, +1");
   for (int s = 0; s < n_sys; ++s)
     if (!std::isfinite(sigma[s])) return set_err(c, FNLH_E_ARG, "set_phase_lag: non-finite phase");
-  // per entry: the edge's sign seen from its first cell, negated from its second
-  std::vector<int8_t> ph(L.ent_edge.size(), 0);
-  for (size_t f = 0; f < L.ent_edge.size(); ++f) {
-    const int32_t e = L.ent_edge[f];
-    if (e == 0) continue;
-    const int8_t sg = edge_phase[std::abs(e) - 1];
-    ph[f] = (int8_t)(e > 0 ? sg : -sg);
+  const bool same = c->ent_phase.p && c->edge_phase_host.size() == (size_t)L.E &&
+                    std::equal(edge_phase, edge_phase + L.E, c->edge_phase_host.begin());
+  if (!same) {
+    // per entry: the edge's sign seen from its first cell, negated from its second
+    std::vector<int8_t> ph(L.ent_edge.size(), 0);
+    for (size_t f = 0; f < L.ent_edge.size(); ++f) {
+      const int32_t e = L.ent_edge[f];
+      if (e == 0) continue;
+      const int8_t sg = edge_phase[std::abs(e) - 1];
+      ph[f] = (int8_t)(e > 0 ? sg : -sg);
+    }
+    if ((rc = dupload(c, c->ent_phase, ph, "periodic couplings"))) return rc;
+    c->edge_phase_host.assign(edge_phase, edge_phase + L.E);
   }
   std::vector<double> cs(2 * (size_t)n_sys);
   for (int s = 0; s < n_sys; ++s) {
     cs[2 * s] = std::cos(sigma[s]);
     cs[2 * s + 1] = std::sin(sigma[s]);
   }
-  if ((rc = dupload(c, c->ent_phase, ph, "periodic couplings"))) return rc;
-  if ((rc = dupload(c, c->phase_cs, cs, "phase table"))) return rc;
+  if (c->phase_cs.bytes == cs.size() * sizeof(double)) {  // same buffer: graphs stay valid
+    HIPC(c, hipMemcpy(c->phase_cs.p, cs.data(), c->phase_cs.bytes, hipMemcpyHostToDevice), "phase table");
+  } else if ((rc = dupload(c, c->phase_cs, cs, "phase table"))) {
+    return rc;
+  }
   c->ibpa.assign(sigma, sigma + n_sys);
   return FNLH_OK;
 }

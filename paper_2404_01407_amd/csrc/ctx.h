@@ -50,6 +50,7 @@ struct fnlh_ctx_s {
   // phase-lagged periodic couplings: per-entry sign, per-system phase (cos, sin)
   DevBuf ent_phase, phase_cs;
   std::vector<double> ibpa;  // inter-blade phase angle per system
+  std::vector<int8_t> edge_phase_host;  // the signs behind ent_phase (repeat calls skip the rebuild)
   // factors
   int n_slots = 0;
   DevBuf dinv;

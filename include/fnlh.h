@@ -304,6 +304,39 @@ typedef struct {
 } fnlh_tune_result;
 int fnlh_autotune(fnlh_ctx c, int32_t n_sys, int32_t sweeps, fnlh_tune_result* out, void* stream);
 
+/* ---- pseudo-time driver: the RK(5,3) scheme around the linear solve (section
+ * "Generalized RK Scheme for The Mean Flow", eqn:rk and the hybrid RK(5,3) coefficient
+ * table alpha = (1/4, 1/6, 3/8, 1/2, 1); section "Generalized RK Scheme for
+ * Time-Linearized Harmonic Flows", eqn:rk_lin; section "Solution Update").  Per
+ * pseudo-time step: Q^(0) = Q^n, Q^(k) = Q^(0) + x_k with K x_k = -Gamma alpha_k R^(k)
+ * solved by fnlh_relax with the options lin (the paper's setting: rtol 1e-2, at most 10
+ * sweeps), Gamma = 1/eps (implicit) or sigma (explicit).  The residual stand-in is the
+ * first-order Rusanov residual (no viscous part, so the table's beta blending has no
+ * effect).  Returns the worst stage-solve status (FNLH_NOT_CONVERGED is the normal
+ * outcome of an inexact stage solve) or an error. */
+
+/* R(Q) = sum over faces of 1/2 (F(Q_i) + F(Q_k)) - 1/2 lambda (Q_k - Q_i), lambda the
+ * larger end spectral radius, boundary faces against bstate (device [B][6]) or the
+ * cell's own state when NULL.  state device [N][6] user order; R device [N][6]; norm2
+ * host ||R||^2 or NULL.  Needs only the mesh. */
+int fnlh_rusanov_residual(fnlh_ctx c, const double* state, const double* bstate, double* R,
+                          double* norm2, void* stream);
+/* n_steps pseudo-time steps of the mean flow: state (device [N][6], in/out) is updated in
+ * place; K is re-assembled at every step (fnlh_assemble_jacobian with eps, sigma,
+ * scheme) and kept through its five stages.  sys: a system whose omega is 0 (the mean).
+ * res_norm host [n_steps] or NULL: ||R(Q^n)|| at the start of each step. */
+int fnlh_rk_mean(fnlh_ctx c, int32_t sys, double* state, const double* bstate, int32_t n_steps,
+                 double eps, double sigma, int32_t scheme, const fnlh_relax_opts* lin,
+                 double* res_norm, void* stream);
+/* n_steps pseudo-time steps of harmonic sys about the assembled state: residual
+ * R(q^) = (J + i omega V) q^ - f^ (J the residual Jacobian, matrix-free in FP64, with the
+ * phase-lagged couplings if set), stage solves with K + i omega V; qhat device [N][6]
+ * complex128 in/out, fhat device [N][6].  Its fixed point is the solution of
+ * (J + i omega V) q^ = f^.  Needs fnlh_assemble_jacobian (Gamma from its eps, sigma,
+ * scheme). */
+int fnlh_rk_harmonic(fnlh_ctx c, int32_t sys, double* qhat, const double* fhat, int32_t n_steps,
+                     const fnlh_relax_opts* lin, double* res_norm, void* stream);
+
 /* ---- learned preconditioner (a project addition; the paper has no learned part).
  * A two-layer per-edge message-passing network on the context's cell graph maps the
  * residual r of system s to a correction dx ~ K_s^-1 r:

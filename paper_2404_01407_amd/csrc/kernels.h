@@ -164,4 +164,12 @@ void launch_inner_init(const SysBatch& sb, const SysState* outer, SysState* inne
 void launch_outer_update(const SysBatch& sb, const SysState* inner, SysState* outer, hipStream_t s);
 void launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 
+// RK driver: Rusanov residual of f.state (internal [NP][6]) into user order R [N][6]
+// (part[tile]: sum |R|^2); stage helpers on user-order vectors of n reals
+void launch_rusanov_residual(const DevPattern& p, const DevFlow& f, const int32_t* iperm, double* R_user,
+                             double* part, hipStream_t s);
+void launch_rk_rhs_real(int64_t n, const double* R, double scale, double* b, hipStream_t s);
+void launch_rk_update(bool complex_state, int64_t n, const double* q0, const double* x, double* q, hipStream_t s);
+void launch_scale(int64_t n, double* y, double scale, hipStream_t s);
+
 }  // namespace fnlh

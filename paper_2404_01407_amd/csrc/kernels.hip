@@ -1114,6 +1114,101 @@ __global__ void __launch_bounds__(256) k_resid_mfree(DevPattern p, DevFlow f, co
   if (r && valid) store_vec(r + ro, acc);
 }
 
+// ================================================================ nonlinear residual
+// Rusanov residual of the state q (internal [NP][6]) with the dissipation coefficients
+// and far field taken from q itself:
+//   R_i = sum_k [1/2 (F(q_i; S_ik) + F(q_k; S_ik)) - 1/2 lam_ik (q_k - q_i)]
+//       + sum_f [1/2 (F(q_i; S_f) + F(q_f; S_f)) - 1/2 lam_f (q_f - q_i)],
+// lam = larger end spectral radius, F(q; S) = A(q; S) q (the flux is homogeneous of
+// degree one).  R goes to user order; part[tile] = sum |R|^2 over the tile.
+__device__ inline void add_rusanov(const double (&Qa)[6], const double (&Qb)[6], const double (&S)[3],
+                                   double (&acc)[6]) {
+  double Aa[36], Ab[36];
+  flux_jacobian(Qa, S, Aa);
+  flux_jacobian(Qb, S, Ab);
+  const double lam = fmax(spectral_radius(Qa, S), spectral_radius(Qb, S));
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    double fa = 0.0, fb = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      fa += Aa[6 * r + c] * Qa[c];
+      fb += Ab[6 * r + c] * Qb[c];
+    }
+    acc[r] += 0.5 * (fa + fb) - 0.5 * lam * (Qb[r] - Qa[r]);
+  }
+}
+
+__global__ void __launch_bounds__(64) k_rusanov_residual(DevPattern p, DevFlow f, const int32_t* __restrict__ iperm,
+                                                         double* __restrict__ R, double* __restrict__ part) {
+  const int64_t tile = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t row = tile * kLanes + lane;
+  const bool valid = lane < p.tile_nrows[tile];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  if (valid) {
+    double Qi[6];
+    load_state(f.state + row * 6, Qi);
+    const int w = p.tile_width[tile];
+    const int64_t s0 = p.tile_slot0[tile];
+    for (int q = 0; q < w; ++q) {
+      const int64_t fe = (s0 + q) * kLanes + lane;
+      const int32_t e = p.ent_edge[fe];
+      if (e == 0) continue;
+      double S[3], Qk[6];
+      entry_area(f, e, S);
+      load_state(f.state + (int64_t)p.ent_nbr[fe] * 6, Qk);
+      add_rusanov(Qi, Qk, S, acc);
+    }
+    for (int32_t j = f.bf_ptr[row]; j < f.bf_ptr[row + 1]; ++j) {
+      const int32_t face = f.bf_idx[j];
+      const double S[3] = {f.bface_area[3 * face], f.bface_area[3 * face + 1], f.bface_area[3 * face + 2]};
+      double Qf[6];
+      if (f.bstate) {
+        load_state(f.bstate + (int64_t)face * 6, Qf);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) Qf[c] = Qi[c];
+      }
+      add_rusanov(Qi, Qf, S, acc);
+    }
+    const int64_t u = iperm[row];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) R[u * 6 + c] = acc[c];
+  }
+  double n2 = 0.0;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) n2 += acc[c] * acc[c];
+  n2 = wave_sum(n2);
+  if (lane == 0) part[tile] = n2;
+}
+
+// RK stage helpers on user-order vectors: b = scale * R (real R -> complex b),
+// q = q0 + Re x (real state), q = q0 + x (complex), y = scale * y (complex)
+__global__ void k_rk_rhs_real(int64_t n, const double* __restrict__ R, double scale, double* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  b[2 * i] = scale * R[i];
+  b[2 * i + 1] = 0.0;
+}
+__global__ void k_rk_update_real(int64_t n, const double* __restrict__ q0, const double* __restrict__ x,
+                                 double* __restrict__ q) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  q[i] = q0[i] + x[2 * i];
+}
+__global__ void k_rk_update_complex(int64_t n, const double* __restrict__ q0, const double* __restrict__ x,
+                                    double* __restrict__ q) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  q[i] = q0[i] + x[i];
+}
+__global__ void k_scale(int64_t n, double* __restrict__ y, double scale) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  y[i] *= scale;
+}
+
 // ================================================================ vectors
 // user [N][width] (one system)  <->  internal [NP][ns][width], slot vs
 __global__ void k_to_internal(int64_t NP, const int32_t* __restrict__ iperm, const double* __restrict__ user,
@@ -1484,6 +1579,22 @@ void launch_inner_init(const SysBatch& sb, const SysState* outer, SysState* inne
 }
 void launch_outer_update(const SysBatch& sb, const SysState* inner, SysState* outer, hipStream_t s) {
   hipLaunchKernelGGL(k_outer_update, dim3(1), dim3(64), 0, s, sb, inner, outer);
+}
+void launch_rusanov_residual(const DevPattern& p, const DevFlow& f, const int32_t* iperm, double* R_user,
+                             double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_rusanov_residual, dim3((unsigned)p.n_tiles), dim3(64), 0, s, p, f, iperm, R_user, part);
+}
+void launch_rk_rhs_real(int64_t n, const double* R, double scale, double* b, hipStream_t s) {
+  hipLaunchKernelGGL(k_rk_rhs_real, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, R, scale, b);
+}
+void launch_rk_update(bool complex_state, int64_t n, const double* q0, const double* x, double* q, hipStream_t s) {
+  if (complex_state)
+    hipLaunchKernelGGL(k_rk_update_complex, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, q0, x, q);
+  else
+    hipLaunchKernelGGL(k_rk_update_real, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, q0, x, q);
+}
+void launch_scale(int64_t n, double* y, double scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, y, scale);
 }
 void launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   const size_t n = bytes / 4;

@@ -85,6 +85,9 @@ def _load():
         "fnlh_get_blocks": (I32, [P, V, V, V]),
         "fnlh_set_harmonics": (I32, [P, I32, V, V]),
         "fnlh_set_phase_lag": (I32, [P, V, I32, V]),
+        "fnlh_rusanov_residual": (I32, [P, V, V, V, C.POINTER(D), V]),
+        "fnlh_rk_mean": (I32, [P, I32, V, V, I32, D, D, I32, C.POINTER(RelaxOpts), V, V]),
+        "fnlh_rk_harmonic": (I32, [P, I32, V, V, I32, C.POINTER(RelaxOpts), V, V]),
         "fnlh_residual": (I32, [P, I32, V, V, V, C.POINTER(D), V]),
         "fnlh_relax": (I32, [P, I32, V, V, V, C.POINTER(RelaxOpts), V, V]),
         "fnlh_get_ordering": (I32, [P, V, C.POINTER(I32)]),
@@ -289,6 +292,46 @@ class Context:
                             C.byref(o), C.cast(rep, C.c_void_p), _stream(stream))
         self._check(rc, allow_positive=True)
         return rc, [r.as_dict() for r in rep]
+
+    def rusanov_residual(self, state, bstate=None, stream=None):
+        """R(Q) of the first-order Rusanov scheme (device [N, 6] float64) and ||R||^2."""
+        import torch
+        _dev_tensor(state, (self.n, 6), "state")
+        R = torch.empty_like(state)
+        n2 = C.c_double(0.0)
+        self._check(LIB.fnlh_rusanov_residual(self.h, _ptr(state), _ptr(bstate), _ptr(R), C.byref(n2),
+                                              _stream(stream)))
+        return R, n2.value
+
+    @staticmethod
+    def _lin(kind, max_sweeps, rtol, check_every, use_graph):
+        return RelaxOpts(KIND[kind], int(max_sweeps), float(rtol), int(check_every), 0, 0.0, 0.0,
+                         int(bool(use_graph)), 0)
+
+    def rk_mean(self, sys, state, n_steps, eps=0.6, sigma=50.0, scheme="implicit", bstate=None, kind="dilu",
+                max_sweeps=10, rtol=1e-2, check_every=10, use_graph=False, stream=None):
+        """n_steps RK(5,3) pseudo-time steps of the mean flow (state updated in place);
+        returns (status, ||R|| at the start of each step)."""
+        _dev_tensor(state, (self.n, 6), "state")
+        hist = np.zeros(max(int(n_steps), 1))
+        o = self._lin(kind, max_sweeps, rtol, check_every, use_graph)
+        rc = LIB.fnlh_rk_mean(self.h, int(sys), _ptr(state), _ptr(bstate), int(n_steps), float(eps), float(sigma),
+                              SCHEME[scheme], C.byref(o), _ptr(hist), _stream(stream))
+        self._check(rc, allow_positive=True)
+        return rc, hist[:int(n_steps)]
+
+    def rk_harmonic(self, sys, qhat, fhat, n_steps, kind="dilu", max_sweeps=10, rtol=1e-2, check_every=10,
+                    use_graph=False, stream=None):
+        """n_steps RK(5,3) pseudo-time steps of harmonic sys about the assembled state
+        (qhat updated in place); returns (status, ||R_l|| at the start of each step)."""
+        for t, nm in ((qhat, "qhat"), (fhat, "fhat")):
+            _dev_tensor(t, (self.n, 6), nm)
+        hist = np.zeros(max(int(n_steps), 1))
+        o = self._lin(kind, max_sweeps, rtol, check_every, use_graph)
+        rc = LIB.fnlh_rk_harmonic(self.h, int(sys), _ptr(qhat), _ptr(fhat), int(n_steps), C.byref(o), _ptr(hist),
+                                  _stream(stream))
+        self._check(rc, allow_positive=True)
+        return rc, hist[:int(n_steps)]
 
     def tune(self, sys_per_lane=0, lanes_per_row=0):
         """Set the sweep-kernel shape (0 = automatic)."""

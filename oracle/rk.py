@@ -64,19 +64,28 @@ def harmonic_residual(J, mesh, omega_row, Qh, fh):
 
 
 def harmonic_step(mesh, Q, Qh, fh, omega_row, colour, eps=0.6, sigma=50.0, scheme="implicit", rtol=1e-2,
-                  max_sweeps=10, kind="DILU", Qff=None):
-    """One pseudo-time step of a harmonic about the state Q; returns (Q^(n+1), ||R_l||)."""
+                  max_sweeps=10, kind="DILU", Qff=None, frozen=False):
+    """One pseudo-time step of a harmonic about the state Q; returns (Q^(n+1), ||R_l||).
+    frozen: frozen turbulence, the 5x5 sub-system of J and K with the turbulence
+    perturbation held at 0."""
     J = assemble.residual_jacobian(Q, mesh.edges, mesh.area, mesh.bface_cell, mesh.bface_area, Qff)
     K = assemble.preconditioner_matrix(J, eps, sigma, scheme)
     G = gamma(scheme, eps, sigma)
-    Q0 = np.asarray(Qh, np.complex128)
+    Q0 = np.asarray(Qh, np.complex128).copy()
+    if frozen:
+        Q0[:, 5] = 0.0
     Qk = Q0.copy()
+    lin = solve.richardson_frozen if frozen else solve.richardson
     r0 = None
     for k in range(5):
-        R = harmonic_residual(J, mesh, omega_row, Qk, fh)
+        if frozen:
+            R = np.zeros_like(Q0)
+            R[:, :5] = harmonic_residual(solve.frozen_turbulence(J), mesh, omega_row, Qk[:, :5], fh[:, :5])
+        else:
+            R = harmonic_residual(J, mesh, omega_row, Qk, fh)
         if k == 0:
             r0 = float(np.linalg.norm(R))
-        x, _ = solve.richardson(K, mesh.volume, mesh.zone, omega_row, -G * ALPHA[k] * R, colour, kind, rtol=rtol,
-                                max_sweeps=max_sweeps)
+        x, _ = lin(K, mesh.volume, mesh.zone, omega_row, -G * ALPHA[k] * R, colour, kind, rtol=rtol,
+                   max_sweeps=max_sweeps)
         Qk = Q0 + x
     return Qk, r0

@@ -44,8 +44,10 @@ def shift(volume, zone, omega_row):
 
 
 def system_diag(K: BlockMatrix, volume, zone, omega_row):
-    """Diagonal blocks of K_s = K + i omega V I."""
-    return K.diag.astype(np.complex128) + 1j * shift(volume, zone, omega_row)[:, None, None] * I6
+    """Diagonal blocks of K_s = K + i omega V I (I of the block size: 6, or 5 for a
+    frozen-turbulence system)."""
+    I = np.eye(K.diag.shape[-1])
+    return K.diag.astype(np.complex128) + 1j * shift(volume, zone, omega_row)[:, None, None] * I
 
 
 def apply(K: BlockMatrix, Ds, x):
@@ -70,22 +72,41 @@ def phase_lagged(K: BlockMatrix, edge_phase, sigma):
 
 
 def dense(K: BlockMatrix, volume, zone, omega_row):
-    """K_s as a dense [6N, 6N] complex matrix (for pins on small meshes)."""
-    n = K.n
+    """K_s as a dense [bN, bN] complex matrix, b the block size (for pins on small meshes)."""
+    n, m = K.n, K.diag.shape[-1]
     Ds = system_diag(K, volume, zone, omega_row)
-    A = np.zeros((6 * n, 6 * n), dtype=np.complex128)
+    A = np.zeros((m * n, m * n), dtype=np.complex128)
     for i in range(n):
-        A[6 * i:6 * i + 6, 6 * i:6 * i + 6] = Ds[i]
+        A[m * i:m * i + m, m * i:m * i + m] = Ds[i]
     for e in range(K.rows.shape[0]):
         i, k = int(K.rows[e]), int(K.cols[e])
-        A[6 * i:6 * i + 6, 6 * k:6 * k + 6] += K.offd[e]
+        A[m * i:m * i + m, m * k:m * k + m] += K.offd[e]
     return A
 
 
 def dense_solve(K, volume, zone, omega_row, b):
     """x = K_s^-1 b by LAPACK gesv: the plain definition of the converged result."""
     A = dense(K, volume, zone, omega_row)
-    return np.linalg.solve(A, np.asarray(b, np.complex128).reshape(-1)).reshape(-1, 6)
+    return np.linalg.solve(A, np.asarray(b, np.complex128).reshape(-1)).reshape(-1, K.diag.shape[-1])
+
+
+def frozen_turbulence(K: BlockMatrix):
+    """The system a frozen-turbulence harmonic solves (section "Brief Description of
+    Hydra": the linearisation freezes the turbulence model, and the shift's unit matrix
+    is 5x5 in section "Generalized RK Scheme for Time-Linearized Harmonic Flows"): the
+    leading 5x5 sub-block of every block, the turbulence unknown left out (held at 0)."""
+    return BlockMatrix(K.n, K.diag[:, :5, :5].copy(), K.rows.copy(), K.cols.copy(), K.offd[:, :5, :5].copy())
+
+
+def richardson_frozen(K: BlockMatrix, volume, zone, omega_row, b, colour, kind="DILU", x0=None, **kw):
+    """richardson on the frozen-turbulence system: the first five unknowns from the 5x5
+    sub-system with b's first five components, the sixth 0."""
+    b = np.asarray(b, np.complex128)
+    x5, info = richardson(frozen_turbulence(K), volume, zone, omega_row, b[:, :5], colour, kind,
+                          None if x0 is None else np.asarray(x0, np.complex128)[:, :5], **kw)
+    x = np.zeros((K.n, 6), np.complex128)
+    x[:, :5] = x5
+    return x, info
 
 
 def reverse_index(K: BlockMatrix):

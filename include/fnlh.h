@@ -304,6 +304,19 @@ typedef struct {
 } fnlh_tune_result;
 int fnlh_autotune(fnlh_ctx c, int32_t n_sys, int32_t sweeps, fnlh_tune_result* out, void* stream);
 
+/* Frozen turbulence (section "Brief Description of Hydra": the harmonic equations are
+ * linearised with the turbulence model frozen, so the unit matrix of the frequency shift
+ * in section "Generalized RK Scheme for Time-Linearized Harmonic Flows" is 5x5).
+ * flags [n_sys] host, 1 = that system solves only the leading 5x5 sub-system of every
+ * block with its sixth unknown held at zero, 0 = the full 6x6 system; NULL clears all.
+ * For a frozen system fnlh_relax sets x's sixth component to 0 and keeps it there,
+ * ignores b's, and leaves the sixth equation's residual out of every norm; fnlh_residual
+ * takes x's sixth component as 0 and returns that residual component as 0.  Frozen
+ * systems use the stored-factor kernels (not the two-colour fused pass) and cannot use
+ * FNLH_LEARNED.  Cleared by fnlh_set_harmonics.  Errors: FNLH_E_ORDER before
+ * set_harmonics, FNLH_E_ARG on a wrong count or a flag other than 0/1. */
+int fnlh_set_frozen_turbulence(fnlh_ctx c, int32_t n_sys, const int8_t* flags);
+
 /* ---- pseudo-time driver: the RK(5,3) scheme around the linear solve (section
  * "Generalized RK Scheme for The Mean Flow", eqn:rk and the hybrid RK(5,3) coefficient
  * table alpha = (1/4, 1/6, 3/8, 1/2, 1); section "Generalized RK Scheme for
@@ -331,7 +344,8 @@ int fnlh_rk_mean(fnlh_ctx c, int32_t sys, double* state, const double* bstate, i
 /* n_steps pseudo-time steps of harmonic sys about the assembled state: residual
  * R(q^) = (J + i omega V) q^ - f^ (J the residual Jacobian, matrix-free in FP64, with the
  * phase-lagged couplings if set), stage solves with K + i omega V; qhat device [N][6]
- * complex128 in/out, fhat device [N][6].  Its fixed point is the solution of
+ * complex128 in/out (its sixth component set to 0 first for a frozen-turbulence system),
+ * fhat device [N][6].  Its fixed point is the solution of
  * (J + i omega V) q^ = f^.  Needs fnlh_assemble_jacobian (Gamma from its eps, sigma,
  * scheme). */
 int fnlh_rk_harmonic(fnlh_ctx c, int32_t sys, double* qhat, const double* fhat, int32_t n_steps,

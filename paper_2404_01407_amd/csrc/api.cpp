@@ -544,6 +544,9 @@ int relax_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, c
   P.inner_max = o->inner_sweeps > 0 ? o->inner_sweeps : std::max(1, o->max_sweeps);
   P.use_graph = o->use_graph != 0;
   P.learned = o->kind == FNLH_LEARNED;
+  if (P.learned)
+    for (int j = 0; j < n; ++j)
+      if (c->is_frozen(sys[j])) return set_err(c, FNLH_E_ARG, "relax: the learned kind does not take frozen-turbulence systems");
   P.learn_every = o->learn_every > 0 ? o->learn_every : 16;
   int rc;
   if ((rc = ensure_vectors(c, n))) return rc;
@@ -557,6 +560,15 @@ int relax_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, c
     launch_to_internal(p, (const int32_t*)c->iperm.p, b[j], (double*)c->b64.p, 12, n, j, s);
   }
   P.path = o->kind == FNLH_JACOBI ? kPathJacobi : (c->L.n_colours == 2 ? kPathRB : kPathGeneral);
+  // frozen-turbulence systems run on the stored-factor kernels (the two-colour pass solves
+  // the first colour's full 6x6 diagonal block in place); their sixth unknown starts at 0
+  bool frozen = false;
+  for (int j = 0; j < n; ++j)
+    if (c->is_frozen(sys[j])) {
+      frozen = true;
+      launch_zero_sixth(c->L.NP, (double*)c->x64.p, n, j, s);
+    }
+  if (frozen && P.path == kPathRB) P.path = kPathGeneral;
   P.fkind = (o->kind == FNLH_DILU || o->kind == FNLH_LEARNED) ? 0 : 1;
   P.cfg.storage = c->storage;
   P.cfg.spw = c->lanes_per_sys;
@@ -1025,6 +1037,11 @@ int fnlh_set_harmonics(fnlh_ctx c, int32_t n_sys, const double* omega, void* str
   HIPC(c, hipMemcpy(c->d_omega.p, omega, n * sizeof(double), hipMemcpyHostToDevice), "copy omega");
   c->n_sys = n_sys;
   invalidate_factors(c);
+  if (c->sys_frozen.p) {  // no system frozen (fnlh_set_frozen_turbulence sets them)
+    dfree(c->sys_frozen);
+    c->buf_gen++;
+  }
+  c->frozen.clear();
   if (c->ent_phase.p) {  // every system's phase back to 0 (fnlh_set_phase_lag sets them)
     c->ibpa.assign(n_sys, 0.0);
     std::vector<double> cs(2 * (size_t)n_sys);
@@ -1089,6 +1106,32 @@ int fnlh_set_phase_lag(fnlh_ctx c, const int8_t* edge_phase, int32_t n_sys, cons
   return FNLH_OK;
 }
 
+int fnlh_set_frozen_turbulence(fnlh_ctx c, int32_t n_sys, const int8_t* flags) {
+  if (!c) return FNLH_E_ARG;
+  if (c->n_sys == 0) return set_err(c, FNLH_E_ORDER, "set_frozen_turbulence: set the harmonics first");
+  bool any = false;
+  if (flags) {
+    if (n_sys != c->n_sys) return set_err(c, FNLH_E_ARG, "set_frozen_turbulence: one flag per system of set_harmonics");
+    for (int s = 0; s < n_sys; ++s) {
+      if (flags[s] != 0 && flags[s] != 1) return set_err(c, FNLH_E_ARG, "set_frozen_turbulence: flags are 0 or 1");
+      any |= flags[s] == 1;
+    }
+  }
+  std::vector<uint8_t> f;
+  if (any) f.assign(flags, flags + n_sys);
+  if (f == c->frozen) return FNLH_OK;
+  int rc;
+  if (!any) {
+    dfree(c->sys_frozen);
+  } else if ((rc = dupload(c, c->sys_frozen, f, "frozen flags"))) {
+    return rc;
+  }
+  c->frozen = f;
+  c->buf_gen++;  // captured sweeps hold the flag table's address
+  invalidate_factors(c);
+  return FNLH_OK;
+}
+
 int fnlh_residual(fnlh_ctx c, int32_t sys, const double* x, const double* b, double* r, double* norm2,
                   void* stream) {
   if (!c) return FNLH_E_ARG;
@@ -1101,6 +1144,7 @@ int fnlh_residual(fnlh_ctx c, int32_t sys, const double* x, const double* b, dou
   DevPattern p = c->pat();
   launch_to_internal(p, (const int32_t*)c->iperm.p, x, (double*)c->x64.p, 12, 1, 0, s);
   launch_to_internal(p, (const int32_t*)c->iperm.p, b, (double*)c->b64.p, 12, 1, 0, s);
+  if (c->is_frozen(sys)) launch_zero_sixth(c->L.NP, (double*)c->x64.p, 1, 0, s);
   SysBatch sb;
   sb.n = 1;
   sb.orow[0] = sys;

@@ -51,6 +51,9 @@ struct fnlh_ctx_s {
   DevBuf ent_phase, phase_cs;
   std::vector<double> ibpa;  // inter-blade phase angle per system
   std::vector<int8_t> edge_phase_host;  // the signs behind ent_phase (repeat calls skip the rebuild)
+  // frozen turbulence: per system 1 = its sixth unknown is held at zero (null: none)
+  DevBuf sys_frozen;
+  std::vector<uint8_t> frozen;
   // factors
   int n_slots = 0;
   DevBuf dinv;
@@ -83,6 +86,7 @@ struct fnlh_ctx_s {
   double st_bytes[FNLH_KSTAT_N] = {0};
   int64_t st_n[FNLH_KSTAT_N] = {0};
 
+  bool is_frozen(int s) const { return !frozen.empty() && frozen[(size_t)s] != 0; }
   DevPattern pat() const {
     DevPattern p;
     p.NP = L.NP;
@@ -99,6 +103,7 @@ struct fnlh_ctx_s {
     p.n_zones = L.n_zones;
     p.ent_phase = (const int8_t*)ent_phase.p;
     p.phase_cs = (const double*)phase_cs.p;
+    p.sys_frozen = (const uint8_t*)sys_frozen.p;
     return p;
   }
   DevFlow flow() const {

@@ -43,6 +43,9 @@ struct DevPattern {
   // (cos sigma, sin sigma) of its inter-blade phase angle
   const int8_t* ent_phase = nullptr;
   const double* phase_cs = nullptr;  // [n_sys][2]
+  // frozen turbulence: per system 1 = the leading 5x5 sub-system only, sixth unknown
+  // held at zero (null: no system frozen)
+  const uint8_t* sys_frozen = nullptr;
 };
 
 struct SysBatch {
@@ -162,6 +165,9 @@ void launch_add_f32(const DevPattern& p, double* x64, const float* d32, int ns, 
                     const SysState* outer, hipStream_t s);
 void launch_inner_init(const SysBatch& sb, const SysState* outer, SysState* inner, int max_sweeps, hipStream_t s);
 void launch_outer_update(const SysBatch& sb, const SysState* inner, SysState* outer, hipStream_t s);
+// zero the sixth unknown of slot vs of an interleaved complex vector [rows][ns][6]
+// (frozen-turbulence systems)
+void launch_zero_sixth(int64_t rows, double* v, int ns, int vs, hipStream_t s);
 void launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 
 // RK driver: Rusanov residual of f.state (internal [NP][6]) into user order R [N][6]

@@ -57,6 +57,16 @@ template <typename A> __device__ inline void apply_phase(const DevPattern& p, in
   }
 }
 
+// Frozen turbulence (system omega row orow): only the leading 5x5 sub-system is solved,
+// so the sixth equation's residual is dropped (it never reaches the factors, whose sixth
+// row and column are zero, and does not count in the norm).
+template <typename A> __device__ inline void mask_frozen(const DevPattern& p, int orow, A (&v)[12]) {
+  if (p.sys_frozen && p.sys_frozen[orow]) {
+    v[10] = (A)0;
+    v[11] = (A)0;
+  }
+}
+
 // acc -= (K_ii + i w I) x_i
 template <typename A>
 __device__ inline void sub_diag_shift(A (&acc)[12], const A (&d)[36], A w, const A (&xi)[12]) {
@@ -510,6 +520,7 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
   }
 #pragma unroll
   for (int j = 0; j < P; ++j) {
+    if (W.run[j]) mask_frozen(p, W.orow[j], r[j]);
     double n2 = (valid && W.run[j]) ? norm2_12(r[j]) : 0.0;
 #pragma unroll
     for (int o = 32; o >= SW; o >>= 1) n2 += __shfl_xor(n2, o, 64);
@@ -637,6 +648,7 @@ __global__ void __launch_bounds__(256) k_jacobi(DevPattern p, const TB* __restri
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     if (!W.run[j]) continue;
+    mask_frozen(p, W.orow[j], r[j]);
     const double n2 = wave_sum(valid ? norm2_12(r[j]) : 0.0);
     if (lane == 0) partial[((int64_t)W.vs[j] * p.n_tiles + tile) * kPartialSlots] = n2;
     A yi[12];
@@ -989,8 +1001,19 @@ __global__ void __launch_bounds__(64) k_factor(DevPattern p, const TB* __restric
       }
     }
   }
+  // frozen turbulence: the inverse of the leading 5x5 block, sixth row and column zero
+  const bool frz = p.sys_frozen && p.sys_frozen[sb.orow[k]];
+  if (frz) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      mr[30 + c] = mi[30 + c] = 0.0;
+      mr[6 * c + 5] = mi[6 * c + 5] = 0.0;
+    }
+    mr[35] = 1.0;
+  }
   bool ok = true;
   cinv6(mr, mi, ok);
+  if (frz) mr[35] = 0.0;
   if (valid && !ok) atomicOr(err, 1);
   if (!valid) {
 #pragma unroll
@@ -1039,6 +1062,7 @@ __global__ void __launch_bounds__(256) k_resid_stored(DevPattern p, const TB* __
     if (p.ent_phase) apply_phase(p, slot * kLanes + lane, sb.orow[k], v);
     sub_kx(acc, kb, v);
   }
+  mask_frozen(p, sb.orow[k], acc);
   double n2 = wave_sum(valid ? norm2_12(acc) : 0.0);
   if (lane == 0) partial[((int64_t)vs * p.n_tiles + tile) * kPartialSlots] = n2;
   if (r && valid) store_vec(r + ro, acc);
@@ -1109,6 +1133,7 @@ __global__ void __launch_bounds__(256) k_resid_mfree(DevPattern p, DevFlow f, co
 #pragma unroll
   for (int c = 0; c < 36; ++c) Ai[c] = f.diag_scale * (0.5 * Ai[c] + ((c % 7 == 0) ? 0.5 * lam_sum : 0.0));
   sub_diag_shift(acc, Ai, shift_w(p, sb.orow[k], row), xi);
+  mask_frozen(p, sb.orow[k], acc);
   double n2 = wave_sum(valid ? norm2_12(acc) : 0.0);
   if (lane == 0) partial[((int64_t)vs * p.n_tiles + tile) * kPartialSlots] = n2;
   if (r && valid) store_vec(r + ro, acc);
@@ -1249,6 +1274,12 @@ __global__ void k_add_f32(int64_t NP, int ns, double* __restrict__ x64, const fl
   if (i >= NP * 12) return;
   const int64_t o = (i / 12) * ns * 12 + vs * 12 + (i % 12);
   x64[o] += (double)d32[o];
+}
+__global__ void k_zero_sixth(int64_t NP, int ns, int vs, double* __restrict__ v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NP) return;
+  v[(i * ns + vs) * 12 + 10] = 0.0;
+  v[(i * ns + vs) * 12 + 11] = 0.0;
 }
 __global__ void k_fill_zero(uint32_t* __restrict__ p, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1595,6 +1626,10 @@ void launch_rk_update(bool complex_state, int64_t n, const double* q0, const dou
 }
 void launch_scale(int64_t n, double* y, double scale, hipStream_t s) {
   hipLaunchKernelGGL(k_scale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, y, scale);
+}
+void launch_zero_sixth(int64_t rows, double* v, int ns, int vs, hipStream_t s) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(k_zero_sixth, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, rows, ns, vs, v);
 }
 void launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   const size_t n = bytes / 4;

@@ -162,6 +162,7 @@ int fnlh_rk_harmonic(fnlh_ctx c, int32_t sys, double* qhat, const double* fhat, 
   sb.dslot[0] = 0;
   sb.vslot[0] = 0;
   launch_to_internal(p, iperm, fhat, (double*)bi.p, 12, 1, 0, s);
+  if (c->is_frozen(sys)) launch_zero_sixth(N, qhat, 1, 0, s);  // the sixth unknown is held at 0
   int worst = FNLH_OK;
   for (int n = 0; n < n_steps; ++n) {
     HIPC(c, hipMemcpyAsync(q0.p, qhat, vu, hipMemcpyDeviceToDevice, s), "copy state");

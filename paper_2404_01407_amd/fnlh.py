@@ -85,6 +85,7 @@ def _load():
         "fnlh_get_blocks": (I32, [P, V, V, V]),
         "fnlh_set_harmonics": (I32, [P, I32, V, V]),
         "fnlh_set_phase_lag": (I32, [P, V, I32, V]),
+        "fnlh_set_frozen_turbulence": (I32, [P, I32, V]),
         "fnlh_rusanov_residual": (I32, [P, V, V, V, C.POINTER(D), V]),
         "fnlh_rk_mean": (I32, [P, I32, V, V, I32, D, D, I32, C.POINTER(RelaxOpts), V, V]),
         "fnlh_rk_harmonic": (I32, [P, I32, V, V, I32, C.POINTER(RelaxOpts), V, V]),
@@ -292,6 +293,15 @@ class Context:
                             C.byref(o), C.cast(rep, C.c_void_p), _stream(stream))
         self._check(rc, allow_positive=True)
         return rc, [r.as_dict() for r in rep]
+
+    def set_frozen_turbulence(self, flags):
+        """Per-system frozen-turbulence flags (leading 5x5 sub-system, sixth unknown held at
+        zero); None clears them."""
+        if flags is None:
+            self._check(LIB.fnlh_set_frozen_turbulence(self.h, 0, None))
+            return
+        f = np.ascontiguousarray(np.asarray(flags).astype(np.int8))
+        self._check(LIB.fnlh_set_frozen_turbulence(self.h, int(f.size), _ptr(f)))
 
     def rusanov_residual(self, state, bstate=None, stream=None):
         """R(Q) of the first-order Rusanov scheme (device [N, 6] float64) and ||R||^2."""

@@ -1,0 +1,210 @@
+"""GPU parity of frozen-turbulence systems (fnlh_set_frozen_turbulence) against the
+oracle's 5x5 sub-system solve: iterates (FP64, 1e-11) for DILU, SGS and Jacobi on the
+two-colour and the general colouring paths with frozen and full systems mixed in one
+call, converged results in FP32/BF16 against the dense 5x5 solve, the residual entry
+point, the RK driver's frozen harmonic steps, batching, graphs and the error paths."""
+import numpy as np
+import pytest
+
+from oracle import assemble, rk, solve
+from paper_2404_01407_amd import synth
+
+from gpu_helpers import relerr, to_dev
+
+pytestmark = pytest.mark.gpu
+
+ITER_TOL = 1e-11
+OMEGA = np.array([[0.0], [18.0], [36.0]])
+FROZEN = [0, 1, 1]
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2404_01407_amd import fnlh
+    return fnlh
+
+
+def _case(kind, seed=3):
+    if kind == "passage":
+        m = synth.passage_block(12, 6, 4, 36, seed=seed)        # two colours
+    else:
+        m = synth.cascade_block(8, 5, 3, 36, seed=seed)         # odd pitch: general colouring
+    Q = synth.flow_state(m, seed)
+    return m, Q, assemble.assemble(m, Q)
+
+
+def _ctx(F, m, Q, storage="f64", frozen=FROZEN):
+    c = F.Context(m, storage=storage)
+    c.assemble_jacobian(to_dev(Q))
+    c.set_harmonics(OMEGA)
+    if frozen is not None:
+        c.set_frozen_turbulence(frozen)
+    return c
+
+
+def _rhs(m, seed):
+    return [synth.rhs(m.n_cells, seed + s, real=(s == 0)) for s in range(3)]
+
+
+def _solve(c, systems, bs, x0=None, **kw):
+    import torch
+    xs = [to_dev(np.zeros((c.n, 6), complex) if x0 is None else x0[i]) for i, _ in enumerate(systems)]
+    st, rep = c.relax(systems, xs, [to_dev(b) for b in bs], **kw)
+    torch.cuda.synchronize()
+    return st, rep, [x.cpu().numpy() for x in xs]
+
+
+def _oracle(K, m, s, b, col, kind, **kw):
+    f = solve.richardson_frozen if FROZEN[s] else solve.richardson
+    return f(K, m.volume, m.zone, OMEGA[s], b, col, kind, **kw)
+
+
+@pytest.mark.parametrize("mesh", ["passage", "cascade"])
+@pytest.mark.parametrize("kind", ["dilu", "sgs", "jacobi"])
+def test_frozen_iterates_match_oracle(F, mesh, kind):
+    m, Q, K = _case(mesh)
+    c = _ctx(F, m, Q)
+    col, nc = c.ordering()
+    bs = _rhs(m, 0)
+    # a non-zero starting sixth component is reset for the frozen systems
+    x0 = [synth.rhs(m.n_cells, 40 + s) for s in range(3)]
+    st, rep, xs = _solve(c, [0, 1, 2], bs, x0=x0, kind=kind, max_sweeps=15, rtol=0.0)
+    for s in range(3):
+        x_or, info = _oracle(K, m, s, bs[s], col, kind.upper(), x0=x0[s], rtol=0.0, max_sweeps=15)
+        assert relerr(xs[s], x_or) <= ITER_TOL, (mesh, kind, s, relerr(xs[s], x_or))
+        if FROZEN[s]:
+            assert np.all(xs[s][:, 5] == 0.0)
+        assert abs(rep[s]["rel_res"] - info.rel_res) <= 1e-9 * max(info.rel_res, 1e-30) + 1e-14, (s, rep[s], info)
+    c.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_frozen_converged_vs_dense(F, storage):
+    m, Q, K = _case("passage")
+    c = _ctx(F, m, Q, storage=storage)
+    bs = _rhs(m, 10)
+    st, rep, xs = _solve(c, [0, 1, 2], bs, kind="dilu", max_sweeps=4000, rtol=1e-11)
+    assert st == F.OK, rep
+    for s in range(3):
+        if FROZEN[s]:
+            x5 = solve.dense_solve(solve.frozen_turbulence(K), m.volume, m.zone, OMEGA[s], bs[s][:, :5])
+            assert relerr(xs[s][:, :5], x5) <= 1e-9, (storage, s)
+            assert np.all(xs[s][:, 5] == 0.0)
+        else:
+            assert relerr(xs[s], solve.dense_solve(K, m.volume, m.zone, OMEGA[s], bs[s])) <= 1e-9
+    c.close()
+
+
+def test_frozen_ignores_sixth_rhs_and_residual(F):
+    m, Q, K = _case("passage")
+    c = _ctx(F, m, Q)
+    bs = _rhs(m, 20)
+    b2 = [b.copy() for b in bs]
+    for b in b2:
+        b[:, 5] = 7.0
+    _, _, xa = _solve(c, [1, 2], bs[1:], kind="dilu", max_sweeps=12, rtol=0.0)
+    _, _, xb = _solve(c, [1, 2], b2[1:], kind="dilu", max_sweeps=12, rtol=0.0)
+    for a, b in zip(xa, xb):
+        assert np.array_equal(a, b)
+    # residual entry point: sixth component 0, the rest the 5x5 residual of x (x6 taken as 0)
+    x = synth.rhs(m.n_cells, 77)
+    rd = to_dev(np.zeros((m.n_cells, 6), complex))
+    n2 = c.residual(1, to_dev(x), to_dev(bs[1]), r=rd)
+    r = rd.cpu().numpy()
+    K5 = solve.frozen_turbulence(K)
+    r5 = bs[1][:, :5] - solve.apply(K5, solve.system_diag(K5, m.volume, m.zone, OMEGA[1]), x[:, :5])
+    assert np.all(r[:, 5] == 0.0)
+    assert relerr(r[:, :5], r5) <= 1e-13
+    assert abs(n2 - np.linalg.norm(r5) ** 2) <= 1e-12 * np.linalg.norm(r5) ** 2
+    c.close()
+
+
+def test_frozen_flags_reset_and_graphs(F):
+    m, Q, K = _case("passage")
+    c = _ctx(F, m, Q, frozen=None)
+    bs = _rhs(m, 30)
+    kw = dict(kind="dilu", max_sweeps=24, rtol=0.0, check_every=8, use_graph=True)
+    _, _, full = _solve(c, [0, 1, 2], bs, **kw)                  # captures the unfrozen sweeps
+    c.set_frozen_turbulence(FROZEN)
+    _, _, frz = _solve(c, [0, 1, 2], bs, **kw)
+    col, _ = c.ordering()
+    for s in range(3):
+        x_or, _ = _oracle(K, m, s, bs[s], col, "DILU", rtol=0.0, max_sweeps=24)
+        assert relerr(frz[s], x_or) <= ITER_TOL, s
+    c.set_frozen_turbulence(None)
+    _, _, back = _solve(c, [0, 1, 2], bs, **kw)
+    c.set_frozen_turbulence(FROZEN)
+    c.set_harmonics(OMEGA)                                       # clears the flags
+    _, _, back2 = _solve(c, [0, 1, 2], bs, **kw)
+    for s in range(3):
+        assert np.array_equal(back[s], full[s])
+        assert np.array_equal(back2[s], full[s])
+    c.close()
+
+
+def test_frozen_batch_matches_per_instance(F):
+    import torch
+    cases = [_case("passage", seed=21), _case("passage", seed=22)]
+    ctxs = [_ctx(F, m, Q, frozen=(FROZEN if i == 0 else None)) for i, (m, Q, K) in enumerate(cases)]
+    B = F.Batch(ctxs)
+    bs = [_rhs(m, 50 + i) for i, (m, Q, K) in enumerate(cases)]
+    xs = [[to_dev(np.zeros((m.n_cells, 6), complex)) for _ in range(3)] for (m, Q, K) in cases]
+    st, reps = B.relax([[0, 1, 2]] * 2, xs, [[to_dev(b) for b in row] for row in bs], kind="dilu",
+                       max_sweeps=3000, rtol=1e-10)
+    torch.cuda.synchronize()
+    assert st == F.OK
+    for i, c in enumerate(ctxs):
+        _, rep, xi = _solve(c, [0, 1, 2], bs[i], kind="dilu", max_sweeps=3000, rtol=1e-10)
+        for s in range(3):
+            assert np.array_equal(xs[i][s].cpu().numpy(), xi[s]), (i, s)
+    B.close()
+    for c in ctxs:
+        c.close()
+
+
+@pytest.mark.parametrize("mesh", ["passage", "cascade"])
+def test_frozen_rk_harmonic_matches_oracle(F, mesh):
+    import torch
+    m, Q, K = _case(mesh)
+    om = np.zeros((2, m.n_zones))
+    om[1] = 18.0
+    rng = np.random.default_rng(5)
+    fh = rng.standard_normal((m.n_cells, 6)) + 1j * rng.standard_normal((m.n_cells, 6))
+    q0 = rng.standard_normal((m.n_cells, 6)) + 1j * rng.standard_normal((m.n_cells, 6))
+    c = F.Context(m)
+    c.assemble_jacobian(to_dev(Q))
+    c.set_harmonics(om)
+    c.set_frozen_turbulence([0, 1])
+    col, _ = c.ordering()
+    qh = to_dev(q0)
+    _, hist = c.rk_harmonic(1, qh, to_dev(fh), 3, max_sweeps=10, rtol=0.0)
+    torch.cuda.synchronize()
+    Qo, h_or = q0.copy(), []
+    for _ in range(3):
+        Qo, r0 = rk.harmonic_step(m, Q, Qo, fh, om[1], col, rtol=0.0, max_sweeps=10, frozen=True)
+        h_or.append(r0)
+    assert relerr(qh.cpu().numpy(), Qo) <= 1e-10
+    np.testing.assert_allclose(hist, h_or, rtol=1e-11)
+    c.close()
+
+
+def test_frozen_errors(F):
+    m, Q, K = _case("passage")
+    c = F.Context(m)
+    with pytest.raises(F.FnlhError):
+        c.set_frozen_turbulence([0, 1, 1])                       # before set_harmonics
+    c.assemble_jacobian(to_dev(Q))
+    c.set_harmonics(OMEGA)
+    with pytest.raises(F.FnlhError):
+        c.set_frozen_turbulence([0, 1])                          # wrong count
+    with pytest.raises(F.FnlhError):
+        c.set_frozen_turbulence([0, 2, 1])                       # not 0/1
+    c.set_frozen_turbulence(FROZEN)
+    net = F.Network(c)
+    net.set_weights(synth.he_init(0))
+    with pytest.raises(F.FnlhError):
+        _solve(c, [1], [synth.rhs(m.n_cells, 1)], kind="learned", max_sweeps=4, rtol=0.0)
+    net.close()
+    c.close()

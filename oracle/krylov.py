@@ -1,0 +1,106 @@
+"""Reference of the Krylov solve around the ILU(0)/DILU preconditioner (test
+infrastructure only; nothing in the product path imports this module).
+
+Paper: section "Generalized RK Scheme for The Mean Flow" notes that the ILU(0)
+approximation of K^-1 serves either as a smoother (the Richardson iteration of
+oracle.solve, the paper's choice) or as the preconditioner of a Newton-Krylov method.
+The paper gives no Krylov algorithm; this is the textbook restarted flexible GMRES
+(FGMRES(m): Saad, Iterative Methods for Sparse Linear Systems, 2nd ed., Alg. 9.6) on the
+system of oracle.solve, (K + i omega V I) x = b, with right preconditioning:
+
+  r0 = b - A x0, beta = ||r0||, v1 = r0 / beta;
+  for j = 1..m:  z_j = M_j^-1 v_j;  w = A z_j;
+                 h_ij = (v_i, w), w -= h_ij v_i for i = 1..j   (modified Gram-Schmidt);
+                 h_{j+1,j} = ||w||;  v_{j+1} = w / h_{j+1,j};
+                 y_j = argmin || beta e1 - Hbar_j y ||  (least squares, j+1 by j);
+                 the residual norm of x0 + Z_j y_j is that minimum;
+  x = x0 + Z_k y_k at the end of the cycle (k the last j); restart from the true residual.
+
+M_j^-1 v: `inner_sweeps` steps of the preconditioned Richardson of oracle.solve from
+x = 0 (one step is exactly M^-1 v for the DILU, SGS or Jacobi M).  The inner products
+are (u, v) = sum conj(u) v over all 6N complex entries; the stop test is
+||r|| <= rtol ||r0|| on the least-squares residual norm, or iters = max_iters.
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import solve
+
+
+@dataclass
+class KrylovInfo:
+    status: int
+    iters: int
+    rel_res: float
+    history: list = field(default_factory=list)   # residual norm after each iteration (index 0: ||r0||)
+    true_res: float = 0.0                          # ||b - A x|| of the returned x, relative
+
+
+def _lstsq_min(Hbar, beta):
+    """y = argmin ||beta e1 - Hbar y||_2 and that minimum (LAPACK least squares)."""
+    rhs = np.zeros(Hbar.shape[0], np.complex128)
+    rhs[0] = beta
+    y = np.linalg.lstsq(Hbar, rhs, rcond=None)[0]
+    return y, float(np.linalg.norm(rhs - Hbar @ y))
+
+
+def fgmres(K, volume, zone, omega_row, b, colour, kind="DILU", x0=None, restart=20, rtol=1e-8, max_iters=1000,
+           inner_sweeps=1):
+    """Restarted flexible GMRES with the inner Richardson preconditioner.  Returns (x, KrylovInfo)."""
+    b = np.asarray(b, np.complex128)
+    x = np.zeros_like(b) if x0 is None else np.asarray(x0, np.complex128).copy()
+    Ds = solve.system_diag(K, volume, zone, omega_row)
+
+    def A(v):
+        return solve.apply(K, Ds, v)
+
+    def M_inv(v):
+        z, _ = solve.richardson(K, volume, zone, omega_row, v, colour, kind, rtol=0.0, max_sweeps=inner_sweeps,
+                                div_factor=np.inf)
+        return z
+
+    r = b - A(x)
+    beta = float(np.linalg.norm(r))
+    n0 = beta
+    hist = [beta]
+    iters = 0
+    res = beta
+    status = solve.OK
+    while True:
+        if res <= rtol * n0:
+            status = solve.OK
+            break
+        if iters >= max_iters:
+            status = solve.NOT_CONVERGED
+            break
+        V = [r / beta]
+        Z = []
+        H = np.zeros((restart + 1, restart), np.complex128)
+        y = None
+        for j in range(restart):
+            Z.append(M_inv(V[j]))
+            w = A(Z[j])
+            for i in range(j + 1):
+                H[i, j] = np.vdot(V[i], w)
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            y, res = _lstsq_min(H[:j + 2, :j + 1], beta)
+            iters += 1
+            hist.append(res)
+            breakdown = H[j + 1, j] == 0.0
+            if not breakdown:
+                V.append(w / H[j + 1, j])
+            if res <= rtol * n0 or iters >= max_iters or breakdown:
+                break
+        x = x + sum(y[i] * Z[i] for i in range(len(y)))
+        r = b - A(x)                 # restart from the true residual
+        beta = float(np.linalg.norm(r))
+        if not np.isfinite(beta):
+            status = solve.DIVERGED
+            break
+        res = beta
+        if beta == 0.0:
+            break
+    true_rel = float(np.linalg.norm(b - A(x)) / n0) if n0 > 0 else 0.0
+    return x, KrylovInfo(status, iters, res / n0 if n0 > 0 else 0.0, hist, true_rel)

@@ -304,6 +304,44 @@ typedef struct {
 } fnlh_tune_result;
 int fnlh_autotune(fnlh_ctx c, int32_t n_sys, int32_t sweeps, fnlh_tune_result* out, void* stream);
 
+/* ---- Krylov solve: restarted flexible GMRES around the same preconditioners (section
+ * "Generalized RK Scheme for The Mean Flow": the ILU(0) approximation of K^-1 is used
+ * either as a smoother, fnlh_relax, or as the preconditioner of a Newton-Krylov method;
+ * the paper gives no Krylov algorithm, this is the textbook FGMRES(m) with right
+ * preconditioning).  Per iteration j: z_j = M^-1 v_j, `inner_sweeps` preconditioned
+ * Richardson sweeps from 0 (one sweep is exactly M^-1 of DILU, SGS or Jacobi; FP32/BF16
+ * sweeps for reduced storage), w = (K + i omega V) z_j with the FP64 operator,
+ * orthogonalised against v_0..v_j by classical Gram-Schmidt with a second pass where
+ * the norm falls below 1/sqrt(2) of its value (DGKS), Givens rotations on the host; x += Z y at the end of each cycle of `restart` iterations, and the next
+ * cycle starts from the true residual.  Inner products sum conj(u) v over all 6N complex
+ * entries.  Stop when the residual norm (the least-squares one within a cycle, the true
+ * one at a restart) is <= rtol ||r0||, after max_iters iterations, or on breakdown. */
+typedef struct {
+  int32_t kind;          /* FNLH_DILU, FNLH_SGS or FNLH_JACOBI: the preconditioner M      */
+  int32_t restart;       /* Krylov vectors per cycle, 1..256                               */
+  int32_t max_iters;     /* total iterations (preconditioner applications) per system     */
+  int32_t inner_sweeps;  /* sweeps per preconditioner application, >= 1                   */
+  double rtol;           /* relative residual target                                        */
+  int32_t use_graph;     /* replay the inner sweeps from HIP graphs                         */
+  int32_t pad_;
+} fnlh_gmres_opts;
+typedef struct {
+  int32_t iters, restarts, status, pad_;
+  double rel_res;        /* ||b - A x|| / ||b - A x0|| of the returned x (true residual, FP64) */
+  double res0;           /* ||b - A x0||                                                     */
+  double t_ms;           /* wall time of the call on the stream (all systems)               */
+} fnlh_gmres_report;
+/* n systems (1..16) of the set harmonics, solved together (each block read of the
+ * preconditioner sweeps and operator products serves all of them): x[j], b[j] device
+ * [N][6] complex128 (x in: x0, out: x), sys[j] their harmonic rows.  rep: host [n] or
+ * NULL.  history: host [n][max_iters + 1] or NULL, the residual norm after each
+ * iteration (index 0: ||r0||; least-squares norms within a cycle).  Device memory:
+ * (2 restart + 2) vectors of 96 N n bytes besides the context's.  Frozen-turbulence and
+ * phase-lagged systems are handled as in fnlh_relax.  Returns the worst status or an
+ * error (FNLH_E_ARG on bad options or more systems than factor slots). */
+int fnlh_gmres(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, const double* const* b,
+               const fnlh_gmres_opts* o, fnlh_gmres_report* rep, double* history, void* stream);
+
 /* Frozen turbulence (section "Brief Description of Hydra": the harmonic equations are
  * linearised with the turbulence model frozen, so the unit matrix of the frequency shift
  * in section "Generalized RK Scheme for Time-Linearized Harmonic Flows" is 5x5).

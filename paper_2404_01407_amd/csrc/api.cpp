@@ -1162,6 +1162,88 @@ int fnlh_residual(fnlh_ctx c, int32_t sys, const double* x, const double* b, dou
   return FNLH_OK;
 }
 
+}  // extern "C"
+
+namespace fnlh {
+
+int precond_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, const double* const* b, int kind,
+                    int inner, bool use_graph, hipStream_t s, PrecondPlan& out) {
+  if (!c) return FNLH_E_ARG;
+  if (kind != FNLH_DILU && kind != FNLH_SGS && kind != FNLH_JACOBI)
+    return set_err(c, FNLH_E_ARG, "preconditioner kind must be DILU, SGS or JACOBI");
+  if (inner < 1) return set_err(c, FNLH_E_ARG, "inner sweeps >= 1");
+  fnlh_relax_opts o{};
+  o.kind = kind;
+  o.max_sweeps = inner;
+  o.rtol = 0.0;
+  o.check_every = inner + 2;
+  o.inner_sweeps = inner;
+  o.use_graph = use_graph ? 1 : 0;
+  RelaxPlan P;
+  int rc = relax_prepare(c, n, sys, x, b, &o, s, P);
+  if (rc) return rc;
+  if (P.G < n) return set_err(c, FNLH_E_ARG, "more systems than factor slots (fnlh_options.factor_slots)");
+  SysBatch sb;
+  sb.n = n;
+  for (int k = 0; k < n; ++k) {
+    sb.orow[k] = sys[k];
+    sb.vslot[k] = k;
+  }
+  if ((rc = relax_factor(c, sb, P.fkind, s))) return rc;
+  out.path = P.path;
+  out.fkind = P.fkind;
+  out.inner = inner;
+  out.reduced = P.reduced;
+  out.use_graph = use_graph;
+  out.cfg = P.cfg;
+  return FNLH_OK;
+}
+
+int precond_apply(fnlh_ctx c, const PrecondPlan& pp, int ns, const SysBatch& sb, const double* v, double* z,
+                  hipStream_t s) {
+  if (sb.n <= 0) return FNLH_OK;
+  // the factor slots of these systems (cached: no refactorisation)
+  SysBatch fb = sb;
+  int rc;
+  if ((rc = relax_factor(c, fb, pp.fkind, s))) return rc;
+  const DevPattern p = c->pat();
+  SysState* st = (SysState*)c->st.p;
+  const size_t zb = (size_t)c->L.NP * ns * 12 * sizeof(double);
+  // exactly `inner` sweeps from zero: launched directly, no host synchronisation (the
+  // states retire every system after its last sweep; with per-kernel timing on, or graph
+  // replay asked for, the sweep loop of fnlh_relax runs them instead)
+  auto run = [&](void* xz, const void* bb) -> int {
+    if (c->stats_on || pp.use_graph)
+      return sweep_loop(c, (Path)pp.path, pp.cfg, ns, fb, xz, bb, c->y.p, st, 0.0, 1e30, pp.inner, pp.inner + 2,
+                        pp.use_graph, s);
+    Timer T{c, s, {}, 0, true, nullptr};
+    if (pp.path == kPathRB)
+      launch_rb_pass(pp.cfg, false, p, c->offd.p, c->diag.p, c->dinv.p, dinv_stride(c), xz, bb, ns, fb, st,
+                     (double*)c->partial.p, c->L.ctile[0], c->L.ctile[1] - c->L.ctile[0], s);
+    for (int k = 1; k <= pp.inner; ++k)
+      one_sweep(c, (Path)pp.path, pp.cfg, ns, fb, xz, bb, c->y.p, st, k, 0.0, 1e30, s, T);
+    return FNLH_OK;
+  };
+  if (!pp.reduced) {
+    launch_fill_zero(z, zb, s);
+    launch_kstate(fb, st, 1.0, pp.inner, s);
+    if ((rc = run(z, v))) return rc;
+  } else {
+    SysState* so = (SysState*)c->st_outer.p;
+    launch_kstate(fb, so, 1.0, 1 << 30, s);
+    launch_to_f32(p, v, (float*)c->rhs32.p, (float*)c->d32.p, ns, fb, so, s);
+    launch_inner_init(fb, so, st, pp.inner, s);
+    if ((rc = run(c->d32.p, c->rhs32.p))) return rc;
+    launch_fill_zero(z, zb, s);
+    launch_add_f32(p, z, (const float*)c->d32.p, ns, fb, so, s);
+  }
+  return check_launch(c, "preconditioner launch");
+}
+
+}  // namespace fnlh
+
+extern "C" {
+
 int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, const double* const* b,
                const fnlh_relax_opts* o, fnlh_sys_report* rep, void* stream) {
   RelaxPlan P;

@@ -151,6 +151,23 @@ int nn_learned_step(fnlh_ctx c, int ns, const SysBatch& sb, double* x, const dou
 int nn_relax_counts(fnlh_ctx c, int ns, int* host_counts, hipStream_t s);
 void nn_release(fnlh_ctx c);  // context destroyed: detach its network
 
+// Preconditioner access for the Krylov solve (api.cpp).  precond_prepare does what
+// fnlh_relax does before its sweeps (validation, x and b into the internal vectors x64
+// and b64 as slots 0..n-1, the frozen systems' sixth unknown zeroed, factors of all n
+// systems, the sweep path) for preconditioner `kind`; precond_apply sets z = M^-1 v for
+// the systems of sb, M^-1 being `inner` preconditioned Richardson sweeps from z = 0 (one
+// sweep is exactly the DILU, SGS or Jacobi M^-1), in the storage precision (FP32/BF16
+// sweeps on the rounded v for reduced storage); v and z internal [NP][ns][12] FP64.
+struct PrecondPlan {
+  int path = 0, fkind = 0, inner = 1;
+  bool reduced = false, use_graph = false;
+  SweepCfg cfg;
+};
+int precond_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, const double* const* b, int kind,
+                    int inner, bool use_graph, hipStream_t s, PrecondPlan& out);
+int precond_apply(fnlh_ctx c, const PrecondPlan& pp, int ns, const SysBatch& sb, const double* v, double* z,
+                  hipStream_t s);
+
 }  // namespace fnlh
 
 #define HIPC(c, expr, what)                              \

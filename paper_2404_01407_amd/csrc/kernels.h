@@ -170,6 +170,26 @@ void launch_outer_update(const SysBatch& sb, const SysState* inner, SysState* ou
 void launch_zero_sixth(int64_t rows, double* v, int ns, int vs, hipStream_t s);
 void launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 
+// ---- restarted flexible GMRES vector kernels (krylov.hip); vectors [NP][ns][12] FP64
+constexpr int kMdot = 8;          // basis vectors per inner-product launch
+constexpr int kMdotBlocks = 1024;  // workgroups of an inner-product launch (partials per product)
+struct KScale {
+  double s[kMaxBatch];
+};
+int mdot_blocks(int64_t NP);
+// out[(i * sb.n + kk) * 2 + {re, im}] = (V_i, w) = sum conj(V_i) w over the valid rows, i < nv,
+// for system kk of sb; partial: mdot_blocks(NP) * nq * 2 doubles with nq >= nv * sb.n
+void launch_mdot(const DevPattern& p, int ns, const double* V, int64_t vstride, int nv, const double* w,
+                 const SysBatch& sb, int nq, double* partial, double* out, hipStream_t s);
+// w += sgn * sum_{i < nv} coef[i * sb.n + kk] V_i  (complex coef)
+void launch_maxpy(const DevPattern& p, int ns, double* w, const double* V, int64_t vstride, int nv,
+                  const double* coef, double sgn, const SysBatch& sb, hipStream_t s);
+// dst = sc.s[kk] * src for system kk of sb
+void launch_mscale(const DevPattern& p, int ns, double* dst, const double* src, const KScale& sc, const SysBatch& sb,
+                   hipStream_t s);
+// sweep states of sb: active, ||r0||^2 = n2, limit sweeps
+void launch_kstate(const SysBatch& sb, SysState* st, double n2, int limit, hipStream_t s);
+
 // RK driver: Rusanov residual of f.state (internal [NP][6]) into user order R [N][6]
 // (part[tile]: sum |R|^2); stage helpers on user-order vectors of n reals
 void launch_rusanov_residual(const DevPattern& p, const DevFlow& f, const int32_t* iperm, double* R_user,

@@ -263,7 +263,9 @@ __global__ void k_check_dominance(DevPattern p, const TB* __restrict__ diag, int
 // systems (batch entries s, s+SW, ...).  The SW lanes of a row load the same block
 // address (one fetch per instruction), and their vector records are adjacent in the
 // interleaved layout.  A tile of 64 rows takes SW waves of 64/SW rows each.
-template <typename TB, int SW, int P, bool UPDATE, bool PIVOT>
+// PH = false: no phase-lagged couplings (p.ent_phase is null), which lets the update pass
+// keep two coupling slots in flight without spilling.
+template <typename TB, int SW, int P, bool UPDATE, bool PIVOT, bool PH = true>
 __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd, const TB* __restrict__ diag,
                                const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                typename TV_of<TB>::T* __restrict__ x, const typename TV_of<TB>::T* __restrict__ b,
@@ -327,11 +329,11 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
         if (!run[j]) continue;
         A xn[12];
         load_vec(xr + vs[j] * 12, xn);
-        if (p.ent_phase) apply_phase(p, slot * kLanes + rl, orow[j], xn);
+        if (PH && p.ent_phase) apply_phase(p, slot * kLanes + rl, orow[j], xn);
         sub_kx(acc[j], kb, xn);
       }
     };
-    if constexpr (P == 1 && UPDATE) {
+    if constexpr (P == 1 && UPDATE && !PH) {
       // two slots in flight: slot q + 1's block and neighbour vector load while slot q
       // is applied (the loop otherwise drains all loads before the next slot's issue);
       // the first-colour pass keeps one slot, its solve needs the registers
@@ -341,7 +343,6 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
         const int nb = p.ent_nbr[slot * kLanes + rl];
         load_block(offd + slot * slot_elems<TB>(), rl, kb);
         if (run[0]) load_vec(x + (int64_t)nb * ns * 12 + vs[0] * 12, xn);
-        if (run[0] && p.ent_phase) apply_phase(p, slot * kLanes + rl, orow[0], xn);
       };
       if (wd > 0) fetch(0, kb0, xn0);
       for (int q = 0; q < wd; q += 2) {
@@ -387,14 +388,15 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
   }
 }
 
-// the update pass with one system per lane and FP32 blocks fits four waves per SIMD
-// without spilling (its two neighbour slots in flight otherwise take it to three)
-template <typename TB, int P, bool UPDATE> constexpr int rb_min_waves() {
-  return (UPDATE && P == 1 && sizeof(TB) == 4) ? 4 : 1;
+// the update pass with four lanes per row, one system per lane, FP32 blocks and no
+// phase-lagged couplings fits four waves per SIMD without spilling (its two neighbour slots in flight otherwise
+// take it to three)
+template <typename TB, int SW, int P, bool UPDATE, bool PH> constexpr int rb_min_waves() {
+  return (UPDATE && !PH && SW == 4 && P == 1 && sizeof(TB) == 4) ? 4 : 1;
 }
 
-template <typename TB, int SW, int P, bool UPDATE, bool PIVOT>
-__global__ void __launch_bounds__(256, (rb_min_waves<TB, P, UPDATE>())) k_rb_pass(DevPattern p, const TB* __restrict__ offd,
+template <typename TB, int SW, int P, bool UPDATE, bool PIVOT, bool PH>
+__global__ void __launch_bounds__(256, (rb_min_waves<TB, SW, P, UPDATE, PH>())) k_rb_pass(DevPattern p, const TB* __restrict__ offd,
                                                  const TB* __restrict__ diag,
                                                  const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                                  typename TV_of<TB>::T* __restrict__ x,
@@ -404,7 +406,7 @@ __global__ void __launch_bounds__(256, (rb_min_waves<TB, P, UPDATE>())) k_rb_pas
   int64_t tile;
   int grp;
   if (!map_tile(nt, 1, tile, grp)) return;
-  rb_tile<TB, SW, P, UPDATE, PIVOT>(p, offd, diag, dinv, dstride, x, b, ns, sb, st, partial, t0 + tile);
+  rb_tile<TB, SW, P, UPDATE, PIVOT, PH>(p, offd, diag, dinv, dstride, x, b, ns, sb, st, partial, t0 + tile);
 }
 
 // Batched form: one launch over the concatenated (instance, tile) work list of many
@@ -1254,25 +1256,34 @@ __global__ void k_to_user(int64_t NP, const int32_t* __restrict__ iperm, const d
   const int32_t u = iperm[row];
   if (u >= 0) user[(int64_t)u * width + c] = internal[(row * ns + vs) * width + c];
 }
+// defect-correction conversions, item (row, system kk of sb, component) with the component
+// fastest, then the system: consecutive lanes touch consecutive entries of the
+// interleaved rows, so each vector is streamed once whatever the number of systems
 __global__ void k_to_f32(int64_t NP, int ns, const double* __restrict__ r64, float* __restrict__ rhs32,
                          float* __restrict__ d32, SysBatch sb, const SysState* __restrict__ outer) {
-  const int k = blockIdx.y;
-  const int vs = sb.vslot[k];
-  if (!outer[vs].active) return;
+  const int nk = sb.n;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= NP * 12) return;
-  const int64_t o = (i / 12) * ns * 12 + vs * 12 + (i % 12);
+  if (i >= NP * nk * 12) return;
+  const int64_t rk = i / 12;
+  const int64_t row = rk / nk;
+  const int kk = (int)(rk - row * nk);
+  const int vs = sb.vslot[kk];
+  if (!outer[vs].active) return;
+  const int64_t o = (row * ns + vs) * 12 + (i - rk * 12);
   rhs32[o] = (float)r64[o];
   d32[o] = 0.0f;
 }
 __global__ void k_add_f32(int64_t NP, int ns, double* __restrict__ x64, const float* __restrict__ d32, SysBatch sb,
                           const SysState* __restrict__ outer) {
-  const int k = blockIdx.y;
-  const int vs = sb.vslot[k];
-  if (!outer[vs].active) return;
+  const int nk = sb.n;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= NP * 12) return;
-  const int64_t o = (i / 12) * ns * 12 + vs * 12 + (i % 12);
+  if (i >= NP * nk * 12) return;
+  const int64_t rk = i / 12;
+  const int64_t row = rk / nk;
+  const int kk = (int)(rk - row * nk);
+  const int vs = sb.vslot[kk];
+  if (!outer[vs].active) return;
+  const int64_t o = (row * ns + vs) * 12 + (i - rk * 12);
   x64[o] += (double)d32[o];
 }
 __global__ void k_zero_sixth(int64_t NP, int ns, int vs, double* __restrict__ v) {
@@ -1418,16 +1429,20 @@ void launch_rb_pass(const SweepCfg& c, bool update, const DevPattern& p, const v
   dim3 block(64 * SW);
 #define FNLH_RB_LAUNCH(SWV)                                                                                     \
   FNLH_DISPATCH_P(P, {                                                                                          \
-    if (update)                                                                                                 \
-      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, true, true>), grid, block, 0, s, p, (const TB*)offd,           \
+    if (update && p.ent_phase)                                                                                  \
+      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, true, true, true>), grid, block, 0, s, p, (const TB*)offd,     \
+                         (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, st, partial, \
+                         t0, nt);                                                                               \
+    else if (update)                                                                                            \
+      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, true, true, false>), grid, block, 0, s, p, (const TB*)offd,    \
                          (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, st, partial, \
                          t0, nt);                                                                               \
     else if (c.pivot)                                                                                           \
-      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, true>), grid, block, 0, s, p, (const TB*)offd,          \
+      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, true, true>), grid, block, 0, s, p, (const TB*)offd,    \
                          (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, st, partial, \
                          t0, nt);                                                                               \
     else                                                                                                        \
-      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, false>), grid, block, 0, s, p, (const TB*)offd,         \
+      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, false, true>), grid, block, 0, s, p, (const TB*)offd,   \
                          (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, st, partial, \
                          t0, nt);                                                                               \
   })
@@ -1596,13 +1611,13 @@ void launch_to_user(const DevPattern& p, const int32_t* iperm, const double* int
 void launch_to_f32(const DevPattern& p, const double* r64, float* rhs32, float* d32, int ns, const SysBatch& sb,
                    const SysState* outer, hipStream_t s) {
   if (sb.n <= 0) return;
-  dim3 grid((unsigned)((p.NP * 12 + 255) / 256), (unsigned)sb.n);
+  dim3 grid((unsigned)((p.NP * sb.n * 12 + 255) / 256));
   hipLaunchKernelGGL(k_to_f32, grid, dim3(256), 0, s, p.NP, ns, r64, rhs32, d32, sb, outer);
 }
 void launch_add_f32(const DevPattern& p, double* x64, const float* d32, int ns, const SysBatch& sb,
                     const SysState* outer, hipStream_t s) {
   if (sb.n <= 0) return;
-  dim3 grid((unsigned)((p.NP * 12 + 255) / 256), (unsigned)sb.n);
+  dim3 grid((unsigned)((p.NP * sb.n * 12 + 255) / 256));
   hipLaunchKernelGGL(k_add_f32, grid, dim3(256), 0, s, p.NP, ns, x64, d32, sb, outer);
 }
 void launch_inner_init(const SysBatch& sb, const SysState* outer, SysState* inner, int max_sweeps, hipStream_t s) {

@@ -60,6 +60,19 @@ class Report(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
 
 
+class GmresOpts(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("restart", C.c_int32), ("max_iters", C.c_int32), ("inner_sweeps", C.c_int32),
+                ("rtol", C.c_double), ("use_graph", C.c_int32), ("pad_", C.c_int32)]
+
+
+class GmresReport(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("status", C.c_int32), ("pad_", C.c_int32),
+                ("rel_res", C.c_double), ("res0", C.c_double), ("t_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+
+
 class TuneResult(C.Structure):
     _fields_ = [("lanes_per_row", C.c_int32), ("sys_per_lane", C.c_int32), ("us_per_sweep", C.c_double),
                 ("us_per_sweep_default", C.c_double), ("candidates", C.c_int32), ("pad_", C.c_int32)]
@@ -86,6 +99,7 @@ def _load():
         "fnlh_set_harmonics": (I32, [P, I32, V, V]),
         "fnlh_set_phase_lag": (I32, [P, V, I32, V]),
         "fnlh_set_frozen_turbulence": (I32, [P, I32, V]),
+        "fnlh_gmres": (I32, [P, I32, V, V, V, C.POINTER(GmresOpts), V, V, V]),
         "fnlh_rusanov_residual": (I32, [P, V, V, V, C.POINTER(D), V]),
         "fnlh_rk_mean": (I32, [P, I32, V, V, I32, D, D, I32, C.POINTER(RelaxOpts), V, V]),
         "fnlh_rk_harmonic": (I32, [P, I32, V, V, I32, C.POINTER(RelaxOpts), V, V]),
@@ -293,6 +307,29 @@ class Context:
                             C.byref(o), C.cast(rep, C.c_void_p), _stream(stream))
         self._check(rc, allow_positive=True)
         return rc, [r.as_dict() for r in rep]
+
+    def gmres(self, systems, xs, bs, kind="dilu", restart=20, max_iters=500, rtol=1e-8, inner_sweeps=1,
+              use_graph=False, history=False, stream=None):
+        """Restarted flexible GMRES with the DILU/SGS/Jacobi preconditioner for up to 16
+        systems at once; xs (in: x0, out: x) and bs complex128 CUDA tensors [N, 6].
+        Returns (status, reports) or, with history=True, (status, reports, histories) where
+        histories[j] holds the residual norm after each iteration (index 0: ||r0||)."""
+        n = len(systems)
+        for t in list(xs) + list(bs):
+            _dev_tensor(t, (self.n, 6), "vector")
+        sysarr = np.ascontiguousarray(systems, dtype=np.int32)
+        xp = (C.c_void_p * n)(*[_ptr(t) for t in xs])
+        bp = (C.c_void_p * n)(*[_ptr(t) for t in bs])
+        o = GmresOpts(KIND[kind], int(restart), int(max_iters), int(inner_sweeps), float(rtol), int(bool(use_graph)), 0)
+        rep = (GmresReport * n)()
+        hist = np.full((n, int(max_iters) + 1), np.nan) if history else None
+        rc = LIB.fnlh_gmres(self.h, n, _ptr(sysarr), C.cast(xp, C.c_void_p), C.cast(bp, C.c_void_p), C.byref(o),
+                            C.cast(rep, C.c_void_p), _ptr(hist), _stream(stream))
+        self._check(rc, allow_positive=True)
+        reps = [r.as_dict() for r in rep]
+        if history:
+            return rc, reps, [h[:r["iters"] + 1] for h, r in zip(hist, reps)]
+        return rc, reps
 
     def set_frozen_turbulence(self, flags):
         """Per-system frozen-turbulence flags (leading 5x5 sub-system, sixth unknown held at

@@ -40,6 +40,7 @@ def test_struct_layouts_match_header(F, tmp_path):
         pytest.skip("no C compiler")
     structs = {"fnlh_mesh": F.Mesh, "fnlh_options": F.Options, "fnlh_relax_opts": F.RelaxOpts,
                "fnlh_sys_report": F.Report, "fnlh_kernel_stats": F.KernelStats,
+               "fnlh_gmres_opts": F.GmresOpts, "fnlh_gmres_report": F.GmresReport,
                "fnlh_tune_result": F.TuneResult}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fnlh.h"', "int main(void) {"]
     for cname, py in structs.items():

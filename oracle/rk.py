@@ -39,9 +39,12 @@ def nonlinear_residual(mesh, Q, Qff=None):
 
 
 def mean_step(mesh, Q, colour, eps=0.6, sigma=50.0, scheme="implicit", rtol=1e-2, max_sweeps=10, kind="DILU",
-              Qff=None):
-    """One pseudo-time step of the mean flow; returns (Q^(n+1), ||R(Q^n)||)."""
+              Qff=None, part=None):
+    """One pseudo-time step of the mean flow; returns (Q^(n+1), ||R(Q^n)||).  part: the
+    stage solves use K with the couplings between partitions dropped."""
     K = assemble.assemble(mesh, Q, eps, sigma, scheme, Qff)
+    if part is not None:
+        K = solve.partition_dropped(K, part)
     G = gamma(scheme, eps, sigma)
     zero = np.zeros(mesh.n_zones)
     Q0 = np.asarray(Q, np.float64)
@@ -64,12 +67,15 @@ def harmonic_residual(J, mesh, omega_row, Qh, fh):
 
 
 def harmonic_step(mesh, Q, Qh, fh, omega_row, colour, eps=0.6, sigma=50.0, scheme="implicit", rtol=1e-2,
-                  max_sweeps=10, kind="DILU", Qff=None, frozen=False):
+                  max_sweeps=10, kind="DILU", Qff=None, frozen=False, part=None):
     """One pseudo-time step of a harmonic about the state Q; returns (Q^(n+1), ||R_l||).
     frozen: frozen turbulence, the 5x5 sub-system of J and K with the turbulence
-    perturbation held at 0."""
+    perturbation held at 0.  part: the stage solves use K with the couplings between
+    partitions dropped (the residual keeps the whole J)."""
     J = assemble.residual_jacobian(Q, mesh.edges, mesh.area, mesh.bface_cell, mesh.bface_area, Qff)
     K = assemble.preconditioner_matrix(J, eps, sigma, scheme)
+    if part is not None:
+        K = solve.partition_dropped(K, part)
     G = gamma(scheme, eps, sigma)
     Q0 = np.asarray(Qh, np.complex128).copy()
     if frozen:

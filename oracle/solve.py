@@ -71,6 +71,20 @@ def phase_lagged(K: BlockMatrix, edge_phase, sigma):
     return BlockMatrix(K.n, K.diag.copy(), K.rows.copy(), K.cols.copy(), K.offd * ph[:, None, None])
 
 
+def partition_dropped(K: BlockMatrix, part):
+    """K with the couplings between cells of different partitions dropped (section
+    "Parallel Implementation": the LHS is split over processors and the entries that
+    couple two nodes of different partitions are ignored, leaving one independent
+    sub-system per partition).  part[i] is the partition of cell i; the diagonal blocks
+    are kept whole.  The dropped blocks are set to zero, so the pattern (and the pairing
+    of entries 2e, 2e+1) is unchanged."""
+    part = np.asarray(part)
+    cross = part[K.rows] != part[K.cols]
+    offd = K.offd.copy()
+    offd[cross] = 0.0
+    return BlockMatrix(K.n, K.diag.copy(), K.rows.copy(), K.cols.copy(), offd)
+
+
 def dense(K: BlockMatrix, volume, zone, omega_row):
     """K_s as a dense [bN, bN] complex matrix, b the block size (for pins on small meshes)."""
     n, m = K.n, K.diag.shape[-1]

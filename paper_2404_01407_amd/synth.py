@@ -397,6 +397,33 @@ def _lowmode_field(rng, xi):
     return f / m if m > 0 else f
 
 
+def rcb_partition(mesh: Mesh, cells_per_part: int) -> np.ndarray:
+    """Partition of the cells into parts of at most cells_per_part cells by recursive
+    coordinate bisection of the centroids (each split halves a part across its longest
+    extent), the kind of domain decomposition a parallel solver distributes over
+    processors.  Returns part[N] int32, parts numbered 0.. in bisection order."""
+    part = np.zeros(mesh.n_cells, np.int32)
+    if cells_per_part >= mesh.n_cells:
+        return part
+    c = mesh.centroid
+    stack = [np.arange(mesh.n_cells)]
+    out = []
+    while stack:
+        ids = stack.pop()
+        if ids.size <= cells_per_part:
+            out.append(ids)
+            continue
+        ext = c[ids].max(axis=0) - c[ids].min(axis=0)
+        ax = int(np.argmax(ext))
+        order = ids[np.argsort(c[ids, ax], kind="stable")]
+        half = order.size // 2
+        stack.append(order[half:])
+        stack.append(order[:half])
+    for k, ids in enumerate(out):
+        part[ids] = k
+    return part
+
+
 def flow_state(mesh: Mesh, seed: int = 1) -> np.ndarray:
     """Smooth mean-flow conservative state per cell (user order), shape [N, 6]:
     (rho, rho u, rho v, rho w, rho E, rho nu~).  Ideal gas, gamma = 1.4."""

@@ -342,6 +342,21 @@ typedef struct {
 int fnlh_gmres(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, const double* const* b,
                const fnlh_gmres_opts* o, fnlh_gmres_report* rep, double* history, void* stream);
 
+/* Partition-dropped couplings (section "Parallel Implementation": the LHS is split over
+ * processors by a domain decomposition and the entries that couple two nodes of different
+ * partitions are ignored, so each partition solves its own sub-system; convergence
+ * degrades as the partitions shrink).  part [N] host, user order: the partition of each
+ * cell (any int32 labels); NULL clears.  Every coupling (K_ab and K_ba) between cells of
+ * different partitions is left out of the matrix the solves use: fnlh_relax, fnlh_gmres,
+ * fnlh_residual and the stage solves of the RK driver work with that K (diagonal blocks
+ * whole), while the RK residuals keep every coupling.  Applied at once to a matrix that
+ * is present and to every later fnlh_assemble_jacobian / fnlh_set_blocks (the dropped
+ * blocks are stored as zeros, and fnlh_get_blocks returns them so).  Changing or clearing
+ * partitions that were already applied needs the matrix again (relax returns
+ * FNLH_E_ORDER until fnlh_assemble_jacobian or fnlh_set_blocks).  Setting the same
+ * couplings again is a no-op. */
+int fnlh_set_partitions(fnlh_ctx c, const int32_t* part, void* stream);
+
 /* Frozen turbulence (section "Brief Description of Hydra": the harmonic equations are
  * linearised with the turbulence model frozen, so the unit matrix of the frequency shift
  * in section "Generalized RK Scheme for Time-Linearized Harmonic Flows" is 5x5).

@@ -936,7 +936,7 @@ int fnlh_destroy(fnlh_ctx c) {
                     &c->vol, &c->zone, &c->iperm, &c->perm, &c->edge_ent, &c->bf_ptr, &c->bf_idx, &c->area,
                     &c->bface_area, &c->offd, &c->diag, &c->offd64, &c->diag64, &c->state, &c->bstate,
                     &c->d_omega, &c->dinv, &c->x64, &c->b64, &c->r64, &c->y, &c->rhs32, &c->d32, &c->partial,
-                    &c->st, &c->st_outer, &c->d_err, &c->ent_phase, &c->phase_cs};
+                    &c->st, &c->st_outer, &c->d_err, &c->ent_phase, &c->phase_cs, &c->sys_frozen, &c->ent_drop};
   for (DevBuf* b : bufs) dfree(*b);
   if (c->h_st) (void)hipHostFree(c->h_st);
   if (c->h_err) (void)hipHostFree(c->h_err);
@@ -974,6 +974,7 @@ int fnlh_assemble_jacobian(fnlh_ctx c, const double* state, const double* bstate
   c->sigma = sigma;
   c->scheme = scheme;
   launch_assemble(c->storage, p, c->flow(), c->offd.p, c->diag.p, s);
+  launch_drop_blocks(c->storage, p, c->L.n_slots, (const int8_t*)c->ent_drop.p, c->offd.p, s);
   if ((rc = check_launch(c, "assemble launch"))) return rc;
   dfree(c->offd64);
   dfree(c->diag64);
@@ -1002,8 +1003,10 @@ int fnlh_set_blocks(fnlh_ctx c, const double* diag, const double* offd, void* st
     HIPC(c, hipMemsetAsync(c->diag64.p, 0, c->diag64.bytes, s), "zero shadow");
     launch_set_blocks(kF64, p, c->L.N, c->L.E, (const int32_t*)c->perm.p, (const int64_t*)c->edge_ent.p, diag, offd,
                       c->offd64.p, c->diag64.p, s);
+    launch_drop_blocks(kF64, p, c->L.n_slots, (const int8_t*)c->ent_drop.p, c->offd64.p, s);
     c->have_shadow = true;
   }
+  launch_drop_blocks(c->storage, p, c->L.n_slots, (const int8_t*)c->ent_drop.p, c->offd.p, s);
   if ((rc = check_launch(c, "set_blocks launch"))) return rc;
   c->have_matrix = true;
   c->assembled = false;
@@ -1103,6 +1106,53 @@ int fnlh_set_phase_lag(fnlh_ctx c, const int8_t* edge_phase, int32_t n_sys, cons
     return rc;
   }
   c->ibpa.assign(sigma, sigma + n_sys);
+  return FNLH_OK;
+}
+
+int fnlh_set_partitions(fnlh_ctx c, const int32_t* part, void* stream) {
+  if (!c) return FNLH_E_ARG;
+  const Layout& L = c->L;
+  std::vector<int8_t> drop;
+  std::vector<int32_t> ph;
+  bool any = false;
+  if (part) {
+    ph.assign(part, part + L.N);
+    drop.assign(L.ent_nbr.size(), 0);
+    for (int64_t e = 0; e < L.E; ++e) {
+      const int64_t f0 = L.edge_ent[2 * e], f1 = L.edge_ent[2 * e + 1];
+      // entry f0 is (a -> b): its neighbour is b; entry f1 (b -> a) has neighbour a
+      const int32_t ua = L.iperm[L.ent_nbr[f1]], ub = L.iperm[L.ent_nbr[f0]];
+      if (part[ua] != part[ub]) {
+        drop[f0] = drop[f1] = 1;
+        any = true;
+      }
+    }
+  }
+  if (!any) ph.clear();
+  if (ph == c->part_host) return FNLH_OK;  // same couplings dropped as before
+  const bool had = c->ent_drop.p != nullptr;
+  int rc;
+  if (!any) {
+    dfree(c->ent_drop);
+  } else if ((rc = dupload(c, c->ent_drop, drop, "partition couplings"))) {
+    return rc;
+  }
+  c->part_host = ph;
+  c->buf_gen++;  // captured sweeps hold the flag table's address
+  if (c->have_matrix) {
+    if (had) {
+      // blocks dropped by the previous partitions are gone: the matrix must be set again
+      c->have_matrix = false;
+      c->assembled = false;
+    } else {
+      hipStream_t s = S(stream);
+      const DevPattern p = c->pat();
+      launch_drop_blocks(c->storage, p, L.n_slots, (const int8_t*)c->ent_drop.p, c->offd.p, s);
+      if (c->have_shadow) launch_drop_blocks(kF64, p, L.n_slots, (const int8_t*)c->ent_drop.p, c->offd64.p, s);
+      if ((rc = check_launch(c, "partition launch"))) return rc;
+    }
+    invalidate_factors(c);
+  }
   return FNLH_OK;
 }
 
@@ -1752,11 +1802,11 @@ int fnlh_get_ordering(fnlh_ctx c, int32_t* colour_of_cell, int32_t* n_colours) {
 
 int fnlh_memory(fnlh_ctx c, size_t* matrix_bytes, size_t* factor_bytes, size_t* vector_bytes) {
   if (!c) return FNLH_E_ARG;
-  const DevBuf* mat[] = {&c->ent_phase, &c->tile_nrows, &c->tile_width, &c->tile_slot0, &c->ent_nbr, &c->ent_edge, &c->ent_rev,
+  const DevBuf* mat[] = {&c->ent_phase, &c->ent_drop, &c->tile_nrows, &c->tile_width, &c->tile_slot0, &c->ent_nbr, &c->ent_edge, &c->ent_rev,
                          &c->vol, &c->zone, &c->iperm, &c->perm, &c->edge_ent, &c->bf_ptr, &c->bf_idx, &c->area,
                          &c->bface_area, &c->offd, &c->diag, &c->offd64, &c->diag64, &c->state, &c->bstate};
   const DevBuf* vec[] = {&c->x64, &c->b64,     &c->r64,     &c->y,  &c->rhs32,   &c->d32,
-                         &c->partial, &c->st, &c->st_outer, &c->d_omega, &c->phase_cs};
+                         &c->partial, &c->st, &c->st_outer, &c->d_omega, &c->phase_cs, &c->sys_frozen};
   size_t m = 0, v = 0;
   for (auto* b : mat) m += b->bytes;
   for (auto* b : vec) v += b->bytes;

@@ -54,6 +54,10 @@ struct fnlh_ctx_s {
   // frozen turbulence: per system 1 = its sixth unknown is held at zero (null: none)
   DevBuf sys_frozen;
   std::vector<uint8_t> frozen;
+  // partition-dropped couplings: per entry 1 = between two partitions (null: none), and
+  // the partition of each user cell behind it
+  DevBuf ent_drop;
+  std::vector<int32_t> part_host;
   // factors
   int n_slots = 0;
   DevBuf dinv;
@@ -116,6 +120,7 @@ struct fnlh_ctx_s {
     f.bstate = (const double*)bstate.p;
     f.diag_scale = scheme == FNLH_IMPLICIT ? 1.0 + 1.0 / (eps * sigma) : 1.0;
     f.offdiag = scheme == FNLH_IMPLICIT ? 1 : 0;
+    f.ent_drop = (const int8_t*)ent_drop.p;
     return f;
   }
   size_t block_bytes() const { return storage == FNLH_F64 ? 8 : storage == FNLH_F32 ? 4 : 2; }

@@ -67,6 +67,8 @@ struct DevFlow {
   const double* bstate = nullptr;      // [B][6] far field or null
   double diag_scale = 1.0;             // 1 + 1/(eps sigma) (implicit) or 1 (explicit)
   int32_t offdiag = 1;                 // 0 for the explicit scheme (K = P)
+  // per entry 1 = coupling between two partitions, left out of the operator (null: none)
+  const int8_t* ent_drop = nullptr;
 };
 
 // One instance of a batched solve: its pattern, matrix, factors, vectors and states.
@@ -165,6 +167,9 @@ void launch_add_f32(const DevPattern& p, double* x64, const float* d32, int ns, 
                     const SysState* outer, hipStream_t s);
 void launch_inner_init(const SysBatch& sb, const SysState* outer, SysState* inner, int max_sweeps, hipStream_t s);
 void launch_outer_update(const SysBatch& sb, const SysState* inner, SysState* outer, hipStream_t s);
+// zero the stored off-diagonal blocks of the entries flagged in ent_drop (flat entries)
+void launch_drop_blocks(int storage, const DevPattern& p, int64_t n_slots, const int8_t* ent_drop, void* offd,
+                        hipStream_t s);
 // zero the sixth unknown of slot vs of an interleaved complex vector [rows][ns][6]
 // (frozen-turbulence systems)
 void launch_zero_sixth(int64_t rows, double* v, int ns, int vs, hipStream_t s);

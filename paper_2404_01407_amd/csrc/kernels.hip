@@ -1106,6 +1106,7 @@ __global__ void __launch_bounds__(256) k_resid_mfree(DevPattern p, DevFlow f, co
     sumS[2] += S[2];
     lam_sum += lam;
     if (!f.offdiag) continue;
+    if (f.ent_drop && f.ent_drop[fe]) continue;  // coupling between partitions: left out
     flux_jacobian(Qk, S, Ak);
 #pragma unroll
     for (int c = 0; c < 36; ++c) Ak[c] = 0.5 * Ak[c] - ((c % 7 == 0) ? 0.5 * lam : 0.0);
@@ -1285,6 +1286,15 @@ __global__ void k_add_f32(int64_t NP, int ns, double* __restrict__ x64, const fl
   if (!outer[vs].active) return;
   const int64_t o = (row * ns + vs) * 12 + (i - rk * 12);
   x64[o] += (double)d32[o];
+}
+template <typename TB>
+__global__ void k_drop_blocks(int64_t n_ent, const int8_t* __restrict__ ent_drop, TB* __restrict__ offd) {
+  const int64_t fe = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (fe >= n_ent || !ent_drop[fe]) return;
+  TB* dst = offd + (fe / kLanes) * slot_elems<TB>();
+  const int lane = (int)(fe % kLanes);
+#pragma unroll
+  for (int c = 0; c < 36; ++c) store_entry<TB>(dst, c, lane, 0.0);
 }
 __global__ void k_zero_sixth(int64_t NP, int ns, int vs, double* __restrict__ v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1641,6 +1651,16 @@ void launch_rk_update(bool complex_state, int64_t n, const double* q0, const dou
 }
 void launch_scale(int64_t n, double* y, double scale, hipStream_t s) {
   hipLaunchKernelGGL(k_scale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, y, scale);
+}
+void launch_drop_blocks(int storage, const DevPattern& p, int64_t n_slots, const int8_t* ent_drop, void* offd,
+                        hipStream_t s) {
+  const int64_t n = n_slots * kLanes;
+  if (n <= 0 || !ent_drop) return;
+  (void)p;
+  FNLH_DISPATCH_STORE(storage, {
+    hipLaunchKernelGGL((k_drop_blocks<TB>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, ent_drop,
+                       (TB*)offd);
+  });
 }
 void launch_zero_sixth(int64_t rows, double* v, int ns, int vs, hipStream_t s) {
   if (rows <= 0) return;

@@ -156,6 +156,7 @@ int fnlh_rk_harmonic(fnlh_ctx c, int32_t sys, double* qhat, const double* fhat, 
   DevFlow fJ = c->flow();  // the residual Jacobian J itself (K without the CFL term)
   fJ.diag_scale = 1.0;
   fJ.offdiag = 1;
+  fJ.ent_drop = nullptr;  // the residual keeps every coupling (only K is partitioned)
   SysBatch sb;
   sb.n = 1;
   sb.orow[0] = sys;

@@ -99,6 +99,7 @@ def _load():
         "fnlh_set_harmonics": (I32, [P, I32, V, V]),
         "fnlh_set_phase_lag": (I32, [P, V, I32, V]),
         "fnlh_set_frozen_turbulence": (I32, [P, I32, V]),
+        "fnlh_set_partitions": (I32, [P, V, V]),
         "fnlh_gmres": (I32, [P, I32, V, V, V, C.POINTER(GmresOpts), V, V, V]),
         "fnlh_rusanov_residual": (I32, [P, V, V, V, C.POINTER(D), V]),
         "fnlh_rk_mean": (I32, [P, I32, V, V, I32, D, D, I32, C.POINTER(RelaxOpts), V, V]),
@@ -330,6 +331,17 @@ class Context:
         if history:
             return rc, reps, [h[:r["iters"] + 1] for h, r in zip(hist, reps)]
         return rc, reps
+
+    def set_partitions(self, part, stream=None):
+        """Drop the couplings between cells of different partitions (part: [N] int labels
+        per user cell) from the matrix the solves use; None clears them."""
+        if part is None:
+            self._check(LIB.fnlh_set_partitions(self.h, None, _stream(stream)))
+            return
+        a = np.ascontiguousarray(part, dtype=np.int32)
+        if a.shape != (self.n,):
+            raise ValueError(f"part must have shape ({self.n},)")
+        self._check(LIB.fnlh_set_partitions(self.h, _ptr(a), _stream(stream)))
 
     def set_frozen_turbulence(self, flags):
         """Per-system frozen-turbulence flags (leading 5x5 sub-system, sixth unknown held at

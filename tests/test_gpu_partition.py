@@ -1,0 +1,207 @@
+"""GPU parity of the partition-dropped couplings (fnlh_set_partitions) against the
+oracle's partition_dropped matrix: iterates (FP64, 1e-11) on the two-colour and general
+paths, converged FP64/FP32 solves against the dense dropped system (the FP64 matrix-free
+operator of FP32 storage leaves the same couplings out), the set_blocks path with its
+FP64 shadow, the stored blocks, the RK driver (stage solves on the dropped K, residuals
+on the whole J) step by step, FGMRES, and the life cycle of the partitions."""
+import numpy as np
+import pytest
+
+from oracle import assemble, rk, solve
+from paper_2404_01407_amd import synth
+
+from gpu_helpers import blocks_user_layout, relerr, to_dev
+
+pytestmark = pytest.mark.gpu
+
+ITER_TOL = 1e-11
+OMEGA = np.array([[0.0], [18.0], [36.0]])
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2404_01407_amd import fnlh
+    return fnlh
+
+
+def _case(kind, seed=4):
+    if kind == "passage":
+        m = synth.passage_block(12, 6, 4, 36, seed=seed)        # two colours
+    else:
+        m = synth.cascade_block(8, 5, 3, 36, seed=seed)         # odd pitch: general colouring
+    Q = synth.flow_state(m, seed)
+    return m, Q, assemble.assemble(m, Q)
+
+
+def _solve(c, systems, bs, **kw):
+    import torch
+    xs = [to_dev(np.zeros((c.n, 6), complex)) for _ in systems]
+    st, rep = c.relax(systems, xs, [to_dev(b) for b in bs], **kw)
+    torch.cuda.synchronize()
+    return st, rep, [x.cpu().numpy() for x in xs]
+
+
+def _rhs(m, seed):
+    return [synth.rhs(m.n_cells, seed + s, real=(s == 0)) for s in range(3)]
+
+
+@pytest.mark.parametrize("mesh", ["passage", "cascade"])
+@pytest.mark.parametrize("kind", ["dilu", "sgs", "jacobi"])
+@pytest.mark.parametrize("before", [True, False])
+def test_partitioned_iterates_match_oracle(F, mesh, kind, before):
+    """Partitions set before the assembly, or applied to an assembled matrix."""
+    m, Q, K = _case(mesh)
+    part = synth.rcb_partition(m, 37)
+    c = F.Context(m)
+    if before:
+        c.set_partitions(part)
+    c.assemble_jacobian(to_dev(Q))
+    if not before:
+        c.set_partitions(part)
+    c.set_harmonics(OMEGA)
+    col, _ = c.ordering()
+    bs = _rhs(m, 0)
+    st, rep, xs = _solve(c, [0, 1, 2], bs, kind=kind, max_sweeps=20, rtol=0.0)
+    Kd = solve.partition_dropped(K, part)
+    for s in range(3):
+        x_or, info = solve.richardson(Kd, m.volume, m.zone, OMEGA[s], bs[s], col, kind.upper(), rtol=0.0,
+                                      max_sweeps=20)
+        assert relerr(xs[s], x_or) <= ITER_TOL, (mesh, kind, s, relerr(xs[s], x_or))
+        assert abs(rep[s]["rel_res"] - info.rel_res) <= 1e-9 * info.rel_res + 1e-15
+    c.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_partitioned_converged_vs_dense(F, storage):
+    m, Q, K = _case("passage")
+    part = synth.rcb_partition(m, 50)
+    c = F.Context(m, storage=storage)
+    c.set_partitions(part)
+    c.assemble_jacobian(to_dev(Q))
+    c.set_harmonics(OMEGA)
+    bs = _rhs(m, 10)
+    st, rep, xs = _solve(c, [0, 1, 2], bs, kind="dilu", max_sweeps=3000, rtol=1e-11)
+    assert st == F.OK, rep
+    Kd = solve.partition_dropped(K, part)
+    for s in range(3):
+        assert relerr(xs[s], solve.dense_solve(Kd, m.volume, m.zone, OMEGA[s], bs[s])) <= 1e-9, (storage, s)
+    c.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_partitioned_set_blocks_and_get_blocks(F, storage):
+    import torch
+    m, Q, K = _case("passage", seed=6)
+    part = synth.rcb_partition(m, 25)
+    c = F.Context(m, storage=storage)
+    d, o = blocks_user_layout(K)
+    c.set_blocks(to_dev(d), to_dev(o))
+    c.set_partitions(part)
+    c.set_harmonics(OMEGA)
+    col, _ = c.ordering()
+    Kd = solve.partition_dropped(K, part)
+    dg, og = c.get_blocks()
+    torch.cuda.synchronize()
+    og = og.cpu().numpy()
+    _, od = blocks_user_layout(Kd)
+    cross = part[m.edges[:, 0]] != part[m.edges[:, 1]]
+    assert cross.any() and np.all(og[cross] == 0.0)
+    assert relerr(og[~cross], od[~cross]) <= (1e-15 if storage == "f64" else 1e-7)
+    bs = _rhs(m, 20)
+    if storage == "f64":
+        st, rep, xs = _solve(c, [0, 1, 2], bs, kind="dilu", max_sweeps=15, rtol=0.0)
+        for s in range(3):
+            x_or, _ = solve.richardson(Kd, m.volume, m.zone, OMEGA[s], bs[s], col, "DILU", rtol=0.0, max_sweeps=15)
+            assert relerr(xs[s], x_or) <= ITER_TOL
+    else:   # FP64 shadow of the blocks: the outer residual is the dropped FP64 operator
+        st, rep, xs = _solve(c, [0, 1, 2], bs, kind="dilu", max_sweeps=3000, rtol=1e-11)
+        assert st == F.OK
+        for s in range(3):
+            assert relerr(xs[s], solve.dense_solve(Kd, m.volume, m.zone, OMEGA[s], bs[s])) <= 1e-9
+    c.close()
+
+
+@pytest.mark.parametrize("mesh", ["passage", "cascade"])
+def test_partitioned_rk_steps_match_oracle(F, mesh):
+    import torch
+    m, Q, K = _case(mesh)
+    part = synth.rcb_partition(m, 30)
+    om = np.zeros((2, m.n_zones))
+    om[1] = 18.0
+    rng = np.random.default_rng(7)
+    fh = rng.standard_normal((m.n_cells, 6)) + 1j * rng.standard_normal((m.n_cells, 6))
+    c = F.Context(m)
+    c.set_partitions(part)
+    st = to_dev(Q)
+    c.assemble_jacobian(st)
+    c.set_harmonics(om)
+    col, _ = c.ordering()
+    qh = to_dev(np.zeros_like(fh))
+    _, hh = c.rk_harmonic(1, qh, to_dev(fh), 3, max_sweeps=10, rtol=0.0)
+    _, hm = c.rk_mean(0, st, 2, max_sweeps=10, rtol=0.0)
+    torch.cuda.synchronize()
+    Qo, ho = np.zeros_like(fh), []
+    for _ in range(3):
+        Qo, r0 = rk.harmonic_step(m, Q, Qo, fh, om[1], col, rtol=0.0, max_sweeps=10, part=part)
+        ho.append(r0)
+    assert relerr(qh.cpu().numpy(), Qo) <= 1e-10
+    np.testing.assert_allclose(hh, ho, rtol=1e-11)
+    Qm, hmo = Q.copy(), []
+    for _ in range(2):
+        Qm, r0 = rk.mean_step(m, Qm, col, rtol=0.0, max_sweeps=10, part=part)
+        hmo.append(r0)
+    assert relerr(st.cpu().numpy(), Qm) <= 1e-10
+    np.testing.assert_allclose(hm, hmo, rtol=1e-11)
+    c.close()
+
+
+def test_partitioned_gmres(F):
+    import torch
+    m, Q, K = _case("passage")
+    part = synth.rcb_partition(m, 40)
+    c = F.Context(m)
+    c.set_partitions(part)
+    c.assemble_jacobian(to_dev(Q))
+    c.set_harmonics(OMEGA)
+    bs = _rhs(m, 30)
+    xs = [to_dev(np.zeros((m.n_cells, 6), complex)) for _ in range(3)]
+    st, rep = c.gmres([0, 1, 2], xs, [to_dev(b) for b in bs], restart=8, max_iters=300, rtol=1e-11)
+    torch.cuda.synchronize()
+    assert st == F.OK
+    Kd = solve.partition_dropped(K, part)
+    for s in range(3):
+        assert relerr(xs[s].cpu().numpy(), solve.dense_solve(Kd, m.volume, m.zone, OMEGA[s], bs[s])) <= 1e-9
+    c.close()
+
+
+def test_partition_life_cycle(F):
+    m, Q, K = _case("passage")
+    p1 = synth.rcb_partition(m, 40)
+    c = F.Context(m)
+    c.assemble_jacobian(to_dev(Q))
+    c.set_harmonics(OMEGA)
+    bs = _rhs(m, 40)
+    kw = dict(kind="dilu", max_sweeps=12, rtol=0.0)
+    _, _, full = _solve(c, [0, 1, 2], bs, **kw)
+    c.set_partitions(p1)
+    _, _, a = _solve(c, [0, 1, 2], bs, **kw)
+    c.set_partitions(p1.copy())                      # the same couplings: no-op
+    _, _, b = _solve(c, [0, 1, 2], bs, **kw)
+    for s in range(3):
+        assert np.array_equal(a[s], b[s])
+        assert relerr(a[s], full[s]) > 1e-6
+    c.set_partitions(None)                           # dropped blocks are gone: matrix needed again
+    with pytest.raises(F.FnlhError):
+        _solve(c, [0, 1, 2], bs, **kw)
+    c.assemble_jacobian(to_dev(Q))
+    c.set_harmonics(OMEGA)
+    _, _, back = _solve(c, [0, 1, 2], bs, **kw)
+    for s in range(3):
+        assert np.array_equal(back[s], full[s])
+    c.set_partitions(np.zeros(m.n_cells, np.int32))  # one partition: nothing dropped
+    _, _, one = _solve(c, [0, 1, 2], bs, **kw)
+    for s in range(3):
+        assert np.array_equal(one[s], full[s])
+    c.close()

@@ -49,13 +49,14 @@ def build_inputs():
 
 
 class Runner:
-    def __init__(self, mesh, Q, om, bs, storage, lanes=0, row_lanes=0, check_every=16, use_graph=True):
+    def __init__(self, mesh, Q, om, bs, storage, lanes=0, row_lanes=0, check_every=16, use_graph=True,
+                 wave_groups=None):
         import torch
         from paper_2404_01407_amd import fnlh
         t0 = time.perf_counter()
         self.ctx = fnlh.Context(mesh, storage=storage, outer="exact")
         self.ingest_ms = 1e3 * (time.perf_counter() - t0)
-        self.ctx.tune(sys_per_lane=lanes, lanes_per_row=row_lanes)
+        self.ctx.tune(sys_per_lane=lanes, lanes_per_row=row_lanes, wave_groups=wave_groups)
         self.check_every = check_every
         self.use_graph = use_graph
         self.Qd = torch.from_numpy(Q).cuda()
@@ -774,6 +775,8 @@ def main():
     ap.add_argument("--no-modes", action="store_true", help="skip the other storage precisions")
     ap.add_argument("--lanes", type=int, default=0, help="systems per lane of the sweep kernels (0 = auto)")
     ap.add_argument("--row-lanes", type=int, default=0, help="lanes sharing a row in the two-colour pass (0 = auto)")
+    ap.add_argument("--wave-groups", type=int, default=None, choices=[0, 1],
+                    help="two-colour pass: one wave per workgroup (1) or a tile per workgroup (0); default: library's")
     ap.add_argument("--check-every", type=int, default=16, help="sweeps between host checks of the stop flags")
     ap.add_argument("--no-graph", action="store_true", help="direct launches instead of graph replay")
     ap.add_argument("--no-stats", action="store_true", help="no per-kernel event timing in the timed region")
@@ -834,7 +837,7 @@ def main():
     mesh, Q, om, bs = build_inputs()
     print(f"[bench] inputs: {mesh.n_cells} cells, {mesh.n_edges} faces, {len(bs)} systems", file=sys.stderr, flush=True)
     main_run = Runner(mesh, Q, om, bs, args.storage, args.lanes, args.row_lanes, args.check_every,
-                      not args.no_graph)
+                      not args.no_graph, args.wave_groups)
     res = main_run.timed(args.steps, args.warmup, stats=not args.no_stats)
     print(f"[bench] {args.storage}: {res['ms_per_step']:.2f} ms/step, sweeps {res['sweeps']}", file=sys.stderr,
           flush=True)

@@ -285,8 +285,11 @@ int fnlh_stats_get(fnlh_ctx c, int32_t which, fnlh_kernel_stats* out);
  *   FNLH_TUNE_SYS_PER_LANE  minimum systems a lane of the sweep kernels carries: 1, 2
  *                           or 4 (0 = automatic).
  *   FNLH_TUNE_LANES_PER_ROW lanes sharing one row in the two-colour pass: 1, 2 or 4
- *                           (0 = automatic: min(4, systems)). */
-enum { FNLH_TUNE_SYS_PER_LANE = 0, FNLH_TUNE_LANES_PER_ROW = 1 };
+ *                           (0 = automatic: min(4, systems)).
+ *   FNLH_TUNE_WAVE_GROUPS   two-colour pass workgroups: 1 = one wave per workgroup
+ *                           (default; finer dispatch), 0 = one 64-row tile per
+ *                           workgroup (its waves together); bitwise the same results. */
+enum { FNLH_TUNE_SYS_PER_LANE = 0, FNLH_TUNE_LANES_PER_ROW = 1, FNLH_TUNE_WAVE_GROUPS = 2 };
 int fnlh_tune(fnlh_ctx c, int32_t param, int32_t value);
 
 /* Autotuner: times `sweeps` preconditioned sweeps of the first n_sys systems (constant

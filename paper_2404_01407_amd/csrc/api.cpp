@@ -221,7 +221,7 @@ struct Timer {
 // A captured run of `K` sweeps (all after the first), replayed with hipGraphLaunch.
 struct GraphEntry {
   // key
-  int path, storage, spw, lpr, pivot, ns, K;
+  int path, storage, spw, lpr, pivot, wg, ns, K;
   SysBatch sb;
   const void *x, *b, *y, *st;
   double rtol, divf;
@@ -306,11 +306,21 @@ void one_sweep(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, const SysBatc
     launch_rb_pass(cfg, true, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, ns, sb, st, part, L.ctile[1],
                    L.ctile[2] - L.ctile[1], s);
     T.end();
-    launch_reduce(sb, part, L.n_tiles, L.ctile[1], L.ctile[2] - L.ctile[1], rb_slots(cfg, sb.n), st,
-                  first ? kReduceSweepNoNorm : kReduceSweep, rtol, divf, 0, s);
+    // the update pass's norms are reduced by the first workgroups of the pass that follows
+    FusedReduce fr;
+    fr.n = sb.n;
+    fr.slots = rb_slots(cfg, sb.n);
+    fr.mode = first ? kReduceSweepNoNorm : kReduceSweep;
+    fr.t0 = L.ctile[1];
+    fr.nt = L.ctile[2] - L.ctile[1];
+    fr.rtol2 = rtol * rtol;
+    fr.div2 = divf * divf;
+    const bool fuse = L.ctile[1] > L.ctile[0];
+    if (!fuse)
+      launch_reduce(sb, part, L.n_tiles, fr.t0, fr.nt, fr.slots, st, fr.mode, rtol, divf, 0, s);
     T.begin(FNLH_KSTAT_SWEEP_SET, 0, k);
     launch_rb_pass(cfg, false, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, ns, sb, st, part, L.ctile[0],
-                   L.ctile[1] - L.ctile[0], s);
+                   L.ctile[1] - L.ctile[0], s, fuse ? &fr : nullptr);
     T.end();
   } else if (path == kPathGeneral) {
     const int m = L.n_colours;
@@ -339,7 +349,7 @@ void one_sweep(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, const SysBatc
 bool same_key(const GraphEntry* g, uint64_t gen, int path, const SweepCfg& cfg, int ns, int K, const SysBatch& sb,
               const void* x, const void* b, const void* y, const void* st, double rtol, double divf, bool stats) {
   if (g->gen != gen || g->path != path || g->storage != cfg.storage || g->spw != cfg.spw || g->lpr != cfg.lanes_per_row ||
-      g->pivot != (int)cfg.pivot || g->ns != ns || g->K != K || g->x != x || g->b != b || g->y != y ||
+      g->pivot != (int)cfg.pivot || g->wg != (int)cfg.wave_groups || g->ns != ns || g->K != K || g->x != x || g->b != b || g->y != y ||
       g->st != st || g->rtol != rtol || g->divf != divf || g->stats != stats || g->sb.n != sb.n)
     return false;
   for (int k = 0; k < sb.n; ++k)
@@ -382,6 +392,7 @@ GraphEntry* get_graph(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, int K,
   g->storage = cfg.storage;
   g->spw = cfg.spw;
   g->lpr = cfg.lanes_per_row;
+  g->wg = (int)cfg.wave_groups;
   g->pivot = cfg.pivot;
   g->ns = ns;
   g->K = K;
@@ -573,6 +584,7 @@ int relax_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, c
   P.cfg.storage = c->storage;
   P.cfg.spw = c->lanes_per_sys;
   P.cfg.lanes_per_row = c->lanes_per_row;
+  P.cfg.wave_groups = c->wave_groups != 0;
   P.cfg.pivot = !c->dom;
   P.G = std::min({n, kMaxBatch, c->n_slots});
   P.tf.assign(n, 0.0);
@@ -1765,6 +1777,11 @@ int fnlh_tune(fnlh_ctx c, int32_t param, int32_t value) {
     if (value != 0 && value != 1 && value != 2 && value != 4)
       return set_err(c, FNLH_E_ARG, "tune: lanes per row must be 0, 1, 2 or 4");
     c->lanes_per_row = value;
+    return FNLH_OK;
+  }
+  if (param == FNLH_TUNE_WAVE_GROUPS) {
+    if (value != 0 && value != 1) return set_err(c, FNLH_E_ARG, "tune: wave groups must be 0 or 1");
+    c->wave_groups = value;
     return FNLH_OK;
   }
   return set_err(c, FNLH_E_ARG, "tune: unknown parameter");

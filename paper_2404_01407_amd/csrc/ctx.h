@@ -32,6 +32,7 @@ struct fnlh_ctx_s {
   int factor_slots_opt = 0;
   int lanes_per_sys = 0;  // systems per lane of the sweep kernels (0 = automatic)
   int lanes_per_row = 0;  // lanes sharing a row in the two-colour pass (0 = automatic)
+  int wave_groups = 1;    // two-colour pass: 1 = one wave per workgroup (default), 0 = a tile per workgroup
   std::string err;
 
   // pattern (device)

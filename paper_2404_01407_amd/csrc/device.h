@@ -345,15 +345,20 @@ __device__ inline double wave_sum(double v) {
 // every XCD a contiguous range of tiles (neighbouring cells, overlapping gathers), and
 // keep the system groups of one tile on the same XCD, adjacent in dispatch order.
 // The grid is 8 * ceil(nt*ng / 8) workgroups; returns false for the spare ones.
-__device__ inline bool map_tile(int64_t nt, int ng, int64_t& tile, int& group) {
+// b: the workgroup's index among the tile workgroups (blockIdx.x unless a kernel puts other
+// work first); the grid holds 8 * ceil(nt * ng / 8) of them.
+__device__ inline bool map_tile_b(int64_t nt, int ng, int64_t b, int64_t& tile, int& group) {
   const int64_t total = nt * ng;
   const int64_t per = (total + 7) / 8;
-  const int64_t b = blockIdx.x;
+  if (b >= 8 * per) return false;
   const int64_t k = (b & 7) * per + (b >> 3);
   if (k >= total) return false;
   tile = k / ng;
   group = (int)(k % ng);
   return true;
+}
+__device__ inline bool map_tile(int64_t nt, int ng, int64_t& tile, int& group) {
+  return map_tile_b(nt, ng, blockIdx.x, tile, group);
 }
 
 // ---------------------------------------------------------------- flux Jacobian

@@ -99,6 +99,7 @@ struct SweepCfg {
   int spw = 0;            // systems per lane (1, 2, 4); 0 = automatic
   int lanes_per_row = 0;  // two-colour pass: lanes sharing a row (1, 2, 4); 0 = automatic
   bool pivot = true;      // first-colour solve pivots (false: diagonal blocks are dominant)
+  bool wave_groups = false;  // two-colour pass: one wave per workgroup (else a whole tile)
 };
 int rb_slots(const SweepCfg& c, int n);  // norm partial slots per tile of the two-colour pass
 void rb_shape(const SweepCfg& c, int n, int& SW, int& P);  // lanes per row, systems per lane
@@ -122,9 +123,19 @@ void launch_factor(int storage, bool dilu, const DevPattern& p, const void* offd
 
 // sweeps; TV = double for F64 storage, float otherwise
 // Vectors: internal layout [NP][ns][12], ns = systems of the solve, slot = vslot.
+// The reduction of an update pass's norms folded into the first-colour pass that follows
+// (same stop logic as launch_reduce with mode kReduceSweep / kReduceSweepNoNorm).
+struct FusedReduce {
+  int n = 0;  // systems of sb to reduce (0: none)
+  int slots = 0;
+  int mode = 0;
+  int64_t t0 = 0, nt = 0;  // the update pass's tile range
+  double rtol2 = 0.0, div2 = 0.0;
+};
 void launch_rb_pass(const SweepCfg& c, bool update, const DevPattern& p, const void* offd, const void* diag,
                     const void* dinv, int64_t dinv_stride, void* x, const void* b, int ns, const SysBatch& sb,
-                    const SysState* st, double* partial, int64_t t0, int64_t nt, hipStream_t s);
+                    const SysState* st, double* partial, int64_t t0, int64_t nt, hipStream_t s,
+                    const FusedReduce* fused = nullptr);
 void launch_fwd(const SweepCfg& c, bool last, const DevPattern& p, const void* offd, const void* diag,
                 const void* dinv, int64_t dinv_stride, void* x, const void* b, void* y, int ns, const SysBatch& sb,
                 const SysState* st, double* partial, int64_t t0, int64_t nt, int64_t cstart, hipStream_t s);

@@ -263,6 +263,65 @@ __global__ void k_check_dominance(DevPattern p, const TB* __restrict__ diag, int
 // systems (batch entries s, s+SW, ...).  The SW lanes of a row load the same block
 // address (one fetch per instruction), and their vector records are adjacent in the
 // interleaved layout.  A tile of 64 rows takes SW waves of 64/SW rows each.
+// Sum of a system's per-tile norm partials (tiles [t0, t0 + nt), `slots` each) in one
+// canonical order whatever the workgroup size (64 or 256 threads): 256 accumulators,
+// accumulator v taking tiles v, v + 256, ... with their slots in order, then a fixed
+// binary tree.  Every reduction of sweep norms uses it, so fused and separate reductions
+// give the same bits.  All threads of the workgroup call it; the result is valid in
+// thread 0.
+__device__ inline double canonical_sum(const double* __restrict__ pp, int64_t nt, int slots) {
+  __shared__ double sh[256];
+  for (int v = threadIdx.x; v < 256; v += blockDim.x) {
+    double s = 0.0;
+    for (int64_t t = v; t < nt; t += 256)
+      for (int q = 0; q < slots; ++q) s += pp[t * kPartialSlots + q];
+    sh[v] = s;
+  }
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    for (int v = threadIdx.x; v < o; v += blockDim.x) sh[v] += sh[v + o];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// The stop logic after one sweep (the norm is that of the sweep's residual, taken before
+// its update; NoNorm: the first sweep, no norm yet).  A system that meets a criterion is
+// marked pending and retires after the next sweep's reduction.
+__device__ inline void sweep_state(SysState& S, double n2, int mode, double rtol2, double div2) {
+  if (!S.active) return;
+  if (S.pending) {
+    S.active = 0;
+    return;
+  }
+  S.sweeps += 1;
+  if (mode == kReduceSweep) {
+    S.last_n2 = n2;
+    if (n2 <= rtol2 * S.norm0sq) {
+      S.status = kOK;
+      S.pending = 1;
+    } else if (!isfinite(n2) || n2 > div2 * S.norm0sq) {
+      S.status = kDiverged;
+      S.pending = 1;
+    }
+  }
+  if (S.sweeps >= S.limit) S.pending = 1;
+}
+
+// The reduction of the update pass's per-tile norms for one system, done by one workgroup
+// of the first-colour pass that follows it (one launch fewer per sweep), in the canonical
+// order.
+__device__ inline void fused_sweep_reduce(const FusedReduce& fr, const SysBatch& sb, const double* __restrict__ partial,
+                                          int64_t n_tiles, SysState* __restrict__ st, int k) {
+  const int vs = sb.vslot[k];
+  const double* pp = partial + ((int64_t)vs * n_tiles + fr.t0) * kPartialSlots;
+  const double n2 = canonical_sum(pp, fr.mode != kReduceSweepNoNorm ? fr.nt : 0, fr.slots);
+  if (threadIdx.x != 0) return;
+  SysState S = st[vs];
+  sweep_state(S, n2, fr.mode, fr.rtol2, fr.div2);
+  st[vs] = S;
+}
+
 // PH = false: no phase-lagged couplings (p.ent_phase is null), which lets the update pass
 // keep two coupling slots in flight without spilling.
 template <typename TB, int SW, int P, bool UPDATE, bool PIVOT, bool PH = true>
@@ -270,10 +329,9 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
                                const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                typename TV_of<TB>::T* __restrict__ x, const typename TV_of<TB>::T* __restrict__ b,
                                int ns, const SysBatch& sb, const SysState* __restrict__ st,
-                               double* __restrict__ partial, int64_t tile) {
+                               double* __restrict__ partial, int64_t tile, int w) {
   using A = typename TV_of<TB>::T;
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
   const int sidx = lane % SW;
   const int rl = w * (kLanes / SW) + lane / SW;  // row within the tile
   const int64_t row = tile * kLanes + rl;
@@ -401,12 +459,25 @@ __global__ void __launch_bounds__(256, (rb_min_waves<TB, SW, P, UPDATE, PH>())) 
                                                  const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                                  typename TV_of<TB>::T* __restrict__ x,
                                                  const typename TV_of<TB>::T* __restrict__ b, int ns, SysBatch sb,
-                                                 const SysState* __restrict__ st, double* __restrict__ partial,
-                                                 int64_t t0, int64_t nt) {
+                                                 SysState* st, double* __restrict__ partial,
+                                                 int64_t t0, int64_t nt, int wave_groups, FusedReduce fr) {
+  // first-colour pass: the first fr.n workgroups reduce the preceding update pass's norms
+  // (one system each) while the others sweep
+  int64_t blk = blockIdx.x;
+  if (!UPDATE && fr.n > 0) {
+    if (blk < fr.n) {
+      fused_sweep_reduce(fr, sb, partial, p.n_tiles, st, (int)blk);
+      return;
+    }
+    blk -= fr.n;
+  }
+  // a tile's SW waves in one workgroup, or (wave_groups) one workgroup per wave: finer
+  // dispatch granularity, the tile's waves still adjacent on one XCD
   int64_t tile;
   int grp;
-  if (!map_tile(nt, 1, tile, grp)) return;
-  rb_tile<TB, SW, P, UPDATE, PIVOT, PH>(p, offd, diag, dinv, dstride, x, b, ns, sb, st, partial, t0 + tile);
+  if (!map_tile_b(nt, wave_groups ? SW : 1, blk, tile, grp)) return;
+  const int w = wave_groups ? grp : (int)(threadIdx.x >> 6);
+  rb_tile<TB, SW, P, UPDATE, PIVOT, PH>(p, offd, diag, dinv, dstride, x, b, ns, sb, st, partial, t0 + tile, w);
 }
 
 // Batched form: one launch over the concatenated (instance, tile) work list of many
@@ -423,10 +494,12 @@ __global__ void __launch_bounds__(256) k_rb_batched(const InstDesc* __restrict__
   const bool pivot = D.pivot;
   if (!UPDATE && !pivot)
     rb_tile<TB, SW, P, UPDATE, false>(D.p, (const TB*)D.offd, (const TB*)D.diag, (const typename DF_of<TB>::T*)D.dinv, D.dstride,
-                                      (A*)D.x, (const A*)D.b, D.ns, D.sb, D.st, D.partial, wi.tile);
+                                      (A*)D.x, (const A*)D.b, D.ns, D.sb, D.st, D.partial, wi.tile,
+                                      (int)(threadIdx.x >> 6));
   else
     rb_tile<TB, SW, P, UPDATE, true>(D.p, (const TB*)D.offd, (const TB*)D.diag, (const typename DF_of<TB>::T*)D.dinv, D.dstride,
-                                     (A*)D.x, (const A*)D.b, D.ns, D.sb, D.st, D.partial, wi.tile);
+                                     (A*)D.x, (const A*)D.b, D.ns, D.sb, D.st, D.partial, wi.tile,
+                                     (int)(threadIdx.x >> 6));
 }
 
 // Systems of one lane when SW lanes share a row: batch entries k = j * SW + sidx.
@@ -677,23 +750,9 @@ __global__ void k_axpy_y(int64_t NP, int ns, A* __restrict__ x, const A* __restr
 __device__ inline void reduce_one(const double* __restrict__ partial, int64_t n_tiles, int64_t t0, int64_t nt,
                                   int slots, SysState* __restrict__ st, int vs, int mode, double rtol2, double div2,
                                   int max_sweeps) {
-  __shared__ double sh[256];
-  double s = 0.0;
-  if (mode != kReduceSweepNoNorm) {
-    // each thread sums whole tiles (their slots in order): a fixed order, no divisions
-    const double* pp = partial + ((int64_t)vs * n_tiles + t0) * kPartialSlots;
-    const int n = (int)nt;
-    for (int t = threadIdx.x; t < n; t += 256)
-      for (int q = 0; q < slots; ++q) s += pp[(int64_t)t * kPartialSlots + q];
-  }
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
-  }
+  const double* pp = partial + ((int64_t)vs * n_tiles + t0) * kPartialSlots;
+  const double n2 = canonical_sum(pp, mode != kReduceSweepNoNorm ? nt : 0, slots);
   if (threadIdx.x != 0) return;
-  const double n2 = sh[0];
   SysState S = st[vs];
   switch (mode) {
     case kReduceInit:
@@ -713,23 +772,7 @@ __device__ inline void reduce_one(const double* __restrict__ partial, int64_t n_
       break;
     case kReduceSweep:
     case kReduceSweepNoNorm:
-      if (!S.active) break;
-      if (S.pending) {
-        S.active = 0;
-        break;
-      }
-      S.sweeps += 1;
-      if (mode == kReduceSweep) {
-        S.last_n2 = n2;
-        if (n2 <= rtol2 * S.norm0sq) {
-          S.status = kOK;
-          S.pending = 1;
-        } else if (!isfinite(n2) || n2 > div2 * S.norm0sq) {
-          S.status = kDiverged;
-          S.pending = 1;
-        }
-      }
-      if (S.sweeps >= S.limit) S.pending = 1;
+      sweep_state(S, n2, mode, rtol2, div2);
       break;
     case kReduceFinal:
       S.last_n2 = n2;
@@ -1431,30 +1474,35 @@ int rb_slots(const SweepCfg& c, int n) {
 
 void launch_rb_pass(const SweepCfg& c, bool update, const DevPattern& p, const void* offd, const void* diag,
                     const void* dinv, int64_t dinv_stride, void* x, const void* b, int ns, const SysBatch& sb,
-                    const SysState* st, double* partial, int64_t t0, int64_t nt, hipStream_t s) {
+                    const SysState* st, double* partial, int64_t t0, int64_t nt, hipStream_t s,
+                    const FusedReduce* fused) {
   if (nt <= 0 || sb.n <= 0) return;
   int SW, P;
   rb_shape(c, sb.n, SW, P);
-  dim3 grid = tile_grid(nt, 1);
-  dim3 block(64 * SW);
+  const int wg = c.wave_groups ? 1 : 0;
+  FusedReduce fr;
+  if (!update && fused) fr = *fused;
+  dim3 grid = tile_grid(nt, wg ? SW : 1);
+  grid.x += (unsigned)fr.n;
+  dim3 block(wg ? 64 : 64 * SW);
 #define FNLH_RB_LAUNCH(SWV)                                                                                     \
   FNLH_DISPATCH_P(P, {                                                                                          \
     if (update && p.ent_phase)                                                                                  \
       hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, true, true, true>), grid, block, 0, s, p, (const TB*)offd,     \
-                         (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, st, partial, \
-                         t0, nt);                                                                               \
+                         (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, (SysState*)st, partial, \
+                         t0, nt, wg, fr);                                                                               \
     else if (update)                                                                                            \
       hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, true, true, false>), grid, block, 0, s, p, (const TB*)offd,    \
-                         (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, st, partial, \
-                         t0, nt);                                                                               \
+                         (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, (SysState*)st, partial, \
+                         t0, nt, wg, fr);                                                                               \
     else if (c.pivot)                                                                                           \
       hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, true, true>), grid, block, 0, s, p, (const TB*)offd,    \
-                         (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, st, partial, \
-                         t0, nt);                                                                               \
+                         (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, (SysState*)st, partial, \
+                         t0, nt, wg, fr);                                                                               \
     else                                                                                                        \
       hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, false, true>), grid, block, 0, s, p, (const TB*)offd,   \
-                         (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, st, partial, \
-                         t0, nt);                                                                               \
+                         (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, (SysState*)st, partial, \
+                         t0, nt, wg, fr);                                                                               \
   })
   FNLH_DISPATCH_STORE(c.storage, {
     using A = typename Fmt<TB>::A;

@@ -392,10 +392,12 @@ class Context:
         self._check(rc, allow_positive=True)
         return rc, hist[:int(n_steps)]
 
-    def tune(self, sys_per_lane=0, lanes_per_row=0):
-        """Set the sweep-kernel shape (0 = automatic)."""
+    def tune(self, sys_per_lane=0, lanes_per_row=0, wave_groups=None):
+        """Set the sweep-kernel shape (0 = automatic); wave_groups (0/1) when given."""
         self._check(LIB.fnlh_tune(self.h, 0, int(sys_per_lane)))
         self._check(LIB.fnlh_tune(self.h, 1, int(lanes_per_row)))
+        if wave_groups is not None:
+            self._check(LIB.fnlh_tune(self.h, 2, int(wave_groups)))
 
     def autotune(self, n_sys, sweeps=16, cache=None, stream=None):
         """Pick the sweep-kernel shape by timing (native autotuner).  ``cache``: path of a

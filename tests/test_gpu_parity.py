@@ -438,3 +438,22 @@ def test_every_general_path_shape_covers_all_systems(F):
                 for a, b in zip(ref, xs):
                     assert np.array_equal(a, b), (lpr, spw)
             c.close()
+
+
+@pytest.mark.parametrize("n_sys", [2, 4, 7])
+def test_wave_groups_bitwise(F, n_sys):
+    """One wave per workgroup (FNLH_TUNE_WAVE_GROUPS) changes only the dispatch of the
+    two-colour passes: the iterates are bitwise those of a tile per workgroup."""
+    m, Q, K = case(shape=(10, 7, 5), seed=13)
+    om = synth.omegas_single_zone(n_sys - 1)
+    bs = [synth.rhs(m.n_cells, s, real=(s == 0)) for s in range(n_sys)]
+    out = []
+    for wg in (0, 1):
+        c = _ctx(F, m, Q)
+        c.set_harmonics(om)
+        c.tune(0, 0, wave_groups=wg)
+        st, rep, xs = _solve(c, list(range(n_sys)), bs, kind="dilu", max_sweeps=15, rtol=0.0)
+        out.append(xs)
+        c.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)

@@ -12,6 +12,7 @@
 // (system, tile), then summed in a fixed order by one workgroup per system, so results
 // are bitwise reproducible run to run.
 #include <cfloat>
+#include <type_traits>
 
 #include "device.h"
 #include "kernels.h"
@@ -322,6 +323,17 @@ __device__ inline void fused_sweep_reduce(const FusedReduce& fr, const SysBatch&
   st[vs] = S;
 }
 
+// Both two-colour passes with FP32 blocks, four lanes per row and one system per lane
+// stage their diagonal and coupling blocks through LDS (float4 [2][9][16] per wave).
+template <typename TB, int SW, int P, bool UPDATE, bool PH> constexpr bool rb_lds_path() {
+  return std::is_same<TB, float>::value && SW == 4 && P == 1 && !PH;
+}
+constexpr int kRbLdsFloat4PerWave = 2 * 144;
+
+// Two coupling slots in flight in the single-system update pass (measured slower than the
+// fully unrolled six-coupling loop on hex tiles; kept for reference).
+constexpr bool kPipelineUpdate = false;
+
 // PH = false: no phase-lagged couplings (p.ent_phase is null), which lets the update pass
 // keep two coupling slots in flight without spilling.
 template <typename TB, int SW, int P, bool UPDATE, bool PIVOT, bool PH = true>
@@ -329,7 +341,7 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
                                const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                typename TV_of<TB>::T* __restrict__ x, const typename TV_of<TB>::T* __restrict__ b,
                                int ns, const SysBatch& sb, const SysState* __restrict__ st,
-                               double* __restrict__ partial, int64_t tile, int w) {
+                               double* __restrict__ partial, int64_t tile, int w, float4* lds = nullptr) {
   using A = typename TV_of<TB>::T;
   const int lane = threadIdx.x & 63;
   const int sidx = lane % SW;
@@ -362,8 +374,50 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
     for (int i = 0; i < 12; ++i) acc[j][i] = 0;
     if (run[j]) load_vec(b + rb + vs[j] * 12, acc[j]);
   }
+  // LDS staging (rb_lds_path): the wave's 16 rows share each block among their 4 lanes;
+  // the wave loads a slot's 16 x 144 bytes once (3 distinct 16-byte loads per lane) into
+  // its LDS buffer and every lane reads its row's block from there
+  const int rowbase = w * (kLanes / SW);
+  float4 pre[3];
+  auto gload = [&](const TB* base) {
+    const float4* src = reinterpret_cast<const float4*>(base);
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int t = lane + 64 * u;  // t = v * 16 + i: chunk v of row rowbase + i
+      if (t < 144) {
+        const nt_f4 dd = ld_stream(src + (t >> 4) * kLanes + rowbase + (t & 15));
+        pre[u] = make_float4(dd.x, dd.y, dd.z, dd.w);
+      }
+    }
+  };
+  auto lstore = [&](float4* buf) {
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int t = lane + 64 * u;
+      if (t < 144) buf[t] = pre[u];
+    }
+  };
+  auto lload = [&](const float4* buf, A(&k)[36]) {
+    const int ir = lane / SW;
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+      const float4 dd = buf[v * 16 + ir];
+      k[4 * v] = (A)dd.x;
+      k[4 * v + 1] = (A)dd.y;
+      k[4 * v + 2] = (A)dd.z;
+      k[4 * v + 3] = (A)dd.w;
+    }
+  };
   A d[36];
-  load_block(diag + tile * slot_elems<TB>(), rl, d);
+  if constexpr (rb_lds_path<TB, SW, P, UPDATE, PH>()) {
+    gload(diag + tile * slot_elems<TB>());
+    lstore(lds + 144);
+    __builtin_amdgcn_wave_barrier();
+    lload(lds + 144, d);
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    load_block(diag + tile * slot_elems<TB>(), rl, d);
+  }
   if (UPDATE) {
 #pragma unroll
     for (int j = 0; j < P; ++j) {
@@ -391,7 +445,26 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
         sub_kx(acc[j], kb, xn);
       }
     };
-    if constexpr (P == 1 && UPDATE && !PH) {
+    if constexpr (rb_lds_path<TB, SW, P, UPDATE, PH>()) {
+      // two buffers: slot q + 1 is loaded while slot q is applied
+      if (wd > 0) {
+        gload(offd + s0 * slot_elems<TB>());
+        lstore(lds);
+      }
+      for (int q = 0; q < wd; ++q) {
+        if (q + 1 < wd) gload(offd + (s0 + q + 1) * slot_elems<TB>());
+        const int64_t slot = s0 + q;
+        const int nb = p.ent_nbr[slot * kLanes + rl];
+        A xn[12];
+        if (run[0]) load_vec(x + (int64_t)nb * ns * 12 + vs[0] * 12, xn);
+        __builtin_amdgcn_wave_barrier();
+        A kb[36];
+        lload(lds + (q & 1) * 144, kb);
+        if (run[0]) sub_kx(acc[0], kb, xn);
+        __builtin_amdgcn_wave_barrier();
+        if (q + 1 < wd) lstore(lds + ((q + 1) & 1) * 144);
+      }
+    } else if constexpr (P == 1 && UPDATE && !PH && kPipelineUpdate) {
       // two slots in flight: slot q + 1's block and neighbour vector load while slot q
       // is applied (the loop otherwise drains all loads before the next slot's issue);
       // the first-colour pass keeps one slot, its solve needs the registers
@@ -450,7 +523,7 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
 // phase-lagged couplings fits four waves per SIMD without spilling (its two neighbour slots in flight otherwise
 // take it to three)
 template <typename TB, int SW, int P, bool UPDATE, bool PH> constexpr int rb_min_waves() {
-  return (UPDATE && !PH && SW == 4 && P == 1 && sizeof(TB) == 4) ? 4 : 1;
+  return (kPipelineUpdate && UPDATE && !PH && SW == 4 && P == 1 && sizeof(TB) == 4) ? 4 : 1;
 }
 
 template <typename TB, int SW, int P, bool UPDATE, bool PIVOT, bool PH>
@@ -477,7 +550,12 @@ __global__ void __launch_bounds__(256, (rb_min_waves<TB, SW, P, UPDATE, PH>())) 
   int grp;
   if (!map_tile_b(nt, wave_groups ? SW : 1, blk, tile, grp)) return;
   const int w = wave_groups ? grp : (int)(threadIdx.x >> 6);
-  rb_tile<TB, SW, P, UPDATE, PIVOT, PH>(p, offd, diag, dinv, dstride, x, b, ns, sb, st, partial, t0 + tile, w);
+  float4* lds = nullptr;
+  if constexpr (rb_lds_path<TB, SW, P, UPDATE, PH>()) {
+    extern __shared__ float4 rb_lds[];
+    lds = rb_lds + (threadIdx.x >> 6) * kRbLdsFloat4PerWave;
+  }
+  rb_tile<TB, SW, P, UPDATE, PIVOT, PH>(p, offd, diag, dinv, dstride, x, b, ns, sb, st, partial, t0 + tile, w, lds);
 }
 
 // Batched form: one launch over the concatenated (instance, tile) work list of many
@@ -1485,26 +1563,33 @@ void launch_rb_pass(const SweepCfg& c, bool update, const DevPattern& p, const v
   dim3 grid = tile_grid(nt, wg ? SW : 1);
   grid.x += (unsigned)fr.n;
   dim3 block(wg ? 64 : 64 * SW);
+  // LDS of the staged update pass (other instantiations do not touch it)
+  const bool ph = p.ent_phase != nullptr;
+  const unsigned lds_bytes = (!ph && c.storage == kF32 && SW == 4 && P == 1)
+                                 ? (unsigned)(block.x / 64) * kRbLdsFloat4PerWave * 16u
+                                 : 0u;
 #define FNLH_RB_LAUNCH(SWV)                                                                                     \
   FNLH_DISPATCH_P(P, {                                                                                          \
-    if (update && p.ent_phase)                                                                                  \
-      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, true, true, true>), grid, block, 0, s, p, (const TB*)offd,     \
-                         (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, (SysState*)st, partial, \
-                         t0, nt, wg, fr);                                                                               \
+    if (update && ph)                                                                                           \
+      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, true, true, true>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, \
+                         (SysState*)st, partial, t0, nt, wg, fr);                                                         \
     else if (update)                                                                                            \
-      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, true, true, false>), grid, block, 0, s, p, (const TB*)offd,    \
-                         (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, (SysState*)st, partial, \
-                         t0, nt, wg, fr);                                                                               \
+      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, true, true, false>), grid, block, lds_bytes, s, p, (const TB*)offd, (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, \
+                         (SysState*)st, partial, t0, nt, wg, fr);                                                \
+    else if (c.pivot && ph)                                                                                     \
+      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, true, true>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, \
+                         (SysState*)st, partial, t0, nt, wg, fr);                                                        \
     else if (c.pivot)                                                                                           \
-      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, true, true>), grid, block, 0, s, p, (const TB*)offd,    \
-                         (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, (SysState*)st, partial, \
-                         t0, nt, wg, fr);                                                                               \
+      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, true, false>), grid, block, lds_bytes, s, p, (const TB*)offd, (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, \
+                         (SysState*)st, partial, t0, nt, wg, fr);                                               \
+    else if (ph)                                                                                                \
+      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, false, true>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, \
+                         (SysState*)st, partial, t0, nt, wg, fr);                                                       \
     else                                                                                                        \
-      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, false, true>), grid, block, 0, s, p, (const TB*)offd,   \
-                         (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, (SysState*)st, partial, \
-                         t0, nt, wg, fr);                                                                               \
+      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, false, false>), grid, block, lds_bytes, s, p, (const TB*)offd, (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, \
+                         (SysState*)st, partial, t0, nt, wg, fr);                                              \
   })
-  FNLH_DISPATCH_STORE(c.storage, {
+FNLH_DISPATCH_STORE(c.storage, {
     using A = typename Fmt<TB>::A;
     if (SW == 1)
       FNLH_RB_LAUNCH(1);

@@ -330,12 +330,8 @@ template <typename TB, int SW, int P, bool UPDATE, bool PH> constexpr bool rb_ld
 }
 constexpr int kRbLdsFloat4PerWave = 2 * 144;
 
-// Two coupling slots in flight in the single-system update pass (measured slower than the
-// fully unrolled six-coupling loop on hex tiles; kept for reference).
-constexpr bool kPipelineUpdate = false;
-
-// PH = false: no phase-lagged couplings (p.ent_phase is null), which lets the update pass
-// keep two coupling slots in flight without spilling.
+// PH = false: no phase-lagged couplings (p.ent_phase is null); the FP32 four-lanes-per-row
+// passes then stage their blocks through LDS (rb_lds_path).
 template <typename TB, int SW, int P, bool UPDATE, bool PIVOT, bool PH = true>
 __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd, const TB* __restrict__ diag,
                                const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
@@ -464,25 +460,6 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
         __builtin_amdgcn_wave_barrier();
         if (q + 1 < wd) lstore(lds + ((q + 1) & 1) * 144);
       }
-    } else if constexpr (P == 1 && UPDATE && !PH && kPipelineUpdate) {
-      // two slots in flight: slot q + 1's block and neighbour vector load while slot q
-      // is applied (the loop otherwise drains all loads before the next slot's issue);
-      // the first-colour pass keeps one slot, its solve needs the registers
-      A kb0[36], kb1[36], xn0[12], xn1[12];
-      auto fetch = [&](int q, A(&kb)[36], A(&xn)[12]) {
-        const int64_t slot = s0 + q;
-        const int nb = p.ent_nbr[slot * kLanes + rl];
-        load_block(offd + slot * slot_elems<TB>(), rl, kb);
-        if (run[0]) load_vec(x + (int64_t)nb * ns * 12 + vs[0] * 12, xn);
-      };
-      if (wd > 0) fetch(0, kb0, xn0);
-      for (int q = 0; q < wd; q += 2) {
-        if (q + 1 < wd) fetch(q + 1, kb1, xn1);
-        if (run[0]) sub_kx(acc[0], kb0, xn0);
-        if (q + 1 >= wd) break;
-        if (q + 2 < wd) fetch(q + 2, kb0, xn0);
-        if (run[0]) sub_kx(acc[0], kb1, xn1);
-      }
     } else if (wd == 6) {
 #pragma unroll
       for (int q = 0; q < 6; ++q) body(q);
@@ -519,15 +496,9 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
   }
 }
 
-// the update pass with four lanes per row, one system per lane, FP32 blocks and no
-// phase-lagged couplings fits four waves per SIMD without spilling (its two neighbour slots in flight otherwise
-// take it to three)
-template <typename TB, int SW, int P, bool UPDATE, bool PH> constexpr int rb_min_waves() {
-  return (kPipelineUpdate && UPDATE && !PH && SW == 4 && P == 1 && sizeof(TB) == 4) ? 4 : 1;
-}
 
 template <typename TB, int SW, int P, bool UPDATE, bool PIVOT, bool PH>
-__global__ void __launch_bounds__(256, (rb_min_waves<TB, SW, P, UPDATE, PH>())) k_rb_pass(DevPattern p, const TB* __restrict__ offd,
+__global__ void __launch_bounds__(256) k_rb_pass(DevPattern p, const TB* __restrict__ offd,
                                                  const TB* __restrict__ diag,
                                                  const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                                  typename TV_of<TB>::T* __restrict__ x,

@@ -323,12 +323,60 @@ __device__ inline void fused_sweep_reduce(const FusedReduce& fr, const SysBatch&
   st[vs] = S;
 }
 
+// LDS staging of the FP32 blocks of one coupling slot for the R = 64 / SW rows of a wave
+// whose SW lanes share a row: the wave loads the slot's R x 144 bytes once (distinct
+// 16-byte loads, U per lane) into its LDS buffer, then every lane reads its row's block
+// from there (a broadcast among the row's lanes), instead of each lane fetching its row's
+// whole block.  Item t = v * R + i is 16-byte chunk v of row rowbase + i.
+template <int SW> struct BlockStage {
+  static constexpr int R = kLanes / SW;
+  static constexpr int N = 9 * R;            // float4 per slot
+  static constexpr int U = (N + 63) / 64;    // loads per lane
+  float4 pre[U];
+  // keep(i): whether row rowbase + i needs this slot's block (others are not fetched)
+  template <typename Keep> __device__ void gload(const float* base, int rowbase, int lane, Keep keep) {
+    const float4* src = reinterpret_cast<const float4*>(base);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = lane + 64 * u;
+      if (t < N && keep(t % R)) {
+        const nt_f4 d = ld_stream(src + (t / R) * kLanes + rowbase + (t % R));
+        pre[u] = make_float4(d.x, d.y, d.z, d.w);
+      }
+    }
+  }
+  __device__ void lstore(float4* buf, int lane) const {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = lane + 64 * u;
+      if (t < N) buf[t] = pre[u];
+    }
+  }
+  template <typename A> __device__ static void lload(const float4* buf, int ir, A (&k)[36]) {
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+      const float4 d = buf[v * R + ir];
+      k[4 * v] = (A)d.x;
+      k[4 * v + 1] = (A)d.y;
+      k[4 * v + 2] = (A)d.z;
+      k[4 * v + 3] = (A)d.w;
+    }
+  }
+};
+struct KeepAll {
+  __device__ bool operator()(int) const { return true; }
+};
+
+// The general-colouring passes with FP32 blocks and four lanes per row stage their
+// coupling blocks through LDS (float4 [2][9][16] per wave), for any systems per lane.
+template <typename TB, int SW> constexpr bool gen_lds_path() { return std::is_same<TB, float>::value && SW == 4; }
+
 // Both two-colour passes with FP32 blocks, four lanes per row and one system per lane
 // stage their diagonal and coupling blocks through LDS (float4 [2][9][16] per wave).
 template <typename TB, int SW, int P, bool UPDATE, bool PH> constexpr bool rb_lds_path() {
   return std::is_same<TB, float>::value && SW == 4 && P == 1 && !PH;
 }
-constexpr int kRbLdsFloat4PerWave = 2 * 144;
+constexpr int kRbLdsFloat4PerWave = 2 * BlockStage<4>::N;
 
 // PH = false: no phase-lagged couplings (p.ent_phase is null); the FP32 four-lanes-per-row
 // passes then stage their blocks through LDS (rb_lds_path).
@@ -370,46 +418,16 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
     for (int i = 0; i < 12; ++i) acc[j][i] = 0;
     if (run[j]) load_vec(b + rb + vs[j] * 12, acc[j]);
   }
-  // LDS staging (rb_lds_path): the wave's 16 rows share each block among their 4 lanes;
-  // the wave loads a slot's 16 x 144 bytes once (3 distinct 16-byte loads per lane) into
-  // its LDS buffer and every lane reads its row's block from there
+  // LDS staging of the blocks (rb_lds_path): see BlockStage
   const int rowbase = w * (kLanes / SW);
-  float4 pre[3];
-  auto gload = [&](const TB* base) {
-    const float4* src = reinterpret_cast<const float4*>(base);
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      const int t = lane + 64 * u;  // t = v * 16 + i: chunk v of row rowbase + i
-      if (t < 144) {
-        const nt_f4 dd = ld_stream(src + (t >> 4) * kLanes + rowbase + (t & 15));
-        pre[u] = make_float4(dd.x, dd.y, dd.z, dd.w);
-      }
-    }
-  };
-  auto lstore = [&](float4* buf) {
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      const int t = lane + 64 * u;
-      if (t < 144) buf[t] = pre[u];
-    }
-  };
-  auto lload = [&](const float4* buf, A(&k)[36]) {
-    const int ir = lane / SW;
-#pragma unroll
-    for (int v = 0; v < 9; ++v) {
-      const float4 dd = buf[v * 16 + ir];
-      k[4 * v] = (A)dd.x;
-      k[4 * v + 1] = (A)dd.y;
-      k[4 * v + 2] = (A)dd.z;
-      k[4 * v + 3] = (A)dd.w;
-    }
-  };
+  BlockStage<SW> stg;
+  constexpr int SN = BlockStage<SW>::N;
   A d[36];
   if constexpr (rb_lds_path<TB, SW, P, UPDATE, PH>()) {
-    gload(diag + tile * slot_elems<TB>());
-    lstore(lds + 144);
+    stg.gload((const float*)(diag + tile * slot_elems<TB>()), rowbase, lane, KeepAll());
+    stg.lstore(lds + SN, lane);
     __builtin_amdgcn_wave_barrier();
-    lload(lds + 144, d);
+    BlockStage<SW>::lload(lds + SN, lane / SW, d);
     __builtin_amdgcn_wave_barrier();
   } else {
     load_block(diag + tile * slot_elems<TB>(), rl, d);
@@ -444,21 +462,21 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
     if constexpr (rb_lds_path<TB, SW, P, UPDATE, PH>()) {
       // two buffers: slot q + 1 is loaded while slot q is applied
       if (wd > 0) {
-        gload(offd + s0 * slot_elems<TB>());
-        lstore(lds);
+        stg.gload((const float*)(offd + s0 * slot_elems<TB>()), rowbase, lane, KeepAll());
+        stg.lstore(lds, lane);
       }
       for (int q = 0; q < wd; ++q) {
-        if (q + 1 < wd) gload(offd + (s0 + q + 1) * slot_elems<TB>());
+        if (q + 1 < wd) stg.gload((const float*)(offd + (s0 + q + 1) * slot_elems<TB>()), rowbase, lane, KeepAll());
         const int64_t slot = s0 + q;
         const int nb = p.ent_nbr[slot * kLanes + rl];
         A xn[12];
         if (run[0]) load_vec(x + (int64_t)nb * ns * 12 + vs[0] * 12, xn);
         __builtin_amdgcn_wave_barrier();
         A kb[36];
-        lload(lds + (q & 1) * 144, kb);
+        BlockStage<SW>::lload(lds + (q & 1) * SN, lane / SW, kb);
         if (run[0]) sub_kx(acc[0], kb, xn);
         __builtin_amdgcn_wave_barrier();
-        if (q + 1 < wd) lstore(lds + ((q + 1) & 1) * 144);
+        if (q + 1 < wd) stg.lstore(lds + ((q + 1) & 1) * SN, lane);
       }
     } else if (wd == 6) {
 #pragma unroll
@@ -621,11 +639,7 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
   }
   const int wd = p.tile_width[tile];
   const int64_t s0 = p.tile_slot0[tile];
-  for (int q = 0; q < wd; ++q) {
-    const int64_t slot = s0 + q;
-    const int nb = p.ent_nbr[slot * kLanes + rl];
-    A kb[36];
-    load_block(offd + slot * slot_elems<TB>(), rl, kb);
+  auto body = [&](int64_t slot, int nb, const A(&kb)[36]) {
     const int64_t nbo = (int64_t)nb * ns * 12;
     const bool lower = nb < cstart;
 #pragma unroll
@@ -640,6 +654,37 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
         if (p.ent_phase) apply_phase(p, slot * kLanes + rl, W.orow[j], v);
         sub_kx(t[j], kb, v);
       }
+    }
+  };
+  if constexpr (gen_lds_path<TB, SW>()) {
+    // blocks staged through LDS (see BlockStage), two buffers
+    extern __shared__ float4 gen_lds[];
+    constexpr int SN = BlockStage<SW>::N;
+    float4* lds = gen_lds + w * 2 * SN;
+    const int rowbase = w * (kLanes / SW);
+    BlockStage<SW> stg;
+    if (wd > 0) {
+      stg.gload((const float*)(offd + s0 * slot_elems<TB>()), rowbase, lane, KeepAll());
+      stg.lstore(lds, lane);
+    }
+    for (int q = 0; q < wd; ++q) {
+      if (q + 1 < wd) stg.gload((const float*)(offd + (s0 + q + 1) * slot_elems<TB>()), rowbase, lane, KeepAll());
+      const int64_t slot = s0 + q;
+      const int nb = p.ent_nbr[slot * kLanes + rl];
+      __builtin_amdgcn_wave_barrier();
+      A kb[36];
+      BlockStage<SW>::lload(lds + (q & 1) * SN, lane / SW, kb);
+      body(slot, nb, kb);
+      __builtin_amdgcn_wave_barrier();
+      if (q + 1 < wd) stg.lstore(lds + ((q + 1) & 1) * SN, lane);
+    }
+  } else {
+    for (int q = 0; q < wd; ++q) {
+      const int64_t slot = s0 + q;
+      const int nb = p.ent_nbr[slot * kLanes + rl];
+      A kb[36];
+      load_block(offd + slot * slot_elems<TB>(), rl, kb);
+      body(slot, nb, kb);
     }
   }
 #pragma unroll
@@ -698,20 +743,53 @@ __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict_
     for (int i = 0; i < 12; ++i) t[j][i] = 0;
   const int wd = p.tile_width[tile];
   const int64_t s0 = p.tile_slot0[tile];
-  for (int q = 0; q < wd; ++q) {
-    const int64_t slot = s0 + q;
-    const int nb = p.ent_nbr[slot * kLanes + rl];
-    if (nb >= cend) {
-      A kb[36];
-      load_block(offd + slot * slot_elems<TB>(), rl, kb);
-      const int64_t nbo = (int64_t)nb * ns * 12;
+  auto body = [&](int64_t slot, int nb, const A(&kb)[36]) {
+    const int64_t nbo = (int64_t)nb * ns * 12;
 #pragma unroll
-      for (int j = 0; j < P; ++j) {
-        if (!W.run[j]) continue;
-        A v[12];
-        load_vec(y + nbo + W.vs[j] * 12, v);
-        if (p.ent_phase) apply_phase(p, slot * kLanes + rl, W.orow[j], v);
-        sub_kx(t[j], kb, v);
+    for (int j = 0; j < P; ++j) {
+      if (!W.run[j]) continue;
+      A v[12];
+      load_vec(y + nbo + W.vs[j] * 12, v);
+      if (p.ent_phase) apply_phase(p, slot * kLanes + rl, W.orow[j], v);
+      sub_kx(t[j], kb, v);
+    }
+  };
+  if constexpr (gen_lds_path<TB, SW>()) {
+    // blocks staged through LDS (see BlockStage), two buffers; only the rows whose
+    // coupling goes to a higher colour fetch theirs
+    extern __shared__ float4 gen_lds[];
+    constexpr int SN = BlockStage<SW>::N;
+    float4* lds = gen_lds + w * 2 * SN;
+    const int rowbase = w * (kLanes / SW);
+    BlockStage<SW> stg;
+    auto upper = [&](int64_t slot) {
+      return [=](int i) { return p.ent_nbr[slot * kLanes + rowbase + i] >= cend; };
+    };
+    if (wd > 0) {
+      stg.gload((const float*)(offd + s0 * slot_elems<TB>()), rowbase, lane, upper(s0));
+      stg.lstore(lds, lane);
+    }
+    for (int q = 0; q < wd; ++q) {
+      if (q + 1 < wd) stg.gload((const float*)(offd + (s0 + q + 1) * slot_elems<TB>()), rowbase, lane, upper(s0 + q + 1));
+      const int64_t slot = s0 + q;
+      const int nb = p.ent_nbr[slot * kLanes + rl];
+      __builtin_amdgcn_wave_barrier();
+      if (nb >= cend) {
+        A kb[36];
+        BlockStage<SW>::lload(lds + (q & 1) * SN, lane / SW, kb);
+        body(slot, nb, kb);
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (q + 1 < wd) stg.lstore(lds + ((q + 1) & 1) * SN, lane);
+    }
+  } else {
+    for (int q = 0; q < wd; ++q) {
+      const int64_t slot = s0 + q;
+      const int nb = p.ent_nbr[slot * kLanes + rl];
+      if (nb >= cend) {
+        A kb[36];
+        load_block(offd + slot * slot_elems<TB>(), rl, kb);
+        body(slot, nb, kb);
       }
     }
   }
@@ -1610,14 +1688,15 @@ void launch_fwd(const SweepCfg& c, bool last, const DevPattern& p, const void* o
   rb_shape(c, sb.n, SW, P);
   dim3 grid = tile_grid(nt, 1);
   dim3 block(64 * SW);
+  const unsigned lds_bytes = (c.storage == kF32 && SW == 4) ? (unsigned)SW * 2 * BlockStage<4>::N * 16u : 0u;
 #define FNLH_FWD_LAUNCH(SWV)                                                                                      \
   FNLH_DISPATCH_P(P, {                                                                                            \
     if (last)                                                                                                     \
-      hipLaunchKernelGGL((k_fwd<TB, SWV, PP, true>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag,      \
+      hipLaunchKernelGGL((k_fwd<TB, SWV, PP, true>), grid, block, lds_bytes, s, p, (const TB*)offd, (const TB*)diag,      \
                          (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, (A*)y, ns, sb, st, partial, t0, nt,     \
                          cstart);                                                                                 \
     else                                                                                                          \
-      hipLaunchKernelGGL((k_fwd<TB, SWV, PP, false>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag,     \
+      hipLaunchKernelGGL((k_fwd<TB, SWV, PP, false>), grid, block, lds_bytes, s, p, (const TB*)offd, (const TB*)diag,     \
                          (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, (A*)y, ns, sb, st, partial, t0, nt,     \
                          cstart);                                                                                 \
   })
@@ -1641,9 +1720,10 @@ void launch_bwd(const SweepCfg& c, const DevPattern& p, const void* offd, const 
   rb_shape(c, sb.n, SW, P);
   dim3 grid = tile_grid(nt, 1);
   dim3 block(64 * SW);
+  const unsigned lds_bytes = (c.storage == kF32 && SW == 4) ? (unsigned)SW * 2 * BlockStage<4>::N * 16u : 0u;
 #define FNLH_BWD_LAUNCH(SWV)                                                                                  \
   FNLH_DISPATCH_P(P, {                                                                                        \
-    hipLaunchKernelGGL((k_bwd<TB, SWV, PP>), grid, block, 0, s, p, (const TB*)offd, (const typename DF_of<TB>::T*)dinv, dinv_stride, \
+    hipLaunchKernelGGL((k_bwd<TB, SWV, PP>), grid, block, lds_bytes, s, p, (const TB*)offd, (const typename DF_of<TB>::T*)dinv, dinv_stride, \
                        (A*)x, (A*)y, ns, sb, st, t0, nt, cend);                                               \
   })
   FNLH_DISPATCH_STORE(c.storage, {

@@ -779,11 +779,18 @@ void batched_sweep(fnlh_batch B, int storage, bool first, double rtol, double di
   const WorkItem* w0 = (const WorkItem*)B->work0.p;
   const WorkItem* w1 = (const WorkItem*)B->work1.p;
   for (const BatchGroup& g : B->groups)
-    launch_rb_batched(storage, g.SW, g.P, true, d, w1 + g.w1_off, g.w1_n, s);
-  launch_reduce_batched(d, (const WorkItem*)B->items.p, B->n_items, first ? kReduceSweepNoNorm : kReduceSweep, rtol,
-                        divf, s);
-  for (const BatchGroup& g : B->groups)
-    launch_rb_batched(storage, g.SW, g.P, false, d, w0 + g.w0_off, g.w0_n, s);
+    launch_rb_batched(storage, g.SW, g.P, true, d, w1 + g.w1_off, g.w1_n, s, true);
+  // the update passes' norm reductions ride in the first first-colour launch
+  const int mode = first ? kReduceSweepNoNorm : kReduceSweep;
+  const WorkItem* red = (const WorkItem*)B->items.p;
+  bool reduced = false;
+  for (const BatchGroup& g : B->groups) {
+    const bool here = !reduced;
+    launch_rb_batched(storage, g.SW, g.P, false, d, w0 + g.w0_off, g.w0_n, s, true, here ? red : nullptr,
+                      here ? B->n_items : 0, mode, rtol, divf);
+    reduced = true;
+  }
+  if (!reduced) launch_reduce_batched(d, red, B->n_items, mode, rtol, divf, s);
 }
 
 // All systems of the batch to their stop criteria (states in B->st, initialised).  At
@@ -798,7 +805,7 @@ int batched_loop(fnlh_batch B, int storage, double rtol, double divf, int max_sw
   const InstDesc* d = (const InstDesc*)B->desc.p;
   const WorkItem* w0 = (const WorkItem*)B->work0.p;
   for (const BatchGroup& g : B->groups)
-    launch_rb_batched(storage, g.SW, g.P, false, d, w0 + g.w0_off, g.w0_n, s);
+    launch_rb_batched(storage, g.SW, g.P, false, d, w0 + g.w0_off, g.w0_n, s, true);
   int launched = 0;
   while (launched < limit) {
     bool graph = false;

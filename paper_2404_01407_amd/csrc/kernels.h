@@ -149,8 +149,13 @@ void launch_axpy_y(int storage, const DevPattern& p, void* x, const void* y, int
                    const SysState* st, hipStream_t s);
 
 // batched two-colour pass over a work list (instances grouped so SW, P are uniform)
+// Batched two-colour pass over the (instance, tile) work list of one shape group.
+// wave_groups: one wave per workgroup.  red (first-colour pass only): the reduction items
+// (instance, system) of the preceding update pass, done by the first n_red workgroups
+// (mode kReduceSweep / kReduceSweepNoNorm, squared tolerances).
 void launch_rb_batched(int storage, int SW, int P, bool update, const InstDesc* inst, const WorkItem* work,
-                       int64_t n_work, hipStream_t s);
+                       int64_t n_work, hipStream_t s, bool wave_groups = false, const WorkItem* red = nullptr,
+                       int n_red = 0, int red_mode = 0, double rtol = 0.0, double div_factor = 0.0);
 void launch_reduce_batched(const InstDesc* inst, const WorkItem* items, int n_items, int mode, double rtol,
                            double div_factor, hipStream_t s);
 

@@ -371,10 +371,10 @@ struct KeepAll {
 // coupling blocks through LDS (float4 [2][9][16] per wave), for any systems per lane.
 template <typename TB, int SW> constexpr bool gen_lds_path() { return std::is_same<TB, float>::value && SW == 4; }
 
-// Both two-colour passes with FP32 blocks, four lanes per row and one system per lane
-// stage their diagonal and coupling blocks through LDS (float4 [2][9][16] per wave).
+// Both two-colour passes with FP32 blocks and four lanes per row stage their diagonal and
+// coupling blocks through LDS (float4 [2][9][16] per wave).
 template <typename TB, int SW, int P, bool UPDATE, bool PH> constexpr bool rb_lds_path() {
-  return std::is_same<TB, float>::value && SW == 4 && P == 1 && !PH;
+  return std::is_same<TB, float>::value && SW == 4;
 }
 constexpr int kRbLdsFloat4PerWave = 2 * BlockStage<4>::N;
 
@@ -469,12 +469,29 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
         if (q + 1 < wd) stg.gload((const float*)(offd + (s0 + q + 1) * slot_elems<TB>()), rowbase, lane, KeepAll());
         const int64_t slot = s0 + q;
         const int nb = p.ent_nbr[slot * kLanes + rl];
-        A xn[12];
-        if (run[0]) load_vec(x + (int64_t)nb * ns * 12 + vs[0] * 12, xn);
-        __builtin_amdgcn_wave_barrier();
-        A kb[36];
-        BlockStage<SW>::lload(lds + (q & 1) * SN, lane / SW, kb);
-        if (run[0]) sub_kx(acc[0], kb, xn);
+        const A* xr = x + (int64_t)nb * ns * 12;
+        if constexpr (P == 1) {
+          // one system: its neighbour vector is fetched before the block is read back
+          A xn[12];
+          if (run[0]) load_vec(xr + vs[0] * 12, xn);
+          if (PH && run[0] && p.ent_phase) apply_phase(p, slot * kLanes + rl, orow[0], xn);
+          __builtin_amdgcn_wave_barrier();
+          A kb[36];
+          BlockStage<SW>::lload(lds + (q & 1) * SN, lane / SW, kb);
+          if (run[0]) sub_kx(acc[0], kb, xn);
+        } else {
+          __builtin_amdgcn_wave_barrier();
+          A kb[36];
+          BlockStage<SW>::lload(lds + (q & 1) * SN, lane / SW, kb);
+#pragma unroll
+          for (int j = 0; j < P; ++j) {
+            if (!run[j]) continue;
+            A xn[12];
+            load_vec(xr + vs[j] * 12, xn);
+            if (PH && p.ent_phase) apply_phase(p, slot * kLanes + rl, orow[j], xn);
+            sub_kx(acc[j], kb, xn);
+          }
+        }
         __builtin_amdgcn_wave_barrier();
         if (q + 1 < wd) stg.lstore(lds + ((q + 1) & 1) * SN, lane);
       }
@@ -551,22 +568,47 @@ __global__ void __launch_bounds__(256) k_rb_pass(DevPattern p, const TB* __restr
 // independent instances; each workgroup reads its instance's descriptor.
 template <typename TB, int SW, int P, bool UPDATE, bool PIVOT>
 __global__ void __launch_bounds__(256) k_rb_batched(const InstDesc* __restrict__ inst,
-                                                    const WorkItem* __restrict__ work, int64_t n_work) {
+                                                    const WorkItem* __restrict__ work, int64_t n_work,
+                                                    int wave_groups, const WorkItem* __restrict__ red, int n_red,
+                                                    int red_mode, double rtol2, double div2) {
   using A = typename TV_of<TB>::T;
+  int64_t blk = blockIdx.x;
+  if (!UPDATE && n_red > 0) {
+    // the preceding update pass's norm reductions, one (instance, system) per workgroup
+    if (blk < n_red) {
+      const WorkItem it = red[blk];
+      const InstDesc& D = inst[it.inst];
+      FusedReduce fr;
+      fr.n = 1;
+      fr.slots = D.slots;
+      fr.mode = red_mode;
+      fr.t0 = D.c1_t0;
+      fr.nt = D.c1_nt;
+      fr.rtol2 = rtol2;
+      fr.div2 = div2;
+      fused_sweep_reduce(fr, D.sb, D.partial, D.p.n_tiles, D.st, it.tile);
+      return;
+    }
+    blk -= n_red;
+  }
   int64_t k;
   int grp;
-  if (!map_tile(n_work, 1, k, grp)) return;
+  if (!map_tile_b(n_work, wave_groups ? SW : 1, blk, k, grp)) return;
+  const int w = wave_groups ? grp : (int)(threadIdx.x >> 6);
   const WorkItem wi = work[k];
   const InstDesc& D = inst[wi.inst];
   const bool pivot = D.pivot;
+  float4* lds = nullptr;
+  if constexpr (rb_lds_path<TB, SW, P, UPDATE, true>()) {
+    extern __shared__ float4 rbb_lds[];
+    lds = rbb_lds + (threadIdx.x >> 6) * kRbLdsFloat4PerWave;
+  }
   if (!UPDATE && !pivot)
     rb_tile<TB, SW, P, UPDATE, false>(D.p, (const TB*)D.offd, (const TB*)D.diag, (const typename DF_of<TB>::T*)D.dinv, D.dstride,
-                                      (A*)D.x, (const A*)D.b, D.ns, D.sb, D.st, D.partial, wi.tile,
-                                      (int)(threadIdx.x >> 6));
+                                      (A*)D.x, (const A*)D.b, D.ns, D.sb, D.st, D.partial, wi.tile, w, lds);
   else
     rb_tile<TB, SW, P, UPDATE, true>(D.p, (const TB*)D.offd, (const TB*)D.diag, (const typename DF_of<TB>::T*)D.dinv, D.dstride,
-                                     (A*)D.x, (const A*)D.b, D.ns, D.sb, D.st, D.partial, wi.tile,
-                                     (int)(threadIdx.x >> 6));
+                                     (A*)D.x, (const A*)D.b, D.ns, D.sb, D.st, D.partial, wi.tile, w, lds);
 }
 
 // Systems of one lane when SW lanes share a row: batch entries k = j * SW + sidx.
@@ -1614,25 +1656,25 @@ void launch_rb_pass(const SweepCfg& c, bool update, const DevPattern& p, const v
   dim3 block(wg ? 64 : 64 * SW);
   // LDS of the staged update pass (other instantiations do not touch it)
   const bool ph = p.ent_phase != nullptr;
-  const unsigned lds_bytes = (!ph && c.storage == kF32 && SW == 4 && P == 1)
+  const unsigned lds_bytes = (c.storage == kF32 && SW == 4)
                                  ? (unsigned)(block.x / 64) * kRbLdsFloat4PerWave * 16u
                                  : 0u;
 #define FNLH_RB_LAUNCH(SWV)                                                                                     \
   FNLH_DISPATCH_P(P, {                                                                                          \
     if (update && ph)                                                                                           \
-      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, true, true, true>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, \
+      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, true, true, true>), grid, block, lds_bytes, s, p, (const TB*)offd, (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, \
                          (SysState*)st, partial, t0, nt, wg, fr);                                                         \
     else if (update)                                                                                            \
       hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, true, true, false>), grid, block, lds_bytes, s, p, (const TB*)offd, (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, \
                          (SysState*)st, partial, t0, nt, wg, fr);                                                \
     else if (c.pivot && ph)                                                                                     \
-      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, true, true>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, \
+      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, true, true>), grid, block, lds_bytes, s, p, (const TB*)offd, (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, \
                          (SysState*)st, partial, t0, nt, wg, fr);                                                        \
     else if (c.pivot)                                                                                           \
       hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, true, false>), grid, block, lds_bytes, s, p, (const TB*)offd, (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, \
                          (SysState*)st, partial, t0, nt, wg, fr);                                               \
     else if (ph)                                                                                                \
-      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, false, true>), grid, block, 0, s, p, (const TB*)offd, (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, \
+      hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, false, true>), grid, block, lds_bytes, s, p, (const TB*)offd, (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, \
                          (SysState*)st, partial, t0, nt, wg, fr);                                                       \
     else                                                                                                        \
       hipLaunchKernelGGL((k_rb_pass<TB, SWV, PP, false, false, false>), grid, block, lds_bytes, s, p, (const TB*)offd, (const TB*)diag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, \
@@ -1651,16 +1693,25 @@ FNLH_DISPATCH_STORE(c.storage, {
 }
 
 void launch_rb_batched(int storage, int SW, int P, bool update, const InstDesc* inst, const WorkItem* work,
-                       int64_t n_work, hipStream_t s) {
-  if (n_work <= 0) return;
-  dim3 grid = tile_grid(n_work, 1);
-  dim3 block(64 * SW);
+                       int64_t n_work, hipStream_t s, bool wave_groups, const WorkItem* red, int n_red, int red_mode,
+                       double rtol, double div_factor) {
+  if (update) n_red = 0;
+  if (n_work <= 0 && n_red <= 0) return;
+  const int wg = wave_groups ? 1 : 0;
+  dim3 grid(n_work > 0 ? tile_grid(n_work, wg ? SW : 1).x : 0u);
+  grid.x += (unsigned)n_red;
+  dim3 block(wg ? 64 : 64 * SW);
+  const unsigned lds_bytes =
+      (storage == kF32 && SW == 4) ? (unsigned)(block.x / 64) * kRbLdsFloat4PerWave * 16u : 0u;
+  const double rtol2 = rtol * rtol, div2 = div_factor * div_factor;
 #define FNLH_RBB_LAUNCH(SWV)                                                                                   \
   FNLH_DISPATCH_P(P, {                                                                                         \
     if (update)                                                                                                \
-      hipLaunchKernelGGL((k_rb_batched<TB, SWV, PP, true, true>), grid, block, 0, s, inst, work, n_work);      \
+      hipLaunchKernelGGL((k_rb_batched<TB, SWV, PP, true, true>), grid, block, lds_bytes, s, inst, work, n_work,   \
+                         wg, red, n_red, red_mode, rtol2, div2);                                              \
     else                                                                                                       \
-      hipLaunchKernelGGL((k_rb_batched<TB, SWV, PP, false, true>), grid, block, 0, s, inst, work, n_work);     \
+      hipLaunchKernelGGL((k_rb_batched<TB, SWV, PP, false, true>), grid, block, lds_bytes, s, inst, work, n_work,  \
+                         wg, red, n_red, red_mode, rtol2, div2);                                              \
   })
   FNLH_DISPATCH_STORE(storage, {
     if (SW == 1)

@@ -323,43 +323,58 @@ __device__ inline void fused_sweep_reduce(const FusedReduce& fr, const SysBatch&
   st[vs] = S;
 }
 
-// LDS staging of the FP32 blocks of one coupling slot for the R = 64 / SW rows of a wave
-// whose SW lanes share a row: the wave loads the slot's R x 144 bytes once (distinct
-// 16-byte loads, U per lane) into its LDS buffer, then every lane reads its row's block
-// from there (a broadcast among the row's lanes), instead of each lane fetching its row's
-// whole block.  Item t = v * R + i is 16-byte chunk v of row rowbase + i.
-template <int SW> struct BlockStage {
+// LDS staging of the blocks of one coupling slot for the R = 64 / SW rows of a wave whose
+// SW lanes share a row: the wave loads the slot's R blocks once (distinct 16-byte chunks,
+// U per lane) into its LDS buffer, then every lane reads its row's block from there (a
+// broadcast among the row's lanes), instead of each lane fetching its row's whole block.
+// Item t = v * R + i is 16-byte chunk v of row rowbase + i (NV chunks per block: FP64 18,
+// FP32 9, BF16 5).
+template <typename TB, int SW> struct BlockStage {
   static constexpr int R = kLanes / SW;
-  static constexpr int N = 9 * R;            // float4 per slot
+  static constexpr int NV = Fmt<TB>::NV;
+  static constexpr int N = NV * R;           // chunks per slot
   static constexpr int U = (N + 63) / 64;    // loads per lane
-  float4 pre[U];
+  uint4 pre[U];
   // keep(i): whether row rowbase + i needs this slot's block (others are not fetched)
-  template <typename Keep> __device__ void gload(const float* base, int rowbase, int lane, Keep keep) {
-    const float4* src = reinterpret_cast<const float4*>(base);
+  template <typename Keep> __device__ void gload(const TB* base, int rowbase, int lane, Keep keep) {
+    const uint4* src = reinterpret_cast<const uint4*>(base);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int t = lane + 64 * u;
       if (t < N && keep(t % R)) {
-        const nt_f4 d = ld_stream(src + (t / R) * kLanes + rowbase + (t % R));
-        pre[u] = make_float4(d.x, d.y, d.z, d.w);
+        const nt_u4 d = ld_stream(src + (t / R) * kLanes + rowbase + (t % R));
+        pre[u] = make_uint4(d.x, d.y, d.z, d.w);
       }
     }
   }
-  __device__ void lstore(float4* buf, int lane) const {
+  __device__ void lstore(uint4* buf, int lane) const {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int t = lane + 64 * u;
       if (t < N) buf[t] = pre[u];
     }
   }
-  template <typename A> __device__ static void lload(const float4* buf, int ir, A (&k)[36]) {
+  template <typename A> __device__ static void lload(const uint4* buf, int ir, A (&k)[36]) {
 #pragma unroll
-    for (int v = 0; v < 9; ++v) {
-      const float4 d = buf[v * R + ir];
-      k[4 * v] = (A)d.x;
-      k[4 * v + 1] = (A)d.y;
-      k[4 * v + 2] = (A)d.z;
-      k[4 * v + 3] = (A)d.w;
+    for (int v = 0; v < NV; ++v) {
+      const uint4 d = buf[v * R + ir];
+      if constexpr (std::is_same<TB, double>::value) {
+        k[2 * v] = (A)__hiloint2double((int)d.y, (int)d.x);
+        k[2 * v + 1] = (A)__hiloint2double((int)d.w, (int)d.z);
+      } else if constexpr (std::is_same<TB, float>::value) {
+        k[4 * v] = (A)__uint_as_float(d.x);
+        k[4 * v + 1] = (A)__uint_as_float(d.y);
+        k[4 * v + 2] = (A)__uint_as_float(d.z);
+        k[4 * v + 3] = (A)__uint_as_float(d.w);
+      } else {
+        const uint32_t w[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const int q = 8 * v + 2 * h;
+          if (q < 36) k[q] = (A)__uint_as_float(w[h] << 16);
+          if (q + 1 < 36) k[q + 1] = (A)__uint_as_float(w[h] & 0xffff0000u);
+        }
+      }
     }
   }
 };
@@ -367,16 +382,18 @@ struct KeepAll {
   __device__ bool operator()(int) const { return true; }
 };
 
-// The general-colouring passes with FP32 blocks and four lanes per row stage their
-// coupling blocks through LDS (float4 [2][9][16] per wave), for any systems per lane.
-template <typename TB, int SW> constexpr bool gen_lds_path() { return std::is_same<TB, float>::value && SW == 4; }
+// The general-colouring passes with four lanes per row stage their coupling blocks through
+// LDS (two slot buffers of 16 blocks per wave), for any block precision and systems per lane.
+template <typename TB, int SW> constexpr bool gen_lds_path() { return SW == 4; }
 
-// Both two-colour passes with FP32 blocks and four lanes per row stage their diagonal and
-// coupling blocks through LDS (float4 [2][9][16] per wave).
-template <typename TB, int SW, int P, bool UPDATE, bool PH> constexpr bool rb_lds_path() {
-  return std::is_same<TB, float>::value && SW == 4;
+// Both two-colour passes with four lanes per row stage their diagonal and coupling blocks
+// through LDS (two slot buffers of 16 blocks per wave), for any block precision.
+template <typename TB, int SW, int P, bool UPDATE, bool PH> constexpr bool rb_lds_path() { return SW == 4; }
+// 16-byte LDS chunks per wave of the staged passes (four lanes per row, two slot buffers)
+constexpr int lds_chunks_per_wave(int storage) {
+  return 2 * (kLanes / 4) * (storage == kF64 ? Fmt<double>::NV : storage == kF32 ? Fmt<float>::NV : Fmt<bf16s>::NV);
 }
-constexpr int kRbLdsFloat4PerWave = 2 * BlockStage<4>::N;
+template <typename TB> constexpr int lds_chunks_per_wave_t() { return 2 * (kLanes / 4) * Fmt<TB>::NV; }
 
 // PH = false: no phase-lagged couplings (p.ent_phase is null); the FP32 four-lanes-per-row
 // passes then stage their blocks through LDS (rb_lds_path).
@@ -385,7 +402,7 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
                                const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                typename TV_of<TB>::T* __restrict__ x, const typename TV_of<TB>::T* __restrict__ b,
                                int ns, const SysBatch& sb, const SysState* __restrict__ st,
-                               double* __restrict__ partial, int64_t tile, int w, float4* lds = nullptr) {
+                               double* __restrict__ partial, int64_t tile, int w, uint4* lds = nullptr) {
   using A = typename TV_of<TB>::T;
   const int lane = threadIdx.x & 63;
   const int sidx = lane % SW;
@@ -420,14 +437,14 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
   }
   // LDS staging of the blocks (rb_lds_path): see BlockStage
   const int rowbase = w * (kLanes / SW);
-  BlockStage<SW> stg;
-  constexpr int SN = BlockStage<SW>::N;
+  BlockStage<TB, SW> stg;
+  constexpr int SN = BlockStage<TB, SW>::N;
   A d[36];
   if constexpr (rb_lds_path<TB, SW, P, UPDATE, PH>()) {
-    stg.gload((const float*)(diag + tile * slot_elems<TB>()), rowbase, lane, KeepAll());
+    stg.gload(diag + tile * slot_elems<TB>(), rowbase, lane, KeepAll());
     stg.lstore(lds + SN, lane);
     __builtin_amdgcn_wave_barrier();
-    BlockStage<SW>::lload(lds + SN, lane / SW, d);
+    BlockStage<TB, SW>::lload(lds + SN, lane / SW, d);
     __builtin_amdgcn_wave_barrier();
   } else {
     load_block(diag + tile * slot_elems<TB>(), rl, d);
@@ -462,11 +479,11 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
     if constexpr (rb_lds_path<TB, SW, P, UPDATE, PH>()) {
       // two buffers: slot q + 1 is loaded while slot q is applied
       if (wd > 0) {
-        stg.gload((const float*)(offd + s0 * slot_elems<TB>()), rowbase, lane, KeepAll());
+        stg.gload(offd + s0 * slot_elems<TB>(), rowbase, lane, KeepAll());
         stg.lstore(lds, lane);
       }
       for (int q = 0; q < wd; ++q) {
-        if (q + 1 < wd) stg.gload((const float*)(offd + (s0 + q + 1) * slot_elems<TB>()), rowbase, lane, KeepAll());
+        if (q + 1 < wd) stg.gload(offd + (s0 + q + 1) * slot_elems<TB>(), rowbase, lane, KeepAll());
         const int64_t slot = s0 + q;
         const int nb = p.ent_nbr[slot * kLanes + rl];
         const A* xr = x + (int64_t)nb * ns * 12;
@@ -477,12 +494,12 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
           if (PH && run[0] && p.ent_phase) apply_phase(p, slot * kLanes + rl, orow[0], xn);
           __builtin_amdgcn_wave_barrier();
           A kb[36];
-          BlockStage<SW>::lload(lds + (q & 1) * SN, lane / SW, kb);
+          BlockStage<TB, SW>::lload(lds + (q & 1) * SN, lane / SW, kb);
           if (run[0]) sub_kx(acc[0], kb, xn);
         } else {
           __builtin_amdgcn_wave_barrier();
           A kb[36];
-          BlockStage<SW>::lload(lds + (q & 1) * SN, lane / SW, kb);
+          BlockStage<TB, SW>::lload(lds + (q & 1) * SN, lane / SW, kb);
 #pragma unroll
           for (int j = 0; j < P; ++j) {
             if (!run[j]) continue;
@@ -556,10 +573,10 @@ __global__ void __launch_bounds__(256) k_rb_pass(DevPattern p, const TB* __restr
   int grp;
   if (!map_tile_b(nt, wave_groups ? SW : 1, blk, tile, grp)) return;
   const int w = wave_groups ? grp : (int)(threadIdx.x >> 6);
-  float4* lds = nullptr;
+  uint4* lds = nullptr;
   if constexpr (rb_lds_path<TB, SW, P, UPDATE, PH>()) {
-    extern __shared__ float4 rb_lds[];
-    lds = rb_lds + (threadIdx.x >> 6) * kRbLdsFloat4PerWave;
+    extern __shared__ uint4 rb_lds[];
+    lds = rb_lds + (threadIdx.x >> 6) * lds_chunks_per_wave_t<TB>();
   }
   rb_tile<TB, SW, P, UPDATE, PIVOT, PH>(p, offd, diag, dinv, dstride, x, b, ns, sb, st, partial, t0 + tile, w, lds);
 }
@@ -598,10 +615,10 @@ __global__ void __launch_bounds__(256) k_rb_batched(const InstDesc* __restrict__
   const WorkItem wi = work[k];
   const InstDesc& D = inst[wi.inst];
   const bool pivot = D.pivot;
-  float4* lds = nullptr;
+  uint4* lds = nullptr;
   if constexpr (rb_lds_path<TB, SW, P, UPDATE, true>()) {
-    extern __shared__ float4 rbb_lds[];
-    lds = rbb_lds + (threadIdx.x >> 6) * kRbLdsFloat4PerWave;
+    extern __shared__ uint4 rbb_lds[];
+    lds = rbb_lds + (threadIdx.x >> 6) * lds_chunks_per_wave_t<TB>();
   }
   if (!UPDATE && !pivot)
     rb_tile<TB, SW, P, UPDATE, false>(D.p, (const TB*)D.offd, (const TB*)D.diag, (const typename DF_of<TB>::T*)D.dinv, D.dstride,
@@ -700,22 +717,22 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
   };
   if constexpr (gen_lds_path<TB, SW>()) {
     // blocks staged through LDS (see BlockStage), two buffers
-    extern __shared__ float4 gen_lds[];
-    constexpr int SN = BlockStage<SW>::N;
-    float4* lds = gen_lds + w * 2 * SN;
+    extern __shared__ uint4 gen_lds[];
+    constexpr int SN = BlockStage<TB, SW>::N;
+    uint4* lds = gen_lds + w * 2 * SN;
     const int rowbase = w * (kLanes / SW);
-    BlockStage<SW> stg;
+    BlockStage<TB, SW> stg;
     if (wd > 0) {
-      stg.gload((const float*)(offd + s0 * slot_elems<TB>()), rowbase, lane, KeepAll());
+      stg.gload(offd + s0 * slot_elems<TB>(), rowbase, lane, KeepAll());
       stg.lstore(lds, lane);
     }
     for (int q = 0; q < wd; ++q) {
-      if (q + 1 < wd) stg.gload((const float*)(offd + (s0 + q + 1) * slot_elems<TB>()), rowbase, lane, KeepAll());
+      if (q + 1 < wd) stg.gload(offd + (s0 + q + 1) * slot_elems<TB>(), rowbase, lane, KeepAll());
       const int64_t slot = s0 + q;
       const int nb = p.ent_nbr[slot * kLanes + rl];
       __builtin_amdgcn_wave_barrier();
       A kb[36];
-      BlockStage<SW>::lload(lds + (q & 1) * SN, lane / SW, kb);
+      BlockStage<TB, SW>::lload(lds + (q & 1) * SN, lane / SW, kb);
       body(slot, nb, kb);
       __builtin_amdgcn_wave_barrier();
       if (q + 1 < wd) stg.lstore(lds + ((q + 1) & 1) * SN, lane);
@@ -799,26 +816,26 @@ __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict_
   if constexpr (gen_lds_path<TB, SW>()) {
     // blocks staged through LDS (see BlockStage), two buffers; only the rows whose
     // coupling goes to a higher colour fetch theirs
-    extern __shared__ float4 gen_lds[];
-    constexpr int SN = BlockStage<SW>::N;
-    float4* lds = gen_lds + w * 2 * SN;
+    extern __shared__ uint4 gen_lds[];
+    constexpr int SN = BlockStage<TB, SW>::N;
+    uint4* lds = gen_lds + w * 2 * SN;
     const int rowbase = w * (kLanes / SW);
-    BlockStage<SW> stg;
+    BlockStage<TB, SW> stg;
     auto upper = [&](int64_t slot) {
       return [=](int i) { return p.ent_nbr[slot * kLanes + rowbase + i] >= cend; };
     };
     if (wd > 0) {
-      stg.gload((const float*)(offd + s0 * slot_elems<TB>()), rowbase, lane, upper(s0));
+      stg.gload(offd + s0 * slot_elems<TB>(), rowbase, lane, upper(s0));
       stg.lstore(lds, lane);
     }
     for (int q = 0; q < wd; ++q) {
-      if (q + 1 < wd) stg.gload((const float*)(offd + (s0 + q + 1) * slot_elems<TB>()), rowbase, lane, upper(s0 + q + 1));
+      if (q + 1 < wd) stg.gload(offd + (s0 + q + 1) * slot_elems<TB>(), rowbase, lane, upper(s0 + q + 1));
       const int64_t slot = s0 + q;
       const int nb = p.ent_nbr[slot * kLanes + rl];
       __builtin_amdgcn_wave_barrier();
       if (nb >= cend) {
         A kb[36];
-        BlockStage<SW>::lload(lds + (q & 1) * SN, lane / SW, kb);
+        BlockStage<TB, SW>::lload(lds + (q & 1) * SN, lane / SW, kb);
         body(slot, nb, kb);
       }
       __builtin_amdgcn_wave_barrier();
@@ -1656,8 +1673,8 @@ void launch_rb_pass(const SweepCfg& c, bool update, const DevPattern& p, const v
   dim3 block(wg ? 64 : 64 * SW);
   // LDS of the staged update pass (other instantiations do not touch it)
   const bool ph = p.ent_phase != nullptr;
-  const unsigned lds_bytes = (c.storage == kF32 && SW == 4)
-                                 ? (unsigned)(block.x / 64) * kRbLdsFloat4PerWave * 16u
+  const unsigned lds_bytes = (SW == 4)
+                                 ? (unsigned)(block.x / 64) * lds_chunks_per_wave(c.storage) * 16u
                                  : 0u;
 #define FNLH_RB_LAUNCH(SWV)                                                                                     \
   FNLH_DISPATCH_P(P, {                                                                                          \
@@ -1702,7 +1719,7 @@ void launch_rb_batched(int storage, int SW, int P, bool update, const InstDesc* 
   grid.x += (unsigned)n_red;
   dim3 block(wg ? 64 : 64 * SW);
   const unsigned lds_bytes =
-      (storage == kF32 && SW == 4) ? (unsigned)(block.x / 64) * kRbLdsFloat4PerWave * 16u : 0u;
+      (SW == 4) ? (unsigned)(block.x / 64) * lds_chunks_per_wave(storage) * 16u : 0u;
   const double rtol2 = rtol * rtol, div2 = div_factor * div_factor;
 #define FNLH_RBB_LAUNCH(SWV)                                                                                   \
   FNLH_DISPATCH_P(P, {                                                                                         \
@@ -1739,7 +1756,7 @@ void launch_fwd(const SweepCfg& c, bool last, const DevPattern& p, const void* o
   rb_shape(c, sb.n, SW, P);
   dim3 grid = tile_grid(nt, 1);
   dim3 block(64 * SW);
-  const unsigned lds_bytes = (c.storage == kF32 && SW == 4) ? (unsigned)SW * 2 * BlockStage<4>::N * 16u : 0u;
+  const unsigned lds_bytes = (SW == 4) ? (unsigned)SW * lds_chunks_per_wave(c.storage) * 16u : 0u;
 #define FNLH_FWD_LAUNCH(SWV)                                                                                      \
   FNLH_DISPATCH_P(P, {                                                                                            \
     if (last)                                                                                                     \
@@ -1771,7 +1788,7 @@ void launch_bwd(const SweepCfg& c, const DevPattern& p, const void* offd, const 
   rb_shape(c, sb.n, SW, P);
   dim3 grid = tile_grid(nt, 1);
   dim3 block(64 * SW);
-  const unsigned lds_bytes = (c.storage == kF32 && SW == 4) ? (unsigned)SW * 2 * BlockStage<4>::N * 16u : 0u;
+  const unsigned lds_bytes = (SW == 4) ? (unsigned)SW * lds_chunks_per_wave(c.storage) * 16u : 0u;
 #define FNLH_BWD_LAUNCH(SWV)                                                                                  \
   FNLH_DISPATCH_P(P, {                                                                                        \
     hipLaunchKernelGGL((k_bwd<TB, SWV, PP>), grid, block, lds_bytes, s, p, (const TB*)offd, (const typename DF_of<TB>::T*)dinv, dinv_stride, \

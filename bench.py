@@ -648,6 +648,8 @@ def run_batch(args):
             tuned[k] = c.autotune(k, sweeps=16)
         c.tune(tuned[k]["sys_per_lane"], tuned[k]["lanes_per_row"])
     B = fnlh.Batch(ctxs)
+    if args.batch_loop_cells is not None:
+        B.set_loop_cells(args.batch_loop_cells)
 
     def batched():
         for row in xd:
@@ -753,7 +755,8 @@ def run_batch(args):
         "data": "synthetic",
         "config": {"workload": (f"{len(ctxs)} independent blade-row instances, {cells} cells, {n_sys_total} systems "
                                 "(mean + 1-8 harmonics each), DILU to a 1e-8 residual drop, batched + graph-replayed"),
-                   "instances": len(ctxs), "cells": cells, "systems": n_sys_total, "storage": args.storage},
+                   "instances": len(ctxs), "cells": cells, "systems": n_sys_total, "storage": args.storage,
+                   "loop_cells": 80000 if args.batch_loop_cells is None else args.batch_loop_cells},
         "time_to_1e-8_ms": round(1e3 * tb, 3),
         "per_instance_loop_ms": round(1e3 * tl, 3),
         "batched_speedup_vs_loop": round(tl / tb, 3),
@@ -801,6 +804,9 @@ def main():
     ap.add_argument("--learn-every", type=int, default=32, help="sweeps between learned corrections")
     ap.add_argument("--no-learned", action="store_true", help="skip the short learned-vs-plain comparison")
     ap.add_argument("--instances", type=int, default=64)
+    ap.add_argument("--batch-loop-cells", type=int, default=None,
+                    help="batch workload: instances of at least this many cells are iterated alone inside the "
+                         "batched call (0: all batched; default: the library's, 80k cells)")
     ap.add_argument("--total-cells", type=float, default=8.0e6)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")

@@ -256,6 +256,15 @@ int fnlh_batch_relax(fnlh_batch b, const int32_t* n_sys, const int32_t* const* s
                      const double* const* const* bvec, const fnlh_relax_opts* opts, fnlh_sys_report* rep,
                      void* stream);
 const char* fnlh_batch_last_error(fnlh_batch b);
+/* Batch scheduling: instances of at least loop_cells cells are iterated one after
+ * another (each with its own sweep loop, as fnlh_relax does) instead of in the shared
+ * launches; smaller instances stay batched.  An instance iterated alone keeps its blocks
+ * largely cache-resident (MI355X's 256 MB Infinity Cache) from one sweep to the next,
+ * while a batched sweep streams every instance through it; launch overhead favours
+ * batching only for small instances.  Default 80,000 cells; loop_cells <= 0: every
+ * eligible instance batched.  Results are the same either way (the batched and
+ * per-instance sweeps are bitwise equal). */
+int fnlh_batch_set_loop_cells(fnlh_batch b, int64_t loop_cells);
 
 /* Kernel timing of the sweep passes.  While enabled, every sweep-pass launch is
  * bracketed by HIP events on the caller's stream; durations and the algorithmic bytes

@@ -718,6 +718,9 @@ struct fnlh_batch_s {
   std::vector<WorkItem> all_w0, all_w1, all_items;
   std::vector<std::pair<int, int>> group_key;  // (SW, P) per group
   std::vector<int> inst_group, inst_base, inst_ns;  // per descriptor
+  // instances of at least this many cells are iterated alone (0: none); 80k cells (about
+  // 100 MB of FP32 blocks) measured best on the uneven 64-instance workload
+  int64_t loop_cells = 80000;
 };
 
 namespace {
@@ -1427,6 +1430,12 @@ int fnlh_batch_destroy(fnlh_batch b) {
 
 const char* fnlh_batch_last_error(fnlh_batch b) { return b ? b->err.c_str() : g_create_error.c_str(); }
 
+int fnlh_batch_set_loop_cells(fnlh_batch B, int64_t loop_cells) {
+  if (!B) return FNLH_E_ARG;
+  B->loop_cells = loop_cells > 0 ? loop_cells : 0;
+  return FNLH_OK;
+}
+
 int fnlh_batch_relax(fnlh_batch B, const int32_t* n_sys, const int32_t* const* sys, double* const* const* x,
                      const double* const* const* bvec, const fnlh_relax_opts* o, fnlh_sys_report* rep, void* stream) {
   if (!B) return FNLH_E_ARG;
@@ -1468,6 +1477,7 @@ int fnlh_batch_relax(fnlh_batch B, const int32_t* n_sys, const int32_t* const* s
       return rc;
     }
     if (plans[i].path != kPathRB || plans[i].G < n_sys[i]) continue;  // solved one by one below
+    if (B->loop_cells > 0 && c->L.N >= B->loop_cells) continue;      // iterated alone (cache-resident)
     SysBatch& sb = sbs[i];
     sb.n = n_sys[i];
     for (int k = 0; k < sb.n; ++k) {

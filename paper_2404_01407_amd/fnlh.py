@@ -118,6 +118,7 @@ def _load():
         "fnlh_batch_destroy": (I32, [P]),
         "fnlh_batch_relax": (I32, [P, V, V, V, V, C.POINTER(RelaxOpts), V, V]),
         "fnlh_batch_last_error": (C.c_char_p, [P]),
+        "fnlh_batch_set_loop_cells": (I32, [P, I64]),
         "fnlh_stats_get": (I32, [P, I32, C.POINTER(KernelStats)]),
         "fnlh_nn_create": (I32, [C.POINTER(P), P]),
         "fnlh_nn_destroy": (I32, [P]),
@@ -477,6 +478,13 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+    def set_loop_cells(self, loop_cells):
+        """Instances of at least loop_cells cells are iterated one after another inside
+        relax (cache-resident working set); smaller ones share the batched launches."""
+        rc = LIB.fnlh_batch_set_loop_cells(self.h, int(loop_cells))
+        if rc < 0:
+            raise FnlhError(rc, "batch: set_loop_cells")
 
     def relax(self, systems, xs, bs, kind="dilu", max_sweeps=500, rtol=1e-8, check_every=8, inner_sweeps=0,
               inner_rtol=0.0, div_factor=0.0, use_graph=True, learn_every=0, stream=None):

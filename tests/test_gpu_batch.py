@@ -126,3 +126,26 @@ def test_batch_learned_converges(F, storage):
         net.close()
     for (_, _, c, _, _) in insts:
         c.close()
+
+
+@pytest.mark.parametrize("loop_cells", [0, 300, 10**9])
+def test_batch_loop_cells_schedule(F, loop_cells):
+    """Instances at or above loop_cells are iterated alone inside the batched call, the
+    rest share the launches; every schedule gives the per-instance results bitwise."""
+    import torch
+    insts = _instances(F, "f32", SPECS[:5])
+    B = F.Batch([c for (_, _, c, _, _) in insts])
+    B.set_loop_cells(loop_cells)
+    systems = [list(range(len(bs))) for (_, _, _, _, bs) in insts]
+    xs = [[torch.zeros((m.n_cells, 6), dtype=torch.complex128, device="cuda") for _ in bs] for (m, _, _, _, bs) in insts]
+    bd = [[to_dev(b) for b in bs] for (_, _, _, _, bs) in insts]
+    st, reps = B.relax(systems, xs, bd, kind="dilu", max_sweeps=2000, rtol=1e-9, check_every=8, use_graph=True)
+    assert st == 0
+    for i, (m, Q, c, om, bs) in enumerate(insts):
+        xi = [torch.zeros((m.n_cells, 6), dtype=torch.complex128, device="cuda") for _ in bs]
+        c.relax(systems[i], xi, [to_dev(b) for b in bs], kind="dilu", max_sweeps=2000, rtol=1e-9, check_every=8)
+        for j in range(len(bs)):
+            assert np.array_equal(xs[i][j].cpu().numpy(), xi[j].cpu().numpy()), (loop_cells, i, j)
+    B.close()
+    for (_, _, c, _, _) in insts:
+        c.close()

@@ -665,14 +665,15 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
                                              const typename TV_of<TB>::T* __restrict__ b,
                                              typename TV_of<TB>::T* __restrict__ y, int ns, SysBatch sb,
                                              const SysState* __restrict__ st, double* __restrict__ partial,
-                                             int64_t t0, int64_t nt, int64_t cstart) {
+                                             int64_t t0, int64_t nt, int64_t cstart, int wave_groups) {
   using A = typename TV_of<TB>::T;
+  // a tile's SW waves in one workgroup, or (wave_groups) one workgroup per wave
   int64_t tile;
   int grp;
-  if (!map_tile(nt, 1, tile, grp)) return;
+  if (!map_tile(nt, wave_groups ? SW : 1, tile, grp)) return;
   tile += t0;
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
+  const int w = wave_groups ? grp : (int)(threadIdx.x >> 6);
   const int sidx = lane % SW;
   const int rl = w * (kLanes / SW) + lane / SW;
   WaveSys<P> W;
@@ -719,7 +720,7 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
     // blocks staged through LDS (see BlockStage), two buffers
     extern __shared__ uint4 gen_lds[];
     constexpr int SN = BlockStage<TB, SW>::N;
-    uint4* lds = gen_lds + w * 2 * SN;
+    uint4* lds = gen_lds + (threadIdx.x >> 6) * 2 * SN;  // this workgroup's wave slot
     const int rowbase = w * (kLanes / SW);
     BlockStage<TB, SW> stg;
     if (wd > 0) {
@@ -779,14 +780,15 @@ __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict_
                                              const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                              typename TV_of<TB>::T* __restrict__ x,
                                              typename TV_of<TB>::T* __restrict__ y, int ns, SysBatch sb,
-                                             const SysState* __restrict__ st, int64_t t0, int64_t nt, int64_t cend) {
+                                             const SysState* __restrict__ st, int64_t t0, int64_t nt, int64_t cend,
+                                             int wave_groups) {
   using A = typename TV_of<TB>::T;
   int64_t tile;
   int grp;
-  if (!map_tile(nt, 1, tile, grp)) return;
+  if (!map_tile(nt, wave_groups ? SW : 1, tile, grp)) return;
   tile += t0;
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
+  const int w = wave_groups ? grp : (int)(threadIdx.x >> 6);
   const int sidx = lane % SW;
   const int rl = w * (kLanes / SW) + lane / SW;
   WaveSys<P> W;
@@ -818,7 +820,7 @@ __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict_
     // coupling goes to a higher colour fetch theirs
     extern __shared__ uint4 gen_lds[];
     constexpr int SN = BlockStage<TB, SW>::N;
-    uint4* lds = gen_lds + w * 2 * SN;
+    uint4* lds = gen_lds + (threadIdx.x >> 6) * 2 * SN;  // this workgroup's wave slot
     const int rowbase = w * (kLanes / SW);
     BlockStage<TB, SW> stg;
     auto upper = [&](int64_t slot) {
@@ -1754,19 +1756,20 @@ void launch_fwd(const SweepCfg& c, bool last, const DevPattern& p, const void* o
   if (nt <= 0 || sb.n <= 0) return;
   int SW, P;
   rb_shape(c, sb.n, SW, P);
-  dim3 grid = tile_grid(nt, 1);
-  dim3 block(64 * SW);
-  const unsigned lds_bytes = (SW == 4) ? (unsigned)SW * lds_chunks_per_wave(c.storage) * 16u : 0u;
+  const int wg = c.wave_groups ? 1 : 0;
+  dim3 grid = tile_grid(nt, wg ? SW : 1);
+  dim3 block(wg ? 64 : 64 * SW);
+  const unsigned lds_bytes = (SW == 4) ? (unsigned)(block.x / 64) * lds_chunks_per_wave(c.storage) * 16u : 0u;
 #define FNLH_FWD_LAUNCH(SWV)                                                                                      \
   FNLH_DISPATCH_P(P, {                                                                                            \
     if (last)                                                                                                     \
       hipLaunchKernelGGL((k_fwd<TB, SWV, PP, true>), grid, block, lds_bytes, s, p, (const TB*)offd, (const TB*)diag,      \
                          (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, (A*)y, ns, sb, st, partial, t0, nt,     \
-                         cstart);                                                                                 \
+                         cstart, wg);                                                                                 \
     else                                                                                                          \
       hipLaunchKernelGGL((k_fwd<TB, SWV, PP, false>), grid, block, lds_bytes, s, p, (const TB*)offd, (const TB*)diag,     \
                          (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, (A*)y, ns, sb, st, partial, t0, nt,     \
-                         cstart);                                                                                 \
+                         cstart, wg);                                                                                 \
   })
   FNLH_DISPATCH_STORE(c.storage, {
     using A = typename Fmt<TB>::A;
@@ -1786,13 +1789,14 @@ void launch_bwd(const SweepCfg& c, const DevPattern& p, const void* offd, const 
   if (nt <= 0 || sb.n <= 0) return;
   int SW, P;
   rb_shape(c, sb.n, SW, P);
-  dim3 grid = tile_grid(nt, 1);
-  dim3 block(64 * SW);
-  const unsigned lds_bytes = (SW == 4) ? (unsigned)SW * lds_chunks_per_wave(c.storage) * 16u : 0u;
+  const int wg = c.wave_groups ? 1 : 0;
+  dim3 grid = tile_grid(nt, wg ? SW : 1);
+  dim3 block(wg ? 64 : 64 * SW);
+  const unsigned lds_bytes = (SW == 4) ? (unsigned)(block.x / 64) * lds_chunks_per_wave(c.storage) * 16u : 0u;
 #define FNLH_BWD_LAUNCH(SWV)                                                                                  \
   FNLH_DISPATCH_P(P, {                                                                                        \
     hipLaunchKernelGGL((k_bwd<TB, SWV, PP>), grid, block, lds_bytes, s, p, (const TB*)offd, (const typename DF_of<TB>::T*)dinv, dinv_stride, \
-                       (A*)x, (A*)y, ns, sb, st, t0, nt, cend);                                               \
+                       (A*)x, (A*)y, ns, sb, st, t0, nt, cend, wg);                                           \
   })
   FNLH_DISPATCH_STORE(c.storage, {
     using A = typename Fmt<TB>::A;

@@ -35,7 +35,7 @@ STATS_PERIOD = 4  # time the sweep-pass launches of every 4th sweep (bounds even
 # + WRITE_SIZE x 1.0, calibrated on a 1 GiB copy), for the kernel these sources build at the
 # default configuration (FP32 blocks, 4 systems, 4 lanes per row):
 # profiles/k_rb_pass_f32_200k_mean3h.md.  Reported only for that configuration.
-UPDATE_PASS_TRAFFIC = {("f32", 4): 230512313}
+UPDATE_PASS_TRAFFIC = {("f32", 4): 230542639}
 
 
 def build_inputs():

@@ -134,7 +134,8 @@ def cpu_baseline(mesh, Q, om, bs, colour, gpu_sweeps):
 def learned_compare(mesh, Q, om, bs, storage, n_pairs, train_steps, batch, learn_every, reps=3, lr=1e-3, seed=0):
     """Learned preconditioner against the plain sweep on the same systems: training pairs
     from the plain solver (b = 0, random start, m DILU sweeps: the iterate is minus its
-    error, its residual -K x), Adam on the GPU, then both solves to the 1e-8 drop."""
+    error, its residual -K x), Adam on the GPU, then both solves to the 1e-8 drop, as
+    Richardson sweeps and as FGMRES(10) with the plain and the learned preconditioner."""
     import numpy as np
     import torch
     from paper_2404_01407_amd import fnlh
@@ -192,10 +193,31 @@ def learned_compare(mesh, Q, om, bs, storage, n_pairs, train_steps, batch, learn
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     learned = solve("learned")
+
+    def fgmres(kind):
+        # FGMRES(10), one DILU sweep per preconditioner application, after the learned
+        # step for kind "learned" (the flexible method admits the nonlinear preconditioner)
+        times, rep = [], None
+        for _ in range(reps):
+            xs = [torch.zeros_like(b) for b in bd]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, rep = ctx.gmres(list(range(S)), xs, bd, kind=kind, restart=10, max_iters=2000, rtol=RTOL,
+                                use_graph=True)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            if st != 0:
+                raise RuntimeError(f"FGMRES {kind} did not converge: {rep}")
+        return {"ms": round(1e3 * float(np.median(times)), 3), "iters": [r["iters"] for r in rep],
+                "learned_steps": [r["learned"] for r in rep], "rel_res": [r["rel_res"] for r in rep]}
+
+    fg = {"dilu": fgmres("dilu"), "learned": fgmres("learned")}
+    fg["speedup_time"] = round(fg["dilu"]["ms"] / fg["learned"]["ms"], 3)
+    fg["iter_ratio"] = round(sum(fg["dilu"]["iters"]) / max(sum(fg["learned"]["iters"]), 1), 3)
     q = max(1, len(hist) // 10)
     out = {"storage": storage, "learn_every": learn_every, "plain": plain, "learned": learned,
            "speedup_time": round(plain["ms"] / learned["ms"], 3),
-           "sweep_ratio": round(sum(plain["sweeps"]) / max(sum(learned["sweeps"]), 1), 3),
+           "sweep_ratio": round(sum(plain["sweeps"]) / max(sum(learned["sweeps"]), 1), 3), "fgmres": fg,
            "training": {"pairs": n_pairs, "pair_sweeps": sweep_choices, "steps": train_steps, "batch": batch,
                         "lr": lr, "generate_s": round(t_gen, 2), "train_s": round(t_train, 2),
                         "ms_per_sample": round(1e3 * t_train / max(train_steps * batch, 1), 3),

@@ -322,14 +322,19 @@ int fnlh_autotune(fnlh_ctx c, int32_t n_sys, int32_t sweeps, fnlh_tune_result* o
  * the paper gives no Krylov algorithm, this is the textbook FGMRES(m) with right
  * preconditioning).  Per iteration j: z_j = M^-1 v_j, `inner_sweeps` preconditioned
  * Richardson sweeps from 0 (one sweep is exactly M^-1 of DILU, SGS or Jacobi; FP32/BF16
- * sweeps for reduced storage), w = (K + i omega V) z_j with the FP64 operator,
+ * sweeps for reduced storage).  FNLH_LEARNED makes M^-1 nonlinear, which the flexible
+ * method admits: z_j = alpha d + (inner DILU sweeps on K z = v_j - K alpha d from 0), d
+ * the attached network's correction for the residual v_j (fnlh_nn_create) and alpha the
+ * complex step minimising ||v_j - alpha K d||, the network part dropped (alpha = 0)
+ * where it is not finite or lowers ||v_j||^2 by less than 1e-3 of itself.  Then
+ * w = (K + i omega V) z_j with the FP64 operator,
  * orthogonalised against v_0..v_j by classical Gram-Schmidt with a second pass where
  * the norm falls below 1/sqrt(2) of its value (DGKS), Givens rotations on the host; x += Z y at the end of each cycle of `restart` iterations, and the next
  * cycle starts from the true residual.  Inner products sum conj(u) v over all 6N complex
  * entries.  Stop when the residual norm (the least-squares one within a cycle, the true
  * one at a restart) is <= rtol ||r0||, after max_iters iterations, or on breakdown. */
 typedef struct {
-  int32_t kind;          /* FNLH_DILU, FNLH_SGS or FNLH_JACOBI: the preconditioner M      */
+  int32_t kind;          /* FNLH_DILU, FNLH_SGS, FNLH_JACOBI or FNLH_LEARNED: M          */
   int32_t restart;       /* Krylov vectors per cycle, 1..256                               */
   int32_t max_iters;     /* total iterations (preconditioner applications) per system     */
   int32_t inner_sweeps;  /* sweeps per preconditioner application, >= 1                   */
@@ -338,7 +343,9 @@ typedef struct {
   int32_t pad_;
 } fnlh_gmres_opts;
 typedef struct {
-  int32_t iters, restarts, status, pad_;
+  int32_t iters, restarts, status;
+  int32_t learned;       /* FNLH_LEARNED: preconditioner applications that kept the
+                            network's correction (the others: iters - learned)             */
   double rel_res;        /* ||b - A x|| / ||b - A x0|| of the returned x (true residual, FP64) */
   double res0;           /* ||b - A x0||                                                     */
   double t_ms;           /* wall time of the call on the stream (all systems)               */
@@ -349,8 +356,10 @@ typedef struct {
  * NULL.  history: host [n][max_iters + 1] or NULL, the residual norm after each
  * iteration (index 0: ||r0||; least-squares norms within a cycle).  Device memory:
  * (2 restart + 2) vectors of 96 N n bytes besides the context's.  Frozen-turbulence and
- * phase-lagged systems are handled as in fnlh_relax.  Returns the worst status or an
- * error (FNLH_E_ARG on bad options or more systems than factor slots). */
+ * phase-lagged systems are handled as in fnlh_relax (FNLH_LEARNED takes no
+ * frozen-turbulence system).  Returns the worst status or an error (FNLH_E_ARG on bad
+ * options, a frozen system with FNLH_LEARNED, or more systems than factor slots;
+ * FNLH_E_ORDER for FNLH_LEARNED without a network with weights). */
 int fnlh_gmres(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, const double* const* b,
                const fnlh_gmres_opts* o, fnlh_gmres_report* rep, double* history, void* stream);
 

@@ -17,7 +17,11 @@ system of oracle.solve, (K + i omega V I) x = b, with right preconditioning:
   x = x0 + Z_k y_k at the end of the cycle (k the last j); restart from the true residual.
 
 M_j^-1 v: `inner_sweeps` steps of the preconditioned Richardson of oracle.solve from
-x = 0 (one step is exactly M^-1 v for the DILU, SGS or Jacobi M).  The inner products
+x = 0 (one step is exactly M^-1 v for the DILU, SGS or Jacobi M).  kind "LEARNED" (a
+project addition: the flexible method admits a nonlinear M_j): z0 = alpha d with d =
+net(v) the learned correction for the residual v and alpha from learned.line_step (0 when
+the step is rejected), then `inner_sweeps` DILU steps of the Richardson iteration on
+A z = v starting from z0.  The inner products
 are (u, v) = sum conj(u) v over all 6N complex entries; the stop test is
 ||r|| <= rtol ||r0|| on the least-squares residual norm, or iters = max_iters.
 """
@@ -25,7 +29,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import solve
+from . import learned, solve
 
 
 @dataclass
@@ -35,6 +39,7 @@ class KrylovInfo:
     rel_res: float
     history: list = field(default_factory=list)   # residual norm after each iteration (index 0: ||r0||)
     true_res: float = 0.0                          # ||b - A x|| of the returned x, relative
+    learned: int = 0                               # LEARNED: applications that kept the step
 
 
 def _lstsq_min(Hbar, beta):
@@ -46,18 +51,28 @@ def _lstsq_min(Hbar, beta):
 
 
 def fgmres(K, volume, zone, omega_row, b, colour, kind="DILU", x0=None, restart=20, rtol=1e-8, max_iters=1000,
-           inner_sweeps=1):
-    """Restarted flexible GMRES with the inner Richardson preconditioner.  Returns (x, KrylovInfo)."""
+           inner_sweeps=1, net=None):
+    """Restarted flexible GMRES with the inner Richardson preconditioner (kind LEARNED:
+    net(r) -> d gives the learned correction).  Returns (x, KrylovInfo)."""
     b = np.asarray(b, np.complex128)
     x = np.zeros_like(b) if x0 is None else np.asarray(x0, np.complex128).copy()
     Ds = solve.system_diag(K, volume, zone, omega_row)
+    if kind == "LEARNED" and net is None:
+        raise ValueError("kind LEARNED needs net")
+    kept = [0]
 
     def A(v):
         return solve.apply(K, Ds, v)
 
     def M_inv(v):
-        z, _ = solve.richardson(K, volume, zone, omega_row, v, colour, kind, rtol=0.0, max_sweeps=inner_sweeps,
-                                div_factor=np.inf)
+        z0, sweep_kind = None, kind
+        if kind == "LEARNED":
+            d = net(v)
+            alpha, _ = learned.line_step(A, v, d)
+            kept[0] += alpha != 0.0
+            z0, sweep_kind = alpha * d, "DILU"
+        z, _ = solve.richardson(K, volume, zone, omega_row, v, colour, sweep_kind, x0=z0, rtol=0.0,
+                                max_sweeps=inner_sweeps, div_factor=np.inf)
         return z
 
     r = b - A(x)
@@ -103,4 +118,4 @@ def fgmres(K, volume, zone, omega_row, b, colour, kind="DILU", x0=None, restart=
         if beta == 0.0:
             break
     true_rel = float(np.linalg.norm(b - A(x)) / n0) if n0 > 0 else 0.0
-    return x, KrylovInfo(status, iters, res / n0 if n0 > 0 else 0.0, hist, true_rel)
+    return x, KrylovInfo(status, iters, res / n0 if n0 > 0 else 0.0, hist, true_rel, kept[0])

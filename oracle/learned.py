@@ -57,6 +57,23 @@ def init_weights(seed=0):
     return pack(mats)
 
 
+def block_jacobi_weights():
+    """Weights for which the network's output is exactly the block-Jacobi correction
+    dx = (K_ii + i w V_i I)^-1 r_i: layer 1 and the layer-2 messages are switched off
+    (W1 = W3 = 0), W2 copies the z/sigma half of u into 12 hidden units and its negative
+    into 12 more, W4 passes those 24 on, and W5 takes the difference of each pair,
+    relu(t) - relu(-t) = t.  Every weight is 0 or +-1 (exact in any precision)."""
+    W = [np.zeros(s) for s in SHAPES]
+    for j in range(12):
+        W[1][12 + j, j] = 1.0
+        W[1][12 + j, 12 + j] = -1.0
+        W[4][j, j] = 1.0
+        W[4][12 + j, j] = -1.0
+    for j in range(24):
+        W[3][j, j] = 1.0
+    return pack(W)
+
+
 def c2r(v):
     """complex [N, 6] -> real [N, 12] as (re, im) pairs."""
     out = np.empty(v.shape[:-1] + (12,))
@@ -143,6 +160,25 @@ def apply(w, K, Ds, r):
     u, g, sigma = features(K, Ds, r)
     d, _ = forward(w, u, g, K.rows, K.cols, r.shape[0])
     return sigma * r2c(d)
+
+
+ACCEPT = 1e-3   # least fractional drop of ||r||^2 for which a learned step is kept
+
+
+def line_step(A, r, d, accept=ACCEPT):
+    """The learned correction d taken as a search direction for the residual r:
+    alpha = (y, r) / (y, y) with y = A d minimises ||r - alpha y|| over complex alpha,
+    and the squared residual falls by the fraction |(y, r)|^2 / (||y||^2 ||r||^2).  The
+    step is kept only if everything is finite and that fraction is >= accept; otherwise
+    alpha = 0.  (u, v) = sum conj(u) v.  Returns (alpha, fraction)."""
+    y = A(d)
+    yr = np.vdot(y, r)
+    yy = float(np.vdot(y, y).real)
+    rr = float(np.vdot(r, r).real)
+    gain = abs(yr) ** 2 / (yy * rr) if (yy > 0.0 and rr > 0.0) else 0.0
+    if not (np.isfinite(yr) and np.isfinite(yy)) or not gain >= accept:
+        return 0.0 + 0.0j, gain
+    return yr / yy, gain
 
 
 class Adam:

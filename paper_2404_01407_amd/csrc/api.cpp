@@ -1241,8 +1241,8 @@ namespace fnlh {
 int precond_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, const double* const* b, int kind,
                     int inner, bool use_graph, hipStream_t s, PrecondPlan& out) {
   if (!c) return FNLH_E_ARG;
-  if (kind != FNLH_DILU && kind != FNLH_SGS && kind != FNLH_JACOBI)
-    return set_err(c, FNLH_E_ARG, "preconditioner kind must be DILU, SGS or JACOBI");
+  if (kind != FNLH_DILU && kind != FNLH_SGS && kind != FNLH_JACOBI && kind != FNLH_LEARNED)
+    return set_err(c, FNLH_E_ARG, "preconditioner kind must be DILU, SGS, JACOBI or LEARNED");
   if (inner < 1) return set_err(c, FNLH_E_ARG, "inner sweeps >= 1");
   fnlh_relax_opts o{};
   o.kind = kind;
@@ -1267,6 +1267,7 @@ int precond_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x,
   out.inner = inner;
   out.reduced = P.reduced;
   out.use_graph = use_graph;
+  out.learned = P.learned;
   out.cfg = P.cfg;
   return FNLH_OK;
 }
@@ -1299,14 +1300,21 @@ int precond_apply(fnlh_ctx c, const PrecondPlan& pp, int ns, const SysBatch& sb,
   if (!pp.reduced) {
     launch_fill_zero(z, zb, s);
     launch_kstate(fb, st, 1.0, pp.inner, s);
+    // the learned step moves z off zero; the sweeps continue from there on K z = v
+    if (pp.learned && (rc = nn_learned_step(c, ns, fb, z, v, nullptr, st, s))) return rc;
     if ((rc = run(z, v))) return rc;
   } else {
     SysState* so = (SysState*)c->st_outer.p;
     launch_kstate(fb, so, 1.0, 1 << 30, s);
-    launch_to_f32(p, v, (float*)c->rhs32.p, (float*)c->d32.p, ns, fb, so, s);
+    launch_fill_zero(z, zb, s);
+    const double* rv = v;
+    if (pp.learned) {  // z = alpha d; the inner sweeps correct the FP64 residual v - K z
+      if ((rc = nn_learned_step(c, ns, fb, z, v, nullptr, so, s))) return rc;
+      rv = nn_step_residual(c);
+    }
+    launch_to_f32(p, rv, (float*)c->rhs32.p, (float*)c->d32.p, ns, fb, so, s);
     launch_inner_init(fb, so, st, pp.inner, s);
     if ((rc = run(c->d32.p, c->rhs32.p))) return rc;
-    launch_fill_zero(z, zb, s);
     launch_add_f32(p, z, (const float*)c->d32.p, ns, fb, so, s);
   }
   return check_launch(c, "preconditioner launch");

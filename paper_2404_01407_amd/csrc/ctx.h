@@ -155,6 +155,9 @@ int nn_relax_begin(fnlh_ctx c, int ns, hipStream_t s);
 int nn_learned_step(fnlh_ctx c, int ns, const SysBatch& sb, double* x, const double* b, double* r,
                     const SysState* st, hipStream_t s);
 int nn_relax_counts(fnlh_ctx c, int ns, int* host_counts, hipStream_t s);
+// the FP64 residual nn_learned_step computed (and updated) when called with r null:
+// [NP][ns][12], b - K x of the corrected x
+double* nn_step_residual(fnlh_ctx c);
 void nn_release(fnlh_ctx c);  // context destroyed: detach its network
 
 // Preconditioner access for the Krylov solve (api.cpp).  precond_prepare does what
@@ -164,9 +167,11 @@ void nn_release(fnlh_ctx c);  // context destroyed: detach its network
 // the systems of sb, M^-1 being `inner` preconditioned Richardson sweeps from z = 0 (one
 // sweep is exactly the DILU, SGS or Jacobi M^-1), in the storage precision (FP32/BF16
 // sweeps on the rounded v for reduced storage); v and z internal [NP][ns][12] FP64.
+// FNLH_LEARNED: z = alpha d from one learned step at z = 0 (nn_learned_step), then the
+// DILU sweeps on the remaining residual v - K z, added to z.
 struct PrecondPlan {
   int path = 0, fkind = 0, inner = 1;
-  bool reduced = false, use_graph = false;
+  bool reduced = false, use_graph = false, learned = false;
   SweepCfg cfg;
 };
 int precond_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, const double* const* b, int kind,

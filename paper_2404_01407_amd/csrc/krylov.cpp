@@ -7,7 +7,8 @@
 // and the operator products.
 //
 // Per iteration j (all systems of the cycle still running):
-//   z_j = M^-1 v_j (precond_apply: inner sweeps from 0), W = -(K + i omega V) z_j (the FP64
+//   z_j = M^-1 v_j (precond_apply: inner sweeps from 0, after a learned step for
+//   FNLH_LEARNED), W = -(K + i omega V) z_j (the FP64
 //   operator residual with b = 0), one classical Gram-Schmidt pass of W against v_0..v_j
 //   (one inner-product launch that also yields ||W||^2, one multi-axpy), a second pass
 //   only where the DGKS test asks for it, the Hessenberg column to the host, a complex
@@ -311,13 +312,15 @@ int fnlh_gmres(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, cons
   HIPC(c, hipEventSynchronize(e1), "event sync");
   float ms = 0.f;
   (void)hipEventElapsedTime(&ms, e0, e1);
+  std::vector<int> counts(2 * n, 0);
+  if (pp.learned && (rc = nn_relax_counts(c, n, counts.data(), s))) return rc;
   int worst = FNLH_OK;
   for (int k = 0; k < n; ++k) {
     if (rep) {
       rep[k].iters = iters[k];
       rep[k].restarts = restarts[k];
       rep[k].status = status[k];
-      rep[k].pad_ = 0;
+      rep[k].learned = counts[2 * k];
       rep[k].rel_res = n0[k] > 0.0 ? beta[k] / n0[k] : 0.0;
       rep[k].res0 = n0[k];
       rep[k].t_ms = ms;

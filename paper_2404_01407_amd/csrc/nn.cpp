@@ -204,6 +204,8 @@ int nn_learned_step(fnlh_ctx c, int ns, const SysBatch& sb, double* x, const dou
   return check_launch(c, "learned step launch");
 }
 
+double* nn_step_residual(fnlh_ctx c) { return (double*)c->nn->rr.p; }
+
 int nn_relax_counts(fnlh_ctx c, int ns, int* host_counts, hipStream_t s) {
   HIPC(c, hipMemcpyAsync(host_counts, c->nn->counts.p, (size_t)ns * 2 * sizeof(int), hipMemcpyDeviceToHost, s),
        "read counts");

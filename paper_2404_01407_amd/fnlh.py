@@ -66,7 +66,7 @@ class GmresOpts(C.Structure):
 
 
 class GmresReport(C.Structure):
-    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("status", C.c_int32), ("pad_", C.c_int32),
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("status", C.c_int32), ("learned", C.c_int32),
                 ("rel_res", C.c_double), ("res0", C.c_double), ("t_ms", C.c_double)]
 
     def as_dict(self):
@@ -312,8 +312,10 @@ class Context:
 
     def gmres(self, systems, xs, bs, kind="dilu", restart=20, max_iters=500, rtol=1e-8, inner_sweeps=1,
               use_graph=False, history=False, stream=None):
-        """Restarted flexible GMRES with the DILU/SGS/Jacobi preconditioner for up to 16
-        systems at once; xs (in: x0, out: x) and bs complex128 CUDA tensors [N, 6].
+        """Restarted flexible GMRES with the DILU/SGS/Jacobi preconditioner, or the
+        learned one (kind="learned": the attached Network's correction, then DILU sweeps),
+        for up to 16 systems at once; xs (in: x0, out: x) and bs complex128 CUDA tensors
+        [N, 6].
         Returns (status, reports) or, with history=True, (status, reports, histories) where
         histories[j] holds the residual norm after each iteration (index 0: ||r0||)."""
         n = len(systems)

@@ -3,11 +3,15 @@ iterates and residual histories in FP64 across restarts for DILU, SGS and Jacobi
 two-colour and general colouring paths (classical Gram-Schmidt twice on the device vs
 modified Gram-Schmidt in the oracle: equal up to rounding, 1e-9), several inner sweeps,
 convergence to the dense solution in FP64/FP32/BF16, frozen-turbulence and phase-lagged
-systems, systems stopping at different iterations, and the error paths."""
+systems, systems stopping at different iterations, and the error paths.  The learned
+kind: with the pass-through network (the block-Jacobi correction, exact weights) the
+device's first iterations follow the oracle's to BF16-activation accuracy; a random
+network's nonlinear preconditioner still reaches the dense solution; zero weights give
+the DILU method step for step."""
 import numpy as np
 import pytest
 
-from oracle import assemble, krylov, solve
+from oracle import assemble, krylov, learned, solve
 from paper_2404_01407_amd import synth
 
 from gpu_helpers import relerr, to_dev
@@ -155,9 +159,94 @@ def test_gmres_errors(F):
     with pytest.raises(F.FnlhError):
         c.gmres([1], [x], [b], inner_sweeps=0)
     with pytest.raises(F.FnlhError):
-        c.gmres([1], [x], [b], kind="learned")
+        c.gmres([1], [x], [b], kind="learned")           # no network attached
     with pytest.raises(F.FnlhError):
         c.gmres([5], [x], [b])
     with pytest.raises(F.FnlhError):
         c.gmres([0] * 17, [x] * 17, [b] * 17)
+    c.close()
+
+
+def _net(F, c, w):
+    net = F.Network(c)
+    net.set_weights(np.asarray(w, np.float32))
+    return net
+
+
+def _random_weights(seed):
+    w = learned.init_weights(seed)
+    w[-64 * 12:] *= 10.0          # full-scale decoder
+    return w
+
+
+@pytest.mark.parametrize("mesh", ["passage", "cascade"])
+def test_gmres_learned_matches_oracle(F, mesh):
+    m, Q, K = _case(mesh)
+    c = _ctx(F, m, Q)
+    wj = learned.block_jacobi_weights()
+    net = _net(F, c, wj)
+    col, _ = c.ordering()
+    bs = [synth.rhs(m.n_cells, 50 + s, real=(s == 0)) for s in range(3)]
+    kw = dict(restart=10, rtol=0.0, max_iters=4)
+    st, rep, hist, xs = _gmres(c, [0, 1, 2], bs, kind="learned", **kw)
+    for s in range(3):
+        Ds = solve.system_diag(K, m.volume, m.zone, OMEGA[s])
+        x_or, info = krylov.fgmres(K, m.volume, m.zone, OMEGA[s], bs[s], col, "LEARNED",
+                                   net=lambda r: learned.apply(wj, K, Ds, r), **kw)
+        _, plain = krylov.fgmres(K, m.volume, m.zone, OMEGA[s], bs[s], col, "DILU", **kw)
+        assert rep[s]["learned"] == info.learned == 4, (s, rep[s], info.learned)
+        np.testing.assert_allclose(hist[s], info.history, rtol=1e-2)
+        assert relerr(xs[s], x_or) <= 1e-2, (mesh, s, relerr(xs[s], x_or))
+        # the learned part moves the first residual well beyond that tolerance
+        assert abs(info.history[1] - plain.history[1]) >= 0.1 * plain.history[1]
+    net.close()
+    c.close()
+
+
+@pytest.mark.parametrize("mesh,storage", [("passage", "f64"), ("passage", "f32"), ("cascade", "f32"),
+                                          ("passage", "bf16")])
+def test_gmres_learned_converges_to_dense(F, mesh, storage):
+    m, Q, K = _case(mesh, seed=5)
+    c = _ctx(F, m, Q, storage=storage)
+    net = _net(F, c, _random_weights(11))
+    bs = [synth.rhs(m.n_cells, 60 + s, real=(s == 0)) for s in range(3)]
+    st, rep, hist, xs = _gmres(c, [0, 1, 2], bs, kind="learned", restart=10, max_iters=400, rtol=1e-11)
+    assert st == F.OK, rep
+    for s in range(3):
+        assert rep[s]["rel_res"] <= 1e-11
+        assert 0 <= rep[s]["learned"] <= rep[s]["iters"]
+        assert relerr(xs[s], solve.dense_solve(K, m.volume, m.zone, OMEGA[s], bs[s])) <= 1e-9, (storage, s)
+    net.close()
+    c.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_gmres_learned_zero_weights_is_dilu(F, storage):
+    m, Q, K = _case("passage", seed=7)
+    c = _ctx(F, m, Q, storage=storage)
+    net = _net(F, c, np.zeros(F.NN_PARAMS))
+    bs = [synth.rhs(m.n_cells, 70 + s, real=(s == 0)) for s in range(3)]
+    kw = dict(restart=6, rtol=0.0, max_iters=14, inner_sweeps=2)
+    _, r0, h0, x0 = _gmres(c, [0, 1, 2], bs, kind="dilu", **kw)
+    _, r1, h1, x1 = _gmres(c, [0, 1, 2], bs, kind="learned", **kw)
+    for s in range(3):
+        assert r1[s]["learned"] == 0 and r1[s]["iters"] == r0[s]["iters"] == 14
+        np.testing.assert_allclose(h1[s], h0[s], rtol=1e-12)
+        assert relerr(x1[s], x0[s]) <= 1e-12
+    net.close()
+    c.close()
+
+
+def test_gmres_learned_refuses_frozen_systems(F):
+    m, Q, K = _case("passage")
+    c = _ctx(F, m, Q)
+    net = _net(F, c, _random_weights(12))
+    c.set_frozen_turbulence([0, 0, 1])
+    b = synth.rhs(m.n_cells, 80)
+    with pytest.raises(F.FnlhError):
+        _gmres(c, [2], [b], kind="learned", restart=5, max_iters=10, rtol=1e-8)
+    st, rep, hist, (x,) = _gmres(c, [1], [b], kind="learned", restart=10, max_iters=400, rtol=1e-11)
+    assert st == F.OK
+    assert relerr(x, solve.dense_solve(K, m.volume, m.zone, OMEGA[1], b)) <= 1e-9
+    net.close()
     c.close()

@@ -2,11 +2,14 @@
 is the minimum over the preconditioned Krylov space built by brute force from its power
 basis; full GMRES on a tiny mesh reaches the dense solution; one iteration suffices when
 the preconditioner is the exact inverse; the residual history never rises within a
-cycle and ends at the true residual; restarted runs converge to the dense solution."""
+cycle and ends at the true residual; restarted runs converge to the dense solution.
+Learned kind: an exact network converges in one iteration, a zero network is the DILU
+method step for step, and the nonlinear preconditioner of a random network still reaches
+the dense solution (flexible GMRES)."""
 import numpy as np
 import pytest
 
-from oracle import assemble, krylov, ordering, solve
+from oracle import assemble, krylov, learned, ordering, solve
 from paper_2404_01407_amd import synth
 
 
@@ -94,3 +97,39 @@ def test_more_inner_sweeps_fewer_iterations():
     _, i3 = krylov.fgmres(K, m.volume, m.zone, om, b, col, "DILU", restart=10, rtol=1e-10, inner_sweeps=3)
     assert i1.status == solve.OK and i3.status == solve.OK
     assert i3.iters < i1.iters
+
+
+def test_learned_exact_network_converges_in_one_iteration():
+    m, K, col = _setup()
+    om = np.array([36.0])
+    b = _b(m.n_cells, 8)
+    net = lambda r: solve.dense_solve(K, m.volume, m.zone, om, r)
+    x, info = krylov.fgmres(K, m.volume, m.zone, om, b, col, "LEARNED", restart=5, rtol=1e-12, net=net)
+    assert info.status == solve.OK and info.iters == 1 and info.learned == 1
+    xd = solve.dense_solve(K, m.volume, m.zone, om, b)
+    assert np.linalg.norm(x - xd) <= 1e-12 * np.linalg.norm(xd)
+
+
+def test_learned_zero_network_is_dilu():
+    m, K, col = _setup()
+    om = np.array([18.0])
+    b = _b(m.n_cells, 9)
+    kw = dict(restart=6, rtol=0.0, max_iters=14, inner_sweeps=2)
+    x0, i0 = krylov.fgmres(K, m.volume, m.zone, om, b, col, "DILU", **kw)
+    x1, i1 = krylov.fgmres(K, m.volume, m.zone, om, b, col, "LEARNED", net=np.zeros_like, **kw)
+    assert i1.learned == 0
+    assert np.array_equal(x0, x1) and i0.history == i1.history
+
+
+def test_learned_random_network_reaches_dense_solution():
+    m, K, col = _setup()
+    om = np.array([18.0])
+    b = _b(m.n_cells, 10)
+    Ds = solve.system_diag(K, m.volume, m.zone, om)
+    w = learned.init_weights(11)
+    w[-64 * 12:] *= 10.0
+    x, info = krylov.fgmres(K, m.volume, m.zone, om, b, col, "LEARNED", restart=10, rtol=1e-11, max_iters=400,
+                            net=lambda r: learned.apply(w, K, Ds, r))
+    assert info.status == solve.OK and info.learned >= 1
+    xd = solve.dense_solve(K, m.volume, m.zone, om, b)
+    assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)

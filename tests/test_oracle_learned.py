@@ -1,6 +1,9 @@
 """Pins of the learned-preconditioner reference (no GPU): finite differences of the
-loss, positive homogeneity, relabelling equivariance, the two-hop receptive field and a
-hand-worked first Adam step."""
+loss, positive homogeneity, relabelling equivariance, the two-hop receptive field, a
+hand-worked first Adam step, the pass-through weights that make the network the
+block-Jacobi correction (closed form), and the line step along a correction: exact
+directions give the inverse scale, orthogonal ones nothing, the acceptance threshold
+on directions of known gain, non-finite directions rejected."""
 import numpy as np
 import pytest
 
@@ -113,3 +116,42 @@ def test_adam_first_step_closed_form():
     w1 = opt.step(w0, g)
     np.testing.assert_allclose(w1, w0 - 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-15)
     np.testing.assert_allclose(w1[:2], [0.99, 2.01], rtol=1e-9)
+
+
+def test_block_jacobi_weights_give_the_diagonal_solve(small):
+    m, K, Ds, r, e = small
+    d = learned.apply(learned.block_jacobi_weights(), K, Ds, r)
+    z = np.array([np.linalg.solve(Ds[i], r[i]) for i in range(m.n_cells)])      # per-cell 6x6 solves
+    assert np.linalg.norm(d - z) <= 1e-13 * np.linalg.norm(z)
+
+
+def _orth(rng, r):
+    """A random vector orthogonal to r, scaled to ||r||."""
+    q = rng.standard_normal(r.shape) + 1j * rng.standard_normal(r.shape)
+    q = q - (np.vdot(r, q) / np.vdot(r, r)) * r
+    return q * (np.linalg.norm(r) / np.linalg.norm(q))
+
+
+def test_line_step_closed_forms(small):
+    m, K, Ds, r, e = small
+    A = lambda v: solve.apply(K, Ds, v)
+    Ainv = lambda v: solve.dense_solve(K, m.volume, m.zone, np.array([18.0]), v)
+    rng = np.random.default_rng(4)
+    c = 2.0 - 3.0j
+    alpha, gain = learned.line_step(A, r, c * Ainv(r))             # exact direction, scaled
+    assert abs(alpha - 1.0 / c) <= 1e-10 * abs(1.0 / c) and abs(gain - 1.0) <= 1e-10
+    q = _orth(rng, r)
+    alpha, gain = learned.line_step(A, r, Ainv(q))                  # A d orthogonal to r
+    assert alpha == 0.0 and gain <= 1e-20
+    # A d = r + t q with q orthogonal to r, ||q|| = ||r||: gain 1 / (1 + t^2), alpha = gain
+    for target, kept in ((2e-3, True), (0.5e-3, False)):
+        t = np.sqrt(1.0 / target - 1.0)
+        alpha, gain = learned.line_step(A, r, Ainv(r + t * q))
+        assert abs(gain - target) <= 1e-8 * target
+        assert (alpha != 0.0) == kept
+        if kept:
+            assert abs(alpha - target) <= 1e-8 * target
+    bad = Ainv(r)
+    bad[3, 2] = np.nan
+    assert learned.line_step(A, r, bad)[0] == 0.0
+    assert learned.line_step(A, r, np.zeros_like(r))[0] == 0.0

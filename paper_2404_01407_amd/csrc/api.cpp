@@ -1300,8 +1300,12 @@ int precond_apply(fnlh_ctx c, const PrecondPlan& pp, int ns, const SysBatch& sb,
   if (!pp.reduced) {
     launch_fill_zero(z, zb, s);
     launch_kstate(fb, st, 1.0, pp.inner, s);
-    // the learned step moves z off zero; the sweeps continue from there on K z = v
-    if (pp.learned && (rc = nn_learned_step(c, ns, fb, z, v, nullptr, st, s))) return rc;
+    // the learned step moves z off zero (its residual there is v itself); the sweeps
+    // continue from there on K z = v
+    if (pp.learned) {
+      HIPC(c, hipMemcpyAsync(nn_step_residual(c), v, zb, hipMemcpyDeviceToDevice, s), "learned residual");
+      if ((rc = nn_learned_step(c, ns, fb, z, v, nn_step_residual(c), st, s))) return rc;
+    }
     if ((rc = run(z, v))) return rc;
   } else {
     SysState* so = (SysState*)c->st_outer.p;
@@ -1309,8 +1313,9 @@ int precond_apply(fnlh_ctx c, const PrecondPlan& pp, int ns, const SysBatch& sb,
     launch_fill_zero(z, zb, s);
     const double* rv = v;
     if (pp.learned) {  // z = alpha d; the inner sweeps correct the FP64 residual v - K z
-      if ((rc = nn_learned_step(c, ns, fb, z, v, nullptr, so, s))) return rc;
       rv = nn_step_residual(c);
+      HIPC(c, hipMemcpyAsync((void*)rv, v, zb, hipMemcpyDeviceToDevice, s), "learned residual");
+      if ((rc = nn_learned_step(c, ns, fb, z, v, (double*)rv, so, s))) return rc;
     }
     launch_to_f32(p, rv, (float*)c->rhs32.p, (float*)c->d32.p, ns, fb, so, s);
     launch_inner_init(fb, so, st, pp.inner, s);

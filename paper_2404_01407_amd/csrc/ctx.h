@@ -155,8 +155,9 @@ int nn_relax_begin(fnlh_ctx c, int ns, hipStream_t s);
 int nn_learned_step(fnlh_ctx c, int ns, const SysBatch& sb, double* x, const double* b, double* r,
                     const SysState* st, hipStream_t s);
 int nn_relax_counts(fnlh_ctx c, int ns, int* host_counts, hipStream_t s);
-// the FP64 residual nn_learned_step computed (and updated) when called with r null:
-// [NP][ns][12], b - K x of the corrected x
+// the learned step's residual scratch, [NP][ns][12] FP64: where nn_learned_step is
+// called with r null it computes b - K x there, and either way it leaves b - K x of the
+// corrected x in the r it was given
 double* nn_step_residual(fnlh_ctx c);
 void nn_release(fnlh_ctx c);  // context destroyed: detach its network
 

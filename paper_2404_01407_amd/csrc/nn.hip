@@ -86,6 +86,22 @@ __device__ inline void copy_lds(uint16_t* dst, const uint16_t* src, int n) {
   for (int i = threadIdx.x; i < n / 8; i += blockDim.x) ((uint4*)dst)[i] = ((const uint4*)src)[i];
 }
 
+// LDS row strides (uint16) of the 32-, 64-, 96- and 128-wide tiles: 16 bytes more than
+// the row, so the 16 rows that one 16-byte operand read of mm_rows / mm_wgrad touches
+// start 4 banks apart and cover the 64 banks once (a stride of 128 or 256 bytes puts
+// them all on the same banks)
+constexpr int kL32 = 40, kL64 = 72, kL96 = 104, kL128 = 136;
+
+// copy a [rows][cols] matrix (cols a multiple of 8, row-contiguous in global memory)
+// into LDS rows of stride ld
+__device__ inline void copy_lds_rows(uint16_t* dst, int ld, const uint16_t* src, int rows, int cols) {
+  const int cpr = cols / 8;
+  for (int i = threadIdx.x; i < rows * cpr; i += blockDim.x) {
+    const int r = i / cpr, c = (i - r * cpr) * 8;
+    *(uint4*)(dst + r * ld + c) = *(const uint4*)(src + (int64_t)r * cols + c);
+  }
+}
+
 // store an MFMA output (64 x 16 NT) to LDS as bf16, optionally transposed ([col][row])
 template <int NT>
 __device__ inline void put(uint16_t* S, int ld, int col0, const f32x4 (&v)[NT], bool transposed) {
@@ -275,13 +291,14 @@ __global__ void k_nn_feat(DevPattern p, const TB* __restrict__ diag, int orow_sy
 }
 
 // ---------------------------------------------------------------- forward pieces
-// edge input row of layer 1 for (tile row t, slot q): [u_i; u_j; K_ij z_j/sigma; 0]
+// edge input row of layer 1 for (tile row t, slot q): [u_i; u_j; K_ij z_j/sigma; 0],
+// zeros where row t has no edge in this slot (one thread per row)
 template <typename TB>
 __device__ inline void l1_row(const DevPattern& p, const TB* __restrict__ offd, const uint16_t* __restrict__ u,
                               int64_t tile, int q, int t, uint16_t* X) {
   const int64_t s0 = p.tile_slot0[tile];
   const int64_t f = (s0 + q) * 64 + t;
-  uint16_t* x = X + t * 64;
+  uint16_t* x = X + t * kL64;
   if (t >= p.tile_nrows[tile] || p.ent_edge[f] == 0) {
 #pragma unroll
     for (int c = 0; c < 64; c += 8) *(uint4*)(x + c) = make_uint4(0, 0, 0, 0);
@@ -316,32 +333,30 @@ __device__ inline void l1_row(const DevPattern& p, const TB* __restrict__ offd, 
   for (int c = 60; c < 64; ++c) x[c] = 0;
 }
 
-// layer-2 edge input row: [h_i; h_j] or zeros for padding
-__device__ inline void l2_row(const DevPattern& p, const uint16_t* __restrict__ h, int64_t tile, int q, int t,
-                              uint16_t* X, bool self_first) {
+// layer-2 edge input row, built by the whole workgroup (256 threads), four threads per
+// tile row (t = threadIdx.x / 4, part = threadIdx.x % 4), each copying 32 of the 128
+// values: [h_i; h_j] (self_first) or [h_j; h_i], zeros where row t has no edge in this slot
+__device__ inline void l2_row(const DevPattern& p, const uint16_t* __restrict__ h, int64_t tile, int q, uint16_t* X,
+                              bool self_first) {
+  const int t = threadIdx.x >> 2, part = threadIdx.x & 3;
   const int64_t f = (p.tile_slot0[tile] + q) * 64 + t;
-  uint16_t* x = X + t * 128;
+  uint16_t* x = X + t * kL128 + 32 * part;
   if (t >= p.tile_nrows[tile] || p.ent_edge[f] == 0) {
 #pragma unroll
-    for (int c = 0; c < 128; c += 8) *(uint4*)(x + c) = make_uint4(0, 0, 0, 0);
+    for (int c = 0; c < 32; c += 8) *(uint4*)(x + c) = make_uint4(0, 0, 0, 0);
     return;
   }
-  const int64_t row = tile * 64 + t;
-  const uint16_t* hs = h + row * 64;
-  const uint16_t* hn = h + (int64_t)p.ent_nbr[f] * 64;
-  const uint16_t* a = self_first ? hs : hn;  // receiver first
-  const uint16_t* b = self_first ? hn : hs;
+  const int64_t src = ((part < 2) == self_first) ? tile * 64 + t : (int64_t)p.ent_nbr[f];
+  const uint16_t* hs = h + src * 64 + 32 * (part & 1);
 #pragma unroll
-  for (int c = 0; c < 64; c += 8) {
-    *(uint4*)(x + c) = *(const uint4*)(a + c);
-    *(uint4*)(x + 64 + c) = *(const uint4*)(b + c);
-  }
+  for (int c = 0; c < 32; c += 8) *(uint4*)(x + c) = *(const uint4*)(hs + c);
 }
 
 // layer 1 of one tile: returns pre-activation of h (pre1) and leaves Y1 = [u; a] in sY
 template <typename TB>
 __device__ inline void l1_tile(const DevPattern& p, const TB* __restrict__ offd, const uint16_t* __restrict__ u,
-                               const uint16_t* W1t, const uint16_t* W2t, int64_t tile, uint16_t* sX, uint16_t* sY,
+                               const uint16_t* W1t, int ldw1, const uint16_t* W2t, int ldw2, int64_t tile,
+                               uint16_t* sX, uint16_t* sY,
                                f32x4 (&pre1)[4], f32x4* pre_m_slot = nullptr) {
   f32x4 agg[4];
   zero(agg);
@@ -352,7 +367,7 @@ __device__ inline void l1_tile(const DevPattern& p, const TB* __restrict__ offd,
     __syncthreads();
     f32x4 acc[4];
     zero(acc);
-    mm_rows<64, 4>(sX, 64, W1t, 64, 0, acc);
+    mm_rows<64, 4>(sX, kL64, W1t, ldw1, 0, acc);
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
@@ -361,33 +376,34 @@ __device__ inline void l1_tile(const DevPattern& p, const TB* __restrict__ offd,
   __syncthreads();
   if (threadIdx.x < 64) {
     const uint16_t* ui = u + (tile * 64 + threadIdx.x) * kNnU;
-    uint16_t* y = sY + threadIdx.x * 96;
+    uint16_t* y = sY + threadIdx.x * kL96;
 #pragma unroll
     for (int c = 0; c < 24; c += 8) *(uint4*)(y + c) = *(const uint4*)(ui + c);
 #pragma unroll
     for (int c = 88; c < 96; ++c) y[c] = 0;
   }
-  put<4>(sY, 96, 24, agg, false);
+  put<4>(sY, kL96, 24, agg, false);
   __syncthreads();
   zero(pre1);
-  mm_rows<96, 4>(sY, 96, W2t, 96, 0, pre1);
+  mm_rows<96, 4>(sY, kL96, W2t, ldw2, 0, pre1);
 }
 
 // layer 2 + decoder of one tile: returns pre2 (pre-activation of q); on exit sX holds
 // Y2 = [h_i; c] and sQ holds q.  d (decoder, 16 columns) in dout.
-__device__ inline void l2_tile(const DevPattern& p, const uint16_t* __restrict__ h, const uint16_t* W3t,
-                               const uint16_t* W4t, const uint16_t* W5t, int64_t tile, uint16_t* sX, uint16_t* sQ,
+__device__ inline void l2_tile(const DevPattern& p, const uint16_t* __restrict__ h, const uint16_t* W3t, int ldw3,
+                               const uint16_t* W4t, int ldw4, const uint16_t* W5t, int ldw5, int64_t tile,
+                               uint16_t* sX, uint16_t* sQ,
                                f32x4 (&pre2)[4], f32x4 (&dout)[1]) {
   f32x4 agg[4];
   zero(agg);
   const int wd = p.tile_width[tile];
   for (int q = 0; q < wd; ++q) {
     __syncthreads();
-    if (threadIdx.x < 64) l2_row(p, h, tile, q, threadIdx.x, sX, true);
+    l2_row(p, h, tile, q, sX, true);
     __syncthreads();
     f32x4 acc[4];
     zero(acc);
-    mm_rows<128, 4>(sX, 128, W3t, 128, 0, acc);
+    mm_rows<128, 4>(sX, kL128, W3t, ldw3, 0, acc);
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
@@ -396,23 +412,23 @@ __device__ inline void l2_tile(const DevPattern& p, const uint16_t* __restrict__
   __syncthreads();
   if (threadIdx.x < 64) {
     const uint16_t* hs = h + (tile * 64 + threadIdx.x) * 64;
-    uint16_t* x = sX + threadIdx.x * 128;
+    uint16_t* x = sX + threadIdx.x * kL128;
 #pragma unroll
     for (int c = 0; c < 64; c += 8) *(uint4*)(x + c) = *(const uint4*)(hs + c);
   }
-  put<4>(sX, 128, 64, agg, false);
+  put<4>(sX, kL128, 64, agg, false);
   __syncthreads();
   zero(pre2);
-  mm_rows<128, 4>(sX, 128, W4t, 128, 0, pre2);
+  mm_rows<128, 4>(sX, kL128, W4t, ldw4, 0, pre2);
   f32x4 qv[4];
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
     for (int i = 0; i < 4; ++i) qv[nt][i] = fmaxf(pre2[nt][i], 0.f);
-  put<4>(sQ, 64, 0, qv, false);
+  put<4>(sQ, kL64, 0, qv, false);
   __syncthreads();
   zero(dout);
-  mm_rows<64, 1>(sQ, 64, W5t, 64, 0, dout);
+  mm_rows<64, 1>(sQ, kL64, W5t, ldw5, 0, dout);
 }
 
 // weight pointers inside the padded layouts
@@ -421,12 +437,12 @@ __device__ inline const uint16_t* WW(const NnBufs& B, int l) { return B.w + nn_p
 
 template <typename TB>
 __global__ void __launch_bounds__(256) k_nn_l1_fwd(DevPattern p, const TB* __restrict__ offd, NnBufs B) {
-  __shared__ __attribute__((aligned(16))) uint16_t sW1[64 * 64], sW2[64 * 96], sX[64 * 64], sY[64 * 96];
-  copy_lds(sW1, WT(B, 0), 64 * 64);
-  copy_lds(sW2, WT(B, 1), 64 * 96);
+  __shared__ __attribute__((aligned(16))) uint16_t sW1[64 * kL64], sW2[64 * kL96], sX[64 * kL64], sY[64 * kL96];
+  copy_lds_rows(sW1, kL64, WT(B, 0), 64, 64);
+  copy_lds_rows(sW2, kL96, WT(B, 1), 64, 96);
   const int64_t tile = blockIdx.x;
   f32x4 pre1[4];
-  l1_tile<TB>(p, offd, B.u, sW1, sW2, tile, sX, sY, pre1);
+  l1_tile<TB>(p, offd, B.u, sW1, kL64, sW2, kL96, tile, sX, sY, pre1);
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
@@ -435,14 +451,14 @@ __global__ void __launch_bounds__(256) k_nn_l1_fwd(DevPattern p, const TB* __res
 }
 
 __global__ void __launch_bounds__(256) k_nn_l2_fwd(DevPattern p, NnBufs B) {
-  __shared__ __attribute__((aligned(16))) uint16_t sW3[64 * 128], sW4[64 * 128], sW5[32 * 64], sX[64 * 128],
-      sQ[64 * 64];
-  copy_lds(sW3, WT(B, 2), 64 * 128);
-  copy_lds(sW4, WT(B, 3), 64 * 128);
-  copy_lds(sW5, WT(B, 4), 32 * 64);
+  __shared__ __attribute__((aligned(16))) uint16_t sW3[64 * kL128], sW4[64 * kL128], sW5[16 * kL64],
+      sX[64 * kL128], sQ[64 * kL64];
+  copy_lds_rows(sW3, kL128, WT(B, 2), 64, 128);
+  copy_lds_rows(sW4, kL128, WT(B, 3), 64, 128);
+  copy_lds_rows(sW5, kL64, WT(B, 4), 16, 64);  // the 16 (12 used) decoder outputs
   const int64_t tile = blockIdx.x;
   f32x4 pre2[4], dout[1];
-  l2_tile(p, B.h, sW3, sW4, sW5, tile, sX, sQ, pre2, dout);
+  l2_tile(p, B.h, sW3, kL128, sW4, kL128, sW5, kL64, tile, sX, sQ, pre2, dout);
 #pragma unroll
   for (int i = 0; i < 4; ++i) B.d[(tile * 64 + orow(i)) * 16 + ocol(0)] = dout[0][i];
 }
@@ -556,8 +572,8 @@ __global__ void k_nn_update(int64_t NP, double* __restrict__ x, const double* __
 // ---------------------------------------------------------------- backward
 // Layer 2 (receiver side) + decoder: dW5, dW4, dW3 (receiver rows), dc, dh (part)
 __global__ void __launch_bounds__(256) k_nn_l2_bwd(DevPattern p, NnBufs B, int G, float scale) {
-  __shared__ __attribute__((aligned(16))) uint16_t sX[64 * 128], sQ[64 * 64], sDD[64 * 32], sDDt[16 * 64],
-      sDP[64 * 64], sDPt[64 * 64];
+  __shared__ __attribute__((aligned(16))) uint16_t sX[64 * kL128], sQ[64 * kL64], sDD[64 * kL32],
+      sDDt[16 * kL64], sDP[64 * kL64], sDPt[64 * kL64];
   const int w = wv();
   f32x4 g5[1], g4[2][4], g3[2][4];
   zero(g5);
@@ -569,7 +585,7 @@ __global__ void __launch_bounds__(256) k_nn_l2_bwd(DevPattern p, NnBufs B, int G
   const float den = (float)B.sc->den;
   for (int64_t tile = blockIdx.x; tile < p.n_tiles; tile += G) {
     f32x4 pre2[4], dout[1];
-    l2_tile(p, B.h, WT(B, 2), WT(B, 3), WT(B, 4), tile, sX, sQ, pre2, dout);
+    l2_tile(p, B.h, WT(B, 2), 128, WT(B, 3), 128, WT(B, 4), 64, tile, sX, sQ, pre2, dout);
     // loss and dd = 2 (d - ehat) scale / den on the 12 used columns
     f32x4 dd[1];
 #pragma unroll
@@ -586,27 +602,27 @@ __global__ void __launch_bounds__(256) k_nn_l2_bwd(DevPattern p, NnBufs B, int G
     }
     __syncthreads();
     // sDD [64][32]: dd in columns 0..15, zeros in 16..31
-    for (int k = threadIdx.x; k < 64 * 32; k += 256) sDD[k] = 0;
+    for (int k = threadIdx.x; k < 64 * kL32; k += 256) sDD[k] = 0;
     __syncthreads();
-    put<1>(sDD, 32, 0, dd, false);
-    put<1>(sDDt, 64, 0, dd, true);
+    put<1>(sDD, kL32, 0, dd, false);
+    put<1>(sDDt, kL64, 0, dd, true);
     __syncthreads();
-    mm_wgrad<1>(sQ, 64, w, sDDt, 64, g5);  // dW5[m][n], m = 16 w + .., n = 0..15
+    mm_wgrad<1>(sQ, kL64, w, sDDt, kL64, g5);  // dW5[m][n], m = 16 w + .., n = 0..15
     f32x4 dq[4];
     zero(dq);
-    mm_rows<32, 4>(sDD, 32, WW(B, 4), 32, 0, dq);  // dq = dd W5^T
+    mm_rows<32, 4>(sDD, kL32, WW(B, 4), 32, 0, dq);  // dq = dd W5^T
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) dq[nt][i] = pre2[nt][i] > 0.f ? dq[nt][i] : 0.f;
-    put<4>(sDP, 64, 0, dq, false);
-    put<4>(sDPt, 64, 0, dq, true);
+    put<4>(sDP, kL64, 0, dq, false);
+    put<4>(sDPt, kL64, 0, dq, true);
     __syncthreads();
-    mm_wgrad<4>(sX, 128, w, sDPt, 64, g4[0]);  // dW4 rows 16w.. (h part)
-    mm_wgrad<4>(sX, 128, w + 4, sDPt, 64, g4[1]);  // dW4 rows 64 + 16w.. (c part)
+    mm_wgrad<4>(sX, kL128, w, sDPt, kL64, g4[0]);  // dW4 rows 16w.. (h part)
+    mm_wgrad<4>(sX, kL128, w + 4, sDPt, kL64, g4[1]);  // dW4 rows 64 + 16w.. (c part)
     f32x4 dy2[8];
     zero(dy2);
-    mm_rows<64, 8>(sDP, 64, WW(B, 3), 64, 0, dy2);  // dY2 = dp2 W4^T: [dh_A | dc]
+    mm_rows<64, 8>(sDP, kL64, WW(B, 3), 64, 0, dy2);  // dY2 = dp2 W4^T: [dh_A | dc]
     f32x4 dh[4], dc[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
@@ -619,21 +635,21 @@ __global__ void __launch_bounds__(256) k_nn_l2_bwd(DevPattern p, NnBufs B, int G
     const int wd = p.tile_width[tile];
     for (int q = 0; q < wd; ++q) {
       __syncthreads();
-      if (threadIdx.x < 64) l2_row(p, B.h, tile, q, threadIdx.x, sX, true);
+      l2_row(p, B.h, tile, q, sX, true);
       __syncthreads();
       f32x4 pre[4];
       zero(pre);
-      mm_rows<128, 4>(sX, 128, WT(B, 2), 128, 0, pre);
+      mm_rows<128, 4>(sX, kL128, WT(B, 2), 128, 0, pre);
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) pre[nt][i] = pre[nt][i] > 0.f ? dc[nt][i] : 0.f;  // dpp
-      put<4>(sDP, 64, 0, pre, false);
-      put<4>(sDPt, 64, 0, pre, true);
+      put<4>(sDP, kL64, 0, pre, false);
+      put<4>(sDPt, kL64, 0, pre, true);
       __syncthreads();
-      mm_wgrad<4>(sX, 128, w, sDPt, 64, g3[0]);
-      mm_wgrad<4>(sX, 128, w + 4, sDPt, 64, g3[1]);
-      mm_rows<64, 4>(sDP, 64, WW(B, 2), 64, 0, dh);  // receiver half of dX2 = dpp W3^T
+      mm_wgrad<4>(sX, kL128, w, sDPt, kL64, g3[0]);
+      mm_wgrad<4>(sX, kL128, w + 4, sDPt, kL64, g3[1]);
+      mm_rows<64, 4>(sDP, kL64, WW(B, 2), 64, 0, dh);  // receiver half of dX2 = dpp W3^T
     }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
@@ -668,7 +684,7 @@ __global__ void __launch_bounds__(256) k_nn_l2_bwd(DevPattern p, NnBufs B, int G
 // Layer 2, sender side: dh_j += sum over i in N(j) of the sender half of dpp_ij W3^T,
 // dpp_ij = dc_i * [p_ij > 0] recomputed from [h_i; h_j].
 __global__ void __launch_bounds__(256) k_nn_l2_bwd_send(DevPattern p, NnBufs B, int G) {
-  __shared__ __attribute__((aligned(16))) uint16_t sX[64 * 128], sDP[64 * 64];
+  __shared__ __attribute__((aligned(16))) uint16_t sX[64 * kL128], sDP[64 * kL64];
   for (int64_t tile = blockIdx.x; tile < p.n_tiles; tile += G) {
     f32x4 dh[4];
     zero(dh);
@@ -676,11 +692,11 @@ __global__ void __launch_bounds__(256) k_nn_l2_bwd_send(DevPattern p, NnBufs B, 
     const int64_t s0 = p.tile_slot0[tile];
     for (int q = 0; q < wd; ++q) {
       __syncthreads();
-      if (threadIdx.x < 64) l2_row(p, B.h, tile, q, threadIdx.x, sX, false);  // [h_nbr; h_self]
+      l2_row(p, B.h, tile, q, sX, false);  // [h_nbr; h_self]
       __syncthreads();
       f32x4 pre[4];
       zero(pre);
-      mm_rows<128, 4>(sX, 128, WT(B, 2), 128, 0, pre);
+      mm_rows<128, 4>(sX, kL128, WT(B, 2), 128, 0, pre);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = orow(i);
@@ -689,9 +705,9 @@ __global__ void __launch_bounds__(256) k_nn_l2_bwd_send(DevPattern p, NnBufs B, 
         for (int nt = 0; nt < 4; ++nt)
           pre[nt][i] = pre[nt][i] > 0.f ? B.dc[(int64_t)nb * 64 + ocol(nt)] : 0.f;
       }
-      put<4>(sDP, 64, 0, pre, false);
+      put<4>(sDP, kL64, 0, pre, false);
       __syncthreads();
-      mm_rows<64, 4>(sDP, 64, WW(B, 2) + 64 * 64, 64, 0, dh);  // sender half: rows 64..127 of W3
+      mm_rows<64, 4>(sDP, kL64, WW(B, 2) + 64 * 64, 64, 0, dh);  // sender half: rows 64..127 of W3
     }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
@@ -704,8 +720,8 @@ __global__ void __launch_bounds__(256) k_nn_l2_bwd_send(DevPattern p, NnBufs B, 
 // Layer 1: dW2, dW1 from dh.
 template <typename TB>
 __global__ void __launch_bounds__(256) k_nn_l1_bwd(DevPattern p, const TB* __restrict__ offd, NnBufs B, int G) {
-  __shared__ __attribute__((aligned(16))) uint16_t sX[64 * 64], sY[64 * 96], sDP[64 * 64], sDPt[64 * 64],
-      sDA[64 * 96];
+  __shared__ __attribute__((aligned(16))) uint16_t sX[64 * kL64], sY[64 * kL96], sDP[64 * kL64],
+      sDPt[64 * kL64], sDA[64 * kL96];
   const int w = wv();
   f32x4 g1[4], g2[2][4];
   zero(g1);
@@ -713,7 +729,7 @@ __global__ void __launch_bounds__(256) k_nn_l1_bwd(DevPattern p, const TB* __res
   zero(g2[1]);
   for (int64_t tile = blockIdx.x; tile < p.n_tiles; tile += G) {
     f32x4 pre1[4];
-    l1_tile<TB>(p, offd, B.u, WT(B, 0), WT(B, 1), tile, sX, sY, pre1);
+    l1_tile<TB>(p, offd, B.u, WT(B, 0), 64, WT(B, 1), 96, tile, sX, sY, pre1);
     f32x4 dp1[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
@@ -721,15 +737,15 @@ __global__ void __launch_bounds__(256) k_nn_l1_bwd(DevPattern p, const TB* __res
       for (int i = 0; i < 4; ++i)
         dp1[nt][i] = pre1[nt][i] > 0.f ? B.dh[(tile * 64 + orow(i)) * 64 + ocol(nt)] : 0.f;
     __syncthreads();
-    put<4>(sDP, 64, 0, dp1, false);
-    put<4>(sDPt, 64, 0, dp1, true);
+    put<4>(sDP, kL64, 0, dp1, false);
+    put<4>(sDPt, kL64, 0, dp1, true);
     __syncthreads();
-    mm_wgrad<4>(sY, 96, w, sDPt, 64, g2[0]);  // dW2 rows 16 w ..
-    if (w < 2) mm_wgrad<4>(sY, 96, w + 4, sDPt, 64, g2[1]);  // rows 64 + 16 w .. (96 rows)
+    mm_wgrad<4>(sY, kL96, w, sDPt, kL64, g2[0]);  // dW2 rows 16 w ..
+    if (w < 2) mm_wgrad<4>(sY, kL96, w + 4, sDPt, kL64, g2[1]);  // rows 64 + 16 w .. (96 rows)
     f32x4 dy1[6];
     zero(dy1);
-    mm_rows<64, 6>(sDP, 64, WW(B, 1), 64, 0, dy1);  // dY1 = dp1 W2^T  [64 x 96]
-    put<6>(sDA, 96, 0, dy1, false);
+    mm_rows<64, 6>(sDP, kL64, WW(B, 1), 64, 0, dy1);  // dY1 = dp1 W2^T  [64 x 96]
+    put<6>(sDA, kL96, 0, dy1, false);
     __syncthreads();
     const int wd = p.tile_width[tile];
     for (int q = 0; q < wd; ++q) {
@@ -738,15 +754,15 @@ __global__ void __launch_bounds__(256) k_nn_l1_bwd(DevPattern p, const TB* __res
       __syncthreads();
       f32x4 pre[4];
       zero(pre);
-      mm_rows<64, 4>(sX, 64, WT(B, 0), 64, 0, pre);
+      mm_rows<64, 4>(sX, kL64, WT(B, 0), 64, 0, pre);
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) pre[nt][i] = pre[nt][i] > 0.f ? bf2f(sDA[orow(i) * 96 + 24 + ocol(nt)]) : 0.f;
+        for (int i = 0; i < 4; ++i) pre[nt][i] = pre[nt][i] > 0.f ? bf2f(sDA[orow(i) * kL96 + 24 + ocol(nt)]) : 0.f;
       __syncthreads();
-      put<4>(sDPt, 64, 0, pre, true);
+      put<4>(sDPt, kL64, 0, pre, true);
       __syncthreads();
-      mm_wgrad<4>(sX, 64, w, sDPt, 64, g1);
+      mm_wgrad<4>(sX, kL64, w, sDPt, kL64, g1);
     }
     __syncthreads();
   }

@@ -451,14 +451,15 @@ __global__ void __launch_bounds__(256) k_nn_l1_fwd(DevPattern p, const TB* __res
 }
 
 __global__ void __launch_bounds__(256) k_nn_l2_fwd(DevPattern p, NnBufs B) {
-  __shared__ __attribute__((aligned(16))) uint16_t sW3[64 * kL128], sW4[64 * kL128], sW5[16 * kL64],
-      sX[64 * kL128], sQ[64 * kL64];
+  // W3 (read once per slot) and W5 in LDS; W4 (once per tile) from the cache, which
+  // leaves room for three workgroups per CU
+  __shared__ __attribute__((aligned(16))) uint16_t sW3[64 * kL128], sW5[16 * kL64], sX[64 * kL128],
+      sQ[64 * kL64];
   copy_lds_rows(sW3, kL128, WT(B, 2), 64, 128);
-  copy_lds_rows(sW4, kL128, WT(B, 3), 64, 128);
   copy_lds_rows(sW5, kL64, WT(B, 4), 16, 64);  // the 16 (12 used) decoder outputs
   const int64_t tile = blockIdx.x;
   f32x4 pre2[4], dout[1];
-  l2_tile(p, B.h, sW3, kL128, sW4, kL128, sW5, kL64, tile, sX, sQ, pre2, dout);
+  l2_tile(p, B.h, sW3, kL128, WT(B, 3), 128, sW5, kL64, tile, sX, sQ, pre2, dout);
 #pragma unroll
   for (int i = 0; i < 4; ++i) B.d[(tile * 64 + orow(i)) * 16 + ocol(0)] = dout[0][i];
 }

@@ -323,14 +323,14 @@ int fnlh_autotune(fnlh_ctx c, int32_t n_sys, int32_t sweeps, fnlh_tune_result* o
  * preconditioning).  Per iteration j: z_j = M^-1 v_j, `inner_sweeps` preconditioned
  * Richardson sweeps from 0 (one sweep is exactly M^-1 of DILU, SGS or Jacobi; FP32/BF16
  * sweeps for reduced storage).  FNLH_LEARNED makes M^-1 nonlinear, which the flexible
- * method admits: z_j = alpha d + (inner DILU sweeps on K z = v_j - K alpha d from 0), d
- * the attached network's correction for the residual v_j (fnlh_nn_create) and alpha the
- * complex step minimising ||v_j - alpha K d||, the network part dropped (alpha = 0)
- * where it is not finite or lowers ||v_j||^2 by less than 1e-3 of itself.  Then
- * w = (K + i omega V) z_j with the FP64 operator,
- * orthogonalised against v_0..v_j by classical Gram-Schmidt with a second pass where
- * the norm falls below 1/sqrt(2) of its value (DGKS), Givens rotations on the host; x += Z y at the end of each cycle of `restart` iterations, and the next
- * cycle starts from the true residual.  Inner products sum conj(u) v over all 6N complex
+ * method admits: z_j = alpha d + e, with d the attached network's correction for the
+ * residual v_j (fnlh_nn_create), alpha the complex step minimising ||v_j - alpha K d||
+ * (set to 0 where it is not finite or lowers ||v_j||^2 by less than 1e-3 of itself),
+ * and e from `inner_sweeps` DILU sweeps from 0 on K e = v_j - alpha K d.  Then
+ * w = (K + i omega V) z_j with the FP64 operator, orthogonalised against v_0..v_j by
+ * classical Gram-Schmidt with a second pass where the norm falls below 1/sqrt(2) of
+ * its value (DGKS), Givens rotations on the host; x += Z y at the end of each cycle of
+ * `restart` iterations, and the next cycle starts from the true residual.  Inner products sum conj(u) v over all 6N complex
  * entries.  Stop when the residual norm (the least-squares one within a cycle, the true
  * one at a restart) is <= rtol ||r0||, after max_iters iterations, or on breakdown. */
 typedef struct {

@@ -250,3 +250,22 @@ def test_gmres_learned_refuses_frozen_systems(F):
     assert relerr(x, solve.dense_solve(K, m.volume, m.zone, OMEGA[1], b)) <= 1e-9
     net.close()
     c.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_gmres_learned_graph_replay_matches_direct(F, storage):
+    """The inner sweeps replayed from HIP graphs give the iterations of the direct
+    launches; the learned step runs outside the graphs in both."""
+    m, Q, K = _case("passage", seed=8)
+    c = _ctx(F, m, Q, storage=storage)
+    net = _net(F, c, _random_weights(13))
+    bs = [synth.rhs(m.n_cells, 90 + s, real=(s == 0)) for s in range(3)]
+    kw = dict(kind="learned", restart=8, rtol=0.0, max_iters=12, inner_sweeps=2)
+    _, r0, h0, x0 = _gmres(c, [0, 1, 2], bs, **kw)
+    _, r1, h1, x1 = _gmres(c, [0, 1, 2], bs, use_graph=True, **kw)
+    for s in range(3):
+        assert r0[s]["learned"] == r1[s]["learned"] and r0[s]["iters"] == r1[s]["iters"] == 12
+        np.testing.assert_allclose(h1[s], h0[s], rtol=1e-12)
+        assert relerr(x1[s], x0[s]) <= 1e-12
+    net.close()
+    c.close()

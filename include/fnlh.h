@@ -451,6 +451,11 @@ int fnlh_nn_set_weights(fnlh_nn nn, const float* w);
 int fnlh_nn_get_weights(fnlh_nn nn, float* w);
 /* dx = network(r) for system sys: r, dx device [N][6] complex128 user order. */
 int fnlh_nn_apply(fnlh_nn nn, int32_t sys, const double* r, double* dx, void* stream);
+/* Workgroups of the backward (gradient) kernels: each sums the weight-gradient partials
+ * of the 64-row tiles g, g + groups, g + 2 groups, ... and the partials are added in a
+ * fixed order, so the gradient is deterministic for a given count.  1..512, or 0 for
+ * the automatic min(512, tiles).  Changes only the summation order of the gradient. */
+int fnlh_nn_set_grad_groups(fnlh_nn nn, int32_t groups);
 /* Mean loss and its gradient over n pairs (device [N][6] user-order r[k], e[k]);
  * grad host [FNLH_NN_PARAMS] or NULL, loss host or NULL.  Synchronises the stream. */
 int fnlh_nn_loss_grad(fnlh_nn nn, int32_t n, const int32_t* sys, const double* const* r,

@@ -73,18 +73,26 @@ int ready(fnlh_nn nn) {
 }
 
 int ensure_train(fnlh_nn nn) {
-  if (nn->ehat.p) return FNLH_OK;
   fnlh_ctx c = nn->c;
-  const size_t NP = (size_t)c->L.NP;
   int rc;
-  if ((rc = dalloc(c, nn->ehat, NP * 16 * sizeof(float), "alloc network"))) return rc;
-  if ((rc = dalloc(c, nn->dc, NP * 64 * sizeof(float), "alloc network"))) return rc;
-  if ((rc = dalloc(c, nn->dh, NP * 64 * sizeof(float), "alloc network"))) return rc;
-  if ((rc = dalloc(c, nn->gpart, (size_t)nn->G * kNnPadded * sizeof(float), "alloc network"))) return rc;
-  if ((rc = dalloc(c, nn->lpart, (size_t)nn->G * sizeof(double), "alloc network"))) return rc;
-  HIPC(c, hipMemset(nn->ehat.p, 0, nn->ehat.bytes), "zero");
+  if (!nn->ehat.p) {
+    const size_t NP = (size_t)c->L.NP;
+    if ((rc = dalloc(c, nn->ehat, NP * 16 * sizeof(float), "alloc network"))) return rc;
+    if ((rc = dalloc(c, nn->dc, NP * 64 * sizeof(float), "alloc network"))) return rc;
+    if ((rc = dalloc(c, nn->dh, NP * 64 * sizeof(float), "alloc network"))) return rc;
+    HIPC(c, hipMemset(nn->ehat.p, 0, nn->ehat.bytes), "zero");
+  }
+  // gradient partials: one row per backward workgroup (their count G may be changed)
+  if (nn->gpart.bytes != (size_t)nn->G * kNnPadded * sizeof(float)) {
+    dfree(nn->gpart);
+    dfree(nn->lpart);
+    if ((rc = dalloc(c, nn->gpart, (size_t)nn->G * kNnPadded * sizeof(float), "alloc network"))) return rc;
+    if ((rc = dalloc(c, nn->lpart, (size_t)nn->G * sizeof(double), "alloc network"))) return rc;
+  }
   return FNLH_OK;
 }
+
+int auto_groups(fnlh_ctx c) { return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxG, c->L.n_tiles)); }
 
 // features + forward of one residual (and the training target when e is given)
 void features(fnlh_nn nn, int sys, const NnVec& r, const NnVec* e, hipStream_t s) {
@@ -224,7 +232,7 @@ int fnlh_nn_create(fnlh_nn* out, fnlh_ctx c) {
   fnlh_nn nn = new fnlh_nn_s();
   nn->c = c;
   const size_t NP = (size_t)c->L.NP;
-  nn->G = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxG, c->L.n_tiles));
+  nn->G = auto_groups(c);
   int rc = 0;
   auto fail = [&](int code) {
     free_all(nn);
@@ -245,6 +253,14 @@ int fnlh_nn_create(fnlh_nn* out, fnlh_ctx c) {
   if (hipMemset(nn->d.p, 0, nn->d.bytes) != hipSuccess) return fail(FNLH_E_HIP);
   c->nn = nn;
   *out = nn;
+  return FNLH_OK;
+}
+
+int fnlh_nn_set_grad_groups(fnlh_nn nn, int32_t groups) {
+  if (!nn) return FNLH_E_ARG;
+  if (!nn->c) return FNLH_E_ORDER;
+  if (groups < 0 || groups > kMaxG) return set_err(nn->c, FNLH_E_ARG, "network: gradient workgroups in 0..512");
+  nn->G = groups == 0 ? auto_groups(nn->c) : groups;
   return FNLH_OK;
 }
 

@@ -122,6 +122,7 @@ def _load():
         "fnlh_stats_get": (I32, [P, I32, C.POINTER(KernelStats)]),
         "fnlh_nn_create": (I32, [C.POINTER(P), P]),
         "fnlh_nn_destroy": (I32, [P]),
+        "fnlh_nn_set_grad_groups": (I32, [P, I32]),
         "fnlh_nn_set_weights": (I32, [P, V]),
         "fnlh_nn_get_weights": (I32, [P, V]),
         "fnlh_nn_apply": (I32, [P, I32, V, V, V]),
@@ -158,14 +159,25 @@ def _stream(stream):
     return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
 
 
-def _dev_tensor(t, shape, dtype_name):
+def _dev_tensor(t, shape, name, dtype="complex128", device=None):
+    """Check a device argument before its pointer crosses the ABI: a torch tensor of the
+    expected dtype (complex128 vectors, float64 states and blocks), shape and layout, on
+    the context's HIP device.  Every check runs before any library call, so a wrong
+    tensor never reaches a kernel that would read or write past its end."""
     import torch
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise TypeError(f"expected a CUDA (HIP) torch tensor for {dtype_name}")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    want = getattr(torch, dtype)
+    if t.dtype != want:
+        raise TypeError(f"{name}: dtype {t.dtype} != {want}")
     if tuple(t.shape) != tuple(shape):
-        raise ValueError(f"{dtype_name}: shape {tuple(t.shape)} != {tuple(shape)}")
+        raise ValueError(f"{name}: shape {tuple(t.shape)} != {tuple(shape)}")
     if not t.is_contiguous():
-        raise ValueError(f"{dtype_name}: tensor must be contiguous")
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if not t.is_cuda:
+        raise TypeError(f"{name}: expected a CUDA (HIP) tensor, got one on {t.device}")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{name}: tensor on cuda:{t.device.index}, context on cuda:{device}")
     return t
 
 
@@ -217,6 +229,7 @@ class Context:
         self.B = int(self.mesh_arrays.s.n_bfaces)
         self.n_zones = int(self.mesh_arrays.s.n_zones)
         self.storage = storage
+        self.device = int(device)
         o, uc = _options(storage, outer, ordering, factor_slots, user_colour, device)
         h = C.c_void_p()
         rc = LIB.fnlh_create(C.byref(h), C.byref(self.mesh_arrays.s), C.byref(o))
@@ -248,15 +261,15 @@ class Context:
         self.close()
 
     def assemble_jacobian(self, state, bstate=None, eps=0.6, sigma=50.0, scheme="implicit", stream=None):
-        _dev_tensor(state, (self.n, 6), "state")
+        _dev_tensor(state, (self.n, 6), "state", "float64", self.device)
         if bstate is not None:
-            _dev_tensor(bstate, (self.B, 6), "bstate")
+            _dev_tensor(bstate, (self.B, 6), "bstate", "float64", self.device)
         self._check(LIB.fnlh_assemble_jacobian(self.h, _ptr(state), _ptr(bstate), float(eps), float(sigma),
                                                SCHEME[scheme], _stream(stream)))
 
     def set_blocks(self, diag, offd, stream=None):
-        _dev_tensor(diag, (self.n, 6, 6), "diag")
-        _dev_tensor(offd, (self.E, 2, 6, 6), "offd")
+        _dev_tensor(diag, (self.n, 6, 6), "diag", "float64", self.device)
+        _dev_tensor(offd, (self.E, 2, 6, 6), "offd", "float64", self.device)
         self._check(LIB.fnlh_set_blocks(self.h, _ptr(diag), _ptr(offd), _stream(stream)))
 
     def get_blocks(self, stream=None):
@@ -285,9 +298,9 @@ class Context:
 
     def residual(self, sys, x, b, r=None, stream=None):
         for t, nm in ((x, "x"), (b, "b")):
-            _dev_tensor(t, (self.n, 6), nm)
+            _dev_tensor(t, (self.n, 6), nm, device=self.device)
         if r is not None:
-            _dev_tensor(r, (self.n, 6), "r")
+            _dev_tensor(r, (self.n, 6), "r", device=self.device)
         n2 = C.c_double(0.0)
         self._check(LIB.fnlh_residual(self.h, int(sys), _ptr(x), _ptr(b), _ptr(r), C.byref(n2), _stream(stream)))
         return n2.value
@@ -297,8 +310,10 @@ class Context:
         """Solve (K + i omega_s V) x = b for each s in ``systems``; xs (in: x0, out: x) and
         bs are complex128 CUDA tensors [N, 6].  Returns (status, list of report dicts)."""
         n = len(systems)
+        if len(xs) != n or len(bs) != n:
+            raise ValueError(f"{n} systems need {n} x and {n} b vectors")
         for t in list(xs) + list(bs):
-            _dev_tensor(t, (self.n, 6), "vector")
+            _dev_tensor(t, (self.n, 6), "vector", device=self.device)
         sysarr = np.ascontiguousarray(systems, dtype=np.int32)
         xp = (C.c_void_p * n)(*[_ptr(t) for t in xs])
         bp = (C.c_void_p * n)(*[_ptr(t) for t in bs])
@@ -319,8 +334,10 @@ class Context:
         Returns (status, reports) or, with history=True, (status, reports, histories) where
         histories[j] holds the residual norm after each iteration (index 0: ||r0||)."""
         n = len(systems)
+        if len(xs) != n or len(bs) != n:
+            raise ValueError(f"{n} systems need {n} x and {n} b vectors")
         for t in list(xs) + list(bs):
-            _dev_tensor(t, (self.n, 6), "vector")
+            _dev_tensor(t, (self.n, 6), "vector", device=self.device)
         sysarr = np.ascontiguousarray(systems, dtype=np.int32)
         xp = (C.c_void_p * n)(*[_ptr(t) for t in xs])
         bp = (C.c_void_p * n)(*[_ptr(t) for t in bs])
@@ -358,7 +375,9 @@ class Context:
     def rusanov_residual(self, state, bstate=None, stream=None):
         """R(Q) of the first-order Rusanov scheme (device [N, 6] float64) and ||R||^2."""
         import torch
-        _dev_tensor(state, (self.n, 6), "state")
+        _dev_tensor(state, (self.n, 6), "state", "float64", self.device)
+        if bstate is not None:
+            _dev_tensor(bstate, (self.B, 6), "bstate", "float64", self.device)
         R = torch.empty_like(state)
         n2 = C.c_double(0.0)
         self._check(LIB.fnlh_rusanov_residual(self.h, _ptr(state), _ptr(bstate), _ptr(R), C.byref(n2),
@@ -374,7 +393,9 @@ class Context:
                 max_sweeps=10, rtol=1e-2, check_every=10, use_graph=False, stream=None):
         """n_steps RK(5,3) pseudo-time steps of the mean flow (state updated in place);
         returns (status, ||R|| at the start of each step)."""
-        _dev_tensor(state, (self.n, 6), "state")
+        _dev_tensor(state, (self.n, 6), "state", "float64", self.device)
+        if bstate is not None:
+            _dev_tensor(bstate, (self.B, 6), "bstate", "float64", self.device)
         hist = np.zeros(max(int(n_steps), 1))
         o = self._lin(kind, max_sweeps, rtol, check_every, use_graph)
         rc = LIB.fnlh_rk_mean(self.h, int(sys), _ptr(state), _ptr(bstate), int(n_steps), float(eps), float(sigma),
@@ -387,7 +408,7 @@ class Context:
         """n_steps RK(5,3) pseudo-time steps of harmonic sys about the assembled state
         (qhat updated in place); returns (status, ||R_l|| at the start of each step)."""
         for t, nm in ((qhat, "qhat"), (fhat, "fhat")):
-            _dev_tensor(t, (self.n, 6), nm)
+            _dev_tensor(t, (self.n, 6), nm, device=self.device)
         hist = np.zeros(max(int(n_steps), 1))
         o = self._lin(kind, max_sweeps, rtol, check_every, use_graph)
         rc = LIB.fnlh_rk_harmonic(self.h, int(sys), _ptr(qhat), _ptr(fhat), int(n_steps), C.byref(o), _ptr(hist),
@@ -499,8 +520,10 @@ class Batch:
         x_ptrs = (C.c_void_p * n)()
         b_ptrs = (C.c_void_p * n)()
         for i, ctx in enumerate(self.contexts):
+            if len(xs[i]) != len(systems[i]) or len(bs[i]) != len(systems[i]):
+                raise ValueError(f"instance {i}: {len(systems[i])} systems need as many x and b vectors")
             for t in list(xs[i]) + list(bs[i]):
-                _dev_tensor(t, (ctx.n, 6), "vector")
+                _dev_tensor(t, (ctx.n, 6), "vector", device=ctx.device)
             sa = np.ascontiguousarray(systems[i], dtype=np.int32)
             xa = (C.c_void_p * len(xs[i]))(*[_ptr(t) for t in xs[i]])
             ba = (C.c_void_p * len(bs[i]))(*[_ptr(t) for t in bs[i]])
@@ -553,6 +576,11 @@ class Network:
             raise ValueError(f"expected {NN_PARAMS} weights, got {w.size}")
         self.ctx._check(LIB.fnlh_nn_set_weights(self.h, _ptr(w)))
 
+    def set_grad_groups(self, groups):
+        """Workgroups of the gradient kernels (each sums the partials of several tiles
+        when fewer than the tiles); 0 = automatic."""
+        self.ctx._check(LIB.fnlh_nn_set_grad_groups(self.h, int(groups)))
+
     def get_weights(self):
         w = np.empty(NN_PARAMS, np.float32)
         self.ctx._check(LIB.fnlh_nn_get_weights(self.h, _ptr(w)))
@@ -560,18 +588,20 @@ class Network:
 
     def apply(self, sys, r, dx=None, stream=None):
         import torch
-        _dev_tensor(r, (self.ctx.n, 6), "r")
+        _dev_tensor(r, (self.ctx.n, 6), "r", device=self.ctx.device)
         if dx is None:
             dx = torch.empty_like(r)
-        _dev_tensor(dx, (self.ctx.n, 6), "dx")
+        _dev_tensor(dx, (self.ctx.n, 6), "dx", device=self.ctx.device)
         self.ctx._check(LIB.fnlh_nn_apply(self.h, int(sys), _ptr(r), _ptr(dx), _stream(stream)))
         return dx
 
     @staticmethod
-    def _lists(systems, rs, es, n_cells):
+    def _lists(systems, rs, es, n_cells, device=None):
         n = len(systems)
+        if len(rs) != n or len(es) != n:
+            raise ValueError(f"{n} systems need {n} r and {n} e vectors")
         for t in list(rs) + list(es):
-            _dev_tensor(t, (n_cells, 6), "vector")
+            _dev_tensor(t, (n_cells, 6), "vector", device=device)
         sa = np.ascontiguousarray(systems, dtype=np.int32)
         rp = (C.c_void_p * n)(*[_ptr(t) for t in rs])
         ep = (C.c_void_p * n)(*[_ptr(t) for t in es])
@@ -579,7 +609,7 @@ class Network:
 
     def loss_grad(self, systems, rs, es, stream=None):
         """Mean loss and its gradient (float32 [NN_PARAMS]) over pairs (r, e)."""
-        n, sa, rp, ep = self._lists(systems, rs, es, self.ctx.n)
+        n, sa, rp, ep = self._lists(systems, rs, es, self.ctx.n, self.ctx.device)
         g = np.empty(NN_PARAMS, np.float32)
         loss = C.c_double(0.0)
         self.ctx._check(LIB.fnlh_nn_loss_grad(self.h, n, _ptr(sa), C.cast(rp, C.c_void_p), C.cast(ep, C.c_void_p),
@@ -587,7 +617,7 @@ class Network:
         return loss.value, g
 
     def add_pairs(self, systems, rs, es, stream=None):
-        n, sa, rp, ep = self._lists(systems, rs, es, self.ctx.n)
+        n, sa, rp, ep = self._lists(systems, rs, es, self.ctx.n, self.ctx.device)
         self.ctx._check(LIB.fnlh_nn_add_pairs(self.h, n, _ptr(sa), C.cast(rp, C.c_void_p), C.cast(ep, C.c_void_p),
                                               _stream(stream)))
 

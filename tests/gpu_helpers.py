@@ -37,3 +37,20 @@ def rounded(K, storage):
 
 def relerr(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def rowerr(a, b):
+    """Worst single entry: max over rows i and the six components k of
+    |a_ik - b_ik| / rms_i |b_ik|.  Each component is measured against its own scale, so a
+    small component (the turbulence variable) or a handful of rows (boundary cells)
+    cannot hide behind the norm of the whole field."""
+    a = np.asarray(a).reshape(-1, 6)
+    b = np.asarray(b).reshape(-1, 6)
+    rms = np.sqrt(np.mean(np.abs(b) ** 2, axis=0))
+    return float(np.max(np.abs(a - b) / np.maximum(rms, 1e-300)))
+
+
+def itererr(a, b):
+    """Iterate parity: the larger of the field's relative error and the per-row,
+    per-component error of rowerr."""
+    return max(relerr(a, b), rowerr(a, b))

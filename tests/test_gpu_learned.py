@@ -102,13 +102,15 @@ def test_forward_matches_oracle(F, small, storage):
     c.close()
 
 
-def test_gradient_matches_oracle(F, small):
-    m, Q, K, om = small
+def _check_gradient(F, m, K, om, groups, seed):
+    """Loss and gradient of two pairs against the oracle's backward pass, with the
+    backward kernels launched on `groups` workgroups (0: automatic)."""
     c = _ctx(F, m, K, om)
     net = F.Network(c)
+    net.set_grad_groups(groups)
     w = _weights(8)
     net.set_weights(w)
-    rng = np.random.default_rng(12)
+    rng = np.random.default_rng(seed)
     systems = [0, 1]
     rs = [_cvec(rng, m.n_cells) for _ in systems]
     es = [_cvec(rng, m.n_cells) for _ in systems]
@@ -125,10 +127,33 @@ def test_gradient_matches_oracle(F, small):
     offs = np.cumsum([0] + [a * b for a, b in learned.SHAPES])
     for k in range(5):
         a, b = g[offs[k]:offs[k + 1]].astype(np.float64), gref[offs[k]:offs[k + 1]]
-        assert relerr(a, b) <= GRAD_TOL, (k, relerr(a, b))
-        assert a @ b / (np.linalg.norm(a) * np.linalg.norm(b)) >= 0.998, k
+        assert relerr(a, b) <= GRAD_TOL, (groups, k, relerr(a, b))
+        assert a @ b / (np.linalg.norm(a) * np.linalg.norm(b)) >= 0.998, (groups, k)
     net.close()
     c.close()
+    return g
+
+
+def test_gradient_matches_oracle(F, small):
+    m, Q, K, om = small
+    _check_gradient(F, m, K, om, 0, 12)
+
+
+@pytest.mark.parametrize("groups", [1, 2, 4])
+def test_gradient_several_tiles_per_workgroup(F, small, groups):
+    """The backward kernels sum the partials of tiles g, g + G, ... per workgroup: with
+    G = 1, 2 or 4 workgroups on the 6 tiles of the 350-cell mesh each sums 6, 3 or
+    1-2 tiles (the path every 200k-cell training step takes, about six tiles each)."""
+    m, Q, K, om = small
+    _check_gradient(F, m, K, om, groups, 12)
+
+
+def test_gradient_more_tiles_than_workgroups(F):
+    """36,000 cells = 563 tiles on the automatic 512 workgroups: 51 of them sum two
+    tiles, the rest one."""
+    m, Q, K = case(shape=(40, 30, 30), seed=33)
+    om = synth.omegas_single_zone(1, 36)
+    _check_gradient(F, m, K, om, 0, 34)
 
 
 def _pairs(F, c, net, systems, per_system, sweeps, seed):

@@ -108,6 +108,42 @@ def test_dilu_defining_property():
     np.testing.assert_allclose(M[pattern], Ap[pattern], rtol=0, atol=1e-12 * np.abs(Ap).max())
 
 
+def test_dilu_defining_property_with_triangles():
+    """diag(M) = diag(K_s) for M = (Dt+L) Dt^-1 (Dt+U) holds on any graph: it defines
+    Dt.  Pinned here on a two-row mesh whose interface edges form triangles (greedy
+    colouring, several colours, per-row frequencies), the case of the three-row sector
+    and the general-colouring kernels, where DILU and ILU(0) differ.  M - K_s is then
+    exactly the strictly off-diagonal part of L Dt^-1 U: the fill DILU leaves out."""
+    m = synth.multi_row(3, 4, 2, n_blades=(36, 60), seed=3)
+    Q = synth.flow_state(m, 3)
+    K = assemble.assemble(m, Q)
+    assert ordering.has_triangle(m.n_cells, m.edges)
+    col = ordering.greedy_colouring(m.n_cells, m.edges)
+    assert col.max() + 1 >= 3
+    for om in (np.array([18.0, 30.0]), np.array([0.0, 0.0]), np.array([-54.0, 90.0])):
+        f = solve.factor(K, m.volume, m.zone, om, col, "DILU")
+        Ap, order, idx = _dense_perm(K, m, om, col)
+        n = K.n
+        L, D, U = _blocks_lower_upper(Ap, n)
+        Dt = np.zeros_like(Ap)
+        for p, i in enumerate(order):
+            Dt[6 * p:6 * p + 6, 6 * p:6 * p + 6] = f.Dt[i]
+        M = (Dt + L) @ np.linalg.solve(Dt, Dt + U)
+        scale = np.abs(Ap).max()
+        diag = np.zeros_like(Ap, dtype=bool)
+        for p in range(n):
+            diag[6 * p:6 * p + 6, 6 * p:6 * p + 6] = True
+        np.testing.assert_allclose(M[diag], Ap[diag], rtol=0, atol=1e-12 * scale)
+        fill = L @ np.linalg.solve(Dt, U)
+        fill[diag] = 0.0
+        np.testing.assert_allclose(M - Ap, fill, rtol=0, atol=1e-12 * scale)
+        # a wrong Dt (one block perturbed) breaks the property
+        Dt2 = Dt.copy()
+        Dt2[6 * (n // 2):6 * (n // 2) + 6, 6 * (n // 2):6 * (n // 2) + 6] *= 1.001
+        M2 = (Dt2 + L) @ np.linalg.solve(Dt2, Dt2 + U)
+        assert np.abs(M2[diag] - Ap[diag]).max() > 1e-6 * scale
+
+
 def test_ilu0_defining_property_with_triangles():
     m = synth.multi_row(3, 4, 2, n_blades=(36, 60), seed=3)
     Q = synth.flow_state(m, 3)

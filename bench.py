@@ -30,6 +30,7 @@ HBM_PEAK_GBS = 8000.0
 SHAPE = (80, 50, 50)
 N_HARM = 3
 RTOL = 1e-8
+CONVERGED = (0, 3)  # FNLH_OK, FNLH_FELL_BACK (learned corrections switched off, plain sweeps converged)
 STATS_PERIOD = 4  # time the sweep-pass launches of every 4th sweep (bounds event overhead)
 # HBM bytes per launch of the update pass from two rocprofv3 counter runs (FETCH_SIZE x 2.0
 # + WRITE_SIZE x 1.0, calibrated on a 1 GiB copy), for the kernel these sources build at the
@@ -73,7 +74,7 @@ class Runner:
         self.ctx.set_harmonics(self.om)
         st, rep = self.ctx.relax(list(range(self.S)), self.xd, self.bd, kind="dilu", max_sweeps=4000, rtol=RTOL,
                                  check_every=self.check_every, use_graph=self.use_graph)
-        if st != 0:
+        if st not in CONVERGED:
             raise RuntimeError(f"solve did not converge: status {st}, reports {rep}")
         return rep
 
@@ -156,7 +157,7 @@ def learned_compare(mesh, Q, om, bs, storage, n_pairs, train_steps, batch, learn
                                 use_graph=True, learn_every=learn_every)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
-            if st != 0:
+            if st not in CONVERGED:
                 raise RuntimeError(f"{kind} solve did not converge: {rep}")
         ms = 1e3 * float(np.median(times))
         return {"ms": round(ms, 3), "sweeps": [r["sweeps"] for r in rep], "outer": [r["outer"] for r in rep],
@@ -206,7 +207,7 @@ def learned_compare(mesh, Q, om, bs, storage, n_pairs, train_steps, batch, learn
                                 use_graph=True)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
-            if st != 0:
+            if st not in CONVERGED:
                 raise RuntimeError(f"FGMRES {kind} did not converge: {rep}")
         return {"ms": round(1e3 * float(np.median(times)), 3), "iters": [r["iters"] for r in rep],
                 "learned_steps": [r["learned"] for r in rep], "rel_res": [r["rel_res"] for r in rep]}
@@ -294,7 +295,7 @@ def run_largest(args):
         ctx.set_harmonics(om)
         st, rep = ctx.relax(list(range(S)), xs, bd, kind=kind, max_sweeps=6000, rtol=RTOL, check_every=16,
                             use_graph=True, learn_every=args.learn_every)
-        if st != 0:
+        if st not in CONVERGED:
             raise RuntimeError(f"largest: {kind} solve did not converge: {rep}")
         return rep
 
@@ -414,7 +415,7 @@ def run_phase(args):
                 ctx.set_phase_lag(mesh.edge_phase, sigma)
                 st, rep = ctx.relax(list(range(r.S)), r.xd, r.bd, kind="dilu", max_sweeps=4000, rtol=RTOL,
                                     check_every=r.check_every, use_graph=r.use_graph)
-                if st != 0:
+                if st not in CONVERGED:
                     raise RuntimeError(f"phased solve did not converge: {rep}")
                 return rep
             r.step = step
@@ -469,7 +470,7 @@ def run_krylov(args):
         ctx.set_harmonics(om)
         st, rep = ctx.gmres(list(range(r.S)), r.xd, r.bd, kind="dilu", restart=args.restart, max_iters=2000,
                             rtol=RTOL, inner_sweeps=args.inner_sweeps)
-        if st != 0:
+        if st not in CONVERGED:
             raise RuntimeError(f"gmres did not converge: {rep}")
         last["rep"] = rep
         return [{"sweeps": q["iters"] * args.inner_sweeps, "outer": q["restarts"], "rel_res": q["rel_res"]}
@@ -679,7 +680,7 @@ def run_batch(args):
                 x.zero_()
         st, reps = B.relax(systems, xd, bd, kind="dilu", max_sweeps=5000, rtol=RTOL, check_every=args.check_every,
                            use_graph=not args.no_graph)
-        if st != 0:
+        if st not in CONVERGED:
             raise RuntimeError(f"batched solve status {st}")
         return reps
 
@@ -690,7 +691,7 @@ def run_batch(args):
                 x.zero_()
             st, rep = c.relax(sy, xr, br, kind="dilu", max_sweeps=5000, rtol=RTOL, check_every=args.check_every,
                               use_graph=False)
-            if st != 0:
+            if st not in CONVERGED:
                 raise RuntimeError(f"per-instance solve status {st}")
             reps.append(rep)
         return reps
@@ -748,7 +749,7 @@ def run_batch(args):
                     x.zero_()
             st, reps = B.relax(systems, xd, bd, kind="learned", max_sweeps=5000, rtol=RTOL,
                                check_every=args.check_every, use_graph=not args.no_graph, learn_every=args.learn_every)
-            if st != 0:
+            if st not in CONVERGED:
                 raise RuntimeError(f"batched learned solve status {st}")
             return reps
 

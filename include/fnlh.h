@@ -58,11 +58,15 @@ extern "C" {
 
 typedef struct fnlh_ctx_s* fnlh_ctx;
 
-/* status codes */
+/* status codes.  Solver outcomes are > 0; the worst over several systems is reported
+ * in the order OK < FELL_BACK < NOT_CONVERGED < DIVERGED. */
 enum {
   FNLH_OK = 0,
   FNLH_NOT_CONVERGED = 1, /* max_sweeps reached above the tolerance            */
   FNLH_DIVERGED = 2,      /* NaN/Inf or ||r|| > div_factor ||r0||               */
+  FNLH_FELL_BACK = 3,     /* FNLH_LEARNED: converged, but the network's corrections
+                             were switched off for the system after three rejections
+                             in a row (the plain sweeps finished the solve)          */
   FNLH_E_ARG = -1,        /* invalid argument                                   */
   FNLH_E_MESH = -2,       /* invalid mesh (ids, duplicates, volumes, colouring) */
   FNLH_E_SINGULAR = -3,   /* a diagonal block to invert is singular / not finite */
@@ -202,7 +206,10 @@ typedef struct {
  * residual of x and dx the network's output for r, x <- x + alpha dx with the complex
  * alpha minimising ||r - alpha K_s dx||.  The FP64 residual judges every correction:
  * one that is not finite or lowers ||r||^2 by less than 0.1% is rejected (counted in
- * fallbacks) and the sweeps go on from the unchanged x.
+ * fallbacks) and the sweeps go on from the unchanged x.  After three rejections in a row
+ * a system gets no more corrections in this call (the network is not evaluated for it
+ * any more; an accepted correction resets the run), and if it then converges its
+ * status is FNLH_FELL_BACK.
  *
  * Solve n systems: sys[j] indexes the omega table, x[j] (in: x0, out: x) and b[j] are
  * device [N][6] complex128 user-order buffers (host arrays of n device pointers).
@@ -442,8 +449,10 @@ int fnlh_rk_harmonic(fnlh_ctx c, int32_t sys, double* qhat, const double* fhat, 
  * it at the latest. */
 typedef struct fnlh_nn_s* fnlh_nn;
 enum { FNLH_NN_PARAMS = 26624 };
-/* Attach a network to c (one per context; FNLH_E_ORDER if c has one).  Weights unset. */
-int fnlh_nn_create(fnlh_nn* out, fnlh_ctx c);
+/* Attach a network to c (one per context; FNLH_E_ORDER if c has one).  Weights unset.
+ * hidden: width of the hidden layers; the matrix-core tiles of the kernels are built for
+ * 64 (0 also means 64), any other value is FNLH_E_ARG. */
+int fnlh_nn_create(fnlh_nn* out, fnlh_ctx c, int32_t hidden);
 int fnlh_nn_destroy(fnlh_nn nn);
 /* host [FNLH_NN_PARAMS] FP32 weights in / out; setting them resets Adam.  Errors:
  * FNLH_E_ARG for non-finite values. */
@@ -467,6 +476,23 @@ int fnlh_nn_loss_grad(fnlh_nn nn, int32_t n, const int32_t* sys, const double* c
 int fnlh_nn_add_pairs(fnlh_nn nn, int32_t n, const int32_t* sys, const double* const* r,
                       const double* const* e, void* stream);
 int fnlh_nn_reserve_pairs(fnlh_nn nn, int64_t n_pairs, void* stream);
+/* Training pairs from the plain solver, generated in the library and appended to the
+ * pool (n * starts * snapshots pairs).  With b = 0 the solution is 0, so an iterate is
+ * minus its own error and its residual is -K_s x: for each start k (0 <= k < starts),
+ * the n systems sys[j] (1 <= n <= 16) start from x0 with the 12 N user-order values
+ * 2u - 1, u = (mix(key + v) >> 11) 2^-53 for value v, key = mix(seed +
+ * 0x9E3779B97F4A7C15 (j starts + k + 1)), mix the splitmix64 finaliser (Steele, Lea and
+ * Flood 2014); then `snapshots` times: `every` sweeps of fnlh_relax over the n systems
+ * together (FNLH_DILU, b = 0, rtol 0, check_every 16, graph replay), and for each j
+ * r = fnlh_residual(sys[j], x, 0) = -K_s x and e = -x stored as one pair.  The pairs
+ * are the ones that sequence of fnlh_relax, fnlh_residual and fnlh_nn_add_pairs calls
+ * would store.  Allocates and frees n + 2 vectors of 96 N bytes; synchronises the stream.
+ * Needs the matrix and harmonics, not weights. */
+int fnlh_nn_generate(fnlh_nn nn, int32_t n, const int32_t* sys, int32_t starts, int32_t snapshots,
+                     int32_t every, uint64_t seed, void* stream);
+/* Read stored pair k back: sys host out (may be NULL), r and e device [N][6] complex128
+ * user order (may be NULL), the BF16 values widened to FP64. */
+int fnlh_nn_get_pair(fnlh_nn nn, int64_t k, int32_t* sys, double* r, double* e, void* stream);
 int fnlh_nn_clear_pairs(fnlh_nn nn);
 int fnlh_nn_pairs(fnlh_nn nn, int64_t* n_pairs);
 /* steps Adam steps on batches of `batch` pairs drawn with replacement (splitmix64 from
@@ -474,6 +500,16 @@ int fnlh_nn_pairs(fnlh_nn nn, int64_t* n_pairs);
  * update.  Synchronises the stream. */
 int fnlh_nn_train(fnlh_nn nn, int32_t steps, int32_t batch, float lr, uint64_t seed, float* loss,
                   void* stream);
+/* Checkpoint of the network: a binary file with the tag "FNLHNN01", the hidden width
+ * and parameter count (int32 each), the Adam step count (int64), then the FP32 master
+ * weights, Adam's first and second moments (FNLH_NN_PARAMS float32 each), little-endian.
+ * fnlh_nn_load restores all of it (weights, moments, step count), so training resumes
+ * exactly where the saved network stopped.  The pair pool is not part of it.  Errors:
+ * FNLH_E_ORDER (save before weights are set), FNLH_E_ARG (file cannot be opened, a
+ * write fails, or the file is not a checkpoint of this network: tag, sizes, length,
+ * non-finite values). */
+int fnlh_nn_save(fnlh_nn nn, const char* path);
+int fnlh_nn_load(fnlh_nn nn, const char* path);
 /* Matrix-core check: out = A B for 64x64 BF16 operands (host a [64][64], host bt = B^T
  * [64][64], raw BF16 bits), FP32 out [64][64], computed by the network's tile routine. */
 int fnlh_nn_selftest(fnlh_ctx c, const uint16_t* a, const uint16_t* bt, float* out);

@@ -21,7 +21,10 @@ x = 0 (one step is exactly M^-1 v for the DILU, SGS or Jacobi M).  kind "LEARNED
 project addition: the flexible method admits a nonlinear M_j): z0 = alpha d with d =
 net(v) the learned correction for the residual v and alpha from learned.line_step (0 when
 the step is rejected), then `inner_sweeps` DILU steps of the Richardson iteration on
-A z = v starting from z0.  The inner products
+A z = v starting from z0.  After OFF_AFTER applications in a row whose step was rejected
+the network is not evaluated again in this solve (alpha = 0 from then on; a kept step
+ends a run of rejections): the controller of the learned part, also a project
+addition.  The inner products
 are (u, v) = sum conj(u) v over all 6N complex entries; the stop test is
 ||r|| <= rtol ||r0|| on the least-squares residual norm, or iters = max_iters.
 """
@@ -40,6 +43,10 @@ class KrylovInfo:
     history: list = field(default_factory=list)   # residual norm after each iteration (index 0: ||r0||)
     true_res: float = 0.0                          # ||b - A x|| of the returned x, relative
     learned: int = 0                               # LEARNED: applications that kept the step
+    switched_off: bool = False                     # LEARNED: the controller stopped the network
+
+
+OFF_AFTER = 3   # rejected learned steps in a row after which the network is not evaluated
 
 
 def _lstsq_min(Hbar, beta):
@@ -60,6 +67,7 @@ def fgmres(K, volume, zone, omega_row, b, colour, kind="DILU", x0=None, restart=
     if kind == "LEARNED" and net is None:
         raise ValueError("kind LEARNED needs net")
     kept = [0]
+    run = [0, False]    # rejections in a row, switched off
 
     def A(v):
         return solve.apply(K, Ds, v)
@@ -67,10 +75,17 @@ def fgmres(K, volume, zone, omega_row, b, colour, kind="DILU", x0=None, restart=
     def M_inv(v):
         z0, sweep_kind = None, kind
         if kind == "LEARNED":
-            d = net(v)
-            alpha, _ = learned.line_step(A, v, d)
-            kept[0] += alpha != 0.0
-            z0, sweep_kind = alpha * d, "DILU"
+            sweep_kind = "DILU"
+            if not run[1]:
+                d = net(v)
+                alpha, _ = learned.line_step(A, v, d)
+                if alpha != 0.0:
+                    kept[0] += 1
+                    run[0] = 0
+                    z0 = alpha * d
+                else:
+                    run[0] += 1
+                    run[1] = run[0] >= OFF_AFTER
         z, _ = solve.richardson(K, volume, zone, omega_row, v, colour, sweep_kind, x0=z0, rtol=0.0,
                                 max_sweeps=inner_sweeps, div_factor=np.inf)
         return z
@@ -118,4 +133,4 @@ def fgmres(K, volume, zone, omega_row, b, colour, kind="DILU", x0=None, restart=
         if beta == 0.0:
             break
     true_rel = float(np.linalg.norm(b - A(x)) / n0) if n0 > 0 else 0.0
-    return x, KrylovInfo(status, iters, res / n0 if n0 > 0 else 0.0, hist, true_rel, kept[0])
+    return x, KrylovInfo(status, iters, res / n0 if n0 > 0 else 0.0, hist, true_rel, kept[0], run[1])

@@ -666,8 +666,15 @@ int relax_finish_launch(fnlh_ctx c, int n, const int32_t* sys, double* const* x,
   return check_launch(c, "final launch");
 }
 
+// Severity order of the per-system outcomes: OK < FELL_BACK < NOT_CONVERGED < DIVERGED.
+int status_rank(int st) {
+  return st == FNLH_OK ? 0 : st == FNLH_FELL_BACK ? 1 : st == FNLH_NOT_CONVERGED ? 2 : 3;
+}
+int worse_status(int a, int b) { return status_rank(b) > status_rank(a) ? b : a; }
+
+// c: the context whose network's controller reports systems switched off (learned kind)
 int relax_reports(const SysState* h, int n, const RelaxPlan& P, const fnlh_relax_opts* o, fnlh_sys_report* rep,
-                  const int* counts = nullptr) {
+                  const int* counts = nullptr, fnlh_ctx c = nullptr) {
   int worst = FNLH_OK;
   for (int j = 0; j < n; ++j) {
     const SysState& S0 = h[j];
@@ -680,6 +687,7 @@ int relax_reports(const SysState* h, int n, const RelaxPlan& P, const fnlh_relax
     int status = S0.status;
     if (status != FNLH_DIVERGED) status = (R.rel_res <= o->rtol) ? FNLH_OK : FNLH_NOT_CONVERGED;
     if (!std::isfinite(R.rel_res)) status = FNLH_DIVERGED;
+    if (status == FNLH_OK && counts && c && nn_system_off(c, j)) status = FNLH_FELL_BACK;
     R.status = status;
     R.t_factor_ms = P.tf.empty() ? 0.0 : P.tf[j];
     R.t_sweep_ms = P.ts.empty() ? 0.0 : P.ts[j];
@@ -688,7 +696,7 @@ int relax_reports(const SysState* h, int n, const RelaxPlan& P, const fnlh_relax
       R.fallbacks = counts[2 * j + 1];
     }
     if (rep) rep[j] = R;
-    if (status == FNLH_DIVERGED || (status == FNLH_NOT_CONVERGED && worst == FNLH_OK)) worst = status;
+    worst = worse_status(worst, status);
   }
   return worst;
 }
@@ -1411,7 +1419,7 @@ int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, cons
     counts.assign(2 * n, 0);
     if ((rc = nn_relax_counts(c, n, counts.data(), s))) return rc;
   }
-  return relax_reports(c->h_st, n, P, o, rep, P.learned ? counts.data() : nullptr);
+  return relax_reports(c->h_st, n, P, o, rep, P.learned ? counts.data() : nullptr, c);
 }
 
 
@@ -1676,7 +1684,7 @@ int fnlh_batch_relax(fnlh_batch B, const int32_t* n_sys, const int32_t* const* s
   int worst = FNLH_OK;
   auto fold = [&](int r) {
     if (r < 0) return;
-    if (r == FNLH_DIVERGED || (r == FNLH_NOT_CONVERGED && worst == FNLH_OK)) worst = r;
+    worst = worse_status(worst, r);
   };
   for (int i = 0; i < n; ++i) {
     if (!batched[i]) continue;
@@ -1689,7 +1697,7 @@ int fnlh_batch_relax(fnlh_batch B, const int32_t* n_sys, const int32_t* const* s
       }
     }
     fold(relax_reports(B->h_st + base[i], n_sys[i], plans[i], o, rep ? rep + base[i] : nullptr,
-                       plans[i].learned ? counts.data() : nullptr));
+                       plans[i].learned ? counts.data() : nullptr, B->inst[i]));
   }
   // the rest one by one
   for (int i = 0; i < n; ++i) {

@@ -155,6 +155,9 @@ int nn_relax_begin(fnlh_ctx c, int ns, hipStream_t s);
 int nn_learned_step(fnlh_ctx c, int ns, const SysBatch& sb, double* x, const double* b, double* r,
                     const SysState* st, hipStream_t s);
 int nn_relax_counts(fnlh_ctx c, int ns, int* host_counts, hipStream_t s);
+// true when system slot vs had its learned corrections switched off in this call
+// (rejected three times in a row): the plain sweeps carried it on
+bool nn_system_off(fnlh_ctx c, int vs);
 // the learned step's residual scratch, [NP][ns][12] FP64: where nn_learned_step is
 // called with r null it computes b - K x there, and either way it leaves b - K x of the
 // corrected x in the r it was given

@@ -316,6 +316,7 @@ int fnlh_gmres(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, cons
   if (pp.learned && (rc = nn_relax_counts(c, n, counts.data(), s))) return rc;
   int worst = FNLH_OK;
   for (int k = 0; k < n; ++k) {
+    if (pp.learned && status[k] == FNLH_OK && nn_system_off(c, k)) status[k] = FNLH_FELL_BACK;
     if (rep) {
       rep[k].iters = iters[k];
       rep[k].restarts = restarts[k];
@@ -326,7 +327,8 @@ int fnlh_gmres(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, cons
       rep[k].t_ms = ms;
     }
     if (status[k] == FNLH_DIVERGED) worst = FNLH_DIVERGED;
-    else if (status[k] == FNLH_NOT_CONVERGED && worst == FNLH_OK) worst = FNLH_NOT_CONVERGED;
+    else if (status[k] == FNLH_NOT_CONVERGED && worst != FNLH_DIVERGED) worst = FNLH_NOT_CONVERGED;
+    else if (status[k] == FNLH_FELL_BACK && worst == FNLH_OK) worst = FNLH_FELL_BACK;
   }
   return worst;
 }

@@ -4,7 +4,9 @@
 // reduction, Adam, the corrected update) is a kernel of nn.hip.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <vector>
 
 #include "ctx.h"
 #include "nn.h"
@@ -23,7 +25,12 @@ struct fnlh_nn_s {
   int step_cap = 0;
   int G = 0;
   int adam_t = 0;
+  int hidden = 64;
   bool weights_set = false;
+  // per call of relax / gmres: counts seen after the last step, rejections in a row,
+  // and the systems whose corrections are switched off for the rest of the call
+  std::vector<int> prev_acc, prev_rej, consec, off;
+  std::vector<int> hcounts;
 };
 
 namespace {
@@ -31,6 +38,8 @@ namespace {
 constexpr float kB1 = 0.9f, kB2 = 0.999f, kEps = 1e-8f;
 constexpr double kAccept = 1e-3;  // minimum fractional drop of ||r||^2 for a learned step
 constexpr int kMaxG = 512;        // workgroups of the backward kernels (gradient partials)
+constexpr int kOffAfter = 3;      // rejected learned corrections in a row that switch a system's off
+constexpr char kMagic[8] = {'F', 'N', 'L', 'H', 'N', 'N', '0', '1'};  // checkpoint file tag
 
 inline hipStream_t S(void* s) { return (hipStream_t)s; }
 
@@ -178,13 +187,41 @@ int nn_relax_begin(fnlh_ctx c, int ns, hipStream_t s) {
   if (!nn->part4.p && (rc = dalloc(c, nn->part4, (size_t)c->L.n_tiles * 4 * sizeof(double), "alloc learned step")))
     return rc;
   launch_fill_zero(nn->counts.p, (size_t)ns * 2 * sizeof(int), s);
+  nn->prev_acc.assign(ns, 0);
+  nn->prev_rej.assign(ns, 0);
+  nn->consec.assign(ns, 0);
+  nn->off.assign(ns, 0);
+  nn->hcounts.assign(2 * ns, 0);
   return check_launch(c, "learned step setup");
 }
 
-int nn_learned_step(fnlh_ctx c, int ns, const SysBatch& sb, double* x, const double* b, double* r,
+bool nn_system_off(fnlh_ctx c, int vs) {
+  fnlh_nn nn = c->nn;
+  return nn && vs >= 0 && vs < (int)nn->off.size() && nn->off[vs] != 0;
+}
+
+int nn_learned_step(fnlh_ctx c, int ns, const SysBatch& sb0, double* x, const double* b, double* r,
                     const SysState* st, hipStream_t s) {
   fnlh_nn nn = c->nn;
   const DevPattern p = c->pat();
+  if ((int)nn->off.size() < ns) {  // first step of a call that did not clear the controller
+    nn->prev_acc.resize(ns, 0);
+    nn->prev_rej.resize(ns, 0);
+    nn->consec.resize(ns, 0);
+    nn->off.resize(ns, 0);
+    nn->hcounts.resize(2 * ns, 0);
+  }
+  // systems whose corrections were rejected kOffAfter times in a row get none
+  SysBatch sb = sb0;
+  sb.n = 0;
+  for (int k = 0; k < sb0.n; ++k) {
+    if (nn->off[sb0.vslot[k]]) continue;
+    sb.orow[sb.n] = sb0.orow[k];
+    sb.vslot[sb.n] = sb0.vslot[k];
+    sb.dslot[sb.n] = sb0.dslot[k];
+    sb.n++;
+  }
+  if (sb.n == 0) return FNLH_OK;
   double* res = r;
   if (!res) {
     res = (double*)nn->rr.p;
@@ -209,7 +246,24 @@ int nn_learned_step(fnlh_ctx c, int ns, const SysBatch& sb, double* x, const dou
   for (int k = 0; k < sb.n; ++k)
     nn_launch_step(p, x, (const double*)nn->xt.p, res, (const double*)nn->rn.p, ns, sb.vslot[k], st,
                    (double*)nn->part4.p, (double*)nn->alpha.p, (int*)nn->counts.p, kAccept, s);
-  return check_launch(c, "learned step launch");
+  int rc = check_launch(c, "learned step launch");
+  if (rc) return rc;
+  // the controller: a rejection extends a system's run of rejections, an acceptance ends it
+  HIPC(c, hipMemcpyAsync(nn->hcounts.data(), nn->counts.p, (size_t)ns * 2 * sizeof(int), hipMemcpyDeviceToHost, s),
+       "read counts");
+  HIPC(c, hipStreamSynchronize(s), "counts sync");
+  for (int k = 0; k < sb.n; ++k) {
+    const int vs = sb.vslot[k];
+    const int acc = nn->hcounts[2 * vs], rej = nn->hcounts[2 * vs + 1];
+    if (rej > nn->prev_rej[vs]) {
+      if (++nn->consec[vs] >= kOffAfter) nn->off[vs] = 1;
+    } else if (acc > nn->prev_acc[vs]) {
+      nn->consec[vs] = 0;
+    }
+    nn->prev_acc[vs] = acc;
+    nn->prev_rej[vs] = rej;
+  }
+  return FNLH_OK;
 }
 
 double* nn_step_residual(fnlh_ctx c) { return (double*)c->nn->rr.p; }
@@ -225,9 +279,11 @@ int nn_relax_counts(fnlh_ctx c, int ns, int* host_counts, hipStream_t s) {
 
 extern "C" {
 
-int fnlh_nn_create(fnlh_nn* out, fnlh_ctx c) {
+int fnlh_nn_create(fnlh_nn* out, fnlh_ctx c, int32_t hidden) {
   if (!out || !c) return FNLH_E_ARG;
   *out = nullptr;
+  if (hidden != 0 && hidden != 64)
+    return set_err(c, FNLH_E_ARG, "network: hidden width 64 only (the matrix-core tiles are built for it)");
   if (c->nn) return set_err(c, FNLH_E_ORDER, "network: context already has one");
   fnlh_nn nn = new fnlh_nn_s();
   nn->c = c;
@@ -360,8 +416,8 @@ int fnlh_nn_add_pairs(fnlh_nn nn, int32_t n, const int32_t* sys, const double* c
   const DevPattern p = c->pat();
   for (int k = 0; k < n; ++k) {
     uint16_t* dst = (uint16_t*)nn->pool.p + (size_t)(nn->n_pairs + k) * pair;
-    nn_launch_pack16(p, (const int32_t*)c->iperm.p, r[k], dst, s);
-    nn_launch_pack16(p, (const int32_t*)c->iperm.p, e[k], dst + pair / 2, s);
+    nn_launch_pack16(p, (const int32_t*)c->iperm.p, r[k], 1.0, dst, s);
+    nn_launch_pack16(p, (const int32_t*)c->iperm.p, e[k], 1.0, dst + pair / 2, s);
     nn->pair_sys.push_back(sys[k]);
   }
   nn->n_pairs += n;
@@ -440,6 +496,143 @@ int fnlh_nn_train(fnlh_nn nn, int32_t steps, int32_t batch, float lr, uint64_t s
   }
   dfree(hist);
   return rc;
+}
+
+int fnlh_nn_generate(fnlh_nn nn, int32_t n, const int32_t* sys, int32_t starts, int32_t snapshots, int32_t every,
+                     uint64_t seed, void* stream) {
+  if (!nn) return FNLH_E_ARG;
+  if (!nn->c) return FNLH_E_ORDER;
+  fnlh_ctx c = nn->c;
+  if (!c->have_matrix || c->n_sys == 0) return set_err(c, FNLH_E_ORDER, "generate: matrix and harmonics first");
+  if (n < 1 || n > 16 || !sys || starts < 1 || snapshots < 1 || every < 1)
+    return set_err(c, FNLH_E_ARG, "generate: need 1..16 systems and starts, snapshots, every >= 1");
+  for (int j = 0; j < n; ++j)
+    if (sys[j] < 0 || sys[j] >= c->n_sys) return set_err(c, FNLH_E_ARG, "generate: system out of range");
+  hipStream_t s = S(stream);
+  const int64_t N = c->L.N;
+  const size_t vb = (size_t)N * 12 * sizeof(double);
+  const int64_t add = (int64_t)n * starts * snapshots;
+  int rc;
+  if (nn->n_pairs + add > nn->cap_pairs && (rc = grow_pairs(nn, nn->n_pairs + add, s))) return rc;
+  DevBuf X, Z, R;
+  if ((rc = dalloc(c, X, (size_t)n * vb, "alloc generate"))) return rc;
+  if ((rc = dalloc(c, Z, vb, "alloc generate")) || (rc = dalloc(c, R, vb, "alloc generate"))) {
+    dfree(X);
+    dfree(Z);
+    return rc;
+  }
+  launch_fill_zero(Z.p, vb, s);
+  std::vector<double*> xp(n);
+  std::vector<const double*> zp(n, (const double*)Z.p);
+  for (int j = 0; j < n; ++j) xp[j] = (double*)X.p + (size_t)j * N * 12;
+  fnlh_relax_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.kind = FNLH_DILU;
+  o.max_sweeps = every;
+  o.rtol = 0.0;
+  o.check_every = 16;
+  o.use_graph = 1;
+  const DevPattern p = c->pat();
+  const size_t pair = (size_t)2 * c->L.NP * 12;  // BF16 values
+  rc = FNLH_OK;
+  for (int k = 0; k < starts && rc >= 0; ++k) {
+    for (int j = 0; j < n; ++j) nn_launch_uniform(N * 12, nn_start_key(seed, (int64_t)j * starts + k), xp[j], s);
+    for (int t = 0; t < snapshots && rc >= 0; ++t) {
+      rc = fnlh_relax(c, n, sys, xp.data(), zp.data(), &o, nullptr, s);
+      for (int j = 0; j < n && rc >= 0; ++j) {
+        rc = fnlh_residual(c, sys[j], xp[j], (const double*)Z.p, (double*)R.p, nullptr, s);
+        if (rc < 0) break;
+        uint16_t* dst = (uint16_t*)nn->pool.p + (size_t)nn->n_pairs * pair;
+        nn_launch_pack16(p, (const int32_t*)c->iperm.p, (const double*)R.p, 1.0, dst, s);
+        nn_launch_pack16(p, (const int32_t*)c->iperm.p, xp[j], -1.0, dst + pair / 2, s);  // e = x* - x = -x
+        nn->pair_sys.push_back(sys[j]);
+        nn->n_pairs++;
+      }
+    }
+  }
+  if (rc >= 0) rc = check_launch(c, "generate launch");
+  const hipError_t e = hipStreamSynchronize(s);
+  dfree(X);
+  dfree(Z);
+  dfree(R);
+  if (rc < 0) return rc;
+  if (e != hipSuccess) return hip_fail(c, e, "generate sync");
+  return FNLH_OK;
+}
+
+int fnlh_nn_get_pair(fnlh_nn nn, int64_t k, int32_t* sys, double* r, double* e, void* stream) {
+  if (!nn) return FNLH_E_ARG;
+  if (!nn->c) return FNLH_E_ORDER;
+  fnlh_ctx c = nn->c;
+  if (k < 0 || k >= nn->n_pairs) return set_err(c, FNLH_E_ARG, "get_pair: index out of range");
+  if (sys) *sys = nn->pair_sys[k];
+  const size_t pair = (size_t)2 * c->L.NP * 12;
+  const uint16_t* base = (const uint16_t*)nn->pool.p + (size_t)k * pair;
+  const DevPattern p = c->pat();
+  hipStream_t s = S(stream);
+  if (r) nn_launch_unpack16(p, (const int32_t*)c->iperm.p, base, r, s);
+  if (e) nn_launch_unpack16(p, (const int32_t*)c->iperm.p, base + pair / 2, e, s);
+  return check_launch(c, "get_pair launch");
+}
+
+namespace {
+struct CkptHead {
+  char magic[8];
+  int32_t hidden, n_params;
+  int64_t adam_t;
+};
+}  // namespace
+
+int fnlh_nn_save(fnlh_nn nn, const char* path) {
+  if (!nn || !path) return FNLH_E_ARG;
+  if (!nn->c) return FNLH_E_ORDER;
+  fnlh_ctx c = nn->c;
+  if (!nn->weights_set) return set_err(c, FNLH_E_ORDER, "save: weights not set");
+  std::vector<float> buf(3 * (size_t)kNnParams);
+  HIPC(c, hipDeviceSynchronize(), "save sync");
+  HIPC(c, hipMemcpy(buf.data(), nn->master.p, kNnParams * sizeof(float), hipMemcpyDeviceToHost), "read master");
+  HIPC(c, hipMemcpy(buf.data() + kNnParams, nn->mom1.p, kNnParams * sizeof(float), hipMemcpyDeviceToHost), "read m");
+  HIPC(c, hipMemcpy(buf.data() + 2 * kNnParams, nn->mom2.p, kNnParams * sizeof(float), hipMemcpyDeviceToHost),
+       "read v");
+  CkptHead h;
+  std::memcpy(h.magic, kMagic, 8);
+  h.hidden = nn->hidden;
+  h.n_params = kNnParams;
+  h.adam_t = nn->adam_t;
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return set_err(c, FNLH_E_ARG, "save: cannot open the file for writing");
+  bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1 && std::fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? FNLH_OK : set_err(c, FNLH_E_ARG, "save: write failed");
+}
+
+int fnlh_nn_load(fnlh_nn nn, const char* path) {
+  if (!nn || !path) return FNLH_E_ARG;
+  if (!nn->c) return FNLH_E_ORDER;
+  fnlh_ctx c = nn->c;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return set_err(c, FNLH_E_ARG, "load: cannot open the file");
+  CkptHead h;
+  std::vector<float> buf(3 * (size_t)kNnParams);
+  bool ok = std::fread(&h, sizeof(h), 1, f) == 1;
+  ok = ok && std::memcmp(h.magic, kMagic, 8) == 0 && h.hidden == nn->hidden && h.n_params == kNnParams &&
+       h.adam_t >= 0 && h.adam_t < (int64_t)1 << 30;
+  ok = ok && std::fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+  char extra;
+  ok = ok && std::fread(&extra, 1, 1, f) == 0;  // nothing after the moments
+  std::fclose(f);
+  if (!ok) return set_err(c, FNLH_E_ARG, "load: not a checkpoint of this network (tag, sizes or length)");
+  for (float v : buf)
+    if (!std::isfinite(v)) return set_err(c, FNLH_E_ARG, "load: non-finite values");
+  HIPC(c, hipMemcpy(nn->master.p, buf.data(), kNnParams * sizeof(float), hipMemcpyHostToDevice), "upload");
+  HIPC(c, hipMemcpy(nn->mom1.p, buf.data() + kNnParams, kNnParams * sizeof(float), hipMemcpyHostToDevice), "upload");
+  HIPC(c, hipMemcpy(nn->mom2.p, buf.data() + 2 * kNnParams, kNnParams * sizeof(float), hipMemcpyHostToDevice),
+       "upload");
+  nn_launch_cast((const float*)nn->master.p, (uint16_t*)nn->wt.p, (uint16_t*)nn->w.p, nullptr);
+  HIPC(c, hipDeviceSynchronize(), "cast weights");
+  nn->adam_t = (int)h.adam_t;
+  nn->weights_set = true;
+  return check_launch(c, "cast weights");
 }
 
 int fnlh_nn_selftest(fnlh_ctx c, const uint16_t* a, const uint16_t* bt, float* out) {

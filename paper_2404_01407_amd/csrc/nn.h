@@ -86,8 +86,15 @@ void nn_launch_backward(int storage, const DevPattern& p, const void* offd, cons
 void nn_launch_grad_reduce(const NnBufs& B, int G, float* grad_packed, double* loss_out, hipStream_t s);
 void nn_launch_adam(float* w, float* m, float* v, const float* g, int n, float lr, float b1, float b2, float eps,
                     int t, hipStream_t s);
-// FP64 user-order vector -> BF16 internal [NP][12] (training pairs)
-void nn_launch_pack16(const DevPattern& p, const int32_t* iperm, const double* user, uint16_t* out, hipStream_t s);
+// sign x FP64 user-order vector -> BF16 internal [NP][12] (training pairs), and back to FP64
+void nn_launch_pack16(const DevPattern& p, const int32_t* iperm, const double* user, double sign, uint16_t* out,
+                      hipStream_t s);
+void nn_launch_unpack16(const DevPattern& p, const int32_t* iperm, const uint16_t* in, double* user, hipStream_t s);
+// Random starts of generated pairs: x[v] = 2 u - 1 with u = (mix(key + v) >> 11) 2^-53,
+// key = nn_start_key(seed, start) = mix(seed + 0x9E3779B97F4A7C15 (start + 1)), mix the
+// splitmix64 finaliser.
+uint64_t nn_start_key(uint64_t seed, int64_t start);
+void nn_launch_uniform(int64_t n, uint64_t key, double* x, hipStream_t s);
 // learned step, per system slot vs: y = r - rn; alpha = <y, r> / <y, y> if that lowers
 // ||r||^2 by at least the fraction accept and the system is active, else 0;
 // x <- x + alpha (xt - x), r <- r - alpha y

@@ -482,11 +482,37 @@ __global__ void k_nn_output(int64_t NP, NnBufs B, NnOut o) {
 // BF16 keeps the exponent range of FP32, so pairs need no scaling (the loss is
 // scale-free as long as r and e share one factor)
 __global__ void k_nn_pack16(int64_t NP, const int32_t* __restrict__ iperm, const double* __restrict__ user,
-                            uint16_t* __restrict__ out) {
+                            double sign, uint16_t* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= NP * 12) return;
   const int32_t u = iperm[t / 12];
-  out[t] = u < 0 ? (uint16_t)0 : f2bf((float)user[(int64_t)u * 12 + t % 12]);
+  out[t] = u < 0 ? (uint16_t)0 : f2bf((float)(sign * user[(int64_t)u * 12 + t % 12]));
+}
+
+// stored BF16 pair vector (internal order) -> FP64 user order
+__global__ void k_nn_unpack16(int64_t NP, const int32_t* __restrict__ iperm, const uint16_t* __restrict__ in,
+                              double* __restrict__ user) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= NP * 12) return;
+  const int32_t u = iperm[t / 12];
+  if (u >= 0) user[(int64_t)u * 12 + t % 12] = (double)bf2f(in[t]);
+}
+
+// splitmix64 finaliser (Steele, Lea and Flood, "Fast splittable pseudorandom number
+// generators", 2014)
+__device__ inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// x[v] = 2 u - 1, u = (mix64(key + v) >> 11) 2^-53 uniform on [0, 1): counter-based, so
+// any value can be recomputed on its own
+__global__ void k_nn_uniform(int64_t n, uint64_t key, double* __restrict__ x) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const double u = (double)(mix64(key + (uint64_t)v) >> 11) * 0x1.0p-53;
+  x[v] = 2.0 * u - 1.0;
 }
 
 // learned step: partial sums per tile of <y, r> (re, im), |y|^2, |r|^2 with y = r - rn
@@ -879,9 +905,26 @@ void nn_launch_output(const DevPattern& p, const NnBufs& B, const NnOut& o, hipS
   hipLaunchKernelGGL(k_nn_output, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p.NP, B, o);
 }
 
-void nn_launch_pack16(const DevPattern& p, const int32_t* iperm, const double* user, uint16_t* out, hipStream_t s) {
+void nn_launch_pack16(const DevPattern& p, const int32_t* iperm, const double* user, double sign, uint16_t* out,
+                      hipStream_t s) {
   const int64_t n = p.NP * 12;
-  hipLaunchKernelGGL(k_nn_pack16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p.NP, iperm, user, out);
+  hipLaunchKernelGGL(k_nn_pack16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p.NP, iperm, user, sign, out);
+}
+
+void nn_launch_unpack16(const DevPattern& p, const int32_t* iperm, const uint16_t* in, double* user, hipStream_t s) {
+  const int64_t n = p.NP * 12;
+  hipLaunchKernelGGL(k_nn_unpack16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p.NP, iperm, in, user);
+}
+
+uint64_t nn_start_key(uint64_t seed, int64_t start) {
+  uint64_t z = seed + 0x9e3779b97f4a7c15ull * (uint64_t)(start + 1);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+void nn_launch_uniform(int64_t n, uint64_t key, double* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_nn_uniform, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, key, x);
 }
 
 void nn_launch_step(const DevPattern& p, double* x, const double* xt, double* r, const double* rn, int ns, int vs,

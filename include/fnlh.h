@@ -221,6 +221,26 @@ int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x,
                const double* const* b, const fnlh_relax_opts* opts, fnlh_sys_report* rep,
                void* stream);
 
+/* The residual of fnlh_residual without allocating: for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Computes r = b - K_s x with the same kernels and the same summation order
+ * as fnlh_residual (bitwise the same r and norm), but its staging vectors, per-tile
+ * partials and reduction state live in a file-scope device array of
+ * fnlh_noalloc_scratch_bytes() bytes (64 MiB) that each device holds from the library's
+ * first context on it until the process ends, instead of buffers the context allocates.
+ * No hipMalloc, hipFree or allocating library call; no host synchronisation.
+ *   x, b device [N][6] complex128 user order (caller-owned); r device [N][6] or NULL;
+ *   norm2 DEVICE double [1] or NULL: receives ||r||_2^2 (stream-ordered).
+ * The scratch holds 2 (3 with r) vectors of 96 x padded rows plus 8 bytes per 64-row
+ * tile: at most about 233,000 cells with r; a larger mesh returns FNLH_E_ARG with the
+ * needed size.  Every call on one device shares that device's array and leaves its
+ * contents behind (nothing is read before it is written in the next call): calls that
+ * overlap on one device (two streams, two host threads) race and give wrong results.
+ * Needs matrix and harmonics (FNLH_E_ORDER). */
+int fnlh_residual_noalloc(fnlh_ctx c, int32_t sys, const double* x, const double* b, double* r,
+                          double* norm2, void* stream);
+size_t fnlh_noalloc_scratch_bytes(void);
+
 /* Ordering actually used: colour per cell (user order, host out [N]) and the count. */
 int fnlh_get_ordering(fnlh_ctx c, int32_t* colour_of_cell, int32_t* n_colours);
 

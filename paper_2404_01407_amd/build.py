@@ -10,7 +10,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libfnlh.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "nn.hip", "krylov.hip", "api.cpp", "nn.cpp", "rk.cpp", "krylov.cpp", "layout.cpp"]
+SOURCES = ["kernels.hip", "nn.hip", "krylov.hip", "noalloc.hip", "api.cpp", "nn.cpp", "rk.cpp", "krylov.cpp",
+           "layout.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

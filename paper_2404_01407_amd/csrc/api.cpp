@@ -58,9 +58,9 @@ int check_launch(fnlh_ctx c, const char* what) {
 }
 
 void outer_residual_of(fnlh_ctx c, int ns, const SysBatch& sb, const double* x, const double* b, double* r,
-                       hipStream_t s) {
+                       hipStream_t s, double* part) {
   DevPattern p = c->pat();
-  double* part = (double*)c->partial.p;
+  if (!part) part = (double*)c->partial.p;
   if (c->storage == FNLH_F64) {
     launch_resid_stored(kF64, p, c->offd.p, c->diag.p, x, b, r, ns, sb, part, s);
   } else if (c->outer == FNLH_OUTER_STORED) {
@@ -926,6 +926,7 @@ int fnlh_create(fnlh_ctx* out, const fnlh_mesh* mesh, const fnlh_options* opts) 
     hip_fail(c, he, "hipSetDevice");
     return fail(FNLH_E_HIP);
   }
+  if ((rc = noalloc_init(c))) return fail(rc);
   const Layout& L = c->L;
   if ((rc = dupload(c, c->tile_nrows, L.tile_nrows, "pattern"))) return fail(rc);
   if ((rc = dupload(c, c->tile_width, L.tile_width, "pattern"))) return fail(rc);

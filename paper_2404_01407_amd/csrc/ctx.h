@@ -140,8 +140,14 @@ int dalloc(fnlh_ctx c, DevBuf& b, size_t bytes, const char* what);
 void dfree(DevBuf& b);
 int check_launch(fnlh_ctx c, const char* what);
 // outer FP64 operator residual of the systems of sb (x, b internal -> r, c->partial)
+// (per-tile norm partials into part, c->partial when null)
 void outer_residual_of(fnlh_ctx c, int ns, const SysBatch& sb, const double* x, const double* b, double* r,
-                       hipStream_t s);
+                       hipStream_t s, double* part = nullptr);
+// The no-allocation residual (noalloc.hip): device address of its scratch array on the
+// context's device, looked up once per device at context creation; the scratch bytes a
+// mesh needs.
+int noalloc_init(fnlh_ctx c);
+size_t noalloc_residual_bytes(const Layout& L, bool with_r);
 
 // Learned preconditioner inside fnlh_relax (nn.cpp).  nn_relax_begin checks that a
 // network with weights is attached, sizes its scratch for ns systems and clears the

@@ -106,6 +106,8 @@ def _load():
         "fnlh_rk_harmonic": (I32, [P, I32, V, V, I32, C.POINTER(RelaxOpts), V, V]),
         "fnlh_residual": (I32, [P, I32, V, V, V, C.POINTER(D), V]),
         "fnlh_relax": (I32, [P, I32, V, V, V, C.POINTER(RelaxOpts), V, V]),
+        "fnlh_residual_noalloc": (I32, [P, I32, V, V, V, V, V]),
+        "fnlh_noalloc_scratch_bytes": (C.c_size_t, []),
         "fnlh_get_ordering": (I32, [P, V, C.POINTER(I32)]),
         "fnlh_memory": (I32, [P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
         "fnlh_last_error": (C.c_char_p, [P]),
@@ -308,6 +310,18 @@ class Context:
         n2 = C.c_double(0.0)
         self._check(LIB.fnlh_residual(self.h, int(sys), _ptr(x), _ptr(b), _ptr(r), C.byref(n2), _stream(stream)))
         return n2.value
+
+    def residual_noalloc(self, sys, x, b, r=None, norm2=None, stream=None):
+        """r = b - K_s x without device allocation (scratch held by the library); norm2:
+        a float64 CUDA tensor of one element receiving ||r||^2 on the device, or None."""
+        for t, nm in ((x, "x"), (b, "b")):
+            _dev_tensor(t, (self.n, 6), nm, device=self.device)
+        if r is not None:
+            _dev_tensor(r, (self.n, 6), "r", device=self.device)
+        if norm2 is not None:
+            _dev_tensor(norm2, (1,), "norm2", "float64", self.device)
+        self._check(LIB.fnlh_residual_noalloc(self.h, int(sys), _ptr(x), _ptr(b), _ptr(r), _ptr(norm2),
+                                              _stream(stream)))
 
     def relax(self, systems, xs, bs, kind="dilu", max_sweeps=500, rtol=1e-8, check_every=8,
               inner_sweeps=0, inner_rtol=0.0, div_factor=0.0, use_graph=False, learn_every=0, stream=None):

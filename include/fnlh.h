@@ -305,10 +305,14 @@ typedef struct {
 enum {
   FNLH_KSTAT_SWEEP_UPDATE = 0, /* two-colour pass over the second colour (reads K_ii) */
   FNLH_KSTAT_SWEEP_SET = 1,    /* two-colour pass over the first colour              */
-  FNLH_KSTAT_FWD = 2,          /* general colouring, forward pass                     */
+  FNLH_KSTAT_FWD = 2,          /* general colouring, forward pass (all but the last colour) */
   FNLH_KSTAT_BWD = 3,          /* general colouring, backward pass                    */
   FNLH_KSTAT_JACOBI = 4,       /* block Jacobi pass                                   */
-  FNLH_KSTAT_N = 5
+  FNLH_KSTAT_FWD_LAST = 5,     /* general colouring, forward pass of the last colour  */
+  FNLH_KSTAT_REMAINDER = 6,    /* two colours plus remainder: the passes over the
+                                  colours past the second and the correction of the
+                                  second colour's rows coupled to them                */
+  FNLH_KSTAT_N = 7
 };
 /* on >= 1 resets the counters and starts timing the launches of every on-th sweep
  * (1 = every launch; a larger period bounds the event overhead); on = 0 stops.
@@ -324,8 +328,18 @@ int fnlh_stats_get(fnlh_ctx c, int32_t which, fnlh_kernel_stats* out);
  *                           (0 = automatic: min(4, systems)).
  *   FNLH_TUNE_WAVE_GROUPS   two-colour pass workgroups: 1 = one wave per workgroup
  *                           (default; finer dispatch), 0 = one 64-row tile per
- *                           workgroup (its waves together); bitwise the same results. */
-enum { FNLH_TUNE_SYS_PER_LANE = 0, FNLH_TUNE_LANES_PER_ROW = 1, FNLH_TUNE_WAVE_GROUPS = 2 };
+ *                           workgroup (its waves together); bitwise the same results.
+ *   FNLH_TUNE_HYBRID        colourings with more than two colours whose colours past
+ *                           the second hold at most a quarter of the rows (e.g. the
+ *                           interface rows of a multi-row sector): 1 = sweep them as
+ *                           the two-colour passes plus passes over the remainder
+ *                           (default; each block of the first two colours read once per
+ *                           sweep), 0 = the general forward/backward passes, 2 = the
+ *                           hybrid passes for any colouring of three or more colours.
+ *                           The same preconditioner either way (equal iterates up to
+ *                           rounding).
+ */
+enum { FNLH_TUNE_SYS_PER_LANE = 0, FNLH_TUNE_LANES_PER_ROW = 1, FNLH_TUNE_WAVE_GROUPS = 2, FNLH_TUNE_HYBRID = 3 };
 int fnlh_tune(fnlh_ctx c, int32_t param, int32_t value);
 
 /* Autotuner: times `sweeps` preconditioned sweeps of the first n_sys systems (constant

@@ -157,13 +157,20 @@ int factor_batch(fnlh_ctx c, const SysBatch& sb, bool dilu, hipStream_t s) {
   return FNLH_OK;
 }
 
-enum Path { kPathRB, kPathGeneral, kPathJacobi };
+// kPathHybrid: the two-colours-plus-remainder sweep of a colouring whose first two
+// colours hold almost every row (see one_sweep)
+enum Path { kPathRB, kPathGeneral, kPathJacobi, kPathHybrid };
 
-// One timed launch: kernel kind, colour, sweep index (0 = the initial pass), events.
+// The passes of the hybrid sweep's remainder, for their byte model.
+enum RemPass { kRemNorm = 1, kRemFwd = 2, kRemBwd = 3, kRemCorrect = 4 };
+
+// One timed launch: kernel kind, colour, sweep index (0 = the initial pass), events,
+// and the remainder pass (RemPass, 0 otherwise).
 struct LaunchRec {
   int kind, colour, sweep;
   hipEvent_t a, b;
   double ms;
+  int mode;
 };
 
 struct Timer {
@@ -189,10 +196,10 @@ struct Timer {
     return e;
   }
   bool open = false;
-  void begin(int kind, int colour, int sweep) {
+  void begin(int kind, int colour, int sweep, int mode = 0) {
     open = c->stats_on && sweep % c->stats_period == 0;
     if (!open) return;
-    LaunchRec r{kind, colour, sweep, get(), get(), 0.0};
+    LaunchRec r{kind, colour, sweep, get(), get(), 0.0, mode};
     (void)hipEventRecord(r.a, s);
     recs.push_back(r);
   }
@@ -238,7 +245,7 @@ namespace {
 
 // Algorithmic bytes of one launch (compulsory traffic: each block, vector entry and
 // factor entry touched once), for `na` active systems.
-double alg_bytes(fnlh_ctx c, int kind, int col, int na) {
+double alg_bytes(fnlh_ctx c, int kind, int col, int na, int mode = 0) {
   const Layout& L = c->L;
   const double sA = (double)c->block_bytes();
   const double sv = (double)c->tv_bytes();
@@ -255,12 +262,30 @@ double alg_bytes(fnlh_ctx c, int kind, int col, int na) {
       shared = L.c_deg[col] * (blk + 4) + nrows(col) * (blk + 12);
       per = nrows(col) * (2 * 12) * sv + L.c_nbr[col] * 12 * sv;
       break;
-    case FNLH_KSTAT_FWD: {
+    case FNLH_KSTAT_FWD:
+    case FNLH_KSTAT_FWD_LAST: {
       const bool last = col == L.n_colours - 1;
       shared = L.c_deg[col] * (blk + 4) + nrows(col) * (blk + 12);
       per = nrows(col) * ((last ? 4 : 3) * 12 * sv + dv) + (L.c_nbr[col] + L.c_nbr_lower[col]) * 12 * sv;
       break;
     }
+    case FNLH_KSTAT_REMAINDER:
+      if (mode == kRemNorm) {  // every colour from col on: b and x read, neighbours' x
+        for (int cc = col; cc < L.n_colours; ++cc) {
+          shared += L.c_deg[cc] * (blk + 4) + nrows(cc) * (blk + 12);
+          per += nrows(cc) * 2 * 12 * sv + L.c_nbr[cc] * 12 * sv;
+        }
+      } else if (mode == kRemFwd) {  // b, x read; x, y written; the factor
+        shared = L.c_deg[col] * (blk + 4) + nrows(col) * (blk + 12);
+        per = nrows(col) * (4 * 12 * sv + dv) + L.c_nbr[col] * 12 * sv;
+      } else if (mode == kRemBwd) {  // upper couplings; x, y read and written; the factor
+        shared = L.c_deg_upper[col] * blk + L.c_deg[col] * 4;
+        per = nrows(col) * (4 * 12 * sv + dv) + L.c_nbr_upper[col] * 12 * sv;
+      } else {  // kRemCorrect: the listed tiles' rows coupled upwards
+        shared = L.c_deg_upper[col] * blk + (double)c->hyb_ents * 4;
+        per = (double)c->hyb_rows * (2 * 12 * sv + dv) + L.c_nbr_upper[col] * 12 * sv;
+      }
+      break;
     case FNLH_KSTAT_BWD:
       shared = L.c_deg_upper[col] * blk + L.c_deg[col] * 4;
       per = nrows(col) * (4 * 12 * sv + dv) + L.c_nbr_upper[col] * 12 * sv;
@@ -287,7 +312,7 @@ void account(fnlh_ctx c, Timer& t, const SysBatch& sb, const SysState* h) {
     }
     c->st_ms[r.kind] += r.ms;
     c->st_n[r.kind] += 1;
-    c->st_bytes[r.kind] += alg_bytes(c, r.kind, r.colour, na);
+    c->st_bytes[r.kind] += alg_bytes(c, r.kind, r.colour, na, r.mode);
   }
   t.recs.clear();
   t.harvested = 0;
@@ -322,19 +347,71 @@ void one_sweep(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, const SysBatc
     launch_rb_pass(cfg, false, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, ns, sb, st, part, L.ctile[0],
                    L.ctile[1] - L.ctile[0], s, fuse ? &fr : nullptr);
     T.end();
+  } else if (path == kPathHybrid) {
+    // Colours C0, C1 hold almost every row; C2 .. C(m-1) are a small remainder (e.g. the
+    // rows at blade-row interfaces).  With x updated in place, the DILU step is
+    //   forward, colours ascending:  x_c += y_c,  y_c = Dt_c^-1 (b - K x)_c
+    //   backward, colours descending: x_c += -Dt_c^-1 sum_{upper} K z (z_c = y_c + that)
+    // and, as in the two-colour pass, the C0 residual is zero on entry (y_C0 = 0) and C0's
+    // backward step is x_C0 = (K_ii + i w)^-1 (b - sum K x): so a sweep is the C1 update
+    // pass, forward and backward passes over the remainder colours, the correction of the
+    // C1 rows coupled to the remainder, and the first-colour pass, which reduces the
+    // norms.  Blocks of C0 and C1 are read once per sweep (the general passes read them
+    // 1.5 times).  The norm is that of the iterate the sweep starts from: C1's in the
+    // update pass, the remainder's in a first pass that only reads (C0's is zero).
+    const int m = L.n_colours;
+    T.begin(FNLH_KSTAT_REMAINDER, 2, k, kRemNorm);
+    launch_fwd(cfg, kFwdNorm, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, y, ns, sb, st, part, L.ctile[2],
+               L.ctile[m] - L.ctile[2], L.cstart[2], s);
+    T.end();
+    T.begin(FNLH_KSTAT_SWEEP_UPDATE, 1, k);
+    launch_rb_pass(cfg, true, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, ns, sb, st, part, L.ctile[1],
+                   L.ctile[2] - L.ctile[1], s);
+    T.end();
+    for (int col = 2; col < m; ++col) {
+      T.begin(FNLH_KSTAT_REMAINDER, col, k, kRemFwd);
+      launch_fwd(cfg, kFwdHybrid, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, y, ns, sb, st, part, L.ctile[col],
+                 L.ctile[col + 1] - L.ctile[col], L.cstart[col], s);
+      T.end();
+    }
+    for (int col = m - 2; col >= 2; --col) {
+      T.begin(FNLH_KSTAT_REMAINDER, col, k, kRemBwd);
+      launch_bwd(cfg, kBwdHybrid, p, c->offd.p, c->dinv.p, ds, x, y, ns, sb, st, L.ctile[col],
+                 L.ctile[col + 1] - L.ctile[col], L.cstart[col + 1], nullptr, s);
+      T.end();
+    }
+    if (c->hyb_ntiles > 0) {
+      T.begin(FNLH_KSTAT_REMAINDER, 1, k, kRemCorrect);
+      launch_bwd(cfg, kBwdCorrect, p, c->offd.p, c->dinv.p, ds, x, y, ns, sb, st, 0, c->hyb_ntiles, L.cstart[2],
+                 (const int32_t*)c->hyb_tiles.p, s);
+      T.end();
+    }
+    FusedReduce fr;
+    fr.n = sb.n;
+    fr.slots = rb_slots(cfg, sb.n);
+    fr.mode = first ? kReduceSweepNoNorm : kReduceSweep;
+    fr.t0 = L.ctile[1];
+    fr.nt = L.ctile[m] - L.ctile[1];
+    fr.rtol2 = rtol * rtol;
+    fr.div2 = divf * divf;
+    T.begin(FNLH_KSTAT_SWEEP_SET, 0, k);
+    launch_rb_pass(cfg, false, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, ns, sb, st, part, L.ctile[0],
+                   L.ctile[1] - L.ctile[0], s, &fr);
+    T.end();
   } else if (path == kPathGeneral) {
     const int m = L.n_colours;
     for (int col = 0; col < m; ++col) {
-      T.begin(FNLH_KSTAT_FWD, col, k);
-      launch_fwd(cfg, col == m - 1, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, y, ns, sb, st, part, L.ctile[col],
-                 L.ctile[col + 1] - L.ctile[col], L.cstart[col], s);
+      const bool last = col == m - 1;
+      T.begin(last ? FNLH_KSTAT_FWD_LAST : FNLH_KSTAT_FWD, col, k);
+      launch_fwd(cfg, last ? kFwdLast : kFwdGeneral, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, y, ns, sb, st,
+                 part, L.ctile[col], L.ctile[col + 1] - L.ctile[col], L.cstart[col], s);
       T.end();
     }
     launch_reduce(sb, part, L.n_tiles, 0, L.n_tiles, rb_slots(cfg, sb.n), st, kReduceSweep, rtol, divf, 0, s);
     for (int col = m - 2; col >= 0; --col) {
       T.begin(FNLH_KSTAT_BWD, col, k);
-      launch_bwd(cfg, p, c->offd.p, c->dinv.p, ds, x, y, ns, sb, st, L.ctile[col], L.ctile[col + 1] - L.ctile[col],
-                 L.cstart[col + 1], s);
+      launch_bwd(cfg, kBwdGeneral, p, c->offd.p, c->dinv.p, ds, x, y, ns, sb, st, L.ctile[col],
+                 L.ctile[col + 1] - L.ctile[col], L.cstart[col + 1], nullptr, s);
       T.end();
     }
   } else {
@@ -443,7 +520,7 @@ int sweep_loop(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, const SysBatc
                hipStream_t s, bool chunk = false) {
   const int limit = chunk ? max_sweeps : max_sweeps + 2;
   Timer T{c, s, {}, 0, true, nullptr};
-  if (path == kPathRB) {
+  if (path == kPathRB || path == kPathHybrid) {
     DevPattern p = c->pat();
     T.begin(FNLH_KSTAT_SWEEP_SET, 0, 0);
     launch_rb_pass(cfg, false, p, c->offd.p, c->diag.p, c->dinv.p, dinv_stride(c), x, b, ns, sb, st,
@@ -469,7 +546,7 @@ int sweep_loop(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, const SysBatc
       HIPC(c, hipGraphLaunch(g->exec, s), "graph launch");
       if (c->stats_on)
         for (const LaunchRec& r : g->tmpl) T.recs.push_back(LaunchRec{r.kind, r.colour, launched + 1 + r.sweep,
-                                                                       r.a, r.b, 0.0});
+                                                                       r.a, r.b, 0.0, r.mode});
       launched += check_every;
     } else {
       for (int i = 0; i < check_every && launched < limit; ++i, ++launched)
@@ -507,6 +584,45 @@ int sweep_loop(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, const SysBatc
 }
 
 // Dominance of the diagonal blocks (decides the first-colour solve), once per matrix.
+// The two-colours-plus-remainder sweep (kPathHybrid) pays when the colours past the
+// second are a small remainder: it reads C0 and C1 once per sweep but adds a few small
+// launches.
+constexpr double kHybridMaxRemainder = 0.25;  // largest fraction of rows past C1
+bool hybrid_ok(fnlh_ctx c) {
+  const Layout& L = c->L;
+  if (!c->hybrid || L.n_colours < 3) return false;
+  if (c->hybrid == 2) return true;
+  int64_t rest = 0;
+  for (int k = 2; k < L.n_colours; ++k) rest += L.ccount[k];
+  return (double)rest <= kHybridMaxRemainder * (double)L.N;
+}
+
+// The tiles of the second colour with a row coupled to a higher colour (the rows the
+// hybrid sweep corrects after the remainder's backward passes), with their row and
+// entry counts for the byte model.
+int setup_hybrid(fnlh_ctx c) {
+  const Layout& L = c->L;
+  c->hyb_ntiles = c->hyb_rows = c->hyb_ents = 0;
+  if (L.n_colours < 3) return FNLH_OK;
+  std::vector<int32_t> tiles;
+  for (int64_t t = L.ctile[1]; t < L.ctile[2]; ++t) {
+    int64_t rows = 0;
+    for (int lane = 0; lane < L.tile_nrows[t]; ++lane) {
+      bool up = false;
+      for (int q = 0; q < L.tile_width[t] && !up; ++q)
+        up = L.ent_nbr[(L.tile_slot0[t] + q) * kTile + lane] >= L.cstart[2];
+      rows += up ? 1 : 0;
+    }
+    if (rows) {
+      tiles.push_back((int32_t)t);
+      c->hyb_rows += rows;
+      c->hyb_ents += (int64_t)L.tile_width[t] * kTile;
+    }
+  }
+  c->hyb_ntiles = (int64_t)tiles.size();
+  return tiles.empty() ? FNLH_OK : dupload(c, c->hyb_tiles, tiles, "pattern");
+}
+
 int ensure_dominance(fnlh_ctx c, hipStream_t s) {
   if (c->dom_known) return FNLH_OK;
   int rc;
@@ -570,7 +686,8 @@ int relax_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, c
     launch_to_internal(p, (const int32_t*)c->iperm.p, x[j], (double*)c->x64.p, 12, n, j, s);
     launch_to_internal(p, (const int32_t*)c->iperm.p, b[j], (double*)c->b64.p, 12, n, j, s);
   }
-  P.path = o->kind == FNLH_JACOBI ? kPathJacobi : (c->L.n_colours == 2 ? kPathRB : kPathGeneral);
+  P.path = o->kind == FNLH_JACOBI ? kPathJacobi
+                                  : (c->L.n_colours == 2 ? kPathRB : (hybrid_ok(c) ? kPathHybrid : kPathGeneral));
   // frozen-turbulence systems run on the stored-factor kernels (the two-colour pass solves
   // the first colour's full 6x6 diagonal block in place); their sixth unknown starts at 0
   bool frozen = false;
@@ -579,7 +696,7 @@ int relax_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, c
       frozen = true;
       launch_zero_sixth(c->L.NP, (double*)c->x64.p, n, j, s);
     }
-  if (frozen && P.path == kPathRB) P.path = kPathGeneral;
+  if (frozen && (P.path == kPathRB || P.path == kPathHybrid)) P.path = kPathGeneral;
   P.fkind = (o->kind == FNLH_DILU || o->kind == FNLH_LEARNED) ? 0 : 1;
   P.cfg.storage = c->storage;
   P.cfg.spw = c->lanes_per_sys;
@@ -941,6 +1058,7 @@ int fnlh_create(fnlh_ctx* out, const fnlh_mesh* mesh, const fnlh_options* opts) 
   if ((rc = dupload(c, c->edge_ent, L.edge_ent, "pattern"))) return fail(rc);
   if ((rc = dupload(c, c->bf_ptr, L.bf_ptr, "pattern"))) return fail(rc);
   if ((rc = dupload(c, c->bf_idx, L.bf_idx, "pattern"))) return fail(rc);
+  if ((rc = setup_hybrid(c))) return fail(rc);
   {
     std::vector<double> a(mesh->area, mesh->area + 3 * mesh->n_edges);
     if ((rc = dupload(c, c->area, a, "geometry"))) return fail(rc);
@@ -967,7 +1085,8 @@ int fnlh_destroy(fnlh_ctx c) {
                     &c->vol, &c->zone, &c->iperm, &c->perm, &c->edge_ent, &c->bf_ptr, &c->bf_idx, &c->area,
                     &c->bface_area, &c->offd, &c->diag, &c->offd64, &c->diag64, &c->state, &c->bstate,
                     &c->d_omega, &c->dinv, &c->x64, &c->b64, &c->r64, &c->y, &c->rhs32, &c->d32, &c->partial,
-                    &c->st, &c->st_outer, &c->d_err, &c->ent_phase, &c->phase_cs, &c->sys_frozen, &c->ent_drop};
+                    &c->st, &c->st_outer, &c->d_err, &c->ent_phase, &c->phase_cs, &c->sys_frozen, &c->ent_drop,
+                    &c->hyb_tiles};
   for (DevBuf* b : bufs) dfree(*b);
   if (c->h_st) (void)hipHostFree(c->h_st);
   if (c->h_err) (void)hipHostFree(c->h_err);
@@ -1299,7 +1418,7 @@ int precond_apply(fnlh_ctx c, const PrecondPlan& pp, int ns, const SysBatch& sb,
       return sweep_loop(c, (Path)pp.path, pp.cfg, ns, fb, xz, bb, c->y.p, st, 0.0, 1e30, pp.inner, pp.inner + 2,
                         pp.use_graph, s);
     Timer T{c, s, {}, 0, true, nullptr};
-    if (pp.path == kPathRB)
+    if (pp.path == kPathRB || pp.path == kPathHybrid)
       launch_rb_pass(pp.cfg, false, p, c->offd.p, c->diag.p, c->dinv.p, dinv_stride(c), xz, bb, ns, fb, st,
                      (double*)c->partial.p, c->L.ctile[0], c->L.ctile[1] - c->L.ctile[0], s);
     for (int k = 1; k <= pp.inner; ++k)
@@ -1771,9 +1890,9 @@ int fnlh_autotune(fnlh_ctx c, int32_t n_sys, int32_t sweeps, fnlh_tune_result* o
     double ms = 0.0;
     int64_t sweeps_timed = 0;
     for (int k = 0; k < FNLH_KSTAT_N; ++k) ms += c->st_ms[k];
-    sweeps_timed = c->st_n[FNLH_KSTAT_SWEEP_UPDATE] + c->st_n[FNLH_KSTAT_JACOBI] +
-                   (c->L.n_colours > 2 ? c->st_n[FNLH_KSTAT_FWD] / c->L.n_colours : 0);
-    if (c->L.n_colours == 1) sweeps_timed = c->st_n[FNLH_KSTAT_FWD];
+    // one update pass (two-colour, hybrid), last-colour forward pass (general) or
+    // Jacobi pass per sweep
+    sweeps_timed = c->st_n[FNLH_KSTAT_SWEEP_UPDATE] + c->st_n[FNLH_KSTAT_FWD_LAST] + c->st_n[FNLH_KSTAT_JACOBI];
     const double us = sweeps_timed > 0 ? 1e3 * ms / (double)sweeps_timed : 1e300;
     ++tried;
     if (cd.lpr == 0 && cd.spw == 0) dflt = us;
@@ -1821,6 +1940,11 @@ int fnlh_tune(fnlh_ctx c, int32_t param, int32_t value) {
   if (param == FNLH_TUNE_WAVE_GROUPS) {
     if (value != 0 && value != 1) return set_err(c, FNLH_E_ARG, "tune: wave groups must be 0 or 1");
     c->wave_groups = value;
+    return FNLH_OK;
+  }
+  if (param == FNLH_TUNE_HYBRID) {
+    if (value < 0 || value > 2) return set_err(c, FNLH_E_ARG, "tune: hybrid must be 0, 1 or 2");
+    c->hybrid = value;
     return FNLH_OK;
   }
   return set_err(c, FNLH_E_ARG, "tune: unknown parameter");

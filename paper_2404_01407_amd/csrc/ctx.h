@@ -33,6 +33,9 @@ struct fnlh_ctx_s {
   int lanes_per_sys = 0;  // systems per lane of the sweep kernels (0 = automatic)
   int lanes_per_row = 0;  // lanes sharing a row in the two-colour pass (0 = automatic)
   int wave_groups = 1;    // two-colour pass: 1 = one wave per workgroup (default), 0 = a tile per workgroup
+  int hybrid = 1;         // colourings with a small remainder past two colours: two-colour passes + remainder
+  DevBuf hyb_tiles;       // second-colour tiles with a row coupled to a higher colour
+  int64_t hyb_ntiles = 0, hyb_rows = 0, hyb_ents = 0;
   std::string err;
 
   // pattern (device)

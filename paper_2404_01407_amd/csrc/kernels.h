@@ -136,12 +136,20 @@ void launch_rb_pass(const SweepCfg& c, bool update, const DevPattern& p, const v
                     const void* dinv, int64_t dinv_stride, void* x, const void* b, int ns, const SysBatch& sb,
                     const SysState* st, double* partial, int64_t t0, int64_t nt, hipStream_t s,
                     const FusedReduce* fused = nullptr);
-void launch_fwd(const SweepCfg& c, bool last, const DevPattern& p, const void* offd, const void* diag,
+// General-colouring passes (k_fwd / k_bwd).  Forward modes: kFwdGeneral / kFwdLast (the
+// textbook forward substitution with the lower colours' y, x += y on the last colour),
+// kFwdHybrid (x updated in place colour by colour, y = Dt^-1 (b - K x), x += y),
+// kFwdNorm (norm partials of b - K x only).  Backward modes: kBwdGeneral, kBwdHybrid
+// (x and y += -Dt^-1 sum_upper K z), kBwdCorrect (x only, over the tiles of tlist).
+enum { kFwdGeneral = 0, kFwdLast = 1, kFwdHybrid = 2, kFwdNorm = 3 };
+enum { kBwdGeneral = 0, kBwdHybrid = 1, kBwdCorrect = 2 };
+void launch_fwd(const SweepCfg& c, int mode, const DevPattern& p, const void* offd, const void* diag,
                 const void* dinv, int64_t dinv_stride, void* x, const void* b, void* y, int ns, const SysBatch& sb,
                 const SysState* st, double* partial, int64_t t0, int64_t nt, int64_t cstart, hipStream_t s);
-void launch_bwd(const SweepCfg& c, const DevPattern& p, const void* offd, const void* dinv, int64_t dinv_stride,
-                void* x, void* y, int ns, const SysBatch& sb, const SysState* st, int64_t t0, int64_t nt,
-                int64_t cend, hipStream_t s);
+// tlist: device list of nt tiles (kBwdCorrect), else tiles t0 .. t0 + nt
+void launch_bwd(const SweepCfg& c, int mode, const DevPattern& p, const void* offd, const void* dinv,
+                int64_t dinv_stride, void* x, void* y, int ns, const SysBatch& sb, const SysState* st, int64_t t0,
+                int64_t nt, int64_t cend, const int32_t* tlist, hipStream_t s);
 void launch_jacobi(const SweepCfg& c, const DevPattern& p, const void* offd, const void* diag, const void* dinv,
                    int64_t dinv_stride, const void* x, const void* b, void* y, int ns, const SysBatch& sb,
                    const SysState* st, double* partial, hipStream_t s);

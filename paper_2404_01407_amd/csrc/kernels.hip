@@ -658,7 +658,14 @@ __device__ inline bool row_systems(const SysBatch& sb, const SysState* __restric
 // Lane mapping as in the two-colour pass: SW lanes share a row (one block fetch serves
 // all of them), each carrying P systems; a 64-row tile takes SW waves; the norm of
 // system k over the rows of wave w goes to partial slot w.
-template <typename TB, int SW, int P, bool LAST>
+//
+// Two further modes serve the two-colours-plus-remainder sweep (see one_sweep), where
+// x is updated in place colour by colour, so that b - K x already holds the lower
+// colours' corrections (the forward substitution of the DILU step):
+//   kFwdHybrid: y_i = Dt_i^-1 (b - K x)_i, stored, and x_i += y_i; no norm.
+//   kFwdNorm:   only ||(b - K x)_i||^2 into the partials (the rows' residual at the
+//               iterate the sweep starts from); nothing is written.
+template <typename TB, int SW, int P, int MODE>
 __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict__ offd, const TB* __restrict__ diag,
                                              const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                              typename TV_of<TB>::T* __restrict__ x,
@@ -682,14 +689,17 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
   const int64_t row = tile * kLanes + rl;
   const bool valid = rl < p.tile_nrows[tile];
   const int64_t rb = row * ns * 12;
-  A r[P][12], t[P][12];
+  constexpr bool kLowerY = MODE == kFwdGeneral || MODE == kFwdLast;
+  A r[P][12], t[P][kLowerY ? 12 : 1];
   {
     A d[36];
     load_block(diag + tile * slot_elems<TB>(), rl, d);
 #pragma unroll
     for (int j = 0; j < P; ++j) {
 #pragma unroll
-      for (int i = 0; i < 12; ++i) t[j][i] = r[j][i] = 0;
+      for (int i = 0; i < 12; ++i) r[j][i] = 0;
+#pragma unroll
+      for (int i = 0; i < (kLowerY ? 12 : 1); ++i) t[j][i] = 0;
       if (!W.run[j]) continue;
       A xi[12];
       load_vec(b + rb + W.vs[j] * 12, r[j]);
@@ -709,10 +719,12 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
       load_vec(x + nbo + W.vs[j] * 12, v);
       if (p.ent_phase) apply_phase(p, slot * kLanes + rl, W.orow[j], v);
       sub_kx(r[j], kb, v);
-      if (lower) {
-        load_vec(y + nbo + W.vs[j] * 12, v);
-        if (p.ent_phase) apply_phase(p, slot * kLanes + rl, W.orow[j], v);
-        sub_kx(t[j], kb, v);
+      if constexpr (kLowerY) {
+        if (lower) {
+          load_vec(y + nbo + W.vs[j] * 12, v);
+          if (p.ent_phase) apply_phase(p, slot * kLanes + rl, W.orow[j], v);
+          sub_kx(t[j], kb, v);
+        }
       }
     }
   };
@@ -750,19 +762,25 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     if (W.run[j]) mask_frozen(p, W.orow[j], r[j]);
-    double n2 = (valid && W.run[j]) ? norm2_12(r[j]) : 0.0;
+    if constexpr (MODE != kFwdHybrid) {
+      double n2 = (valid && W.run[j]) ? norm2_12(r[j]) : 0.0;
 #pragma unroll
-    for (int o = 32; o >= SW; o >>= 1) n2 += __shfl_xor(n2, o, 64);
-    if (lane < SW && j * SW + lane < sb.n && W.run[j])
-      partial[((int64_t)W.vs[j] * p.n_tiles + tile) * kPartialSlots + w] = n2;
-    if (!W.run[j]) continue;
-#pragma unroll
-    for (int i = 0; i < 12; ++i) t[j][i] += r[j][i];
+      for (int o = 32; o >= SW; o >>= 1) n2 += __shfl_xor(n2, o, 64);
+      if (lane < SW && j * SW + lane < sb.n && W.run[j])
+        partial[((int64_t)W.vs[j] * p.n_tiles + tile) * kPartialSlots + w] = n2;
+    }
+    if (MODE == kFwdNorm || !W.run[j]) continue;
     A yi[12];
-    apply_dinv(dinv + (int64_t)W.ds[j] * dstride + tile * DinvTile<typename DF_of<TB>::T>::N, rl, t[j], yi);
+    if constexpr (kLowerY) {
+#pragma unroll
+      for (int i = 0; i < 12; ++i) t[j][i] += r[j][i];
+      apply_dinv(dinv + (int64_t)W.ds[j] * dstride + tile * DinvTile<typename DF_of<TB>::T>::N, rl, t[j], yi);
+    } else {
+      apply_dinv(dinv + (int64_t)W.ds[j] * dstride + tile * DinvTile<typename DF_of<TB>::T>::N, rl, r[j], yi);
+    }
     if (valid) {
       store_vec(y + rb + W.vs[j] * 12, yi);
-      if (LAST) {
+      if (MODE == kFwdLast || MODE == kFwdHybrid) {
         A xi[12];
         load_vec(x + rb + W.vs[j] * 12, xi);
 #pragma unroll
@@ -775,24 +793,29 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
 
 // General colouring, backward pass of colour c (rows of higher colours are >= cend and
 // already hold z in y):  z_i = y_i - Dt_i^-1 sum_{k upper} K_ik z_k;  x_i += z_i; y_i <- z_i
-template <typename TB, int SW, int P>
+// In the two-colours-plus-remainder sweep x already holds x + y (kFwdHybrid), so
+//   kBwdHybrid:  d_i = -Dt_i^-1 sum_{k upper} K_ik z_k;  x_i += d_i;  y_i += d_i (= z_i)
+//   kBwdCorrect: the same x update without z, for the rows of the second colour, over
+//                the tiles listed in tlist (those with a row coupled to a higher colour)
+// and, with no reduction since the update pass, they run for the systems that pass ran.
+template <typename TB, int SW, int P, int MODE>
 __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict__ offd,
                                              const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                              typename TV_of<TB>::T* __restrict__ x,
                                              typename TV_of<TB>::T* __restrict__ y, int ns, SysBatch sb,
                                              const SysState* __restrict__ st, int64_t t0, int64_t nt, int64_t cend,
-                                             int wave_groups) {
+                                             int wave_groups, const int32_t* __restrict__ tlist) {
   using A = typename TV_of<TB>::T;
   int64_t tile;
   int grp;
   if (!map_tile(nt, wave_groups ? SW : 1, tile, grp)) return;
-  tile += t0;
+  tile = tlist ? (int64_t)tlist[tile] : tile + t0;
   const int lane = threadIdx.x & 63;
   const int w = wave_groups ? grp : (int)(threadIdx.x >> 6);
   const int sidx = lane % SW;
   const int rl = w * (kLanes / SW) + lane / SW;
   WaveSys<P> W;
-  const bool any = row_systems<SW, P>(sb, st, sidx, false, W);
+  const bool any = row_systems<SW, P>(sb, st, sidx, MODE != kBwdGeneral, W);
   if (!__any(any)) return;
   const int64_t row = tile * kLanes + rl;
   const bool valid = rl < p.tile_nrows[tile];
@@ -861,14 +884,22 @@ __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict_
     apply_dinv(dinv + (int64_t)W.ds[j] * dstride + tile * DinvTile<typename DF_of<TB>::T>::N, rl, t[j], z);
     if (valid) {
       A yi[12], xi[12];
-      load_vec(y + rb + W.vs[j] * 12, yi);
+      if (MODE != kBwdCorrect) load_vec(y + rb + W.vs[j] * 12, yi);
       load_vec(x + rb + W.vs[j] * 12, xi);
+      if constexpr (MODE == kBwdGeneral) {
 #pragma unroll
-      for (int i = 0; i < 12; ++i) {
-        z[i] += yi[i];
-        xi[i] += z[i];
+        for (int i = 0; i < 12; ++i) {
+          z[i] += yi[i];
+          xi[i] += z[i];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+          xi[i] += z[i];
+          if constexpr (MODE == kBwdHybrid) z[i] += yi[i];
+        }
       }
-      store_vec(y + rb + W.vs[j] * 12, z);
+      if (MODE != kBwdCorrect) store_vec(y + rb + W.vs[j] * 12, z);
       store_vec(x + rb + W.vs[j] * 12, xi);
     }
   }
@@ -1750,7 +1781,7 @@ void launch_reduce_batched(const InstDesc* inst, const WorkItem* items, int n_it
                      div_factor * div_factor);
 }
 
-void launch_fwd(const SweepCfg& c, bool last, const DevPattern& p, const void* offd, const void* diag,
+void launch_fwd(const SweepCfg& c, int mode, const DevPattern& p, const void* offd, const void* diag,
                 const void* dinv, int64_t dinv_stride, void* x, const void* b, void* y, int ns, const SysBatch& sb,
                 const SysState* st, double* partial, int64_t t0, int64_t nt, int64_t cstart, hipStream_t s) {
   if (nt <= 0 || sb.n <= 0) return;
@@ -1760,16 +1791,20 @@ void launch_fwd(const SweepCfg& c, bool last, const DevPattern& p, const void* o
   dim3 grid = tile_grid(nt, wg ? SW : 1);
   dim3 block(wg ? 64 : 64 * SW);
   const unsigned lds_bytes = (SW == 4) ? (unsigned)(block.x / 64) * lds_chunks_per_wave(c.storage) * 16u : 0u;
+#define FNLH_FWD_ONE(SWV, MD)                                                                                     \
+  hipLaunchKernelGGL((k_fwd<TB, SWV, PP, MD>), grid, block, lds_bytes, s, p, (const TB*)offd, (const TB*)diag,        \
+                     (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, (A*)y, ns, sb, st, partial, t0,  \
+                     nt, cstart, wg)
 #define FNLH_FWD_LAUNCH(SWV)                                                                                      \
   FNLH_DISPATCH_P(P, {                                                                                            \
-    if (last)                                                                                                     \
-      hipLaunchKernelGGL((k_fwd<TB, SWV, PP, true>), grid, block, lds_bytes, s, p, (const TB*)offd, (const TB*)diag,      \
-                         (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, (A*)y, ns, sb, st, partial, t0, nt,     \
-                         cstart, wg);                                                                                 \
+    if (mode == kFwdLast)                                                                                         \
+      FNLH_FWD_ONE(SWV, kFwdLast);                                                                                \
+    else if (mode == kFwdHybrid)                                                                                  \
+      FNLH_FWD_ONE(SWV, kFwdHybrid);                                                                              \
+    else if (mode == kFwdNorm)                                                                                    \
+      FNLH_FWD_ONE(SWV, kFwdNorm);                                                                                \
     else                                                                                                          \
-      hipLaunchKernelGGL((k_fwd<TB, SWV, PP, false>), grid, block, lds_bytes, s, p, (const TB*)offd, (const TB*)diag,     \
-                         (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, (A*)y, ns, sb, st, partial, t0, nt,     \
-                         cstart, wg);                                                                                 \
+      FNLH_FWD_ONE(SWV, kFwdGeneral);                                                                             \
   })
   FNLH_DISPATCH_STORE(c.storage, {
     using A = typename Fmt<TB>::A;
@@ -1781,11 +1816,12 @@ void launch_fwd(const SweepCfg& c, bool last, const DevPattern& p, const void* o
       FNLH_FWD_LAUNCH(4);
   });
 #undef FNLH_FWD_LAUNCH
+#undef FNLH_FWD_ONE
 }
 
-void launch_bwd(const SweepCfg& c, const DevPattern& p, const void* offd, const void* dinv, int64_t dinv_stride,
-                void* x, void* y, int ns, const SysBatch& sb, const SysState* st, int64_t t0, int64_t nt,
-                int64_t cend, hipStream_t s) {
+void launch_bwd(const SweepCfg& c, int mode, const DevPattern& p, const void* offd, const void* dinv,
+                int64_t dinv_stride, void* x, void* y, int ns, const SysBatch& sb, const SysState* st, int64_t t0,
+                int64_t nt, int64_t cend, const int32_t* tlist, hipStream_t s) {
   if (nt <= 0 || sb.n <= 0) return;
   int SW, P;
   rb_shape(c, sb.n, SW, P);
@@ -1793,10 +1829,17 @@ void launch_bwd(const SweepCfg& c, const DevPattern& p, const void* offd, const 
   dim3 grid = tile_grid(nt, wg ? SW : 1);
   dim3 block(wg ? 64 : 64 * SW);
   const unsigned lds_bytes = (SW == 4) ? (unsigned)(block.x / 64) * lds_chunks_per_wave(c.storage) * 16u : 0u;
+#define FNLH_BWD_ONE(SWV, MD)                                                                                 \
+  hipLaunchKernelGGL((k_bwd<TB, SWV, PP, MD>), grid, block, lds_bytes, s, p, (const TB*)offd,                   \
+                     (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (A*)y, ns, sb, st, t0, nt, cend, wg, tlist)
 #define FNLH_BWD_LAUNCH(SWV)                                                                                  \
   FNLH_DISPATCH_P(P, {                                                                                        \
-    hipLaunchKernelGGL((k_bwd<TB, SWV, PP>), grid, block, lds_bytes, s, p, (const TB*)offd, (const typename DF_of<TB>::T*)dinv, dinv_stride, \
-                       (A*)x, (A*)y, ns, sb, st, t0, nt, cend, wg);                                           \
+    if (mode == kBwdHybrid)                                                                                   \
+      FNLH_BWD_ONE(SWV, kBwdHybrid);                                                                          \
+    else if (mode == kBwdCorrect)                                                                             \
+      FNLH_BWD_ONE(SWV, kBwdCorrect);                                                                         \
+    else                                                                                                      \
+      FNLH_BWD_ONE(SWV, kBwdGeneral);                                                                         \
   })
   FNLH_DISPATCH_STORE(c.storage, {
     using A = typename Fmt<TB>::A;
@@ -1808,6 +1851,7 @@ void launch_bwd(const SweepCfg& c, const DevPattern& p, const void* offd, const 
       FNLH_BWD_LAUNCH(4);
   });
 #undef FNLH_BWD_LAUNCH
+#undef FNLH_BWD_ONE
 }
 
 void launch_jacobi(const SweepCfg& c, const DevPattern& p, const void* offd, const void* diag, const void* dinv,

@@ -82,7 +82,7 @@ class KernelStats(C.Structure):
     _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("alg_bytes", C.c_double)]
 
 
-KSTAT = {"sweep_update": 0, "sweep_set": 1, "fwd": 2, "bwd": 3, "jacobi": 4}
+KSTAT = {"sweep_update": 0, "sweep_set": 1, "fwd": 2, "bwd": 3, "jacobi": 4, "fwd_last": 5, "remainder": 6}
 
 
 def _load():
@@ -434,12 +434,16 @@ class Context:
         self._check(rc, allow_positive=True)
         return rc, hist[:int(n_steps)]
 
-    def tune(self, sys_per_lane=0, lanes_per_row=0, wave_groups=None):
-        """Set the sweep-kernel shape (0 = automatic); wave_groups (0/1) when given."""
+    def tune(self, sys_per_lane=0, lanes_per_row=0, wave_groups=None, hybrid=None):
+        """Set the sweep-kernel shape (0 = automatic); wave_groups (0/1) and hybrid (0/1:
+        two-colour passes plus remainder passes for nearly two-coloured orderings) when
+        given."""
         self._check(LIB.fnlh_tune(self.h, 0, int(sys_per_lane)))
         self._check(LIB.fnlh_tune(self.h, 1, int(lanes_per_row)))
         if wave_groups is not None:
             self._check(LIB.fnlh_tune(self.h, 2, int(wave_groups)))
+        if hybrid is not None:
+            self._check(LIB.fnlh_tune(self.h, 3, int(hybrid)))
 
     def autotune(self, n_sys, sweeps=16, cache=None, stream=None):
         """Pick the sweep-kernel shape by timing (native autotuner).  ``cache``: path of a

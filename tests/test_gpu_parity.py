@@ -156,11 +156,17 @@ def test_nonzero_initial_guess(F):
     c.close()
 
 
-def test_general_colouring_with_triangles(F):
+@pytest.mark.parametrize("hybrid", [0, 1])
+def test_general_colouring_with_triangles(F, hybrid):
+    """Three-row mesh with triangles (greedy colouring, 4 colours, the last two a small
+    remainder): the general forward/backward passes (hybrid 0) and the two-colour passes
+    plus remainder passes (hybrid 1, the default here) both give the oracle's DILU / SGS
+    iterates on that colouring and converge to the dense solution."""
     m = synth.multi_row(6, 8, 4, n_blades=(36, 60, 48), seed=5)
     Q = synth.flow_state(m, 5)
     K = assemble.assemble(m, Q)
     c = _ctx(F, m, Q)
+    c.tune(hybrid=hybrid)
     col, nc = c.ordering()
     assert nc >= 3 and ordering.is_valid(col, m.edges)
     om = synth.omegas_multi_row(2, (36, 60, 48))
@@ -458,9 +464,11 @@ def test_graph_replay_after_buffer_reallocation(F):
     c.close()
 
 
-def test_every_general_path_shape_covers_all_systems(F):
+@pytest.mark.parametrize("hybrid", [0, 2])
+def test_every_general_path_shape_covers_all_systems(F, hybrid):
     # general colouring (triangles): 11 systems under every kernel shape, iterates equal
-    # the oracle's and do not depend on the shape
+    # the oracle's and do not depend on the shape, for the general passes and for the
+    # two-colour plus remainder passes
     m = synth.multi_row(5, 6, 3, n_blades=(36, 60, 48), seed=7)
     Q = synth.flow_state(m, 7)
     K = assemble.assemble(m, Q)
@@ -471,7 +479,7 @@ def test_every_general_path_shape_covers_all_systems(F):
         for spw in (0, 1, 4):
             c = _ctx(F, m, Q)
             c.set_harmonics(om)
-            c.tune(spw, lpr)
+            c.tune(spw, lpr, hybrid=hybrid)
             st, rep, xs = _solve(c, list(range(11)), bs, kind="dilu", max_sweeps=12, rtol=0.0)
             assert all(r["sweeps"] == 12 for r in rep), (lpr, spw)
             if ref is None:
@@ -505,3 +513,37 @@ def test_wave_groups_bitwise(F, n_sys):
         c.close()
     for a, b in zip(*out):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_hybrid_matches_general_passes(F, storage):
+    """The two-colour plus remainder sweep computes the general passes' DILU step: on a
+    colouring with five colours (three past the second) the iterates agree to rounding
+    after every sweep count, the stop test sees the same residual norms (same sweep
+    counts to a 1e-10 drop) and both reach the dense solution; SGS likewise."""
+    m = synth.multi_row(4, 4, 3, n_blades=(36, 60, 48), seed=5)
+    Q = synth.flow_state(m, 5)
+    K = assemble.assemble(m, Q)
+    om = synth.omegas_multi_row(3, (36, 60, 48))
+    bs = [synth.rhs(m.n_cells, s, real=(s == 0)) for s in range(4)]
+    out = {}
+    for hybrid in (0, 2):
+        c = _ctx(F, m, Q, storage=storage)
+        c.set_harmonics(om)
+        c.tune(hybrid=hybrid)
+        assert c.ordering()[1] == 5
+        res = {}
+        for kind in ("dilu", "sgs"):
+            res[kind, 7] = _solve(c, list(range(4)), bs, kind=kind, max_sweeps=7, rtol=0.0)
+            res[kind, "conv"] = _solve(c, list(range(4)), bs, kind=kind, max_sweeps=4000, rtol=1e-10)
+        out[hybrid] = res
+        c.close()
+    tol = 1e-11 if storage == "f64" else 1e-4
+    for kind in ("dilu", "sgs"):
+        for s in range(4):
+            assert itererr(out[2][kind, 7][2][s], out[0][kind, 7][2][s]) <= tol, (kind, s)
+            xd = solve.dense_solve(K, m.volume, m.zone, om[s], bs[s])
+            assert relerr(out[2][kind, "conv"][2][s], xd) <= 1e-8, (kind, s)
+            assert out[2][kind, "conv"][0] == 0
+        if storage == "f64":
+            assert [r["sweeps"] for r in out[2][kind, "conv"][1]] == [r["sweeps"] for r in out[0][kind, "conv"][1]]

@@ -1,18 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the shared-Jacobian, frequency-shifted block solve on one MI355X.
 
-Workload (the precision configuration: 200k-cell hex annular sector 80x50x50 as an edge
-list with 589,500 interior faces and 21,000 boundary faces, mean flow + 3 harmonics at
-omega = 0, 18, 36, 54 = 0..3 x BPF for 36 blades).  One step is the whole hot path on
-inputs already resident in HBM:
+Default workload (the largest single-GPU configuration): a three-row sector (rotor-
+stator-rotor, 3 x 100x64x100 = 1,920,000 cells, 5,717,200 faces, pitch-overlap interfaces
+between the rows), mean flow + 10 harmonics at mixed per-row frequencies, one Jacobian
+stored in FP32 for all 11 systems.  One step is the whole hot path on inputs already
+resident in HBM:
     assemble K from the FP64 state (Rusanov first-order Jacobian, eps = 0.6, sigma = 50)
-    -> set the harmonics (factor slots invalidated) -> DILU factorisation of 4 systems
-    -> preconditioned Richardson of all 4 systems to a 1e-8 relative residual drop,
-       FP64 outer residual of the exact operator (defect correction for FP32/BF16 blocks).
-Mesh ingest (validation, colouring, numbering: host work done once per mesh) is
-outside the step and reported as ingest_ms.
+    -> set the harmonics (factor slots invalidated) -> DILU factorisation of 11 systems
+    -> preconditioned Richardson of all 11 systems to a 1e-8 relative residual drop,
+       FP32 sweeps inside an FP64 defect correction with the exact FP64 operator.
+Mesh ingest (validation, colouring, numbering: host work done once per mesh) is outside
+the step and reported as ingest_ms.  Other workloads (--workload): the 200k-cell precision
+configuration, 64 batched instances, the learned preconditioner's held-out protocol,
+phase-lagged cascade, FGMRES, the RK driver, partitions.
 
-value = cell-unknown updates per second: one update is the 6 complex unknowns of one
+value = cell-system-sweep updates per second: one update is the 6 complex unknowns of one
 cell of one system advanced by one preconditioned sweep (x6 for scalar unknowns).
 """
 import argparse
@@ -255,31 +258,300 @@ def run_learned(args):
     print(json.dumps(out), flush=True)
 
 
-def run_largest(args):
-    """Three-row sector (rotor-stator-rotor, 3 x 100x64x100 = 1.92M cells plus the pitch-
-    overlap interface couplings, greedy colouring), mean + 10 harmonics at mixed per-row
-    frequencies, FP32 blocks with the FP64 defect correction, DILU sweeps to 1e-8; then
-    the same solve with learned corrections.  Device memory is read for 1, 3, 6 and 11
-    systems: the matrix part does not depend on the harmonic count."""
-    import numpy as np
+LARGEST_PROFILE = "k_rb_pass_update_f32_1920k_mean10h.md"
+
+
+def calib_copy():
+    """A plain elementwise kernel of known traffic for the counter calibration:
+    torch.neg over 1 GiB (reads 1 GiB, writes 1 GiB), three times."""
     import torch
-    from paper_2404_01407_amd import fnlh, synth
-    t0 = time.perf_counter()
-    mesh = synth.multi_row(*args.largest_shape, n_blades=(36, 60, 48), seed=5)
+    xs = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    ys = torch.empty_like(xs)
+    for _ in range(3):
+        torch.neg(xs, out=ys)
+    torch.cuda.synchronize()
+    del xs, ys
+    print("[bench] calibration: torch.neg over 1 GiB (read 1 GiB, write 1 GiB) x3", file=sys.stderr, flush=True)
+
+
+def kernel_sources_sha():
+    """Fingerprint of the sweep kernels' sources: a counter summary taken with other
+    sources no longer describes the kernel this build launches."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.h", "device.h"):
+        with open(os.path.join(ROOT, "paper_2404_01407_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(name):
+    """HBM bytes per launch of the dominant kernel from the committed counter summary
+    (its line 'traffic_bytes_per_launch <bytes> sources <sha16>', FETCH_SIZE and
+    WRITE_SIZE scaled by the copy-kernel calibration); (None, why) when the summary is
+    missing or was taken with other kernel sources."""
+    import re
+    try:
+        with open(os.path.join(ROOT, "profiles", name)) as fh:
+            text = fh.read()
+    except OSError:
+        return None, f"profiles/{name} missing"
+    m = re.search(r"traffic_bytes_per_launch\s+(\d+)\s+sources\s+([0-9a-f]{16})", text)
+    if not m:
+        return None, f"no traffic line in profiles/{name}"
+    if m.group(2) != kernel_sources_sha():
+        return None, "kernel sources changed since the counter runs"
+    return int(m.group(1)), f"profiles/{name}"
+
+
+def build_largest(shape):
+    import numpy as np  # noqa: F401
+    from paper_2404_01407_amd import synth
+    mesh = synth.multi_row(*shape, n_blades=(36, 60, 48), seed=5)
     Q = synth.flow_state(mesh, 5)
     n_h = 10
     om = synth.omegas_multi_row(n_h, (36, 60, 48))
     bs = [synth.rhs(mesh.n_cells, s, real=(s == 0)) for s in range(n_h + 1)]
-    print(f"[bench] largest: {mesh.n_cells} cells, {mesh.n_edges} faces, {len(bs)} systems, inputs "
+    return mesh, Q, om, bs
+
+
+_POOL = {}
+
+
+def _pool_worker(s):
+    """One system's DILU factorisation and one sweep of the oracle in a forked worker
+    (K, mesh and colouring inherited from the parent), on one thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import solve
+    g = _POOL
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        f = solve.factor(g["K"], g["mesh"].volume, g["mesh"].zone, g["om"][s], g["colour"], "DILU")
+        t_fac = time.perf_counter() - t0
+        Ds = solve.system_diag(g["K"], g["mesh"].volume, g["mesh"].zone, g["om"][s])
+        x = np.zeros_like(g["bs"][s])
+        t0 = time.perf_counter()
+        r = g["bs"][s] - solve.apply(g["K"], Ds, x)
+        x = x + solve.precondition(g["K"], f, r)
+        t_sw = time.perf_counter() - t0
+    return t_fac, t_sw
+
+
+def cpu_sample_largest(mesh, Q, om, bs, colour, pool_workers):
+    """The oracle as it stands, timed on a bounded sample of the same workload before the
+    GPU is touched: assembly of K, then (1) on one thread the DILU factorisation of one
+    harmonic system and one sweep, (2) a process pool with one system per worker (the
+    systems are decoupled), every system's factorisation and one sweep.  Step times are
+    extrapolated to the GPU's sweep counts afterwards (cpu_baseline_from)."""
+    import multiprocessing as mp
+    from threadpoolctl import threadpool_limits
+    from oracle import assemble
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        K = assemble.assemble(mesh, Q, eps=0.6, sigma=50.0)
+        t_asm = time.perf_counter() - t0
+    _POOL.update(K=K, mesh=mesh, om=om, bs=bs, colour=colour)
+    t_fac1, t_sw1 = _pool_worker(1)
+    S = len(bs)
+    W = max(1, min(S, pool_workers))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(W) as pool:
+        res = pool.map(_pool_worker, range(S), chunksize=1)
+    t_pool = time.perf_counter() - t0
+    _POOL.clear()
+    return {"t_asm": t_asm, "t_fac1": t_fac1, "t_sw1": t_sw1, "workers": W, "t_pool_wall": t_pool,
+            "pool": res, "cpu_count": os.cpu_count()}
+
+
+def cpu_baseline_from(sample, n_cells, gpu_sweeps, label):
+    """Extrapolate the sampled oracle costs to the GPU's sweep counts: one thread
+    (assembly + every factorisation + every sweep in turn) and the pool (assembly, then
+    the systems spread over the workers, each factorisation and its sweeps)."""
+    S = len(gpu_sweeps)
+    t_single = sample["t_asm"] + S * sample["t_fac1"] + sum(gpu_sweeps) * sample["t_sw1"]
+    W = sample["workers"]
+    per_sys = [f + n * sw for (f, sw), n in zip(sample["pool"], gpu_sweeps)]
+    loads = [0.0] * W
+    for t in sorted(per_sys, reverse=True):  # longest first onto the least-loaded worker
+        loads[loads.index(min(loads))] += t
+    t_pool = sample["t_asm"] + max(loads)
+    updates = n_cells * sum(gpu_sweeps)
+    return {"value": updates / t_pool, "unit": "cell-system-sweep updates/s", "cores": W, "kind": "oracle",
+            "sample": (f"oracle (NumPy FP64) on the {label}: assembly {sample['t_asm']:.1f} s (1 thread); "
+                       f"pool of {W} processes (one thread each, os.cpu_count() = {sample['cpu_count']}): every "
+                       f"system's DILU factorisation and one sweep, {sample['t_pool_wall']:.1f} s wall; step "
+                       f"extrapolated to the GPU sweep counts = {t_pool:.1f} s"),
+            "extrapolated_step_s": round(t_pool, 2),
+            "single_thread": {"value": updates / t_single, "cores": 1,
+                              "factor_s": round(sample["t_fac1"], 2), "sweep_s": round(sample["t_sw1"], 2),
+                              "extrapolated_step_s": round(t_single, 1)},
+            "cpu_count": sample["cpu_count"]}
+
+
+def train_heldout(storage, meshes_seeds, starts, snapshots, every, rounds, steps_per_round, batch, lr, seed=0):
+    """The learned preconditioner's training protocol: pairs from the plain solver on
+    training meshes (200k-cell passages, one seed each, mean + 3 harmonics), generated in
+    the library (random starts, a snapshot every `every` DILU sweeps), then Adam on the
+    GPU, a round of steps on each mesh in turn (the state moves device to device).
+    Returns (checkpoint path, report)."""
+    import tempfile
+    import numpy as np
+    import torch
+    from paper_2404_01407_amd import fnlh, synth
+    ctxs, nets = [], []
+    t0 = time.perf_counter()
+    for sd in meshes_seeds:
+        m = synth.passage_block(*SHAPE, 36, seed=sd)
+        c = fnlh.Context(m, storage=storage, outer="exact")
+        c.assemble_jacobian(torch.from_numpy(synth.flow_state(m, sd)).cuda(), eps=0.6, sigma=50.0)
+        c.set_harmonics(synth.omegas_single_zone(N_HARM, 36))
+        n = fnlh.Network(c)
+        n.reserve_pairs((N_HARM + 1) * starts * snapshots)
+        ctxs.append(c)
+        nets.append(n)
+    t_setup = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k, n in enumerate(nets):
+        n.generate(list(range(N_HARM + 1)), starts, snapshots, every, seed=1000 + k)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    nets[0].set_weights(synth.he_init(seed))
+    hist = []
+    t0 = time.perf_counter()
+    prev = nets[0]
+    for r in range(rounds):
+        for k, n in enumerate(nets):
+            if n is not prev:
+                n.copy_state_from(prev)
+            hist.append(n.train(steps_per_round, batch=batch, lr=lr, seed=seed + 17 * r + k))
+            prev = n
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    path = os.path.join(tempfile.mkdtemp(prefix="fnlh_"), "net.fnlhnn")
+    prev.save(path)
+    h = np.concatenate(hist)
+    q = max(1, len(h) // 10)
+    pairs = sum(n.n_pairs() for n in nets)
+    for n, c in zip(nets, ctxs):
+        n.close()
+        c.close()
+    return path, {"train_meshes": [f"passage_block{SHAPE} seed {s}" for s in meshes_seeds], "pairs": pairs,
+                  "snapshot_every": every, "snapshots_per_start": snapshots, "adam_steps": len(h), "batch": batch,
+                  "lr": lr, "setup_s": round(t_setup, 2), "generate_s": round(t_gen, 2),
+                  "train_s": round(t_train, 2), "ms_per_sample": round(1e3 * t_train / max(len(h) * batch, 1), 3),
+                  "loss_first": round(float(np.mean(h[:q])), 4), "loss_last": round(float(np.mean(h[-q:])), 4)}
+
+
+def time_solve(ctx, bd, kind, reps, learn_every=32, max_sweeps=6000):
+    """Median wall time of a whole solve to the 1e-8 drop (graph replay) and its report."""
+    import numpy as np
+    import torch
+    times, rep, st = [], None, 0
+    S = len(bd)
+    for _ in range(reps):
+        xs = [torch.zeros_like(b) for b in bd]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, rep = ctx.relax(list(range(S)), xs, bd, kind=kind, max_sweeps=max_sweeps, rtol=RTOL, check_every=16,
+                            use_graph=True, learn_every=learn_every)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        if st not in CONVERGED:
+            raise RuntimeError(f"{kind} solve did not converge: {rep}")
+    return {"ms": round(1e3 * float(np.median(times)), 3), "status": st, "sweeps": [r["sweeps"] for r in rep],
+            "outer": [r["outer"] for r in rep], "learned_steps": [r["learned"] for r in rep],
+            "rejected": [r["fallbacks"] for r in rep], "fell_back": sum(r["status"] == 3 for r in rep),
+            "rel_res": [r["rel_res"] for r in rep]}
+
+
+def learned_eval(ctx, bd, ckpt, reps, learn_every, plain=None):
+    """Plain DILU against learned + DILU (+ FP64 defect correction in reduced precision) on
+    ctx's systems with the trained network loaded from ckpt."""
+    from paper_2404_01407_amd import fnlh
+    if plain is None:
+        plain = time_solve(ctx, bd, "dilu", reps)
+    net = fnlh.Network(ctx)
+    net.load(ckpt)
+    learned = time_solve(ctx, bd, "learned", reps, learn_every)
+    net.close()
+    return {"plain": plain, "learned": learned, "speedup_time": round(plain["ms"] / learned["ms"], 3),
+            "sweep_ratio": round(sum(plain["sweeps"]) / max(sum(learned["sweeps"]), 1), 3)}
+
+
+def heldout_eval(storage, ckpt, reps, learn_every, seed=14):
+    """The held-out test of the learned preconditioner: a 200k-cell passage of a seed no
+    pair came from, mean + 3 harmonics."""
+    import torch
+    from paper_2404_01407_amd import fnlh, synth
+    m = synth.passage_block(*SHAPE, 36, seed=seed)
+    c = fnlh.Context(m, storage=storage, outer="exact")
+    c.assemble_jacobian(torch.from_numpy(synth.flow_state(m, seed)).cuda(), eps=0.6, sigma=50.0)
+    c.set_harmonics(synth.omegas_single_zone(N_HARM, 36))
+    bd = [torch.from_numpy(synth.rhs(m.n_cells, s, real=(s == 0))).cuda() for s in range(N_HARM + 1)]
+    res = learned_eval(c, bd, ckpt, reps, learn_every)
+    res["mesh"] = f"passage_block{SHAPE} seed {seed} (held out)"
+    c.close()
+    return res
+
+
+def precision_summary(args):
+    """The 200k-cell precision configuration as a sub-field: time to 1e-8 and the error of
+    each block precision's solution against the FP64 one (FP64 is held to the oracle by
+    the parity tests)."""
+    import torch
+    mesh, Q, om, bs = build_inputs()
+    sols, out = {}, {}
+    for s in ("f64", "f32", "bf16"):
+        r = Runner(mesh, Q, om, bs, s, check_every=16, use_graph=True)
+        m = r.timed(3, 1)
+        sols[s] = [x.clone() for x in r.xd]
+        out[s] = {"ms_per_step": round(m["ms_per_step"], 3), "updates_per_s": round(m["updates_per_s"]),
+                  "sweeps": m["sweeps"], "outer": m["outer"]}
+        r.ctx.close()
+    for s in ("f32", "bf16"):
+        out[s]["err_vs_f64"] = [float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+                                for a, b in zip(sols[s], sols["f64"])]
+    return {"workload": "200k-cell passage 80x50x50, mean + 3 harmonics, DILU to 1e-8", "by_storage": out}
+
+
+def run_largest(args):
+    """The headline: three-row sector (rotor-stator-rotor, 3 x 100x64x100 = 1.92M cells
+    plus the pitch-overlap interface couplings, greedy colouring: two large colours and a
+    remainder of interface rows), mean + 10 harmonics at mixed per-row frequencies, one
+    shared Jacobian in FP32 with the FP64 defect correction, DILU sweeps (two-colour
+    passes plus remainder passes) to a 1e-8 residual drop.  One step = assemble K, set the
+    harmonics, factor the 11 systems, sweep all of them to 1e-8 with the FP64 outer
+    residual.  The last timed step also times every sweep-pass launch with HIP events."""
+    import numpy as np
+    import torch
+    from paper_2404_01407_amd import fnlh
+    t0 = time.perf_counter()
+    mesh, Q, om, bs = build_largest(args.largest_shape)
+    S = len(bs)
+    print(f"[bench] largest: {mesh.n_cells} cells, {mesh.n_edges} faces, {S} systems, inputs "
           f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    colour, _, n_col = fnlh.order_mesh(mesh)
+    sample = None
+    if not args.no_cpu_baseline:
+        # the oracle sample runs before the GPU is initialised (its process pool forks)
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        sample = cpu_sample_largest(mesh, Q, om, bs, colour, min(16, os.cpu_count() or 1))
+        print(f"[bench] oracle sample: assembly {sample['t_asm']:.1f} s, factor {sample['t_fac1']:.1f} s, sweep "
+              f"{sample['t_sw1']:.1f} s, pool of {sample['workers']} {sample['t_pool_wall']:.1f} s", file=sys.stderr,
+              flush=True)
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calib_copy:
+        calib_copy()
     t0 = time.perf_counter()
     ctx = fnlh.Context(mesh, storage=args.storage, outer="exact")
     ingest_ms = 1e3 * (time.perf_counter() - t0)
-    colour, n_col = ctx.ordering()
+    ctx.tune(hybrid=args.hybrid)
     Qd = torch.from_numpy(Q).cuda()
     bd = [torch.from_numpy(b).cuda() for b in bs]
     mem = {}
-    for k in (1, 3, 6, n_h + 1):
+    for k in (1, 3, 6, S):
         ctx.assemble_jacobian(Qd, eps=0.6, sigma=50.0)
         ctx.set_harmonics(om[:k])
         xs = [torch.zeros_like(b) for b in bd[:k]]
@@ -287,103 +559,104 @@ def run_largest(args):
         mem[k] = ctx.memory()
         del xs
     print(f"[bench] largest: memory by system count {mem}", file=sys.stderr, flush=True)
-    S = len(bs)
+    xd = [torch.zeros_like(b) for b in bd]
 
-    def step(kind):
-        xs = [torch.zeros_like(b) for b in bd]
+    def step():
+        for x in xd:
+            x.zero_()
         ctx.assemble_jacobian(Qd, eps=0.6, sigma=50.0)
         ctx.set_harmonics(om)
-        st, rep = ctx.relax(list(range(S)), xs, bd, kind=kind, max_sweeps=6000, rtol=RTOL, check_every=16,
-                            use_graph=True, learn_every=args.learn_every)
+        st, rep = ctx.relax(list(range(S)), xd, bd, kind="dilu", max_sweeps=6000, rtol=RTOL, check_every=16,
+                            use_graph=not args.no_graph)
         if st not in CONVERGED:
-            raise RuntimeError(f"largest: {kind} solve did not converge: {rep}")
+            raise RuntimeError(f"largest: solve did not converge: {rep}")
         return rep
 
-    step("dilu")
+    for _ in range(args.warmup):
+        step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        rep = step("dilu")
+    reps = []
+    for i in range(args.steps):
+        if i == args.steps - 1 and not args.no_stats:
+            ctx.stats_enable(True, period=1)  # events around every sweep-pass launch of the last step
+        reps.append(step())
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
-    sweeps = [r["sweeps"] for r in rep]
-    print(f"[bench] largest: {1e3 * dt:.1f} ms/step, sweeps {sweeps}", file=sys.stderr, flush=True)
-    ctx.stats_enable(True, period=STATS_PERIOD)
-    step("dilu")
-    torch.cuda.synchronize()
-    st = ctx.stats()
+    stats = ctx.stats()
     ctx.stats_enable(False)
+    rep = reps[-1]
+    sweeps = [r["sweeps"] for r in rep]
+    updates_per_step = [mesh.n_cells * sum(r["sweeps"] for r in rp) for rp in reps]
+    print(f"[bench] largest: {1e3 * dt:.1f} ms/step, sweeps {sweeps}", file=sys.stderr, flush=True)
     kernels = {}
-    for name in ("fwd", "bwd", "sweep_update", "sweep_set"):
-        k = st[name]
+    for name, k in stats.items():
         if k["launches"]:
             ms = k["total_ms"] / k["launches"]
             kernels[name] = {"launches": k["launches"], "avg_launch_us": round(1e3 * ms, 2),
+                             "alg_bytes_per_launch": round(k["alg_bytes"] / k["launches"]),
                              "achieved_GBs": round(k["alg_bytes"] / k["launches"] / (ms * 1e-3) / 1e9, 1)}
-    tot_ms = sum(st[n]["total_ms"] for n in ("fwd", "bwd", "sweep_update", "sweep_set"))
-    tot_b = sum(st[n]["alg_bytes"] for n in ("fwd", "bwd", "sweep_update", "sweep_set"))
-    sweep_gbs = tot_b / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
+    sweep_kinds = [n for n in ("sweep_update", "sweep_set", "fwd", "fwd_last", "bwd", "remainder") if n in kernels]
+    tot_ms = sum(stats[n]["total_ms"] for n in sweep_kinds)
+    tot_b = sum(stats[n]["alg_bytes"] for n in sweep_kinds)
+    dom = max(sweep_kinds, key=lambda n: stats[n]["total_ms"]) if sweep_kinds else None
+    roofline = None
+    if dom:
+        kd = kernels[dom]
+        names = {"sweep_update": "k_rb_pass<f32, update> (second-colour update pass)",
+                 "sweep_set": "k_rb_pass<f32, set> (first-colour pass)", "fwd": "k_fwd<f32> (general forward)",
+                 "bwd": "k_bwd<f32> (general backward)"}
+        traffic, src = traffic_from_profile(LARGEST_PROFILE) if dom == "sweep_update" else (None, "no counter run")
+        roofline = {"bound": "hbm", "achieved": kd["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "traffic_source": src, "kernel": names.get(dom, dom), "avg_launch_us": kd["avg_launch_us"],
+                    "alg_bytes_per_launch": kd["alg_bytes_per_launch"], "launches": kd["launches"],
+                    "all_sweep_kernels_GBs": round(tot_b / (tot_ms * 1e-3) / 1e9, 1) if tot_ms else None,
+                    "all_sweep_kernels_frac": round(tot_b / (tot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if tot_ms else None}
     learned = None
     if not args.no_learned:
-        net = fnlh.Network(ctx)
-        net.set_weights(synth.he_init(0))
-        zero = torch.zeros_like(bd[0])
-        gen = torch.Generator(device="cuda")
-        gen.manual_seed(99)
-        n_pairs = 8 * S
-        net.reserve_pairs(n_pairs)
-        t0 = time.perf_counter()
-        for k in range(8):
-            xs = [torch.randn(bd[0].shape, dtype=torch.complex128, device="cuda", generator=gen) for _ in range(S)]
-            ctx.relax(list(range(S)), xs, [zero] * S, kind="dilu", max_sweeps=[8, 16, 32, 64][k % 4], rtol=0.0,
-                      check_every=8)
-            for j in range(S):
-                r = torch.empty_like(xs[j])
-                ctx.residual(j, xs[j], zero, r)
-                net.add_pairs([j], [r], [-xs[j]])
-            del xs
-        hist = net.train(64, batch=4, lr=1e-3, seed=1)
-        torch.cuda.synchronize()
-        t_train = time.perf_counter() - t0
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rep_l = step("learned")
-        torch.cuda.synchronize()
-        t_l = time.perf_counter() - t0
-        learned = {"ms": round(1e3 * t_l, 2), "sweeps": [r["sweeps"] for r in rep_l],
-                   "learned_steps": [r["learned"] for r in rep_l], "rejected": [r["fallbacks"] for r in rep_l],
-                   "rel_res": [r["rel_res"] for r in rep_l], "pairs": n_pairs, "train_steps": 64,
-                   "generate_and_train_s": round(t_train, 2),
-                   "loss_first": round(float(np.mean(hist[:6])), 4), "loss_last": round(float(np.mean(hist[-6:])), 4),
+        print("[bench] learned: training on held-out-protocol pairs (seeds 10-13)", file=sys.stderr, flush=True)
+        ckpt, training = train_heldout(args.storage, [10, 11, 12, 13], args.learn_starts, 8, 4, args.learn_rounds,
+                                       8, 8, 1e-3)
+        on5 = learned_eval(ctx, bd, ckpt, 1, args.learn_every, plain=time_solve(ctx, bd, "dilu", 1))
+        print(f"[bench] learned on the sector: plain {on5['plain']['ms']} ms, learned {on5['learned']['ms']} ms",
+              file=sys.stderr, flush=True)
+        held = heldout_eval(args.storage, ckpt, 3, args.learn_every)
+        print(f"[bench] learned on held-out seed 14: plain {held['plain']['ms']} ms, learned "
+              f"{held['learned']['ms']} ms", file=sys.stderr, flush=True)
+        learned = {"training": training, "on_this_workload": on5, "held_out_200k": held,
                    "learn_every": args.learn_every}
-        print(f"[bench] largest learned: {learned['ms']} ms, sweeps {learned['sweeps']}", file=sys.stderr,
-              flush=True)
-        net.close()
-    updates = mesh.n_cells * sum(sweeps)
+    colours = ctx.ordering()[1]
+    ctx.close()
+    precision = None
+    if not args.no_modes:
+        precision = precision_summary(args)
+    cpu = cpu_baseline_from(sample, mesh.n_cells, sweeps, "same 1.92M-cell sector") if sample else None
     out = {
         "metric": METRIC,
-        "value": round(updates / dt),
-        "unit": "cell-unknown updates/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "value": round(sum(updates_per_step) / (dt * args.steps)),
+        "unit": "cell-system-sweep updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(1e3 * dt, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"f64": "f64", "f32": "f32 blocks, f32 sweep, f64 outer residual",
-                  "bf16": "bf16 blocks, f32 sweep, f64 outer residual"}[args.storage],
+        "dtype": _dtype_of(args.storage),
         "data": "synthetic",
-        "config": {"workload": ("three-row sector rotor-stator-rotor 3 x 100x64x100 (36/60/48 blades), mean + 10 "
-                                "harmonics at mixed per-row frequencies, one shared Jacobian, DILU sweeps on a "
-                                "greedy colouring to a 1e-8 residual drop"),
-                   "cells": mesh.n_cells, "faces": mesh.n_edges, "systems": S, "colours": n_col,
-                   "storage": args.storage},
+        "config": {"workload": ("three-row sector rotor-stator-rotor 3 x 100x64x100 (36/60/48 blades, pitch-overlap "
+                                "interfaces), mean + 10 harmonics at mixed per-row frequencies, one shared FP32 "
+                                "Jacobian, DILU (two-colour + remainder passes) with FP64 defect correction to a "
+                                "1e-8 residual drop"),
+                   "cells": mesh.n_cells, "faces": mesh.n_edges, "systems": S, "colours": colours,
+                   "storage": args.storage, "eps": 0.6, "sigma": 50.0},
         "time_to_1e-8_ms": round(1e3 * dt, 3),
         "sweeps": sweeps,
         "outer": [r["outer"] for r in rep],
         "rel_res": [r["rel_res"] for r in rep],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
         "sweep_kernels": kernels,
-        "sweep_kernels_GBs": round(sweep_gbs, 1),
-        "sweep_kernels_frac_of_hbm_peak": round(sweep_gbs / HBM_PEAK_GBS, 4),
         "memory_bytes_by_systems": {str(k): v for k, v in mem.items()},
         "learned": learned,
+        "precision_200k": precision,
         "ingest_ms": round(ingest_ms, 1),
     }
     print(json.dumps(out), flush=True)
@@ -450,8 +723,9 @@ def run_phase(args):
 
 
 def _dtype_of(storage):
-    return {"f64": "f64", "f32": "f32 blocks, f32 sweep, f64 outer residual",
-            "bf16": "bf16 blocks, f32 sweep, f64 outer residual"}[storage]
+    return {"f64": "f64 blocks and factor inverses, f64 sweep",
+            "f32": "f32 blocks, f16 factor inverses (power-of-two row scale), f32 sweep, f64 outer residual",
+            "bf16": "bf16 blocks, f16 factor inverses (power-of-two row scale), f32 sweep, f64 outer residual"}[storage]
 
 
 def run_krylov(args):
@@ -806,11 +1080,12 @@ def main():
     ap.add_argument("--check-every", type=int, default=16, help="sweeps between host checks of the stop flags")
     ap.add_argument("--no-graph", action="store_true", help="direct launches instead of graph replay")
     ap.add_argument("--no-stats", action="store_true", help="no per-kernel event timing in the timed region")
-    ap.add_argument("--workload", default="precision",
+    ap.add_argument("--workload", default="largest",
                     choices=["precision", "batch", "learned", "largest", "phase", "krylov", "rk", "partition"],
-                    help="precision: 200k cells, mean + 3 harmonics (default); batch: 64 uneven instances; "
-                         "learned: network training and learned vs plain solves; largest: 1.92M-cell three-row "
-                         "sector, mean + 10 harmonics; phase: phase-lagged periodic cascade; krylov: FGMRES vs "
+                    help="largest: 1.92M-cell three-row sector, mean + 10 harmonics (default); precision: 200k "
+                         "cells, mean + 3 harmonics at FP64/FP32/BF16; batch: 64 uneven instances; learned: the "
+                         "held-out training protocol and learned vs plain solves; phase: phase-lagged periodic "
+                         "cascade; krylov: FGMRES vs "
                          "Richardson; rk: RK(5,3) pseudo-time steps around paper-mode solves; partition: RK convergence "
                          "with the couplings between partitions dropped, by partition size")
     ap.add_argument("--part-sizes", type=float, nargs="+", default=[16384, 4096, 1024, 256, 64],
@@ -826,6 +1101,13 @@ def main():
     ap.add_argument("--batch", type=int, default=8, help="learned workload: pairs per Adam step")
     ap.add_argument("--learn-every", type=int, default=32, help="sweeps between learned corrections")
     ap.add_argument("--no-learned", action="store_true", help="skip the short learned-vs-plain comparison")
+    ap.add_argument("--hybrid", type=int, default=1, choices=[0, 1, 2],
+                    help="multi-colour orderings: 1 two-colour + remainder passes when the remainder is small "
+                         "(default), 0 general passes, 2 always two-colour + remainder")
+    ap.add_argument("--learn-starts", type=int, default=16,
+                    help="largest workload: random starts per system and training mesh (8 snapshots each)")
+    ap.add_argument("--learn-rounds", type=int, default=15,
+                    help="largest workload: training rounds (8 Adam steps on each of the 4 meshes per round)")
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--batch-loop-cells", type=int, default=None,
                     help="batch workload: instances of at least this many cells are iterated alone inside the "
@@ -837,14 +1119,14 @@ def main():
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "largest":
+        return run_largest(args)  # initialises the GPU after its CPU oracle sample
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "batch":
         return run_batch(args)
     if args.workload == "learned":
         return run_learned(args)
-    if args.workload == "largest":
-        return run_largest(args)
     if args.workload == "phase":
         return run_phase(args)
     if args.workload == "krylov":
@@ -855,13 +1137,7 @@ def main():
         return run_partition(args)
 
     if args.calib_copy:
-        xs = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
-        ys = torch.empty_like(xs)
-        for _ in range(3):
-            torch.neg(xs, out=ys)
-        torch.cuda.synchronize()
-        del xs, ys
-        print("[bench] calibration: torch.neg over 1 GiB (read 1 GiB, write 1 GiB) x3", file=sys.stderr, flush=True)
+        calib_copy()
 
     mesh, Q, om, bs = build_inputs()
     print(f"[bench] inputs: {mesh.n_cells} cells, {mesh.n_edges} faces, {len(bs)} systems", file=sys.stderr, flush=True)

@@ -544,6 +544,10 @@ int fnlh_nn_train(fnlh_nn nn, int32_t steps, int32_t batch, float lr, uint64_t s
  * non-finite values). */
 int fnlh_nn_save(fnlh_nn nn, const char* path);
 int fnlh_nn_load(fnlh_nn nn, const char* path);
+/* The same state (FP32 weights, Adam moments and step count) copied device to device
+ * from src to dst, networks of two contexts on one device (e.g. training one network
+ * on pairs from several meshes, a round on each in turn).  src needs weights. */
+int fnlh_nn_copy_state(fnlh_nn dst, fnlh_nn src);
 /* Matrix-core check: out = A B for 64x64 BF16 operands (host a [64][64], host bt = B^T
  * [64][64], raw BF16 bits), FP32 out [64][64], computed by the network's tile routine. */
 int fnlh_nn_selftest(fnlh_ctx c, const uint16_t* a, const uint16_t* bt, float* out);

@@ -575,6 +575,23 @@ int fnlh_nn_get_pair(fnlh_nn nn, int64_t k, int32_t* sys, double* r, double* e, 
   return check_launch(c, "get_pair launch");
 }
 
+int fnlh_nn_copy_state(fnlh_nn dst, fnlh_nn src) {
+  if (!dst || !src) return FNLH_E_ARG;
+  if (!dst->c || !src->c) return FNLH_E_ORDER;
+  fnlh_ctx c = dst->c;
+  if (!src->weights_set) return set_err(c, FNLH_E_ORDER, "copy_state: source has no weights");
+  if (src->c->dev != c->dev) return set_err(c, FNLH_E_ARG, "copy_state: networks on different devices");
+  HIPC(c, hipDeviceSynchronize(), "copy sync");
+  HIPC(c, hipMemcpy(dst->master.p, src->master.p, kNnParams * sizeof(float), hipMemcpyDeviceToDevice), "copy");
+  HIPC(c, hipMemcpy(dst->mom1.p, src->mom1.p, kNnParams * sizeof(float), hipMemcpyDeviceToDevice), "copy");
+  HIPC(c, hipMemcpy(dst->mom2.p, src->mom2.p, kNnParams * sizeof(float), hipMemcpyDeviceToDevice), "copy");
+  nn_launch_cast((const float*)dst->master.p, (uint16_t*)dst->wt.p, (uint16_t*)dst->w.p, nullptr);
+  HIPC(c, hipDeviceSynchronize(), "cast weights");
+  dst->adam_t = src->adam_t;
+  dst->weights_set = true;
+  return check_launch(c, "cast weights");
+}
+
 namespace {
 struct CkptHead {
   char magic[8];

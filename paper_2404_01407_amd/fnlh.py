@@ -127,6 +127,7 @@ def _load():
         "fnlh_nn_get_pair": (I32, [P, I64, C.POINTER(I32), V, V, V]),
         "fnlh_nn_save": (I32, [P, C.c_char_p]),
         "fnlh_nn_load": (I32, [P, C.c_char_p]),
+        "fnlh_nn_copy_state": (I32, [P, P]),
         "fnlh_nn_destroy": (I32, [P]),
         "fnlh_nn_set_grad_groups": (I32, [P, I32]),
         "fnlh_nn_set_weights": (I32, [P, V]),
@@ -668,6 +669,10 @@ class Network:
 
     def load(self, path):
         self.ctx._check(LIB.fnlh_nn_load(self.h, os.fsencode(path)))
+
+    def copy_state_from(self, other):
+        """Take other's weights, Adam moments and step count (device to device)."""
+        self.ctx._check(LIB.fnlh_nn_copy_state(self.h, other.h))
 
     def clear_pairs(self):
         self.ctx._check(LIB.fnlh_nn_clear_pairs(self.h))

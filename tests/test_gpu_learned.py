@@ -422,6 +422,23 @@ def test_save_load_resumes_training_bitwise(F, small, tmp_path):
         c.close()
 
 
+def test_copy_state_equals_checkpoint(F, small):
+    """Training state copied device to device continues exactly as the original."""
+    m, Q, K, om = small
+    ctxs = [_ctx(F, m, K, om) for _ in range(2)]
+    a, b = [F.Network(c) for c in ctxs]
+    for n in (a, b):
+        n.generate([0, 2], 2, 2, 4, seed=5)
+    a.set_weights(_weights(23))
+    a.train(4, batch=2, lr=1e-3, seed=1)
+    b.copy_state_from(a)
+    assert np.array_equal(a.train(3, batch=2, lr=1e-3, seed=2), b.train(3, batch=2, lr=1e-3, seed=2))
+    assert np.array_equal(a.get_weights(), b.get_weights())
+    for n, c in zip((a, b), ctxs):
+        n.close()
+        c.close()
+
+
 def test_network_width_is_checked(F, small):
     m, Q, K, om = small
     c = _ctx(F, m, K, om)

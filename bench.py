@@ -35,17 +35,12 @@ N_HARM = 3
 RTOL = 1e-8
 CONVERGED = (0, 3)  # FNLH_OK, FNLH_FELL_BACK (learned corrections switched off, plain sweeps converged)
 STATS_PERIOD = 4  # time the sweep-pass launches of every 4th sweep (bounds event overhead)
-# HBM bytes per launch of the update pass from two rocprofv3 counter runs (FETCH_SIZE x 2.0
-# + WRITE_SIZE x 1.0, calibrated on a 1 GiB copy), for the kernel these sources build at the
-# default configuration (FP32 blocks, 4 systems, 4 lanes per row):
-# profiles/k_rb_pass_f32_200k_mean3h.md.  Reported only for that configuration.
-UPDATE_PASS_TRAFFIC = {("f32", 4): 230542639}
 
 
-def build_inputs():
+def build_inputs(shape=SHAPE):
     import numpy as np
     from paper_2404_01407_amd import synth
-    mesh = synth.passage_block(*SHAPE, 36, seed=2)
+    mesh = synth.passage_block(*shape, 36, seed=2)
     Q = synth.flow_state(mesh, 2)
     om = synth.omegas_single_zone(N_HARM, 36)
     bs = [synth.rhs(mesh.n_cells, s, real=(s == 0)) for s in range(N_HARM + 1)]
@@ -302,6 +297,10 @@ def traffic_from_profile(name):
     if m.group(2) != kernel_sources_sha():
         return None, "kernel sources changed since the counter runs"
     return int(m.group(1)), f"profiles/{name}"
+
+
+def precision_profile_name(storage, n_cells):
+    return f"k_rb_pass_{storage}_{n_cells // 1000}k_mean3h.md"
 
 
 def build_largest(shape):
@@ -1094,6 +1093,9 @@ def main():
     ap.add_argument("--part-cfl", type=float, nargs="+", default=[50.0, 10.0], help="partition workload: CFL numbers")
     ap.add_argument("--restart", type=int, default=20, help="krylov workload: Krylov vectors per cycle")
     ap.add_argument("--inner-sweeps", type=int, default=1, help="krylov workload: sweeps per preconditioner application")
+    ap.add_argument("--shape", type=int, nargs=3, default=list(SHAPE),
+                    help="precision workload: passage cells (axial, pitch, radial); 160 100 100 gives a 1.6M-cell "
+                         "working set far above the Infinity Cache")
     ap.add_argument("--largest-shape", type=int, nargs=3, default=[100, 64, 100],
                     help="largest workload: cells per row (axial, pitch, radial)")
     ap.add_argument("--pairs", type=int, default=10000, help="learned workload: training pairs")
@@ -1139,7 +1141,7 @@ def main():
     if args.calib_copy:
         calib_copy()
 
-    mesh, Q, om, bs = build_inputs()
+    mesh, Q, om, bs = build_inputs(tuple(args.shape))
     print(f"[bench] inputs: {mesh.n_cells} cells, {mesh.n_edges} faces, {len(bs)} systems", file=sys.stderr, flush=True)
     main_run = Runner(mesh, Q, om, bs, args.storage, args.lanes, args.row_lanes, args.check_every,
                       not args.no_graph, args.wave_groups)
@@ -1152,11 +1154,11 @@ def main():
     avg_ms = upd["total_ms"] / max(upd["launches"], 1)
     bytes_per_launch = upd["alg_bytes"] / max(upd["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    traffic = None
-    if (args.storage, len(bs)) in UPDATE_PASS_TRAFFIC and args.lanes == 0 and args.row_lanes == 0:
-        traffic = UPDATE_PASS_TRAFFIC[(args.storage, len(bs))]
+    traffic, traffic_src = None, "not measured for a tuned kernel shape"
+    if args.lanes == 0 and args.row_lanes == 0:
+        traffic, traffic_src = traffic_from_profile(precision_profile_name(args.storage, mesh.n_cells))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": traffic_src,
                 "kernel": f"k_rb_pass<{args.storage}, update> (two-colour sweep pass over the second colour)",
                 "avg_launch_us": round(1e3 * avg_ms, 2), "alg_bytes_per_launch": round(bytes_per_launch),
                 "launches": upd["launches"]}
@@ -1213,11 +1215,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f64": "f64", "f32": "f32 blocks, f32 sweep, f64 outer residual",
-                  "bf16": "bf16 blocks, f32 sweep, f64 outer residual"}[args.storage],
+        "dtype": _dtype_of(args.storage),
         "data": "synthetic",
-        "config": {"workload": ("200k-cell hex annular passage sector 80x50x50 (589,500 faces), mean + 3 harmonics "
-                                "(omega = 0, 18, 36, 54), DILU-preconditioned Richardson to a 1e-8 residual drop"),
+        "config": {"workload": (f"{mesh.n_cells}-cell hex annular passage sector {'x'.join(map(str, args.shape))} "
+                                f"({mesh.n_edges} faces), mean + 3 harmonics (omega = 0, 18, 36, 54), "
+                                "DILU-preconditioned Richardson to a 1e-8 residual drop"),
                    "cells": mesh.n_cells, "faces": mesh.n_edges, "systems": len(bs), "storage": args.storage,
                    "eps": 0.6, "sigma": 50.0},
         "time_to_1e-8_ms": round(res["ms_per_step"], 3),

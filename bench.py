@@ -270,13 +270,18 @@ def calib_copy():
 
 
 def kernel_sources_sha():
-    """Fingerprint of the sweep kernels' sources: a counter summary taken with other
-    sources no longer describes the kernel this build launches."""
+    """Fingerprint of the sweep kernels' sources (comments and layout stripped): a
+    counter summary taken with other code no longer describes the kernel this build
+    launches."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("kernels.hip", "kernels.h", "device.h"):
-        with open(os.path.join(ROOT, "paper_2404_01407_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2404_01407_amd", "csrc", f)) as fh:
+            code = fh.read()
+        code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 

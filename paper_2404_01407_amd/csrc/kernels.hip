@@ -558,7 +558,13 @@ __global__ void __launch_bounds__(256) k_rb_pass(DevPattern p, const TB* __restr
                                                  SysState* st, double* __restrict__ partial,
                                                  int64_t t0, int64_t nt, int wave_groups, FusedReduce fr) {
   // first-colour pass: the first fr.n workgroups reduce the preceding update pass's norms
-  // (one system each) while the others sweep
+  // (one system each) while the others sweep.  The sweeping workgroups read each
+  // system's `active` flag while a reducing workgroup may be rewriting that state: a
+  // system the reduction retires (it was pending) may or may not be swept here, and both
+  // are right, because its update pass did not run this sweep (pending systems skip
+  // it), so this pass would recompute exactly the x it computed last sweep.  The flags
+  // the sweeping workgroups act on are otherwise unchanged by the reduction (it only
+  // turns pending systems off and running ones pending).
   int64_t blk = blockIdx.x;
   if (!UPDATE && fr.n > 0) {
     if (blk < fr.n) {

@@ -830,6 +830,11 @@ def run_rk(args):
         "stage_solves_per_step": stage_solves,
         "mean_residual_first_last": [hist_m[0], hist_m[-1]],
         "harmonic_residual_first_last": [[h[0], h[-1]] for h in hist_h],
+        # the paper's harmonic residual monitor: R_z = sqrt(mean over the harmonics of the
+        # squared RMS of each harmonic's residual), RMS over the 6N complex entries
+        "R_z_per_step": [float(np.sqrt(np.mean([(h[k] ** 2) / (6 * mesh.n_cells) for h in hist_h])))
+                         for k in range(len(hist_h[0]))],
+        "mean_rms_per_step": [float(v / np.sqrt(6 * mesh.n_cells)) for v in hist_m],
     }
     print(json.dumps(res), flush=True)
 
@@ -946,8 +951,9 @@ def run_batch(args):
     for c, sy in zip(ctxs, systems):
         k = len(sy)
         if k not in tuned:
-            tuned[k] = c.autotune(k, sweeps=16)
-        c.tune(tuned[k]["sys_per_lane"], tuned[k]["lanes_per_row"])
+            tuned[k] = c.autotune(k, rtol=RTOL)
+        c.tune(tuned[k]["sys_per_lane"], tuned[k]["lanes_per_row"], wave_groups=tuned[k]["wave_groups"],
+               hybrid=tuned[k]["hybrid"])
     B = fnlh.Batch(ctxs)
     if args.batch_loop_cells is not None:
         B.set_loop_cells(args.batch_loop_cells)

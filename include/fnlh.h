@@ -184,6 +184,9 @@ typedef struct {
   double div_factor;     /* DIVERGED when ||r|| > div_factor ||r0|| (0 = 1e3)               */
   int32_t use_graph;     /* 1: replay check_every sweeps as one captured hipGraph            */
   int32_t learn_every;   /* FNLH_LEARNED, FP64 blocks: sweeps between learned corrections (0 = 16) */
+  double* history;       /* host [n][history_len] or NULL: residual history per system (fnlh_relax) */
+  int32_t history_len;   /* entries per system                                                */
+  int32_t pad_;
 } fnlh_relax_opts;
 
 typedef struct {
@@ -216,7 +219,13 @@ typedef struct {
  * Returns the worst per-system status (FNLH_OK if all converged) or an error.
  * The tolerance test is evaluated on the residual of the previous iterate, computed
  * inside the sweep; the returned x is one sweep past the first iterate that met it and
- * rel_res is recomputed for it with the outer operator. */
+ * rel_res is recomputed for it with the outer operator.
+ * history (opts, optional): entry m of system j is ||b - K_s x^m|| after m sweeps as the
+ * stop test measured it (entry 0 the initial residual; FP64 blocks: the FP64 residual of
+ * every sweep; FP32/BF16 blocks: the FP64 residual after each outer correction and, in
+ * between, the inner iteration's residual of the stored operator), entry sweeps the
+ * returned x's (rel_res times res0), NaN beyond; at most history_len entries.  The
+ * batched relax ignores it. */
 int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x,
                const double* const* b, const fnlh_relax_opts* opts, fnlh_sys_report* rep,
                void* stream);
@@ -292,6 +301,16 @@ const char* fnlh_batch_last_error(fnlh_batch b);
  * eligible instance batched.  Results are the same either way (the batched and
  * per-instance sweeps are bitwise equal). */
 int fnlh_batch_set_loop_cells(fnlh_batch b, int64_t loop_cells);
+/* Batch autotuner: for each of the n_cand (1..64) candidate thresholds cand[k] (cells;
+ * <= 0 batches every eligible instance) it runs fnlh_batch_relax with the arguments given
+ * from a zero start, once to warm up and once timed with events on the stream (ms[k],
+ * may be NULL), keeps the fastest threshold on the batch (*pick, may be NULL) and solves
+ * once more with it: x is overwritten and holds that solve's result.  The instance
+ * contexts' own settings (fnlh_autotune) are left as they are.  Returns the status of
+ * the last solve. */
+int fnlh_batch_autotune(fnlh_batch b, const int32_t* n_sys, const int32_t* const* sys, double* const* const* x,
+                        const double* const* const* bvec, const fnlh_relax_opts* opts, int32_t n_cand,
+                        const int64_t* cand, int64_t* pick, double* ms, void* stream);
 
 /* Kernel timing of the sweep passes.  While enabled, every sweep-pass launch is
  * bracketed by HIP events on the caller's stream; durations and the algorithmic bytes
@@ -342,20 +361,29 @@ int fnlh_stats_get(fnlh_ctx c, int32_t which, fnlh_kernel_stats* out);
 enum { FNLH_TUNE_SYS_PER_LANE = 0, FNLH_TUNE_LANES_PER_ROW = 1, FNLH_TUNE_WAVE_GROUPS = 2, FNLH_TUNE_HYBRID = 3 };
 int fnlh_tune(fnlh_ctx c, int32_t param, int32_t value);
 
-/* Autotuner: times `sweeps` preconditioned sweeps of the first n_sys systems (constant
- * right-hand side, zero start) for every feasible kernel shape (lanes per row 1/2/4 x
- * systems per lane 1/2/4 of the sweep kernels) and keeps the fastest on the context
- * (as fnlh_tune would).  Requires harmonics; the ordering is the context's.  out
- * (may be NULL) receives the choice and the measured time per sweep. */
+/* Autotuner: picks the sweep configuration by the time of whole solves.  For every
+ * candidate (path: two-colour plus remainder or general passes when the ordering has
+ * three or more colours; kernel shape: lanes per row 1/2/4 x systems per lane 1/2/4 or
+ * automatic; one wave or one tile per workgroup) it solves the first n_sys systems
+ * (right-hand side of ones, zero start, graph replay) to rtol with at most max_sweeps
+ * sweeps (rtol 0: exactly max_sweeps sweeps), once to warm up (factors, graphs) and
+ * twice timed with events on the stream, and keeps the fastest on the context (as
+ * fnlh_tune would).  The candidates give the same iterates up to rounding (bitwise for
+ * the kernel shape and workgroup mapping).  Requires harmonics; allocates two
+ * n_sys-vector buffers for the call.  out (may be NULL) receives the choice, its time
+ * and that of the first (default) candidate. */
 typedef struct {
-  int32_t lanes_per_row;
-  int32_t sys_per_lane;
-  double us_per_sweep;     /* best: sum of sweep-pass kernel times per sweep (all systems) */
-  double us_per_sweep_default;  /* the automatic choice, for comparison */
-  int32_t candidates;      /* shapes timed */
-  int32_t pad_;
+  int32_t lanes_per_row;   /* 0 = automatic */
+  int32_t sys_per_lane;    /* 0 = automatic */
+  int32_t wave_groups;     /* 1 = one wave per workgroup */
+  int32_t hybrid;          /* path knob (FNLH_TUNE_HYBRID)  */
+  double ms_best;          /* fastest solve of the pick (ms)  */
+  double ms_default;       /* the default configuration's      */
+  int32_t sweeps;          /* sweeps of the pick's solve, summed over the systems */
+  int32_t candidates;      /* configurations timed */
 } fnlh_tune_result;
-int fnlh_autotune(fnlh_ctx c, int32_t n_sys, int32_t sweeps, fnlh_tune_result* out, void* stream);
+int fnlh_autotune(fnlh_ctx c, int32_t n_sys, double rtol, int32_t max_sweeps, fnlh_tune_result* out,
+                  void* stream);
 
 /* ---- Krylov solve: restarted flexible GMRES around the same preconditioners (section
  * "Generalized RK Scheme for The Mean Flow": the ILU(0) approximation of K^-1 is used

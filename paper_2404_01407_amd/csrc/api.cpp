@@ -1465,6 +1465,17 @@ int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, cons
   if (rc) return rc;
   SysState* st = (SysState*)c->st.p;
   SysState* so = (SysState*)c->st_outer.p;
+  // residual history: norm^2 per sweep on the device, [n][len]
+  const int hlen = (o->history && o->history_len > 0) ? o->history_len : 0;
+  DevBuf hist;
+  struct FreeOnExit {
+    DevBuf* b;
+    ~FreeOnExit() { dfree(*b); }
+  } hist_guard{&hist};
+  if (hlen) {
+    if ((rc = dalloc(c, hist, (size_t)n * hlen * sizeof(double), "alloc history"))) return rc;
+    launch_fill_zero(hist.p, hist.bytes, s);
+  }
   for (int g0 = 0; g0 < n; g0 += P.G) {
     SysBatch sb;
     sb.n = std::min(P.G, n - g0);
@@ -1479,6 +1490,7 @@ int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, cons
       outer_residual(c, n, sb, nullptr, s);
       launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, 1, st, kReduceInit, 0, 0,
                     o->max_sweeps, s);
+      if (hlen) launch_set_history(sb, st, (double*)hist.p, hlen, s);
       if (!P.learned) {
         if ((rc = sweep_loop(c, P.path, P.cfg, n, sb, c->x64.p, c->b64.p, c->y.p, st, o->rtol, P.divf,
                              o->max_sweeps, P.check_every, P.use_graph, s)))
@@ -1502,6 +1514,7 @@ int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, cons
       outer_residual(c, n, sb, (double*)c->r64.p, s);
       launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, 1, so, kReduceInit, 0, 0,
                     o->max_sweeps, s);
+      if (hlen) launch_set_history(sb, so, (double*)hist.p, hlen, s);
       for (int it = 0; it < 100000; ++it) {
         if ((rc = check_launch(c, "outer launch"))) return rc;
         HIPC(c, hipMemcpyAsync(c->h_st, so, sizeof(SysState) * (sb.vslot[sb.n - 1] + 1), hipMemcpyDeviceToHost, s),
@@ -1539,7 +1552,24 @@ int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, cons
     counts.assign(2 * n, 0);
     if ((rc = nn_relax_counts(c, n, counts.data(), s))) return rc;
   }
-  return relax_reports(c->h_st, n, P, o, rep, P.learned ? counts.data() : nullptr, c);
+  std::vector<fnlh_sys_report> reps(n);
+  const int worst = relax_reports(c->h_st, n, P, o, reps.data(), P.learned ? counts.data() : nullptr, c);
+  if (rep) std::copy(reps.begin(), reps.end(), rep);
+  if (hlen) {
+    std::vector<double> h((size_t)n * hlen);
+    HIPC(c, hipMemcpyAsync(h.data(), hist.p, hist.bytes, hipMemcpyDeviceToHost, s), "read history");
+    HIPC(c, hipStreamSynchronize(s), "history sync");
+    for (int j = 0; j < n; ++j) {
+      double* out = o->history + (size_t)j * hlen;
+      const int sw = reps[j].sweeps;
+      for (int m = 0; m < hlen; ++m) {
+        if (m < sw) out[m] = std::sqrt(std::max(h[(size_t)j * hlen + m], 0.0));
+        else if (m == sw) out[m] = reps[j].rel_res * reps[j].res0;
+        else out[m] = std::nan("");
+      }
+    }
+  }
+  return worst;
 }
 
 
@@ -1575,6 +1605,52 @@ int fnlh_batch_set_loop_cells(fnlh_batch B, int64_t loop_cells) {
   if (!B) return FNLH_E_ARG;
   B->loop_cells = loop_cells > 0 ? loop_cells : 0;
   return FNLH_OK;
+}
+
+int fnlh_batch_autotune(fnlh_batch B, const int32_t* n_sys, const int32_t* const* sys, double* const* const* x,
+                        const double* const* const* bvec, const fnlh_relax_opts* o, int32_t n_cand,
+                        const int64_t* cand, int64_t* pick, double* ms, void* stream) {
+  if (!B) return FNLH_E_ARG;
+  if (!n_sys || !sys || !x || !bvec || !o || n_cand < 1 || n_cand > 64 || !cand) {
+    B->err = "batch autotune: bad arguments";
+    return FNLH_E_ARG;
+  }
+  hipStream_t s = S(stream);
+  const int n = (int)B->inst.size();
+  auto zero_x = [&]() {
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n_sys[i]; ++j)
+        if (x[i] && x[i][j]) launch_fill_zero(x[i][j], (size_t)B->inst[i]->L.N * 12 * sizeof(double), s);
+  };
+  fnlh_ctx c0 = B->inst[0];
+  const int64_t save = B->loop_cells;
+  double best = 1e300;
+  int64_t best_lc = save;
+  for (int k = 0; k < n_cand; ++k) {
+    B->loop_cells = cand[k] > 0 ? cand[k] : 0;
+    float f = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {  // a warm-up (factors, graphs), then one timed solve
+      zero_x();
+      if (hipEventRecord(c0->ev[0], s) != hipSuccess) return hip_fail(c0, hipGetLastError(), "event");
+      const int rc = fnlh_batch_relax(B, n_sys, sys, x, bvec, o, nullptr, stream);
+      if (rc < 0) {
+        B->loop_cells = save;
+        return rc;
+      }
+      if (hipEventRecord(c0->ev[1], s) != hipSuccess || hipEventSynchronize(c0->ev[1]) != hipSuccess)
+        return hip_fail(c0, hipGetLastError(), "event");
+      (void)hipEventElapsedTime(&f, c0->ev[0], c0->ev[1]);
+    }
+    if (ms) ms[k] = f;
+    if (f < best) {
+      best = f;
+      best_lc = B->loop_cells;
+    }
+  }
+  B->loop_cells = best_lc;
+  if (pick) *pick = best_lc;
+  zero_x();
+  return fnlh_batch_relax(B, n_sys, sys, x, bvec, o, nullptr, stream);
 }
 
 int fnlh_batch_relax(fnlh_batch B, const int32_t* n_sys, const int32_t* const* sys, double* const* const* x,
@@ -1832,20 +1908,26 @@ int fnlh_batch_relax(fnlh_batch B, const int32_t* n_sys, const int32_t* const* s
   return worst;
 }
 
-int fnlh_autotune(fnlh_ctx c, int32_t n_sys, int32_t sweeps, fnlh_tune_result* out, void* stream) {
+int fnlh_autotune(fnlh_ctx c, int32_t n_sys, double rtol, int32_t max_sweeps, fnlh_tune_result* out,
+                  void* stream) {
   if (!c) return FNLH_E_ARG;
   if (!c->have_matrix || c->n_sys == 0) return set_err(c, FNLH_E_ORDER, "autotune: matrix and harmonics first");
-  if (n_sys < 1 || n_sys > c->n_sys || n_sys > kMaxBatch || sweeps < 2)
-    return set_err(c, FNLH_E_ARG, "autotune: need 1 <= n_sys <= min(harmonics, 16), sweeps >= 2");
+  if (n_sys < 1 || n_sys > c->n_sys || n_sys > kMaxBatch || max_sweeps < 2 || !(rtol >= 0.0))
+    return set_err(c, FNLH_E_ARG, "autotune: need 1 <= n_sys <= min(harmonics, 16), max_sweeps >= 2, rtol >= 0");
   hipStream_t s = S(stream);
   const size_t vb = (size_t)c->L.N * 12 * sizeof(double);
   DevBuf xb, bb;
+  struct FreeOnExit {
+    DevBuf* a;
+    DevBuf* b;
+    ~FreeOnExit() {
+      dfree(*a);
+      dfree(*b);
+    }
+  } guard{&xb, &bb};
   int rc;
-  if ((rc = dalloc(c, xb, vb * n_sys, "autotune alloc")) || (rc = dalloc(c, bb, vb * n_sys, "autotune alloc"))) {
-    dfree(xb);
-    dfree(bb);
+  if ((rc = dalloc(c, xb, vb * n_sys, "autotune alloc")) || (rc = dalloc(c, bb, vb * n_sys, "autotune alloc")))
     return rc;
-  }
   std::vector<double> ones(c->L.N * 12, 1.0);
   std::vector<double*> xs(n_sys), bs(n_sys);
   std::vector<int32_t> sys(n_sys);
@@ -1853,72 +1935,94 @@ int fnlh_autotune(fnlh_ctx c, int32_t n_sys, int32_t sweeps, fnlh_tune_result* o
     xs[j] = (double*)xb.p + (size_t)j * c->L.N * 12;
     bs[j] = (double*)bb.p + (size_t)j * c->L.N * 12;
     sys[j] = j;
-    (void)hipMemcpyAsync(bs[j], ones.data(), vb, hipMemcpyHostToDevice, s);
+    HIPC(c, hipMemcpyAsync(bs[j], ones.data(), vb, hipMemcpyHostToDevice, s), "autotune rhs");
   }
+  // the objective: wall time of a whole solve (factorisation cached after the warm-up,
+  // graph-replayed sweeps, FP64 outer corrections) to rtol, or of max_sweeps sweeps
   fnlh_relax_opts o;
   std::memset(&o, 0, sizeof(o));
   o.kind = FNLH_DILU;
-  o.max_sweeps = sweeps;
-  o.rtol = 0.0;
-  o.check_every = sweeps;
-  o.inner_sweeps = sweeps;
-  o.inner_rtol = 1e-30;
-  const int save_spw = c->lanes_per_sys, save_lpr = c->lanes_per_row;
-  const bool save_stats = c->stats_on;
-  const int save_period = c->stats_period;
+  o.max_sweeps = max_sweeps;
+  o.rtol = rtol;
+  o.check_every = 16;
+  o.use_graph = 1;
+  if (rtol == 0.0) {
+    o.inner_sweeps = max_sweeps;
+    o.inner_rtol = 1e-30;
+  }
   struct Cand {
-    int lpr, spw;
+    int hybrid, lpr, spw, wg;
   };
-  std::vector<Cand> cands = {{0, 0}};
-  for (int lpr : {1, 2, 4})
-    for (int spw : {1, 2, 4})
-      if (lpr * spw <= 4 * ((n_sys + 3) / 4) * 4 && lpr <= std::max(1, n_sys)) cands.push_back({lpr, spw});
+  const int save_spw = c->lanes_per_sys, save_lpr = c->lanes_per_row, save_wg = c->wave_groups,
+            save_hyb = c->hybrid;
+  const bool save_stats = c->stats_on;
+  c->stats_on = false;
+  std::vector<Cand> cands;
+  std::vector<int> paths = {save_hyb};
+  if (c->L.n_colours >= 3) paths = {1, 0};
+  for (int hy : paths) {
+    cands.push_back({hy, 0, 0, 1});
+    for (int lpr : {1, 2, 4})
+      for (int spw : {1, 2, 4})
+        if (lpr <= std::max(1, n_sys)) cands.push_back({hy, lpr, spw, 1});
+    cands.push_back({hy, 0, 0, 0});  // a 64-row tile per workgroup
+  }
   double best = 1e300, dflt = 0.0;
-  Cand pick{0, 0};
+  int best_sweeps = 0;
+  Cand pick = cands[0];
   int tried = 0;
   for (const Cand& cd : cands) {
+    c->hybrid = cd.hybrid;
     c->lanes_per_sys = cd.spw;
     c->lanes_per_row = cd.lpr;
-    // warm-up (factors, code), then a timed run
-    for (int rep = 0; rep < 2; ++rep) {
-      (void)hipMemsetAsync(xb.p, 0, vb * n_sys, s);
-      fnlh_stats_enable(c, rep == 1 ? 1 : 0);
-      rc = fnlh_relax(c, n_sys, sys.data(), xs.data(), bs.data(), &o, nullptr, stream);
+    c->wave_groups = cd.wg;
+    double ms[2] = {0.0, 0.0};
+    int sweeps = 0;
+    for (int rep = 0; rep < 3 && rc >= 0; ++rep) {  // a warm-up (factors, graphs), then two timed solves
+      launch_fill_zero(xb.p, vb * n_sys, s);
+      HIPC(c, hipEventRecord(c->ev[0], s), "event");
+      std::vector<fnlh_sys_report> reps(n_sys);
+      rc = fnlh_relax(c, n_sys, sys.data(), xs.data(), (const double* const*)bs.data(), &o, reps.data(), stream);
       if (rc < 0) break;
+      HIPC(c, hipEventRecord(c->ev[1], s), "event");
+      HIPC(c, hipEventSynchronize(c->ev[1]), "event sync");
+      float f = 0.f;
+      (void)hipEventElapsedTime(&f, c->ev[0], c->ev[1]);
+      if (rep > 0) ms[rep - 1] = f;
+      sweeps = 0;
+      for (const auto& r : reps) sweeps += r.sweeps;
     }
     if (rc < 0) break;
-    double ms = 0.0;
-    int64_t sweeps_timed = 0;
-    for (int k = 0; k < FNLH_KSTAT_N; ++k) ms += c->st_ms[k];
-    // one update pass (two-colour, hybrid), last-colour forward pass (general) or
-    // Jacobi pass per sweep
-    sweeps_timed = c->st_n[FNLH_KSTAT_SWEEP_UPDATE] + c->st_n[FNLH_KSTAT_FWD_LAST] + c->st_n[FNLH_KSTAT_JACOBI];
-    const double us = sweeps_timed > 0 ? 1e3 * ms / (double)sweeps_timed : 1e300;
+    const double t = std::min(ms[0], ms[1]);
     ++tried;
-    if (cd.lpr == 0 && cd.spw == 0) dflt = us;
-    if (us < best) {
-      best = us;
+    if (tried == 1) dflt = t;
+    if (t < best) {
+      best = t;
       pick = cd;
+      best_sweeps = sweeps;
     }
   }
   c->stats_on = save_stats;
-  c->stats_period = save_period;
-  dfree(xb);
-  dfree(bb);
   if (rc < 0) {
     c->lanes_per_sys = save_spw;
     c->lanes_per_row = save_lpr;
+    c->wave_groups = save_wg;
+    c->hybrid = save_hyb;
     return rc;
   }
+  c->hybrid = pick.hybrid;
   c->lanes_per_sys = pick.spw;
   c->lanes_per_row = pick.lpr;
+  c->wave_groups = pick.wg;
   if (out) {
     out->lanes_per_row = pick.lpr;
     out->sys_per_lane = pick.spw;
-    out->us_per_sweep = best;
-    out->us_per_sweep_default = dflt;
+    out->wave_groups = pick.wg;
+    out->hybrid = pick.hybrid;
+    out->ms_best = best;
+    out->ms_default = dflt;
+    out->sweeps = best_sweeps;
     out->candidates = tried;
-    out->pad_ = 0;
   }
   return FNLH_OK;
 }

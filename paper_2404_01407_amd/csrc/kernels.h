@@ -24,6 +24,12 @@ struct SysState {
   int32_t status;       // FNLH_OK / NOT_CONVERGED / DIVERGED
   int32_t limit;        // max sweeps
   int32_t outer_iters;  // FP64 corrections (reduced precision)
+  // optional residual history, norm^2 of the iterate after m sweeps at hist[m]
+  // (m < hist_len); hist_off: sweeps of the outer solve before this inner one
+  // (default: none, so a state built field by field never carries a stale pointer)
+  double* hist = nullptr;
+  int32_t hist_len = 0;
+  int32_t hist_off = 0;
 };
 
 struct DevPattern {
@@ -198,6 +204,9 @@ void launch_drop_blocks(int storage, const DevPattern& p, int64_t n_slots, const
 // (frozen-turbulence systems)
 void launch_zero_sixth(int64_t rows, double* v, int ns, int vs, hipStream_t s);
 void launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+// attach a residual history of len entries per system slot to the states of sb
+// (hist + vslot * len; null detaches) and record the initial norm^2 at entry 0
+void launch_set_history(const SysBatch& sb, SysState* st, double* hist, int len, hipStream_t s);
 
 // ---- restarted flexible GMRES vector kernels (krylov.hip); vectors [NP][ns][12] FP64
 constexpr int kMdot = 8;          // basis vectors per inner-product launch

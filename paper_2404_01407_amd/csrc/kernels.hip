@@ -297,6 +297,9 @@ __device__ inline void sweep_state(SysState& S, double n2, int mode, double rtol
   }
   S.sweeps += 1;
   if (mode == kReduceSweep) {
+    // the norm is that of the iterate before this sweep, after sweeps - 1 of them (the
+    // first sweep's is the initial norm, recorded at set-up)
+    if (S.hist && S.sweeps >= 2 && S.hist_off + S.sweeps - 1 < S.hist_len) S.hist[S.hist_off + S.sweeps - 1] = n2;
     S.last_n2 = n2;
     if (n2 <= rtol2 * S.norm0sq) {
       S.status = kOK;
@@ -983,6 +986,9 @@ __device__ inline void reduce_one(const double* __restrict__ partial, int64_t n_
     case kReduceInit:
       S.norm0sq = n2;
       S.last_n2 = n2;
+      S.hist = nullptr;
+      S.hist_len = 0;
+      S.hist_off = 0;
       S.sweeps = 0;
       S.pending = 0;
       S.outer_iters = 0;
@@ -1005,6 +1011,7 @@ __device__ inline void reduce_one(const double* __restrict__ partial, int64_t n_
     case kReduceOuter:
       S.last_n2 = n2;
       if (!S.active) break;
+      if (S.hist && S.sweeps < S.hist_len) S.hist[S.sweeps] = n2;  // the FP64 norm after a correction
       if (n2 <= rtol2 * S.norm0sq) {
         S.status = kOK;
         S.active = 0;
@@ -1049,11 +1056,26 @@ __global__ void k_inner_init(SysBatch sb, const SysState* __restrict__ outer, Sy
   I.sweeps = 0;
   I.outer_iters = 0;
   I.status = kNotConverged;
+  I.hist = O.hist;
+  I.hist_len = O.hist_len;
+  I.hist_off = O.sweeps;
   int lim = O.limit - O.sweeps;
   if (lim > max_inner) lim = max_inner;
   I.limit = lim;
   I.active = (O.active && lim > 0 && O.last_n2 > 0.0) ? 1 : 0;
   inner[vs] = I;
+}
+
+__global__ void k_set_history(SysBatch sb, SysState* __restrict__ st, double* __restrict__ hist, int len) {
+  const int k = threadIdx.x;
+  if (k >= sb.n) return;
+  const int vs = sb.vslot[k];
+  SysState S = st[vs];
+  S.hist = hist ? hist + (int64_t)vs * len : nullptr;
+  S.hist_len = hist ? len : 0;
+  S.hist_off = 0;
+  if (S.hist && len > 0) S.hist[0] = S.norm0sq;
+  st[vs] = S;
 }
 
 __global__ void k_outer_update(SysBatch sb, const SysState* __restrict__ inner, SysState* __restrict__ outer) {
@@ -1971,6 +1993,10 @@ void launch_drop_blocks(int storage, const DevPattern& p, int64_t n_slots, const
 void launch_zero_sixth(int64_t rows, double* v, int ns, int vs, hipStream_t s) {
   if (rows <= 0) return;
   hipLaunchKernelGGL(k_zero_sixth, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, rows, ns, vs, v);
+}
+void launch_set_history(const SysBatch& sb, SysState* st, double* hist, int len, hipStream_t s) {
+  if (sb.n <= 0) return;
+  hipLaunchKernelGGL(k_set_history, dim3(1), dim3(64), 0, s, sb, st, hist, len);
 }
 void launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   const size_t n = bytes / 4;

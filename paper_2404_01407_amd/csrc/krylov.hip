@@ -168,6 +168,9 @@ __global__ void k_kstate(SysBatch sb, SysState* __restrict__ st, double n2, int 
   S.status = 1;  // not converged
   S.limit = limit;
   S.outer_iters = 0;
+  S.hist = nullptr;  // preconditioner sweeps keep no residual history
+  S.hist_len = 0;
+  S.hist_off = 0;
   st[sb.vslot[k]] = S;
 }
 

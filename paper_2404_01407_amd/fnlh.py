@@ -47,7 +47,8 @@ class Options(C.Structure):
 class RelaxOpts(C.Structure):
     _fields_ = [("kind", C.c_int32), ("max_sweeps", C.c_int32), ("rtol", C.c_double),
                 ("check_every", C.c_int32), ("inner_sweeps", C.c_int32), ("inner_rtol", C.c_double),
-                ("div_factor", C.c_double), ("use_graph", C.c_int32), ("learn_every", C.c_int32)]
+                ("div_factor", C.c_double), ("use_graph", C.c_int32), ("learn_every", C.c_int32),
+                ("history", C.c_void_p), ("history_len", C.c_int32), ("pad_", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -74,8 +75,9 @@ class GmresReport(C.Structure):
 
 
 class TuneResult(C.Structure):
-    _fields_ = [("lanes_per_row", C.c_int32), ("sys_per_lane", C.c_int32), ("us_per_sweep", C.c_double),
-                ("us_per_sweep_default", C.c_double), ("candidates", C.c_int32), ("pad_", C.c_int32)]
+    _fields_ = [("lanes_per_row", C.c_int32), ("sys_per_lane", C.c_int32), ("wave_groups", C.c_int32),
+                ("hybrid", C.c_int32), ("ms_best", C.c_double), ("ms_default", C.c_double), ("sweeps", C.c_int32),
+                ("candidates", C.c_int32)]
 
 
 class KernelStats(C.Structure):
@@ -115,12 +117,13 @@ def _load():
         "fnlh_version": (C.c_char_p, []),
         "fnlh_stats_enable": (I32, [P, I32]),
         "fnlh_tune": (I32, [P, I32, I32]),
-        "fnlh_autotune": (I32, [P, I32, I32, C.POINTER(TuneResult), V]),
+        "fnlh_autotune": (I32, [P, I32, D, I32, C.POINTER(TuneResult), V]),
         "fnlh_batch_create": (I32, [C.POINTER(P), I32, V]),
         "fnlh_batch_destroy": (I32, [P]),
         "fnlh_batch_relax": (I32, [P, V, V, V, V, C.POINTER(RelaxOpts), V, V]),
         "fnlh_batch_last_error": (C.c_char_p, [P]),
         "fnlh_batch_set_loop_cells": (I32, [P, I64]),
+        "fnlh_batch_autotune": (I32, [P, V, V, V, V, C.POINTER(RelaxOpts), I32, V, C.POINTER(I64), V, V]),
         "fnlh_stats_get": (I32, [P, I32, C.POINTER(KernelStats)]),
         "fnlh_nn_create": (I32, [C.POINTER(P), P, I32]),
         "fnlh_nn_generate": (I32, [P, I32, V, I32, I32, I32, C.c_uint64, V]),
@@ -325,9 +328,12 @@ class Context:
                                               _stream(stream)))
 
     def relax(self, systems, xs, bs, kind="dilu", max_sweeps=500, rtol=1e-8, check_every=8,
-              inner_sweeps=0, inner_rtol=0.0, div_factor=0.0, use_graph=False, learn_every=0, stream=None):
+              inner_sweeps=0, inner_rtol=0.0, div_factor=0.0, use_graph=False, learn_every=0, history=False,
+              stream=None):
         """Solve (K + i omega_s V) x = b for each s in ``systems``; xs (in: x0, out: x) and
-        bs are complex128 CUDA tensors [N, 6].  Returns (status, list of report dicts)."""
+        bs are complex128 CUDA tensors [N, 6].  Returns (status, list of report dicts), or
+        with history=True (status, reports, histories): histories[j][m] the residual norm
+        after m sweeps (entry sweeps: the returned x's)."""
         n = len(systems)
         if len(xs) != n or len(bs) != n:
             raise ValueError(f"{n} systems need {n} x and {n} b vectors")
@@ -336,13 +342,18 @@ class Context:
         sysarr = np.ascontiguousarray(systems, dtype=np.int32)
         xp = (C.c_void_p * n)(*[_ptr(t) for t in xs])
         bp = (C.c_void_p * n)(*[_ptr(t) for t in bs])
+        hist = np.full((n, int(max_sweeps) + 2), np.nan) if history else None
         o = RelaxOpts(KIND[kind], int(max_sweeps), float(rtol), int(check_every), int(inner_sweeps),
-                      float(inner_rtol), float(div_factor), int(bool(use_graph)), int(learn_every))
+                      float(inner_rtol), float(div_factor), int(bool(use_graph)), int(learn_every), _ptr(hist),
+                      0 if hist is None else hist.shape[1], 0)
         rep = (Report * n)()
         rc = LIB.fnlh_relax(self.h, n, _ptr(sysarr), C.cast(xp, C.c_void_p), C.cast(bp, C.c_void_p),
                             C.byref(o), C.cast(rep, C.c_void_p), _stream(stream))
         self._check(rc, allow_positive=True)
-        return rc, [r.as_dict() for r in rep]
+        reps = [r.as_dict() for r in rep]
+        if history:
+            return rc, reps, [h[:r["sweeps"] + 1] for h, r in zip(hist, reps)]
+        return rc, reps
 
     def gmres(self, systems, xs, bs, kind="dilu", restart=20, max_iters=500, rtol=1e-8, inner_sweeps=1,
               use_graph=False, history=False, stream=None):
@@ -446,9 +457,10 @@ class Context:
         if hybrid is not None:
             self._check(LIB.fnlh_tune(self.h, 3, int(hybrid)))
 
-    def autotune(self, n_sys, sweeps=16, cache=None, stream=None):
-        """Pick the sweep-kernel shape by timing (native autotuner).  ``cache``: path of a
-        JSON file keyed by mesh signature, storage, system count and device; a hit
+    def autotune(self, n_sys, rtol=1e-8, max_sweeps=6000, cache=None, stream=None):
+        """Pick the sweep configuration (path, kernel shape, workgroup mapping) by the
+        time of whole solves to rtol (native autotuner).  ``cache``: path of a JSON file
+        keyed by mesh signature, storage, system count, tolerance and device; a hit
         applies the stored choice without timing."""
         import json
         key = None
@@ -456,18 +468,19 @@ class Context:
             import torch
             col, nc = self.ordering()
             dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
-            key = f"{self.n}:{self.E}:{nc}:{int(np.bincount(col).max())}:{self.storage}:{n_sys}:{dev}"
+            key = f"{self.n}:{self.E}:{nc}:{int(np.bincount(col).max())}:{self.storage}:{n_sys}:{rtol}:{dev}"
             try:
                 db = json.load(open(cache))
             except (OSError, ValueError):
                 db = {}
             if key in db:
                 r = db[key]
-                self.tune(r["sys_per_lane"], r["lanes_per_row"])
+                self.tune(r["sys_per_lane"], r["lanes_per_row"], wave_groups=r["wave_groups"], hybrid=r["hybrid"])
                 return dict(r, cached=True)
         res = TuneResult()
-        self._check(LIB.fnlh_autotune(self.h, int(n_sys), int(sweeps), C.byref(res), _stream(stream)))
-        out = {k: getattr(res, k) for k, _ in res._fields_ if k != "pad_"}
+        self._check(LIB.fnlh_autotune(self.h, int(n_sys), float(rtol), int(max_sweeps), C.byref(res),
+                                      _stream(stream)))
+        out = {k: getattr(res, k) for k, _ in res._fields_}
         if cache:
             try:
                 db = json.load(open(cache))
@@ -532,10 +545,8 @@ class Batch:
         if rc < 0:
             raise FnlhError(rc, "batch: set_loop_cells")
 
-    def relax(self, systems, xs, bs, kind="dilu", max_sweeps=500, rtol=1e-8, check_every=8, inner_sweeps=0,
-              inner_rtol=0.0, div_factor=0.0, use_graph=True, learn_every=0, stream=None):
-        """systems[i]: system ids of instance i; xs[i][j], bs[i][j]: complex128 CUDA
-        tensors [N_i, 6].  Returns (status, reports per instance)."""
+    def _args(self, systems, xs, bs, kind, max_sweeps, rtol, check_every, inner_sweeps, inner_rtol, div_factor,
+              use_graph, learn_every):
         n = len(self.contexts)
         nsys = np.array([len(sy) for sy in systems], np.int32)
         keep = []
@@ -556,6 +567,15 @@ class Batch:
             b_ptrs[i] = C.cast(ba, C.c_void_p).value
         o = RelaxOpts(KIND[kind], int(max_sweeps), float(rtol), int(check_every), int(inner_sweeps),
                       float(inner_rtol), float(div_factor), int(bool(use_graph)), int(learn_every))
+        return nsys, sys_ptrs, x_ptrs, b_ptrs, o, keep
+
+    def relax(self, systems, xs, bs, kind="dilu", max_sweeps=500, rtol=1e-8, check_every=8, inner_sweeps=0,
+              inner_rtol=0.0, div_factor=0.0, use_graph=True, learn_every=0, stream=None):
+        """systems[i]: system ids of instance i; xs[i][j], bs[i][j]: complex128 CUDA
+        tensors [N_i, 6].  Returns (status, reports per instance)."""
+        nsys, sys_ptrs, x_ptrs, b_ptrs, o, keep = self._args(systems, xs, bs, kind, max_sweeps, rtol, check_every,
+                                                             inner_sweeps, inner_rtol, div_factor, use_graph,
+                                                             learn_every)
         total = int(nsys.sum())
         rep = (Report * total)()
         rc = LIB.fnlh_batch_relax(self.h, _ptr(nsys), C.cast(sys_ptrs, C.c_void_p), C.cast(x_ptrs, C.c_void_p),
@@ -563,10 +583,28 @@ class Batch:
         if rc < 0:
             raise FnlhError(rc, LIB.fnlh_batch_last_error(self.h).decode())
         out, k = [], 0
-        for i in range(n):
+        for i in range(len(self.contexts)):
             out.append([rep[k + j].as_dict() for j in range(nsys[i])])
             k += nsys[i]
         return rc, out
+
+    def autotune(self, systems, xs, bs, candidates=(0, 40000, 80000, 160000, 1 << 40), kind="dilu",
+                 max_sweeps=5000, rtol=1e-8, check_every=16, use_graph=True, stream=None):
+        """Native batch autotuner over the size threshold of the schedule (see
+        set_loop_cells): times a whole batched solve for each candidate, keeps the
+        fastest; xs are overwritten with the solution of the picked schedule.  Returns
+        (status, pick, {candidate: ms})."""
+        nsys, sys_ptrs, x_ptrs, b_ptrs, o, keep = self._args(systems, xs, bs, kind, max_sweeps, rtol, check_every,
+                                                             0, 0.0, 0.0, use_graph, 0)
+        cand = np.ascontiguousarray(candidates, dtype=np.int64)
+        ms = np.zeros(cand.size)
+        pick = C.c_int64(0)
+        rc = LIB.fnlh_batch_autotune(self.h, _ptr(nsys), C.cast(sys_ptrs, C.c_void_p), C.cast(x_ptrs, C.c_void_p),
+                                     C.cast(b_ptrs, C.c_void_p), C.byref(o), int(cand.size), _ptr(cand),
+                                     C.byref(pick), _ptr(ms), _stream(stream))
+        if rc < 0:
+            raise FnlhError(rc, LIB.fnlh_batch_last_error(self.h).decode())
+        return rc, pick.value, {int(c): float(t) for c, t in zip(cand, ms)}
 
 
 NN_PARAMS = 26624

@@ -149,3 +149,66 @@ def test_batch_loop_cells_schedule(F, loop_cells):
     B.close()
     for (_, _, c, _, _) in insts:
         c.close()
+
+
+@pytest.mark.parametrize("shape", ["hex", "three_row"])
+def test_autotune_picks_a_timed_configuration(F, shape):
+    """fnlh_autotune times whole solves to the tolerance over path (three-row mesh: two
+    colours plus remainder, general), kernel shape and workgroup mapping; the pick is no
+    slower than the default configuration it timed, stays on the context, and the solve
+    with it reaches the same solution (to the tolerance) as the default one."""
+    import torch
+    if shape == "hex":
+        m = synth.passage_block(12, 8, 6, 36, seed=9)
+        om = synth.omegas_single_zone(2, 36)
+    else:
+        m = synth.multi_row(6, 8, 4, n_blades=(36, 60, 48), seed=5)
+        om = synth.omegas_multi_row(2, (36, 60, 48))
+    Q = synth.flow_state(m, 9)
+    bs = [to_dev(synth.rhs(m.n_cells, 20 + s, real=(s == 0))) for s in range(3)]
+    sols = []
+    for tuned in (False, True):
+        c = F.Context(m, storage="f32")
+        c.assemble_jacobian(to_dev(Q))
+        c.set_harmonics(om)
+        if tuned:
+            r = c.autotune(3, rtol=1e-9, max_sweeps=3000)
+            n_paths = 2 if shape == "three_row" else 1
+            assert r["candidates"] == n_paths * 8 and not r["cached"]  # 3 systems: 1-2 lanes per row
+            assert 0 < r["ms_best"] <= r["ms_default"] and r["sweeps"] > 0
+            assert r["hybrid"] in ((0, 1) if shape == "three_row" else (1,))
+        xs = [torch.zeros_like(b) for b in bs]
+        st, rep = c.relax([0, 1, 2], xs, bs, kind="dilu", max_sweeps=3000, rtol=1e-9, use_graph=True)
+        assert st == 0 and all(q["rel_res"] <= 1e-9 for q in rep)
+        sols.append([x.cpu().numpy() for x in xs])
+        c.close()
+    K = assemble.assemble(m, Q)
+    for s in range(3):
+        xd = solve.dense_solve(K, m.volume, m.zone, om[s], bs[s].cpu().numpy())
+        for x in (sols[0][s], sols[1][s]):
+            assert relerr(x, xd) <= 1e-7
+
+
+def test_batch_autotune_picks_a_schedule(F):
+    """fnlh_batch_autotune times the batched solve for each size threshold, keeps the
+    fastest and leaves its solution in x: bitwise the per-instance solves (every schedule
+    gives them)."""
+    import torch
+    insts = _instances(F, "f32", SPECS)
+    B = F.Batch([c for (_, _, c, _, _) in insts])
+    systems = [list(range(len(bs))) for (_, _, _, _, bs) in insts]
+    xs = [[torch.full((m.n_cells, 6), 7.0, dtype=torch.complex128, device="cuda") for _ in bs]
+          for (m, _, _, _, bs) in insts]
+    bd = [[to_dev(b) for b in bs] for (_, _, _, _, bs) in insts]
+    cands = (0, 300, 1 << 40)
+    st, pick, ms = B.autotune(systems, xs, bd, candidates=cands, rtol=1e-9, check_every=8)
+    assert st == 0 and pick in (0, 300, 1 << 40) and all(ms[k] > 0 for k in cands)
+    assert ms[pick] == min(ms.values())
+    for i, (m, Q, c, om, bs) in enumerate(insts):
+        xi = [torch.zeros((m.n_cells, 6), dtype=torch.complex128, device="cuda") for _ in bs]
+        c.relax(systems[i], xi, [to_dev(b) for b in bs], kind="dilu", max_sweeps=5000, rtol=1e-9, check_every=8)
+        for j in range(len(bs)):
+            assert np.array_equal(xs[i][j].cpu().numpy(), xi[j].cpu().numpy()), (i, j)
+    B.close()
+    for (_, _, c, _, _) in insts:
+        c.close()

@@ -547,3 +547,60 @@ def test_hybrid_matches_general_passes(F, storage):
             assert out[2][kind, "conv"][0] == 0
         if storage == "f64":
             assert [r["sweeps"] for r in out[2][kind, "conv"][1]] == [r["sweeps"] for r in out[0][kind, "conv"][1]]
+
+
+@pytest.mark.parametrize("mesh,hybrid", [("hex", 1), ("three_row", 1), ("three_row", 0)])
+def test_residual_history_matches_oracle(F, mesh, hybrid):
+    """fnlh_relax's residual history (FP64 blocks): entry m is ||b - K_s x^m|| after m
+    sweeps as the stop test measured it, entry `sweeps` the returned x's; it equals the
+    oracle's Richardson history sweep for sweep, on the two-colour, the two-colour plus
+    remainder and the general passes."""
+    if mesh == "hex":
+        m, Q, K = case(shape=(9, 6, 5), seed=8)
+        om = synth.omegas_single_zone(2)
+    else:
+        m = synth.multi_row(6, 8, 4, n_blades=(36, 60, 48), seed=5)
+        Q = synth.flow_state(m, 5)
+        K = assemble.assemble(m, Q)
+        om = synth.omegas_multi_row(2, (36, 60, 48))
+    c = _ctx(F, m, Q)
+    c.tune(hybrid=hybrid)
+    c.set_harmonics(om)
+    col, _ = c.ordering()
+    bs = [synth.rhs(m.n_cells, s, real=(s == 0)) for s in range(3)]
+    xs = [to_dev(np.zeros((m.n_cells, 6), complex)) for _ in bs]
+    st, rep, hist = c.relax([0, 1, 2], xs, [to_dev(b) for b in bs], kind="dilu", max_sweeps=3000, rtol=1e-9,
+                            history=True)
+    assert st == 0
+    for s in range(3):
+        n = rep[s]["sweeps"]
+        assert len(hist[s]) == n + 1 and np.all(np.isfinite(hist[s]))
+        _, info = solve.richardson(K, m.volume, m.zone, om[s], bs[s], col, "DILU", rtol=0.0, max_sweeps=n)
+        # relative 1e-9, and near the tolerance the FP64 rounding of the residual itself
+        # (about 1e-17 of the initial norm here) decides: 1e-14 of the initial norm
+        np.testing.assert_allclose(hist[s], info.history, rtol=1e-9, atol=1e-14 * info.history[0])
+        # the stop test: x^(n-1) is the first iterate at the tolerance, x^n is returned
+        assert hist[s][-2] <= 1e-9 * hist[s][0] < hist[s][-3]
+    c.close()
+
+
+def test_residual_history_reduced_precision(F):
+    """FP32 blocks: the history holds the initial FP64 residual, the inner iteration's
+    residuals in between and the FP64 residual after each correction; it falls to the
+    tolerance and ends at the returned x's residual."""
+    m, Q, K = case()
+    om = synth.omegas_single_zone(1)
+    c = _ctx(F, m, Q, storage="f32")
+    c.set_harmonics(om)
+    bs = [synth.rhs(m.n_cells, s, real=(s == 0)) for s in range(2)]
+    xs = [to_dev(np.zeros((m.n_cells, 6), complex)) for _ in bs]
+    st, rep, hist = c.relax([0, 1], xs, [to_dev(b) for b in bs], kind="dilu", max_sweeps=3000, rtol=1e-10,
+                            history=True)
+    assert st == 0
+    for s in range(2):
+        h = hist[s]
+        assert len(h) == rep[s]["sweeps"] + 1 and np.all(np.isfinite(h)) and np.all(h > 0)
+        assert abs(h[0] - np.linalg.norm(bs[s])) <= 1e-12 * h[0]
+        assert abs(h[-1] - rep[s]["rel_res"] * rep[s]["res0"]) <= 1e-12 * h[0]
+        assert h[-1] <= 1e-10 * h[0] and h[len(h) // 2] < 1e-3 * h[0]
+    c.close()

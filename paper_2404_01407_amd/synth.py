@@ -382,9 +382,21 @@ def chain(n: int, seed: int = 3, permute: bool = False) -> Mesh:
     return passage_block(n, 1, 1, 36, seed=seed, jitter=0.0, permute=permute)
 
 
-def _lowmode_field(rng, xi):
-    """Seeded sum of cosines with wave numbers 0..2 in each direction, scaled to [-1, 1]."""
-    f = np.zeros(xi.shape[0])
+def _waves(xi):
+    """e[d][k] = exp(i pi k xi_d) for k = 0, 1, 2 in each direction d."""
+    out = []
+    for d in range(3):
+        e1 = np.exp(1j * np.pi * xi[:, d])
+        out.append([None, e1, e1 * e1])
+    return out
+
+
+def _lowmode_field(rng, e):
+    """Seeded sum of cosines with wave numbers 0..2 in each direction, scaled to [-1, 1]:
+    f = sum over (kx, ky, kz) != 0 of c cos(pi (kx x + ky y + kz z) + ph), evaluated as the
+    real part of sum_kx e^{i pi kx x} sum_ky e^{i pi ky y} sum_kz c e^{i ph} e^{i pi kz z}
+    (e from _waves)."""
+    a = np.zeros((3, 3, 3), np.complex128)
     for kx in range(3):
         for ky in range(3):
             for kz in range(3):
@@ -392,7 +404,16 @@ def _lowmode_field(rng, xi):
                     continue
                 c = rng.normal() / (1.0 + kx + ky + kz)
                 ph = rng.uniform(0, 2 * np.pi)
-                f += c * np.cos(np.pi * (kx * xi[:, 0] + ky * xi[:, 1] + kz * xi[:, 2]) + ph)
+                a[kx, ky, kz] = c * np.exp(1j * ph)
+    n = e[0][1].shape[0]
+    f = np.zeros(n, np.complex128)
+    for kx in range(3):
+        g = np.zeros(n, np.complex128)
+        for ky in range(3):
+            h = a[kx, ky, 0] + a[kx, ky, 1] * e[2][1] + a[kx, ky, 2] * e[2][2]
+            g += h if ky == 0 else e[1][ky] * h
+        f += g if kx == 0 else e[0][kx] * g
+    f = f.real
     m = np.max(np.abs(f))
     return f / m if m > 0 else f
 
@@ -435,7 +456,8 @@ def flow_state(mesh: Mesh, seed: int = 1) -> np.ndarray:
     inv[s2u] = np.arange(mesh.n_cells)
     xi = meta["xi"][inv]
     th = meta["theta"][inv]
-    f = [_lowmode_field(rng, xi) for _ in range(6)]
+    waves = _waves(xi)
+    f = [_lowmode_field(rng, waves) for _ in range(6)]
     rho = 1.0 + 0.05 * f[0]
     mach = 0.45 + 0.15 * f[1]
     a = 1.0 + 0.02 * f[2]

@@ -617,7 +617,7 @@ def run_largest(args):
                     "alg_bytes_per_launch": kd["alg_bytes_per_launch"], "launches": kd["launches"],
                     "all_sweep_kernels_GBs": round(tot_b / (tot_ms * 1e-3) / 1e9, 1) if tot_ms else None,
                     "all_sweep_kernels_frac": round(tot_b / (tot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if tot_ms else None}
-    learned = None
+    learned = ckpt = None
     if not args.no_learned:
         print("[bench] learned: training on held-out-protocol pairs (seeds 10-13)", file=sys.stderr, flush=True)
         ckpt, training = train_heldout(args.storage, [10, 11, 12, 13], args.learn_starts, 8, 4, args.learn_rounds,
@@ -635,6 +635,11 @@ def run_largest(args):
     precision = None
     if not args.no_modes:
         precision = precision_summary(args)
+    batch = None
+    if not args.no_batch:
+        print("[bench] batching: 64 instances", file=sys.stderr, flush=True)
+        batch = batch_measure(args, ckpt=ckpt if learned else None, steps=2, warmup=1,
+                              training=learned["training"] if learned else None)
     cpu = cpu_baseline_from(sample, mesh.n_cells, sweeps, "same 1.92M-cell sector") if sample else None
     out = {
         "metric": METRIC,
@@ -661,6 +666,7 @@ def run_largest(args):
         "memory_bytes_by_systems": {str(k): v for k, v in mem.items()},
         "learned": learned,
         "precision_200k": precision,
+        "batching_8M": batch,
         "ingest_ms": round(ingest_ms, 1),
     }
     print(json.dumps(out), flush=True)
@@ -907,16 +913,21 @@ def run_partition(args):
     print(json.dumps(res), flush=True)
 
 
-def run_batch(args):
+def batch_measure(args, ckpt=None, steps=None, warmup=1, training=None):
     """Batching workload: 64 independent blade-row instances, seeded log-uniform sizes in
     [20k, 300k] cells (~8M total), passage shapes (2n', n', n'), blade counts U{20..80},
     1-8 harmonics each (mean + harmonics, omega_l = l x BPF).  One step = relax every
     system of every instance to 1e-8 (FP32 blocks, FP64 outer residual), x0 = 0.
-    Batched: one launch per colour phase and system-count group over all instances,
-    graph-replayed; baseline: the same solves issued instance by instance."""
+    Batched: one launch per colour phase and system-count group over the instances below
+    the size threshold the batch autotuner picks, graph-replayed; baseline: the same
+    solves issued instance by instance (graph-replayed as well).  The instance contexts
+    are autotuned first (one per system count, whole-solve time).  With ckpt, the learned
+    preconditioner (one trained state loaded into every instance's network) is timed in
+    the batched form too."""
     import numpy as np
     import torch
     from paper_2404_01407_amd import fnlh, synth
+    steps = args.steps if steps is None else steps
     specs = synth.batch_instances(args.instances, args.total_cells, seed=3)
     t0 = time.perf_counter()
     ctxs, systems, bd, xd, cells = [], [], [], [], 0
@@ -940,13 +951,14 @@ def run_batch(args):
         xd.append([torch.zeros_like(b) for b in row])
         cells += m.n_cells
         del m, Q
-        if q % 8 == 7:
+        if q % 16 == 15:
             print(f"[bench] batch setup: {q + 1}/{len(specs)} instances, {cells} cells", file=sys.stderr, flush=True)
     setup_s = time.perf_counter() - t0
     n_sys_total = sum(len(sy) for sy in systems)
     print(f"[bench] batch: {len(ctxs)} instances, {cells} cells, {n_sys_total} systems, setup {setup_s:.1f} s",
           file=sys.stderr, flush=True)
-    # autotune one representative per system count, share the choice
+    # autotune one representative per system count (whole solves to 1e-8), share the choice
+    t0 = time.perf_counter()
     tuned = {}
     for c, sy in zip(ctxs, systems):
         k = len(sy)
@@ -955,15 +967,22 @@ def run_batch(args):
         c.tune(tuned[k]["sys_per_lane"], tuned[k]["lanes_per_row"], wave_groups=tuned[k]["wave_groups"],
                hybrid=tuned[k]["hybrid"])
     B = fnlh.Batch(ctxs)
+    use_graph = not args.no_graph
     if args.batch_loop_cells is not None:
         B.set_loop_cells(args.batch_loop_cells)
+        sched = {"loop_cells": args.batch_loop_cells, "autotuned": False}
+    else:
+        st, pick, ms = B.autotune(systems, xd, bd, rtol=RTOL, check_every=args.check_every, use_graph=use_graph)
+        sched = {"loop_cells": pick, "autotuned": True, "ms_by_loop_cells": {str(k): round(v, 1) for k, v in ms.items()}}
+    tune_s = time.perf_counter() - t0
+    print(f"[bench] batch autotune ({tune_s:.1f} s): contexts {tuned}, schedule {sched}", file=sys.stderr, flush=True)
 
-    def batched():
+    def batched(kind="dilu"):
         for row in xd:
             for x in row:
                 x.zero_()
-        st, reps = B.relax(systems, xd, bd, kind="dilu", max_sweeps=5000, rtol=RTOL, check_every=args.check_every,
-                           use_graph=not args.no_graph)
+        st, reps = B.relax(systems, xd, bd, kind=kind, max_sweeps=5000, rtol=RTOL, check_every=args.check_every,
+                           use_graph=use_graph, learn_every=args.learn_every)
         if st not in CONVERGED:
             raise RuntimeError(f"batched solve status {st}")
         return reps
@@ -974,105 +993,76 @@ def run_batch(args):
             for x in xr:
                 x.zero_()
             st, rep = c.relax(sy, xr, br, kind="dilu", max_sweeps=5000, rtol=RTOL, check_every=args.check_every,
-                              use_graph=False)
+                              use_graph=use_graph)
             if st not in CONVERGED:
                 raise RuntimeError(f"per-instance solve status {st}")
             reps.append(rep)
         return reps
 
-    def timeit(fn, steps, warmup):
-        for _ in range(warmup):
+    def timeit(fn, n, w):
+        for _ in range(w):
             fn()
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for _ in range(steps):
+        for _ in range(n):
             reps = fn()
         torch.cuda.synchronize()
-        return (time.perf_counter() - t) / steps, reps
+        return (time.perf_counter() - t) / n, reps
 
-    print(f"[bench] autotuned: {tuned}", file=sys.stderr, flush=True)
-    tb, reps_b = timeit(batched, args.steps, args.warmup)
+    tb, reps_b = timeit(batched, steps, warmup)
     print(f"[bench] batched: {1e3 * tb:.1f} ms per step", file=sys.stderr, flush=True)
-    tl, reps_l = timeit(loop, max(1, args.steps // 2), 1)
+    tl, reps_l = timeit(loop, max(1, steps // 2), 1)
     print(f"[bench] per-instance loop: {1e3 * tl:.1f} ms per step", file=sys.stderr, flush=True)
     learned = None
-    if not args.no_learned:
-        # one set of weights for every instance (the network is local per edge): trained
-        # on pairs from the plain solver of the largest instance, then batched learned
-        # solves of all instances
-        big = max(range(len(ctxs)), key=lambda i: ctxs[i].n)
+    if ckpt is not None:
         nets = [fnlh.Network(c) for c in ctxs]
         for net in nets:
-            net.set_weights(synth.he_init(0))
-        cb, nb = ctxs[big], nets[big]
-        zero = torch.zeros((cb.n, 6), dtype=torch.complex128, device="cuda")
-        gen = torch.Generator(device="cuda").manual_seed(77)
-        n_pairs = 256
-        nb.reserve_pairs(n_pairs)
-        t0 = time.perf_counter()
-        k = 0
-        while nb.n_pairs() < n_pairs:
-            take = min(len(systems[big]), n_pairs - nb.n_pairs())
-            xs_ = [torch.randn((cb.n, 6), dtype=torch.complex128, device="cuda", generator=gen) for _ in range(take)]
-            cb.relax(list(range(take)), xs_, [zero] * take, kind="dilu", max_sweeps=[4, 8, 16, 32, 64, 128][k % 6],
-                     rtol=0.0, check_every=16, use_graph=True)
-            for j in range(take):
-                r = torch.empty_like(xs_[j])
-                cb.residual(j, xs_[j], zero, r)
-                nb.add_pairs([j], [r], [-xs_[j]])
-            k += 1
-        hist = nb.train(128, batch=8, lr=1e-3, seed=1)
-        w = nb.get_weights()
-        for net in nets:
-            net.set_weights(w)
-        t_train = time.perf_counter() - t0
-
-        def batched_learned():
-            for row in xd:
-                for x in row:
-                    x.zero_()
-            st, reps = B.relax(systems, xd, bd, kind="learned", max_sweeps=5000, rtol=RTOL,
-                               check_every=args.check_every, use_graph=not args.no_graph, learn_every=args.learn_every)
-            if st not in CONVERGED:
-                raise RuntimeError(f"batched learned solve status {st}")
-            return reps
-
-        tln, reps_ln = timeit(batched_learned, max(1, args.steps // 2), 1)
+            net.load(ckpt)
+        tln, reps_ln = timeit(lambda: batched("learned"), max(1, steps // 2), 1)
         print(f"[bench] batched learned: {1e3 * tln:.1f} ms per step", file=sys.stderr, flush=True)
         learned = {"ms": round(1e3 * tln, 3), "vs_batched_plain": round(tb / tln, 3),
                    "sweeps_total": sum(r["sweeps"] for rep in reps_ln for r in rep),
                    "plain_sweeps_total": sum(r["sweeps"] for rep in reps_b for r in rep),
                    "learned_steps": sum(r["learned"] for rep in reps_ln for r in rep),
                    "rejected": sum(r["fallbacks"] for rep in reps_ln for r in rep),
-                   "worst_rel_res": max(r["rel_res"] for rep in reps_ln for r in rep),
-                   "training": {"pairs": n_pairs, "steps": 128, "batch": 8, "generate_and_train_s": round(t_train, 2),
-                                "loss_first": round(float(np.mean(hist[:12])), 4),
-                                "loss_last": round(float(np.mean(hist[-12:])), 4), "on_instance_cells": cb.n}}
+                   "fell_back": sum(r["status"] == 3 for rep in reps_ln for r in rep),
+                   "worst_rel_res": max(r["rel_res"] for rep in reps_ln for r in rep), "training": training}
         for net in nets:
             net.close()
     ncell = [c.n for c in ctxs]
     updates = sum(ncell[i] * r["sweeps"] for i, rep in enumerate(reps_b) for r in rep)
-    worst = max(r["rel_res"] for rep in reps_b for r in rep)
     sweeps = [r["sweeps"] for rep in reps_b for r in rep]
+    out = {"workload": (f"{len(ctxs)} independent blade-row instances, {cells} cells, {n_sys_total} systems "
+                        "(mean + 1-8 harmonics each), DILU to a 1e-8 residual drop, batched + graph-replayed"),
+           "instances": len(ctxs), "cells": cells, "systems": n_sys_total, "storage": args.storage,
+           "time_to_1e-8_ms": round(1e3 * tb, 3), "updates_per_s": round(updates / tb),
+           "per_instance_loop_ms": round(1e3 * tl, 3), "batched_speedup_vs_loop": round(tl / tb, 3),
+           "sweeps_min_max": [min(sweeps), max(sweeps)],
+           "worst_rel_res": max(r["rel_res"] for rep in reps_b for r in rep),
+           "autotune": {"contexts": {str(k): v for k, v in tuned.items()}, "schedule": sched,
+                        "seconds": round(tune_s, 1)},
+           "setup_s": round(setup_s, 1), "learned_batched": learned}
+    B.close()
+    for c in ctxs:
+        c.close()
+    return out
+
+
+def run_batch(args):
+    ckpt = training = None
+    if not args.no_learned:
+        ckpt, training = train_heldout(args.storage, [10, 11, 12, 13], args.learn_starts, 8, 4, args.learn_rounds, 8,
+                                       8, 1e-3)
+    res = batch_measure(args, ckpt=ckpt, training=training, warmup=args.warmup)
     out = {
-        "metric": METRIC, "value": round(updates / tb), "unit": "cell-unknown updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * tb, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 blocks, f32 sweep, f64 outer residual" if args.storage == "f32" else args.storage,
-        "data": "synthetic",
-        "config": {"workload": (f"{len(ctxs)} independent blade-row instances, {cells} cells, {n_sys_total} systems "
-                                "(mean + 1-8 harmonics each), DILU to a 1e-8 residual drop, batched + graph-replayed"),
-                   "instances": len(ctxs), "cells": cells, "systems": n_sys_total, "storage": args.storage,
-                   "loop_cells": 80000 if args.batch_loop_cells is None else args.batch_loop_cells},
-        "time_to_1e-8_ms": round(1e3 * tb, 3),
-        "per_instance_loop_ms": round(1e3 * tl, 3),
-        "batched_speedup_vs_loop": round(tl / tb, 3),
-        "sweeps_min_max": [min(sweeps), max(sweeps)], "worst_rel_res": worst,
-        "autotune": {str(k): v for k, v in tuned.items()}, "setup_s": round(setup_s, 1),
-        "learned_batched": learned,
+        "metric": METRIC, "value": res["updates_per_s"], "unit": "cell-system-sweep updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["time_to_1e-8_ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": _dtype_of(args.storage), "data": "synthetic",
+        "config": {"workload": res["workload"], "instances": res["instances"], "cells": res["cells"],
+                   "systems": res["systems"], "storage": args.storage},
+        "batch": res,
     }
     print(json.dumps(out), flush=True)
-    B.close()
 
 
 def main():
@@ -1114,6 +1104,7 @@ def main():
     ap.add_argument("--batch", type=int, default=8, help="learned workload: pairs per Adam step")
     ap.add_argument("--learn-every", type=int, default=32, help="sweeps between learned corrections")
     ap.add_argument("--no-learned", action="store_true", help="skip the short learned-vs-plain comparison")
+    ap.add_argument("--no-batch", action="store_true", help="largest workload: skip the 64-instance batching field")
     ap.add_argument("--hybrid", type=int, default=1, choices=[0, 1, 2],
                     help="multi-colour orderings: 1 two-colour + remainder passes when the remainder is small "
                          "(default), 0 general passes, 2 always two-colour + remainder")

@@ -26,7 +26,11 @@
  *   FNLH_DILU    (D~ + L) D~^-1 (D~ + U) on a colour ordering (equals block ILU(0) when
  *                the cell graph has no triangles, e.g. every hex mesh),
  *   FNLH_SGS     (D + L) D^-1 (D + U),
- *   FNLH_JACOBI  block diagonal (the paper's explicit, point-by-point inversion).
+ *   FNLH_JACOBI  block diagonal (the paper's explicit, point-by-point inversion),
+ *   FNLH_PILU    ILU(0) inside each partition of fnlh_set_partitions, in the natural
+ *                (cell id) order, the couplings between partitions left out (section
+ *                "Parallel Implementation"; DILU on that order, which is ILU(0) when
+ *                the cell graph has no triangles).
  * The stopping test is the paper's relative 2-norm of B - A x (section "Results",
  * key-parameter table: 1e-2 and 10 iterations there; any rtol / max here).
  *
@@ -90,7 +94,7 @@ enum { FNLH_OUTER_EXACT = 0, FNLH_OUTER_STORED = 1 };
 /* colour ordering: AUTO = two colours when the cell graph is bipartite, else greedy */
 enum { FNLH_ORDER_AUTO = 0, FNLH_ORDER_GREEDY = 1, FNLH_ORDER_BIPARTITE = 2, FNLH_ORDER_USER = 3 };
 /* preconditioner */
-enum { FNLH_DILU = 0, FNLH_SGS = 1, FNLH_JACOBI = 2, FNLH_LEARNED = 3 };
+enum { FNLH_DILU = 0, FNLH_SGS = 1, FNLH_JACOBI = 2, FNLH_LEARNED = 3, FNLH_PILU = 4 };
 /* scheme of the preconditioner matrix (section "Generalized RK Scheme for The Mean Flow") */
 enum { FNLH_IMPLICIT = 0, FNLH_EXPLICIT = 1 };
 
@@ -175,7 +179,7 @@ int fnlh_residual(fnlh_ctx c, int32_t sys, const double* x, const double* b, dou
                   double* norm2, void* stream);
 
 typedef struct {
-  int32_t kind;          /* FNLH_DILU | FNLH_SGS | FNLH_JACOBI | FNLH_LEARNED               */
+  int32_t kind;          /* FNLH_DILU | FNLH_SGS | FNLH_JACOBI | FNLH_LEARNED | FNLH_PILU   */
   int32_t max_sweeps;    /* >= 0: total preconditioned sweeps per system                  */
   double rtol;           /* stop when ||b - K_s x|| <= rtol ||b - K_s x0||                 */
   int32_t check_every;   /* sweeps between host read-backs of the device stop flags (>=1) */
@@ -225,7 +229,15 @@ typedef struct {
  * every sweep; FP32/BF16 blocks: the FP64 residual after each outer correction and, in
  * between, the inner iteration's residual of the stored operator), entry sweeps the
  * returned x's (rel_res times res0), NaN beyond; at most history_len entries.  The
- * batched relax ignores it. */
+ * batched relax ignores it.
+ * FNLH_PILU (section "Parallel Implementation"): each partition of fnlh_set_partitions
+ * is factored and swept on its own by one workgroup, in the natural order of its cells
+ * (level by level), with its y vector in LDS; FNLH_E_ORDER without partitions,
+ * FNLH_E_ARG when the largest partition's y does not fit in a workgroup's LDS (64 KiB:
+ * at most 1365 cells with FP32/BF16 blocks, 682 with FP64).  The first use after new
+ * partitions builds the position layout on the host; the first factorisation after new
+ * blocks copies the in-partition couplings into position order (device memory about
+ * that of the off-diagonal blocks). */
 int fnlh_relax(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x,
                const double* const* b, const fnlh_relax_opts* opts, fnlh_sys_report* rep,
                void* stream);
@@ -331,7 +343,8 @@ enum {
   FNLH_KSTAT_REMAINDER = 6,    /* two colours plus remainder: the passes over the
                                   colours past the second and the correction of the
                                   second colour's rows coupled to them                */
-  FNLH_KSTAT_N = 7
+  FNLH_KSTAT_PILU = 7,         /* partition-local ILU(0) sweep                          */
+  FNLH_KSTAT_N = 8
 };
 /* on >= 1 resets the counters and starts timing the launches of every on-th sweep
  * (1 = every launch; a larger period bounds the event overhead); on = 0 stops.
@@ -403,7 +416,7 @@ int fnlh_autotune(fnlh_ctx c, int32_t n_sys, double rtol, int32_t max_sweeps, fn
  * entries.  Stop when the residual norm (the least-squares one within a cycle, the true
  * one at a restart) is <= rtol ||r0||, after max_iters iterations, or on breakdown. */
 typedef struct {
-  int32_t kind;          /* FNLH_DILU, FNLH_SGS, FNLH_JACOBI or FNLH_LEARNED: M          */
+  int32_t kind;          /* FNLH_DILU, FNLH_SGS, FNLH_JACOBI, FNLH_LEARNED or FNLH_PILU: M */
   int32_t restart;       /* Krylov vectors per cycle, 1..256                               */
   int32_t max_iters;     /* total iterations (preconditioner applications) per system     */
   int32_t inner_sweeps;  /* sweeps per preconditioner application, >= 1                   */

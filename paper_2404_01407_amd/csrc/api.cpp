@@ -135,6 +135,7 @@ int64_t dinv_stride(fnlh_ctx c) { return c->L.n_tiles * dinv_tile_elems(c->stora
 void invalidate_factors(fnlh_ctx c) {
   std::fill(c->slot_sys.begin(), c->slot_sys.end(), -1);
   std::fill(c->slot_kind.begin(), c->slot_kind.end(), -1);
+  c->pl_packed = false;
 }
 
 // outer FP64 operator residual of the systems of sb (x64, b64 -> r, partial)
@@ -142,12 +143,23 @@ void outer_residual(fnlh_ctx c, int ns, const SysBatch& sb, double* r, hipStream
   outer_residual_of(c, ns, sb, (const double*)c->x64.p, (const double*)c->b64.p, r, s);
 }
 
-int factor_batch(fnlh_ctx c, const SysBatch& sb, bool dilu, hipStream_t s) {
+// fkind: 0 DILU on the colour ordering, 1 the shifted diagonal blocks (SGS, Jacobi),
+// 2 partition-local ILU(0) (blocks packed into position order first if stale)
+int factor_batch(fnlh_ctx c, const SysBatch& sb, int fkind, hipStream_t s) {
   DevPattern p = c->pat();
   HIPC(c, hipMemsetAsync(c->d_err.p, 0, sizeof(int), s), "clear error flag");
-  for (int col = 0; col < c->L.n_colours; ++col) {
-    launch_factor(c->storage, dilu, p, c->offd.p, c->diag.p, c->dinv.p, dinv_stride(c), sb, c->L.ctile[col],
-                  c->L.ctile[col + 1] - c->L.ctile[col], c->L.cstart[col], (int*)c->d_err.p, s);
+  if (fkind == 2) {
+    const PiluDev q = c->pilu();
+    if (!c->pl_packed) {
+      launch_pilu_pack(c->storage, q, c->offd.p, c->diag.p, c->pl_coup.p, c->pl_diag.p, s);
+      c->pl_packed = true;
+    }
+    launch_pilu_factor(c->storage, p, q, c->pl_coup.p, c->pl_diag.p, c->dinv.p, dinv_stride(c), sb,
+                       (int*)c->d_err.p, s);
+  } else {
+    for (int col = 0; col < c->L.n_colours; ++col)
+      launch_factor(c->storage, fkind == 0, p, c->offd.p, c->diag.p, c->dinv.p, dinv_stride(c), sb,
+                    c->L.ctile[col], c->L.ctile[col + 1] - c->L.ctile[col], c->L.cstart[col], (int*)c->d_err.p, s);
   }
   int rc = check_launch(c, "factor launch");
   if (rc) return rc;
@@ -159,7 +171,8 @@ int factor_batch(fnlh_ctx c, const SysBatch& sb, bool dilu, hipStream_t s) {
 
 // kPathHybrid: the two-colours-plus-remainder sweep of a colouring whose first two
 // colours hold almost every row (see one_sweep)
-enum Path { kPathRB, kPathGeneral, kPathJacobi, kPathHybrid };
+// kPathPilu: the partition-local ILU(0) sweep (one launch per sweep)
+enum Path { kPathRB, kPathGeneral, kPathJacobi, kPathHybrid, kPathPilu };
 
 // The passes of the hybrid sweep's remainder, for their byte model.
 enum RemPass { kRemNorm = 1, kRemFwd = 2, kRemBwd = 3, kRemCorrect = 4 };
@@ -290,6 +303,13 @@ double alg_bytes(fnlh_ctx c, int kind, int col, int na, int mode = 0) {
       shared = L.c_deg_upper[col] * blk + L.c_deg[col] * 4;
       per = nrows(col) * (4 * 12 * sv + dv) + L.c_nbr_upper[col] * 12 * sv;
       break;
+    case FNLH_KSTAT_PILU: {  // in-partition couplings, diagonal blocks and tables; per
+                             // system b read, x read and written, the factor
+      const PiluLayout& Q = c->pl;
+      shared = (double)Q.n_coup * (blk + 12) + (double)L.N * (blk + 4);
+      per = (double)L.N * (3 * 12 * sv + dv);
+      break;
+    }
     case FNLH_KSTAT_JACOBI: {
       double deg = 0;
       for (int cc = 0; cc < L.n_colours; ++cc) deg += L.c_deg[cc];
@@ -398,6 +418,14 @@ void one_sweep(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, const SysBatc
     launch_rb_pass(cfg, false, p, c->offd.p, c->diag.p, c->dinv.p, ds, x, b, ns, sb, st, part, L.ctile[0],
                    L.ctile[1] - L.ctile[0], s, &fr);
     T.end();
+  } else if (path == kPathPilu) {
+    const PiluDev q = c->pilu();
+    double* pp = (double*)c->pl_partial.p;
+    T.begin(FNLH_KSTAT_PILU, 0, k);
+    launch_pilu_sweep(cfg.storage, p, q, c->pl_coup.p, c->pl_diag.p, c->dinv.p, ds, x, b, ns, sb, st, pp,
+                      c->pl_lds_max, s);
+    T.end();
+    launch_reduce(sb, pp, q.pt, 0, q.pt, kPartialSlots, st, kReduceSweep, rtol, divf, 0, s);
   } else if (path == kPathGeneral) {
     const int m = L.n_colours;
     for (int col = 0; col < m; ++col) {
@@ -639,6 +667,52 @@ int ensure_dominance(fnlh_ctx c, hipStream_t s) {
   return FNLH_OK;
 }
 
+// The partition-local ILU(0) tables for the current partitions (built on first use),
+// its packed-block buffers, and norm partials for n systems.
+int ensure_pilu(fnlh_ctx c, int n, hipStream_t s) {
+  if (c->part_host.empty())
+    return set_err(c, FNLH_E_ORDER, "partition-local ILU: no partitions (fnlh_set_partitions first)");
+  int rc;
+  if (!c->pl_built) {
+    std::string e;
+    if ((rc = build_pilu(c->L, c->part_host, c->pl, e))) return set_err(c, rc, e);
+    const PiluLayout& Q = c->pl;
+    if (Q.n_groups > c->L.n_tiles) return set_err(c, FNLH_E_ARG, "partition-local ILU: factor slots too small");
+    const size_t slot_bytes = (size_t)c->slot_elems_storage() * c->block_bytes();
+    if ((rc = dupload(c, c->pl_part_ptr, Q.part_ptr, "partition tables")) ||
+        (rc = dupload(c, c->pl_part_lev, Q.part_lev, "partition tables")) ||
+        (rc = dupload(c, c->pl_lev_ptr, Q.lev_ptr, "partition tables")) ||
+        (rc = dupload(c, c->pl_pos_row, Q.pos_row, "partition tables")) ||
+        (rc = dupload(c, c->pl_gwidth, Q.g_width, "partition tables")) ||
+        (rc = dupload(c, c->pl_gslot0, Q.g_slot0, "partition tables")))
+      return rc;
+    if (Q.n_slots > 0 && ((rc = dupload(c, c->pl_epos, Q.e_pos, "partition tables")) ||
+                          (rc = dupload(c, c->pl_esrc, Q.e_src, "partition tables")) ||
+                          (rc = dupload(c, c->pl_erev, Q.e_rev, "partition tables")) ||
+                          (rc = dalloc(c, c->pl_coup, (size_t)Q.n_slots * slot_bytes, "alloc packed blocks"))))
+      return rc;
+    if ((rc = dalloc(c, c->pl_diag, (size_t)Q.n_groups * slot_bytes, "alloc packed blocks"))) return rc;
+    dfree(c->pl_partial);
+    c->pl_cap = 0;
+    c->pl_built = true;
+    c->pl_packed = false;
+    c->buf_gen++;  // captured sweeps hold the tables' addresses
+  }
+  if (pilu_systems_per_group(c->storage, 1, c->pl.max_rows, c->pl_lds_max) < 1)
+    return set_err(c, FNLH_E_ARG,
+                   "partition-local ILU: the largest partition has " + std::to_string(c->pl.max_rows) +
+                       " cells; at most " + std::to_string(c->pl_lds_max / pilu_lds_row_bytes(c->storage)) +
+                       " fit in a workgroup's LDS");
+  if (n > c->pl_cap) {
+    const size_t bytes = (size_t)n * c->pilu().pt * kPartialSlots * sizeof(double);
+    if ((rc = dalloc(c, c->pl_partial, bytes, "alloc partition partials"))) return rc;
+    HIPC(c, hipMemsetAsync(c->pl_partial.p, 0, bytes, s), "zero partition partials");  // entries past n_parts
+    c->pl_cap = n;
+    c->buf_gen++;
+  }
+  return FNLH_OK;
+}
+
 // ---------------------------------------------------------------- relax phases
 struct RelaxPlan {
   Path path = kPathRB;
@@ -660,7 +734,8 @@ int relax_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, c
     if (sys[j] < 0 || sys[j] >= c->n_sys) return set_err(c, FNLH_E_ARG, "relax: system out of range");
     if (!x[j] || !b[j]) return set_err(c, FNLH_E_ARG, "relax: null vector");
   }
-  if (o->kind != FNLH_DILU && o->kind != FNLH_SGS && o->kind != FNLH_JACOBI && o->kind != FNLH_LEARNED)
+  if (o->kind != FNLH_DILU && o->kind != FNLH_SGS && o->kind != FNLH_JACOBI && o->kind != FNLH_LEARNED &&
+      o->kind != FNLH_PILU)
     return set_err(c, FNLH_E_ARG, "relax: unsupported preconditioner kind");
   if (o->learn_every < 0) return set_err(c, FNLH_E_ARG, "relax: learn_every >= 0");
   if (o->max_sweeps < 0 || !(o->rtol >= 0.0)) return set_err(c, FNLH_E_ARG, "relax: need max_sweeps >= 0, rtol >= 0");
@@ -678,6 +753,7 @@ int relax_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, c
   int rc;
   if ((rc = ensure_vectors(c, n))) return rc;
   if (P.learned && (rc = nn_relax_begin(c, n, s))) return rc;
+  if (o->kind == FNLH_PILU && (rc = ensure_pilu(c, n, s))) return rc;
   const int want_slots = c->factor_slots_opt > 0 ? c->factor_slots_opt : std::min<int>(c->n_sys, 64);
   if ((rc = ensure_slots(c, want_slots))) return rc;
   if ((rc = ensure_dominance(c, s))) return rc;
@@ -687,6 +763,7 @@ int relax_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, c
     launch_to_internal(p, (const int32_t*)c->iperm.p, b[j], (double*)c->b64.p, 12, n, j, s);
   }
   P.path = o->kind == FNLH_JACOBI ? kPathJacobi
+           : o->kind == FNLH_PILU ? kPathPilu
                                   : (c->L.n_colours == 2 ? kPathRB : (hybrid_ok(c) ? kPathHybrid : kPathGeneral));
   // frozen-turbulence systems run on the stored-factor kernels (the two-colour pass solves
   // the first colour's full 6x6 diagonal block in place); their sixth unknown starts at 0
@@ -697,7 +774,7 @@ int relax_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, c
       launch_zero_sixth(c->L.NP, (double*)c->x64.p, n, j, s);
     }
   if (frozen && (P.path == kPathRB || P.path == kPathHybrid)) P.path = kPathGeneral;
-  P.fkind = (o->kind == FNLH_DILU || o->kind == FNLH_LEARNED) ? 0 : 1;
+  P.fkind = (o->kind == FNLH_DILU || o->kind == FNLH_LEARNED) ? 0 : o->kind == FNLH_PILU ? 2 : 1;
   P.cfg.storage = c->storage;
   P.cfg.spw = c->lanes_per_sys;
   P.cfg.lanes_per_row = c->lanes_per_row;
@@ -739,7 +816,7 @@ int relax_factor(fnlh_ctx c, SysBatch& sb, int fkind, hipStream_t s) {
     c->slot_sys[need.dslot[k]] = -1;
     c->slot_kind[need.dslot[k]] = -1;
   }
-  int rc = factor_batch(c, need, fkind == 0, s);
+  int rc = factor_batch(c, need, fkind, s);
   if (rc) return rc;
   for (int k = 0; k < need.n; ++k) {
     c->slot_sys[need.dslot[k]] = need.orow[k];
@@ -1086,7 +1163,9 @@ int fnlh_destroy(fnlh_ctx c) {
                     &c->bface_area, &c->offd, &c->diag, &c->offd64, &c->diag64, &c->state, &c->bstate,
                     &c->d_omega, &c->dinv, &c->x64, &c->b64, &c->r64, &c->y, &c->rhs32, &c->d32, &c->partial,
                     &c->st, &c->st_outer, &c->d_err, &c->ent_phase, &c->phase_cs, &c->sys_frozen, &c->ent_drop,
-                    &c->hyb_tiles};
+                    &c->hyb_tiles, &c->pl_part_ptr, &c->pl_part_lev, &c->pl_lev_ptr, &c->pl_pos_row,
+                    &c->pl_gwidth, &c->pl_gslot0, &c->pl_epos, &c->pl_esrc, &c->pl_erev, &c->pl_coup, &c->pl_diag,
+                    &c->pl_partial};
   for (DevBuf* b : bufs) dfree(*b);
   if (c->h_st) (void)hipHostFree(c->h_st);
   if (c->h_err) (void)hipHostFree(c->h_err);
@@ -1288,6 +1367,8 @@ int fnlh_set_partitions(fnlh_ctx c, const int32_t* part, void* stream) {
     return rc;
   }
   c->part_host = ph;
+  c->pl_built = false;  // the partition-local ILU tables follow the partitions
+  c->pl_packed = false;
   c->buf_gen++;  // captured sweeps hold the flag table's address
   if (c->have_matrix) {
     if (had) {
@@ -1369,8 +1450,8 @@ namespace fnlh {
 int precond_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, const double* const* b, int kind,
                     int inner, bool use_graph, hipStream_t s, PrecondPlan& out) {
   if (!c) return FNLH_E_ARG;
-  if (kind != FNLH_DILU && kind != FNLH_SGS && kind != FNLH_JACOBI && kind != FNLH_LEARNED)
-    return set_err(c, FNLH_E_ARG, "preconditioner kind must be DILU, SGS, JACOBI or LEARNED");
+  if (kind != FNLH_DILU && kind != FNLH_SGS && kind != FNLH_JACOBI && kind != FNLH_LEARNED && kind != FNLH_PILU)
+    return set_err(c, FNLH_E_ARG, "preconditioner kind must be DILU, SGS, JACOBI, LEARNED or PILU");
   if (inner < 1) return set_err(c, FNLH_E_ARG, "inner sweeps >= 1");
   fnlh_relax_opts o{};
   o.kind = kind;
@@ -2088,9 +2169,13 @@ int fnlh_memory(fnlh_ctx c, size_t* matrix_bytes, size_t* factor_bytes, size_t* 
   if (!c) return FNLH_E_ARG;
   const DevBuf* mat[] = {&c->ent_phase, &c->ent_drop, &c->tile_nrows, &c->tile_width, &c->tile_slot0, &c->ent_nbr, &c->ent_edge, &c->ent_rev,
                          &c->vol, &c->zone, &c->iperm, &c->perm, &c->edge_ent, &c->bf_ptr, &c->bf_idx, &c->area,
-                         &c->bface_area, &c->offd, &c->diag, &c->offd64, &c->diag64, &c->state, &c->bstate};
+                         &c->bface_area, &c->offd, &c->diag, &c->offd64, &c->diag64, &c->state, &c->bstate,
+                         &c->hyb_tiles, &c->pl_part_ptr, &c->pl_part_lev, &c->pl_lev_ptr, &c->pl_pos_row,
+                         &c->pl_gwidth, &c->pl_gslot0, &c->pl_epos, &c->pl_esrc, &c->pl_erev, &c->pl_coup,
+                         &c->pl_diag};
   const DevBuf* vec[] = {&c->x64, &c->b64,     &c->r64,     &c->y,  &c->rhs32,   &c->d32,
-                         &c->partial, &c->st, &c->st_outer, &c->d_omega, &c->phase_cs, &c->sys_frozen};
+                         &c->partial, &c->st, &c->st_outer, &c->d_omega, &c->phase_cs, &c->sys_frozen,
+                         &c->pl_partial};
   size_t m = 0, v = 0;
   for (auto* b : mat) m += b->bytes;
   for (auto* b : vec) v += b->bytes;

@@ -62,6 +62,15 @@ struct fnlh_ctx_s {
   // the partition of each user cell behind it
   DevBuf ent_drop;
   std::vector<int32_t> part_host;
+  // partition-local natural-order ILU(0) (FNLH_PILU): the position layout of the
+  // partitions above, its device tables, the blocks packed in position order (stale
+  // after new blocks), norm partials for pl_cap systems, and the LDS a workgroup may use
+  fnlh::PiluLayout pl;
+  bool pl_built = false, pl_packed = false;
+  int pl_cap = 0;
+  int pl_lds_max = 65536;
+  DevBuf pl_part_ptr, pl_part_lev, pl_lev_ptr, pl_pos_row, pl_gwidth, pl_gslot0, pl_epos, pl_esrc, pl_erev, pl_coup,
+      pl_diag, pl_partial;
   // factors
   int n_slots = 0;
   DevBuf dinv;
@@ -113,6 +122,24 @@ struct fnlh_ctx_s {
     p.phase_cs = (const double*)phase_cs.p;
     p.sys_frozen = (const uint8_t*)sys_frozen.p;
     return p;
+  }
+  fnlh::PiluDev pilu() const {
+    fnlh::PiluDev q;
+    q.part_ptr = (const int32_t*)pl_part_ptr.p;
+    q.part_lev = (const int32_t*)pl_part_lev.p;
+    q.lev_ptr = (const int32_t*)pl_lev_ptr.p;
+    q.pos_row = (const int32_t*)pl_pos_row.p;
+    q.g_width = (const int32_t*)pl_gwidth.p;
+    q.g_slot0 = (const int64_t*)pl_gslot0.p;
+    q.e_pos = (const int32_t*)pl_epos.p;
+    q.e_src = (const int32_t*)pl_esrc.p;
+    q.e_rev = (const int32_t*)pl_erev.p;
+    q.n_parts = pl.n_parts;
+    q.n_groups = pl.n_groups;
+    q.n_slots = pl.n_slots;
+    q.pt = (pl.n_parts + fnlh::kPartialSlots - 1) / fnlh::kPartialSlots;
+    q.max_rows = pl.max_rows;
+    return q;
   }
   DevFlow flow() const {
     DevFlow f;

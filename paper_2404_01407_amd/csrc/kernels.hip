@@ -1317,6 +1317,288 @@ __global__ void __launch_bounds__(64) k_factor(DevPattern p, const TB* __restric
   store_dinv<TD>(dbase + tile * DinvTile<TD>::N, lane, mr, mi);
 }
 
+// ================================================================ partition-local ILU(0)
+// Section "Parallel Implementation": every partition runs ILU(0) on its own block of the
+// LHS, the couplings to other partitions left out.  Inside a partition the order is the
+// natural one (cell ids), processed level by level (cells of one level are never
+// coupled): one workgroup per (partition, systems), the partition's y vector in LDS.
+// Blocks are read from packed copies in position order (PiluLayout), so the lanes of a
+// wave, which take consecutive positions of one level, load coalesced 16-byte vectors.
+
+// packed couplings and diagonal blocks: one thread per (entry or position, 16-byte chunk)
+template <typename TB>
+__global__ void k_pilu_pack(PiluDev q, const TB* __restrict__ offd, const TB* __restrict__ diag, TB* __restrict__ coup,
+                            TB* __restrict__ pdiag) {
+  constexpr int NV = Fmt<TB>::NV;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n_ent = q.n_slots * kLanes, n_pos = q.n_groups * kLanes;
+  const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+  if (t < n_ent * NV) {
+    const int64_t e = t / NV;
+    const int v = (int)(t % NV);
+    const int32_t src = q.e_src[e];
+    const uint4 val =
+        src < 0 ? zero : reinterpret_cast<const uint4*>(offd)[((int64_t)(src >> 6) * NV + v) * kLanes + (src & 63)];
+    reinterpret_cast<uint4*>(coup)[((e >> 6) * NV + v) * kLanes + (e & 63)] = val;
+  } else if (t < (n_ent + n_pos) * NV) {
+    const int64_t k = t - n_ent * NV;
+    const int64_t pos = k / NV;
+    const int v = (int)(k % NV);
+    const int32_t row = q.pos_row[pos];
+    const uint4 val =
+        row < 0 ? zero : reinterpret_cast<const uint4*>(diag)[((int64_t)(row >> 6) * NV + v) * kLanes + (row & 63)];
+    reinterpret_cast<uint4*>(pdiag)[((pos >> 6) * NV + v) * kLanes + (pos & 63)] = val;
+  }
+}
+
+// Dt_i = K_ii + i w_i I - sum_{j lower, same partition} K_ij Dt_j^-1 K_ji, level by level
+// (one wave per (partition, system)); the inverses go to the factor slot in position
+// order (tile g = position / 64).  The inverses of lower levels are read back from global
+// memory after the workgroup barrier that ends their level: the wave wrote them itself.
+template <typename TB, typename TD>
+__global__ void __launch_bounds__(64) k_pilu_factor(DevPattern p, PiluDev q, const TB* __restrict__ coup,
+                                                    const TB* __restrict__ pdiag, TD* dinv, int64_t dstride,
+                                                    SysBatch sb, int* __restrict__ err) {
+  const int64_t part = blockIdx.x;
+  const int k = blockIdx.y;
+  const int lane = threadIdx.x;
+  TD* dbase = dinv + (int64_t)sb.dslot[k] * dstride;
+  const bool frz = p.sys_frozen && p.sys_frozen[sb.orow[k]];
+  const int l0 = q.part_lev[part], l1 = q.part_lev[part + 1];
+  for (int l = l0; l < l1; ++l) {
+    const int a = q.lev_ptr[l], e = q.lev_ptr[l + 1];
+    for (int qq = a + lane; qq < e; qq += kLanes) {
+      const int64_t g = qq >> 6;
+      const int ln = qq & 63;
+      const int64_t row = q.pos_row[qq];
+      double mr[36], mi[36];
+      const TB* ds = pdiag + g * slot_elems<TB>();
+#pragma unroll
+      for (int c = 0; c < 36; ++c) {
+        mr[c] = load_entry_f64<TB>(ds, c, ln);
+        mi[c] = 0.0;
+      }
+      const double wv = shift_w(p, sb.orow[k], row);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) mi[7 * c] += wv;
+      const int wd = q.g_width[g];
+      const int64_t s0 = q.g_slot0[g];
+      for (int kk = 0; kk < wd; ++kk) {
+        const int64_t fe = (s0 + kk) * kLanes + ln;
+        const int nb = q.e_pos[fe];
+        if (nb < 0 || nb > qq) break;  // lower neighbours come first
+        const TB* ks = coup + (s0 + kk) * slot_elems<TB>();
+        double kij[36];
+#pragma unroll
+        for (int c = 0; c < 36; ++c) kij[c] = load_entry_f64<TB>(ks, c, ln);
+        const int32_t rv = q.e_rev[fe];
+        const TB* rs = coup + (int64_t)(rv >> 6) * slot_elems<TB>();
+        const int rl = rv & 63;
+        const TD* dn = dbase + (int64_t)(nb >> 6) * DinvTile<TD>::N;
+        const int nl = nb & 63;
+        for (int c = 0; c < 6; ++c) {
+          double kc[6];
+#pragma unroll
+          for (int q2 = 0; q2 < 6; ++q2) kc[q2] = load_entry_f64<TB>(rs, 6 * q2 + c, rl);
+          double tr[6], ti[6];
+#pragma unroll
+          for (int r = 0; r < 6; ++r) {
+            double sr = 0.0, si = 0.0;
+#pragma unroll
+            for (int q2 = 0; q2 < 6; ++q2) {
+              double dr, di;
+              load_dinv_entry<TD>(dn, nl, 6 * r + q2, dr, di);
+              sr += dr * kc[q2];
+              si += di * kc[q2];
+            }
+            tr[r] = sr;
+            ti[r] = si;
+          }
+#pragma unroll
+          for (int r = 0; r < 6; ++r) {
+            double sr = 0.0, si = 0.0;
+#pragma unroll
+            for (int q2 = 0; q2 < 6; ++q2) {
+              sr += kij[6 * r + q2] * tr[q2];
+              si += kij[6 * r + q2] * ti[q2];
+            }
+            mr[6 * r + c] -= sr;
+            mi[6 * r + c] -= si;
+          }
+        }
+      }
+      if (frz) {  // the inverse of the leading 5x5 block, sixth row and column zero
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          mr[30 + c] = mi[30 + c] = 0.0;
+          mr[6 * c + 5] = mi[6 * c + 5] = 0.0;
+        }
+        mr[35] = 1.0;
+      }
+      bool ok = true;
+      cinv6(mr, mi, ok);
+      if (frz) mr[35] = 0.0;
+      if (!ok) atomicOr(err, 1);
+      store_dinv<TD>(dbase + g * DinvTile<TD>::N, ln, mr, mi);
+    }
+    __syncthreads();
+  }
+}
+
+// One preconditioned Richardson sweep of each partition for P systems (one wave):
+//   forward, levels ascending:   r_i = b_i - (K_ii + i w) x_i - sum_j K_ij x_j   (||r||^2)
+//                                y_i = Dt_i^-1 (r_i - sum_{j lower} K_ij y_j)
+//   backward, levels descending: z_i = y_i - Dt_i^-1 sum_{j upper} K_ij z_j
+//   x_i += z_i.
+// y (then z) of the partition's rows lives in LDS, [row in partition][P][12]; x and b
+// are the interleaved vectors [NP][ns][12].
+template <typename TB, int P>
+__global__ void __launch_bounds__(64) k_pilu_sweep(DevPattern p, PiluDev q, const TB* __restrict__ coup,
+                                                   const TB* __restrict__ pdiag,
+                                                   const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
+                                                   typename TV_of<TB>::T* __restrict__ x,
+                                                   const typename TV_of<TB>::T* __restrict__ b, int ns, SysBatch sb,
+                                                   const SysState* __restrict__ st, double* __restrict__ partial) {
+  using A = typename TV_of<TB>::T;
+  using TD = typename DF_of<TB>::T;
+  extern __shared__ uint4 pilu_lds[];
+  A* ys = reinterpret_cast<A*>(pilu_lds);
+  const int64_t part = blockIdx.x;
+  const int lane = threadIdx.x;
+  WaveSys<P> W;
+  if (!wave_systems<P>(sb, st, (int)blockIdx.y, true, W)) return;
+  const int q0 = q.part_ptr[part], q1 = q.part_ptr[part + 1];
+  const int l0 = q.part_lev[part], l1 = q.part_lev[part + 1];
+  double n2[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) n2[j] = 0.0;
+  for (int l = l0; l < l1; ++l) {
+    const int a = q.lev_ptr[l], e = q.lev_ptr[l + 1];
+    for (int qq = a + lane; qq < e; qq += kLanes) {
+      const int64_t g = qq >> 6;
+      const int ln = qq & 63;
+      const int64_t row = q.pos_row[qq];
+      const int64_t rb = row * ns * 12;
+      A r[P][12], t[P][12];
+      {
+        A d[36];
+        load_block(pdiag + g * slot_elems<TB>(), ln, d);
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+#pragma unroll
+          for (int i = 0; i < 12; ++i) r[j][i] = t[j][i] = 0;
+          if (!W.run[j]) continue;
+          A xi[12];
+          load_vec(b + rb + W.vs[j] * 12, r[j]);
+          load_vec(x + rb + W.vs[j] * 12, xi);
+          sub_diag_shift(r[j], d, (A)shift_w(p, W.orow[j], row), xi);
+        }
+      }
+      const int wd = q.g_width[g];
+      const int64_t s0 = q.g_slot0[g];
+      for (int kk = 0; kk < wd; ++kk) {
+        const int64_t fe = (s0 + kk) * kLanes + ln;
+        const int nb = q.e_pos[fe];
+        if (nb < 0) break;
+        A kb[36];
+        load_block(coup + (s0 + kk) * slot_elems<TB>(), ln, kb);
+        const int64_t nbo = (int64_t)q.pos_row[nb] * ns * 12;
+        const int32_t src = q.e_src[fe];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          if (!W.run[j]) continue;
+          A v[12];
+          load_vec(x + nbo + W.vs[j] * 12, v);
+          if (p.ent_phase) apply_phase(p, src, W.orow[j], v);
+          sub_kx(r[j], kb, v);
+          if (nb < qq) {
+            load_vec(ys + ((int64_t)(nb - q0) * P + j) * 12, v);
+            if (p.ent_phase) apply_phase(p, src, W.orow[j], v);
+            sub_kx(t[j], kb, v);
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        if (!W.run[j]) continue;
+        mask_frozen(p, W.orow[j], r[j]);
+        n2[j] += norm2_12(r[j]);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) t[j][i] += r[j][i];
+        A yi[12];
+        apply_dinv(dinv + (int64_t)W.ds[j] * dstride + g * DinvTile<TD>::N, ln, t[j], yi);
+        store_vec(ys + ((int64_t)(qq - q0) * P + j) * 12, yi);
+      }
+    }
+    __syncthreads();
+  }
+  // the top level has no upper neighbours: z = y there
+  for (int l = l1 - 2; l >= l0; --l) {
+    const int a = q.lev_ptr[l], e = q.lev_ptr[l + 1];
+    for (int qq = a + lane; qq < e; qq += kLanes) {
+      const int64_t g = qq >> 6;
+      const int ln = qq & 63;
+      const int wd = q.g_width[g];
+      const int64_t s0 = q.g_slot0[g];
+      A u[P][12];
+#pragma unroll
+      for (int j = 0; j < P; ++j)
+#pragma unroll
+        for (int i = 0; i < 12; ++i) u[j][i] = 0;
+      bool any = false;
+      for (int kk = 0; kk < wd; ++kk) {
+        const int64_t fe = (s0 + kk) * kLanes + ln;
+        const int nb = q.e_pos[fe];
+        if (nb < 0) break;
+        if (nb < qq) continue;
+        any = true;
+        A kb[36];
+        load_block(coup + (s0 + kk) * slot_elems<TB>(), ln, kb);
+        const int32_t src = q.e_src[fe];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          if (!W.run[j]) continue;
+          A v[12];
+          load_vec(ys + ((int64_t)(nb - q0) * P + j) * 12, v);
+          if (p.ent_phase) apply_phase(p, src, W.orow[j], v);
+          sub_kx(u[j], kb, v);
+        }
+      }
+      if (!any) continue;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        if (!W.run[j]) continue;
+        A d[12], yi[12];
+        apply_dinv(dinv + (int64_t)W.ds[j] * dstride + g * DinvTile<TD>::N, ln, u[j], d);
+        A* yp = ys + ((int64_t)(qq - q0) * P + j) * 12;
+        load_vec(yp, yi);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) yi[i] += d[i];
+        store_vec(yp, yi);
+      }
+    }
+    __syncthreads();
+  }
+  for (int qq = q0 + lane; qq < q1; qq += kLanes) {
+    const int64_t rb = (int64_t)q.pos_row[qq] * ns * 12;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      if (!W.run[j]) continue;
+      A xi[12], zi[12];
+      load_vec(x + rb + W.vs[j] * 12, xi);
+      load_vec(ys + ((int64_t)(qq - q0) * P + j) * 12, zi);
+#pragma unroll
+      for (int i = 0; i < 12; ++i) xi[i] += zi[i];
+      store_vec(x + rb + W.vs[j] * 12, xi);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const double s = wave_sum(n2[j]);
+    if (lane == 0 && W.run[j]) partial[(int64_t)W.vs[j] * q.pt * kPartialSlots + part] = s;
+  }
+}
+
 // ================================================================ FP64 residuals
 // One wave per (tile, system), FP64 vectors in the interleaved layout.
 template <typename TB>
@@ -2002,6 +2284,48 @@ void launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   const size_t n = bytes / 4;
   if (n == 0) return;
   hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (uint32_t*)p, n);
+}
+
+void launch_pilu_pack(int storage, const PiluDev& q, const void* offd, const void* diag, void* coup, void* pdiag,
+                      hipStream_t s) {
+  FNLH_DISPATCH_STORE(storage, {
+    const int64_t n = (q.n_slots + q.n_groups) * kLanes * Fmt<TB>::NV;
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_pilu_pack<TB>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, q, (const TB*)offd,
+                       (const TB*)diag, (TB*)coup, (TB*)pdiag);
+  });
+}
+void launch_pilu_factor(int storage, const DevPattern& p, const PiluDev& q, const void* coup, const void* pdiag,
+                        void* dinv, int64_t dinv_stride, const SysBatch& sb, int* err, hipStream_t s) {
+  if (q.n_parts <= 0 || sb.n <= 0) return;
+  dim3 grid((unsigned)q.n_parts, (unsigned)sb.n);
+  FNLH_DISPATCH_STORE(storage, {
+    using TD = typename DF_of<TB>::T;
+    hipLaunchKernelGGL((k_pilu_factor<TB, TD>), grid, dim3(64), 0, s, p, q, (const TB*)coup, (const TB*)pdiag,
+                       (TD*)dinv, dinv_stride, sb, err);
+  });
+}
+int pilu_lds_row_bytes(int storage) { return 12 * (storage == kF64 ? 8 : 4); }
+int pilu_systems_per_group(int storage, int nb, int max_rows, int lds_max) {
+  int P = nb < 4 ? nb : 4;
+  while (P > 0 && (int64_t)max_rows * P * pilu_lds_row_bytes(storage) > lds_max) --P;
+  return P;
+}
+void launch_pilu_sweep(int storage, const DevPattern& p, const PiluDev& q, const void* coup, const void* pdiag,
+                       const void* dinv, int64_t dinv_stride, void* x, const void* b, int ns, const SysBatch& sb,
+                       const SysState* st, double* partial, int lds_max, hipStream_t s) {
+  if (q.n_parts <= 0 || sb.n <= 0) return;
+  const int P = pilu_systems_per_group(storage, sb.n, q.max_rows, lds_max);
+  if (P <= 0) return;  // the caller checks that a partition fits
+  dim3 grid((unsigned)q.n_parts, (unsigned)((sb.n + P - 1) / P));
+  const unsigned lds = (unsigned)q.max_rows * P * pilu_lds_row_bytes(storage);
+  FNLH_DISPATCH_STORE(storage, {
+    using A = typename Fmt<TB>::A;
+    FNLH_DISPATCH_P(P, {
+      hipLaunchKernelGGL((k_pilu_sweep<TB, PP>), grid, dim3(64), lds, s, p, q, (const TB*)coup, (const TB*)pdiag,
+                         (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, st, partial);
+    });
+  });
 }
 
 }  // namespace fnlh

@@ -415,4 +415,123 @@ int build_layout(const fnlh_mesh& m, const fnlh_options& o, Layout& L, std::stri
   return FNLH_OK;
 }
 
+int build_pilu(const Layout& L, const std::vector<int32_t>& part, PiluLayout& P, std::string& err) {
+  const int64_t N = L.N;
+  if ((int64_t)part.size() != N) {
+    err = "partition-local ILU: one partition label per cell needed";
+    return FNLH_E_ARG;
+  }
+  if (L.n_slots * kTile >= (int64_t)INT32_MAX) {
+    err = "partition-local ILU: mesh too large for 32-bit entry indices";
+    return FNLH_E_ARG;
+  }
+  P = PiluLayout();
+  // in-partition neighbours of user cell u, as (neighbour id, flat SELL entry)
+  auto each_coupling = [&](int64_t u, auto&& f) {
+    const int64_t row = L.perm[u];
+    const int64_t t = row / kTile;
+    const int lane = (int)(row % kTile);
+    for (int q = 0; q < L.tile_width[t]; ++q) {
+      const int64_t fe = (L.tile_slot0[t] + q) * kTile + lane;
+      if (L.ent_edge[fe] == 0) continue;
+      const int32_t v = L.iperm[L.ent_nbr[fe]];
+      if (part[v] == part[u]) f(v, fe);
+    }
+  };
+  // partitions by ascending label
+  std::vector<int32_t> labels(part.begin(), part.end());
+  std::sort(labels.begin(), labels.end());
+  labels.erase(std::unique(labels.begin(), labels.end()), labels.end());
+  P.n_parts = (int64_t)labels.size();
+  std::vector<int32_t> pidx(N);
+  std::vector<int64_t> psize(P.n_parts, 0);
+  for (int64_t u = 0; u < N; ++u) {
+    pidx[u] = (int32_t)(std::lower_bound(labels.begin(), labels.end(), part[u]) - labels.begin());
+    psize[pidx[u]]++;
+  }
+  // levels, visiting cells by ascending id (the natural order inside every partition)
+  std::vector<int32_t> level(N, 0);
+  for (int64_t u = 0; u < N; ++u) {
+    int32_t lv = 0;
+    each_coupling(u, [&](int32_t v, int64_t) {
+      if (v < u) lv = std::max(lv, level[v] + 1);
+    });
+    level[u] = lv;
+  }
+  // positions: partition, then (level, id)
+  std::vector<int32_t> cells(N);
+  std::iota(cells.begin(), cells.end(), 0);
+  std::stable_sort(cells.begin(), cells.end(), [&](int32_t a, int32_t b) {
+    if (pidx[a] != pidx[b]) return pidx[a] < pidx[b];
+    return level[a] < level[b];
+  });
+  std::vector<int32_t> pos_of(N);
+  for (int64_t q = 0; q < N; ++q) pos_of[cells[q]] = (int32_t)q;
+  P.part_ptr.assign(P.n_parts + 1, 0);
+  for (int64_t k = 0; k < P.n_parts; ++k) {
+    P.part_ptr[k + 1] = P.part_ptr[k] + (int32_t)psize[k];
+    P.max_rows = std::max<int32_t>(P.max_rows, (int32_t)psize[k]);
+  }
+  P.part_lev.assign(P.n_parts + 1, 0);
+  P.lev_ptr.assign(1, 0);
+  for (int64_t k = 0; k < P.n_parts; ++k) {
+    const int32_t a = P.part_ptr[k], b = P.part_ptr[k + 1];
+    for (int32_t q = a; q < b; ++q)
+      if (q + 1 == b || level[cells[q + 1]] != level[cells[q]]) P.lev_ptr.push_back(q + 1);
+    P.part_lev[k + 1] = (int32_t)P.lev_ptr.size() - 1;
+    P.max_levels = std::max(P.max_levels, P.part_lev[k + 1] - P.part_lev[k]);
+  }
+  // packed couplings per group of 64 positions, lower neighbours first
+  P.n_groups = (N + kTile - 1) / kTile;
+  P.pos_row.assign(P.n_groups * kTile, -1);
+  for (int64_t q = 0; q < N; ++q) P.pos_row[q] = L.perm[cells[q]];
+  std::vector<std::vector<std::pair<int32_t, int64_t>>> nb(kTile);
+  P.g_width.assign(P.n_groups, 0);
+  P.g_slot0.assign(P.n_groups, 0);
+  int64_t slot = 0;
+  for (int64_t g = 0; g < P.n_groups; ++g) {
+    int32_t w = 0;
+    for (int lane = 0; lane < kTile; ++lane) {
+      const int64_t q = g * kTile + lane;
+      int32_t d = 0;
+      if (q < N) each_coupling(cells[q], [&](int32_t, int64_t) { ++d; });
+      w = std::max(w, d);
+    }
+    P.g_width[g] = w;
+    P.g_slot0[g] = slot;
+    slot += w;
+  }
+  P.n_slots = slot;
+  P.e_pos.assign(P.n_slots * kTile, -1);
+  P.e_src.assign(P.n_slots * kTile, -1);
+  P.e_rev.assign(P.n_slots * kTile, -1);
+  std::vector<int32_t> packed_of(L.n_slots * kTile, -1);
+  for (int64_t g = 0; g < P.n_groups; ++g) {
+    for (int lane = 0; lane < kTile; ++lane) {
+      const int64_t q = g * kTile + lane;
+      if (q >= N) continue;
+      std::vector<std::pair<int32_t, int64_t>>& list = nb[lane];
+      list.clear();
+      each_coupling(cells[q], [&](int32_t v, int64_t fe) { list.emplace_back(pos_of[v], fe); });
+      std::sort(list.begin(), list.end());
+      for (size_t k = 0; k < list.size(); ++k) {
+        const int64_t pe = (P.g_slot0[g] + (int64_t)k) * kTile + lane;
+        P.e_pos[pe] = list[k].first;
+        P.e_src[pe] = (int32_t)list[k].second;
+        packed_of[list[k].second] = (int32_t)pe;
+      }
+      P.n_coup += (int64_t)list.size();
+    }
+  }
+  for (int64_t pe = 0; pe < P.n_slots * kTile; ++pe) {
+    if (P.e_src[pe] < 0) continue;
+    P.e_rev[pe] = packed_of[L.ent_rev[P.e_src[pe]]];
+    if (P.e_rev[pe] < 0) {
+      err = "partition-local ILU: coupling without its transpose";
+      return FNLH_E_MESH;
+    }
+  }
+  return FNLH_OK;
+}
+
 }  // namespace fnlh

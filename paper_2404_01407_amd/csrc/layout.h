@@ -55,4 +55,31 @@ struct Layout {
 // Validate and build.  Returns FNLH_OK or a negative code with a message in err.
 int build_layout(const fnlh_mesh& m, const fnlh_options& o, Layout& L, std::string& err);
 
+// Partition-local ILU(0) in the natural order (section "Parallel Implementation": each
+// partition factors and solves its own block of the LHS, the couplings to other
+// partitions ignored).  Inside a partition the order is the user cell numbering; a
+// cell's level is one more than the highest level among its in-partition neighbours of
+// lower number (0 if none), so the cells of one level are never coupled and can be
+// processed together.  Positions number the cells partition by partition (partitions
+// by ascending label), inside a partition by (level, cell id); the in-partition
+// couplings of a position are packed in SELL-64 form over groups of 64 consecutive
+// positions, lower neighbours first.
+struct PiluLayout {
+  int64_t n_parts = 0, n_groups = 0, n_slots = 0;
+  int32_t max_rows = 0, max_levels = 0;
+  int64_t n_coup = 0;                // in-partition couplings (directed)
+  std::vector<int32_t> part_ptr;     // [n_parts+1] position range of each partition
+  std::vector<int32_t> part_lev;     // [n_parts+1] level range of each partition (into lev_ptr)
+  std::vector<int32_t> lev_ptr;      // [levels+1] position range of each level
+  std::vector<int32_t> pos_row;      // [n_groups*64] internal row of each position, -1 past N
+  std::vector<int32_t> g_width;      // [n_groups] couplings of the group's widest position
+  std::vector<int64_t> g_slot0;      // [n_groups] first packed slot
+  std::vector<int32_t> e_pos;        // [n_slots*64] neighbour position, -1 padding
+  std::vector<int32_t> e_src;        // [n_slots*64] the coupling's flat entry in the SELL layout
+  std::vector<int32_t> e_rev;        // [n_slots*64] packed entry of the transposed coupling
+};
+
+// part: [N] partition label of each user cell.
+int build_pilu(const Layout& L, const std::vector<int32_t>& part, PiluLayout& P, std::string& err);
+
 }  // namespace fnlh

@@ -21,7 +21,7 @@ E_ARG, E_MESH, E_SINGULAR, E_OOM, E_HIP, E_ORDER = -1, -2, -3, -4, -5, -6
 STORAGE = {"f64": 0, "f32": 1, "bf16": 2}
 OUTER = {"exact": 0, "stored": 1}
 ORDERING = {"auto": 0, "greedy": 1, "bipartite": 2, "user": 3}
-KIND = {"dilu": 0, "sgs": 1, "jacobi": 2, "learned": 3}
+KIND = {"dilu": 0, "sgs": 1, "jacobi": 2, "learned": 3, "pilu": 4}
 SCHEME = {"implicit": 0, "explicit": 1}
 
 
@@ -84,7 +84,8 @@ class KernelStats(C.Structure):
     _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("alg_bytes", C.c_double)]
 
 
-KSTAT = {"sweep_update": 0, "sweep_set": 1, "fwd": 2, "bwd": 3, "jacobi": 4, "fwd_last": 5, "remainder": 6}
+KSTAT = {"sweep_update": 0, "sweep_set": 1, "fwd": 2, "bwd": 3, "jacobi": 4, "fwd_last": 5, "remainder": 6,
+         "pilu": 7}
 
 
 def _load():

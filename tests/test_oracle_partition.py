@@ -3,7 +3,11 @@ one with every block between two partitions struck out and nothing else changed;
 partition leaves K unchanged; one cell per partition leaves the block diagonal, which
 the Richardson iteration solves exactly in one sweep; the solve splits into independent
 per-partition solves; and the RK iteration converges more slowly as the partitions
-shrink (the paper's degradation rule, in kind).  Also the bisection partition generator."""
+shrink (the paper's degradation rule, in kind).  Also the bisection partition generator.
+Partition-local ILU(0) in the natural order, as the oracle of the GPU's "pilu" kind
+(DILU with every cell its own class, in id order, on the dropped matrix): on a hex mesh
+(no triangles in the cell graph) it is the textbook block ILU(0) in id order, and its
+preconditioner splits into each partition's own ILU(0) of its own block of K."""
 import numpy as np
 import pytest
 
@@ -100,3 +104,47 @@ def test_rk_converges_slower_with_smaller_partitions(small):
         x_star = solve.dense_solve(J, m.volume, m.zone, om, fh)      # the same fixed point whatever the split
         assert np.linalg.norm(Qh - x_star) <= 1e-4 * np.linalg.norm(x_star), (size, n, hist[-1] / hist[0])
     assert steps[0] < steps[1] < steps[2] < steps[3], steps
+
+
+def _sub_matrix(K, cells):
+    """The partition's own block of K as a BlockMatrix on its cells (renumbered 0..)."""
+    loc = -np.ones(K.n, np.int64)
+    loc[cells] = np.arange(cells.size)
+    keep = np.nonzero((loc[K.rows] >= 0) & (loc[K.cols] >= 0))[0]
+    return assemble.BlockMatrix(cells.size, K.diag[cells].copy(), loc[K.rows[keep]], loc[K.cols[keep]],
+                                K.offd[keep].copy())
+
+
+def test_natural_dilu_is_textbook_ilu0_per_partition(small):
+    m, Q, K, col = small
+    part = synth.rcb_partition(m, 24)
+    Kd = solve.partition_dropped(K, part)
+    om = np.array([18.0])
+    r = _b(m.n_cells, 5)
+    natural = np.arange(m.n_cells)
+    f_dilu = solve.factor(Kd, m.volume, m.zone, om, natural, "DILU")
+    z = solve.precondition(Kd, f_dilu, r)
+    # the textbook IKJ ILU(0) in id order (one colour class: the order is the ids')
+    f_ilu = solve.factor(Kd, m.volume, m.zone, om, np.zeros(m.n_cells, np.int64), "ILU0")
+    z_ilu = solve.precondition(Kd, f_ilu, r)
+    np.testing.assert_allclose(z, z_ilu, rtol=0, atol=1e-12 * np.abs(z).max())
+    # each partition alone: its block of the undropped K, its own ILU(0) in id order
+    for p in np.unique(part):
+        cells = np.nonzero(part == p)[0]                               # ascending: id order kept
+        Kp = _sub_matrix(K, cells)
+        fp = solve.factor(Kp, m.volume[cells], m.zone[cells], om, np.zeros(cells.size, np.int64), "ILU0")
+        zp = solve.precondition(Kp, fp, r[cells])
+        np.testing.assert_allclose(z[cells], zp, rtol=0, atol=1e-12 * np.abs(zp).max())
+
+
+def test_natural_order_differs_from_the_colouring(small):
+    """The natural order is a different preconditioner from the colour ordering's (a
+    mistake that handed the colouring to the natural-order kind would show here)."""
+    m, Q, K, col = small
+    part = synth.rcb_partition(m, 40)
+    Kd = solve.partition_dropped(K, part)
+    om = np.array([18.0])
+    r = _b(m.n_cells, 6)
+    zn = solve.precondition(Kd, solve.factor(Kd, m.volume, m.zone, om, np.arange(m.n_cells), "DILU"), r)
+    zc = solve.precondition(Kd, solve.factor(Kd, m.volume, m.zone, om, col, "DILU"), r)
+    assert np.linalg.norm(zn - zc) > 1e-3 * np.linalg.norm(zc)

@@ -233,8 +233,9 @@ typedef struct {
  * FNLH_PILU (section "Parallel Implementation"): each partition of fnlh_set_partitions
  * is factored and swept on its own by one workgroup, in the natural order of its cells
  * (level by level), with its y vector in LDS; FNLH_E_ORDER without partitions,
- * FNLH_E_ARG when the largest partition's y does not fit in a workgroup's LDS (64 KiB:
- * at most 1365 cells with FP32/BF16 blocks, 682 with FP64).  The first use after new
+ * FNLH_E_ARG when the largest partition's y does not fit in a workgroup's LDS (the
+ * device's limit less 1 KiB, 159 KiB on MI355X: at most 3392 cells with FP32/BF16
+ * blocks, 1696 with FP64).  The first use after new
  * partitions builds the position layout on the host; the first factorisation after new
  * blocks copies the in-partition couplings into position order (device memory about
  * that of the off-diagonal blocks). */
@@ -370,8 +371,24 @@ int fnlh_stats_get(fnlh_ctx c, int32_t which, fnlh_kernel_stats* out);
  *                           hybrid passes for any colouring of three or more colours.
  *                           The same preconditioner either way (equal iterates up to
  *                           rounding).
+ *   FNLH_TUNE_PILU_UNIT     FNLH_PILU: cells per work unit, the consecutive partitions
+ *                           (by label) that one workgroup sweeps together, their levels
+ *                           merged (a larger partition is a unit of its own); 0 =
+ *                           automatic (N / 2048, between 64 and 1024).  More cells per
+ *                           unit fill the wave's lanes on small partitions, fewer give
+ *                           more workgroups.  Bitwise the same results.
+ *   FNLH_TUNE_PILU_THREADS  FNLH_PILU: lanes of a sweep workgroup, four per row of a
+ *                           level: 64, 128 or 256 (0 = automatic, after the units'
+ *                           average level width).  Bitwise the same results.
  */
-enum { FNLH_TUNE_SYS_PER_LANE = 0, FNLH_TUNE_LANES_PER_ROW = 1, FNLH_TUNE_WAVE_GROUPS = 2, FNLH_TUNE_HYBRID = 3 };
+enum {
+  FNLH_TUNE_SYS_PER_LANE = 0,
+  FNLH_TUNE_LANES_PER_ROW = 1,
+  FNLH_TUNE_WAVE_GROUPS = 2,
+  FNLH_TUNE_HYBRID = 3,
+  FNLH_TUNE_PILU_UNIT = 4,
+  FNLH_TUNE_PILU_THREADS = 5
+};
 int fnlh_tune(fnlh_ctx c, int32_t param, int32_t value);
 
 /* Autotuner: picks the sweep configuration by the time of whole solves.  For every

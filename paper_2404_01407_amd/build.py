@@ -48,7 +48,8 @@ def build(verbose: bool = True) -> str:
         if rc != 0:
             raise RuntimeError(f"hipcc failed on {os.path.basename(f)}:\n" + err)
     tmp = LIB + ".tmp"
-    link = [hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
+    # -z defs: a symbol left undefined fails the link here, not the first load on a GPU
+    link = [hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", "-Wl,-z,defs", *objs, "-o", tmp]
     if verbose:
         print(" ".join(link), flush=True)
     rc, err = _run(link)

@@ -674,19 +674,32 @@ int ensure_pilu(fnlh_ctx c, int n, hipStream_t s) {
     return set_err(c, FNLH_E_ORDER, "partition-local ILU: no partitions (fnlh_set_partitions first)");
   int rc;
   if (!c->pl_built) {
+    // the largest LDS a workgroup's y vector may take: the device's less a reserve for the
+    // sweep's static LDS, once the sweep kernels allow it
+    int dev_lds = 0;
+    constexpr int kStaticReserve = 1024;
+    if (hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->dev) == hipSuccess &&
+        dev_lds - kStaticReserve > c->pl_lds_max && pilu_allow_lds(c->storage, dev_lds - kStaticReserve))
+      c->pl_lds_max = dev_lds - kStaticReserve;
+    (void)hipGetLastError();
+    const int64_t N = c->L.N;
+    const int32_t fit = c->pl_lds_max / pilu_lds_row_bytes(c->storage);
+    int32_t unit = c->pl_unit_rows > 0 ? c->pl_unit_rows : (int32_t)std::min<int64_t>(1024, std::max<int64_t>(64, N / 2048));
+    unit = std::min(unit, fit);
     std::string e;
-    if ((rc = build_pilu(c->L, c->part_host, c->pl, e))) return set_err(c, rc, e);
+    if ((rc = build_pilu(c->L, c->part_host, unit, c->pl, e))) return set_err(c, rc, e);
     const PiluLayout& Q = c->pl;
     if (Q.n_groups > c->L.n_tiles) return set_err(c, FNLH_E_ARG, "partition-local ILU: factor slots too small");
     const size_t slot_bytes = (size_t)c->slot_elems_storage() * c->block_bytes();
-    if ((rc = dupload(c, c->pl_part_ptr, Q.part_ptr, "partition tables")) ||
-        (rc = dupload(c, c->pl_part_lev, Q.part_lev, "partition tables")) ||
+    if ((rc = dupload(c, c->pl_unit_ptr, Q.unit_ptr, "partition tables")) ||
+        (rc = dupload(c, c->pl_unit_lev, Q.unit_lev, "partition tables")) ||
         (rc = dupload(c, c->pl_lev_ptr, Q.lev_ptr, "partition tables")) ||
         (rc = dupload(c, c->pl_pos_row, Q.pos_row, "partition tables")) ||
         (rc = dupload(c, c->pl_gwidth, Q.g_width, "partition tables")) ||
         (rc = dupload(c, c->pl_gslot0, Q.g_slot0, "partition tables")))
       return rc;
     if (Q.n_slots > 0 && ((rc = dupload(c, c->pl_epos, Q.e_pos, "partition tables")) ||
+                          (rc = dupload(c, c->pl_erow, Q.e_row, "partition tables")) ||
                           (rc = dupload(c, c->pl_esrc, Q.e_src, "partition tables")) ||
                           (rc = dupload(c, c->pl_erev, Q.e_rev, "partition tables")) ||
                           (rc = dalloc(c, c->pl_coup, (size_t)Q.n_slots * slot_bytes, "alloc packed blocks"))))
@@ -700,13 +713,13 @@ int ensure_pilu(fnlh_ctx c, int n, hipStream_t s) {
   }
   if (pilu_systems_per_group(c->storage, 1, c->pl.max_rows, c->pl_lds_max) < 1)
     return set_err(c, FNLH_E_ARG,
-                   "partition-local ILU: the largest partition has " + std::to_string(c->pl.max_rows) +
+                   "partition-local ILU: the largest partition has " + std::to_string(c->pl.max_part) +
                        " cells; at most " + std::to_string(c->pl_lds_max / pilu_lds_row_bytes(c->storage)) +
                        " fit in a workgroup's LDS");
   if (n > c->pl_cap) {
     const size_t bytes = (size_t)n * c->pilu().pt * kPartialSlots * sizeof(double);
     if ((rc = dalloc(c, c->pl_partial, bytes, "alloc partition partials"))) return rc;
-    HIPC(c, hipMemsetAsync(c->pl_partial.p, 0, bytes, s), "zero partition partials");  // entries past n_parts
+    HIPC(c, hipMemsetAsync(c->pl_partial.p, 0, bytes, s), "zero partition partials");  // entries past n_units
     c->pl_cap = n;
     c->buf_gen++;
   }
@@ -1163,9 +1176,9 @@ int fnlh_destroy(fnlh_ctx c) {
                     &c->bface_area, &c->offd, &c->diag, &c->offd64, &c->diag64, &c->state, &c->bstate,
                     &c->d_omega, &c->dinv, &c->x64, &c->b64, &c->r64, &c->y, &c->rhs32, &c->d32, &c->partial,
                     &c->st, &c->st_outer, &c->d_err, &c->ent_phase, &c->phase_cs, &c->sys_frozen, &c->ent_drop,
-                    &c->hyb_tiles, &c->pl_part_ptr, &c->pl_part_lev, &c->pl_lev_ptr, &c->pl_pos_row,
-                    &c->pl_gwidth, &c->pl_gslot0, &c->pl_epos, &c->pl_esrc, &c->pl_erev, &c->pl_coup, &c->pl_diag,
-                    &c->pl_partial};
+                    &c->hyb_tiles, &c->pl_unit_ptr, &c->pl_unit_lev, &c->pl_lev_ptr, &c->pl_pos_row,
+                    &c->pl_gwidth, &c->pl_gslot0, &c->pl_epos, &c->pl_erow, &c->pl_esrc, &c->pl_erev, &c->pl_coup,
+                    &c->pl_diag, &c->pl_partial};
   for (DevBuf* b : bufs) dfree(*b);
   if (c->h_st) (void)hipHostFree(c->h_st);
   if (c->h_err) (void)hipHostFree(c->h_err);
@@ -2132,6 +2145,22 @@ int fnlh_tune(fnlh_ctx c, int32_t param, int32_t value) {
     c->hybrid = value;
     return FNLH_OK;
   }
+  if (param == FNLH_TUNE_PILU_THREADS) {
+    if (value != 0 && value != 64 && value != 128 && value != 256)
+      return set_err(c, FNLH_E_ARG, "tune: sweep workgroup size must be 0, 64, 128 or 256");
+    if (value != c->pl_threads) c->buf_gen++;  // captured sweeps hold the launch shape
+    c->pl_threads = value;
+    return FNLH_OK;
+  }
+  if (param == FNLH_TUNE_PILU_UNIT) {
+    if (value < 0) return set_err(c, FNLH_E_ARG, "tune: cells per work unit must be >= 0");
+    if (value != c->pl_unit_rows) {
+      c->pl_unit_rows = value;
+      c->pl_built = false;  // new units: new tables (the factors follow the positions)
+      invalidate_factors(c);
+    }
+    return FNLH_OK;
+  }
   return set_err(c, FNLH_E_ARG, "tune: unknown parameter");
 }
 
@@ -2170,9 +2199,9 @@ int fnlh_memory(fnlh_ctx c, size_t* matrix_bytes, size_t* factor_bytes, size_t* 
   const DevBuf* mat[] = {&c->ent_phase, &c->ent_drop, &c->tile_nrows, &c->tile_width, &c->tile_slot0, &c->ent_nbr, &c->ent_edge, &c->ent_rev,
                          &c->vol, &c->zone, &c->iperm, &c->perm, &c->edge_ent, &c->bf_ptr, &c->bf_idx, &c->area,
                          &c->bface_area, &c->offd, &c->diag, &c->offd64, &c->diag64, &c->state, &c->bstate,
-                         &c->hyb_tiles, &c->pl_part_ptr, &c->pl_part_lev, &c->pl_lev_ptr, &c->pl_pos_row,
-                         &c->pl_gwidth, &c->pl_gslot0, &c->pl_epos, &c->pl_esrc, &c->pl_erev, &c->pl_coup,
-                         &c->pl_diag};
+                         &c->hyb_tiles, &c->pl_unit_ptr, &c->pl_unit_lev, &c->pl_lev_ptr, &c->pl_pos_row,
+                         &c->pl_gwidth, &c->pl_gslot0, &c->pl_epos, &c->pl_erow, &c->pl_esrc, &c->pl_erev,
+                         &c->pl_coup, &c->pl_diag};
   const DevBuf* vec[] = {&c->x64, &c->b64,     &c->r64,     &c->y,  &c->rhs32,   &c->d32,
                          &c->partial, &c->st, &c->st_outer, &c->d_omega, &c->phase_cs, &c->sys_frozen,
                          &c->pl_partial};

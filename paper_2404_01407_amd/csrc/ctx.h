@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -68,9 +69,11 @@ struct fnlh_ctx_s {
   fnlh::PiluLayout pl;
   bool pl_built = false, pl_packed = false;
   int pl_cap = 0;
-  int pl_lds_max = 65536;
-  DevBuf pl_part_ptr, pl_part_lev, pl_lev_ptr, pl_pos_row, pl_gwidth, pl_gslot0, pl_epos, pl_esrc, pl_erev, pl_coup,
-      pl_diag, pl_partial;
+  int pl_lds_max = 65536 - 1024;  // dynamic LDS of a sweep workgroup; raised to the device's at first use
+  int pl_unit_rows = 0;     // cells per work unit (0: automatic)
+  int pl_threads = 0;       // sweep workgroup size (0: automatic)
+  DevBuf pl_unit_ptr, pl_unit_lev, pl_lev_ptr, pl_pos_row, pl_gwidth, pl_gslot0, pl_epos, pl_erow, pl_esrc, pl_erev,
+      pl_coup, pl_diag, pl_partial;
   // factors
   int n_slots = 0;
   DevBuf dinv;
@@ -125,20 +128,24 @@ struct fnlh_ctx_s {
   }
   fnlh::PiluDev pilu() const {
     fnlh::PiluDev q;
-    q.part_ptr = (const int32_t*)pl_part_ptr.p;
-    q.part_lev = (const int32_t*)pl_part_lev.p;
+    q.unit_ptr = (const int32_t*)pl_unit_ptr.p;
+    q.unit_lev = (const int32_t*)pl_unit_lev.p;
     q.lev_ptr = (const int32_t*)pl_lev_ptr.p;
     q.pos_row = (const int32_t*)pl_pos_row.p;
     q.g_width = (const int32_t*)pl_gwidth.p;
     q.g_slot0 = (const int64_t*)pl_gslot0.p;
     q.e_pos = (const int32_t*)pl_epos.p;
+    q.e_row = (const int32_t*)pl_erow.p;
     q.e_src = (const int32_t*)pl_esrc.p;
     q.e_rev = (const int32_t*)pl_erev.p;
-    q.n_parts = pl.n_parts;
+    q.n_units = pl.n_units;
     q.n_groups = pl.n_groups;
     q.n_slots = pl.n_slots;
-    q.pt = (pl.n_parts + fnlh::kPartialSlots - 1) / fnlh::kPartialSlots;
+    q.pt = (pl.n_units + fnlh::kPartialSlots - 1) / fnlh::kPartialSlots;
     q.max_rows = pl.max_rows;
+    const int64_t levels = pl.lev_ptr.empty() ? 1 : (int64_t)pl.lev_ptr.size() - 1;
+    q.threads = pl_threads > 0 ? pl_threads
+                               : fnlh::pilu_threads((int)((pl.n_groups * 64 + levels - 1) / std::max<int64_t>(levels, 1)));
     return q;
   }
   DevFlow flow() const {

@@ -163,22 +163,24 @@ void launch_axpy_y(int storage, const DevPattern& p, void* x, const void* y, int
                    const SysState* st, hipStream_t s);
 
 // Partition-local natural-order ILU(0) (layout.h, PiluLayout): device copies of the
-// position, level and packed-coupling tables.  Norm partials of system slot vs, partition
-// k at partial[vs * pt * kPartialSlots + k] (pt = ceil(n_parts / kPartialSlots); the
-// entries past n_parts stay zero), so launch_reduce sums them with n_tiles = nt = pt and
-// slots = kPartialSlots.
+// work-unit, level, position and packed-coupling tables.  Norm partials of system slot
+// vs, unit k at partial[vs * pt * kPartialSlots + k] (pt = ceil(n_units / kPartialSlots);
+// the entries past n_units stay zero), so launch_reduce sums them with n_tiles = nt = pt
+// and slots = kPartialSlots.
 struct PiluDev {
-  const int32_t* part_ptr = nullptr;
-  const int32_t* part_lev = nullptr;
+  const int32_t* unit_ptr = nullptr;
+  const int32_t* unit_lev = nullptr;
   const int32_t* lev_ptr = nullptr;
   const int32_t* pos_row = nullptr;
   const int32_t* g_width = nullptr;
   const int64_t* g_slot0 = nullptr;
   const int32_t* e_pos = nullptr;
+  const int32_t* e_row = nullptr;
   const int32_t* e_src = nullptr;
   const int32_t* e_rev = nullptr;
-  int64_t n_parts = 0, n_groups = 0, n_slots = 0, pt = 0;
-  int32_t max_rows = 0, pad_ = 0;
+  int64_t n_units = 0, n_groups = 0, n_slots = 0, pt = 0;
+  int32_t max_rows = 0;
+  int32_t threads = 256;  // sweep workgroup size (pilu_threads)
 };
 // copy the in-partition couplings and the diagonal blocks into the position layout
 void launch_pilu_pack(int storage, const PiluDev& q, const void* offd, const void* diag, void* coup, void* pdiag,
@@ -186,12 +188,18 @@ void launch_pilu_pack(int storage, const PiluDev& q, const void* offd, const voi
 // Dt^-1 of every position for the systems of sb (slot dslot, group-major tiles)
 void launch_pilu_factor(int storage, const DevPattern& p, const PiluDev& q, const void* coup, const void* pdiag,
                         void* dinv, int64_t dinv_stride, const SysBatch& sb, int* err, hipStream_t s);
-// LDS bytes per partition row and system of the sweep (the y vector held there)
+// LDS bytes per unit row and system of the sweep (the y vector held there)
 int pilu_lds_row_bytes(int storage);
-// systems per workgroup of the sweep for nb systems within lds_max bytes (0: a partition
-// does not fit)
+// systems per workgroup of the sweep for nb systems within lds_max bytes (0: a unit does
+// not fit)
 int pilu_systems_per_group(int storage, int nb, int max_rows, int lds_max);
-// one sweep x <- x + M^-1 (b - K x) for every partition and system of sb, norms of
+// allow the sweep kernels of this storage lds bytes of dynamic LDS (above the 64 KiB
+// default); false if the runtime refuses
+bool pilu_allow_lds(int storage, int lds);
+// sweep workgroup size for units whose levels hold avg_width rows on average (four
+// lanes per row): 64, 128 or 256
+int pilu_threads(int avg_width);
+// one sweep x <- x + M^-1 (b - K x) for every unit and system of sb, norms of
 // b - K x (before the update) into the partials; systems pending or inactive are skipped
 void launch_pilu_sweep(int storage, const DevPattern& p, const PiluDev& q, const void* coup, const void* pdiag,
                        const void* dinv, int64_t dinv_stride, void* x, const void* b, int ns, const SysBatch& sb,

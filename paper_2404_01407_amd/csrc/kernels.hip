@@ -1321,7 +1321,9 @@ __global__ void __launch_bounds__(64) k_factor(DevPattern p, const TB* __restric
 // Section "Parallel Implementation": every partition runs ILU(0) on its own block of the
 // LHS, the couplings to other partitions left out.  Inside a partition the order is the
 // natural one (cell ids), processed level by level (cells of one level are never
-// coupled): one workgroup per (partition, systems), the partition's y vector in LDS.
+// coupled): one workgroup per (work unit, systems), a unit being one or more whole
+// partitions whose levels are merged (cells of different partitions are never coupled
+// either), the unit's y vector in LDS.
 // Blocks are read from packed copies in position order (PiluLayout), so the lanes of a
 // wave, which take consecutive positions of one level, load coalesced 16-byte vectors.
 
@@ -1352,19 +1354,19 @@ __global__ void k_pilu_pack(PiluDev q, const TB* __restrict__ offd, const TB* __
 }
 
 // Dt_i = K_ii + i w_i I - sum_{j lower, same partition} K_ij Dt_j^-1 K_ji, level by level
-// (one wave per (partition, system)); the inverses go to the factor slot in position
+// (one wave per (unit, system)); the inverses go to the factor slot in position
 // order (tile g = position / 64).  The inverses of lower levels are read back from global
 // memory after the workgroup barrier that ends their level: the wave wrote them itself.
 template <typename TB, typename TD>
 __global__ void __launch_bounds__(64) k_pilu_factor(DevPattern p, PiluDev q, const TB* __restrict__ coup,
                                                     const TB* __restrict__ pdiag, TD* dinv, int64_t dstride,
                                                     SysBatch sb, int* __restrict__ err) {
-  const int64_t part = blockIdx.x;
+  const int64_t unit = blockIdx.x;
   const int k = blockIdx.y;
   const int lane = threadIdx.x;
   TD* dbase = dinv + (int64_t)sb.dslot[k] * dstride;
   const bool frz = p.sys_frozen && p.sys_frozen[sb.orow[k]];
-  const int l0 = q.part_lev[part], l1 = q.part_lev[part + 1];
+  const int l0 = q.unit_lev[unit], l1 = q.unit_lev[unit + 1];
   for (int l = l0; l < l1; ++l) {
     const int a = q.lev_ptr[l], e = q.lev_ptr[l + 1];
     for (int qq = a + lane; qq < e; qq += kLanes) {
@@ -1445,89 +1447,192 @@ __global__ void __launch_bounds__(64) k_pilu_factor(DevPattern p, PiluDev q, con
   }
 }
 
-// One preconditioned Richardson sweep of each partition for P systems (one wave):
+// Row r of y = Dinv a (complex 6x6 times complex 6), the factor of one position streamed
+// row by row from its tile.  The products are accumulated with explicit fused
+// multiply-adds in a fixed order, so the result does not depend on how the compiler
+// contracts the kernel it is inlined in (the same for every number of systems a
+// workgroup carries).
+__device__ inline float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <typename A> __device__ inline void cmac(A dr, A di, A ar, A ai, A& yr, A& yi) {
+  yr = fmad(dr, ar, yr);
+  yr = fmad(-di, ai, yr);
+  yi = fmad(dr, ai, yi);
+  yi = fmad(di, ar, yi);
+}
+template <typename TD, typename A>
+__device__ inline void dinv_row(const TD* __restrict__ t, int lane, int r, const A (&a)[12], A& yr, A& yi);
+template <typename A>
+__device__ inline void dinv_row(const double* __restrict__ t, int lane, int r, const A (&a)[12], A& yr, A& yi) {
+  const double2* p = reinterpret_cast<const double2*>(t) + lane;
+  yr = 0;
+  yi = 0;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const nt_d2 d = ld_stream(p + (6 * r + c) * kLanes);
+    cmac((A)d.x, (A)d.y, a[2 * c], a[2 * c + 1], yr, yi);
+  }
+}
+template <typename A>
+__device__ inline void dinv_row(const float* __restrict__ t, int lane, int r, const A (&a)[12], A& yr, A& yi) {
+  const float4* p = reinterpret_cast<const float4*>(t) + lane;
+  yr = 0;
+  yi = 0;
+#pragma unroll
+  for (int h = 0; h < 3; ++h) {
+    const nt_f4 d = ld_stream(p + (3 * r + h) * kLanes);
+    cmac((A)d.x, (A)d.y, a[4 * h], a[4 * h + 1], yr, yi);
+    cmac((A)d.z, (A)d.w, a[4 * h + 2], a[4 * h + 3], yr, yi);
+  }
+}
+template <typename A>
+__device__ inline void dinv_row(const hfac* __restrict__ t, int lane, int r, const A (&a)[12], A& yr, A& yi) {
+  // entries 6r .. 6r+5 lie in the 16-byte vectors (6r)/4 and (6r)/4 + 1 (four per vector)
+  const uint4* p = reinterpret_cast<const uint4*>(t) + lane;
+  const int v0 = (6 * r) >> 2;
+  const nt_u4 d0 = ld_stream(p + v0 * kLanes);
+  const nt_u4 d1 = ld_stream(p + (v0 + 1) * kLanes);
+  const uint32_t w[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+  const int o = 6 * r - 4 * v0;  // 0 or 2
+  const A sc = (A)reinterpret_cast<const float*>(t + 72 * kLanes)[lane];
+  A sr = 0, si = 0;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const uint32_t q = o ? w[c + 2] : w[c];
+    cmac((A)h2f(q & 0xffffu), (A)h2f(q >> 16), a[2 * c], a[2 * c + 1], sr, si);
+  }
+  yr = sr * sc;
+  yi = si * sc;
+}
+
+// One preconditioned Richardson sweep of each unit for P systems:
 //   forward, levels ascending:   r_i = b_i - (K_ii + i w) x_i - sum_j K_ij x_j   (||r||^2)
 //                                y_i = Dt_i^-1 (r_i - sum_{j lower} K_ij y_j)
 //   backward, levels descending: z_i = y_i - Dt_i^-1 sum_{j upper} K_ij z_j
 //   x_i += z_i.
-// y (then z) of the partition's rows lives in LDS, [row in partition][P][12]; x and b
-// are the interleaved vectors [NP][ns][12].
-template <typename TB, int P>
-__global__ void __launch_bounds__(64) k_pilu_sweep(DevPattern p, PiluDev q, const TB* __restrict__ coup,
-                                                   const TB* __restrict__ pdiag,
-                                                   const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
-                                                   typename TV_of<TB>::T* __restrict__ x,
-                                                   const typename TV_of<TB>::T* __restrict__ b, int ns, SysBatch sb,
-                                                   const SysState* __restrict__ st, double* __restrict__ partial) {
+// y (then z) of the unit's rows lives in LDS, [row in unit][P][12]; x and b are the
+// interleaved vectors [NP][ns][12].  A level's rows are taken NT/4 at a time by the
+// workgroup's NT lanes (64, 128 or 256, after the units' level widths), four lanes per
+// row: the row's blocks (its diagonal block and
+// couplings) are dealt out to the four lanes in turn, their partial sums combined by
+// shuffles within the quad, and each lane forms rows {s, s+4} of the factor solve.
+// Cutting the work of a row four ways shortens the chain of dependent steps that every
+// level adds to the sweep.
+template <typename TB, int P, int NT>
+__global__ void __launch_bounds__(NT) k_pilu_sweep(DevPattern p, PiluDev q, const TB* __restrict__ coup,
+                                                             const TB* __restrict__ pdiag,
+                                                             const typename DF_of<TB>::T* __restrict__ dinv,
+                                                             int64_t dstride, typename TV_of<TB>::T* __restrict__ x,
+                                                             const typename TV_of<TB>::T* __restrict__ b, int ns,
+                                                             SysBatch sb, const SysState* __restrict__ st,
+                                                             double* __restrict__ partial) {
   using A = typename TV_of<TB>::T;
   using TD = typename DF_of<TB>::T;
   extern __shared__ uint4 pilu_lds[];
+  __shared__ double wsum[NT / kLanes][P];
   A* ys = reinterpret_cast<A*>(pilu_lds);
-  const int64_t part = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int64_t unit = blockIdx.x;
+  const int sl = threadIdx.x & 3;    // lane within the row's quad
+  const int slot = threadIdx.x >> 2;  // row slot, 64 per pass
+  constexpr int kSlots = NT / 4;
   WaveSys<P> W;
   if (!wave_systems<P>(sb, st, (int)blockIdx.y, true, W)) return;
-  const int q0 = q.part_ptr[part], q1 = q.part_ptr[part + 1];
-  const int l0 = q.part_lev[part], l1 = q.part_lev[part + 1];
+  const int q0 = q.unit_ptr[unit], q1 = q.unit_ptr[unit + 1];
+  const int l0 = q.unit_lev[unit], l1 = q.unit_lev[unit + 1];
   double n2[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) n2[j] = 0.0;
   for (int l = l0; l < l1; ++l) {
     const int a = q.lev_ptr[l], e = q.lev_ptr[l + 1];
-    for (int qq = a + lane; qq < e; qq += kLanes) {
+    for (int base = a; base < e; base += kSlots) {
+      const int qq = base + slot;
+      const bool act = qq < e;
       const int64_t g = qq >> 6;
       const int ln = qq & 63;
-      const int64_t row = q.pos_row[qq];
-      const int64_t rb = row * ns * 12;
       A r[P][12], t[P][12];
-      {
-        A d[36];
-        load_block(pdiag + g * slot_elems<TB>(), ln, d);
 #pragma unroll
-        for (int j = 0; j < P; ++j) {
+      for (int j = 0; j < P; ++j)
 #pragma unroll
-          for (int i = 0; i < 12; ++i) r[j][i] = t[j][i] = 0;
-          if (!W.run[j]) continue;
-          A xi[12];
-          load_vec(b + rb + W.vs[j] * 12, r[j]);
-          load_vec(x + rb + W.vs[j] * 12, xi);
-          sub_diag_shift(r[j], d, (A)shift_w(p, W.orow[j], row), xi);
+        for (int i = 0; i < 12; ++i) r[j][i] = t[j][i] = 0;
+      if (act) {
+        const int64_t row = q.pos_row[qq];
+        const int wd = q.g_width[g];
+        const int64_t s0 = q.g_slot0[g];
+        // item 0 is the diagonal block, item i > 0 coupling i - 1; lane sl takes sl, sl+4, ..
+        for (int i = sl; i <= wd; i += 4) {
+          int nb = qq, src = -1;
+          int64_t vrow = row;
+          const TB* blk = pdiag + g * slot_elems<TB>();
+          if (i > 0) {
+            const int64_t fe = (s0 + i - 1) * kLanes + ln;
+            nb = q.e_pos[fe];
+            if (nb < 0) break;
+            vrow = q.e_row[fe];
+            src = q.e_src[fe];
+            blk = coup + (s0 + i - 1) * slot_elems<TB>();
+          }
+          A kb[36];
+          load_block(blk, ln, kb);
+          const int64_t vo = vrow * ns * 12;
+#pragma unroll
+          for (int j = 0; j < P; ++j) {
+            if (!W.run[j]) continue;
+            A v[12];
+            load_vec(x + vo + W.vs[j] * 12, v);
+            if (src >= 0 && p.ent_phase) apply_phase(p, src, W.orow[j], v);
+            sub_kx(r[j], kb, v);
+            if (i == 0) {  // the shift i w of the diagonal block
+              const A w = (A)shift_w(p, W.orow[j], row);
+#pragma unroll
+              for (int c = 0; c < 6; ++c) {
+                r[j][2 * c] = fmad(w, v[2 * c + 1], r[j][2 * c]);
+                r[j][2 * c + 1] = fmad(-w, v[2 * c], r[j][2 * c + 1]);
+              }
+            } else if (nb < qq) {
+              load_vec(ys + ((int64_t)(nb - q0) * P + j) * 12, v);
+              if (p.ent_phase) apply_phase(p, src, W.orow[j], v);
+              sub_kx(t[j], kb, v);
+            }
+          }
         }
-      }
-      const int wd = q.g_width[g];
-      const int64_t s0 = q.g_slot0[g];
-      for (int kk = 0; kk < wd; ++kk) {
-        const int64_t fe = (s0 + kk) * kLanes + ln;
-        const int nb = q.e_pos[fe];
-        if (nb < 0) break;
-        A kb[36];
-        load_block(coup + (s0 + kk) * slot_elems<TB>(), ln, kb);
-        const int64_t nbo = (int64_t)q.pos_row[nb] * ns * 12;
-        const int32_t src = q.e_src[fe];
+        if (sl == 0) {
 #pragma unroll
-        for (int j = 0; j < P; ++j) {
-          if (!W.run[j]) continue;
-          A v[12];
-          load_vec(x + nbo + W.vs[j] * 12, v);
-          if (p.ent_phase) apply_phase(p, src, W.orow[j], v);
-          sub_kx(r[j], kb, v);
-          if (nb < qq) {
-            load_vec(ys + ((int64_t)(nb - q0) * P + j) * 12, v);
-            if (p.ent_phase) apply_phase(p, src, W.orow[j], v);
-            sub_kx(t[j], kb, v);
+          for (int j = 0; j < P; ++j) {
+            if (!W.run[j]) continue;
+            A bi[12];
+            load_vec(b + row * ns * 12 + W.vs[j] * 12, bi);
+#pragma unroll
+            for (int i = 0; i < 12; ++i) r[j][i] += bi[i];
           }
         }
       }
+      // the quad's partial sums (every lane takes part in the shuffles)
 #pragma unroll
-      for (int j = 0; j < P; ++j) {
-        if (!W.run[j]) continue;
-        mask_frozen(p, W.orow[j], r[j]);
-        n2[j] += norm2_12(r[j]);
+      for (int j = 0; j < P; ++j)
 #pragma unroll
-        for (int i = 0; i < 12; ++i) t[j][i] += r[j][i];
-        A yi[12];
-        apply_dinv(dinv + (int64_t)W.ds[j] * dstride + g * DinvTile<TD>::N, ln, t[j], yi);
-        store_vec(ys + ((int64_t)(qq - q0) * P + j) * 12, yi);
+        for (int i = 0; i < 12; ++i) {
+          r[j][i] += __shfl_xor(r[j][i], 1, kLanes);
+          r[j][i] += __shfl_xor(r[j][i], 2, kLanes);
+          t[j][i] += __shfl_xor(t[j][i], 1, kLanes);
+          t[j][i] += __shfl_xor(t[j][i], 2, kLanes);
+        }
+      if (act) {
+        const TD* dt = dinv + g * DinvTile<TD>::N;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          if (!W.run[j]) continue;
+          mask_frozen(p, W.orow[j], r[j]);
+          if (sl == 0) n2[j] += norm2_12(r[j]);
+#pragma unroll
+          for (int i = 0; i < 12; ++i) t[j][i] += r[j][i];
+          A* yp = ys + ((int64_t)(qq - q0) * P + j) * 12;
+          for (int rr = sl; rr < 6; rr += 4) {
+            A yr, yi;
+            dinv_row(dt + (int64_t)W.ds[j] * dstride, ln, rr, t[j], yr, yi);
+            yp[2 * rr] = yr;
+            yp[2 * rr + 1] = yi;
+          }
+        }
       }
     }
     __syncthreads();
@@ -1535,67 +1640,91 @@ __global__ void __launch_bounds__(64) k_pilu_sweep(DevPattern p, PiluDev q, cons
   // the top level has no upper neighbours: z = y there
   for (int l = l1 - 2; l >= l0; --l) {
     const int a = q.lev_ptr[l], e = q.lev_ptr[l + 1];
-    for (int qq = a + lane; qq < e; qq += kLanes) {
+    for (int base = a; base < e; base += kSlots) {
+      const int qq = base + slot;
+      const bool act = qq < e;
       const int64_t g = qq >> 6;
       const int ln = qq & 63;
-      const int wd = q.g_width[g];
-      const int64_t s0 = q.g_slot0[g];
       A u[P][12];
 #pragma unroll
       for (int j = 0; j < P; ++j)
 #pragma unroll
         for (int i = 0; i < 12; ++i) u[j][i] = 0;
-      bool any = false;
-      for (int kk = 0; kk < wd; ++kk) {
-        const int64_t fe = (s0 + kk) * kLanes + ln;
-        const int nb = q.e_pos[fe];
-        if (nb < 0) break;
-        if (nb < qq) continue;
-        any = true;
-        A kb[36];
-        load_block(coup + (s0 + kk) * slot_elems<TB>(), ln, kb);
-        const int32_t src = q.e_src[fe];
+      int any = 0;
+      if (act) {
+        const int wd = q.g_width[g];
+        const int64_t s0 = q.g_slot0[g];
+        for (int k = sl; k < wd; k += 4) {
+          const int64_t fe = (s0 + k) * kLanes + ln;
+          const int nb = q.e_pos[fe];
+          if (nb < qq) continue;  // lower neighbours and padding (-1)
+          any = 1;
+          A kb[36];
+          load_block(coup + (s0 + k) * slot_elems<TB>(), ln, kb);
+          const int src = q.e_src[fe];
+#pragma unroll
+          for (int j = 0; j < P; ++j) {
+            if (!W.run[j]) continue;
+            A v[12];
+            load_vec(ys + ((int64_t)(nb - q0) * P + j) * 12, v);
+            if (p.ent_phase) apply_phase(p, src, W.orow[j], v);
+            sub_kx(u[j], kb, v);
+          }
+        }
+      }
+      any |= __shfl_xor(any, 1, kLanes);
+      any |= __shfl_xor(any, 2, kLanes);
+#pragma unroll
+      for (int j = 0; j < P; ++j)
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+          u[j][i] += __shfl_xor(u[j][i], 1, kLanes);
+          u[j][i] += __shfl_xor(u[j][i], 2, kLanes);
+        }
+      if (act && any) {
+        const TD* dt = dinv + g * DinvTile<TD>::N;
 #pragma unroll
         for (int j = 0; j < P; ++j) {
           if (!W.run[j]) continue;
-          A v[12];
-          load_vec(ys + ((int64_t)(nb - q0) * P + j) * 12, v);
-          if (p.ent_phase) apply_phase(p, src, W.orow[j], v);
-          sub_kx(u[j], kb, v);
+          A* yp = ys + ((int64_t)(qq - q0) * P + j) * 12;
+          for (int rr = sl; rr < 6; rr += 4) {
+            A dr, di;
+            dinv_row(dt + (int64_t)W.ds[j] * dstride, ln, rr, u[j], dr, di);
+            yp[2 * rr] += dr;
+            yp[2 * rr + 1] += di;
+          }
         }
-      }
-      if (!any) continue;
-#pragma unroll
-      for (int j = 0; j < P; ++j) {
-        if (!W.run[j]) continue;
-        A d[12], yi[12];
-        apply_dinv(dinv + (int64_t)W.ds[j] * dstride + g * DinvTile<TD>::N, ln, u[j], d);
-        A* yp = ys + ((int64_t)(qq - q0) * P + j) * 12;
-        load_vec(yp, yi);
-#pragma unroll
-        for (int i = 0; i < 12; ++i) yi[i] += d[i];
-        store_vec(yp, yi);
       }
     }
     __syncthreads();
   }
-  for (int qq = q0 + lane; qq < q1; qq += kLanes) {
+  // x += z, three of the twelve values of a row per lane
+  for (int qq = q0 + slot; qq < q1; qq += kSlots) {
     const int64_t rb = (int64_t)q.pos_row[qq] * ns * 12;
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       if (!W.run[j]) continue;
-      A xi[12], zi[12];
-      load_vec(x + rb + W.vs[j] * 12, xi);
-      load_vec(ys + ((int64_t)(qq - q0) * P + j) * 12, zi);
+      A* xp = x + rb + W.vs[j] * 12 + 3 * sl;
+      const A* zp = ys + ((int64_t)(qq - q0) * P + j) * 12 + 3 * sl;
 #pragma unroll
-      for (int i = 0; i < 12; ++i) xi[i] += zi[i];
-      store_vec(x + rb + W.vs[j] * 12, xi);
+      for (int i = 0; i < 3; ++i) xp[i] += zp[i];
     }
   }
+  // norms: per wave, then the workgroup's waves in order
 #pragma unroll
   for (int j = 0; j < P; ++j) {
-    const double s = wave_sum(n2[j]);
-    if (lane == 0 && W.run[j]) partial[(int64_t)W.vs[j] * q.pt * kPartialSlots + part] = s;
+    const double sum = wave_sum(n2[j]);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6][j] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      if (!W.run[j]) continue;
+      double tot = 0.0;
+      for (int w = 0; w < NT / kLanes; ++w) tot += wsum[w][j];
+      partial[(int64_t)W.vs[j] * q.pt * kPartialSlots + unit] = tot;
+    }
   }
 }
 
@@ -2297,8 +2426,8 @@ void launch_pilu_pack(int storage, const PiluDev& q, const void* offd, const voi
 }
 void launch_pilu_factor(int storage, const DevPattern& p, const PiluDev& q, const void* coup, const void* pdiag,
                         void* dinv, int64_t dinv_stride, const SysBatch& sb, int* err, hipStream_t s) {
-  if (q.n_parts <= 0 || sb.n <= 0) return;
-  dim3 grid((unsigned)q.n_parts, (unsigned)sb.n);
+  if (q.n_units <= 0 || sb.n <= 0) return;
+  dim3 grid((unsigned)q.n_units, (unsigned)sb.n);
   FNLH_DISPATCH_STORE(storage, {
     using TD = typename DF_of<TB>::T;
     hipLaunchKernelGGL((k_pilu_factor<TB, TD>), grid, dim3(64), 0, s, p, q, (const TB*)coup, (const TB*)pdiag,
@@ -2306,26 +2435,60 @@ void launch_pilu_factor(int storage, const DevPattern& p, const PiluDev& q, cons
   });
 }
 int pilu_lds_row_bytes(int storage) { return 12 * (storage == kF64 ? 8 : 4); }
+#define FNLH_PILU_ATTR(PV, NTV)                                                                                      \
+  ok = ok && hipFuncSetAttribute((const void*)k_pilu_sweep<TB, PV, NTV>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                 lds) == hipSuccess
+bool pilu_allow_lds(int storage, int lds) {
+  bool ok = true;
+  FNLH_DISPATCH_STORE(storage, {
+    FNLH_PILU_ATTR(1, 64);
+    FNLH_PILU_ATTR(2, 64);
+    FNLH_PILU_ATTR(3, 64);
+    FNLH_PILU_ATTR(4, 64);
+    FNLH_PILU_ATTR(1, 128);
+    FNLH_PILU_ATTR(2, 128);
+    FNLH_PILU_ATTR(3, 128);
+    FNLH_PILU_ATTR(4, 128);
+    FNLH_PILU_ATTR(1, 256);
+    FNLH_PILU_ATTR(2, 256);
+    FNLH_PILU_ATTR(3, 256);
+    FNLH_PILU_ATTR(4, 256);
+  });
+  (void)hipGetLastError();
+  return ok;
+}
+#undef FNLH_PILU_ATTR
+int pilu_threads(int avg_width) { return avg_width <= 16 ? 64 : avg_width <= 32 ? 128 : 256; }
 int pilu_systems_per_group(int storage, int nb, int max_rows, int lds_max) {
   int P = nb < 4 ? nb : 4;
   while (P > 0 && (int64_t)max_rows * P * pilu_lds_row_bytes(storage) > lds_max) --P;
   return P;
 }
+#define FNLH_PILU_LAUNCH(NTV)                                                                                  \
+  hipLaunchKernelGGL((k_pilu_sweep<TB, PP, NTV>), grid, dim3(NTV), lds, s, p, q, (const TB*)coup,              \
+                     (const TB*)pdiag, (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, \
+                     st, partial)
 void launch_pilu_sweep(int storage, const DevPattern& p, const PiluDev& q, const void* coup, const void* pdiag,
                        const void* dinv, int64_t dinv_stride, void* x, const void* b, int ns, const SysBatch& sb,
                        const SysState* st, double* partial, int lds_max, hipStream_t s) {
-  if (q.n_parts <= 0 || sb.n <= 0) return;
+  if (q.n_units <= 0 || sb.n <= 0) return;
   const int P = pilu_systems_per_group(storage, sb.n, q.max_rows, lds_max);
-  if (P <= 0) return;  // the caller checks that a partition fits
-  dim3 grid((unsigned)q.n_parts, (unsigned)((sb.n + P - 1) / P));
+  if (P <= 0) return;  // the caller checks that a unit fits
+  dim3 grid((unsigned)q.n_units, (unsigned)((sb.n + P - 1) / P));
   const unsigned lds = (unsigned)q.max_rows * P * pilu_lds_row_bytes(storage);
+  const int nt = q.threads;
   FNLH_DISPATCH_STORE(storage, {
     using A = typename Fmt<TB>::A;
     FNLH_DISPATCH_P(P, {
-      hipLaunchKernelGGL((k_pilu_sweep<TB, PP>), grid, dim3(64), lds, s, p, q, (const TB*)coup, (const TB*)pdiag,
-                         (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)b, ns, sb, st, partial);
+      if (nt == 64)
+        FNLH_PILU_LAUNCH(64);
+      else if (nt == 128)
+        FNLH_PILU_LAUNCH(128);
+      else
+        FNLH_PILU_LAUNCH(256);
     });
   });
 }
+#undef FNLH_PILU_LAUNCH
 
 }  // namespace fnlh

@@ -415,7 +415,8 @@ int build_layout(const fnlh_mesh& m, const fnlh_options& o, Layout& L, std::stri
   return FNLH_OK;
 }
 
-int build_pilu(const Layout& L, const std::vector<int32_t>& part, PiluLayout& P, std::string& err) {
+int build_pilu(const Layout& L, const std::vector<int32_t>& part, int32_t unit_rows, PiluLayout& P,
+               std::string& err) {
   const int64_t N = L.N;
   if ((int64_t)part.size() != N) {
     err = "partition-local ILU: one partition label per cell needed";
@@ -449,6 +450,21 @@ int build_pilu(const Layout& L, const std::vector<int32_t>& part, PiluLayout& P,
     pidx[u] = (int32_t)(std::lower_bound(labels.begin(), labels.end(), part[u]) - labels.begin());
     psize[pidx[u]]++;
   }
+  for (int64_t k = 0; k < P.n_parts; ++k) P.max_part = std::max<int32_t>(P.max_part, (int32_t)psize[k]);
+  // work units: consecutive partitions while they fit in unit_rows cells
+  std::vector<int32_t> unit_of(P.n_parts);
+  {
+    int64_t rows = 0, u = -1;
+    for (int64_t k = 0; k < P.n_parts; ++k) {
+      if (u < 0 || rows + psize[k] > std::max<int64_t>(unit_rows, 1)) {
+        ++u;
+        rows = 0;
+      }
+      unit_of[k] = (int32_t)u;
+      rows += psize[k];
+    }
+    P.n_units = u + 1;
+  }
   // levels, visiting cells by ascending id (the natural order inside every partition)
   std::vector<int32_t> level(N, 0);
   for (int64_t u = 0; u < N; ++u) {
@@ -458,34 +474,36 @@ int build_pilu(const Layout& L, const std::vector<int32_t>& part, PiluLayout& P,
     });
     level[u] = lv;
   }
-  // positions: partition, then (level, id)
+  // positions: unit, then (level, partition, id)
   std::vector<int32_t> cells(N);
   std::iota(cells.begin(), cells.end(), 0);
   std::stable_sort(cells.begin(), cells.end(), [&](int32_t a, int32_t b) {
-    if (pidx[a] != pidx[b]) return pidx[a] < pidx[b];
-    return level[a] < level[b];
+    const int32_t ua = unit_of[pidx[a]], ub = unit_of[pidx[b]];
+    if (ua != ub) return ua < ub;
+    if (level[a] != level[b]) return level[a] < level[b];
+    return pidx[a] < pidx[b];
   });
   std::vector<int32_t> pos_of(N);
   for (int64_t q = 0; q < N; ++q) pos_of[cells[q]] = (int32_t)q;
-  P.part_ptr.assign(P.n_parts + 1, 0);
-  for (int64_t k = 0; k < P.n_parts; ++k) {
-    P.part_ptr[k + 1] = P.part_ptr[k] + (int32_t)psize[k];
-    P.max_rows = std::max<int32_t>(P.max_rows, (int32_t)psize[k]);
+  P.unit_ptr.assign(P.n_units + 1, 0);
+  for (int64_t k = 0; k < P.n_parts; ++k) P.unit_ptr[unit_of[k] + 1] += (int32_t)psize[k];
+  for (int64_t w = 0; w < P.n_units; ++w) {
+    P.max_rows = std::max(P.max_rows, P.unit_ptr[w + 1]);
+    P.unit_ptr[w + 1] += P.unit_ptr[w];
   }
-  P.part_lev.assign(P.n_parts + 1, 0);
+  P.unit_lev.assign(P.n_units + 1, 0);
   P.lev_ptr.assign(1, 0);
-  for (int64_t k = 0; k < P.n_parts; ++k) {
-    const int32_t a = P.part_ptr[k], b = P.part_ptr[k + 1];
+  for (int64_t w = 0; w < P.n_units; ++w) {
+    const int32_t a = P.unit_ptr[w], b = P.unit_ptr[w + 1];
     for (int32_t q = a; q < b; ++q)
       if (q + 1 == b || level[cells[q + 1]] != level[cells[q]]) P.lev_ptr.push_back(q + 1);
-    P.part_lev[k + 1] = (int32_t)P.lev_ptr.size() - 1;
-    P.max_levels = std::max(P.max_levels, P.part_lev[k + 1] - P.part_lev[k]);
+    P.unit_lev[w + 1] = (int32_t)P.lev_ptr.size() - 1;
+    P.max_levels = std::max(P.max_levels, P.unit_lev[w + 1] - P.unit_lev[w]);
   }
   // packed couplings per group of 64 positions, lower neighbours first
   P.n_groups = (N + kTile - 1) / kTile;
   P.pos_row.assign(P.n_groups * kTile, -1);
   for (int64_t q = 0; q < N; ++q) P.pos_row[q] = L.perm[cells[q]];
-  std::vector<std::vector<std::pair<int32_t, int64_t>>> nb(kTile);
   P.g_width.assign(P.n_groups, 0);
   P.g_slot0.assign(P.n_groups, 0);
   int64_t slot = 0;
@@ -503,20 +521,22 @@ int build_pilu(const Layout& L, const std::vector<int32_t>& part, PiluLayout& P,
   }
   P.n_slots = slot;
   P.e_pos.assign(P.n_slots * kTile, -1);
+  P.e_row.assign(P.n_slots * kTile, -1);
   P.e_src.assign(P.n_slots * kTile, -1);
   P.e_rev.assign(P.n_slots * kTile, -1);
   std::vector<int32_t> packed_of(L.n_slots * kTile, -1);
+  std::vector<std::pair<int32_t, int64_t>> list;
   for (int64_t g = 0; g < P.n_groups; ++g) {
     for (int lane = 0; lane < kTile; ++lane) {
       const int64_t q = g * kTile + lane;
       if (q >= N) continue;
-      std::vector<std::pair<int32_t, int64_t>>& list = nb[lane];
       list.clear();
       each_coupling(cells[q], [&](int32_t v, int64_t fe) { list.emplace_back(pos_of[v], fe); });
       std::sort(list.begin(), list.end());
       for (size_t k = 0; k < list.size(); ++k) {
         const int64_t pe = (P.g_slot0[g] + (int64_t)k) * kTile + lane;
         P.e_pos[pe] = list[k].first;
+        P.e_row[pe] = P.pos_row[list[k].first];
         P.e_src[pe] = (int32_t)list[k].second;
         packed_of[list[k].second] = (int32_t)pe;
       }

@@ -60,26 +60,31 @@ int build_layout(const fnlh_mesh& m, const fnlh_options& o, Layout& L, std::stri
 // partitions ignored).  Inside a partition the order is the user cell numbering; a
 // cell's level is one more than the highest level among its in-partition neighbours of
 // lower number (0 if none), so the cells of one level are never coupled and can be
-// processed together.  Positions number the cells partition by partition (partitions
-// by ascending label), inside a partition by (level, cell id); the in-partition
-// couplings of a position are packed in SELL-64 form over groups of 64 consecutive
-// positions, lower neighbours first.
+// processed together.  Consecutive partitions (by ascending label) are grouped into
+// work units of at most unit_rows cells (a partition larger than that is a unit of its
+// own); a unit is processed by one workgroup, level by level, its partitions' levels
+// merged (cells of different partitions are never coupled either).  Positions number
+// the cells unit by unit, inside a unit by (level, partition, cell id); the
+// in-partition couplings of a position are packed in SELL-64 form over groups of 64
+// consecutive positions, lower neighbours first.
 struct PiluLayout {
-  int64_t n_parts = 0, n_groups = 0, n_slots = 0;
-  int32_t max_rows = 0, max_levels = 0;
+  int64_t n_parts = 0, n_units = 0, n_groups = 0, n_slots = 0;
+  int32_t max_part = 0, max_rows = 0, max_levels = 0;  // largest partition, largest unit
   int64_t n_coup = 0;                // in-partition couplings (directed)
-  std::vector<int32_t> part_ptr;     // [n_parts+1] position range of each partition
-  std::vector<int32_t> part_lev;     // [n_parts+1] level range of each partition (into lev_ptr)
+  std::vector<int32_t> unit_ptr;     // [n_units+1] position range of each unit
+  std::vector<int32_t> unit_lev;     // [n_units+1] level range of each unit (into lev_ptr)
   std::vector<int32_t> lev_ptr;      // [levels+1] position range of each level
   std::vector<int32_t> pos_row;      // [n_groups*64] internal row of each position, -1 past N
   std::vector<int32_t> g_width;      // [n_groups] couplings of the group's widest position
   std::vector<int64_t> g_slot0;      // [n_groups] first packed slot
   std::vector<int32_t> e_pos;        // [n_slots*64] neighbour position, -1 padding
+  std::vector<int32_t> e_row;        // [n_slots*64] neighbour internal row, -1 padding
   std::vector<int32_t> e_src;        // [n_slots*64] the coupling's flat entry in the SELL layout
   std::vector<int32_t> e_rev;        // [n_slots*64] packed entry of the transposed coupling
 };
 
-// part: [N] partition label of each user cell.
-int build_pilu(const Layout& L, const std::vector<int32_t>& part, PiluLayout& P, std::string& err);
+// part: [N] partition label of each user cell; unit_rows: cells per work unit (>= 1).
+int build_pilu(const Layout& L, const std::vector<int32_t>& part, int32_t unit_rows, PiluLayout& P,
+               std::string& err);
 
 }  // namespace fnlh

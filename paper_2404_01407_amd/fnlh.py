@@ -447,16 +447,22 @@ class Context:
         self._check(rc, allow_positive=True)
         return rc, hist[:int(n_steps)]
 
-    def tune(self, sys_per_lane=0, lanes_per_row=0, wave_groups=None, hybrid=None):
-        """Set the sweep-kernel shape (0 = automatic); wave_groups (0/1) and hybrid (0/1:
-        two-colour passes plus remainder passes for nearly two-coloured orderings) when
-        given."""
+    def tune(self, sys_per_lane=0, lanes_per_row=0, wave_groups=None, hybrid=None, pilu_unit=None,
+             pilu_threads=None):
+        """Set the sweep-kernel shape (0 = automatic); wave_groups (0/1), hybrid (0/1:
+        two-colour passes plus remainder passes for nearly two-coloured orderings),
+        pilu_unit (kind "pilu": cells per work unit, 0 = automatic) and pilu_threads
+        (kind "pilu": sweep workgroup size 64/128/256, 0 = automatic) when given."""
         self._check(LIB.fnlh_tune(self.h, 0, int(sys_per_lane)))
         self._check(LIB.fnlh_tune(self.h, 1, int(lanes_per_row)))
         if wave_groups is not None:
             self._check(LIB.fnlh_tune(self.h, 2, int(wave_groups)))
         if hybrid is not None:
             self._check(LIB.fnlh_tune(self.h, 3, int(hybrid)))
+        if pilu_unit is not None:
+            self._check(LIB.fnlh_tune(self.h, 4, int(pilu_unit)))
+        if pilu_threads is not None:
+            self._check(LIB.fnlh_tune(self.h, 5, int(pilu_threads)))
 
     def autotune(self, n_sys, rtol=1e-8, max_sweeps=6000, cache=None, stream=None):
         """Pick the sweep configuration (path, kernel shape, workgroup mapping) by the

@@ -273,6 +273,43 @@ def test_pilu_stats(F):
     c.close()
 
 
+def test_pilu_work_units_bitwise(F):
+    """Work units (consecutive partitions swept by one workgroup, levels merged) and the
+    workgroup size change the schedule, not the arithmetic: each partition alone, the
+    automatic unit and units of up to 400 cells, with 64, 128 and 256 lanes, give the
+    same iterates bit for bit."""
+    m, Q, K = _case("passage", seed=8, shape=(24, 12, 6))
+    part = synth.rcb_partition(m, 40)
+    c = _ctx(F, m, Q, part)
+    bs = _rhs(m, 70)
+    out = []
+    for unit, nt in ((1, 0), (0, 64), (0, 128), (400, 256)):
+        c.tune(pilu_unit=unit, pilu_threads=nt)
+        _, rep, xs = _solve(c, [0, 1, 2], bs, max_sweeps=6, rtol=0.0)
+        out.append(xs)
+    for xs in out[1:]:
+        for s in range(3):
+            assert np.array_equal(xs[s], out[0][s])
+    Kd = solve.partition_dropped(K, part)
+    x_or, _ = solve.richardson(Kd, m.volume, m.zone, OMEGA[2], bs[2], _natural(m), "DILU", rtol=0.0, max_sweeps=6)
+    assert itererr(out[2][2], x_or) <= ITER_TOL
+    c.close()
+
+
+def test_pilu_partitions_above_64k_lds(F):
+    """Partitions of 1440 cells: FP64 y vectors of 138 KB, more than 64 KiB of LDS."""
+    m, Q, K = _case("passage", seed=14, shape=(24, 12, 10))
+    part = synth.rcb_partition(m, 1500)
+    assert np.bincount(part).max() * 96 > 65536
+    c = _ctx(F, m, Q, part)
+    bs = _rhs(m, 80)
+    st, rep, xs = _solve(c, [1], bs[1:2], max_sweeps=3, rtol=0.0)
+    Kd = solve.partition_dropped(K, part)
+    x_or, _ = solve.richardson(Kd, m.volume, m.zone, OMEGA[1], bs[1], _natural(m), "DILU", rtol=0.0, max_sweeps=3)
+    assert itererr(xs[0], x_or) <= ITER_TOL
+    c.close()
+
+
 def test_pilu_errors(F):
     m, Q, K = _case("passage", seed=13)
     c = F.Context(m)
@@ -282,8 +319,8 @@ def test_pilu_errors(F):
     with pytest.raises(F.FnlhError):          # no partitions
         _solve(c, [0], bs[:1], max_sweeps=3, rtol=0.0)
     c.close()
-    big, Qb, _ = _case("passage", seed=13, shape=(24, 12, 10))
-    c = _ctx(F, big, Qb, synth.rcb_partition(big, 1500), storage="f32")
+    big, Qb, _ = _case("passage", seed=13, shape=(24, 12, 30))
+    c = _ctx(F, big, Qb, synth.rcb_partition(big, 4500), storage="f32")   # 4320 cells: 207 KB of y
     with pytest.raises(F.FnlhError):          # a partition larger than a workgroup's LDS holds
         _solve(c, [0], [synth.rhs(big.n_cells, 1)], max_sweeps=3, rtol=0.0)
     c.close()

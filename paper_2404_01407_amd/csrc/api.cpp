@@ -294,8 +294,8 @@ double alg_bytes(fnlh_ctx c, int kind, int col, int na, int mode = 0) {
       } else if (mode == kRemBwd) {  // upper couplings; x, y read and written; the factor
         shared = L.c_deg_upper[col] * blk + L.c_deg[col] * 4;
         per = nrows(col) * (4 * 12 * sv + dv) + L.c_nbr_upper[col] * 12 * sv;
-      } else {  // kRemCorrect: the listed tiles' rows coupled upwards
-        shared = L.c_deg_upper[col] * blk + (double)c->hyb_ents * 4;
+      } else {  // kRemCorrect: the second colour's rows coupled upwards, their upward couplings
+        shared = (double)c->hyb_ents * (blk + 8) + (double)c->hyb_rows * 4;
         per = (double)c->hyb_rows * (2 * 12 * sv + dv) + L.c_nbr_upper[col] * 12 * sv;
       }
       break;
@@ -397,13 +397,12 @@ void one_sweep(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, const SysBatc
     for (int col = m - 2; col >= 2; --col) {
       T.begin(FNLH_KSTAT_REMAINDER, col, k, kRemBwd);
       launch_bwd(cfg, kBwdHybrid, p, c->offd.p, c->dinv.p, ds, x, y, ns, sb, st, L.ctile[col],
-                 L.ctile[col + 1] - L.ctile[col], L.cstart[col + 1], nullptr, s);
+                 L.ctile[col + 1] - L.ctile[col], L.cstart[col + 1], s);
       T.end();
     }
-    if (c->hyb_ntiles > 0) {
+    if (c->hyb_groups > 0) {
       T.begin(FNLH_KSTAT_REMAINDER, 1, k, kRemCorrect);
-      launch_bwd(cfg, kBwdCorrect, p, c->offd.p, c->dinv.p, ds, x, y, ns, sb, st, 0, c->hyb_ntiles, L.cstart[2],
-                 (const int32_t*)c->hyb_tiles.p, s);
+      launch_correct(cfg.storage, p, c->corr(), c->offd.p, c->dinv.p, ds, x, y, ns, sb, st, s);
       T.end();
     }
     FusedReduce fr;
@@ -439,7 +438,7 @@ void one_sweep(fnlh_ctx c, Path path, const SweepCfg& cfg, int ns, const SysBatc
     for (int col = m - 2; col >= 0; --col) {
       T.begin(FNLH_KSTAT_BWD, col, k);
       launch_bwd(cfg, kBwdGeneral, p, c->offd.p, c->dinv.p, ds, x, y, ns, sb, st, L.ctile[col],
-                 L.ctile[col + 1] - L.ctile[col], L.cstart[col + 1], nullptr, s);
+                 L.ctile[col + 1] - L.ctile[col], L.cstart[col + 1], s);
       T.end();
     }
   } else {
@@ -625,30 +624,56 @@ bool hybrid_ok(fnlh_ctx c) {
   return (double)rest <= kHybridMaxRemainder * (double)L.N;
 }
 
-// The tiles of the second colour with a row coupled to a higher colour (the rows the
-// hybrid sweep corrects after the remainder's backward passes), with their row and
-// entry counts for the byte model.
+// The second-colour rows coupled to a higher colour (the rows the hybrid sweep corrects
+// after the remainder's backward passes), packed 64 to a group with their upward
+// couplings in slot order; counts of rows and entries for the byte model.
 int setup_hybrid(fnlh_ctx c) {
   const Layout& L = c->L;
-  c->hyb_ntiles = c->hyb_rows = c->hyb_ents = 0;
+  c->hyb_groups = c->hyb_rows = c->hyb_ents = 0;
   if (L.n_colours < 3) return FNLH_OK;
-  std::vector<int32_t> tiles;
+  std::vector<int32_t> rows;
+  std::vector<std::vector<int32_t>> ents;
   for (int64_t t = L.ctile[1]; t < L.ctile[2]; ++t) {
-    int64_t rows = 0;
     for (int lane = 0; lane < L.tile_nrows[t]; ++lane) {
-      bool up = false;
-      for (int q = 0; q < L.tile_width[t] && !up; ++q)
-        up = L.ent_nbr[(L.tile_slot0[t] + q) * kTile + lane] >= L.cstart[2];
-      rows += up ? 1 : 0;
-    }
-    if (rows) {
-      tiles.push_back((int32_t)t);
-      c->hyb_rows += rows;
-      c->hyb_ents += (int64_t)L.tile_width[t] * kTile;
+      std::vector<int32_t> up;
+      for (int q = 0; q < L.tile_width[t]; ++q) {
+        const int64_t fe = (L.tile_slot0[t] + q) * kTile + lane;
+        if (L.ent_edge[fe] != 0 && L.ent_nbr[fe] >= L.cstart[2]) up.push_back((int32_t)fe);
+      }
+      if (!up.empty()) {
+        rows.push_back((int32_t)(t * kTile + lane));
+        ents.push_back(up);
+      }
     }
   }
-  c->hyb_ntiles = (int64_t)tiles.size();
-  return tiles.empty() ? FNLH_OK : dupload(c, c->hyb_tiles, tiles, "pattern");
+  if (rows.empty()) return FNLH_OK;
+  const int64_t ng = ((int64_t)rows.size() + kTile - 1) / kTile;
+  std::vector<int32_t> row(ng * kTile, -1), width(ng, 0);
+  std::vector<int64_t> slot0(ng, 0);
+  int64_t slots = 0;
+  for (int64_t g = 0; g < ng; ++g) {
+    int32_t w = 0;
+    for (int lane = 0; lane < kTile && g * kTile + lane < (int64_t)rows.size(); ++lane)
+      w = std::max<int32_t>(w, (int32_t)ents[g * kTile + lane].size());
+    width[g] = w;
+    slot0[g] = slots;
+    slots += w;
+  }
+  std::vector<int32_t> fe(slots * kTile, -1);
+  for (int64_t i = 0; i < (int64_t)rows.size(); ++i) {
+    const int64_t g = i / kTile;
+    const int lane = (int)(i % kTile);
+    row[i] = rows[i];
+    for (size_t k = 0; k < ents[i].size(); ++k) fe[(slot0[g] + (int64_t)k) * kTile + lane] = ents[i][k];
+    c->hyb_ents += (int64_t)ents[i].size();
+  }
+  c->hyb_rows = (int64_t)rows.size();
+  c->hyb_groups = ng;
+  int rc;
+  if ((rc = dupload(c, c->corr_row, row, "pattern")) || (rc = dupload(c, c->corr_width, width, "pattern")) ||
+      (rc = dupload(c, c->corr_slot0, slot0, "pattern")) || (rc = dupload(c, c->corr_fe, fe, "pattern")))
+    return rc;
+  return FNLH_OK;
 }
 
 int ensure_dominance(fnlh_ctx c, hipStream_t s) {
@@ -1176,8 +1201,8 @@ int fnlh_destroy(fnlh_ctx c) {
                     &c->bface_area, &c->offd, &c->diag, &c->offd64, &c->diag64, &c->state, &c->bstate,
                     &c->d_omega, &c->dinv, &c->x64, &c->b64, &c->r64, &c->y, &c->rhs32, &c->d32, &c->partial,
                     &c->st, &c->st_outer, &c->d_err, &c->ent_phase, &c->phase_cs, &c->sys_frozen, &c->ent_drop,
-                    &c->hyb_tiles, &c->pl_unit_ptr, &c->pl_unit_lev, &c->pl_lev_ptr, &c->pl_pos_row,
-                    &c->pl_gwidth, &c->pl_gslot0, &c->pl_epos, &c->pl_erow, &c->pl_esrc, &c->pl_erev, &c->pl_coup,
+                    &c->corr_row, &c->corr_width, &c->corr_slot0, &c->corr_fe, &c->pl_unit_ptr,
+                    &c->pl_unit_lev, &c->pl_lev_ptr, &c->pl_pos_row, &c->pl_gwidth, &c->pl_gslot0, &c->pl_epos, &c->pl_erow, &c->pl_esrc, &c->pl_erev, &c->pl_coup,
                     &c->pl_diag, &c->pl_partial};
   for (DevBuf* b : bufs) dfree(*b);
   if (c->h_st) (void)hipHostFree(c->h_st);
@@ -2199,7 +2224,8 @@ int fnlh_memory(fnlh_ctx c, size_t* matrix_bytes, size_t* factor_bytes, size_t* 
   const DevBuf* mat[] = {&c->ent_phase, &c->ent_drop, &c->tile_nrows, &c->tile_width, &c->tile_slot0, &c->ent_nbr, &c->ent_edge, &c->ent_rev,
                          &c->vol, &c->zone, &c->iperm, &c->perm, &c->edge_ent, &c->bf_ptr, &c->bf_idx, &c->area,
                          &c->bface_area, &c->offd, &c->diag, &c->offd64, &c->diag64, &c->state, &c->bstate,
-                         &c->hyb_tiles, &c->pl_unit_ptr, &c->pl_unit_lev, &c->pl_lev_ptr, &c->pl_pos_row,
+                         &c->corr_row, &c->corr_width, &c->corr_slot0, &c->corr_fe, &c->pl_unit_ptr,
+                         &c->pl_unit_lev, &c->pl_lev_ptr, &c->pl_pos_row,
                          &c->pl_gwidth, &c->pl_gslot0, &c->pl_epos, &c->pl_erow, &c->pl_esrc, &c->pl_erev,
                          &c->pl_coup, &c->pl_diag};
   const DevBuf* vec[] = {&c->x64, &c->b64,     &c->r64,     &c->y,  &c->rhs32,   &c->d32,

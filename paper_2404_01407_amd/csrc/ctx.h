@@ -35,8 +35,9 @@ struct fnlh_ctx_s {
   int lanes_per_row = 0;  // lanes sharing a row in the two-colour pass (0 = automatic)
   int wave_groups = 1;    // two-colour pass: 1 = one wave per workgroup (default), 0 = a tile per workgroup
   int hybrid = 1;         // colourings with a small remainder past two colours: two-colour passes + remainder
-  DevBuf hyb_tiles;       // second-colour tiles with a row coupled to a higher colour
-  int64_t hyb_ntiles = 0, hyb_rows = 0, hyb_ents = 0;
+  // second-colour rows coupled to a higher colour, packed for the correction (CorrDev)
+  DevBuf corr_row, corr_width, corr_slot0, corr_fe;
+  int64_t hyb_groups = 0, hyb_rows = 0, hyb_ents = 0;
   std::string err;
 
   // pattern (device)
@@ -125,6 +126,15 @@ struct fnlh_ctx_s {
     p.phase_cs = (const double*)phase_cs.p;
     p.sys_frozen = (const uint8_t*)sys_frozen.p;
     return p;
+  }
+  fnlh::CorrDev corr() const {
+    fnlh::CorrDev q;
+    q.row = (const int32_t*)corr_row.p;
+    q.width = (const int32_t*)corr_width.p;
+    q.slot0 = (const int64_t*)corr_slot0.p;
+    q.fe = (const int32_t*)corr_fe.p;
+    q.n_groups = hyb_groups;
+    return q;
   }
   fnlh::PiluDev pilu() const {
     fnlh::PiluDev q;

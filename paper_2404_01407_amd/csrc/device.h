@@ -163,23 +163,23 @@ template <> struct DinvTile<hfac> {
   static constexpr int64_t N = 74 * kLanes;
 };
 
-template <typename TD> __device__ inline void store_dinv(TD* tile, int lane, const double (&re)[36], const double (&im)[36]);
-template <> __device__ inline void store_dinv<double>(double* t, int lane, const double (&re)[36], const double (&im)[36]) {
+// Store a row's D~^-1 (re, im: 36 complex entries, row-major, of the arithmetic type F).
+template <typename F> __device__ inline void store_dinv(double* t, int lane, const F (&re)[36], const F (&im)[36]) {
   double2* p = reinterpret_cast<double2*>(t) + lane;
 #pragma unroll
-  for (int c = 0; c < 36; ++c) p[c * kLanes] = make_double2(re[c], im[c]);
+  for (int c = 0; c < 36; ++c) p[c * kLanes] = make_double2((double)re[c], (double)im[c]);
 }
-template <> __device__ inline void store_dinv<float>(float* t, int lane, const double (&re)[36], const double (&im)[36]) {
+template <typename F> __device__ inline void store_dinv(float* t, int lane, const F (&re)[36], const F (&im)[36]) {
   float4* p = reinterpret_cast<float4*>(t) + lane;
 #pragma unroll
   for (int v = 0; v < 18; ++v)
     p[v * kLanes] = make_float4((float)re[2 * v], (float)im[2 * v], (float)re[2 * v + 1], (float)im[2 * v + 1]);
 }
 
-template <> __device__ inline void store_dinv<hfac>(hfac* t, int lane, const double (&re)[36], const double (&im)[36]) {
+template <typename F> __device__ inline void store_dinv(hfac* t, int lane, const F (&re)[36], const F (&im)[36]) {
   double m = 0.0;
 #pragma unroll
-  for (int c = 0; c < 36; ++c) m = fmax(m, fmax(fabs(re[c]), fabs(im[c])));
+  for (int c = 0; c < 36; ++c) m = fmax(m, fmax(fabs((double)re[c]), fabs((double)im[c])));
   // entries scaled by 2^(14 - e) with m in [2^e, 2^(e+1)) stay below 2^15 (FP16 max 65504)
   int e = 0;
   if (m > 0.0 && isfinite(m)) e = ilogb(m);
@@ -191,8 +191,8 @@ template <> __device__ inline void store_dinv<hfac>(hfac* t, int lane, const dou
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
       const int c = 4 * v + h;
-      const uint16_t a = __builtin_bit_cast(uint16_t, (_Float16)(float)(re[c] * up));
-      const uint16_t b = __builtin_bit_cast(uint16_t, (_Float16)(float)(im[c] * up));
+      const uint16_t a = __builtin_bit_cast(uint16_t, (_Float16)(float)((double)re[c] * up));
+      const uint16_t b = __builtin_bit_cast(uint16_t, (_Float16)(float)((double)im[c] * up));
       w[h] = (uint32_t)a | ((uint32_t)b << 16);
     }
     p[v * kLanes] = make_uint4(w[0], w[1], w[2], w[3]);
@@ -418,29 +418,29 @@ __device__ inline double spectral_radius(const double (&Q)[6], const double (&S)
 // In-place Gauss-Jordan with partial (row) pivoting; row interchanges are undone as
 // column interchanges at the end.  All indexing is static (selects), so the matrix
 // stays in registers.  ok <- false for a zero or non-finite pivot.
-__device__ inline void cinv6(double (&ar)[36], double (&ai)[36], bool& ok) {
+template <typename F> __device__ inline void cinv6(F (&ar)[36], F (&ai)[36], bool& ok) {
   int piv[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    double best = ar[6 * k + k] * ar[6 * k + k] + ai[6 * k + k] * ai[6 * k + k];
+    F best = ar[6 * k + k] * ar[6 * k + k] + ai[6 * k + k] * ai[6 * k + k];
     int p = k;
 #pragma unroll
     for (int i = k + 1; i < 6; ++i) {
-      double m = ar[6 * i + k] * ar[6 * i + k] + ai[6 * i + k] * ai[6 * i + k];
+      F m = ar[6 * i + k] * ar[6 * i + k] + ai[6 * i + k] * ai[6 * i + k];
       if (m > best) {
         best = m;
         p = i;
       }
     }
     piv[k] = p;
-    if (!(best > 0.0) || !isfinite(best)) ok = false;
+    if (!(best > (F)0) || !isfinite(best)) ok = false;
 #pragma unroll
     for (int i = k + 1; i < 6; ++i) {
       const bool sw = (p == i);
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        double tr = ar[6 * k + c], ti = ai[6 * k + c];
-        double vr = ar[6 * i + c], vi = ai[6 * i + c];
+        F tr = ar[6 * k + c], ti = ai[6 * k + c];
+        F vr = ar[6 * i + c], vi = ai[6 * i + c];
         ar[6 * k + c] = sw ? vr : tr;
         ai[6 * k + c] = sw ? vi : ti;
         ar[6 * i + c] = sw ? tr : vr;
@@ -448,13 +448,13 @@ __device__ inline void cinv6(double (&ar)[36], double (&ai)[36], bool& ok) {
       }
     }
     // pivot reciprocal
-    const double pr = ar[6 * k + k], pi = ai[6 * k + k];
-    const double den = pr * pr + pi * pi;
-    const double ivr = pr / den, ivi = -pi / den;
+    const F pr = ar[6 * k + k], pi = ai[6 * k + k];
+    const F den = pr * pr + pi * pi;
+    const F ivr = pr / den, ivi = -pi / den;
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       if (c == k) continue;
-      double r = ar[6 * k + c], i = ai[6 * k + c];
+      F r = ar[6 * k + c], i = ai[6 * k + c];
       ar[6 * k + c] = r * ivr - i * ivi;
       ai[6 * k + c] = r * ivi + i * ivr;
     }
@@ -463,11 +463,11 @@ __device__ inline void cinv6(double (&ar)[36], double (&ai)[36], bool& ok) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
       if (i == k) continue;
-      const double fr = ar[6 * i + k], fi = ai[6 * i + k];
+      const F fr = ar[6 * i + k], fi = ai[6 * i + k];
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         if (c == k) continue;
-        const double br = ar[6 * k + c], bi = ai[6 * k + c];
+        const F br = ar[6 * k + c], bi = ai[6 * k + c];
         ar[6 * i + c] -= fr * br - fi * bi;
         ai[6 * i + c] -= fr * bi + fi * br;
       }
@@ -482,8 +482,8 @@ __device__ inline void cinv6(double (&ar)[36], double (&ai)[36], bool& ok) {
       const bool sw = (piv[k] == i);
 #pragma unroll
       for (int r = 0; r < 6; ++r) {
-        double tr = ar[6 * r + k], ti = ai[6 * r + k];
-        double vr = ar[6 * r + i], vi = ai[6 * r + i];
+        F tr = ar[6 * r + k], ti = ai[6 * r + k];
+        F vr = ar[6 * r + i], vi = ai[6 * r + i];
         ar[6 * r + k] = sw ? vr : tr;
         ai[6 * r + k] = sw ? vi : ti;
         ar[6 * r + i] = sw ? tr : vr;

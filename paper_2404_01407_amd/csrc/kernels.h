@@ -146,16 +146,30 @@ void launch_rb_pass(const SweepCfg& c, bool update, const DevPattern& p, const v
 // textbook forward substitution with the lower colours' y, x += y on the last colour),
 // kFwdHybrid (x updated in place colour by colour, y = Dt^-1 (b - K x), x += y),
 // kFwdNorm (norm partials of b - K x only).  Backward modes: kBwdGeneral, kBwdHybrid
-// (x and y += -Dt^-1 sum_upper K z), kBwdCorrect (x only, over the tiles of tlist).
+// (x and y += -Dt^-1 sum_upper K z).
 enum { kFwdGeneral = 0, kFwdLast = 1, kFwdHybrid = 2, kFwdNorm = 3 };
-enum { kBwdGeneral = 0, kBwdHybrid = 1, kBwdCorrect = 2 };
+enum { kBwdGeneral = 0, kBwdHybrid = 1 };
 void launch_fwd(const SweepCfg& c, int mode, const DevPattern& p, const void* offd, const void* diag,
                 const void* dinv, int64_t dinv_stride, void* x, const void* b, void* y, int ns, const SysBatch& sb,
                 const SysState* st, double* partial, int64_t t0, int64_t nt, int64_t cstart, hipStream_t s);
-// tlist: device list of nt tiles (kBwdCorrect), else tiles t0 .. t0 + nt
 void launch_bwd(const SweepCfg& c, int mode, const DevPattern& p, const void* offd, const void* dinv,
                 int64_t dinv_stride, void* x, void* y, int ns, const SysBatch& sb, const SysState* st, int64_t t0,
-                int64_t nt, int64_t cend, const int32_t* tlist, hipStream_t s);
+                int64_t nt, int64_t cend, hipStream_t s);
+// The second-colour rows coupled to higher colours (two colours plus remainder), packed
+// 64 to a group with their upward couplings: row[g * 64 + lane] (internal row, -1
+// padding), width[g], slot0[g], fe[(slot0[g] + k) * 64 + lane] (flat SELL entry, -1
+// padding, in slot order).
+struct CorrDev {
+  const int32_t* row = nullptr;
+  const int32_t* width = nullptr;
+  const int64_t* slot0 = nullptr;
+  const int32_t* fe = nullptr;
+  int64_t n_groups = 0;
+};
+// x_i += -Dt_i^-1 sum_{k upper} K_ik y_k for those rows (systems not pending)
+void launch_correct(int storage, const DevPattern& p, const CorrDev& q, const void* offd, const void* dinv,
+                    int64_t dinv_stride, void* x, const void* y, int ns, const SysBatch& sb, const SysState* st,
+                    hipStream_t s);
 void launch_jacobi(const SweepCfg& c, const DevPattern& p, const void* offd, const void* diag, const void* dinv,
                    int64_t dinv_stride, const void* x, const void* b, void* y, int ns, const SysBatch& sb,
                    const SysState* st, double* partial, hipStream_t s);

@@ -804,21 +804,19 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
 // already hold z in y):  z_i = y_i - Dt_i^-1 sum_{k upper} K_ik z_k;  x_i += z_i; y_i <- z_i
 // In the two-colours-plus-remainder sweep x already holds x + y (kFwdHybrid), so
 //   kBwdHybrid:  d_i = -Dt_i^-1 sum_{k upper} K_ik z_k;  x_i += d_i;  y_i += d_i (= z_i)
-//   kBwdCorrect: the same x update without z, for the rows of the second colour, over
-//                the tiles listed in tlist (those with a row coupled to a higher colour)
-// and, with no reduction since the update pass, they run for the systems that pass ran.
+// and, with no reduction since the update pass, it runs for the systems that pass ran.
 template <typename TB, int SW, int P, int MODE>
 __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict__ offd,
                                              const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
                                              typename TV_of<TB>::T* __restrict__ x,
                                              typename TV_of<TB>::T* __restrict__ y, int ns, SysBatch sb,
                                              const SysState* __restrict__ st, int64_t t0, int64_t nt, int64_t cend,
-                                             int wave_groups, const int32_t* __restrict__ tlist) {
+                                             int wave_groups) {
   using A = typename TV_of<TB>::T;
   int64_t tile;
   int grp;
   if (!map_tile(nt, wave_groups ? SW : 1, tile, grp)) return;
-  tile = tlist ? (int64_t)tlist[tile] : tile + t0;
+  tile += t0;
   const int lane = threadIdx.x & 63;
   const int w = wave_groups ? grp : (int)(threadIdx.x >> 6);
   const int sidx = lane % SW;
@@ -893,7 +891,7 @@ __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict_
     apply_dinv(dinv + (int64_t)W.ds[j] * dstride + tile * DinvTile<typename DF_of<TB>::T>::N, rl, t[j], z);
     if (valid) {
       A yi[12], xi[12];
-      if (MODE != kBwdCorrect) load_vec(y + rb + W.vs[j] * 12, yi);
+      load_vec(y + rb + W.vs[j] * 12, yi);
       load_vec(x + rb + W.vs[j] * 12, xi);
       if constexpr (MODE == kBwdGeneral) {
 #pragma unroll
@@ -908,9 +906,64 @@ __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict_
           if constexpr (MODE == kBwdHybrid) z[i] += yi[i];
         }
       }
-      if (MODE != kBwdCorrect) store_vec(y + rb + W.vs[j] * 12, z);
+      store_vec(y + rb + W.vs[j] * 12, z);
       store_vec(x + rb + W.vs[j] * 12, xi);
     }
+  }
+}
+
+// The correction of the two-colours-plus-remainder sweep: every second-colour row coupled
+// to a higher colour gets x_i += -Dt_i^-1 sum_{k upper} K_ik z_k (z of the remainder in
+// y), the same update as the backward step without z.  The rows are packed 64 to a group
+// with their upward couplings (flat entries of the SELL layout, in slot order), one wave
+// per group and P systems, so the launch touches only those rows (about one in
+// seventy of the second colour on a three-row sector).
+template <typename TB, int P>
+__global__ void __launch_bounds__(64) k_correct(DevPattern p, CorrDev q, const TB* __restrict__ offd,
+                                                const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
+                                                typename TV_of<TB>::T* __restrict__ x,
+                                                const typename TV_of<TB>::T* __restrict__ y, int ns, SysBatch sb,
+                                                const SysState* __restrict__ st) {
+  using A = typename TV_of<TB>::T;
+  const int64_t g = blockIdx.x;
+  const int lane = threadIdx.x;
+  WaveSys<P> W;
+  if (!wave_systems<P>(sb, st, (int)blockIdx.y, true, W)) return;
+  const int32_t row = q.row[g * kLanes + lane];
+  if (row < 0) return;
+  A t[P][12];
+#pragma unroll
+  for (int j = 0; j < P; ++j)
+#pragma unroll
+    for (int i = 0; i < 12; ++i) t[j][i] = 0;
+  const int wd = q.width[g];
+  const int64_t s0 = q.slot0[g];
+  for (int k = 0; k < wd; ++k) {
+    const int32_t fe = q.fe[(s0 + k) * kLanes + lane];
+    if (fe < 0) break;
+    const int64_t nbo = (int64_t)p.ent_nbr[fe] * ns * 12;
+    A kb[36];
+    load_block(offd + (int64_t)(fe >> 6) * slot_elems<TB>(), fe & 63, kb);
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      if (!W.run[j]) continue;
+      A v[12];
+      load_vec(y + nbo + W.vs[j] * 12, v);
+      if (p.ent_phase) apply_phase(p, fe, W.orow[j], v);
+      sub_kx(t[j], kb, v);
+    }
+  }
+  const int64_t rb = (int64_t)row * ns * 12;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    if (!W.run[j]) continue;
+    A z[12], xi[12];
+    apply_dinv(dinv + (int64_t)W.ds[j] * dstride + (int64_t)(row >> 6) * DinvTile<typename DF_of<TB>::T>::N, row & 63,
+               t[j], z);
+    load_vec(x + rb + W.vs[j] * 12, xi);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) xi[i] += z[i];
+    store_vec(x + rb + W.vs[j] * 12, xi);
   }
 }
 
@@ -1223,25 +1276,63 @@ __global__ void k_get_diag(int64_t N, const int32_t* __restrict__ perm, const TB
 // Colour c, one wave per (tile, system):
 //   Dt_i = K_ii + i w_i I - sum_{k in N(i), col k < c} K_ik Dt_k^-1 K_ki   (DILU)
 //   Dt_i = K_ii + i w_i I                                                (SGS / Jacobi)
-// in FP64 from the stored blocks, inverted by Gauss-Jordan with partial pivoting.
+// inverted by Gauss-Jordan with partial pivoting.  Arithmetic type F: FP64 with FP64
+// blocks; FP32 with FP32/BF16 blocks, whose factor inverses are stored in FP16 (the FP64
+// defect correction makes the factor's precision irrelevant to the converged result).
+// Per lower neighbour k the two blocks are loaded whole, and T = Dt_k^-1 K_ki is formed
+// row by row (one row of Dt_k^-1 per step) and folded into Dt_i as the rank-one update
+// K_ik[:, r] T[r, :].
+template <typename TB> struct Fact_of {
+  using T = float;
+};
+template <> struct Fact_of<double> {
+  using T = double;
+};
+// row r of Dt^-1 (six complex entries) of one lane's factor tile
+template <typename TD, typename F>
+__device__ inline void dinv_row_entries(const TD* __restrict__ t, int lane, int r, F (&dr)[6], F (&di)[6]);
+template <typename F>
+__device__ inline void dinv_row_entries(const double* __restrict__ t, int lane, int r, F (&dr)[6], F (&di)[6]) {
+  const double2* p = reinterpret_cast<const double2*>(t) + lane;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const double2 d = p[(6 * r + c) * kLanes];
+    dr[c] = (F)d.x;
+    di[c] = (F)d.y;
+  }
+}
+template <typename F>
+__device__ inline void dinv_row_entries(const hfac* __restrict__ t, int lane, int r, F (&dr)[6], F (&di)[6]) {
+  const uint4* p = reinterpret_cast<const uint4*>(t) + lane;
+  const int v0 = (6 * r) >> 2;
+  const uint4 d0 = p[v0 * kLanes];
+  const uint4 d1 = p[(v0 + 1) * kLanes];
+  const uint32_t w[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+  const int o = 6 * r - 4 * v0;  // 0 or 2
+  const F sc = (F)reinterpret_cast<const float*>(t + 72 * kLanes)[lane];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const uint32_t q = o ? w[c + 2] : w[c];
+    dr[c] = (F)h2f(q & 0xffffu) * sc;
+    di[c] = (F)h2f(q >> 16) * sc;
+  }
+}
 template <typename TB, typename TD, bool DILU>
 __global__ void __launch_bounds__(64) k_factor(DevPattern p, const TB* __restrict__ offd,
                                                const TB* __restrict__ diag, TD* __restrict__ dinv,
                                                int64_t dstride, SysBatch sb, int64_t t0, int64_t nt, int64_t cstart,
                                                int* __restrict__ err) {
+  using F = typename Fact_of<TB>::T;
   const int64_t tile = t0 + blockIdx.x;
   const int k = blockIdx.y;
   const int lane = threadIdx.x;
   const int64_t row = tile * kLanes + lane;
   const bool valid = lane < p.tile_nrows[tile];
-  double mr[36], mi[36];
-  const TB* dslot = diag + tile * slot_elems<TB>();
+  F mr[36], mi[36];
+  load_block(diag + tile * slot_elems<TB>(), lane, mr);
 #pragma unroll
-  for (int c = 0; c < 36; ++c) {
-    mr[c] = load_entry_f64<TB>(dslot, c, lane);
-    mi[c] = 0.0;
-  }
-  const double wv = shift_w(p, sb.orow[k], row);
+  for (int c = 0; c < 36; ++c) mi[c] = (F)0;
+  const F wv = (F)shift_w(p, sb.orow[k], row);
 #pragma unroll
   for (int c = 0; c < 6; ++c) mi[7 * c] += wv;
   TD* dbase = dinv + (int64_t)sb.dslot[k] * dstride;
@@ -1252,43 +1343,36 @@ __global__ void __launch_bounds__(64) k_factor(DevPattern p, const TB* __restric
       const int64_t fe = (s0 + q) * kLanes + lane;
       const int nb = p.ent_nbr[fe];
       if (p.ent_edge[fe] == 0 || nb >= cstart) continue;
-      const TB* ks = offd + (s0 + q) * slot_elems<TB>();
-      double kij[36];
-#pragma unroll
-      for (int c = 0; c < 36; ++c) kij[c] = load_entry_f64<TB>(ks, c, lane);
+      F kij[36], kji[36];
+      load_block(offd + (s0 + q) * slot_elems<TB>(), lane, kij);
       const int32_t rv = p.ent_rev[fe];
-      const TB* rs = offd + (int64_t)(rv >> 6) * slot_elems<TB>();
-      const int rl = rv & 63;
+      load_block(offd + (int64_t)(rv >> 6) * slot_elems<TB>(), rv & 63, kji);
       const TD* dn = dbase + (int64_t)(nb >> 6) * DinvTile<TD>::N;
       const int nl = nb & 63;
-      for (int c = 0; c < 6; ++c) {
-        double kc[6];
 #pragma unroll
-        for (int q2 = 0; q2 < 6; ++q2) kc[q2] = load_entry_f64<TB>(rs, 6 * q2 + c, rl);
-        double tr[6], ti[6];
+      for (int r = 0; r < 6; ++r) {
+        F dr[6], di[6];
+        dinv_row_entries(dn, nl, r, dr, di);
+        F tr[6], ti[6];  // row r of Dt_k^-1 K_ki
 #pragma unroll
-        for (int r = 0; r < 6; ++r) {
-          double sr = 0.0, si = 0.0;
+        for (int c = 0; c < 6; ++c) {
+          F sr = 0, si = 0;
 #pragma unroll
           for (int q2 = 0; q2 < 6; ++q2) {
-            double dr, di;
-            load_dinv_entry<TD>(dn, nl, 6 * r + q2, dr, di);
-            sr += dr * kc[q2];
-            si += di * kc[q2];
+            sr += dr[q2] * kji[6 * q2 + c];
+            si += di[q2] * kji[6 * q2 + c];
           }
-          tr[r] = sr;
-          ti[r] = si;
+          tr[c] = sr;
+          ti[c] = si;
         }
 #pragma unroll
-        for (int r = 0; r < 6; ++r) {
-          double sr = 0.0, si = 0.0;
+        for (int i = 0; i < 6; ++i) {
+          const F a = kij[6 * i + r];
 #pragma unroll
-          for (int q2 = 0; q2 < 6; ++q2) {
-            sr += kij[6 * r + q2] * tr[q2];
-            si += kij[6 * r + q2] * ti[q2];
+          for (int c = 0; c < 6; ++c) {
+            mr[6 * i + c] -= a * tr[c];
+            mi[6 * i + c] -= a * ti[c];
           }
-          mr[6 * r + c] -= sr;
-          mi[6 * r + c] -= si;
         }
       }
     }
@@ -1298,23 +1382,23 @@ __global__ void __launch_bounds__(64) k_factor(DevPattern p, const TB* __restric
   if (frz) {
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      mr[30 + c] = mi[30 + c] = 0.0;
-      mr[6 * c + 5] = mi[6 * c + 5] = 0.0;
+      mr[30 + c] = mi[30 + c] = (F)0;
+      mr[6 * c + 5] = mi[6 * c + 5] = (F)0;
     }
-    mr[35] = 1.0;
+    mr[35] = (F)1;
   }
   bool ok = true;
   cinv6(mr, mi, ok);
-  if (frz) mr[35] = 0.0;
+  if (frz) mr[35] = (F)0;
   if (valid && !ok) atomicOr(err, 1);
   if (!valid) {
 #pragma unroll
     for (int c = 0; c < 36; ++c) {
-      mr[c] = 0.0;
-      mi[c] = 0.0;
+      mr[c] = (F)0;
+      mi[c] = (F)0;
     }
   }
-  store_dinv<TD>(dbase + tile * DinvTile<TD>::N, lane, mr, mi);
+  store_dinv(dbase + tile * DinvTile<TD>::N, lane, mr, mi);
 }
 
 // ================================================================ partition-local ILU(0)
@@ -1441,7 +1525,7 @@ __global__ void __launch_bounds__(64) k_pilu_factor(DevPattern p, PiluDev q, con
       cinv6(mr, mi, ok);
       if (frz) mr[35] = 0.0;
       if (!ok) atomicOr(err, 1);
-      store_dinv<TD>(dbase + g * DinvTile<TD>::N, ln, mr, mi);
+      store_dinv(dbase + g * DinvTile<TD>::N, ln, mr, mi);
     }
     __syncthreads();
   }
@@ -2260,7 +2344,7 @@ void launch_fwd(const SweepCfg& c, int mode, const DevPattern& p, const void* of
 
 void launch_bwd(const SweepCfg& c, int mode, const DevPattern& p, const void* offd, const void* dinv,
                 int64_t dinv_stride, void* x, void* y, int ns, const SysBatch& sb, const SysState* st, int64_t t0,
-                int64_t nt, int64_t cend, const int32_t* tlist, hipStream_t s) {
+                int64_t nt, int64_t cend, hipStream_t s) {
   if (nt <= 0 || sb.n <= 0) return;
   int SW, P;
   rb_shape(c, sb.n, SW, P);
@@ -2270,13 +2354,11 @@ void launch_bwd(const SweepCfg& c, int mode, const DevPattern& p, const void* of
   const unsigned lds_bytes = (SW == 4) ? (unsigned)(block.x / 64) * lds_chunks_per_wave(c.storage) * 16u : 0u;
 #define FNLH_BWD_ONE(SWV, MD)                                                                                 \
   hipLaunchKernelGGL((k_bwd<TB, SWV, PP, MD>), grid, block, lds_bytes, s, p, (const TB*)offd,                   \
-                     (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (A*)y, ns, sb, st, t0, nt, cend, wg, tlist)
+                     (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (A*)y, ns, sb, st, t0, nt, cend, wg)
 #define FNLH_BWD_LAUNCH(SWV)                                                                                  \
   FNLH_DISPATCH_P(P, {                                                                                        \
     if (mode == kBwdHybrid)                                                                                   \
       FNLH_BWD_ONE(SWV, kBwdHybrid);                                                                          \
-    else if (mode == kBwdCorrect)                                                                             \
-      FNLH_BWD_ONE(SWV, kBwdCorrect);                                                                         \
     else                                                                                                      \
       FNLH_BWD_ONE(SWV, kBwdGeneral);                                                                         \
   })
@@ -2291,6 +2373,20 @@ void launch_bwd(const SweepCfg& c, int mode, const DevPattern& p, const void* of
   });
 #undef FNLH_BWD_LAUNCH
 #undef FNLH_BWD_ONE
+}
+void launch_correct(int storage, const DevPattern& p, const CorrDev& q, const void* offd, const void* dinv,
+                    int64_t dinv_stride, void* x, const void* y, int ns, const SysBatch& sb, const SysState* st,
+                    hipStream_t s) {
+  if (q.n_groups <= 0 || sb.n <= 0) return;
+  const int P = sb.n < 4 ? sb.n : 4;
+  dim3 grid((unsigned)q.n_groups, (unsigned)((sb.n + P - 1) / P));
+  FNLH_DISPATCH_STORE(storage, {
+    using A = typename Fmt<TB>::A;
+    FNLH_DISPATCH_P(P, {
+      hipLaunchKernelGGL((k_correct<TB, PP>), grid, dim3(64), 0, s, p, q, (const TB*)offd,
+                         (const typename DF_of<TB>::T*)dinv, dinv_stride, (A*)x, (const A*)y, ns, sb, st);
+    });
+  });
 }
 
 void launch_jacobi(const SweepCfg& c, const DevPattern& p, const void* offd, const void* diag, const void* dinv,

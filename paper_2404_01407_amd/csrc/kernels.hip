@@ -1855,25 +1855,38 @@ __global__ void __launch_bounds__(256) k_resid_stored(DevPattern p, const TB* __
   if (r && valid) store_vec(r + ro, acc);
 }
 
-__global__ void __launch_bounds__(256) k_resid_mfree(DevPattern p, DevFlow f, const double* __restrict__ x,
-                                                     const double* __restrict__ b, double* __restrict__ r, int ns,
-                                                     SysBatch sb, double* __restrict__ partial, int spw) {
+// The matrix-free FP64 operator: each coupling's Rusanov Jacobian is rebuilt from the
+// FP64 state (the ALU-bound part) once per lane and applied to the P systems the lane
+// carries; one wave per (tile, P systems).
+template <int P>
+__global__ void __launch_bounds__(64) k_resid_mfree(DevPattern p, DevFlow f, const double* __restrict__ x,
+                                                    const double* __restrict__ b, double* __restrict__ r, int ns,
+                                                    SysBatch sb, double* __restrict__ partial) {
   int64_t tile;
   int grp;
-  const int ng = (sb.n + spw - 1) / spw;
+  const int ng = (sb.n + P - 1) / P;
   if (!map_tile(p.n_tiles, ng, tile, grp)) return;
-  const int lane = threadIdx.x & 63;
-  const int k = grp * spw + (int)(threadIdx.x >> 6);
-  if (k >= sb.n) return;
-  const int vs = sb.vslot[k];
+  const int lane = threadIdx.x;
+  int vs[P], orow[P];
+  bool on[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int k = grp * P + j;
+    on[j] = k < sb.n;
+    vs[j] = on[j] ? sb.vslot[k] : 0;
+    orow[j] = on[j] ? sb.orow[k] : 0;
+  }
   const int64_t row = tile * kLanes + lane;
   const bool valid = lane < p.tile_nrows[tile];
-  const int64_t ro = (row * ns + vs) * 12;
   double Qi[6] = {1, 0, 0, 0, 2.5, 0};
   if (valid) load_state(f.state + row * 6, Qi);
-  double acc[12], xi[12];
-  load_vec(b + ro, acc);
-  load_vec(x + ro, xi);
+  double acc[P][12];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc[j][i] = 0.0;
+    if (on[j]) load_vec(b + (row * ns + vs[j]) * 12, acc[j]);
+  }
   double sumS[3] = {0, 0, 0}, lam_sum = 0.0;
   const int w = p.tile_width[tile];
   const int64_t s0 = p.tile_slot0[tile];
@@ -1882,7 +1895,7 @@ __global__ void __launch_bounds__(256) k_resid_mfree(DevPattern p, DevFlow f, co
     const int32_t e = p.ent_edge[fe];
     if (e == 0) continue;
     const int nb = p.ent_nbr[fe];
-    double S[3], Qk[6], Ak[36], v[12];
+    double S[3], Qk[6], Ak[36];
     entry_area(f, e, S);
     load_state(f.state + (int64_t)nb * 6, Qk);
     const double lam = fmax(spectral_radius(Qi, S), spectral_radius(Qk, S));
@@ -1895,9 +1908,14 @@ __global__ void __launch_bounds__(256) k_resid_mfree(DevPattern p, DevFlow f, co
     flux_jacobian(Qk, S, Ak);
 #pragma unroll
     for (int c = 0; c < 36; ++c) Ak[c] = 0.5 * Ak[c] - ((c % 7 == 0) ? 0.5 * lam : 0.0);
-    load_vec(x + ((int64_t)nb * ns + vs) * 12, v);
-    if (p.ent_phase) apply_phase(p, fe, sb.orow[k], v);
-    sub_kx(acc, Ak, v);
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      if (!on[j]) continue;
+      double v[12];
+      load_vec(x + ((int64_t)nb * ns + vs[j]) * 12, v);
+      if (p.ent_phase) apply_phase(p, fe, orow[j], v);
+      sub_kx(acc[j], Ak, v);
+    }
   }
   if (valid) {
     for (int32_t j = f.bf_ptr[row]; j < f.bf_ptr[row + 1]; ++j) {
@@ -1920,11 +1938,21 @@ __global__ void __launch_bounds__(256) k_resid_mfree(DevPattern p, DevFlow f, co
   flux_jacobian(Qi, sumS, Ai);
 #pragma unroll
   for (int c = 0; c < 36; ++c) Ai[c] = f.diag_scale * (0.5 * Ai[c] + ((c % 7 == 0) ? 0.5 * lam_sum : 0.0));
-  sub_diag_shift(acc, Ai, shift_w(p, sb.orow[k], row), xi);
-  mask_frozen(p, sb.orow[k], acc);
-  double n2 = wave_sum(valid ? norm2_12(acc) : 0.0);
-  if (lane == 0) partial[((int64_t)vs * p.n_tiles + tile) * kPartialSlots] = n2;
-  if (r && valid) store_vec(r + ro, acc);
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    double xi[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) xi[i] = 0.0;
+    if (on[j]) {
+      load_vec(x + (row * ns + vs[j]) * 12, xi);
+      sub_diag_shift(acc[j], Ai, shift_w(p, orow[j], row), xi);
+      mask_frozen(p, orow[j], acc[j]);
+    }
+    const double n2 = wave_sum(valid && on[j] ? norm2_12(acc[j]) : 0.0);
+    if (!on[j]) continue;
+    if (lane == 0) partial[((int64_t)vs[j] * p.n_tiles + tile) * kPartialSlots] = n2;
+    if (r && valid) store_vec(r + (row * ns + vs[j]) * 12, acc[j]);
+  }
 }
 
 // ================================================================ nonlinear residual
@@ -2436,9 +2464,13 @@ void launch_resid_stored(int storage, const DevPattern& p, const void* offd, con
 void launch_resid_mfree(const DevPattern& p, const DevFlow& f, const double* x, const double* b, double* r, int ns,
                         const SysBatch& sb, double* partial, hipStream_t s) {
   if (sb.n <= 0) return;
-  const int spw = 4 < sb.n ? 4 : sb.n;
-  dim3 grid = tile_grid(p.n_tiles, ng_of(sb, spw));
-  hipLaunchKernelGGL(k_resid_mfree, grid, dim3(64 * spw), 0, s, p, f, x, b, r, ns, sb, partial, spw);
+  // at most three systems a lane (four would leave one wave per SIMD), spread evenly
+  const int groups = (sb.n + 2) / 3;
+  const int P = (sb.n + groups - 1) / groups;
+  dim3 grid = tile_grid(p.n_tiles, ng_of(sb, P));
+  FNLH_DISPATCH_P(P, {
+    hipLaunchKernelGGL((k_resid_mfree<PP>), grid, dim3(64), 0, s, p, f, x, b, r, ns, sb, partial);
+  });
 }
 
 void launch_to_internal(const DevPattern& p, const int32_t* iperm, const double* user, double* internal, int width,

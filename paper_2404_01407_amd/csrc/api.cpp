@@ -796,10 +796,8 @@ int relax_prepare(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, c
   if ((rc = ensure_slots(c, want_slots))) return rc;
   if ((rc = ensure_dominance(c, s))) return rc;
   DevPattern p = c->pat();
-  for (int j = 0; j < n; ++j) {
-    launch_to_internal(p, (const int32_t*)c->iperm.p, x[j], (double*)c->x64.p, 12, n, j, s);
-    launch_to_internal(p, (const int32_t*)c->iperm.p, b[j], (double*)c->b64.p, 12, n, j, s);
-  }
+  launch_to_internal_n(p, (const int32_t*)c->iperm.p, x, n, (double*)c->x64.p, n, 0, s);
+  launch_to_internal_n(p, (const int32_t*)c->iperm.p, b, n, (double*)c->b64.p, n, 0, s);
   P.path = o->kind == FNLH_JACOBI ? kPathJacobi
            : o->kind == FNLH_PILU ? kPathPilu
                                   : (c->L.n_colours == 2 ? kPathRB : (hybrid_ok(c) ? kPathHybrid : kPathGeneral));
@@ -893,8 +891,7 @@ int relax_finish_launch(fnlh_ctx c, int n, const int32_t* sys, double* const* x,
     launch_reduce(sb, (const double*)c->partial.p, c->L.n_tiles, 0, c->L.n_tiles, 1, fin, kReduceFinal, 0, 0, 0, s);
   }
   DevPattern p = c->pat();
-  for (int j = 0; j < n; ++j)
-    launch_to_user(p, (const int32_t*)c->iperm.p, (const double*)c->x64.p, x[j], 12, n, j, s);
+  launch_to_user_n(p, (const int32_t*)c->iperm.p, (const double*)c->x64.p, x, n, n, 0, s);
   return check_launch(c, "final launch");
 }
 

@@ -248,6 +248,18 @@ void launch_to_internal(const DevPattern& p, const int32_t* iperm, const double*
                         int ns, int vs, hipStream_t s);
 void launch_to_user(const DevPattern& p, const int32_t* iperm, const double* internal, double* user, int width,
                     int ns, int vs, hipStream_t s);
+// n systems' complex vectors (user [N][6], host array of device pointers) <-> internal
+// slots vs0 .. vs0 + n - 1, in launches of up to kMaxBatch systems
+struct VecPtrs {
+  const double* p[kMaxBatch];
+};
+struct VecPtrsOut {
+  double* p[kMaxBatch];
+};
+void launch_to_internal_n(const DevPattern& p, const int32_t* iperm, const double* const* users, int n,
+                          double* internal, int ns, int vs0, hipStream_t s);
+void launch_to_user_n(const DevPattern& p, const int32_t* iperm, const double* internal, double* const* users, int n,
+                      int ns, int vs0, hipStream_t s);
 void launch_to_f32(const DevPattern& p, const double* r64, float* rhs32, float* d32, int ns, const SysBatch& sb,
                    const SysState* outer, hipStream_t s);
 void launch_add_f32(const DevPattern& p, double* x64, const float* d32, int ns, const SysBatch& sb,

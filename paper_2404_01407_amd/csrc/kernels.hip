@@ -2070,6 +2070,29 @@ __global__ void k_to_user(int64_t NP, const int32_t* __restrict__ iperm, const d
   const int32_t u = iperm[row];
   if (u >= 0) user[(int64_t)u * width + c] = internal[(row * ns + vs) * width + c];
 }
+// Several systems' complex vectors at once: item (internal row, system j, component),
+// component fastest, so the interleaved rows [row][ns][12] are written (read) as one
+// stream while each user vector is gathered (scattered) by rows.
+__global__ void k_to_internal_n(int64_t NP, const int32_t* __restrict__ iperm, VecPtrs users,
+                                double* __restrict__ internal, int ns, int vs0, int n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= NP * n * 12) return;
+  const int64_t row = t / (n * 12);
+  const int rem = (int)(t % (n * 12));
+  const int j = rem / 12, c = rem % 12;
+  const int32_t u = iperm[row];
+  internal[(row * ns + vs0 + j) * 12 + c] = u >= 0 ? users.p[j][(int64_t)u * 12 + c] : 0.0;
+}
+__global__ void k_to_user_n(int64_t NP, const int32_t* __restrict__ iperm, const double* __restrict__ internal,
+                            VecPtrsOut users, int ns, int vs0, int n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= NP * n * 12) return;
+  const int64_t row = t / (n * 12);
+  const int rem = (int)(t % (n * 12));
+  const int j = rem / 12, c = rem % 12;
+  const int32_t u = iperm[row];
+  if (u >= 0) users.p[j][(int64_t)u * 12 + c] = internal[(row * ns + vs0 + j) * 12 + c];
+}
 // defect-correction conversions, item (row, system kk of sb, component) with the component
 // fastest, then the system: consecutive lanes touch consecutive entries of the
 // interleaved rows, so each vector is streamed once whatever the number of systems
@@ -2484,6 +2507,28 @@ void launch_to_user(const DevPattern& p, const int32_t* iperm, const double* int
   const int64_t n = p.NP * width;
   hipLaunchKernelGGL(k_to_user, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p.NP, iperm, internal, user,
                      width, ns, vs);
+}
+void launch_to_internal_n(const DevPattern& p, const int32_t* iperm, const double* const* users, int n,
+                          double* internal, int ns, int vs0, hipStream_t s) {
+  for (int j0 = 0; j0 < n; j0 += kMaxBatch) {
+    const int m = n - j0 < kMaxBatch ? n - j0 : kMaxBatch;
+    VecPtrs v;
+    for (int j = 0; j < m; ++j) v.p[j] = users[j0 + j];
+    const int64_t items = p.NP * m * 12;
+    hipLaunchKernelGGL(k_to_internal_n, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s, p.NP, iperm, v,
+                       internal, ns, vs0 + j0, m);
+  }
+}
+void launch_to_user_n(const DevPattern& p, const int32_t* iperm, const double* internal, double* const* users, int n,
+                      int ns, int vs0, hipStream_t s) {
+  for (int j0 = 0; j0 < n; j0 += kMaxBatch) {
+    const int m = n - j0 < kMaxBatch ? n - j0 : kMaxBatch;
+    VecPtrsOut v;
+    for (int j = 0; j < m; ++j) v.p[j] = users[j0 + j];
+    const int64_t items = p.NP * m * 12;
+    hipLaunchKernelGGL(k_to_user_n, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s, p.NP, iperm, internal,
+                       v, ns, vs0 + j0, m);
+  }
 }
 void launch_to_f32(const DevPattern& p, const double* r64, float* rhs32, float* d32, int ns, const SysBatch& sb,
                    const SysState* outer, hipStream_t s) {

@@ -306,7 +306,7 @@ int fnlh_gmres(fnlh_ctx c, int32_t n, const int32_t* sys, double* const* x, cons
       }
     }
   }
-  for (int k = 0; k < n; ++k) launch_to_user(p, (const int32_t*)c->iperm.p, x64, x[k], 12, n, k, s);
+  launch_to_user_n(p, (const int32_t*)c->iperm.p, x64, x, n, n, 0, s);
   if ((rc = check_launch(c, "gmres final"))) return rc;
   HIPC(c, hipEventRecord(e1, s), "event");
   HIPC(c, hipEventSynchronize(e1), "event sync");

@@ -856,6 +856,8 @@ def run_partition_ilu(args):
     import numpy as np
     import torch
     from paper_2404_01407_amd import fnlh, synth
+    if args.calib_copy:
+        calib_copy()
     shape = tuple(args.shape)
     out = []
     for numbering in args.part_numbering:

@@ -6,7 +6,8 @@ between partitions left out) against the oracle: Richardson with the natural-ord
 than a wave and span several 64-position groups, five systems per call (two workgroups
 per partition), frozen-turbulence and phase-lagged systems, converged FP32/BF16 solves
 against the dense dropped system, the residual history, graph replay, FGMRES, the RK
-driver, new partitions, the kernel statistics and the error paths."""
+driver, new partitions, work units and workgroup sizes, single-cell partitions, the kernel
+statistics and the error paths."""
 import numpy as np
 import pytest
 
@@ -310,6 +311,22 @@ def test_pilu_partitions_above_64k_lds(F):
     c.close()
 
 
+def test_pilu_single_cell_partitions(F):
+    """One cell per partition: no in-partition couplings (no packed slots at all), the
+    dropped matrix is block diagonal and one sweep solves it exactly."""
+    m, Q, K = _case("cascade", seed=15)
+    part = np.arange(m.n_cells, dtype=np.int32)[::-1].copy()     # labels in any order
+    c = _ctx(F, m, Q, part)
+    bs = _rhs(m, 90)
+    st, rep, xs = _solve(c, [0, 1, 2], bs, max_sweeps=1, rtol=0.0)
+    for s in range(3):
+        Ds = solve.system_diag(K, m.volume, m.zone, OMEGA[s])
+        xd = np.linalg.solve(Ds, bs[s][..., None])[..., 0]
+        assert relerr(xs[s], xd) <= 1e-12, s
+        assert rep[s]["rel_res"] <= 1e-12
+    c.close()
+
+
 def test_pilu_errors(F):
     m, Q, K = _case("passage", seed=13)
     c = F.Context(m)
@@ -323,4 +340,12 @@ def test_pilu_errors(F):
     c = _ctx(F, big, Qb, synth.rcb_partition(big, 4500), storage="f32")   # 4320 cells: 207 KB of y
     with pytest.raises(F.FnlhError):          # a partition larger than a workgroup's LDS holds
         _solve(c, [0], [synth.rhs(big.n_cells, 1)], max_sweeps=3, rtol=0.0)
+    c.close()
+    # the batched relax takes DILU, SGS and the learned kind only
+    c = _ctx(F, m, Q, synth.rcb_partition(m, 40))
+    B = F.Batch([c])
+    x = to_dev(np.zeros((m.n_cells, 6), complex))
+    with pytest.raises(F.FnlhError):
+        B.relax([[0]], [[x]], [[to_dev(bs[0])]], kind="pilu", max_sweeps=3, rtol=0.0)
+    B.close()
     c.close()

@@ -1531,11 +1531,12 @@ __global__ void __launch_bounds__(64) k_pilu_factor(DevPattern p, PiluDev q, con
   }
 }
 
-// Row r of y = Dinv a (complex 6x6 times complex 6), the factor of one position streamed
-// row by row from its tile.  The products are accumulated with explicit fused
-// multiply-adds in a fixed order, so the result does not depend on how the compiler
-// contracts the kernel it is inlined in (the same for every number of systems a
-// workgroup carries).
+// Row r of y = Dinv a (complex 6x6 times complex 6) for one position's factor, in two
+// steps: load() fetches the row (its address does not depend on the data it multiplies,
+// so a sweep issues it before its other loads), apply() forms the row's product.  The
+// products are accumulated with explicit fused multiply-adds in a fixed order, so the
+// result does not depend on how the compiler contracts the kernel it is inlined in (the
+// same for every number of systems a workgroup carries).
 __device__ inline float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ inline double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 template <typename A> __device__ inline void cmac(A dr, A di, A ar, A ai, A& yr, A& yi) {
@@ -1544,50 +1545,51 @@ template <typename A> __device__ inline void cmac(A dr, A di, A ar, A ai, A& yr,
   yi = fmad(dr, ai, yi);
   yi = fmad(di, ar, yi);
 }
-template <typename TD, typename A>
-__device__ inline void dinv_row(const TD* __restrict__ t, int lane, int r, const A (&a)[12], A& yr, A& yi);
-template <typename A>
-__device__ inline void dinv_row(const double* __restrict__ t, int lane, int r, const A (&a)[12], A& yr, A& yi) {
-  const double2* p = reinterpret_cast<const double2*>(t) + lane;
-  yr = 0;
-  yi = 0;
+template <typename TD> struct DinvRow;
+template <> struct DinvRow<double> {
+  double2 d[6];
+  __device__ inline void load(const double* __restrict__ t, int lane, int r) {
+    const double2* p = reinterpret_cast<const double2*>(t) + lane;
 #pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    const nt_d2 d = ld_stream(p + (6 * r + c) * kLanes);
-    cmac((A)d.x, (A)d.y, a[2 * c], a[2 * c + 1], yr, yi);
+    for (int c = 0; c < 6; ++c) {
+      const nt_d2 v = ld_stream(p + (6 * r + c) * kLanes);
+      d[c] = make_double2(v.x, v.y);
+    }
   }
-}
-template <typename A>
-__device__ inline void dinv_row(const float* __restrict__ t, int lane, int r, const A (&a)[12], A& yr, A& yi) {
-  const float4* p = reinterpret_cast<const float4*>(t) + lane;
-  yr = 0;
-  yi = 0;
+  template <typename A> __device__ inline void apply(const A (&a)[12], A& yr, A& yi) const {
+    yr = 0;
+    yi = 0;
 #pragma unroll
-  for (int h = 0; h < 3; ++h) {
-    const nt_f4 d = ld_stream(p + (3 * r + h) * kLanes);
-    cmac((A)d.x, (A)d.y, a[4 * h], a[4 * h + 1], yr, yi);
-    cmac((A)d.z, (A)d.w, a[4 * h + 2], a[4 * h + 3], yr, yi);
+    for (int c = 0; c < 6; ++c) cmac((A)d[c].x, (A)d[c].y, a[2 * c], a[2 * c + 1], yr, yi);
   }
-}
-template <typename A>
-__device__ inline void dinv_row(const hfac* __restrict__ t, int lane, int r, const A (&a)[12], A& yr, A& yi) {
+};
+template <> struct DinvRow<hfac> {
   // entries 6r .. 6r+5 lie in the 16-byte vectors (6r)/4 and (6r)/4 + 1 (four per vector)
-  const uint4* p = reinterpret_cast<const uint4*>(t) + lane;
-  const int v0 = (6 * r) >> 2;
-  const nt_u4 d0 = ld_stream(p + v0 * kLanes);
-  const nt_u4 d1 = ld_stream(p + (v0 + 1) * kLanes);
-  const uint32_t w[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
-  const int o = 6 * r - 4 * v0;  // 0 or 2
-  const A sc = (A)reinterpret_cast<const float*>(t + 72 * kLanes)[lane];
-  A sr = 0, si = 0;
-#pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    const uint32_t q = o ? w[c + 2] : w[c];
-    cmac((A)h2f(q & 0xffffu), (A)h2f(q >> 16), a[2 * c], a[2 * c + 1], sr, si);
+  uint4 d0, d1;
+  float sc;
+  int o;  // 0 or 2: the row's first entry within d0
+  __device__ inline void load(const hfac* __restrict__ t, int lane, int r) {
+    const uint4* p = reinterpret_cast<const uint4*>(t) + lane;
+    const int v0 = (6 * r) >> 2;
+    const nt_u4 a = ld_stream(p + v0 * kLanes);
+    const nt_u4 b = ld_stream(p + (v0 + 1) * kLanes);
+    d0 = make_uint4(a.x, a.y, a.z, a.w);
+    d1 = make_uint4(b.x, b.y, b.z, b.w);
+    sc = reinterpret_cast<const float*>(t + 72 * kLanes)[lane];
+    o = 6 * r - 4 * v0;
   }
-  yr = sr * sc;
-  yi = si * sc;
-}
+  template <typename A> __device__ inline void apply(const A (&a)[12], A& yr, A& yi) const {
+    const uint32_t w[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+    A sr = 0, si = 0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const uint32_t q = o ? w[c + 2] : w[c];
+      cmac((A)h2f(q & 0xffffu), (A)h2f(q >> 16), a[2 * c], a[2 * c + 1], sr, si);
+    }
+    yr = sr * (A)sc;
+    yi = si * (A)sc;
+  }
+};
 
 // One preconditioned Richardson sweep of each unit for P systems:
 //   forward, levels ascending:   r_i = b_i - (K_ii + i w) x_i - sum_j K_ij x_j   (||r||^2)
@@ -1638,23 +1640,46 @@ __global__ void __launch_bounds__(NT) k_pilu_sweep(DevPattern p, PiluDev q, cons
       for (int j = 0; j < P; ++j)
 #pragma unroll
         for (int i = 0; i < 12; ++i) r[j][i] = t[j][i] = 0;
+      // the lane's rows of the factor solve (rows sl and sl + 4 of each system's factor)
+      DinvRow<TD> fr[P][2];
       if (act) {
         const int64_t row = q.pos_row[qq];
         const int wd = q.g_width[g];
         const int64_t s0 = q.g_slot0[g];
-        // item 0 is the diagonal block, item i > 0 coupling i - 1; lane sl takes sl, sl+4, ..
-        for (int i = sl; i <= wd; i += 4) {
-          int nb = qq, src = -1;
-          int64_t vrow = row;
-          const TB* blk = pdiag + g * slot_elems<TB>();
-          if (i > 0) {
+        // loads in three rounds: the factor rows (their address is the position's), the
+        // indices of items sl and sl + 4 (item 0 the diagonal block, item i > 0 coupling
+        // i - 1) with b, then their blocks and vectors
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          if (!W.run[j]) continue;
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            if (sl + 4 * h < 6) fr[j][h].load(dinv + (int64_t)W.ds[j] * dstride + g * DinvTile<TD>::N, ln, sl + 4 * h);
+        }
+        int nbv[2], srcv[2];
+        int64_t vrowv[2];
+        bool on[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int i = sl + 4 * h;
+          on[h] = i <= wd;
+          nbv[h] = qq;
+          srcv[h] = -1;
+          vrowv[h] = row;
+          if (on[h] && i > 0) {
             const int64_t fe = (s0 + i - 1) * kLanes + ln;
-            nb = q.e_pos[fe];
-            if (nb < 0) break;
-            vrow = q.e_row[fe];
-            src = q.e_src[fe];
-            blk = coup + (s0 + i - 1) * slot_elems<TB>();
+            nbv[h] = q.e_pos[fe];
+            vrowv[h] = q.e_row[fe];
+            srcv[h] = q.e_src[fe];
+            on[h] = nbv[h] >= 0;
           }
+        }
+        A bv[P][12];
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+          if (sl == 0 && W.run[j]) load_vec(b + row * ns * 12 + W.vs[j] * 12, bv[j]);
+        auto item = [&](int i, int nb, int src, int64_t vrow) {
+          const TB* blk = i == 0 ? pdiag + g * slot_elems<TB>() : coup + (s0 + i - 1) * slot_elems<TB>();
           A kb[36];
           load_block(blk, ln, kb);
           const int64_t vo = vrow * ns * 12;
@@ -1678,15 +1703,25 @@ __global__ void __launch_bounds__(NT) k_pilu_sweep(DevPattern p, PiluDev q, cons
               sub_kx(t[j], kb, v);
             }
           }
+        };
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          if (on[h]) item(sl + 4 * h, nbv[h], srcv[h], vrowv[h]);
+        // rows with more than seven couplings (general meshes)
+        if (on[1]) {
+          for (int i = sl + 8; i <= wd; i += 4) {
+            const int64_t fe = (s0 + i - 1) * kLanes + ln;
+            const int nb = q.e_pos[fe];
+            if (nb < 0) break;
+            item(i, nb, q.e_src[fe], q.e_row[fe]);
+          }
         }
         if (sl == 0) {
 #pragma unroll
           for (int j = 0; j < P; ++j) {
             if (!W.run[j]) continue;
-            A bi[12];
-            load_vec(b + row * ns * 12 + W.vs[j] * 12, bi);
 #pragma unroll
-            for (int i = 0; i < 12; ++i) r[j][i] += bi[i];
+            for (int i = 0; i < 12; ++i) r[j][i] += bv[j][i];
           }
         }
       }
@@ -1701,7 +1736,6 @@ __global__ void __launch_bounds__(NT) k_pilu_sweep(DevPattern p, PiluDev q, cons
           t[j][i] += __shfl_xor(t[j][i], 2, kLanes);
         }
       if (act) {
-        const TD* dt = dinv + g * DinvTile<TD>::N;
 #pragma unroll
         for (int j = 0; j < P; ++j) {
           if (!W.run[j]) continue;
@@ -1710,9 +1744,12 @@ __global__ void __launch_bounds__(NT) k_pilu_sweep(DevPattern p, PiluDev q, cons
 #pragma unroll
           for (int i = 0; i < 12; ++i) t[j][i] += r[j][i];
           A* yp = ys + ((int64_t)(qq - q0) * P + j) * 12;
-          for (int rr = sl; rr < 6; rr += 4) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int rr = sl + 4 * h;
+            if (rr >= 6) continue;
             A yr, yi;
-            dinv_row(dt + (int64_t)W.ds[j] * dstride, ln, rr, t[j], yr, yi);
+            fr[j][h].apply(t[j], yr, yi);
             yp[2 * rr] = yr;
             yp[2 * rr + 1] = yi;
           }
@@ -1735,17 +1772,21 @@ __global__ void __launch_bounds__(NT) k_pilu_sweep(DevPattern p, PiluDev q, cons
 #pragma unroll
         for (int i = 0; i < 12; ++i) u[j][i] = 0;
       int any = 0;
+      DinvRow<TD> fr[P][2];
       if (act) {
         const int wd = q.g_width[g];
         const int64_t s0 = q.g_slot0[g];
-        for (int k = sl; k < wd; k += 4) {
-          const int64_t fe = (s0 + k) * kLanes + ln;
-          const int nb = q.e_pos[fe];
-          if (nb < qq) continue;  // lower neighbours and padding (-1)
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          if (!W.run[j]) continue;
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            if (sl + 4 * h < 6) fr[j][h].load(dinv + (int64_t)W.ds[j] * dstride + g * DinvTile<TD>::N, ln, sl + 4 * h);
+        }
+        auto coupling = [&](int k, int nb, int src) {
           any = 1;
           A kb[36];
           load_block(coup + (s0 + k) * slot_elems<TB>(), ln, kb);
-          const int src = q.e_src[fe];
 #pragma unroll
           for (int j = 0; j < P; ++j) {
             if (!W.run[j]) continue;
@@ -1754,6 +1795,27 @@ __global__ void __launch_bounds__(NT) k_pilu_sweep(DevPattern p, PiluDev q, cons
             if (p.ent_phase) apply_phase(p, src, W.orow[j], v);
             sub_kx(u[j], kb, v);
           }
+        };
+        // couplings sl and sl + 4: indices first, then the upper ones' blocks
+        int nbv[2], srcv[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int k = sl + 4 * h;
+          nbv[h] = -1;
+          srcv[h] = 0;
+          if (k < wd) {
+            const int64_t fe = (s0 + k) * kLanes + ln;
+            nbv[h] = q.e_pos[fe];
+            srcv[h] = q.e_src[fe];
+          }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          if (nbv[h] > qq) coupling(sl + 4 * h, nbv[h], srcv[h]);  // upper only (lower and padding skipped)
+        for (int k = sl + 8; k < wd; k += 4) {
+          const int64_t fe = (s0 + k) * kLanes + ln;
+          const int nb = q.e_pos[fe];
+          if (nb > qq) coupling(k, nb, q.e_src[fe]);
         }
       }
       any |= __shfl_xor(any, 1, kLanes);
@@ -1766,14 +1828,16 @@ __global__ void __launch_bounds__(NT) k_pilu_sweep(DevPattern p, PiluDev q, cons
           u[j][i] += __shfl_xor(u[j][i], 2, kLanes);
         }
       if (act && any) {
-        const TD* dt = dinv + g * DinvTile<TD>::N;
 #pragma unroll
         for (int j = 0; j < P; ++j) {
           if (!W.run[j]) continue;
           A* yp = ys + ((int64_t)(qq - q0) * P + j) * 12;
-          for (int rr = sl; rr < 6; rr += 4) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int rr = sl + 4 * h;
+            if (rr >= 6) continue;
             A dr, di;
-            dinv_row(dt + (int64_t)W.ds[j] * dstride, ln, rr, u[j], dr, di);
+            fr[j][h].apply(u[j], dr, di);
             yp[2 * rr] += dr;
             yp[2 * rr + 1] += di;
           }
@@ -2616,16 +2680,10 @@ bool pilu_allow_lds(int storage, int lds) {
   FNLH_DISPATCH_STORE(storage, {
     FNLH_PILU_ATTR(1, 64);
     FNLH_PILU_ATTR(2, 64);
-    FNLH_PILU_ATTR(3, 64);
-    FNLH_PILU_ATTR(4, 64);
     FNLH_PILU_ATTR(1, 128);
     FNLH_PILU_ATTR(2, 128);
-    FNLH_PILU_ATTR(3, 128);
-    FNLH_PILU_ATTR(4, 128);
     FNLH_PILU_ATTR(1, 256);
     FNLH_PILU_ATTR(2, 256);
-    FNLH_PILU_ATTR(3, 256);
-    FNLH_PILU_ATTR(4, 256);
   });
   (void)hipGetLastError();
   return ok;
@@ -2633,7 +2691,9 @@ bool pilu_allow_lds(int storage, int lds) {
 #undef FNLH_PILU_ATTR
 int pilu_threads(int avg_width) { return avg_width <= 16 ? 64 : avg_width <= 32 ? 128 : 256; }
 int pilu_systems_per_group(int storage, int nb, int max_rows, int lds_max) {
-  int P = nb < 4 ? nb : 4;
+  // at most two systems a workgroup: the sweep keeps each lane's factor rows, item
+  // indices and b in registers, and more workgroups hide the level chain's latency
+  int P = nb < 2 ? nb : 2;
   while (P > 0 && (int64_t)max_rows * P * pilu_lds_row_bytes(storage) > lds_max) --P;
   return P;
 }
@@ -2652,14 +2712,23 @@ void launch_pilu_sweep(int storage, const DevPattern& p, const PiluDev& q, const
   const int nt = q.threads;
   FNLH_DISPATCH_STORE(storage, {
     using A = typename Fmt<TB>::A;
-    FNLH_DISPATCH_P(P, {
+    if (P == 1) {
+      constexpr int PP = 1;
       if (nt == 64)
         FNLH_PILU_LAUNCH(64);
       else if (nt == 128)
         FNLH_PILU_LAUNCH(128);
       else
         FNLH_PILU_LAUNCH(256);
-    });
+    } else {
+      constexpr int PP = 2;
+      if (nt == 64)
+        FNLH_PILU_LAUNCH(64);
+      else if (nt == 128)
+        FNLH_PILU_LAUNCH(128);
+      else
+        FNLH_PILU_LAUNCH(256);
+    }
   });
 }
 #undef FNLH_PILU_LAUNCH

@@ -3,7 +3,7 @@ set_partitions factored and swept on its own in the natural cell order, the coup
 between partitions left out) against the oracle: Richardson with the natural-order DILU
 (every cell its own class, in id order) on the partition_dropped matrix.  Iterates (FP64,
 1e-11) on two-colour and general-colouring meshes, partitions whose levels are wider
-than a wave and span several 64-position groups, five systems per call (two workgroups
+than a wave and span several 64-position groups, five systems per call (three workgroups
 per partition), frozen-turbulence and phase-lagged systems, converged FP32/BF16 solves
 against the dense dropped system, the residual history, graph replay, FGMRES, the RK
 driver, new partitions, work units and workgroup sizes, single-cell partitions, the kernel
@@ -100,8 +100,8 @@ def test_pilu_iterates_match_oracle(F, mesh):
 
 def test_pilu_wide_levels_many_groups_five_systems(F):
     """Partitions of up to 600 cells: levels of more than 64 rows (a wave loops over a
-    level), partitions straddling 64-position groups, and five systems (a workgroup takes
-    four, a second one the fifth)."""
+    level), partitions straddling 64-position groups, and five systems (workgroups take
+    two, two and one)."""
     m, Q, K = _case("passage", seed=8, shape=(24, 12, 6))
     part = synth.rcb_partition(m, 600)
     widths = _level_widths(m, part)

@@ -11,6 +11,11 @@ import ctypes as C
 import os
 
 import numpy as np
+# torch before the library: torch carries its own HIP runtime (soname libamdhip64.so.7),
+# and libfnlh, loaded after it, binds to that same runtime.  Loaded the other way round,
+# libfnlh would bring in /opt/rocm's runtime and torch its own beside it, two HIP and
+# HSA runtimes in one process, and the library's hipSetDevice then finds no device.
+import torch  # noqa: E402,F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libfnlh.so")

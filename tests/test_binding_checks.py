@@ -110,3 +110,19 @@ def test_device_index_checked(ctx):
         ctx.residual(0, x, x)
     with pytest.raises(ValueError):
         ctx.relax([0], [x], [x])
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Importing the binding before torch must still leave one HIP runtime in the process
+    (torch's): two runtimes side by side leave the library without a device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import paper_2404_01407_amd.fnlh\nimport torch\n"
+            "print('\\n'.join(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l})))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=600)
+    assert out.returncode == 0, out.stderr[-2000:]
+    libs = out.stdout.split()
+    assert len(libs) == 1, libs
+    assert os.path.realpath(libs[0]).startswith(os.path.realpath(os.path.dirname(torch.__file__))), libs

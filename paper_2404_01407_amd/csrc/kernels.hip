@@ -396,7 +396,18 @@ template <typename TB, int SW, int P, bool UPDATE, bool PH> constexpr bool rb_ld
 constexpr int lds_chunks_per_wave(int storage) {
   return 2 * (kLanes / 4) * (storage == kF64 ? Fmt<double>::NV : storage == kF32 ? Fmt<float>::NV : Fmt<bf16s>::NV);
 }
-template <typename TB> constexpr int lds_chunks_per_wave_t() { return 2 * (kLanes / 4) * Fmt<TB>::NV; }
+// The first-colour pass with FP32 or BF16 blocks parks its diagonal block in a third slot
+// buffer until the elimination that follows the couplings, instead of holding it in 36
+// registers through the coupling loop (the register count sets the waves per SIMD).
+// FP64 keeps it in registers.
+template <typename TB, bool UPDATE> constexpr bool rb_diag_in_lds() { return !UPDATE && !std::is_same<TB, double>::value; }
+template <typename TB, bool UPDATE> constexpr int rb_lds_chunks_t() {
+  return (rb_diag_in_lds<TB, UPDATE>() ? 3 : 2) * (kLanes / 4) * Fmt<TB>::NV;
+}
+constexpr int rb_lds_chunks(int storage, bool update) {
+  return (!update && storage != kF64 ? 3 : 2) * (kLanes / 4) *
+         (storage == kF64 ? Fmt<double>::NV : storage == kF32 ? Fmt<float>::NV : Fmt<bf16s>::NV);
+}
 
 // PH = false: no phase-lagged couplings (p.ent_phase is null); the FP32 four-lanes-per-row
 // passes then stage their blocks through LDS (rb_lds_path).
@@ -442,8 +453,13 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
   const int rowbase = w * (kLanes / SW);
   BlockStage<TB, SW> stg;
   constexpr int SN = BlockStage<TB, SW>::N;
+  constexpr bool kDiagLds = rb_lds_path<TB, SW, P, UPDATE, PH>() && rb_diag_in_lds<TB, UPDATE>();
   A d[36];
-  if constexpr (rb_lds_path<TB, SW, P, UPDATE, PH>()) {
+  if constexpr (kDiagLds) {
+    // read back after the couplings (third slot buffer, untouched by their staging)
+    stg.gload(diag + tile * slot_elems<TB>(), rowbase, lane, KeepAll());
+    stg.lstore(lds + 2 * SN, lane);
+  } else if constexpr (rb_lds_path<TB, SW, P, UPDATE, PH>()) {
     stg.gload(diag + tile * slot_elems<TB>(), rowbase, lane, KeepAll());
     stg.lstore(lds + SN, lane);
     __builtin_amdgcn_wave_barrier();
@@ -499,6 +515,22 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
           A kb[36];
           BlockStage<TB, SW>::lload(lds + (q & 1) * SN, lane / SW, kb);
           if (run[0]) sub_kx(acc[0], kb, xn);
+        } else if constexpr (!std::is_same<TB, double>::value) {
+          // every system's neighbour vector is requested before the block is read back and
+          // before any of them is used: one gather latency per slot, not one per system
+          A xn[P][12];
+#pragma unroll
+          for (int j = 0; j < P; ++j)
+            if (run[j]) load_vec(xr + vs[j] * 12, xn[j]);
+          __builtin_amdgcn_wave_barrier();
+          A kb[36];
+          BlockStage<TB, SW>::lload(lds + (q & 1) * SN, lane / SW, kb);
+#pragma unroll
+          for (int j = 0; j < P; ++j) {
+            if (!run[j]) continue;
+            if (PH && p.ent_phase) apply_phase(p, slot * kLanes + rl, orow[j], xn[j]);
+            sub_kx(acc[j], kb, xn[j]);
+          }
         } else {
           __builtin_amdgcn_wave_barrier();
           A kb[36];
@@ -521,6 +553,10 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
     } else {
       for (int q = 0; q < wd; ++q) body(q);
     }
+  }
+  if constexpr (kDiagLds) {
+    __builtin_amdgcn_wave_barrier();
+    BlockStage<TB, SW>::lload(lds + 2 * SN, lane / SW, d);
   }
 #pragma unroll
   for (int j = 0; j < P; ++j) {
@@ -585,7 +621,7 @@ __global__ void __launch_bounds__(256) k_rb_pass(DevPattern p, const TB* __restr
   uint4* lds = nullptr;
   if constexpr (rb_lds_path<TB, SW, P, UPDATE, PH>()) {
     extern __shared__ uint4 rb_lds[];
-    lds = rb_lds + (threadIdx.x >> 6) * lds_chunks_per_wave_t<TB>();
+    lds = rb_lds + (threadIdx.x >> 6) * rb_lds_chunks_t<TB, UPDATE>();
   }
   rb_tile<TB, SW, P, UPDATE, PIVOT, PH>(p, offd, diag, dinv, dstride, x, b, ns, sb, st, partial, t0 + tile, w, lds);
 }
@@ -627,7 +663,7 @@ __global__ void __launch_bounds__(256) k_rb_batched(const InstDesc* __restrict__
   uint4* lds = nullptr;
   if constexpr (rb_lds_path<TB, SW, P, UPDATE, true>()) {
     extern __shared__ uint4 rbb_lds[];
-    lds = rbb_lds + (threadIdx.x >> 6) * lds_chunks_per_wave_t<TB>();
+    lds = rbb_lds + (threadIdx.x >> 6) * rb_lds_chunks_t<TB, UPDATE>();
   }
   if (!UPDATE && !pivot)
     rb_tile<TB, SW, P, UPDATE, false>(D.p, (const TB*)D.offd, (const TB*)D.diag, (const typename DF_of<TB>::T*)D.dinv, D.dstride,
@@ -2345,7 +2381,7 @@ void launch_rb_pass(const SweepCfg& c, bool update, const DevPattern& p, const v
   // LDS of the staged update pass (other instantiations do not touch it)
   const bool ph = p.ent_phase != nullptr;
   const unsigned lds_bytes = (SW == 4)
-                                 ? (unsigned)(block.x / 64) * lds_chunks_per_wave(c.storage) * 16u
+                                 ? (unsigned)(block.x / 64) * rb_lds_chunks(c.storage, update) * 16u
                                  : 0u;
 #define FNLH_RB_LAUNCH(SWV)                                                                                     \
   FNLH_DISPATCH_P(P, {                                                                                          \
@@ -2390,7 +2426,7 @@ void launch_rb_batched(int storage, int SW, int P, bool update, const InstDesc* 
   grid.x += (unsigned)n_red;
   dim3 block(wg ? 64 : 64 * SW);
   const unsigned lds_bytes =
-      (SW == 4) ? (unsigned)(block.x / 64) * lds_chunks_per_wave(storage) * 16u : 0u;
+      (SW == 4) ? (unsigned)(block.x / 64) * rb_lds_chunks(storage, update) * 16u : 0u;
   const double rtol2 = rtol * rtol, div2 = div_factor * div_factor;
 #define FNLH_RBB_LAUNCH(SWV)                                                                                   \
   FNLH_DISPATCH_P(P, {                                                                                         \

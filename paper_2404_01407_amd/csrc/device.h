@@ -237,32 +237,44 @@ __device__ inline void apply_dinv(const float* __restrict__ t, int lane, const A
   }
 }
 __device__ inline float h2f(uint32_t bits) { return (float)__builtin_bit_cast(_Float16, (uint16_t)bits); }
+// A row's FP16 D~^-1 held in registers: load() issues the reads, apply() uses them, so a
+// caller can have the next row's (or system's) factor in flight while it works.
+struct HfacInv {
+  uint32_t w[36];  // complex entry (r, c) at 6r + c: low half re, high half im
+  float sc;
+  __device__ inline void load(const hfac* __restrict__ t, int lane) {
+    const uint4* p = reinterpret_cast<const uint4*>(t) + lane;
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+      const nt_u4 d = ld_stream(p + v * kLanes);
+      w[4 * v] = d.x;
+      w[4 * v + 1] = d.y;
+      w[4 * v + 2] = d.z;
+      w[4 * v + 3] = d.w;
+    }
+    sc = reinterpret_cast<const float*>(t + 72 * kLanes)[lane];
+  }
+  template <typename A> __device__ inline void apply(const A (&a)[12], A (&y)[12]) const {
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      A yr = 0, yi = 0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const uint32_t q = w[6 * r + c];
+        const A dr = (A)h2f(q & 0xffffu), di = (A)h2f(q >> 16);
+        yr += dr * a[2 * c] - di * a[2 * c + 1];
+        yi += dr * a[2 * c + 1] + di * a[2 * c];
+      }
+      y[2 * r] = yr * (A)sc;
+      y[2 * r + 1] = yi * (A)sc;
+    }
+  }
+};
 template <typename A>
 __device__ inline void apply_dinv(const hfac* __restrict__ t, int lane, const A (&a)[12], A (&y)[12]) {
-  const uint4* p = reinterpret_cast<const uint4*>(t) + lane;
-  uint32_t w[36];
-#pragma unroll
-  for (int v = 0; v < 9; ++v) {
-    const nt_u4 d = ld_stream(p + v * kLanes);
-    w[4 * v] = d.x;
-    w[4 * v + 1] = d.y;
-    w[4 * v + 2] = d.z;
-    w[4 * v + 3] = d.w;
-  }
-  const A sc = (A)reinterpret_cast<const float*>(t + 72 * kLanes)[lane];
-#pragma unroll
-  for (int r = 0; r < 6; ++r) {
-    A yr = 0, yi = 0;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      const uint32_t q = w[6 * r + c];  // complex entry (r, c): low half re, high half im
-      const A dr = (A)h2f(q & 0xffffu), di = (A)h2f(q >> 16);
-      yr += dr * a[2 * c] - di * a[2 * c + 1];
-      yi += dr * a[2 * c + 1] + di * a[2 * c];
-    }
-    y[2 * r] = yr * sc;
-    y[2 * r + 1] = yi * sc;
-  }
+  HfacInv f;
+  f.load(t, lane);
+  f.apply(a, y);
 }
 
 template <typename TD> __device__ inline void load_dinv_entry(const TD* t, int lane, int c, double& re, double& im);

@@ -558,6 +558,36 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
     __builtin_amdgcn_wave_barrier();
     BlockStage<TB, SW>::lload(lds + 2 * SN, lane / SW, d);
   }
+  if constexpr (UPDATE && !std::is_same<TB, double>::value) {
+    // FP16 factor inverses: system j + 1's factor row is requested before system j's
+    // norm reduction and update, so its latency overlaps j's work; j's own x is requested
+    // before j's factor solve
+    HfacInv f[2];
+    auto request = [&](int j) {
+      if (run[j]) f[j & 1].load(dinv + (int64_t)ds[j] * dstride + tile * DinvTile<hfac>::N, rl);
+    };
+    request(0);
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      double n2 = (valid && run[j]) ? norm2_12(acc[j]) : 0.0;
+#pragma unroll
+      for (int o = 32; o >= SW; o >>= 1) n2 += __shfl_xor(n2, o, 64);
+      if (lane < SW && j * SW + lane < sb.n && run[j])
+        partial[((int64_t)vs[j] * p.n_tiles + tile) * kPartialSlots + w] = n2;
+      if (j + 1 < P) request(j + 1);
+      if (!run[j]) continue;
+      A xo[12];
+      if (valid) load_vec(x + rb + vs[j] * 12, xo);
+      A y[12];
+      f[j & 1].apply(acc[j], y);
+      if (valid) {
+#pragma unroll
+        for (int i = 0; i < 12; ++i) y[i] += xo[i];
+        store_vec(x + rb + vs[j] * 12, y);
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     if (UPDATE) {
@@ -588,14 +618,13 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
 }
 
 
+
 template <typename TB, int SW, int P, bool UPDATE, bool PIVOT, bool PH>
-__global__ void __launch_bounds__(256) k_rb_pass(DevPattern p, const TB* __restrict__ offd,
-                                                 const TB* __restrict__ diag,
-                                                 const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride,
-                                                 typename TV_of<TB>::T* __restrict__ x,
-                                                 const typename TV_of<TB>::T* __restrict__ b, int ns, SysBatch sb,
-                                                 SysState* st, double* __restrict__ partial,
-                                                 int64_t t0, int64_t nt, int wave_groups, FusedReduce fr) {
+__global__ void __launch_bounds__(256)
+k_rb_pass(DevPattern p, const TB* __restrict__ offd, const TB* __restrict__ diag,
+          const typename DF_of<TB>::T* __restrict__ dinv, int64_t dstride, typename TV_of<TB>::T* __restrict__ x,
+          const typename TV_of<TB>::T* __restrict__ b, int ns, SysBatch sb, SysState* st,
+          double* __restrict__ partial, int64_t t0, int64_t nt, int wave_groups, FusedReduce fr) {
   // first-colour pass: the first fr.n workgroups reduce the preceding update pass's norms
   // (one system each) while the others sweep.  The sweeping workgroups read each
   // system's `active` flag while a reducing workgroup may be rewriting that state: a

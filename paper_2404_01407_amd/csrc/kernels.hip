@@ -449,6 +449,15 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
     for (int i = 0; i < 12; ++i) acc[j][i] = 0;
     if (run[j]) load_vec(b + rb + vs[j] * 12, acc[j]);
   }
+  // update pass, FP32/BF16: every system's own x is requested together, before the
+  // diagonal block is staged (one latency for all of them)
+  constexpr bool kXFirst = UPDATE && !std::is_same<TB, double>::value;
+  A xo[kXFirst ? P : 1][12];
+  if constexpr (kXFirst) {
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+      if (run[j]) load_vec(x + rb + vs[j] * 12, xo[j]);
+  }
   // LDS staging of the blocks (rb_lds_path): see BlockStage
   const int rowbase = w * (kLanes / SW);
   BlockStage<TB, SW> stg;
@@ -468,7 +477,11 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
   } else {
     load_block(diag + tile * slot_elems<TB>(), rl, d);
   }
-  if (UPDATE) {
+  if constexpr (kXFirst) {
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+      if (run[j]) sub_diag_shift(acc[j], d, (A)shift_w(p, orow[j], row), xo[j]);
+  } else if (UPDATE) {
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       if (!run[j]) continue;
@@ -764,8 +777,28 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
   const bool valid = rl < p.tile_nrows[tile];
   const int64_t rb = row * ns * 12;
   constexpr bool kLowerY = MODE == kFwdGeneral || MODE == kFwdLast;
+  // FP32/BF16 blocks: each step's loads for all of a lane's systems are requested
+  // before any of them is used (one latency per step, not one per system)
+  constexpr bool kBatch = !std::is_same<TB, double>::value;
   A r[P][12], t[P][kLowerY ? 12 : 1];
-  {
+  if constexpr (kBatch) {
+    A xi[P][12];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+#pragma unroll
+      for (int i = 0; i < 12; ++i) r[j][i] = 0;
+#pragma unroll
+      for (int i = 0; i < (kLowerY ? 12 : 1); ++i) t[j][i] = 0;
+      if (!W.run[j]) continue;
+      load_vec(b + rb + W.vs[j] * 12, r[j]);
+      load_vec(x + rb + W.vs[j] * 12, xi[j]);
+    }
+    A d[36];
+    load_block(diag + tile * slot_elems<TB>(), rl, d);
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+      if (W.run[j]) sub_diag_shift(r[j], d, (A)shift_w(p, W.orow[j], row), xi[j]);
+  } else {
     A d[36];
     load_block(diag + tile * slot_elems<TB>(), rl, d);
 #pragma unroll
@@ -786,6 +819,32 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
   auto body = [&](int64_t slot, int nb, const A(&kb)[36]) {
     const int64_t nbo = (int64_t)nb * ns * 12;
     const bool lower = nb < cstart;
+    if constexpr (kBatch) {
+      A v[P][12];
+#pragma unroll
+      for (int j = 0; j < P; ++j)
+        if (W.run[j]) load_vec(x + nbo + W.vs[j] * 12, v[j]);
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        if (!W.run[j]) continue;
+        if (p.ent_phase) apply_phase(p, slot * kLanes + rl, W.orow[j], v[j]);
+        sub_kx(r[j], kb, v[j]);
+      }
+      if constexpr (kLowerY) {
+        if (lower) {
+#pragma unroll
+          for (int j = 0; j < P; ++j)
+            if (W.run[j]) load_vec(y + nbo + W.vs[j] * 12, v[j]);
+#pragma unroll
+          for (int j = 0; j < P; ++j) {
+            if (!W.run[j]) continue;
+            if (p.ent_phase) apply_phase(p, slot * kLanes + rl, W.orow[j], v[j]);
+            sub_kx(t[j], kb, v[j]);
+          }
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       if (!W.run[j]) continue;
@@ -832,6 +891,47 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
       load_block(offd + slot * slot_elems<TB>(), rl, kb);
       body(slot, nb, kb);
     }
+  }
+  if constexpr (kBatch && MODE != kFwdNorm) {
+    // system j + 1's factor row is requested before system j's reduction and solve
+    HfacInv f[2];
+    auto request = [&](int j) {
+      if (W.run[j]) f[j & 1].load(dinv + (int64_t)W.ds[j] * dstride + tile * DinvTile<hfac>::N, rl);
+    };
+    request(0);
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      if (W.run[j]) mask_frozen(p, W.orow[j], r[j]);
+      if constexpr (MODE != kFwdHybrid) {
+        double n2 = (valid && W.run[j]) ? norm2_12(r[j]) : 0.0;
+#pragma unroll
+        for (int o = 32; o >= SW; o >>= 1) n2 += __shfl_xor(n2, o, 64);
+        if (lane < SW && j * SW + lane < sb.n && W.run[j])
+          partial[((int64_t)W.vs[j] * p.n_tiles + tile) * kPartialSlots + w] = n2;
+      }
+      if (j + 1 < P) request(j + 1);
+      if (!W.run[j]) continue;
+      constexpr bool kAddX = MODE == kFwdLast || MODE == kFwdHybrid;
+      A xi[12];
+      if (kAddX && valid) load_vec(x + rb + W.vs[j] * 12, xi);
+      A yi[12];
+      if constexpr (kLowerY) {
+#pragma unroll
+        for (int i = 0; i < 12; ++i) t[j][i] += r[j][i];
+        f[j & 1].apply(t[j], yi);
+      } else {
+        f[j & 1].apply(r[j], yi);
+      }
+      if (valid) {
+        store_vec(y + rb + W.vs[j] * 12, yi);
+        if (kAddX) {
+#pragma unroll
+          for (int i = 0; i < 12; ++i) xi[i] += yi[i];
+          store_vec(x + rb + W.vs[j] * 12, xi);
+        }
+      }
+    }
+    return;
   }
 #pragma unroll
   for (int j = 0; j < P; ++j) {
@@ -899,8 +999,24 @@ __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict_
     for (int i = 0; i < 12; ++i) t[j][i] = 0;
   const int wd = p.tile_width[tile];
   const int64_t s0 = p.tile_slot0[tile];
+  // FP32/BF16 blocks: each step's loads for all of a lane's systems are requested
+  // before any of them is used (one latency per step, not one per system)
+  constexpr bool kBatch = !std::is_same<TB, double>::value;
   auto body = [&](int64_t slot, int nb, const A(&kb)[36]) {
     const int64_t nbo = (int64_t)nb * ns * 12;
+    if constexpr (kBatch) {
+      A v[P][12];
+#pragma unroll
+      for (int j = 0; j < P; ++j)
+        if (W.run[j]) load_vec(y + nbo + W.vs[j] * 12, v[j]);
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        if (!W.run[j]) continue;
+        if (p.ent_phase) apply_phase(p, slot * kLanes + rl, W.orow[j], v[j]);
+        sub_kx(t[j], kb, v[j]);
+      }
+      return;
+    }
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       if (!W.run[j]) continue;
@@ -949,15 +1065,26 @@ __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict_
       }
     }
   }
+  HfacInv f[kBatch ? 2 : 1];
+  auto request = [&](int j) {
+    if constexpr (kBatch)
+      if (W.run[j]) f[j & 1].load(dinv + (int64_t)W.ds[j] * dstride + tile * DinvTile<hfac>::N, rl);
+  };
+  request(0);
 #pragma unroll
   for (int j = 0; j < P; ++j) {
+    if (j + 1 < P) request(j + 1);  // the next system's factor row while this one is solved
     if (!W.run[j]) continue;
-    A z[12];
-    apply_dinv(dinv + (int64_t)W.ds[j] * dstride + tile * DinvTile<typename DF_of<TB>::T>::N, rl, t[j], z);
+    A z[12], yi[12], xi[12];
     if (valid) {
-      A yi[12], xi[12];
       load_vec(y + rb + W.vs[j] * 12, yi);
       load_vec(x + rb + W.vs[j] * 12, xi);
+    }
+    if constexpr (kBatch)
+      f[j & 1].apply(t[j], z);
+    else
+      apply_dinv(dinv + (int64_t)W.ds[j] * dstride + tile * DinvTile<typename DF_of<TB>::T>::N, rl, t[j], z);
+    if (valid) {
       if constexpr (MODE == kBwdGeneral) {
 #pragma unroll
         for (int i = 0; i < 12; ++i) {
@@ -1007,15 +1134,18 @@ __global__ void __launch_bounds__(64) k_correct(DevPattern p, CorrDev q, const T
     const int32_t fe = q.fe[(s0 + k) * kLanes + lane];
     if (fe < 0) break;
     const int64_t nbo = (int64_t)p.ent_nbr[fe] * ns * 12;
+    // every system's z of this neighbour is requested before any is used
+    A v[P][12];
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+      if (W.run[j]) load_vec(y + nbo + W.vs[j] * 12, v[j]);
     A kb[36];
     load_block(offd + (int64_t)(fe >> 6) * slot_elems<TB>(), fe & 63, kb);
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       if (!W.run[j]) continue;
-      A v[12];
-      load_vec(y + nbo + W.vs[j] * 12, v);
-      if (p.ent_phase) apply_phase(p, fe, W.orow[j], v);
-      sub_kx(t[j], kb, v);
+      if (p.ent_phase) apply_phase(p, fe, W.orow[j], v[j]);
+      sub_kx(t[j], kb, v[j]);
     }
   }
   const int64_t rb = (int64_t)row * ns * 12;
@@ -1023,9 +1153,9 @@ __global__ void __launch_bounds__(64) k_correct(DevPattern p, CorrDev q, const T
   for (int j = 0; j < P; ++j) {
     if (!W.run[j]) continue;
     A z[12], xi[12];
+    load_vec(x + rb + W.vs[j] * 12, xi);
     apply_dinv(dinv + (int64_t)W.ds[j] * dstride + (int64_t)(row >> 6) * DinvTile<typename DF_of<TB>::T>::N, row & 63,
                t[j], z);
-    load_vec(x + rb + W.vs[j] * 12, xi);
 #pragma unroll
     for (int i = 0; i < 12; ++i) xi[i] += z[i];
     store_vec(x + rb + W.vs[j] * 12, xi);

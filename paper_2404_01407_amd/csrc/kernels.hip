@@ -1518,8 +1518,12 @@ __global__ void __launch_bounds__(64) k_factor(DevPattern p, const TB* __restric
                                                int64_t dstride, SysBatch sb, int64_t t0, int64_t nt, int64_t cstart,
                                                int* __restrict__ err) {
   using F = typename Fact_of<TB>::T;
-  const int64_t tile = t0 + blockIdx.x;
-  const int k = blockIdx.y;
+  // the systems of one tile are adjacent in dispatch order on one XCD, so the tile's
+  // coupling blocks, read by every system, come from that XCD's L2 after the first
+  int64_t tile;
+  int k;
+  if (!map_tile(nt, sb.n, tile, k)) return;
+  tile += t0;
   const int lane = threadIdx.x;
   const int64_t row = tile * kLanes + lane;
   const bool valid = lane < p.tile_nrows[tile];
@@ -2461,7 +2465,7 @@ void launch_factor(int storage, bool dilu, const DevPattern& p, const void* offd
                    int64_t dinv_stride, const SysBatch& sb, int64_t t0, int64_t nt, int64_t cstart, int* err,
                    hipStream_t s) {
   if (nt <= 0 || sb.n <= 0) return;
-  dim3 grid((unsigned)nt, (unsigned)sb.n);
+  const dim3 grid = tile_grid(nt, sb.n);
   FNLH_DISPATCH_STORE(storage, {
     using TD = typename DF_of<TB>::T;
     if (dilu)

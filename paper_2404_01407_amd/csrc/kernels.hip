@@ -514,10 +514,15 @@ __device__ inline void rb_tile(const DevPattern& p, const TB* __restrict__ offd,
         stg.gload(offd + s0 * slot_elems<TB>(), rowbase, lane, KeepAll());
         stg.lstore(lds, lane);
       }
+      // the neighbour index of slot q + 1 is requested while slot q is applied
+      int nb_next = wd > 0 ? p.ent_nbr[s0 * kLanes + rl] : 0;
       for (int q = 0; q < wd; ++q) {
-        if (q + 1 < wd) stg.gload(offd + (s0 + q + 1) * slot_elems<TB>(), rowbase, lane, KeepAll());
+        const int nb = nb_next;
+        if (q + 1 < wd) {
+          stg.gload(offd + (s0 + q + 1) * slot_elems<TB>(), rowbase, lane, KeepAll());
+          nb_next = p.ent_nbr[(s0 + q + 1) * kLanes + rl];
+        }
         const int64_t slot = s0 + q;
-        const int nb = p.ent_nbr[slot * kLanes + rl];
         const A* xr = x + (int64_t)nb * ns * 12;
         if constexpr (P == 1) {
           // one system: its neighbour vector is fetched before the block is read back
@@ -872,10 +877,14 @@ __global__ void __launch_bounds__(256) k_fwd(DevPattern p, const TB* __restrict_
       stg.gload(offd + s0 * slot_elems<TB>(), rowbase, lane, KeepAll());
       stg.lstore(lds, lane);
     }
+    int nb_next = wd > 0 ? p.ent_nbr[s0 * kLanes + rl] : 0;  // one slot ahead
     for (int q = 0; q < wd; ++q) {
-      if (q + 1 < wd) stg.gload(offd + (s0 + q + 1) * slot_elems<TB>(), rowbase, lane, KeepAll());
+      const int nb = nb_next;
+      if (q + 1 < wd) {
+        stg.gload(offd + (s0 + q + 1) * slot_elems<TB>(), rowbase, lane, KeepAll());
+        nb_next = p.ent_nbr[(s0 + q + 1) * kLanes + rl];
+      }
       const int64_t slot = s0 + q;
-      const int nb = p.ent_nbr[slot * kLanes + rl];
       __builtin_amdgcn_wave_barrier();
       A kb[36];
       BlockStage<TB, SW>::lload(lds + (q & 1) * SN, lane / SW, kb);
@@ -1041,10 +1050,14 @@ __global__ void __launch_bounds__(256) k_bwd(DevPattern p, const TB* __restrict_
       stg.gload(offd + s0 * slot_elems<TB>(), rowbase, lane, upper(s0));
       stg.lstore(lds, lane);
     }
+    int nb_next = wd > 0 ? p.ent_nbr[s0 * kLanes + rl] : 0;  // one slot ahead
     for (int q = 0; q < wd; ++q) {
-      if (q + 1 < wd) stg.gload(offd + (s0 + q + 1) * slot_elems<TB>(), rowbase, lane, upper(s0 + q + 1));
+      const int nb = nb_next;
+      if (q + 1 < wd) {
+        stg.gload(offd + (s0 + q + 1) * slot_elems<TB>(), rowbase, lane, upper(s0 + q + 1));
+        nb_next = p.ent_nbr[(s0 + q + 1) * kLanes + rl];
+      }
       const int64_t slot = s0 + q;
-      const int nb = p.ent_nbr[slot * kLanes + rl];
       __builtin_amdgcn_wave_barrier();
       if (nb >= cend) {
         A kb[36];
@@ -1130,22 +1143,36 @@ __global__ void __launch_bounds__(64) k_correct(DevPattern p, CorrDev q, const T
     for (int i = 0; i < 12; ++i) t[j][i] = 0;
   const int wd = q.width[g];
   const int64_t s0 = q.slot0[g];
-  for (int k = 0; k < wd; ++k) {
-    const int32_t fe = q.fe[(s0 + k) * kLanes + lane];
-    if (fe < 0) break;
-    const int64_t nbo = (int64_t)p.ent_nbr[fe] * ns * 12;
-    // every system's z of this neighbour is requested before any is used
-    A v[P][12];
+  // The latency chain of a wave is the launch time (a few hundred waves): the entry and
+  // neighbour indices of up to eight couplings are requested in two rounds, then each
+  // coupling's block and its neighbour's z for every system in one.
+  constexpr int kIdx = 8;
+  bool more = true;
+  for (int k0 = 0; k0 < wd && more; k0 += kIdx) {
+    int32_t fe[kIdx], nb[kIdx];
 #pragma unroll
-    for (int j = 0; j < P; ++j)
-      if (W.run[j]) load_vec(y + nbo + W.vs[j] * 12, v[j]);
-    A kb[36];
-    load_block(offd + (int64_t)(fe >> 6) * slot_elems<TB>(), fe & 63, kb);
+    for (int u = 0; u < kIdx; ++u) fe[u] = k0 + u < wd ? q.fe[(s0 + k0 + u) * kLanes + lane] : -1;
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-      if (!W.run[j]) continue;
-      if (p.ent_phase) apply_phase(p, fe, W.orow[j], v[j]);
-      sub_kx(t[j], kb, v[j]);
+    for (int u = 0; u < kIdx; ++u) nb[u] = fe[u] >= 0 ? p.ent_nbr[fe[u]] : 0;
+#pragma unroll
+    for (int u = 0; u < kIdx; ++u) {
+      if (fe[u] < 0) {
+        more = false;
+        break;
+      }
+      const int64_t nbo = (int64_t)nb[u] * ns * 12;
+      A v[P][12];
+#pragma unroll
+      for (int j = 0; j < P; ++j)
+        if (W.run[j]) load_vec(y + nbo + W.vs[j] * 12, v[j]);
+      A kb[36];
+      load_block(offd + (int64_t)(fe[u] >> 6) * slot_elems<TB>(), fe[u] & 63, kb);
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        if (!W.run[j]) continue;
+        if (p.ent_phase) apply_phase(p, fe[u], W.orow[j], v[j]);
+        sub_kx(t[j], kb, v[j]);
+      }
     }
   }
   const int64_t rb = (int64_t)row * ns * 12;

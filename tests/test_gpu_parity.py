@@ -515,6 +515,35 @@ def test_wave_groups_bitwise(F, n_sys):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("mesh,hybrid", [("hex", 1), ("three_row", 1), ("three_row", 0)])
+def test_reduced_precision_three_systems_a_lane(F, storage, mesh, hybrid):
+    """Eleven systems in one call (four lanes a row, three systems a lane: the passes that
+    request every system's loads together and the next system's FP16 factor ahead) give
+    each system the iterates it gets when swept alone (one system a lane), to FP32
+    rounding; on the two-colour passes, the two-colour plus remainder passes and the
+    general passes."""
+    n = 11
+    if mesh == "hex":
+        m, Q, K = case(shape=(9, 6, 5), seed=8)
+        om = synth.omegas_single_zone(n - 1)
+    else:
+        m = synth.multi_row(4, 4, 3, n_blades=(36, 60, 48), seed=5)
+        Q = synth.flow_state(m, 5)
+        om = synth.omegas_multi_row(n - 1, (36, 60, 48))
+    bs = [synth.rhs(m.n_cells, s, real=(s == 0)) for s in range(n)]
+    c = _ctx(F, m, Q, storage=storage)
+    c.set_harmonics(om)
+    c.tune(hybrid=hybrid)
+    st, rep, xs = _solve(c, list(range(n)), bs, kind="dilu", max_sweeps=12, rtol=0.0)
+    assert all(r["sweeps"] == 12 for r in rep)
+    for s in (0, 3, 7, 10):
+        _, rep1, x1 = _solve(c, [s], [bs[s]], kind="dilu", max_sweeps=12, rtol=0.0)
+        assert rep1[0]["sweeps"] == 12
+        assert relerr(xs[s], x1[0]) <= 1e-5, (s, relerr(xs[s], x1[0]))
+    c.close()
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
 def test_hybrid_matches_general_passes(F, storage):
     """The two-colour plus remainder sweep computes the general passes' DILU step: on a

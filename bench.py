@@ -1108,6 +1108,17 @@ def batch_measure(args, ckpt=None, steps=None, warmup=1, training=None):
     print(f"[bench] batched: {1e3 * tb:.1f} ms per step", file=sys.stderr, flush=True)
     tl, reps_l = timeit(loop, max(1, steps // 2), 1)
     print(f"[bench] per-instance loop: {1e3 * tl:.1f} ms per step", file=sys.stderr, flush=True)
+    # algorithmic bytes of every sweep pass of one solve of all instances (the library's
+    # byte model, summed from an untimed loop with launch statistics on); the batched call
+    # sweeps the same systems as often (same iterates), so the same bytes over its time
+    # give its average sweep-byte rate
+    for c in ctxs:
+        c.stats_enable(True)
+    loop()
+    alg_bytes = 0
+    for c in ctxs:
+        alg_bytes += sum(v["alg_bytes"] for v in c.stats().values())
+        c.stats_enable(False)
     learned = None
     if ckpt is not None:
         nets = [fnlh.Network(c) for c in ctxs]
@@ -1132,6 +1143,8 @@ def batch_measure(args, ckpt=None, steps=None, warmup=1, training=None):
            "instances": len(ctxs), "cells": cells, "systems": n_sys_total, "storage": args.storage,
            "time_to_1e-8_ms": round(1e3 * tb, 3), "updates_per_s": round(updates / tb),
            "per_instance_loop_ms": round(1e3 * tl, 3), "batched_speedup_vs_loop": round(tl / tb, 3),
+           "sweep_alg_bytes": int(alg_bytes), "sweep_alg_GBs_over_call": round(alg_bytes / tb / 1e9, 1),
+           "sweep_alg_frac_over_call": round(alg_bytes / tb / 1e9 / HBM_PEAK_GBS, 4),
            "sweeps_min_max": [min(sweeps), max(sweeps)],
            "worst_rel_res": max(r["rel_res"] for rep in reps_b for r in rep),
            "autotune": {"contexts": {str(k): v for k, v in tuned.items()}, "schedule": sched,
